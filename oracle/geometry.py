@@ -1,0 +1,400 @@
+"""Analytic level sets, node labels and control points (oracle).
+
+Sec. 2.1 of the paper: a *control point* x_c is the intersection of a grid line
+segment with the immersed surface Gamma; the grid point whose 1D stencil crosses
+Gamma is *affected*.  The level set phi < 0 marks the inside of the body.
+
+Readings used where the paper is silent (all shared with the GPU library):
+  * vertex-centred grid, nodes x_i = -1 + i h, i = 0..n, h = 2/n;
+  * a node with phi = 0 is not solved for in boundary problems; in interface
+    problems phi <= 0 is Omega^-;
+  * box-face nodes carry known Dirichlet values when the box bounds the domain;
+  * n points from Omega^- into Omega^+ (into the solved region).
+
+Parity: labels are pinned by exact counts on symmetric cases and by the
+consistency of the crossings with them (tests/test_oracle_geometry.py).
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Tuple
+
+import numpy as np
+
+from . import INACTIVE, PLUS, MINUS, BOX
+
+SIDE_INTERIOR, SIDE_EXTERIOR, SIDE_INTERFACE = 0, 1, 2
+GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION = 0, 1, 2
+
+
+class Grid:
+    """Uniform vertex-centred grid on [-1, 1]^dim with n intervals per axis.
+    Coarse multigrid levels use the same origin and spacing h * 2^level."""
+
+    def __init__(self, dim: int, n: int, h: float = None, lo: float = -1.0):
+        self.dim = dim
+        self.n = n
+        self.h = (2.0 / n) if h is None else h
+        self.lo = lo
+        self.shape = (n + 1,) * dim
+
+    def coord(self, i):
+        return self.lo + np.asarray(i) * self.h
+
+    def node_coords(self) -> List[np.ndarray]:
+        x1 = self.lo + np.arange(self.n + 1) * self.h
+        return list(np.meshgrid(*([x1] * self.dim), indexing="ij"))
+
+    def flat(self, idx) -> int:
+        """Flat index with x fastest: ix + (n+1) iy + (n+1)^2 iz."""
+        f = 0
+        for d in reversed(range(self.dim)):
+            f = f * (self.n + 1) + int(idx[d])
+        return f
+
+    def unflat(self, f: int) -> Tuple[int, ...]:
+        out = []
+        for d in range(self.dim):
+            out.append(f % (self.n + 1))
+            f //= (self.n + 1)
+        return tuple(out)
+
+    def inside(self, idx) -> bool:
+        return all(0 <= int(i) <= self.n for i in idx)
+
+
+# ---------------------------------------------------------------------------
+# level sets
+# ---------------------------------------------------------------------------
+class Sphere:
+    """phi = |x - c| - r (circle in 2D).  Classification compares the squared
+    distance (summed over axes in x, y, z order) with r*r, so that it is exact
+    for dyadic coordinates."""
+
+    def __init__(self, center, r):
+        self.c = [float(v) for v in center]
+        self.r = float(r)
+
+    def sign(self, X):
+        d2 = 0.0
+        for d in range(len(self.c)):
+            t = X[d] - self.c[d]
+            d2 = d2 + t * t
+        return np.sign(d2 - self.r * self.r)
+
+    def crossing(self, xa, axis, dir_, solved_inside: bool, h: float = None):
+        """Root of phi on the segment from node xa (the solved-side node) to
+        xa + dir_*h e_axis: walking from xa, the exit point of the sphere when
+        xa is inside, the entry point otherwise.  Returns the coordinate along
+        `axis` (not yet clamped) and the sphere index 0."""
+        q = self.r * self.r
+        for o in range(len(self.c)):
+            if o != axis:
+                t = xa[o] - self.c[o]
+                q = q - t * t
+        s = math.sqrt(max(q, 0.0))
+        if solved_inside:
+            return self.c[axis] + dir_ * s, 0
+        return self.c[axis] - dir_ * s, 0
+
+    def grad_dir(self, x, which=0):
+        g = np.array([x[d] - self.c[d] for d in range(len(self.c))])
+        return g / np.linalg.norm(g)
+
+    def curvature(self, x, which=0):
+        return 1.0 / self.r
+
+
+def _cheb_t_u(L: int, c: float):
+    """T_L(c) and U_{L-1}(c) by the three-term recurrences."""
+    t0, t1 = 1.0, c
+    u0, u1 = 1.0, 2.0 * c   # U_0, U_1
+    if L == 0:
+        return 1.0, 0.0
+    for _ in range(L - 1):
+        t0, t1 = t1, 2.0 * c * t1 - t0
+    if L == 1:
+        return c, 1.0
+    for _ in range(L - 2):
+        u0, u1 = u1, 2.0 * c * u1 - u0
+    return t1, u1
+
+
+class Star2D:
+    """phi = rho - (r0 + eps cos(L theta)), theta measured about the centre.
+    cos(L theta) = T_L(cos theta) (Chebyshev), so phi uses only +, *, / and sqrt."""
+
+    def __init__(self, cx, cy, r0, eps, lobes):
+        self.cx, self.cy, self.r0, self.eps, self.L = float(cx), float(cy), float(r0), float(eps), int(round(lobes))
+
+    def phi_scalar(self, x, y):
+        dx = x - self.cx
+        dy = y - self.cy
+        rho = math.sqrt(dx * dx + dy * dy)
+        c = dx / rho if rho > 0.0 else 1.0
+        t, _ = _cheb_t_u(self.L, c)
+        return rho - (self.r0 + self.eps * t)
+
+    def sign(self, X):
+        """Vectorised form of phi_scalar (same operations, same order)."""
+        x = np.asarray(X[0], dtype=np.float64)
+        y = np.asarray(X[1], dtype=np.float64)
+        dx = x - self.cx
+        dy = y - self.cy
+        rho = np.sqrt(dx * dx + dy * dy)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            c = np.where(rho > 0.0, dx / np.where(rho > 0.0, rho, 1.0), 1.0)
+        t0, t1 = np.ones_like(c), c
+        for _ in range(self.L - 1):
+            t0, t1 = t1, 2.0 * c * t1 - t0
+        t = t1 if self.L >= 1 else np.ones_like(c)
+        return np.sign(rho - (self.r0 + self.eps * t))
+
+    def crossing(self, xa, axis, dir_, solved_inside=None, h: float = None):
+        """Bisection (64 halvings) on the segment between the two nodes, using
+        the sign of phi; a zero at an end point is the root."""
+        lo_pt = list(xa)
+        if dir_ < 0:
+            lo_pt[axis] = xa[axis] - h
+        hi_pt = list(lo_pt)
+        hi_pt[axis] = lo_pt[axis] + h
+        s_lo = np.sign(self.phi_scalar(*lo_pt))
+        s_hi = np.sign(self.phi_scalar(*hi_pt))
+        if s_lo == 0:
+            return lo_pt[axis], 0
+        if s_hi == 0:
+            return hi_pt[axis], 0
+        a, b = lo_pt[axis], hi_pt[axis]
+        p = list(lo_pt)
+        for _ in range(64):
+            m = 0.5 * (a + b)
+            p[axis] = m
+            s = np.sign(self.phi_scalar(*p))
+            if s == 0:
+                return m, 0
+            if s == s_lo:
+                a = m
+            else:
+                b = m
+        return 0.5 * (a + b), 0
+
+    def grad_dir(self, x, which=0):
+        dx = x[0] - self.cx
+        dy = x[1] - self.cy
+        rho = math.sqrt(dx * dx + dy * dy)
+        c = dx / rho
+        _, u = _cheb_t_u(self.L, c)
+        dT = self.L * u                       # d T_L / dc
+        r3 = rho * rho * rho
+        gc = np.array([dy * dy / r3, -dx * dy / r3])   # grad of c = dx/rho
+        g = np.array([dx / rho, dy / rho]) - self.eps * dT * gc
+        return g / np.linalg.norm(g)
+
+    def curvature(self, x, which=0):
+        dx = x[0] - self.cx
+        dy = x[1] - self.cy
+        rho = math.sqrt(dx * dx + dy * dy)
+        c, s = dx / rho, dy / rho
+        t, u = _cheb_t_u(self.L, c)
+        R = self.r0 + self.eps * t
+        Rp = -self.eps * self.L * s * u           # R'(theta)
+        Rpp = -self.eps * self.L * self.L * t     # R''(theta)
+        return abs(R * R + 2 * Rp * Rp - R * Rpp) / (R * R + Rp * Rp) ** 1.5
+
+
+class SphereUnion:
+    """Union of spheres: a node is inside if inside any sphere, on Gamma if on
+    some sphere and inside none, outside otherwise."""
+
+    def __init__(self, spheres):
+        self.spheres = [Sphere(c, r) for c, r in spheres]
+
+    def sign(self, X):
+        s = np.ones(np.shape(X[0]))
+        on = np.zeros(np.shape(X[0]), dtype=bool)
+        inside = np.zeros(np.shape(X[0]), dtype=bool)
+        for sp in self.spheres:
+            si = sp.sign(X)
+            inside |= si < 0
+            on |= si == 0
+        s[on] = 0.0
+        s[inside] = -1.0
+        return s
+
+    def crossing(self, xa, axis, dir_, solved_inside=False, h: float = None):
+        """From the outside node xa towards its neighbour: the first entry
+        point into any sphere whose chord overlaps the segment."""
+        a0 = xa[axis]
+        a1 = xa[axis] + dir_ * h
+        lo, hi = min(a0, a1), max(a0, a1)
+        best, best_i, best_x = None, -1, None
+        for i, sp in enumerate(self.spheres):
+            q = sp.r * sp.r
+            for o in range(len(sp.c)):
+                if o != axis:
+                    t = xa[o] - sp.c[o]
+                    q = q - t * t
+            if q < 0.0:
+                continue
+            s = math.sqrt(q)
+            c0, c1 = sp.c[axis] - s, sp.c[axis] + s
+            if c1 < lo or c0 > hi:
+                continue
+            entry = c0 if dir_ > 0 else c1
+            dist = (entry - a0) * dir_
+            if best is None or dist < best:
+                best, best_i, best_x = dist, i, entry
+        return best_x, best_i
+
+    def grad_dir(self, x, which=0):
+        return self.spheres[which].grad_dir(x)
+
+    def curvature(self, x, which=0):
+        return 1.0 / self.spheres[which].r
+
+
+def make_geometry(kind: int, params, dim: int):
+    """Geometry from the parameter list of the C ABI: sphere [c..., r];
+    star [cx, cy, r0, eps, lobes]; union [count, (c..., r) * count]."""
+    if kind == GEOM_SPHERE:
+        g = Sphere(params[:-1], params[-1])
+    elif kind == GEOM_STAR2D:
+        g = Star2D(*params[:5])
+    elif kind == GEOM_SPHERE_UNION:
+        cnt = int(params[0])
+        sp = []
+        for i in range(cnt):
+            base = 1 + (dim + 1) * i
+            sp.append((params[base: base + dim], params[base + dim]))
+        g = SphereUnion(sp)
+    else:
+        raise ValueError("unknown geometry kind")
+    return g
+
+
+# ---------------------------------------------------------------------------
+# labels
+# ---------------------------------------------------------------------------
+class GeometryUnresolved(Exception):
+    pass
+
+
+def node_labels(grid: Grid, geom, side: int) -> np.ndarray:
+    """Label per node (array indexed [ix, iy(, iz)]):
+    PLUS = unknown in Omega^+, MINUS = unknown in Omega^- (interfaces only),
+    BOX = box-face node with a known Dirichlet value, INACTIVE otherwise.
+    Omega^+ is {phi < 0} for interior problems, {phi > 0} for exterior
+    problems and interfaces; Omega^- = {phi <= 0} for interfaces."""
+    X = grid.node_coords()
+    s = geom.sign(X)
+    face = np.zeros(grid.shape, dtype=bool)
+    for d in range(grid.dim):
+        idx = [slice(None)] * grid.dim
+        idx[d] = 0
+        face[tuple(idx)] = True
+        idx[d] = grid.n
+        face[tuple(idx)] = True
+    lab = np.zeros(grid.shape, dtype=np.uint8)
+    if side == SIDE_INTERIOR:
+        if np.any(face & (s <= 0)):
+            raise GeometryUnresolved("body touches the box")
+        lab[(s < 0) & ~face] = PLUS
+    elif side == SIDE_EXTERIOR:
+        if np.any(face & (s <= 0)):
+            raise GeometryUnresolved("body touches the box")
+        lab[(s > 0) & ~face] = PLUS
+        lab[(s > 0) & face] = BOX
+    else:
+        if np.any(face & (s <= 0)):
+            raise GeometryUnresolved("interface touches the box")
+        lab[(s <= 0) & ~face] = MINUS
+        lab[(s > 0) & ~face] = PLUS
+        lab[(s > 0) & face] = BOX
+    return lab
+
+
+def is_crossing(la: int, lb: int, side: int) -> bool:
+    """A control point lies on the segment between two nodes when one is an
+    unknown and the other lies across Gamma (not a box-face node)."""
+    if side == SIDE_INTERFACE:
+        return {int(la), int(lb)} == {PLUS, MINUS}
+    return {int(la), int(lb)} == {PLUS, INACTIVE}
+
+
+class ControlPoint:
+    __slots__ = ("axis", "p", "q", "x", "n", "kappa", "a", "dir", "which")
+
+    def __repr__(self):
+        return f"CP(axis={self.axis}, p={self.p}, x={self.x}, n={self.n})"
+
+
+def control_points(grid: Grid, geom, side: int, labels: np.ndarray) -> List[ControlPoint]:
+    """All control points, ordered by axis, then by the flat index of the
+    lower node of the segment.  For each control point and each side sigma of
+    the problem, a[sigma] is the adjacent unknown of that side and dir[sigma]
+    the step (+1/-1 along the axis) from it towards Gamma."""
+    out: List[ControlPoint] = []
+    lab_flat = labels.ravel(order="F")
+    dim = grid.dim
+    n1 = grid.n + 1
+    strides = [n1 ** d for d in range(dim)]
+    for axis in range(dim):
+        # lower nodes p with p + e_axis inside the grid, in increasing flat order
+        lower = [slice(None)] * dim
+        upper = [slice(None)] * dim
+        lower[axis] = slice(0, grid.n)
+        upper[axis] = slice(1, grid.n + 1)
+        la_arr = labels[tuple(lower)]
+        lb_arr = labels[tuple(upper)]
+        if side == SIDE_INTERFACE:
+            mask = ((la_arr == PLUS) & (lb_arr == MINUS)) | ((la_arr == MINUS) & (lb_arr == PLUS))
+        else:
+            mask = ((la_arr == PLUS) & (lb_arr == INACTIVE)) | ((la_arr == INACTIVE) & (lb_arr == PLUS))
+        idx = np.nonzero(mask)
+        flat_p = np.zeros(idx[0].shape, dtype=np.int64)
+        for d in reversed(range(dim)):
+            flat_p = flat_p * n1 + idx[d]
+        for p in np.sort(flat_p):
+            p = int(p)
+            q = p + strides[axis]
+            la, lb = lab_flat[p], lab_flat[q]
+            assert is_crossing(la, lb, side)
+            cp = ControlPoint()
+            cp.axis, cp.p, cp.q = axis, p, q
+            # solved-side node used for the root search
+            if side == SIDE_INTERFACE:
+                a_node = p if la == MINUS else q          # walk from Omega^-
+                inside = True
+            else:
+                a_node = p if la == PLUS else q
+                inside = (side == SIDE_INTERIOR)
+            dir_ = 1 if a_node == p else -1
+            xa = [float(grid.coord(v)) for v in grid.unflat(a_node)]
+            root, which = geom.crossing(xa, axis, dir_, inside, grid.h)
+            lo_c = float(grid.coord(grid.unflat(p)[axis]))
+            hi_c = float(grid.coord(grid.unflat(q)[axis]))
+            root = min(max(root, lo_c), hi_c)
+            x = list(xa)
+            x[axis] = root
+            cp.x = np.array(x)
+            cp.which = which
+            g = geom.grad_dir(cp.x, which)       # direction of grad phi (outward)
+            cp.n = -g if side == SIDE_INTERIOR else g
+            cp.kappa = geom.curvature(cp.x, which)
+            cp.a, cp.dir = {}, {}
+            if side == SIDE_INTERFACE:
+                cp.a[PLUS] = p if la == PLUS else q
+                cp.a[MINUS] = p if la == MINUS else q
+            else:
+                cp.a[PLUS] = p if la == PLUS else q
+            for sg, node in cp.a.items():
+                cp.dir[sg] = 1 if node == p else -1
+            out.append(cp)
+    return out
+
+
+def check_curvature(cps, h: float, limit: float = 0.25):
+    """The curvature condition |kappa h| < 1/4 (Sec. 2.1)."""
+    for cp in cps:
+        if abs(cp.kappa * h) >= limit:
+            raise GeometryUnresolved(f"|kappa h| = {abs(cp.kappa*h):.3f} >= 1/4 at {cp.x}")

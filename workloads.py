@@ -1,0 +1,315 @@
+"""Seeded synthetic workloads for the immersed-interface Poisson solver.
+
+This module only *describes* problems: grid sizes, the analytic geometry
+parameters, the manufactured solutions and the boundary/interface data they
+induce, and the serving request stream.  It contains none of the method's
+arithmetic (no level-set classification, no crossings, no stencils, no fits):
+both the CPU oracle and the GPU library receive the geometry as parameters and
+compute everything else themselves.  Data are sampled at the control points and
+with the normals that the side under test reports.
+
+Conventions (shared problem statement, Sec. 2.1-2.2 of the paper):
+  * the PDE is  div(beta grad u) = f  (so f = beta * Laplacian(u));
+  * n points from Omega^- into Omega^+ (into the solved region for boundary
+    problems); Neumann data is  qbar = beta dn u;  interface data are
+    j0 = u^+ - u^-  and  j1 = beta^+ dn u^+ - beta^- dn u^-.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# geometry kinds, problem sides and boundary-condition kinds; the integer values
+# are the ones the C ABI uses (include/iim.h)
+GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION = 0, 1, 2
+SIDE_INTERIOR, SIDE_EXTERIOR, SIDE_INTERFACE = 0, 1, 2
+BC_DIRICHLET, BC_NEUMANN, BC_JUMP = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Manufactured:
+    """A manufactured solution on each side: u, grad u, Laplacian u."""
+    u_plus: Callable
+    grad_plus: Callable
+    lap_plus: Callable
+    u_minus: Optional[Callable] = None
+    grad_minus: Optional[Callable] = None
+    lap_minus: Optional[Callable] = None
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    dim: int
+    n: int
+    geom_kind: int
+    geom_params: List[float]
+    side: int
+    bc: int
+    beta_plus: float = 1.0
+    beta_minus: float = 1.0
+    exact: Optional[Manufactured] = None
+    precision: str = "fp64"       # fp64 | mixed32 | mixed16
+    note: str = ""
+
+    # -- data sampling (pure evaluation of the manufactured solution) ----------
+    def cp_data(self, xyz: np.ndarray, normal: np.ndarray) -> np.ndarray:
+        """Boundary/interface data at control points xyz (ncp, dim) with unit
+        normals (ncp, dim).  Returns (ncp,) or (ncp, 2) for jumps (j0, j1)."""
+        ex = self.exact
+        X = [xyz[:, d] for d in range(self.dim)]
+        if self.bc == BC_DIRICHLET:
+            return np.asarray(ex.u_plus(*X), dtype=np.float64)
+        if self.bc == BC_NEUMANN:
+            g = ex.grad_plus(*X)
+            dn = sum(g[d] * normal[:, d] for d in range(self.dim))
+            return self.beta_plus * np.asarray(dn, dtype=np.float64)
+        gp = ex.grad_plus(*X)
+        gm = ex.grad_minus(*X)
+        dnp = sum(gp[d] * normal[:, d] for d in range(self.dim))
+        dnm = sum(gm[d] * normal[:, d] for d in range(self.dim))
+        j0 = ex.u_plus(*X) - ex.u_minus(*X)
+        j1 = self.beta_plus * dnp - self.beta_minus * dnm
+        return np.stack([np.asarray(j0, np.float64), np.asarray(j1, np.float64)], axis=1)
+
+    def node_coords(self) -> List[np.ndarray]:
+        """Full-grid node coordinates, arrays of shape (n+1,)*dim indexed [ix,iy(,iz)]."""
+        h = 2.0 / self.n
+        x1 = -1.0 + np.arange(self.n + 1) * h
+        return list(np.meshgrid(*([x1] * self.dim), indexing="ij"))
+
+    def box_data(self) -> np.ndarray:
+        """u^+ sampled on every grid node (only box-face nodes are read)."""
+        X = self.node_coords()
+        return np.asarray(self.exact.u_plus(*X), dtype=np.float64) * np.ones_like(X[0])
+
+    def rhs(self, labels: np.ndarray) -> np.ndarray:
+        """f = beta * Lap(u) on every node, chosen per side from `labels`
+        (1 = Omega^+, 2 = Omega^-), zero elsewhere."""
+        X = self.node_coords()
+        ex = self.exact
+        f = np.zeros(labels.shape)
+        fp = self.beta_plus * ex.lap_plus(*X) * np.ones_like(X[0])
+        f[labels == 1] = fp[labels == 1]
+        if ex.lap_minus is not None:
+            fm = self.beta_minus * ex.lap_minus(*X) * np.ones_like(X[0])
+            f[labels == 2] = fm[labels == 2]
+        return f
+
+    def exact_solution(self, labels: np.ndarray) -> np.ndarray:
+        X = self.node_coords()
+        ex = self.exact
+        u = np.full(labels.shape, np.nan)
+        up = ex.u_plus(*X) * np.ones_like(X[0])
+        u[labels == 1] = up[labels == 1]
+        if ex.u_minus is not None:
+            um = ex.u_minus(*X) * np.ones_like(X[0])
+            u[labels == 2] = um[labels == 2]
+        return u
+
+
+# ---------------------------------------------------------------------------
+# manufactured solutions
+# ---------------------------------------------------------------------------
+TWO_PI = 2.0 * math.pi
+PI = math.pi
+
+
+def ms_sin2pi_cos2pi() -> Manufactured:
+    """u = sin(2 pi x) cos(2 pi y)."""
+    u = lambda x, y: np.sin(TWO_PI * x) * np.cos(TWO_PI * y)
+    g = lambda x, y: (TWO_PI * np.cos(TWO_PI * x) * np.cos(TWO_PI * y),
+                      -TWO_PI * np.sin(TWO_PI * x) * np.sin(TWO_PI * y))
+    lap = lambda x, y: -2.0 * TWO_PI ** 2 * u(x, y)
+    return Manufactured(u, g, lap)
+
+
+def ms_sin_pi_3d() -> Manufactured:
+    """u = sin(pi x) sin(pi y) sin(pi z)."""
+    u = lambda x, y, z: np.sin(PI * x) * np.sin(PI * y) * np.sin(PI * z)
+    g = lambda x, y, z: (PI * np.cos(PI * x) * np.sin(PI * y) * np.sin(PI * z),
+                         PI * np.sin(PI * x) * np.cos(PI * y) * np.sin(PI * z),
+                         PI * np.sin(PI * x) * np.sin(PI * y) * np.cos(PI * z))
+    lap = lambda x, y, z: -3.0 * PI ** 2 * u(x, y, z)
+    return Manufactured(u, g, lap)
+
+
+def ms_star_interface() -> Manufactured:
+    """Inside (Omega^-): u = e^x cos y; outside (Omega^+): u = x^2 - y^2.
+    Both harmonic, so f = 0 on both sides."""
+    up = lambda x, y: x * x - y * y
+    gp = lambda x, y: (2.0 * x, -2.0 * y)
+    lp = lambda x, y: 0.0 * x
+    um = lambda x, y: np.exp(x) * np.cos(y)
+    gm = lambda x, y: (np.exp(x) * np.cos(y), -np.exp(x) * np.sin(y))
+    lm = lambda x, y: 0.0 * x
+    return Manufactured(up, gp, lp, um, gm, lm)
+
+
+def ms_cos_sinh() -> Manufactured:
+    """u = cos(2x) sinh(y) + z^2."""
+    u = lambda x, y, z: np.cos(2 * x) * np.sinh(y) + z * z
+    g = lambda x, y, z: (-2 * np.sin(2 * x) * np.sinh(y), np.cos(2 * x) * np.cosh(y), 2 * z)
+    lap = lambda x, y, z: -3.0 * np.cos(2 * x) * np.sinh(y) + 2.0
+    return Manufactured(u, g, lap)
+
+
+def ms_paper_interface(dim: int = 2) -> Manufactured:
+    """The paper's material-interface solution (Sec. 2.4):
+    u^+ = 0.6 + 0.4 sin(4 pi x) sin(2 pi y),  u^- = sin(4 pi x) sin(2 pi y)."""
+    s = lambda x, y: np.sin(2 * TWO_PI * x) * np.sin(TWO_PI * y)
+    gs = lambda x, y: (2 * TWO_PI * np.cos(2 * TWO_PI * x) * np.sin(TWO_PI * y),
+                       TWO_PI * np.sin(2 * TWO_PI * x) * np.cos(TWO_PI * y))
+    ls = lambda x, y: -((2 * TWO_PI) ** 2 + TWO_PI ** 2) * s(x, y)
+    up = lambda x, y: 0.6 + 0.4 * s(x, y)
+    gp = lambda x, y: tuple(0.4 * c for c in gs(x, y))
+    lp = lambda x, y: 0.4 * ls(x, y)
+    return Manufactured(up, gp, lp, s, gs, ls)
+
+
+def ms_polynomial(coefs: dict, dim: int) -> Manufactured:
+    """u = sum_c coef * x^a y^b (z^c) — used by patch tests (exact for degree <= k-1)."""
+    def u(*X):
+        out = 0.0 * X[0]
+        for e, c in coefs.items():
+            t = c + 0.0 * X[0]
+            for d in range(dim):
+                t = t * X[d] ** e[d]
+            out = out + t
+        return out
+
+    def g(*X):
+        comps = []
+        for dd in range(dim):
+            out = 0.0 * X[0]
+            for e, c in coefs.items():
+                if e[dd] == 0:
+                    continue
+                t = c * e[dd] + 0.0 * X[0]
+                for d in range(dim):
+                    t = t * X[d] ** (e[d] - (1 if d == dd else 0))
+                out = out + t
+            comps.append(out)
+        return tuple(comps)
+
+    def lap(*X):
+        out = 0.0 * X[0]
+        for e, c in coefs.items():
+            for dd in range(dim):
+                if e[dd] < 2:
+                    continue
+                t = c * e[dd] * (e[dd] - 1) + 0.0 * X[0]
+                for d in range(dim):
+                    t = t * X[d] ** (e[d] - (2 if d == dd else 0))
+                out = out + t
+        return out
+
+    return Manufactured(u, g, lap)
+
+
+# ---------------------------------------------------------------------------
+# geometry draws
+# ---------------------------------------------------------------------------
+def draw_sphere_union(count: int = 16, seed: int = 0, lo: float = -0.7, hi: float = 0.7,
+                      rmin: float = 0.08, rmax: float = 0.2, min_gap: float = 0.05) -> List[Tuple]:
+    """Spheres drawn in order from numpy default_rng(seed); sphere i is redrawn
+    until its surface gap to every earlier sphere is at least min_gap."""
+    rng = np.random.default_rng(seed)
+    out: List[Tuple] = []
+    while len(out) < count:
+        c = rng.uniform(lo, hi, size=3)
+        r = rng.uniform(rmin, rmax)
+        ok = all(np.linalg.norm(c - np.array(c2)) - r - r2 >= min_gap for (c2, r2) in out)
+        if ok:
+            out.append((tuple(float(v) for v in c), float(r)))
+    return out
+
+
+def union_params(spheres: Sequence[Tuple]) -> List[float]:
+    p: List[float] = [float(len(spheres))]
+    for c, r in spheres:
+        p += [float(v) for v in c] + [float(r)]
+    return p
+
+
+# ---------------------------------------------------------------------------
+# the five workload configurations and small variants for parity tests
+# ---------------------------------------------------------------------------
+def cfg1_circle(n: int = 64) -> Workload:
+    """2D Dirichlet, interior of the circle r=0.5 at the origin."""
+    return Workload("cfg1_circle_dirichlet", 2, n, GEOM_SPHERE, [0.0, 0.0, 0.5],
+                    SIDE_INTERIOR, BC_DIRICHLET, exact=ms_sin2pi_cos2pi(), precision="fp64")
+
+
+def cfg2_star(n: int = 1024, beta_plus: float = 1.0, beta_minus: float = 1.0) -> Workload:
+    """2D interface: star r(theta)=0.5+0.1cos(5 theta); Dirichlet box."""
+    return Workload("cfg2_star_interface", 2, n, GEOM_STAR2D, [0.0, 0.0, 0.5, 0.1, 5.0],
+                    SIDE_INTERFACE, BC_JUMP, beta_plus, beta_minus,
+                    exact=ms_star_interface(), precision="fp64")
+
+
+def cfg3_sphere(n: int = 256, precision: str = "mixed32") -> Workload:
+    """3D Dirichlet, interior of the sphere r=0.6 at the origin."""
+    return Workload("cfg3_sphere_dirichlet", 3, n, GEOM_SPHERE, [0.0, 0.0, 0.0, 0.6],
+                    SIDE_INTERIOR, BC_DIRICHLET, exact=ms_sin_pi_3d(), precision=precision)
+
+
+def cfg4_spheres(n: int = 384, count: int = 16, seed: int = 0, precision: str = "mixed16",
+                 spheres: Optional[List[Tuple]] = None) -> Workload:
+    """3D Neumann on a union of spheres, Dirichlet on the box, exterior domain."""
+    sp = spheres if spheres is not None else draw_sphere_union(count, seed)
+    return Workload("cfg4_spheres_neumann", 3, n, GEOM_SPHERE_UNION, union_params(sp),
+                    SIDE_EXTERIOR, BC_NEUMANN, exact=ms_cos_sinh(), precision=precision,
+                    note=f"{len(sp)} spheres, seed {seed}")
+
+
+def small_spheres_union() -> List[Tuple]:
+    """A resolvable-at-small-n stand-in for cfg 4 (3 spheres, radius >= 0.3)."""
+    return [((-0.35, -0.3, 0.05), 0.32), ((0.4, 0.25, -0.2), 0.3), ((0.05, 0.45, 0.5), 0.3)]
+
+
+def small_circles_union_2d() -> List[Tuple]:
+    return [((-0.35, -0.3), 0.3), ((0.4, 0.3), 0.33)]
+
+
+# ---------------------------------------------------------------------------
+# serving stream (cfg 5)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float
+    workload: Workload
+
+
+def serving_requests(count: int = 2000, rate: float = 10.0, seed: int = 1,
+                     n2d: Tuple[int, int] = (128, 2048), n3d: Tuple[int, int] = (32, 192)) -> List[Request]:
+    """Poisson arrivals at `rate` per second; each request is a 2D circle or 3D
+    sphere interior Dirichlet problem with the cfg-1 / cfg-3 manufactured
+    solutions, radius U[0.3,0.7], centre offset uniform in the ball of radius 0.2."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        dim = 2 if rng.uniform() < 0.5 else 3
+        r = float(rng.uniform(0.3, 0.7))
+        # uniform in the ball of radius 0.2 (rejection sampling)
+        while True:
+            off = rng.uniform(-0.2, 0.2, size=dim)
+            if np.linalg.norm(off) <= 0.2:
+                break
+        if dim == 2:
+            n = int(rng.integers(n2d[0], n2d[1] + 1))
+            w = Workload(f"req{i}_circle", 2, n, GEOM_SPHERE, [float(off[0]), float(off[1]), r],
+                         SIDE_INTERIOR, BC_DIRICHLET, exact=ms_sin2pi_cos2pi(), precision="mixed32")
+        else:
+            n = int(rng.integers(n3d[0], n3d[1] + 1))
+            w = Workload(f"req{i}_sphere", 3, n, GEOM_SPHERE,
+                         [float(off[0]), float(off[1]), float(off[2]), r],
+                         SIDE_INTERIOR, BC_DIRICHLET, exact=ms_sin_pi_3d(), precision="mixed32")
+        out.append(Request(i, t, w))
+    return out
