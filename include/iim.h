@@ -1,0 +1,218 @@
+/*
+ * iim.h -- C ABI of the MI355X immersed-interface Poisson library.
+ *
+ * The library solves  div(beta grad u) = f  on a uniform vertex-centred grid
+ * of [lo, hi]^dim (dim = 2 or 3, n intervals per axis, h = (hi - lo)/n) with
+ * an immersed boundary or interface Gamma given by an analytic level set
+ * (Gabbard, Paris & van Rees, "A high order multigrid-preconditioned immersed
+ * interface solver for the Poisson equation with boundary and interface
+ * conditions", JCP 2025):
+ *   - boundary problems (Sec. 2.1): u = ubar (Dirichlet) or beta dn u = qbar
+ *     (Neumann) on Gamma, the solved region Omega^+ being the interior or the
+ *     exterior of the body; box faces bounding the domain carry Dirichlet data;
+ *   - interface problems (Sec. 2.2): Omega^- = {phi <= 0}, Omega^+ = {phi > 0},
+ *     [u] = u^+ - u^- = j0 and [beta dn u] = j1 on Gamma, Dirichlet box.
+ * The normal n at a control point points from Omega^- into Omega^+ (into the
+ * solved region for boundary problems).
+ *
+ * The discretisation is the (n, k) = (4, 5) immersed-interface method
+ * (Sec. 2.1-2.3): dimension-split 4th-order central differences with
+ * least-squares ghost values at every crossing of a grid line with Gamma.
+ * The system L_Omega u + L_Gamma u_Gamma = f is solved matrix-free by
+ * right-preconditioned FGMRES(restart) (Sec. 4.1) with one Shortley-Weller
+ * multigrid V-cycle as preconditioner (Sec. 3.1, 3.3).  The operator, the
+ * Krylov basis, dot products and least-squares fits are FP64; the V-cycle runs
+ * in FP64, FP32, or FP32 with FP16 storage of its iterates.
+ *
+ * Conventions for every call:
+ *   - return 0 on success, IIM_NOT_CONVERGED (> 0) when a solve stopped at
+ *     max_iters (outputs still valid), a negative IIM_E_* code on error; the
+ *     message of the last error of the calling thread is iim_last_error();
+ *   - no C++ exception crosses this interface;
+ *   - "full-grid array": (n+1)^dim values, x fastest: node (i, j, k) at
+ *     i + (n+1) j + (n+1)^2 k;
+ *   - the caller owns every buffer it passes; the library owns the handle and
+ *     all device memory it allocated (released by iim_destroy);
+ *   - device pointers must be on the device that was current at iim_create;
+ *     work is ordered on the stream given at creation.
+ */
+#ifndef IIM_H
+#define IIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IIM_OK 0
+#define IIM_NOT_CONVERGED 1
+#define IIM_E_INVALID_ARG (-1)
+#define IIM_E_GEOMETRY_UNRESOLVED (-2)
+#define IIM_E_BUDGET (-3)
+#define IIM_E_DEVICE (-4)
+#define IIM_E_BREAKDOWN (-5)
+#define IIM_E_INTERNAL (-6)
+
+/* geometry kinds (params layout in brackets) */
+#define IIM_GEOM_SPHERE 0       /* circle / sphere [c_1..c_dim, r]                 */
+#define IIM_GEOM_STAR2D 1       /* star r(t)=r0+eps cos(L t) [cx, cy, r0, eps, L]   */
+#define IIM_GEOM_SPHERE_UNION 2 /* union [count, (c_1..c_dim, r) x count]          */
+
+/* which side is solved */
+#define IIM_SIDE_INTERIOR 0  /* Omega^+ = {phi < 0}                          */
+#define IIM_SIDE_EXTERIOR 1  /* Omega^+ = {phi > 0}, Dirichlet box faces       */
+#define IIM_SIDE_INTERFACE 2 /* Omega^- = {phi <= 0}, Omega^+ = {phi > 0}     */
+
+/* condition on Gamma */
+#define IIM_BC_DIRICHLET 0
+#define IIM_BC_NEUMANN 1
+#define IIM_BC_JUMP 2
+
+/* V-cycle precision */
+#define IIM_PREC_FP64 0
+#define IIM_PREC_MIXED32 1 /* FP32 V-cycle                                   */
+#define IIM_PREC_MIXED16 2 /* FP32 V-cycle arithmetic, FP16 iterate storage  */
+
+/* memory kinds of caller buffers */
+#define IIM_MEM_HOST 0
+#define IIM_MEM_DEVICE 1
+
+typedef struct iim_grid {
+    int32_t dim;  /* 2 or 3 */
+    int32_t n;    /* intervals per axis, >= 8 */
+    double lo;    /* domain [lo, hi]^dim */
+    double hi;
+} iim_grid;
+
+typedef struct iim_geometry {
+    int32_t kind;    /* IIM_GEOM_* */
+    int32_t side;    /* IIM_SIDE_* */
+    int32_t bc;      /* IIM_BC_* (IIM_BC_JUMP iff side == IIM_SIDE_INTERFACE) */
+    int32_t nparams; /* number of doubles in params */
+    const double* params; /* host pointer, copied at creation */
+} iim_geometry;
+
+typedef struct iim_options {
+    int32_t order_n;    /* interior order; 4 */
+    int32_t order_k;    /* least-squares polynomial order; 5 */
+    double beta_plus;   /* coefficient in Omega^+ */
+    double beta_minus;  /* coefficient in Omega^- (interfaces) */
+    double rtol;        /* stop when ||b - L u||_2 / ||b||_2 <= rtol */
+    int32_t max_iters;  /* total FGMRES iterations */
+    int32_t restart;    /* FGMRES restart length (<= 32) */
+    int32_t nu_pre;     /* red-black Gauss-Seidel sweeps before / after */
+    int32_t nu_post;    /*   the coarse-grid correction                 */
+    int32_t coarsest_n; /* direct solve once n_level <= coarsest_n */
+    int32_t precision;  /* IIM_PREC_* */
+    double ls_axis_t;   /* least-squares half-ellipse semi-axes in units of h */
+    double ls_axis_n;   /*   (0 = defaults k and k - 1/2) */
+    int32_t use_graph;  /* capture the V-cycle in a HIP graph (1) or not (0) */
+    int32_t reserved;
+} iim_options;
+
+typedef struct iim_stats {
+    int32_t status;        /* return code of the solve */
+    int32_t iterations;    /* FGMRES iterations performed */
+    int32_t cycles;        /* restart cycles */
+    int32_t hist_len;      /* entries written to the history */
+    double final_rel_residual; /* true ||b - L u|| / ||b|| at exit */
+    double t_solve_ms;     /* wall time of the solve (host clock) */
+    double t_apply_ms;     /* GPU time in the high-order operator */
+    double t_vcycle_ms;    /* GPU time in the preconditioner */
+    double t_krylov_ms;    /* GPU time in orthogonalisation and updates */
+} iim_stats;
+
+typedef struct iim_info {
+    int32_t dim, n, levels, sides;
+    int64_t n_unknowns;       /* active degrees of freedom */
+    int64_t n_control_points;
+    int64_t n_ls_entries;     /* sum of least-squares set sizes over control points and sides */
+    int64_t n_irregular;      /* nodes whose high-order stencil uses ghost or box values */
+    int64_t box_lo[3], box_dims[3]; /* padded level-0 storage box (node indices) */
+    int64_t device_bytes;     /* device memory held by the handle */
+    double t_setup_ms;        /* wall time of iim_create */
+} iim_info;
+
+typedef struct iim_problem iim_problem;
+
+/* Defaults: (4,5), beta = 1, rtol 1e-10, restart 10, V(2,2), coarsest 8, FP64. */
+int iim_default_options(iim_options* opt);
+
+/* Builds everything a solve needs on the device (Sec. 2.1 and 3.1-3.3):
+ * node labels, control points, least-squares fits (FP64), irregular-node
+ * records, and the Shortley-Weller hierarchy with its coarse inverse.
+ * stream: a hipStream_t (NULL = default stream).  Fails with
+ * IIM_E_GEOMETRY_UNRESOLVED if |kappa h| >= 1/4 at a control point or a fit
+ * stays rank deficient, IIM_E_INVALID_ARG for unsupported options. */
+int iim_create(const iim_grid* grid, const iim_geometry* geom, const iim_options* opt,
+               void* stream, iim_problem** out);
+
+/* Releases all device memory of the handle (NULL is ignored). */
+void iim_destroy(iim_problem* p);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* iim_last_error(void);
+
+int iim_get_info(const iim_problem* p, iim_info* info);
+
+/* Control points x_c (Sec. 2.1) in the library's order: by axis, then by the
+ * flat index of the segment's lower node.  Call with xyz = normal = NULL to get
+ * the count.  xyz, normal: host arrays of count*dim doubles. */
+int iim_control_points(const iim_problem* p, int64_t* count, double* xyz, double* normal);
+
+/* Node labels on the full grid (host array of (n+1)^dim bytes):
+ * 0 inactive, 1 Omega^+ unknown, 2 Omega^- unknown, 3 box face with known value. */
+int iim_node_labels(const iim_problem* p, uint8_t* labels);
+
+/* Boundary data u_Gamma (Sec. 2.3): cp_data holds one value per control point
+ * (ubar or qbar) or two (j0, j1) for interfaces; box_data is a full-grid array
+ * of which only box-face nodes are read (NULL if no face bounds the domain).
+ * Both live in memory of kind mem_kind; they are copied. */
+int iim_set_boundary_data(iim_problem* p, const double* cp_data, const double* box_data,
+                          int32_t mem_kind);
+
+/* Source term f (full-grid array, read at the unknowns); builds the right-hand
+ * side b = f - L_Gamma u_Gamma with the current boundary data. */
+int iim_set_rhs(iim_problem* p, const double* f, int32_t mem_kind);
+
+/* FGMRES solve.  u: device full-grid array receiving the solution (NaN at nodes
+ * that are not unknowns).  x0: device full-grid initial guess or NULL (zero).
+ * hist: host array of hist_cap doubles receiving the relative residual estimate
+ * after every iteration (may be NULL).  st: may be NULL. */
+int iim_solve(iim_problem* p, double* u, const double* x0, double* hist, int32_t hist_cap,
+              iim_stats* st);
+
+/* y = L_Omega x (with_data = 0) or y = L_Omega x + L_Gamma u_Gamma (with_data = 1)
+ * at the unknowns, 0 elsewhere.  x, y: device full-grid arrays. */
+int iim_apply(iim_problem* p, const double* x, double* y, int32_t with_data);
+
+/* z = M^{-1} v, one V-cycle with zero initial guess on Lap z = v / beta
+ * (Sec. 3.3), in the handle's precision.  v, z: device full-grid arrays. */
+int iim_vcycle(iim_problem* p, const double* v, double* z);
+
+/* Least-squares stencil of control point cp on side (1 = Omega^+, 2 = Omega^-):
+ * m grid points (full-grid flat indices in idx) and the (m+1) x r weights in
+ * weights[row * r + col] (row 0 multiplies u(x_c); columns: ghosts 1..w, then
+ * the normal derivative when present).  Host buffers of capacity cap rows;
+ * returns the sizes in *m and *r. */
+int iim_ls_stencil(const iim_problem* p, int64_t cp, int32_t side, int32_t* m, int32_t* r,
+                   int64_t* idx, double* weights, int32_t cap);
+
+/* Multigrid level access for tests: number of intervals of a level, its labels
+ * (host full-level array) and one operation on device full-level FP64 arrays:
+ *   op 0: out = A_l in1 (Shortley-Weller operator, unscaled)
+ *   op 1: in-place red-black sweep on out with right-hand side in1
+ *   op 2: out(level+1) = half-weighting of in1 restricted to unknowns
+ *   op 3: out(level-1) = prolongation of in1 (level) onto the finer unknowns
+ *   op 4: out = coarse direct solve of in1 (coarsest level only)
+ * All in the handle's V-cycle precision. */
+int iim_level_info(const iim_problem* p, int32_t level, int32_t* n, int64_t* n_unknowns);
+int iim_level_labels(const iim_problem* p, int32_t level, uint8_t* labels);
+int iim_level_op(iim_problem* p, int32_t level, int32_t op, const double* in1, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IIM_H */

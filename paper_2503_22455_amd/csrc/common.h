@@ -1,0 +1,305 @@
+// Internal definitions shared by the HIP kernels and the host core.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+#include "iim.h"
+
+namespace iim {
+
+// ---------------------------------------------------------------------------
+// errors: host code throws Error; the C ABI converts it to a status code
+// ---------------------------------------------------------------------------
+struct Error : public std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define IIM_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::iim::Error(IIM_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define IIM_LAUNCH_CHECK() IIM_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// node labels: kind in bits 0-1, flags above
+// ---------------------------------------------------------------------------
+enum : uint8_t { K_INACTIVE = 0, K_PLUS = 1, K_MINUS = 2, K_BOX = 3 };
+constexpr uint8_t KIND_MASK = 3;
+constexpr uint8_t F_HO_IRR = 4;  // high-order stencil needs ghost or box values
+constexpr uint8_t F_SW_IRR = 8;  // Shortley-Weller row differs from the 5/7-point one
+
+__host__ __device__ inline bool is_unknown(uint8_t lab) {
+    uint8_t k = lab & KIND_MASK;
+    return k == K_PLUS || k == K_MINUS;
+}
+
+// ---------------------------------------------------------------------------
+// storage box of a level: a padded bounding box of its unknowns, x fastest
+// ---------------------------------------------------------------------------
+struct Box {
+    int lo[3];
+    int dims[3];
+    __host__ __device__ int64_t size() const { return (int64_t)dims[0] * dims[1] * dims[2]; }
+    __host__ __device__ int64_t idx(int i, int j, int k) const {
+        return (int64_t)(i - lo[0]) + (int64_t)dims[0] * ((int64_t)(j - lo[1]) + (int64_t)dims[1] * (k - lo[2]));
+    }
+    __host__ __device__ int64_t stride(int d) const {
+        return d == 0 ? 1 : (d == 1 ? (int64_t)dims[0] : (int64_t)dims[0] * dims[1]);
+    }
+    __host__ __device__ void coords(int64_t l, int* ijk) const {
+        ijk[0] = (int)(l % dims[0]) + lo[0];
+        int64_t r = l / dims[0];
+        ijk[1] = (int)(r % dims[1]) + lo[1];
+        ijk[2] = (int)(r / dims[1]) + lo[2];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// geometry on one grid level
+// ---------------------------------------------------------------------------
+struct Geom {
+    int kind;       // IIM_GEOM_*
+    int side;       // IIM_SIDE_*
+    int dim;
+    int n;          // intervals of this level
+    double lo, h;   // node i at lo + i * h
+    const double* p;  // device copy of the parameters
+};
+
+__device__ inline double node_coord(const Geom& g, int i) {
+#pragma clang fp contract(off)
+    return g.lo + (double)i * g.h;
+}
+
+// sign of phi for one sphere [c..., r]: squared distance summed x, y, z first
+__device__ inline int sphere_sign(const double* c, double r, int dim, const double* x) {
+#pragma clang fp contract(off)
+    double d2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        double t = x[d] - c[d];
+        d2 = d2 + t * t;
+    }
+    double q = d2 - r * r;
+    return q < 0.0 ? -1 : (q > 0.0 ? 1 : 0);
+}
+
+// Chebyshev T_L(c) and U_{L-1}(c) by three-term recurrences
+__device__ inline void cheb_tu(int L, double c, double* T, double* U) {
+#pragma clang fp contract(off)
+    double t0 = 1.0, t1 = c;
+    for (int i = 0; i < L - 1; ++i) {
+        double t2 = 2.0 * c * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+    }
+    *T = (L == 0) ? 1.0 : t1;
+    double u0 = 1.0, u1 = 2.0 * c;
+    for (int i = 0; i < L - 2; ++i) {
+        double u2 = 2.0 * c * u1 - u0;
+        u0 = u1;
+        u1 = u2;
+    }
+    *U = (L <= 1) ? (L == 1 ? 1.0 : 0.0) : u1;
+}
+
+// phi = rho - (r0 + eps T_L(dx/rho)) for the star
+__device__ inline double star_phi(const double* p, double x, double y) {
+#pragma clang fp contract(off)
+    double dx = x - p[0];
+    double dy = y - p[1];
+    double rho = sqrt(dx * dx + dy * dy);
+    double c = rho > 0.0 ? dx / rho : 1.0;
+    int L = (int)llround(p[4]);
+    double t0 = 1.0, t1 = c;
+    for (int i = 0; i < L - 1; ++i) {
+        double t2 = 2.0 * c * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+    }
+    double t = L >= 1 ? t1 : 1.0;
+    return rho - (p[2] + p[3] * t);
+}
+
+__device__ inline int sgn(double v) { return v < 0.0 ? -1 : (v > 0.0 ? 1 : 0); }
+
+// sign of phi (-1 inside the body, 0 on Gamma, +1 outside)
+__device__ inline int geom_sign(const Geom& g, const double* x) {
+    if (g.kind == IIM_GEOM_SPHERE) return sphere_sign(g.p, g.p[g.dim], g.dim, x);
+    if (g.kind == IIM_GEOM_STAR2D) return sgn(star_phi(g.p, x[0], x[1]));
+    int cnt = (int)llround(g.p[0]);
+    bool on = false;
+    for (int s = 0; s < cnt; ++s) {
+        const double* q = g.p + 1 + (g.dim + 1) * s;
+        int v = sphere_sign(q, q[g.dim], g.dim, x);
+        if (v < 0) return -1;
+        if (v == 0) on = true;
+    }
+    return on ? 0 : 1;
+}
+
+// kind of a node of the level (box faces included), or 255 = rejected
+__device__ inline uint8_t node_kind(const Geom& g, const int* ijk) {
+    double x[3] = {0.0, 0.0, 0.0};
+    bool face = false;
+    for (int d = 0; d < g.dim; ++d) {
+        x[d] = node_coord(g, ijk[d]);
+        if (ijk[d] == 0 || ijk[d] == g.n) face = true;
+    }
+    int s = geom_sign(g, x);
+    if (face) {
+        if (s <= 0) return 255;  // body touches the box
+        return g.side == IIM_SIDE_INTERIOR ? K_INACTIVE : K_BOX;
+    }
+    if (g.side == IIM_SIDE_INTERIOR) return s < 0 ? K_PLUS : K_INACTIVE;
+    if (g.side == IIM_SIDE_EXTERIOR) return s > 0 ? K_PLUS : K_INACTIVE;
+    return s <= 0 ? K_MINUS : K_PLUS;
+}
+
+// Root of phi on the segment from node xa (coordinate vector) to xa + dir h e_axis.
+// xa is the unknown for boundary problems, the Omega^- node for interfaces.
+// Returns the coordinate along the axis, clamped to the segment; *which = sphere index.
+__device__ inline double crossing_root(const Geom& g, const double* xa, int axis, int dir, int* which) {
+#pragma clang fp contract(off)
+    *which = 0;
+    double a0 = xa[axis];
+    double a1 = xa[axis] + (double)dir * g.h;
+    double lo = fmin(a0, a1), hi = fmax(a0, a1);
+    double root;
+    if (g.kind == IIM_GEOM_SPHERE) {
+        const double* c = g.p;
+        double r = g.p[g.dim];
+        double q = r * r;
+        for (int o = 0; o < g.dim; ++o)
+            if (o != axis) {
+                double t = xa[o] - c[o];
+                q = q - t * t;
+            }
+        double s = sqrt(fmax(q, 0.0));
+        bool inside = (g.side != IIM_SIDE_EXTERIOR);  // interior problems and interfaces walk out
+        root = inside ? c[axis] + (double)dir * s : c[axis] - (double)dir * s;
+    } else if (g.kind == IIM_GEOM_STAR2D) {
+        double lo_pt[2] = {xa[0], xa[1]};
+        if (dir < 0) lo_pt[axis] = xa[axis] - g.h;
+        double hi_pt[2] = {lo_pt[0], lo_pt[1]};
+        hi_pt[axis] = lo_pt[axis] + g.h;
+        int s_lo = sgn(star_phi(g.p, lo_pt[0], lo_pt[1]));
+        int s_hi = sgn(star_phi(g.p, hi_pt[0], hi_pt[1]));
+        if (s_lo == 0) {
+            root = lo_pt[axis];
+        } else if (s_hi == 0) {
+            root = hi_pt[axis];
+        } else {
+            double a = lo_pt[axis], b = hi_pt[axis];
+            double pt[2] = {lo_pt[0], lo_pt[1]};
+            root = 0.0;
+            bool hit = false;
+            for (int it = 0; it < 64; ++it) {
+                double m = 0.5 * (a + b);
+                pt[axis] = m;
+                int s = sgn(star_phi(g.p, pt[0], pt[1]));
+                if (s == 0) {
+                    root = m;
+                    hit = true;
+                    break;
+                }
+                if (s == s_lo) a = m; else b = m;
+            }
+            if (!hit) root = 0.5 * (a + b);
+        }
+    } else {
+        int cnt = (int)llround(g.p[0]);
+        double best = 0.0, best_x = a0;
+        int best_i = -1;
+        for (int s = 0; s < cnt; ++s) {
+            const double* c = g.p + 1 + (g.dim + 1) * s;
+            double r = c[g.dim];
+            double q = r * r;
+            for (int o = 0; o < g.dim; ++o)
+                if (o != axis) {
+                    double t = xa[o] - c[o];
+                    q = q - t * t;
+                }
+            if (q < 0.0) continue;
+            double sq = sqrt(q);
+            double c0 = c[axis] - sq, c1 = c[axis] + sq;
+            if (c1 < lo || c0 > hi) continue;
+            double entry = dir > 0 ? c0 : c1;
+            double dist = (entry - a0) * (double)dir;
+            if (best_i < 0 || dist < best) {
+                best = dist;
+                best_i = s;
+                best_x = entry;
+            }
+        }
+        *which = best_i < 0 ? 0 : best_i;
+        root = best_x;
+    }
+    return fmin(fmax(root, lo), hi);
+}
+
+// unit normal from Omega^- into Omega^+ at a point of Gamma
+__device__ inline void geom_normal(const Geom& g, const double* x, int which, double* n) {
+    double v[3] = {0.0, 0.0, 0.0};
+    if (g.kind == IIM_GEOM_STAR2D) {
+        double dx = x[0] - g.p[0], dy = x[1] - g.p[1];
+        double rho = sqrt(dx * dx + dy * dy);
+        double c = dx / rho;
+        double T, U;
+        cheb_tu((int)llround(g.p[4]), c, &T, &U);
+        double dT = g.p[4] * U;
+        double r3 = rho * rho * rho;
+        v[0] = dx / rho - g.p[3] * dT * (dy * dy / r3);
+        v[1] = dy / rho - g.p[3] * dT * (-dx * dy / r3);
+    } else {
+        const double* c = (g.kind == IIM_GEOM_SPHERE) ? g.p : g.p + 1 + (g.dim + 1) * which;
+        for (int d = 0; d < g.dim; ++d) v[d] = x[d] - c[d];
+    }
+    double nn = 0.0;
+    for (int d = 0; d < g.dim; ++d) nn += v[d] * v[d];
+    nn = sqrt(nn);
+    double sgn_ = (g.side == IIM_SIDE_INTERIOR) ? -1.0 : 1.0;
+    for (int d = 0; d < 3; ++d) n[d] = d < g.dim ? sgn_ * v[d] / nn : 0.0;
+}
+
+// largest principal curvature magnitude at a point of Gamma
+__device__ inline double geom_curvature(const Geom& g, const double* x, int which) {
+    if (g.kind == IIM_GEOM_SPHERE) return 1.0 / g.p[g.dim];
+    if (g.kind == IIM_GEOM_SPHERE_UNION) return 1.0 / g.p[1 + (g.dim + 1) * which + g.dim];
+    double dx = x[0] - g.p[0], dy = x[1] - g.p[1];
+    double rho = sqrt(dx * dx + dy * dy);
+    double c = dx / rho, s = dy / rho;
+    double T, U;
+    int L = (int)llround(g.p[4]);
+    cheb_tu(L, c, &T, &U);
+    double R = g.p[2] + g.p[3] * T;
+    double Rp = -g.p[3] * L * s * U;
+    double Rpp = -g.p[3] * L * L * T;
+    return fabs(R * R + 2 * Rp * Rp - R * Rpp) / pow(R * R + Rp * Rp, 1.5);
+}
+
+// ---------------------------------------------------------------------------
+// irregular high-order stencil slots (one int32 per axis direction)
+// ---------------------------------------------------------------------------
+enum : int { SLOT_REG = 0, SLOT_GHOST = 1, SLOT_BOX = 2 };
+__host__ __device__ inline int slot_type(int s) { return s & 3; }
+__host__ __device__ inline int slot_j(int s) { return (s >> 2) & 3; }
+__host__ __device__ inline int slot_cs(int s) { return s >> 4; }
+__host__ __device__ inline int make_slot(int type, int j, int cs) { return type | (j << 2) | (cs << 4); }
+
+// 4th-order central second-derivative coefficients a_0, a_1, a_2
+constexpr double A0 = -2.5, A1 = 4.0 / 3.0, A2 = -1.0 / 12.0;
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace iim

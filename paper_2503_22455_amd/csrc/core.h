@@ -1,0 +1,99 @@
+// Problem state held by an iim_problem handle.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace iim {
+
+void set_error(const std::string& m);
+const char* last_error();
+
+// owner of every device allocation of a handle
+struct DevMem {
+    std::vector<void*> ptrs;
+    size_t total = 0;
+    void* alloc(size_t bytes);
+    void release(void* p);
+    ~DevMem();
+};
+
+struct Level {
+    int n = 0;
+    double h = 0.0;
+    Geom geom{};
+    Box box{};
+    int core_lo[3] = {0, 0, 0}, core_hi[3] = {-1, -1, -1};
+    int64_t nunk = 0;
+    uint8_t* labels = nullptr;
+    int64_t nirr = 0;
+    int32_t* irr_index = nullptr;
+    double* rec64 = nullptr;
+    float* rec32 = nullptr;
+    void* z = nullptr;  // iterate (storage type)
+    void* b = nullptr;  // right-hand side (arithmetic type)
+};
+
+constexpr int KRED = 16;  // reduction outputs per launch
+
+struct Problem {
+    DevMem mem;
+    hipStream_t stream = nullptr;
+    iim_grid grid{};
+    iim_options opt{};
+    int dim = 2, kind = 0, side = 0, bc = 0, nsides = 1, w = 2;
+    double h = 0.0;
+    std::vector<double> params;
+    double* d_params = nullptr;
+
+    // level 0 storage and control points
+    Box box{};
+    CPDev cp{};
+    // least-squares stencils: CSR over control-point sides
+    std::vector<int64_t> h_ptr;
+    int64_t nnz = 0;
+    int nrows = 0, nrows_apply = 0;
+    int64_t* ls_ptr = nullptr;
+    int32_t* ls_idx = nullptr;
+    double* ls_S = nullptr;   // [nrows][nnz] raw weights of the grid points
+    double* ls_Sc = nullptr;  // [ncs][nrows] weights of u(x_c)
+    double* W_apply = nullptr;
+    double* dcoef = nullptr;
+    double* ghost = nullptr;
+    double* cpdata = nullptr;
+    // irregular high-order nodes
+    int64_t ho_nirr = 0;
+    int32_t* ho_irr_index = nullptr;
+    int32_t* ho_slots = nullptr;
+    // multigrid
+    std::vector<Level> levels;
+    int64_t nc = 0;
+    int32_t* coarse_list = nullptr;
+    double* Ainv64 = nullptr;
+    float* Ainv32 = nullptr;
+    // solve vectors (level-0 box)
+    double *boxval = nullptr, *rhs = nullptr, *xk = nullptr, *rk = nullptr, *wk = nullptr;
+    double *Vb = nullptr, *Zb = nullptr;
+    double *red_part = nullptr, *red_out = nullptr;
+    double* red_scale = nullptr;
+    hipEvent_t ev[8] = {};
+    double t_setup_ms = 0.0;
+
+    void setup();
+    void build_level_labels(Level& L, int pad);
+    int64_t select(const uint8_t* flags, int64_t n, int32_t* out);
+    void check_err(int* d_err, const char* what);
+    LevelDev level_dev(int l) const;
+    GhostDev ghost_dev() const;
+    void apply_box(const double* x, double* y, int with_data);
+    template <typename T, typename S> void vcycle_t(const double* v, double* out);
+    void vcycle(const double* v, double* out);
+    int solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st);
+    int level_op(int level, int op, const double* in1, double* out);
+    template <typename T, typename S> int level_op_t(int level, int op, const double* in1, double* out);
+    ~Problem();
+};
+
+}  // namespace iim

@@ -1,0 +1,984 @@
+// Host core of the library: problem setup on the device, the multigrid
+// V-cycle driver, the FGMRES solver, and the C ABI (include/iim.h).
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "core.h"
+
+namespace iim {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& m) { g_last_error = m; }
+const char* last_error() { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// device memory helpers
+// ---------------------------------------------------------------------------
+void* DevMem::alloc(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(e == hipErrorOutOfMemory ? IIM_E_BUDGET : IIM_E_DEVICE,
+                    std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    ptrs.push_back(p);
+    total += bytes;
+    return p;
+}
+
+void DevMem::release(void* p) {
+    for (auto& q : ptrs)
+        if (q == p) {
+            (void)hipFree(q);
+            q = nullptr;
+        }
+}
+
+DevMem::~DevMem() {
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+static Box make_box(int dim, const int* mn, const int* mx, int pad, bool empty) {
+    Box b;
+    for (int d = 0; d < 3; ++d) {
+        if (d >= dim) {
+            b.lo[d] = 0;
+            b.dims[d] = 1;
+        } else if (empty) {
+            b.lo[d] = 0;
+            b.dims[d] = 1;
+        } else {
+            b.lo[d] = mn[d] - pad;
+            b.dims[d] = mx[d] - mn[d] + 1 + 2 * pad;
+        }
+    }
+    return b;
+}
+
+// classify a level's full grid and build its storage box and labels
+void Problem::build_level_labels(Level& L, int pad) {
+    int* d_bbox = (int*)mem.alloc(8 * sizeof(int));
+    int h_init[8] = {1 << 30, 1 << 30, 1 << 30, -(1 << 30), -(1 << 30), -(1 << 30), 0, 0};
+    IIM_HIP(hipMemcpyAsync(d_bbox, h_init, sizeof(h_init), hipMemcpyHostToDevice, stream));
+    unsigned long long* d_cnt = (unsigned long long*)mem.alloc(sizeof(unsigned long long));
+    IIM_HIP(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), stream));
+    run_classify_bbox(L.geom, d_bbox, d_bbox + 6, d_cnt, stream);
+    int h_bbox[8];
+    unsigned long long cnt = 0;
+    IIM_HIP(hipMemcpyAsync(h_bbox, d_bbox, sizeof(h_bbox), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipMemcpyAsync(&cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipStreamSynchronize(stream));
+    mem.release(d_bbox);
+    mem.release(d_cnt);
+    if (h_bbox[6]) throw Error(IIM_E_GEOMETRY_UNRESOLVED, "the immersed body touches the domain box");
+    L.nunk = (int64_t)cnt;
+    bool empty = cnt == 0;
+    int mn[3] = {h_bbox[0], h_bbox[1], dim == 3 ? h_bbox[2] : 0};
+    int mx[3] = {h_bbox[3], h_bbox[4], dim == 3 ? h_bbox[5] : 0};
+    L.box = make_box(dim, mn, mx, pad, empty);
+    for (int d = 0; d < 3; ++d) {
+        L.core_lo[d] = empty ? 1 : (d < dim ? mn[d] : 0);
+        L.core_hi[d] = empty ? 0 : (d < dim ? mx[d] : 0);
+    }
+    if (L.box.size() > (int64_t)INT32_MAX) throw Error(IIM_E_BUDGET, "storage box exceeds 2^31 nodes");
+    L.labels = (uint8_t*)mem.alloc(L.box.size());
+    run_box_labels(L.geom, L.box, L.labels, stream);
+}
+
+// flagged-node selection with a temporary buffer
+int64_t Problem::select(const uint8_t* flags, int64_t n, int32_t* out) {
+    size_t tb = select_tmp_bytes(n);
+    void* tmp = mem.alloc(tb);
+    int64_t* d_count = (int64_t*)mem.alloc(sizeof(int64_t));
+    int64_t c = select_flagged(flags, n, out, tmp, tb, d_count, stream);
+    mem.release(tmp);
+    mem.release(d_count);
+    return c;
+}
+
+void Problem::check_err(int* d_err, const char* what) {
+    int h = 0;
+    IIM_HIP(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipStreamSynchronize(stream));
+    if (h) {
+        std::string m = std::string(what) + " failed (code " + std::to_string(h) + ")";
+        if (h & 2) m += ": |kappa h| >= 1/4 at a control point";
+        if (h & 32) m += ": least-squares set exceeds its capacity";
+        if (h & 128) m += ": least-squares fit rank deficient after growth";
+        if (h & 16) m += ": singular coarse-level matrix";
+        throw Error(IIM_E_GEOMETRY_UNRESOLVED, m);
+    }
+}
+
+void Problem::setup() {
+    const double t0 = now_ms();
+    w = opt.order_n / 2;
+    h = (grid.hi - grid.lo) / grid.n;
+    nsides = (side == IIM_SIDE_INTERFACE) ? 2 : 1;
+    d_params = (double*)mem.alloc(params.size() * sizeof(double));
+    IIM_HIP(hipMemcpyAsync(d_params, params.data(), params.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    int* d_err = (int*)mem.alloc(sizeof(int));
+    IIM_HIP(hipMemsetAsync(d_err, 0, sizeof(int), stream));
+
+    // ---- levels and their labels
+    std::vector<int> sizes{grid.n};
+    while (sizes.back() > opt.coarsest_n) sizes.push_back((sizes.back() + 1) / 2);
+    levels.resize(sizes.size());
+    for (size_t l = 0; l < sizes.size(); ++l) {
+        Level& L = levels[l];
+        L.n = sizes[l];
+        L.h = h * (double)(1 << l);
+        L.geom = Geom{kind, side, dim, L.n, grid.lo, L.h, d_params};
+        build_level_labels(L, l == 0 ? 2 : 1);
+    }
+    Level& L0 = levels[0];
+    if (L0.nunk == 0) throw Error(IIM_E_INVALID_ARG, "the problem has no unknowns");
+    box = L0.box;
+
+    // ---- control points (level 0)
+    {
+        uint8_t* flags = (uint8_t*)mem.alloc(box.size());
+        std::vector<int32_t*> per_axis;
+        std::vector<int64_t> counts;
+        for (int a = 0; a < dim; ++a) {
+            run_cp_flags(L0.geom, box, L0.labels, a, flags, stream);
+            int32_t* tmp = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
+            counts.push_back(select(flags, box.size(), tmp));
+            per_axis.push_back(tmp);
+        }
+        int64_t ncp = 0;
+        cp.axis_start[0] = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (a < dim) ncp += counts[a];
+            cp.axis_start[a + 1] = (int)ncp;
+        }
+        cp.ncp = ncp;
+        cp.nsides = nsides;
+        cp.lower = (int32_t*)mem.alloc(ncp * sizeof(int32_t));
+        cp.axis = (int32_t*)mem.alloc(ncp * sizeof(int32_t));
+        cp.a = (int32_t*)mem.alloc(ncp * nsides * sizeof(int32_t));
+        cp.dir = (int32_t*)mem.alloc(ncp * nsides * sizeof(int32_t));
+        cp.x = (double*)mem.alloc(3 * ncp * sizeof(double));
+        cp.n = (double*)mem.alloc(3 * ncp * sizeof(double));
+        cp.kappa = (double*)mem.alloc(ncp * sizeof(double));
+        std::vector<int32_t> axes(ncp);
+        for (int a = 0; a < dim; ++a) {
+            IIM_HIP(hipMemcpyAsync(cp.lower + cp.axis_start[a], per_axis[a], counts[a] * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, stream));
+            for (int64_t i = cp.axis_start[a]; i < cp.axis_start[a + 1]; ++i) axes[i] = a;
+        }
+        IIM_HIP(hipMemcpyAsync(cp.axis, axes.data(), ncp * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+        for (auto p : per_axis) mem.release(p);
+        mem.release(flags);
+        run_cp_compute(L0.geom, box, L0.labels, cp, d_err, stream);
+        check_err(d_err, "control points");
+    }
+
+    // ---- least-squares stencils (FP64)
+    const int64_t ncs = cp.ncp * nsides;
+    nrows = w + ((bc == IIM_BC_DIRICHLET) ? 0 : 1);
+    {
+        LSParams P;
+        P.dim = dim;
+        P.order_k = opt.order_k;
+        P.w = w;
+        P.nrows = nrows;
+        P.nsides = nsides;
+        P.a0 = opt.ls_axis_t > 0 ? opt.ls_axis_t : (double)opt.order_k;
+        P.b0 = opt.ls_axis_n > 0 ? opt.ls_axis_n : opt.order_k - 0.5;
+        P.max_grow = 6;
+        P.mcap = dim == 2 ? 192 : 768;
+        const int K = opt.order_k;
+        const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
+        int64_t waves = std::min<int64_t>(std::max<int64_t>(ncs, 1), dim == 2 ? 4096 : 1024);
+        double* scratch = (double*)mem.alloc((size_t)waves * (p + 4) * P.mcap * sizeof(double));
+        int32_t* d_m = (int32_t*)mem.alloc(std::max<int64_t>(ncs, 1) * sizeof(int32_t));
+        int32_t* d_grow = (int32_t*)mem.alloc(std::max<int64_t>(ncs, 1) * sizeof(int32_t));
+        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, scratch, waves,
+               d_err, stream);
+        check_err(d_err, "least-squares sizes");
+        std::vector<int32_t> hm(ncs);
+        if (ncs) IIM_HIP(hipMemcpyAsync(hm.data(), d_m, ncs * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+        h_ptr.assign(ncs + 1, 0);
+        for (int64_t i = 0; i < ncs; ++i) h_ptr[i + 1] = h_ptr[i] + hm[i];
+        nnz = h_ptr[ncs];
+        ls_ptr = (int64_t*)mem.alloc((ncs + 1) * sizeof(int64_t));
+        IIM_HIP(hipMemcpyAsync(ls_ptr, h_ptr.data(), (ncs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        ls_idx = (int32_t*)mem.alloc(nnz * sizeof(int32_t));
+        ls_S = (double*)mem.alloc(nrows * nnz * sizeof(double));
+        ls_Sc = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * nrows * sizeof(double));
+        run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, scratch, waves, d_err,
+               stream);
+        check_err(d_err, "least-squares fits");
+        mem.release(scratch);
+        mem.release(d_m);
+        mem.release(d_grow);
+        // apply weights
+        dcoef = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * w * sizeof(double));
+        if (bc == IIM_BC_NEUMANN) {
+            W_apply = (double*)mem.alloc(w * nnz * sizeof(double));
+            nrows_apply = w;
+        } else {
+            W_apply = ls_S;
+            nrows_apply = nrows;
+        }
+        run_apply_weights(bc, ls_ptr, ncs, w, nrows, ls_S, ls_Sc, opt.beta_plus, nnz,
+                          bc == IIM_BC_NEUMANN ? W_apply : nullptr, dcoef, stream);
+        ghost = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * w * sizeof(double));
+        cpdata = (double*)mem.alloc(std::max<int64_t>(cp.ncp, 1) * 2 * sizeof(double));
+        IIM_HIP(hipMemsetAsync(cpdata, 0, std::max<int64_t>(cp.ncp, 1) * 2 * sizeof(double), stream));
+    }
+
+    // ---- irregular high-order nodes
+    {
+        uint8_t* flags = (uint8_t*)mem.alloc(box.size());
+        run_ho_irr_flag(L0.geom, box, L0.labels, flags, stream);
+        int32_t* nodes = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
+        ho_nirr = select(flags, box.size(), nodes);
+        ho_irr_index = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
+        run_fill_int(ho_irr_index, box.size(), -1, stream);
+        ho_slots = (int32_t*)mem.alloc(std::max<int64_t>(ho_nirr, 1) * 2 * dim * sizeof(int32_t));
+        run_ho_irr_records(L0.geom, box, L0.labels, cp, nodes, ho_nirr, ho_slots, ho_irr_index, d_err, stream);
+        check_err(d_err, "irregular records");
+        mem.release(nodes);
+        mem.release(flags);
+    }
+
+    // ---- Shortley-Weller rows on every level
+    for (size_t l = 0; l < levels.size(); ++l) {
+        Level& L = levels[l];
+        int64_t bs = L.box.size();
+        uint8_t* flags = (uint8_t*)mem.alloc(bs);
+        run_sw_irr_flag(L.geom, L.box, L.labels, flags, stream);
+        int32_t* nodes = (int32_t*)mem.alloc(bs * sizeof(int32_t));
+        L.nirr = select(flags, bs, nodes);
+        L.irr_index = (int32_t*)mem.alloc(bs * sizeof(int32_t));
+        run_fill_int(L.irr_index, bs, -1, stream);
+        const int R = 1 + 2 * dim;
+        L.rec64 = (double*)mem.alloc(std::max<int64_t>(L.nirr, 1) * R * sizeof(double));
+        L.rec32 = (float*)mem.alloc(std::max<int64_t>(L.nirr, 1) * R * sizeof(float));
+        run_sw_records(L.geom, L.box, L.labels, nodes, L.nirr, bc, opt.beta_plus, opt.beta_minus, L.rec64, L.rec32,
+                       L.irr_index, stream);
+        mem.release(nodes);
+        mem.release(flags);
+    }
+
+    // ---- coarsest level: dense inverse of the scaled SW matrix
+    {
+        Level& Lc = levels.back();
+        int64_t bs = Lc.box.size();
+        const int R = 1 + 2 * dim;
+        std::vector<uint8_t> lab(bs);
+        std::vector<int32_t> irr(bs);
+        std::vector<double> rec(std::max<int64_t>(Lc.nirr, 1) * R);
+        IIM_HIP(hipMemcpyAsync(lab.data(), Lc.labels, bs, hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipMemcpyAsync(irr.data(), Lc.irr_index, bs * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipMemcpyAsync(rec.data(), Lc.rec64, rec.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+        std::vector<int32_t> list, col_of(bs, -1);
+        for (int64_t l = 0; l < bs; ++l) {
+            if (!is_unknown(lab[l])) continue;
+            double diag = (lab[l] & F_SW_IRR) ? rec[(int64_t)irr[l] * R] : -2.0 * dim;
+            if (diag == 0.0) continue;
+            col_of[l] = (int32_t)list.size();
+            list.push_back((int32_t)l);
+        }
+        nc = (int64_t)list.size();
+        if (nc > 4096) throw Error(IIM_E_INVALID_ARG, "coarsest level too large for a dense solve");
+        coarse_list = (int32_t*)mem.alloc(std::max<int64_t>(nc, 1) * sizeof(int32_t));
+        int32_t* d_col = (int32_t*)mem.alloc(bs * sizeof(int32_t));
+        if (nc) IIM_HIP(hipMemcpyAsync(coarse_list, list.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        IIM_HIP(hipMemcpyAsync(d_col, col_of.data(), bs * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        double* A = (double*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(double));
+        Ainv64 = (double*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(double));
+        Ainv32 = (float*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(float));
+        run_coarse_assemble(Lc.box, dim, Lc.labels, Lc.irr_index, Lc.rec64, coarse_list, d_col, nc, A, stream);
+        run_coarse_invert(A, Ainv64, nc, d_err, stream);
+        check_err(d_err, "coarse inverse");
+        run_convert<double, float>(Ainv64, Ainv32, nc * nc, 1.0, stream);
+        IIM_HIP(hipStreamSynchronize(stream));
+        mem.release(A);
+        mem.release(d_col);
+    }
+
+    // ---- solve buffers
+    const int64_t N = box.size();
+    const int m = opt.restart;
+    boxval = (double*)mem.alloc(N * sizeof(double));
+    rhs = (double*)mem.alloc(N * sizeof(double));
+    xk = (double*)mem.alloc(N * sizeof(double));
+    rk = (double*)mem.alloc(N * sizeof(double));
+    wk = (double*)mem.alloc(N * sizeof(double));
+    Vb = (double*)mem.alloc((size_t)(m + 1) * N * sizeof(double));
+    Zb = (double*)mem.alloc((size_t)m * N * sizeof(double));
+    for (double* p : {boxval, rhs, xk, rk, wk}) IIM_HIP(hipMemsetAsync(p, 0, N * sizeof(double), stream));
+    IIM_HIP(hipMemsetAsync(Vb, 0, (size_t)(m + 1) * N * sizeof(double), stream));
+    IIM_HIP(hipMemsetAsync(Zb, 0, (size_t)m * N * sizeof(double), stream));
+    red_part = (double*)mem.alloc((size_t)(KRED + 1) * RED_BLOCKS * sizeof(double));
+    red_out = (double*)mem.alloc(4 * 64 * sizeof(double));
+    IIM_HIP(hipMemsetAsync(red_out, 0, 4 * 64 * sizeof(double), stream));
+    red_scale = (double*)mem.alloc(2 * sizeof(double));
+    size_t tsz = opt.precision == IIM_PREC_FP64 ? sizeof(double) : sizeof(float);
+    size_t ssz = opt.precision == IIM_PREC_FP64 ? 8 : (opt.precision == IIM_PREC_MIXED32 ? 4 : 2);
+    for (Level& L : levels) {
+        L.z = mem.alloc(L.box.size() * ssz);
+        L.b = mem.alloc(L.box.size() * tsz);
+        IIM_HIP(hipMemsetAsync(L.z, 0, L.box.size() * ssz, stream));
+        IIM_HIP(hipMemsetAsync(L.b, 0, L.box.size() * tsz, stream));
+    }
+    for (int i = 0; i < 8; ++i) IIM_HIP(hipEventCreate(&ev[i]));
+    IIM_HIP(hipStreamSynchronize(stream));
+    mem.release(d_err);
+    t_setup_ms = now_ms() - t0;
+}
+
+LevelDev Problem::level_dev(int l) const {
+    const Level& L = levels[l];
+    LevelDev D;
+    D.dim = dim;
+    D.n = L.n;
+    D.box = L.box;
+    for (int d = 0; d < 3; ++d) {
+        D.core_lo[d] = L.core_lo[d];
+        D.core_hi[d] = L.core_hi[d];
+    }
+    D.labels = L.labels;
+    D.irr_index = L.irr_index;
+    D.rec64 = L.rec64;
+    D.rec32 = L.rec32;
+    return D;
+}
+
+GhostDev Problem::ghost_dev() const {
+    GhostDev G;
+    G.bc = bc;
+    G.nsides = nsides;
+    G.w = w;
+    G.nrows = nrows_apply;
+    G.beta_plus = opt.beta_plus;
+    G.beta_minus = opt.beta_minus;
+    G.ptr = ls_ptr;
+    G.idx = ls_idx;
+    G.W = W_apply;
+    G.Sc = ls_Sc;
+    G.dcoef = dcoef;
+    G.nnz = nnz;
+    G.ncp = cp.ncp;
+    return G;
+}
+
+// ---------------------------------------------------------------------------
+// operators
+// ---------------------------------------------------------------------------
+void Problem::apply_box(const double* x, double* y, int with_data) {
+    run_ghosts(ghost_dev(), x, cpdata, with_data, ghost, stream);
+    const Level& L0 = levels[0];
+    run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ghost, boxval, w, 1.0 / (h * h),
+                 opt.beta_plus, opt.beta_minus, x, y, with_data, stream);
+}
+
+template <typename T, typename S>
+void Problem::vcycle_t(const double* v, double* out) {
+    const int nl = (int)levels.size();
+    LevelDev D0 = level_dev(0);
+    run_absmax(v, box.size(), red_part, red_scale, stream);
+    run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
+    for (int l = 0; l < nl - 1; ++l) {
+        LevelDev D = level_dev(l), C = level_dev(l + 1);
+        S* z = (S*)levels[l].z;
+        T* b = (T*)levels[l].b;
+        run_zero<S>(z, levels[l].box.size(), stream);
+        for (int s = 0; s < opt.nu_pre; ++s) {
+            run_rbgs<T, S>(D, 0, z, b, stream);
+            run_rbgs<T, S>(D, 1, z, b, stream);
+        }
+        run_resid_restrict<T, S>(D, C, z, b, (T*)levels[l + 1].b, stream);
+    }
+    {
+        Level& Lc = levels[nl - 1];
+        run_zero<S>((S*)Lc.z, Lc.box.size(), stream);
+        const T* Ainv = std::is_same<T, double>::value ? (const T*)Ainv64 : (const T*)Ainv32;
+        run_coarse_solve<T, S>(level_dev(nl - 1), coarse_list, nc, Ainv, (const T*)Lc.b, (S*)Lc.z, stream);
+    }
+    const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+    for (int l = nl - 2; l >= 0; --l) {
+        LevelDev D = level_dev(l), C = level_dev(l + 1);
+        S* z = (S*)levels[l].z;
+        T* b = (T*)levels[l].b;
+        run_prolong<T, S>(D, C, mode, (const S*)levels[l + 1].z, z, stream);
+        for (int s = 0; s < opt.nu_post; ++s) {
+            run_rbgs<T, S>(D, 0, z, b, stream);
+            run_rbgs<T, S>(D, 1, z, b, stream);
+        }
+    }
+    run_cast_out<S>(D0, (const S*)levels[0].z, red_scale + 1, out, stream);
+}
+
+void Problem::vcycle(const double* v, double* out) {
+    if (opt.precision == IIM_PREC_FP64)
+        vcycle_t<double, double>(v, out);
+    else if (opt.precision == IIM_PREC_MIXED32)
+        vcycle_t<float, float>(v, out);
+    else
+        vcycle_t<float, __half>(v, out);
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES(m), right preconditioned, classical Gram-Schmidt with one
+// re-orthogonalisation; Givens rotations on the host.
+// ---------------------------------------------------------------------------
+int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st) {
+    const double t0 = now_ms();
+    const int64_t N = box.size();
+    const int m = opt.restart;
+    iim_stats S{};
+    float t_apply = 0.f, t_vc = 0.f, t_kr = 0.f;
+    if (x0_full)
+        run_full_to_box(dim, grid.n, box, x0_full, xk, levels[0].labels, 1, stream);
+    else
+        IIM_HIP(hipMemsetAsync(xk, 0, N * sizeof(double), stream));
+    double bnorm2;
+    run_norm2(rhs, N, red_part, red_out, stream);
+    IIM_HIP(hipMemcpyAsync(&bnorm2, red_out, sizeof(double), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipStreamSynchronize(stream));
+    const double bnorm = std::sqrt(bnorm2);
+    int status = IIM_OK;
+    int its = 0, cycles = 0, hl = 0;
+    double true_rel = 0.0;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hbuf(3 * 64);
+    if (bnorm == 0.0) {
+        IIM_HIP(hipMemsetAsync(xk, 0, N * sizeof(double), stream));
+    } else {
+        while (true) {
+            // true residual r = b - A x
+            apply_box(xk, wk, 0);
+            run_copy(rhs, rk, N, stream);
+            run_axpby(-1.0, wk, 1.0, rk, N, stream);
+            double rn2;
+            run_norm2(rk, N, red_part, red_out, stream);
+            IIM_HIP(hipMemcpyAsync(&rn2, red_out, sizeof(double), hipMemcpyDeviceToHost, stream));
+            IIM_HIP(hipStreamSynchronize(stream));
+            const double beta = std::sqrt(rn2);
+            true_rel = beta / bnorm;
+            if (!(true_rel == true_rel)) {
+                status = IIM_E_BREAKDOWN;
+                break;
+            }
+            if (true_rel <= opt.rtol) break;
+            if (its >= opt.max_iters) {
+                status = IIM_NOT_CONVERGED;
+                break;
+            }
+            ++cycles;
+            // v_0 = r / beta
+            IIM_HIP(hipMemcpyAsync(red_out + 192, &rn2, sizeof(double), hipMemcpyHostToDevice, stream));
+            run_normalize(rk, red_out + 192, Vb, N, stream);
+            std::fill(gv.begin(), gv.end(), 0.0);
+            gv[0] = beta;
+            int k = 0;
+            bool breakdown = false;
+            for (int j = 0; j < m; ++j) {
+                double* vj = Vb + (size_t)j * N;
+                double* zj = Zb + (size_t)j * N;
+                IIM_HIP(hipEventRecord(ev[0], stream));
+                vcycle(vj, zj);
+                IIM_HIP(hipEventRecord(ev[1], stream));
+                apply_box(zj, wk, 0);
+                IIM_HIP(hipEventRecord(ev[2], stream));
+                // CGS2: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2, |w|^2
+                run_multidot(Vb, N, j + 1, wk, N, red_part, red_out, stream);
+                run_update_dot(Vb, N, j + 1, red_out, wk, N, j + 1, 0, red_part, red_out + 64, stream);
+                run_update_dot(Vb, N, j + 1, red_out + 64, wk, N, 0, 1, red_part, red_out + 128, stream);
+                run_normalize(wk, red_out + 128, Vb + (size_t)(j + 1) * N, N, stream);
+                IIM_HIP(hipEventRecord(ev[3], stream));
+                IIM_HIP(hipMemcpyAsync(hbuf.data(), red_out, 3 * 64 * sizeof(double), hipMemcpyDeviceToHost, stream));
+                IIM_HIP(hipStreamSynchronize(stream));
+                float a1, a2, a3;
+                IIM_HIP(hipEventElapsedTime(&a1, ev[0], ev[1]));
+                IIM_HIP(hipEventElapsedTime(&a2, ev[1], ev[2]));
+                IIM_HIP(hipEventElapsedTime(&a3, ev[2], ev[3]));
+                t_vc += a1;
+                t_apply += a2;
+                t_kr += a3;
+                for (int i = 0; i <= j; ++i) H[i * m + j] = hbuf[i] + hbuf[64 + i];
+                const double hn = std::sqrt(hbuf[128]);
+                H[(j + 1) * m + j] = hn;
+                if (!(hn == hn)) {
+                    breakdown = true;
+                    break;
+                }
+                for (int i = 0; i < j; ++i) {
+                    double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                    H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                    H[i * m + j] = t;
+                }
+                double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+                cs[j] = H[j * m + j] / den;
+                sn[j] = H[(j + 1) * m + j] / den;
+                H[j * m + j] = den;
+                H[(j + 1) * m + j] = 0.0;
+                gv[j + 1] = -sn[j] * gv[j];
+                gv[j] = cs[j] * gv[j];
+                ++its;
+                k = j + 1;
+                const double est = std::fabs(gv[j + 1]) / bnorm;
+                if (hist && hl < hist_cap) hist[hl++] = est;
+                if (est <= opt.rtol || its >= opt.max_iters || hn == 0.0) break;
+            }
+            if (breakdown) {
+                status = IIM_E_BREAKDOWN;
+                break;
+            }
+            for (int i = k - 1; i >= 0; --i) {
+                double acc = gv[i];
+                for (int l = i + 1; l < k; ++l) acc -= H[i * m + l] * y[l];
+                y[i] = acc / H[i * m + i];
+            }
+            IIM_HIP(hipMemcpyAsync(red_out + 192, y.data(), k * sizeof(double), hipMemcpyHostToDevice, stream));
+            run_axpy_multi(Zb, N, k, red_out + 192, xk, N, stream);
+        }
+    }
+    if (u_full) run_box_to_full(dim, grid.n, box, xk, levels[0].labels, std::nan(""), u_full, stream);
+    IIM_HIP(hipStreamSynchronize(stream));
+    S.status = status;
+    S.iterations = its;
+    S.cycles = cycles;
+    S.hist_len = hl;
+    S.final_rel_residual = true_rel;
+    S.t_solve_ms = now_ms() - t0;
+    S.t_apply_ms = t_apply;
+    S.t_vcycle_ms = t_vc;
+    S.t_krylov_ms = t_kr;
+    if (st) *st = S;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// level operations for tests (FP64 in and out, the handle's precision inside)
+// ---------------------------------------------------------------------------
+template <typename T, typename S>
+int Problem::level_op_t(int l, int op, const double* in1, double* out) {
+    const int nl = (int)levels.size();
+    if (l < 0 || l >= nl) throw Error(IIM_E_INVALID_ARG, "level out of range");
+    if (op == 2 && l == nl - 1) throw Error(IIM_E_INVALID_ARG, "no coarser level");
+    if (op == 3 && l == 0) throw Error(IIM_E_INVALID_ARG, "no finer level");
+    if (op == 4 && l != nl - 1) throw Error(IIM_E_INVALID_ARG, "coarse solve only on the coarsest level");
+    if (op < 0 || op > 4) throw Error(IIM_E_INVALID_ARG, "bad op");
+    Level& L = levels[l];
+    const int64_t bs = L.box.size();
+    const double h2 = L.h * L.h;
+    double* t64 = (double*)mem.alloc(bs * sizeof(double));
+    T* tb = (T*)mem.alloc(bs * sizeof(T));
+    S* tz = (S*)mem.alloc(bs * sizeof(S));
+    run_full_to_box(dim, L.n, L.box, in1, t64, L.labels, 1, stream);
+    LevelDev D = level_dev(l);
+    if (op == 0) {  // out = A_l in1
+        run_convert<double, S>(t64, tz, bs, 1.0, stream);
+        run_sw_apply<T, S>(D, tz, tb, stream);
+        run_convert<T, double>(tb, t64, bs, 1.0 / h2, stream);
+        run_box_to_full(dim, L.n, L.box, t64, L.labels, 0.0, out, stream);
+    } else if (op == 1) {  // one red-black sweep on out with right-hand side in1
+        run_convert<double, T>(t64, tb, bs, h2, stream);
+        run_full_to_box(dim, L.n, L.box, out, t64, L.labels, 1, stream);
+        run_convert<double, S>(t64, tz, bs, 1.0, stream);
+        run_rbgs<T, S>(D, 0, tz, tb, stream);
+        run_rbgs<T, S>(D, 1, tz, tb, stream);
+        run_convert<S, double>(tz, t64, bs, 1.0, stream);
+        run_box_to_full(dim, L.n, L.box, t64, L.labels, 0.0, out, stream);
+    } else if (op == 2) {  // out(l+1) = half-weighting of in1
+        Level& C = levels[l + 1];
+        run_convert<double, T>(t64, tb, bs, 1.0, stream);
+        run_zero<S>(tz, bs, stream);
+        T* cb = (T*)mem.alloc(C.box.size() * sizeof(T));
+        double* c64 = (double*)mem.alloc(C.box.size() * sizeof(double));
+        run_resid_restrict<T, S>(D, level_dev(l + 1), tz, tb, cb, stream);
+        run_convert<T, double>(cb, c64, C.box.size(), 0.25, stream);
+        run_box_to_full(dim, C.n, C.box, c64, C.labels, 0.0, out, stream);
+        IIM_HIP(hipStreamSynchronize(stream));
+        mem.release(cb);
+        mem.release(c64);
+    } else if (op == 3) {  // out(l-1) = prolongation of in1
+        Level& F = levels[l - 1];
+        run_convert<double, S>(t64, tz, bs, 1.0, stream);
+        S* fz = (S*)mem.alloc(F.box.size() * sizeof(S));
+        double* f64 = (double*)mem.alloc(F.box.size() * sizeof(double));
+        run_zero<S>(fz, F.box.size(), stream);
+        const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+        run_prolong<T, S>(level_dev(l - 1), D, mode, tz, fz, stream);
+        run_convert<S, double>(fz, f64, F.box.size(), 1.0, stream);
+        run_box_to_full(dim, F.n, F.box, f64, F.labels, 0.0, out, stream);
+        IIM_HIP(hipStreamSynchronize(stream));
+        mem.release(fz);
+        mem.release(f64);
+    } else {  // coarse direct solve
+        run_convert<double, T>(t64, tb, bs, h2, stream);
+        run_zero<S>(tz, bs, stream);
+        const T* Ainv = std::is_same<T, double>::value ? (const T*)Ainv64 : (const T*)Ainv32;
+        run_coarse_solve<T, S>(D, coarse_list, nc, Ainv, tb, tz, stream);
+        run_convert<S, double>(tz, t64, bs, 1.0, stream);
+        run_box_to_full(dim, L.n, L.box, t64, L.labels, 0.0, out, stream);
+    }
+    IIM_HIP(hipStreamSynchronize(stream));
+    mem.release(t64);
+    mem.release(tb);
+    mem.release(tz);
+    return IIM_OK;
+}
+
+int Problem::level_op(int l, int op, const double* in1, double* out) {
+    if (opt.precision == IIM_PREC_FP64) return level_op_t<double, double>(l, op, in1, out);
+    if (opt.precision == IIM_PREC_MIXED32) return level_op_t<float, float>(l, op, in1, out);
+    return level_op_t<float, __half>(l, op, in1, out);
+}
+
+Problem::~Problem() {
+    for (int i = 0; i < 8; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+}
+
+}  // namespace iim
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace iim;
+
+struct iim_problem {
+    std::unique_ptr<Problem> p;
+};
+
+#define ABI_TRY(...)                                               \
+    try {                                                          \
+        __VA_ARGS__;                                               \
+    } catch (const iim::Error& e) {                                \
+        iim::set_error(e.what());                                  \
+        return e.code;                                             \
+    } catch (const std::exception& e) {                            \
+        iim::set_error(std::string("internal error: ") + e.what()); \
+        return IIM_E_INTERNAL;                                     \
+    } catch (...) {                                                \
+        iim::set_error("internal error");                          \
+        return IIM_E_INTERNAL;                                     \
+    }
+
+extern "C" {
+
+int iim_default_options(iim_options* o) {
+    if (!o) return IIM_E_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->order_n = 4;
+    o->order_k = 5;
+    o->beta_plus = 1.0;
+    o->beta_minus = 1.0;
+    o->rtol = 1e-10;
+    o->max_iters = 500;
+    o->restart = 10;
+    o->nu_pre = 2;
+    o->nu_post = 2;
+    o->coarsest_n = 8;
+    o->precision = IIM_PREC_FP64;
+    o->ls_axis_t = 0.0;
+    o->ls_axis_n = 0.0;
+    o->use_graph = 0;
+    return IIM_OK;
+}
+
+const char* iim_last_error(void) { return iim::last_error(); }
+
+int iim_create(const iim_grid* g, const iim_geometry* geo, const iim_options* opt, void* stream, iim_problem** out) {
+    ABI_TRY({
+        iim::set_error("");
+        if (!g || !geo || !out) throw Error(IIM_E_INVALID_ARG, "null argument");
+        *out = nullptr;
+        iim_options o;
+        if (opt) o = *opt; else iim_default_options(&o);
+        if (g->dim != 2 && g->dim != 3) throw Error(IIM_E_INVALID_ARG, "dim must be 2 or 3");
+        if (g->n < 8 || g->n > 16384) throw Error(IIM_E_INVALID_ARG, "n out of range");
+        if (!(g->hi > g->lo)) throw Error(IIM_E_INVALID_ARG, "empty domain");
+        if (o.order_n != 4 || o.order_k != 5) throw Error(IIM_E_INVALID_ARG, "only the (4,5) discretisation is built");
+        if (o.restart < 1 || o.restart > 11) throw Error(IIM_E_INVALID_ARG, "restart must be in [1, 11]");
+        if (o.coarsest_n < 2) throw Error(IIM_E_INVALID_ARG, "coarsest_n must be >= 2");
+        if (o.precision < 0 || o.precision > 2) throw Error(IIM_E_INVALID_ARG, "bad precision");
+        if (!(o.beta_plus > 0) || !(o.beta_minus > 0)) throw Error(IIM_E_INVALID_ARG, "beta must be positive");
+        if ((geo->side == IIM_SIDE_INTERFACE) != (geo->bc == IIM_BC_JUMP))
+            throw Error(IIM_E_INVALID_ARG, "jump conditions go with interface problems");
+        if (geo->kind < 0 || geo->kind > 2 || geo->side < 0 || geo->side > 2 || geo->bc < 0 || geo->bc > 2)
+            throw Error(IIM_E_INVALID_ARG, "bad geometry enums");
+        if (geo->kind == IIM_GEOM_STAR2D && (g->dim != 2 || geo->nparams < 5))
+            throw Error(IIM_E_INVALID_ARG, "star needs dim 2 and 5 parameters");
+        if (geo->kind == IIM_GEOM_SPHERE && geo->nparams < g->dim + 1)
+            throw Error(IIM_E_INVALID_ARG, "sphere needs dim + 1 parameters");
+        if (geo->kind == IIM_GEOM_SPHERE_UNION &&
+            (geo->nparams < 1 || geo->nparams < 1 + (g->dim + 1) * (int)geo->params[0]))
+            throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
+        if (!geo->params) throw Error(IIM_E_INVALID_ARG, "null params");
+        if (geo->side != IIM_SIDE_INTERIOR) {
+            // box faces must coincide on every level
+            int n = g->n;
+            while (n > o.coarsest_n) {
+                if (n % 2) throw Error(IIM_E_INVALID_ARG, "exterior/interface problems need n = m 2^L with m <= coarsest_n");
+                n /= 2;
+            }
+        }
+        auto p = std::make_unique<Problem>();
+        p->stream = (hipStream_t)stream;
+        p->grid = *g;
+        p->opt = o;
+        p->dim = g->dim;
+        p->kind = geo->kind;
+        p->side = geo->side;
+        p->bc = geo->bc;
+        p->params.assign(geo->params, geo->params + geo->nparams);
+        p->setup();
+        auto* h = new iim_problem;
+        h->p = std::move(p);
+        *out = h;
+        return IIM_OK;
+    })
+}
+
+void iim_destroy(iim_problem* p) {
+    if (!p) return;
+    try {
+        if (p->p) (void)hipStreamSynchronize(p->p->stream);
+    } catch (...) {
+    }
+    delete p;
+}
+
+int iim_get_info(const iim_problem* h, iim_info* info) {
+    ABI_TRY({
+        if (!h || !info) throw Error(IIM_E_INVALID_ARG, "null argument");
+        const Problem& p = *h->p;
+        std::memset(info, 0, sizeof(*info));
+        info->dim = p.dim;
+        info->n = p.grid.n;
+        info->levels = (int)p.levels.size();
+        info->sides = p.nsides;
+        info->n_unknowns = p.levels[0].nunk;
+        info->n_control_points = p.cp.ncp;
+        info->n_ls_entries = p.nnz;
+        info->n_irregular = p.ho_nirr;
+        for (int d = 0; d < 3; ++d) {
+            info->box_lo[d] = p.box.lo[d];
+            info->box_dims[d] = p.box.dims[d];
+        }
+        info->device_bytes = (int64_t)p.mem.total;
+        info->t_setup_ms = p.t_setup_ms;
+        return IIM_OK;
+    })
+}
+
+int iim_control_points(const iim_problem* h, int64_t* count, double* xyz, double* normal) {
+    ABI_TRY({
+        if (!h || !count) throw Error(IIM_E_INVALID_ARG, "null argument");
+        const Problem& p = *h->p;
+        *count = p.cp.ncp;
+        if (!xyz && !normal) return IIM_OK;
+        const int64_t n = p.cp.ncp;
+        std::vector<double> x(3 * n), nv(3 * n);
+        IIM_HIP(hipMemcpyAsync(x.data(), p.cp.x, 3 * n * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+        IIM_HIP(hipMemcpyAsync(nv.data(), p.cp.n, 3 * n * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        for (int64_t c = 0; c < n; ++c)
+            for (int d = 0; d < p.dim; ++d) {
+                if (xyz) xyz[c * p.dim + d] = x[d * n + c];
+                if (normal) normal[c * p.dim + d] = nv[d * n + c];
+            }
+        return IIM_OK;
+    })
+}
+
+static void labels_to_full(const Problem& p, int level, uint8_t* out) {
+    const Level& L = p.levels[level];
+    std::vector<uint8_t> lab(L.box.size());
+    IIM_HIP(hipMemcpyAsync(lab.data(), L.labels, lab.size(), hipMemcpyDeviceToHost, p.stream));
+    IIM_HIP(hipStreamSynchronize(p.stream));
+    const int64_t n1 = L.n + 1;
+    const int64_t tot = p.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    for (int64_t f = 0; f < tot; ++f) {
+        int ijk[3] = {(int)(f % n1), (int)((f / n1) % n1), p.dim == 3 ? (int)(f / (n1 * n1)) : 0};
+        bool inb = true;
+        for (int d = 0; d < 3; ++d) inb = inb && ijk[d] >= L.box.lo[d] && ijk[d] < L.box.lo[d] + L.box.dims[d];
+        out[f] = inb ? (lab[L.box.idx(ijk[0], ijk[1], ijk[2])] & KIND_MASK) : 0;
+    }
+}
+
+int iim_node_labels(const iim_problem* h, uint8_t* labels) {
+    ABI_TRY({
+        if (!h || !labels) throw Error(IIM_E_INVALID_ARG, "null argument");
+        labels_to_full(*h->p, 0, labels);
+        return IIM_OK;
+    })
+}
+
+int iim_set_boundary_data(iim_problem* h, const double* cp_data, const double* box_data, int32_t mem_kind) {
+    ABI_TRY({
+        if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        const int64_t ncd = p.cp.ncp * (p.bc == IIM_BC_JUMP ? 2 : 1);
+        hipMemcpyKind k = mem_kind == IIM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        if (ncd) {
+            if (!cp_data) throw Error(IIM_E_INVALID_ARG, "cp_data is required");
+            IIM_HIP(hipMemcpyAsync(p.cpdata, cp_data, ncd * sizeof(double), k, p.stream));
+        }
+        if (box_data) {
+            const int64_t n1 = p.grid.n + 1;
+            const int64_t tot = p.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+            double* tmp = (double*)p.mem.alloc(tot * sizeof(double));
+            IIM_HIP(hipMemcpyAsync(tmp, box_data, tot * sizeof(double), k, p.stream));
+            run_full_to_box(p.dim, p.grid.n, p.box, tmp, p.boxval, p.levels[0].labels, 2, p.stream);
+            IIM_HIP(hipStreamSynchronize(p.stream));
+            p.mem.release(tmp);
+        } else {
+            IIM_HIP(hipMemsetAsync(p.boxval, 0, p.box.size() * sizeof(double), p.stream));
+        }
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        return IIM_OK;
+    })
+}
+
+int iim_set_rhs(iim_problem* h, const double* f, int32_t mem_kind) {
+    ABI_TRY({
+        if (!h || !f) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        const int64_t n1 = p.grid.n + 1;
+        const int64_t tot = p.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+        const double* src = f;
+        double* tmp = nullptr;
+        if (mem_kind != IIM_MEM_DEVICE) {
+            tmp = (double*)p.mem.alloc(tot * sizeof(double));
+            IIM_HIP(hipMemcpyAsync(tmp, f, tot * sizeof(double), hipMemcpyHostToDevice, p.stream));
+            src = tmp;
+        }
+        // b = f - L_Gamma u_Gamma = f - apply(0, with data)
+        run_full_to_box(p.dim, p.grid.n, p.box, src, p.rhs, p.levels[0].labels, 1, p.stream);
+        IIM_HIP(hipMemsetAsync(p.xk, 0, p.box.size() * sizeof(double), p.stream));
+        p.apply_box(p.xk, p.wk, 1);
+        run_axpby(-1.0, p.wk, 1.0, p.rhs, p.box.size(), p.stream);
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        if (tmp) p.mem.release(tmp);
+        return IIM_OK;
+    })
+}
+
+int iim_solve(iim_problem* h, double* u, const double* x0, double* hist, int32_t hist_cap, iim_stats* st) {
+    ABI_TRY({
+        if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
+        int r = h->p->solve(u, x0, hist, hist_cap, st);
+        if (r == IIM_E_BREAKDOWN) iim::set_error("FGMRES breakdown (non-finite value)");
+        if (r == IIM_NOT_CONVERGED) iim::set_error("FGMRES reached max_iters");
+        return r;
+    })
+}
+
+int iim_apply(iim_problem* h, const double* x, double* y, int32_t with_data) {
+    ABI_TRY({
+        if (!h || !x || !y) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        run_full_to_box(p.dim, p.grid.n, p.box, x, p.rk, p.levels[0].labels, 1, p.stream);
+        p.apply_box(p.rk, p.wk, with_data);
+        run_box_to_full(p.dim, p.grid.n, p.box, p.wk, p.levels[0].labels, 0.0, y, p.stream);
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        return IIM_OK;
+    })
+}
+
+int iim_vcycle(iim_problem* h, const double* v, double* z) {
+    ABI_TRY({
+        if (!h || !v || !z) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        run_full_to_box(p.dim, p.grid.n, p.box, v, p.rk, p.levels[0].labels, 1, p.stream);
+        p.vcycle(p.rk, p.wk);
+        run_box_to_full(p.dim, p.grid.n, p.box, p.wk, p.levels[0].labels, 0.0, z, p.stream);
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        return IIM_OK;
+    })
+}
+
+int iim_ls_stencil(const iim_problem* h, int64_t c, int32_t side, int32_t* m, int32_t* r, int64_t* idx, double* wts,
+                   int32_t cap) {
+    ABI_TRY({
+        if (!h || !m || !r) throw Error(IIM_E_INVALID_ARG, "null argument");
+        const Problem& p = *h->p;
+        if (c < 0 || c >= p.cp.ncp) throw Error(IIM_E_INVALID_ARG, "control point out of range");
+        if (side != 1 && !(side == 2 && p.nsides == 2)) throw Error(IIM_E_INVALID_ARG, "bad side");
+        const int64_t cs = c * p.nsides + (side == 1 ? 0 : 1);
+        const int64_t b0 = p.h_ptr[cs], b1 = p.h_ptr[cs + 1];
+        *m = (int32_t)(b1 - b0);
+        *r = p.nrows;
+        if (!idx && !wts) return IIM_OK;
+        if (*m + 1 > cap) throw Error(IIM_E_INVALID_ARG, "capacity too small");
+        std::vector<int32_t> li(b1 - b0);
+        std::vector<double> sc(p.nrows), s((size_t)p.nrows * (b1 - b0));
+        if (b1 > b0) IIM_HIP(hipMemcpyAsync(li.data(), p.ls_idx + b0, (b1 - b0) * sizeof(int32_t), hipMemcpyDeviceToHost, p.stream));
+        IIM_HIP(hipMemcpyAsync(sc.data(), p.ls_Sc + cs * p.nrows, p.nrows * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+        for (int k = 0; k < p.nrows; ++k)
+            if (b1 > b0)
+                IIM_HIP(hipMemcpyAsync(s.data() + (size_t)k * (b1 - b0), p.ls_S + (size_t)k * p.nnz + b0,
+                                       (b1 - b0) * sizeof(double), hipMemcpyDeviceToHost, p.stream));
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        const int64_t n1 = p.grid.n + 1;
+        for (int64_t a = 0; a < b1 - b0; ++a) {
+            int ijk[3];
+            p.box.coords(li[a], ijk);
+            if (idx) idx[a] = ijk[0] + n1 * (ijk[1] + n1 * (int64_t)ijk[2]);
+        }
+        if (wts) {
+            for (int k = 0; k < p.nrows; ++k) {
+                wts[k] = sc[k];
+                for (int64_t a = 0; a < b1 - b0; ++a) wts[(1 + a) * p.nrows + k] = s[(size_t)k * (b1 - b0) + a];
+            }
+        }
+        return IIM_OK;
+    })
+}
+
+int iim_level_info(const iim_problem* h, int32_t level, int32_t* n, int64_t* nunk) {
+    ABI_TRY({
+        if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
+        const Problem& p = *h->p;
+        if (level < 0 || level >= (int)p.levels.size()) throw Error(IIM_E_INVALID_ARG, "level out of range");
+        if (n) *n = p.levels[level].n;
+        if (nunk) *nunk = p.levels[level].nunk;
+        return IIM_OK;
+    })
+}
+
+int iim_level_labels(const iim_problem* h, int32_t level, uint8_t* labels) {
+    ABI_TRY({
+        if (!h || !labels) throw Error(IIM_E_INVALID_ARG, "null argument");
+        const Problem& p = *h->p;
+        if (level < 0 || level >= (int)p.levels.size()) throw Error(IIM_E_INVALID_ARG, "level out of range");
+        labels_to_full(p, level, labels);
+        return IIM_OK;
+    })
+}
+
+int iim_level_op(iim_problem* h, int32_t level, int32_t op, const double* in1, double* out) {
+    ABI_TRY({
+        if (!h || !in1 || !out) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        return p.level_op(level, op, in1, out);
+    })
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// Host-side launch wrappers of the HIP kernels (one declaration per kernel family).
+#pragma once
+
+#include "common.h"
+
+namespace iim {
+
+// ---- setup (setup.hip) -----------------------------------------------------
+// Classify every node of the level's full grid; bbox = {min x,y,z, max x,y,z}
+// of the unknowns (atomics on integers: order independent), err != 0 when the
+// body touches the box, count = number of unknowns.
+void run_classify_bbox(const Geom& g, int* d_bbox, int* d_err, unsigned long long* d_count,
+                       hipStream_t s);
+void run_box_labels(const Geom& g, const Box& b, uint8_t* labels, hipStream_t s);
+// crossing flags along one axis: flags[l] = 1 if the segment (l, l + e_axis) carries a control point
+void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, int axis, uint8_t* flags,
+                  hipStream_t s);
+// indices l with flags[l] != 0, in increasing order; returns the count (synchronises)
+int64_t select_flagged(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
+                       int64_t* d_count, hipStream_t s);
+size_t select_tmp_bytes(int64_t n);
+
+struct CPDev {
+    int64_t ncp;
+    int nsides;
+    int axis_start[4];   // cps of axis d: [axis_start[d], axis_start[d+1])
+    int32_t* lower;      // local index of the lower node of the segment
+    int32_t* axis;
+    int32_t* a;          // [nsides][ncp] local index of the side's adjacent unknown
+    int32_t* dir;        // [nsides][ncp] step from that node towards Gamma
+    double* x;           // [3][ncp]
+    double* n;           // [3][ncp]
+    double* kappa;       // [ncp]
+};
+void run_cp_compute(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
+                    int* d_err, hipStream_t s);
+
+// high-order irregular nodes (level 0)
+void run_ho_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s);
+void run_ho_irr_records(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
+                        const int32_t* nodes, int64_t nirr, int32_t* slots, int32_t* irr_index,
+                        int* d_err, hipStream_t s);
+
+// Shortley-Weller rows of one level: flags of irregular unknowns, then their rows
+// rec[k * (1 + 2 dim)] = {diag, coefficient of neighbour (d, -), (d, +), ...} scaled by h^2
+void run_sw_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s);
+void run_sw_records(const Geom& g, const Box& b, const uint8_t* labels, const int32_t* nodes,
+                    int64_t nirr, int bc, double beta_plus, double beta_minus, double* rec64,
+                    float* rec32, int32_t* irr_index, hipStream_t s);
+// dense scaled SW matrix on the coarsest level (rows/cols = listed unknowns), then its inverse
+void run_coarse_assemble(const Box& b, int dim, const uint8_t* labels, const int32_t* irr_index,
+                         const double* rec64, const int32_t* list, const int32_t* col_of, int64_t nc,
+                         double* A, hipStream_t s);
+void run_coarse_invert(double* A, double* Ainv, int64_t nc, int* d_err, hipStream_t s);
+void run_fill_int(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// ---- least squares (lsq.hip) -------------------------------------------------
+struct LSParams {
+    int dim, order_k, w, nrows;  // nrows = w (+1 with the normal derivative)
+    int nsides;
+    double a0, b0;               // initial semi-axes (units of h)
+    int max_grow;
+    int mcap;                    // capacity of the per-wave scratch (rows)
+};
+// pass 0: sizes (m, growth) per control point side; pass 1: fill idx / weights
+void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P,
+            int pass, int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx,
+            double* S, double* Sc, double* scratch, int64_t scratch_waves, int* d_err, hipStream_t s);
+
+// ---- operators (ops.hip) -------------------------------------------------------
+struct GhostDev {
+    int bc, nsides, w, nrows;
+    double beta_plus, beta_minus;
+    const int64_t* ptr;   // [ncs + 1]
+    const int32_t* idx;   // [nnz] local indices
+    const double* W;      // [nrows][nnz] apply weights
+    const double* Sc;     // [ncs][nrows] weights of u(x_c) (raw)
+    const double* dcoef;  // [ncs][w] data coefficients (Dirichlet / Neumann)
+    int64_t nnz, ncp;
+};
+void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
+                hipStream_t s);
+void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
+                  const int32_t* irr_index, const int32_t* slots, const double* ghost, const double* boxval,
+                  int w, double inv_h2, double beta_plus, double beta_minus, const double* x, double* y,
+                  int with_data, hipStream_t s);
+
+// V-cycle kernels; T = arithmetic type, S = iterate storage type
+struct LevelDev {
+    int dim, n;
+    Box box;
+    int core_lo[3], core_hi[3];
+    const uint8_t* labels;
+    const int32_t* irr_index;
+    const double* rec64;
+    const float* rec32;
+};
+template <typename T, typename S>
+void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s);
+template <typename T, typename S>
+void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const T* b, T* bc, hipStream_t s);
+template <typename T, typename S>
+void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S* z, hipStream_t s);
+template <typename T, typename S>
+void run_sw_apply(const LevelDev& L, const S* z, T* y, hipStream_t s);
+template <typename T, typename S>
+void run_coarse_solve(const LevelDev& L, const int32_t* list, int64_t nc, const T* Ainv, const T* b, S* z,
+                      hipStream_t s);
+template <typename S>
+void run_zero(S* p, int64_t n, hipStream_t s);
+
+// casts at the precision boundary: rhs0 = scale * h2 * v / beta(node); v FP64, level-0 box
+template <typename T>
+void run_cast_in(const LevelDev& L, const double* v, const double* scale_dev, double h2, double beta_plus,
+                 double beta_minus, T* rhs, hipStream_t s);
+template <typename S>
+void run_cast_out(const LevelDev& L, const S* z, const double* scale_dev, double* out, hipStream_t s);
+
+// apply weights from the raw stencils (Neumann closure folded in) and data coefficients
+void run_apply_weights(int bc, const int64_t* ptr, int64_t ncs, int w, int nrows, const double* S, const double* Sc,
+                       double beta, int64_t nnz, double* W, double* dcoef, hipStream_t s);
+// b[i] = scale * a[i] with conversion between double, float and half
+template <typename A, typename B>
+void run_convert(const A* a, B* b, int64_t n, double scale, hipStream_t s);
+
+// full grid <-> storage box
+void run_full_to_box(int dim, int n, const Box& b, const double* full, double* boxed, const uint8_t* labels,
+                     int only_unknowns, hipStream_t s);
+void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const uint8_t* labels, double fill,
+                     double* full, hipStream_t s);
+
+// ---- vector kernels (blas.hip) ---------------------------------------------------
+// Deterministic reductions: a fixed grid of RED_BLOCKS blocks, per-block partials
+// combined in a fixed order by a single-block second stage.
+constexpr int RED_BLOCKS = 512;
+constexpr int RED_THREADS = 256;
+// out[i] = <V_i, w> for i < k; V_i = V + i * ld
+void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* part, double* out,
+                  hipStream_t s);
+// w -= sum_{i<k} h[i] V_i; then out[i] = <V_i, w> for i < k2 and out[k2] = <w, w> (if with_norm)
+void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
+                    int with_norm, double* part, double* out, hipStream_t s);
+// y = x / sqrt(*nrm2)
+void run_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
+// x += sum_{i<k} y[i] Z_i  (y on the device)
+void run_axpy_multi(const double* Z, int64_t ld, int k, const double* y, double* x, int64_t n, hipStream_t s);
+// y = a x + b y
+void run_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
+void run_copy(const double* x, double* y, int64_t n, hipStream_t s);
+// out[0] = max |x|, out[1] = 1 / max|x| (1 if zero)
+void run_absmax(const double* x, int64_t n, double* part, double* out, hipStream_t s);
+// out[0] = <x, x>
+void run_norm2(const double* x, int64_t n, double* part, double* out, hipStream_t s);
+
+}  // namespace iim

@@ -1,0 +1,322 @@
+// Least-squares ghost stencils, one wavefront per control point and side
+// (Sec. 2.1-2.2 of the paper).
+//
+// The interpolation set holds x_c, then the side's unknowns inside the
+// half-ellipse (2D) / half-ellipsoid (3D) with tangential semi-axis a and
+// normal semi-axis b (units of h), in increasing flat order, minus the one
+// closest to x_c.  The monomials of total degree <= k-1 in xi = (y - x_c)/(a h)
+// form A; one Householder QR A = QR gives every stencil as s = Q R^{-T} e
+// (one triangular solve and one product with Q per stencil).
+//
+// Wave layout: candidates of the search window are visited 64 at a time in
+// increasing flat order and compacted with a ballot, so the set order is the
+// flat order regardless of timing; the QR keeps A column-major in a per-wave
+// global scratch slab (lanes own rows); every reduction is a fixed xor
+// butterfly, so results do not depend on scheduling.
+#include "kernels.h"
+
+namespace iim {
+
+constexpr int LS_MAXC = 1024;  // candidates kept per set (LDS list)
+constexpr double SET_TOL = 1e-12;
+constexpr double RANK_TOL = 1e-10;
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ inline double wave_min(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// monomial exponents of total degree <= deg: 2D (i, t-i) i = t..0; 3D (i, j, t-i-j)
+__device__ inline int monomials(int dim, int deg, int (*e)[3]) {
+    int c = 0;
+    for (int t = 0; t <= deg; ++t) {
+        if (dim == 2) {
+            for (int i = t; i >= 0; --i) {
+                e[c][0] = i;
+                e[c][1] = t - i;
+                e[c][2] = 0;
+                ++c;
+            }
+        } else {
+            for (int i = t; i >= 0; --i)
+                for (int j = t - i; j >= 0; --j) {
+                    e[c][0] = i;
+                    e[c][1] = j;
+                    e[c][2] = t - i - j;
+                    ++c;
+                }
+        }
+    }
+    return c;
+}
+
+__device__ inline double ipow(double x, int e) {
+    double r = 1.0;
+    for (int i = 0; i < e; ++i) r *= x;
+    return r;
+}
+
+__global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels, CPDev cp, LSParams P, int pass,
+                                           int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx_out,
+                                           double* S_out, double* Sc_out, double* scratch, int* err) {
+    __shared__ int32_t list_idx[LS_MAXC];
+    __shared__ double list_r2[LS_MAXC];
+    __shared__ int ex[84][3];
+    __shared__ double tauv[84];
+    __shared__ double Y[84][4];
+    __shared__ double E[4][84];
+    const int lane = threadIdx.x;
+    const int K = P.order_k;
+    const int p = g.dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
+    if (lane == 0) monomials(g.dim, K - 1, ex);
+    __syncthreads();
+    const int64_t ncs = cp.ncp * P.nsides;
+    const int mcap = P.mcap;
+    double* Acol = scratch + (int64_t)blockIdx.x * (int64_t)(p + 4) * mcap;  // [p][mcap] then s [4][mcap]
+    double* Scol = Acol + (int64_t)p * mcap;
+
+    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
+        const int64_t c = cs / P.nsides;
+        const int sidx = (int)(cs % P.nsides);
+        const uint8_t side = sidx == 0 ? K_PLUS : K_MINUS;
+        double xc[3], nrm[3], nu[3];
+        for (int d = 0; d < 3; ++d) {
+            xc[d] = cp.x[d * cp.ncp + c];
+            nrm[d] = cp.n[d * cp.ncp + c];
+            nu[d] = sidx == 0 ? nrm[d] : -nrm[d];
+        }
+        const int axis = cp.axis[c];
+        const int64_t anode = cp.a[sidx * cp.ncp + c];
+        const int adir = cp.dir[sidx * cp.ncp + c];
+        int g0 = 0, g1 = P.max_grow;
+        if (pass == 1) {
+            g0 = g1 = grow_out[cs];
+            if (g0 < 0) continue;
+        }
+        bool done = false;
+        for (int grow = g0; grow <= g1 && !done; ++grow) {
+            const double a = P.a0 + 0.5 * grow, bb = P.b0 + 0.5 * grow;
+            const int R = (int)ceil(fmax(a, bb)) + 1;
+            int wlo[3] = {0, 0, 0}, wlen[3] = {1, 1, 1};
+            for (int d = 0; d < g.dim; ++d) {
+                int ci = (int)floor((xc[d] - g.lo) / g.h + 0.5);
+                int lo = max(0, ci - R), hi = min(g.n, ci + R);
+                wlo[d] = lo;
+                wlen[d] = hi - lo + 1;
+            }
+            const int total = wlen[0] * wlen[1] * wlen[2];
+            int count = 0;
+            bool overflow = false;
+            for (int base = 0; base < total; base += 64) {
+                int t = base + lane;
+                bool keep = false;
+                int32_t lidx = 0;
+                double r2 = 0.0;
+                if (t < total) {
+                    int ijk[3] = {wlo[0] + t % wlen[0], wlo[1] + (t / wlen[0]) % wlen[1], wlo[2] + t / (wlen[0] * wlen[1])};
+                    bool inbox = true;
+                    for (int d = 0; d < 3; ++d) inbox = inbox && ijk[d] >= b.lo[d] && ijk[d] < b.lo[d] + b.dims[d];
+                    if (inbox) {
+                        lidx = (int32_t)b.idx(ijk[0], ijk[1], ijk[2]);
+                        if ((labels[lidx] & KIND_MASK) == side) {
+#pragma clang fp contract(off)
+                            double nn = 0.0;
+                            for (int d = 0; d < g.dim; ++d) {
+                                double delta = (node_coord(g, ijk[d]) - xc[d]) / g.h;
+                                nn += delta * nu[d];
+                                r2 += delta * delta;
+                            }
+                            double t2 = fmax(r2 - nn * nn, 0.0);
+                            keep = (nn >= -SET_TOL) && (t2 / (a * a) + nn * nn / (bb * bb) <= 1.0 + SET_TOL);
+                        }
+                    }
+                }
+                unsigned long long mask = __ballot(keep);
+                int before = __popcll(mask & ((1ull << lane) - 1ull));
+                if (keep) {
+                    int pos = count + before;
+                    if (pos < LS_MAXC) {
+                        list_idx[pos] = lidx;
+                        list_r2[pos] = r2;
+                    }
+                }
+                count += __popcll(mask);
+                if (count > LS_MAXC) overflow = true;
+            }
+            __syncthreads();
+            if (overflow) {
+                if (lane == 0) atomicOr(err, 32);
+                break;
+            }
+            if (count == 0) continue;  // no candidates: grow
+            // closest candidate: minimal r2, ties within SET_TOL to the lowest index (first in list)
+            double dmin = 1e300;
+            for (int i = lane; i < count; i += 64) dmin = fmin(dmin, list_r2[i]);
+            dmin = wave_min(dmin);
+            int closest = count;
+            for (int i = lane; i < count; i += 64)
+                if (list_r2[i] <= dmin + SET_TOL) closest = min(closest, i);
+            for (int off = 32; off > 0; off >>= 1) closest = min(closest, __shfl_xor(closest, off, 64));
+            const int m = count - 1;
+            const int M = m + 1;  // rows: x_c then the m points
+            if (M < p) continue;  // too few points: grow
+            if (M > mcap) {
+                if (lane == 0) atomicOr(err, 32);
+                break;
+            }
+            // assemble A (column-major), row 0 = x_c
+            const double sc = a * g.h;
+            for (int r = lane; r < M; r += 64) {
+                double xi[3] = {0.0, 0.0, 0.0};
+                if (r > 0) {
+                    int li = list_idx[r - 1 + (r - 1 >= closest ? 1 : 0)];
+                    int ijk[3];
+                    b.coords(li, ijk);
+                    for (int d = 0; d < g.dim; ++d) xi[d] = (node_coord(g, ijk[d]) - xc[d]) / sc;
+                }
+                for (int col = 0; col < p; ++col)
+                    Acol[(int64_t)col * mcap + r] = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) *
+                                                   ipow(xi[2], ex[col][2]);
+            }
+            __syncthreads();
+            // Householder QR
+            double rmax = 0.0, rmin = 1e300;
+            for (int col = 0; col < p; ++col) {
+                double* v = Acol + (int64_t)col * mcap;
+                double s = 0.0;
+                for (int r = col + 1 + lane; r < M; r += 64) s += v[r] * v[r];
+                s = wave_sum(s);
+                double alpha = v[col];
+                double norm = sqrt(alpha * alpha + s);
+                double tau = 0.0, beta = alpha;
+                if (s != 0.0) {
+                    beta = alpha >= 0.0 ? -norm : norm;
+                    tau = (beta - alpha) / beta;
+                    double inv = 1.0 / (alpha - beta);
+                    for (int r = col + 1 + lane; r < M; r += 64) v[r] *= inv;
+                }
+                __syncthreads();
+                if (lane == 0) {
+                    v[col] = beta;
+                    tauv[col] = tau;
+                }
+                rmax = fmax(rmax, fabs(beta));
+                rmin = fmin(rmin, fabs(beta));
+                for (int c2 = col + 1; c2 < p; ++c2) {
+                    double* u = Acol + (int64_t)c2 * mcap;
+                    double dot = 0.0;
+                    for (int r = col + 1 + lane; r < M; r += 64) dot += v[r] * u[r];
+                    dot = wave_sum(dot) + u[col];
+                    double f = tau * dot;
+                    __syncthreads();
+                    if (lane == 0) u[col] -= f;
+                    for (int r = col + 1 + lane; r < M; r += 64) u[r] -= f * v[r];
+                }
+                __syncthreads();
+            }
+            if (rmin < RANK_TOL * rmax) continue;  // rank deficient: grow
+            done = true;
+            if (pass == 0) {
+                if (lane == 0) {
+                    m_out[cs] = m;
+                    grow_out[cs] = grow;
+                }
+                break;
+            }
+            // evaluation functionals: ghosts j = 1..w at anode + j adir e_axis, then d/dn
+            int acoord[3];
+            b.coords(anode, acoord);
+            double xa[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, acoord[d]);
+            for (int k = 0; k < P.nrows; ++k)
+                for (int col = lane; col < p; col += 64) {
+                    double val;
+                    if (k < P.w) {
+                        double xg[3] = {xa[0], xa[1], xa[2]};
+                        xg[axis] = xa[axis] + (double)((k + 1) * adir) * g.h;
+                        double xi[3] = {0.0, 0.0, 0.0};
+                        for (int d = 0; d < g.dim; ++d) xi[d] = (xg[d] - xc[d]) / sc;
+                        val = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) * ipow(xi[2], ex[col][2]);
+                    } else {
+                        int deg = ex[col][0] + ex[col][1] + ex[col][2];
+                        val = 0.0;
+                        if (deg == 1) {
+                            int d = ex[col][0] ? 0 : (ex[col][1] ? 1 : 2);
+                            val = nrm[d] / sc;
+                        }
+                    }
+                    E[k][col] = val;
+                }
+            __syncthreads();
+            // R^T Y = E^T (forward substitution), one lane per functional
+            if (lane < P.nrows) {
+                for (int i = 0; i < p; ++i) {
+                    double acc = E[lane][i];
+                    for (int l2 = 0; l2 < i; ++l2) acc -= Acol[(int64_t)i * mcap + l2] * Y[l2][lane];
+                    Y[i][lane] = acc / Acol[(int64_t)i * mcap + i];
+                }
+            }
+            __syncthreads();
+            // s = Q [Y; 0]: apply the reflectors in reverse order
+            for (int k = 0; k < P.nrows; ++k)
+                for (int r = lane; r < M; r += 64) Scol[(int64_t)k * mcap + r] = r < p ? Y[r][k] : 0.0;
+            __syncthreads();
+            for (int col = p - 1; col >= 0; --col) {
+                const double* v = Acol + (int64_t)col * mcap;
+                double tau = tauv[col];
+                double dots[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int k = 0; k < P.nrows; ++k) {
+                    const double* s = Scol + (int64_t)k * mcap;
+                    double d0 = 0.0;
+                    for (int r = col + 1 + lane; r < M; r += 64) d0 += v[r] * s[r];
+                    dots[k] = wave_sum(d0) + s[col];
+                }
+                __syncthreads();
+                for (int k = 0; k < P.nrows; ++k) {
+                    double* s = Scol + (int64_t)k * mcap;
+                    double f = tau * dots[k];
+                    if (lane == 0) s[col] -= f;
+                    for (int r = col + 1 + lane; r < M; r += 64) s[r] -= f * v[r];
+                }
+                __syncthreads();
+            }
+            // write: Sc[cs][k] (weight of u(x_c)), S[k][ptr + alpha], idx
+            const int64_t base = ptr[cs];
+            const int64_t nnz = ptr[ncs];
+            if (ptr[cs + 1] - base != m) {  // both passes enumerate the same set
+                if (lane == 0) atomicOr(err, 256);
+                break;
+            }
+            if (lane < P.nrows) Sc_out[cs * P.nrows + lane] = Scol[(int64_t)lane * mcap];
+            for (int r = 1 + lane; r < M; r += 64) {
+                int li = list_idx[r - 1 + (r - 1 >= closest ? 1 : 0)];
+                idx_out[base + r - 1] = li;
+                for (int k = 0; k < P.nrows; ++k) S_out[(int64_t)k * nnz + base + r - 1] = Scol[(int64_t)k * mcap + r];
+            }
+            __syncthreads();
+        }
+        if (!done && pass == 0 && lane == 0) {
+            m_out[cs] = 0;
+            grow_out[cs] = -1;
+            atomicOr(err, 128);
+        }
+        __syncthreads();
+    }
+}
+
+void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P, int pass,
+            int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx, double* S, double* Sc,
+            double* scratch, int64_t scratch_waves, int* d_err, hipStream_t s) {
+    int64_t ncs = cp.ncp * P.nsides;
+    if (ncs == 0) return;
+    int blocks = (int)std::min<int64_t>(ncs, scratch_waves);
+    hipLaunchKernelGGL(k_ls, dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr, idx, S,
+                       Sc, scratch, d_err);
+    IIM_LAUNCH_CHECK();
+}
+
+}  // namespace iim

@@ -1,0 +1,580 @@
+// Hot-path operators: ghost values and the high-order apply (Sec. 2.1-2.3),
+// and the Shortley-Weller V-cycle kernels (Sec. 3.1, 3.3).
+//
+// Storage: every level keeps its vectors in a padded bounding box of its
+// unknowns (x fastest); nodes that are not unknowns hold zero, so regular
+// stencils need no masks.  Nodes whose stencil differs from the constant one
+// carry a flag in their label byte and an index into a compact record list.
+#include "kernels.h"
+
+namespace iim {
+
+// ---------------------------------------------------------------------------
+// ghost values: one 16-lane group per control point (all its sides)
+// ---------------------------------------------------------------------------
+constexpr int GL = 16;
+
+__global__ void __launch_bounds__(256) k_ghosts(GhostDev G, const double* x, const double* cpdata, int with_data,
+                                                double* ghost) {
+    const int lane = threadIdx.x % GL;
+    const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / GL;
+    if (c >= G.ncp) return;  // whole 16-lane groups exit together
+    double dots[2][4];
+    for (int s = 0; s < G.nsides; ++s) {
+        int64_t cs = c * G.nsides + s;
+        int64_t b0 = G.ptr[cs], b1 = G.ptr[cs + 1];
+        for (int k = 0; k < 4; ++k) dots[s][k] = 0.0;
+        for (int64_t a = b0 + lane; a < b1; a += GL) {
+            double xv = x[G.idx[a]];
+            for (int k = 0; k < G.nrows; ++k) dots[s][k] += G.W[k * G.nnz + a] * xv;
+        }
+        for (int k = 0; k < G.nrows; ++k)
+            for (int off = GL / 2; off > 0; off >>= 1) dots[s][k] += __shfl_xor(dots[s][k], off, GL);
+    }
+    if (lane != 0) return;
+    const int w = G.w;
+    if (G.bc != IIM_BC_JUMP) {
+        for (int j = 0; j < w; ++j) {
+            double gv = dots[0][j];
+            if (with_data) gv += G.dcoef[c * w + j] * cpdata[c];
+            ghost[c * w + j] = gv;
+        }
+        return;
+    }
+    // interface: Sec. 2.2 closed form with D = beta+ s_c+ - beta- s_c-
+    const int R = G.nrows;  // w ghosts + normal derivative
+    const double* scp = G.Sc + (c * 2 + 0) * R;
+    const double* scm = G.Sc + (c * 2 + 1) * R;
+    double bp = G.beta_plus, bm = G.beta_minus;
+    double D = bp * scp[w] - bm * scm[w];
+    double ubar = -(bp * dots[0][w] - bm * dots[1][w]) / D;
+    double Up = ubar, Um = ubar;
+    if (with_data) {
+        double j0 = cpdata[2 * c], j1 = cpdata[2 * c + 1];
+        Up += (j1 - bm * scm[w] * j0) / D;
+        Um += (j1 - bp * scp[w] * j0) / D;
+    }
+    for (int j = 0; j < w; ++j) {
+        ghost[(c * 2 + 0) * w + j] = scp[j] * Up + dots[0][j];
+        ghost[(c * 2 + 1) * w + j] = scm[j] * Um + dots[1][j];
+    }
+}
+
+void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
+                hipStream_t s) {
+    if (G.ncp == 0) return;
+    int64_t threads = G.ncp * GL;
+    hipLaunchKernelGGL(k_ghosts, dim3(cdiv(threads, 256)), dim3(256), 0, s, G, x, cpdata, with_data, ghost);
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// high-order apply: y = beta/h^2 sum_d sum_j a_|j| u~(i + j e_d)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, const uint8_t* __restrict__ labels,
+                                                  const int32_t* __restrict__ irr_index,
+                                                  const int32_t* __restrict__ slots, const double* __restrict__ ghost,
+                                                  const double* __restrict__ boxval, int w, double inv_h2, double bp,
+                                                  double bm, const double* __restrict__ x, double* __restrict__ y,
+                                                  int with_data) {
+    int i = clo.x + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = clo.y + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? clo.z + blockIdx.z : 0;
+    if (i > chi.x || j > chi.y) return;
+    const int64_t l = b.idx(i, j, k);
+    const uint8_t lab = labels[l];
+    const uint8_t kind = lab & KIND_MASK;
+    if (kind != K_PLUS && kind != K_MINUS) {
+        y[l] = 0.0;
+        return;
+    }
+    const double beta = (kind == K_PLUS) ? bp : bm;
+    const int64_t st[3] = {1, (int64_t)b.dims[0], (int64_t)b.dims[0] * b.dims[1]};
+    const double xc = x[l];
+    double acc = (double)DIM * A0 * xc;
+    if (!(lab & F_HO_IRR)) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            acc += A1 * (x[l + st[d]] + x[l - st[d]]) + A2 * (x[l + 2 * st[d]] + x[l - 2 * st[d]]);
+        y[l] = beta * inv_h2 * acc;
+        return;
+    }
+    const int32_t* rec = slots + (int64_t)irr_index[l] * 2 * DIM;
+    for (int d = 0; d < DIM; ++d)
+        for (int t = 0; t < 2; ++t) {
+            const int dir = t ? 1 : -1;
+            const int64_t sd = dir * st[d];
+            const int slot = rec[2 * d + t];
+            const int type = slot_type(slot), j0 = slot_j(slot);
+            double v[2];
+            for (int jj = 1; jj <= 2; ++jj) {
+                const int64_t q = l + jj * sd;
+                double val;
+                if (type == SLOT_REG || jj < j0) {
+                    val = x[q];
+                } else if (type == SLOT_GHOST) {
+                    uint8_t kq = labels[q] & KIND_MASK;
+                    if (kq == kind)
+                        val = x[q];  // back on the stencil's side beyond a sliver
+                    else if (kq == K_BOX)
+                        val = with_data ? boxval[q] : 0.0;
+                    else
+                        val = ghost[(int64_t)slot_cs(slot) * w + (jj - j0)];
+                } else {  // box face at offset j0
+                    const int64_t face = l + j0 * sd;
+                    const double fv = with_data ? boxval[face] : 0.0;
+                    if (jj == j0) {
+                        val = fv;
+                    } else {
+                        // degree-4 Lagrange extrapolation one step beyond the face
+                        val = 5.0 * fv - 10.0 * x[face - sd] + 10.0 * x[face - 2 * sd] - 5.0 * x[face - 3 * sd] +
+                              x[face - 4 * sd];
+                    }
+                }
+                v[jj - 1] = val;
+            }
+            acc += A1 * v[0] + A2 * v[1];
+        }
+    y[l] = beta * inv_h2 * acc;
+}
+
+void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
+                  const int32_t* irr_index, const int32_t* slots, const double* ghost, const double* boxval, int w,
+                  double inv_h2, double beta_plus, double beta_minus, const double* x, double* y, int with_data,
+                  hipStream_t s) {
+    int3 lo = make_int3(core_lo[0], core_lo[1], core_lo[2]);
+    int3 hi = make_int3(core_hi[0], core_hi[1], core_hi[2]);
+    int nx = hi.x - lo.x + 1, ny = hi.y - lo.y + 1, nz = hi.z - lo.z + 1;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return;
+    dim3 blk(64, 4, 1);
+    dim3 grd(cdiv(nx, 64), cdiv(ny, 4), dim == 3 ? nz : 1);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_ho_apply<2>, grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval, w, inv_h2,
+                           beta_plus, beta_minus, x, y, with_data);
+    else
+        hipLaunchKernelGGL(k_ho_apply<3>, grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval, w, inv_h2,
+                           beta_plus, beta_minus, x, y, with_data);
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Shortley-Weller level kernels (scaled rows: h^2 x operator)
+// ---------------------------------------------------------------------------
+template <typename T> __device__ inline const T* rec_ptr(const LevelDev& L);
+template <> __device__ inline const float* rec_ptr<float>(const LevelDev& L) { return L.rec32; }
+template <> __device__ inline const double* rec_ptr<double>(const LevelDev& L) { return L.rec64; }
+
+__device__ inline float to_f(float v) { return v; }
+__device__ inline float to_f(__half v) { return __half2float(v); }
+__device__ inline __half from_f(float v, __half*) { return __float2half(v); }
+__device__ inline float from_f(float v, float*) { return v; }
+
+// load an iterate of storage type S as arithmetic type T
+template <typename T, typename S> __device__ inline T load_it(const S* p, int64_t i) { return (T)to_f(p[i]); }
+template <> __device__ inline double load_it<double, double>(const double* p, int64_t i) { return p[i]; }
+
+// store a value of arithmetic type T into storage type S
+template <typename T, typename S> __device__ inline void store_t(S* p, int64_t i, T v) {
+    p[i] = from_f((float)v, (S*)nullptr);
+}
+template <> __device__ inline void store_t<double, double>(double* p, int64_t i, double v) { p[i] = v; }
+
+// (A' z)(l) and the diagonal at an unknown l; off-diagonal sum returned in *off
+template <typename T, typename S, int DIM>
+__device__ inline void sw_row(const LevelDev& L, int64_t l, uint8_t lab, const S* z, T* diag, T* off) {
+    const int64_t st[3] = {1, (int64_t)L.box.dims[0], (int64_t)L.box.dims[0] * L.box.dims[1]};
+    T acc = 0;
+    if (!(lab & F_SW_IRR)) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) acc += load_it<T, S>(z, l + st[d]) + load_it<T, S>(z, l - st[d]);
+        *diag = (T)(-2 * DIM);
+    } else {
+        const T* rec = rec_ptr<T>(L) + (int64_t)L.irr_index[l] * (1 + 2 * DIM);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            acc += rec[1 + 2 * d] * load_it<T, S>(z, l - st[d]) + rec[2 + 2 * d] * load_it<T, S>(z, l + st[d]);
+        *diag = rec[0];
+    }
+    *off = acc;
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_rbgs(LevelDev L, int colour, S* z, const T* b) {
+    int i = L.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
+    if (i > L.core_hi[0] || j > L.core_hi[1]) return;
+    if (((i + j + k) & 1) != colour) return;
+    int64_t l = L.box.idx(i, j, k);
+    uint8_t lab = L.labels[l];
+    if (!is_unknown(lab)) return;
+    T diag, off;
+    sw_row<T, S, DIM>(L, l, lab, z, &diag, &off);
+    if (diag != (T)0) store_t<T, S>(z, l, (b[l] - off) / diag);
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_sw_apply(LevelDev L, const S* z, T* y) {
+    int i = L.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
+    if (i > L.core_hi[0] || j > L.core_hi[1]) return;
+    int64_t l = L.box.idx(i, j, k);
+    uint8_t lab = L.labels[l];
+    if (!is_unknown(lab)) {
+        y[l] = (T)0;
+        return;
+    }
+    T diag, off;
+    sw_row<T, S, DIM>(L, l, lab, z, &diag, &off);
+    y[l] = diag * load_it<T, S>(z, l) + off;
+}
+
+// residual of the fine level at an in-box node (zero off the unknowns)
+template <typename T, typename S, int DIM>
+__device__ inline T fine_resid(const LevelDev& F, int64_t l, const S* z, const T* b) {
+    uint8_t lab = F.labels[l];
+    if (!is_unknown(lab)) return (T)0;
+    T diag, off;
+    sw_row<T, S, DIM>(F, l, lab, z, &diag, &off);
+    return b[l] - (diag * load_it<T, S>(z, l) + off);
+}
+
+// coarse rhs (scaled by h_c^2 = 4 h_f^2): 4 * half-weighting of the fine residual
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_resid_restrict(LevelDev F, LevelDev C, const S* z, const T* b, T* bc) {
+    int I = C.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int J = C.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int K = DIM == 3 ? C.core_lo[2] + blockIdx.z : 0;
+    if (I > C.core_hi[0] || J > C.core_hi[1]) return;
+    int64_t lc = C.box.idx(I, J, K);
+    if (!is_unknown(C.labels[lc])) {
+        bc[lc] = (T)0;
+        return;
+    }
+    const int64_t st[3] = {1, (int64_t)F.box.dims[0], (int64_t)F.box.dims[0] * F.box.dims[1]};
+    const int f2[3] = {2 * I, 2 * J, 2 * K};
+    for (int d = 0; d < DIM; ++d)
+        if (f2[d] - 1 < F.box.lo[d] || f2[d] + 1 >= F.box.lo[d] + F.box.dims[d]) {
+            bc[lc] = (T)0;  // cannot happen: a coarse unknown is a fine unknown
+            return;
+        }
+    int64_t lf = F.box.idx(2 * I, 2 * J, 2 * K);
+    const T w0 = (T)0.5, w1 = DIM == 2 ? (T)0.125 : (T)(1.0 / 12.0);
+    T acc = w0 * fine_resid<T, S, DIM>(F, lf, z, b);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+        acc += w1 * (fine_resid<T, S, DIM>(F, lf + st[d], z, b) + fine_resid<T, S, DIM>(F, lf - st[d], z, b));
+    bc[lc] = (T)4 * acc;
+}
+
+// z_f += P z_c at fine unknowns; mode 0 = (bi/tri)linear, 1 = average of in-domain parents
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_prolong(LevelDev F, LevelDev C, int mode, const S* zc, S* z) {
+    int i = F.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = F.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? F.core_lo[2] + blockIdx.z : 0;
+    if (i > F.core_hi[0] || j > F.core_hi[1]) return;
+    int64_t l = F.box.idx(i, j, k);
+    if (!is_unknown(F.labels[l])) return;
+    int f[3] = {i, j, k};
+    int lo[3], nb[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = f[d] >> 1;  // floor for non-negative indices
+        nb[d] = (d < DIM && (f[d] & 1)) ? 2 : 1;
+    }
+    T sum = 0;
+    int cnt = 0;
+    for (int a = 0; a < nb[0]; ++a)
+        for (int bq = 0; bq < nb[1]; ++bq)
+            for (int cq = 0; cq < nb[2]; ++cq) {
+                int P[3] = {lo[0] + a, lo[1] + bq, lo[2] + cq};
+                bool inb = true;
+                for (int d = 0; d < 3; ++d) inb = inb && P[d] >= C.box.lo[d] && P[d] < C.box.lo[d] + C.box.dims[d];
+                T v = 0;
+                bool use = mode == 0;
+                if (inb) {
+                    int64_t lp = C.box.idx(P[0], P[1], P[2]);
+                    v = load_it<T, S>(zc, lp);
+                    if (mode == 1) {
+                        uint8_t kk = C.labels[lp] & KIND_MASK;
+                        use = kk == K_PLUS || kk == K_MINUS || kk == K_BOX;
+                    }
+                } else if (mode == 1) {
+                    use = false;
+                }
+                if (use) {
+                    sum += v;
+                    cnt += 1;
+                }
+            }
+    if (cnt > 0) {
+        T corr = sum / (T)cnt;
+        store_t<T, S>(z, l, load_it<T, S>(z, l) + corr);
+    }
+}
+
+template <typename T, typename S>
+__global__ void k_coarse_solve(const int32_t* list, int64_t nc, const T* Ainv, const T* b, S* z) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nc) return;
+    T acc = 0;
+    for (int64_t c = 0; c < nc; ++c) acc += Ainv[r * nc + c] * b[list[c]];
+    store_t<T, S>(z, list[r], acc);
+}
+
+template <typename S>
+__global__ void k_zero(S* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = S(0.0f);
+}
+
+static inline void level_grid(const LevelDev& L, dim3* grd, dim3* blk) {
+    int nx = L.core_hi[0] - L.core_lo[0] + 1, ny = L.core_hi[1] - L.core_lo[1] + 1;
+    int nz = L.dim == 3 ? L.core_hi[2] - L.core_lo[2] + 1 : 1;
+    *blk = dim3(64, 4, 1);
+    *grd = dim3(cdiv(std::max(nx, 1), 64), cdiv(std::max(ny, 1), 4), std::max(nz, 1));
+}
+
+template <typename T, typename S>
+void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s) {
+    dim3 g, k;
+    level_grid(L, &g, &k);
+    if (L.dim == 2)
+        hipLaunchKernelGGL((k_rbgs<T, S, 2>), g, k, 0, s, L, colour, z, b);
+    else
+        hipLaunchKernelGGL((k_rbgs<T, S, 3>), g, k, 0, s, L, colour, z, b);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename T, typename S>
+void run_sw_apply(const LevelDev& L, const S* z, T* y, hipStream_t s) {
+    dim3 g, k;
+    level_grid(L, &g, &k);
+    if (L.dim == 2)
+        hipLaunchKernelGGL((k_sw_apply<T, S, 2>), g, k, 0, s, L, z, y);
+    else
+        hipLaunchKernelGGL((k_sw_apply<T, S, 3>), g, k, 0, s, L, z, y);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename T, typename S>
+void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const T* b, T* bc, hipStream_t s) {
+    dim3 g, k;
+    level_grid(C, &g, &k);
+    if (F.dim == 2)
+        hipLaunchKernelGGL((k_resid_restrict<T, S, 2>), g, k, 0, s, F, C, z, b, bc);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<T, S, 3>), g, k, 0, s, F, C, z, b, bc);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename T, typename S>
+void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S* z, hipStream_t s) {
+    dim3 g, k;
+    level_grid(F, &g, &k);
+    if (F.dim == 2)
+        hipLaunchKernelGGL((k_prolong<T, S, 2>), g, k, 0, s, F, C, mode, zc, z);
+    else
+        hipLaunchKernelGGL((k_prolong<T, S, 3>), g, k, 0, s, F, C, mode, zc, z);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename T, typename S>
+void run_coarse_solve(const LevelDev& L, const int32_t* list, int64_t nc, const T* Ainv, const T* b, S* z,
+                      hipStream_t s) {
+    if (nc == 0) return;
+    hipLaunchKernelGGL((k_coarse_solve<T, S>), dim3(cdiv(nc, 64)), dim3(64), 0, s, list, nc, Ainv, b, z);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename S>
+void run_zero(S* p, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    int blocks = (int)std::min<int64_t>(cdiv(n, 256), 4096);
+    hipLaunchKernelGGL((k_zero<S>), dim3(blocks), dim3(256), 0, s, p, n);
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// precision boundary
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_cast_in(LevelDev L, const double* v, const double* scale, double h2, double bp, double bm, T* rhs) {
+    int64_t n = L.box.size();
+    double sc = *scale;
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t kk = L.labels[l] & KIND_MASK;
+        double val = 0.0;
+        if (kk == K_PLUS) val = sc * h2 * v[l] / bp;
+        else if (kk == K_MINUS) val = sc * h2 * v[l] / bm;
+        rhs[l] = (T)val;
+    }
+}
+
+template <typename S>
+__global__ void k_cast_out(LevelDev L, const S* z, const double* scale, double* out) {
+    int64_t n = L.box.size();
+    double inv = 1.0 / *scale;
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x) {
+        double val = is_unknown(L.labels[l]) ? (double)load_it<double, S>(z, l) * inv : 0.0;
+        out[l] = val;
+    }
+}
+
+template <typename T>
+void run_cast_in(const LevelDev& L, const double* v, const double* scale_dev, double h2, double bp, double bm, T* rhs,
+                 hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(L.box.size(), 256), 4096);
+    hipLaunchKernelGGL((k_cast_in<T>), dim3(blocks), dim3(256), 0, s, L, v, scale_dev, h2, bp, bm, rhs);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename S>
+void run_cast_out(const LevelDev& L, const S* z, const double* scale_dev, double* out, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(L.box.size(), 256), 4096);
+    hipLaunchKernelGGL((k_cast_out<S>), dim3(blocks), dim3(256), 0, s, L, z, scale_dev, out);
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// full grid <-> storage box
+// ---------------------------------------------------------------------------
+__global__ void k_full_to_box(int dim, int n, Box b, const double* full, double* boxed, const uint8_t* labels,
+                              int only_unknowns) {
+    int64_t tot = b.size();
+    int64_t n1 = n + 1;
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < tot; l += (int64_t)gridDim.x * blockDim.x) {
+        int ijk[3];
+        b.coords(l, ijk);
+        bool in = true;
+        for (int d = 0; d < dim; ++d) in = in && ijk[d] >= 0 && ijk[d] <= n;
+        double v = 0.0;
+        if (in) {
+            uint8_t kk = labels[l] & KIND_MASK;
+            bool take = only_unknowns == 1 ? (kk == K_PLUS || kk == K_MINUS) : (only_unknowns == 2 ? kk == K_BOX : true);
+            if (take) v = full[ijk[0] + n1 * (ijk[1] + n1 * (int64_t)ijk[2])];
+        }
+        boxed[l] = v;
+    }
+}
+
+void run_full_to_box(int dim, int n, const Box& b, const double* full, double* boxed, const uint8_t* labels,
+                     int only_unknowns, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
+    hipLaunchKernelGGL(k_full_to_box, dim3(blocks), dim3(256), 0, s, dim, n, b, full, boxed, labels, only_unknowns);
+    IIM_LAUNCH_CHECK();
+}
+
+__global__ void k_box_to_full(int dim, int n, Box b, const double* boxed, const uint8_t* labels, double fill,
+                              double* full) {
+    int64_t n1 = n + 1;
+    int64_t tot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < tot; f += (int64_t)gridDim.x * blockDim.x) {
+        int ijk[3] = {(int)(f % n1), (int)((f / n1) % n1), dim == 3 ? (int)(f / (n1 * n1)) : 0};
+        bool inb = true;
+        for (int d = 0; d < 3; ++d) inb = inb && ijk[d] >= b.lo[d] && ijk[d] < b.lo[d] + b.dims[d];
+        double v = fill;
+        if (inb) {
+            int64_t l = b.idx(ijk[0], ijk[1], ijk[2]);
+            if (is_unknown(labels[l])) v = boxed[l];
+        }
+        full[f] = v;
+    }
+}
+
+void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const uint8_t* labels, double fill,
+                     double* full, hipStream_t s) {
+    int64_t n1 = n + 1;
+    int64_t tot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    int blocks = (int)std::min<int64_t>(cdiv(tot, 256), 8192);
+    hipLaunchKernelGGL(k_box_to_full, dim3(blocks), dim3(256), 0, s, dim, n, b, boxed, labels, fill, full);
+    IIM_LAUNCH_CHECK();
+}
+
+// explicit instantiations
+#define INST_TS(T, S)                                                                                     \
+    template void run_rbgs<T, S>(const LevelDev&, int, S*, const T*, hipStream_t);                        \
+    template void run_resid_restrict<T, S>(const LevelDev&, const LevelDev&, const S*, const T*, T*,      \
+                                           hipStream_t);                                                  \
+    template void run_prolong<T, S>(const LevelDev&, const LevelDev&, int, const S*, S*, hipStream_t);    \
+    template void run_sw_apply<T, S>(const LevelDev&, const S*, T*, hipStream_t);                         \
+    template void run_coarse_solve<T, S>(const LevelDev&, const int32_t*, int64_t, const T*, const T*, S*, \
+                                         hipStream_t);
+INST_TS(double, double)
+INST_TS(float, float)
+INST_TS(float, __half)
+template void run_zero<double>(double*, int64_t, hipStream_t);
+template void run_zero<float>(float*, int64_t, hipStream_t);
+template void run_zero<__half>(__half*, int64_t, hipStream_t);
+template void run_cast_in<double>(const LevelDev&, const double*, const double*, double, double, double, double*,
+                                  hipStream_t);
+template void run_cast_in<float>(const LevelDev&, const double*, const double*, double, double, double, float*,
+                                 hipStream_t);
+template void run_cast_out<double>(const LevelDev&, const double*, const double*, double*, hipStream_t);
+template void run_cast_out<float>(const LevelDev&, const float*, const double*, double*, hipStream_t);
+template void run_cast_out<__half>(const LevelDev&, const __half*, const double*, double*, hipStream_t);
+
+}  // namespace iim
+
+namespace iim {
+
+// Neumann apply weights: W_j = S_j - (Sc_j / Sc_n) S_n, data coefficient Sc_j / (beta Sc_n)
+__global__ void k_combine_neumann(const int64_t* ptr, int64_t ncs, int w, int nrows, const double* S, const double* Sc,
+                                  double beta, int64_t nnz, double* W, double* dcoef) {
+    int64_t cs = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (cs >= ncs) return;
+    const double scn = Sc[cs * nrows + w];
+    for (int j = 0; j < w; ++j) {
+        const double scj = Sc[cs * nrows + j];
+        const double f = scj / scn;
+        for (int64_t a = ptr[cs]; a < ptr[cs + 1]; ++a) W[j * nnz + a] = S[j * nnz + a] - f * S[w * nnz + a];
+        dcoef[cs * w + j] = scj / (beta * scn);
+    }
+}
+
+__global__ void k_copy_dcoef(int64_t ncs, int w, int nrows, const double* Sc, double* dcoef) {
+    int64_t cs = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (cs >= ncs) return;
+    for (int j = 0; j < w; ++j) dcoef[cs * w + j] = Sc[cs * nrows + j];
+}
+
+void run_apply_weights(int bc, const int64_t* ptr, int64_t ncs, int w, int nrows, const double* S, const double* Sc,
+                       double beta, int64_t nnz, double* W, double* dcoef, hipStream_t s) {
+    if (ncs == 0) return;
+    if (bc == IIM_BC_NEUMANN)
+        hipLaunchKernelGGL(k_combine_neumann, dim3(cdiv(ncs, 128)), dim3(128), 0, s, ptr, ncs, w, nrows, S, Sc, beta,
+                           nnz, W, dcoef);
+    else
+        hipLaunchKernelGGL(k_copy_dcoef, dim3(cdiv(ncs, 128)), dim3(128), 0, s, ncs, w, nrows, Sc, dcoef);
+    IIM_LAUNCH_CHECK();
+}
+
+__device__ inline double to_d(double v) { return v; }
+__device__ inline double to_d(float v) { return (double)v; }
+__device__ inline double to_d(__half v) { return (double)__half2float(v); }
+__device__ inline void from_d(double v, double* p) { *p = v; }
+__device__ inline void from_d(double v, float* p) { *p = (float)v; }
+__device__ inline void from_d(double v, __half* p) { *p = __float2half((float)v); }
+
+template <typename A, typename B>
+__global__ void k_convert(const A* a, B* b, int64_t n, double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        from_d(to_d(a[i]) * scale, &b[i]);
+}
+
+template <typename A, typename B>
+void run_convert(const A* a, B* b, int64_t n, double scale, hipStream_t s) {
+    if (n == 0) return;
+    int blocks = (int)std::min<int64_t>(cdiv(n, 256), 4096);
+    hipLaunchKernelGGL((k_convert<A, B>), dim3(blocks), dim3(256), 0, s, a, b, n, scale);
+    IIM_LAUNCH_CHECK();
+}
+template void run_convert<double, double>(const double*, double*, int64_t, double, hipStream_t);
+template void run_convert<double, float>(const double*, float*, int64_t, double, hipStream_t);
+template void run_convert<double, __half>(const double*, __half*, int64_t, double, hipStream_t);
+template void run_convert<float, double>(const float*, double*, int64_t, double, hipStream_t);
+template void run_convert<__half, double>(const __half*, double*, int64_t, double, hipStream_t);
+
+}  // namespace iim

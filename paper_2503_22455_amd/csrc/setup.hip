@@ -1,0 +1,506 @@
+// Setup kernels: node labels, control points, irregular-node records and the
+// Shortley-Weller hierarchy (Sec. 2.1 and 3.1-3.3 of the paper).
+#include <hipcub/hipcub.hpp>
+
+#include "kernels.h"
+
+namespace iim {
+
+// ---------------------------------------------------------------------------
+// labels
+// ---------------------------------------------------------------------------
+__global__ void k_classify_bbox(Geom g, int* bbox, int* err, unsigned long long* count) {
+    int64_t n1 = g.n + 1;
+    int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        int ijk[3] = {(int)(l % n1), (int)((l / n1) % n1), g.dim == 3 ? (int)(l / (n1 * n1)) : 0};
+        uint8_t k = node_kind(g, ijk);
+        if (k == 255) {
+            atomicOr(err, 1);
+            continue;
+        }
+        if (k == K_PLUS || k == K_MINUS) {
+            for (int d = 0; d < 3; ++d) {
+                atomicMin(&bbox[d], ijk[d]);
+                atomicMax(&bbox[3 + d], ijk[d]);
+            }
+            atomicAdd(count, 1ull);
+        }
+    }
+}
+
+void run_classify_bbox(const Geom& g, int* d_bbox, int* d_err, unsigned long long* d_count, hipStream_t s) {
+    int64_t n1 = g.n + 1;
+    int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
+    hipLaunchKernelGGL(k_classify_bbox, dim3(blocks), dim3(256), 0, s, g, d_bbox, d_err, d_count);
+    IIM_LAUNCH_CHECK();
+}
+
+__global__ void k_box_labels(Geom g, Box b, uint8_t* labels) {
+    int64_t total = b.size();
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        int ijk[3];
+        b.coords(l, ijk);
+        bool in = true;
+        for (int d = 0; d < g.dim; ++d) in = in && ijk[d] >= 0 && ijk[d] <= g.n;
+        uint8_t k = in ? node_kind(g, ijk) : K_INACTIVE;
+        labels[l] = (k == 255) ? K_INACTIVE : k;
+    }
+}
+
+void run_box_labels(const Geom& g, const Box& b, uint8_t* labels, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
+    hipLaunchKernelGGL(k_box_labels, dim3(blocks), dim3(256), 0, s, g, b, labels);
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// control points
+// ---------------------------------------------------------------------------
+__device__ inline bool crossing_pair(uint8_t la, uint8_t lb, int side) {
+    la &= KIND_MASK;
+    lb &= KIND_MASK;
+    if (side == IIM_SIDE_INTERFACE)
+        return (la == K_PLUS && lb == K_MINUS) || (la == K_MINUS && lb == K_PLUS);
+    return (la == K_PLUS && lb == K_INACTIVE) || (la == K_INACTIVE && lb == K_PLUS);
+}
+
+__global__ void k_cp_flags(Geom g, Box b, const uint8_t* labels, int axis, uint8_t* flags) {
+    int64_t total = b.size();
+    int64_t st = b.stride(axis);
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        int ijk[3];
+        b.coords(l, ijk);
+        bool ok = ijk[axis] - b.lo[axis] + 1 < b.dims[axis];
+        for (int d = 0; d < g.dim; ++d) ok = ok && ijk[d] >= 0 && ijk[d] <= g.n;
+        ok = ok && ijk[axis] + 1 <= g.n;
+        flags[l] = (ok && crossing_pair(labels[l], labels[l + st], g.side)) ? 1 : 0;
+    }
+}
+
+void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, int axis, uint8_t* flags, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
+    hipLaunchKernelGGL(k_cp_flags, dim3(blocks), dim3(256), 0, s, g, b, labels, axis, flags);
+    IIM_LAUNCH_CHECK();
+}
+
+size_t select_tmp_bytes(int64_t n) {
+    size_t bytes = 0;
+    hipcub::CountingInputIterator<int32_t> it(0);
+    hipcub::DeviceSelect::Flagged(nullptr, bytes, it, (const uint8_t*)nullptr, (int32_t*)nullptr,
+                                  (int64_t*)nullptr, (int)n);
+    return bytes;
+}
+
+int64_t select_flagged(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
+                       int64_t* d_count, hipStream_t s) {
+    hipcub::CountingInputIterator<int32_t> it(0);
+    IIM_HIP(hipcub::DeviceSelect::Flagged(tmp, tmp_bytes, it, flags, out, d_count, (int)n, s));
+    int64_t cnt = 0;
+    IIM_HIP(hipMemcpyAsync(&cnt, d_count, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    IIM_HIP(hipStreamSynchronize(s));
+    return cnt;
+}
+
+__global__ void k_cp_compute(Geom g, Box b, const uint8_t* labels, CPDev cp, int* err) {
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= cp.ncp) return;
+    int axis = cp.axis[c];
+    int64_t p = cp.lower[c];
+    int64_t q = p + b.stride(axis);
+    uint8_t kp = labels[p] & KIND_MASK;
+    int64_t a;
+    if (g.side == IIM_SIDE_INTERFACE)
+        a = (kp == K_MINUS) ? p : q;
+    else
+        a = (kp == K_PLUS) ? p : q;
+    int dir = (a == p) ? 1 : -1;
+    int ijk[3];
+    b.coords(a, ijk);
+    double xa[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, ijk[d]);
+    int which = 0;
+    double root = crossing_root(g, xa, axis, dir, &which);
+    double x[3] = {xa[0], xa[1], xa[2]};
+    x[axis] = root;
+    double nv[3];
+    geom_normal(g, x, which, nv);
+    double kap = geom_curvature(g, x, which);
+    for (int d = 0; d < 3; ++d) {
+        cp.x[d * cp.ncp + c] = x[d];
+        cp.n[d * cp.ncp + c] = nv[d];
+    }
+    cp.kappa[c] = kap;
+    // side 0 = Omega^+, side 1 = Omega^-
+    int64_t aplus = (kp == K_PLUS) ? p : q;
+    cp.a[c] = (int32_t)aplus;
+    cp.dir[c] = (aplus == p) ? 1 : -1;
+    if (cp.nsides == 2) {
+        int64_t aminus = (kp == K_MINUS) ? p : q;
+        cp.a[cp.ncp + c] = (int32_t)aminus;
+        cp.dir[cp.ncp + c] = (aminus == p) ? 1 : -1;
+    }
+    if (!(fabs(kap * g.h) < 0.25)) atomicOr(err, 2);
+}
+
+void run_cp_compute(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, int* d_err,
+                    hipStream_t s) {
+    if (cp.ncp == 0) return;
+    hipLaunchKernelGGL(k_cp_compute, dim3(cdiv(cp.ncp, 128)), dim3(128), 0, s, g, b, labels, cp, d_err);
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// irregular high-order nodes
+// ---------------------------------------------------------------------------
+// index of the control point on segment (lower, lower + e_axis), -1 if none
+__device__ inline int64_t find_cp(const CPDev& cp, int axis, int32_t lower) {
+    int lo = cp.axis_start[axis], hi = cp.axis_start[axis + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int32_t v = cp.lower[mid];
+        if (v == lower) return mid;
+        if (v < lower) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+// kind of node ijk + j dir e_d, or INACTIVE outside the grid; *l = its box index
+__device__ inline uint8_t kind_at(const Geom& g, const Box& b, const uint8_t* labels, const int* ijk, int d,
+                                  int step, int64_t* l) {
+    int c[3] = {ijk[0], ijk[1], ijk[2]};
+    c[d] += step;
+    if (c[d] < 0 || c[d] > g.n || c[d] < b.lo[d] || c[d] >= b.lo[d] + b.dims[d]) {
+        *l = -1;
+        return 255;
+    }
+    *l = b.idx(c[0], c[1], c[2]);
+    return labels[*l] & KIND_MASK;
+}
+
+__global__ void k_ho_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags) {
+    int64_t total = b.size();
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t lab = labels[l];
+        uint8_t k = lab & KIND_MASK;
+        bool irr = false;
+        if (k == K_PLUS || k == K_MINUS) {
+            int ijk[3];
+            b.coords(l, ijk);
+            for (int d = 0; d < g.dim && !irr; ++d)
+                for (int s = -2; s <= 2; ++s) {
+                    if (s == 0) continue;
+                    int64_t q;
+                    if (kind_at(g, b, labels, ijk, d, s, &q) != k) irr = true;
+                }
+        }
+        flags[l] = irr ? 1 : 0;
+        if (irr) labels[l] = lab | F_HO_IRR;
+    }
+}
+
+void run_ho_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
+    hipLaunchKernelGGL(k_ho_irr_flag, dim3(blocks), dim3(256), 0, s, g, b, labels, flags);
+    IIM_LAUNCH_CHECK();
+}
+
+// One record per irregular node: 2*dim slots, slot (d, dir) at 2d + (dir > 0).
+__global__ void k_ho_irr_records(Geom g, Box b, const uint8_t* labels, CPDev cp, const int32_t* nodes,
+                                 int64_t nirr, int32_t* slots, int32_t* irr_index, int* err) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nirr) return;
+    int64_t l = nodes[k];
+    irr_index[l] = (int32_t)k;
+    uint8_t side = labels[l] & KIND_MASK;
+    int sidx = (side == K_PLUS) ? 0 : 1;
+    int ijk[3];
+    b.coords(l, ijk);
+    for (int d = 0; d < g.dim; ++d)
+        for (int t = 0; t < 2; ++t) {
+            int dir = t ? 1 : -1;
+            int slot = make_slot(SLOT_REG, 0, 0);
+            int64_t prev = l;
+            for (int j = 1; j <= 2; ++j) {
+                int64_t q;
+                uint8_t kq = kind_at(g, b, labels, ijk, d, dir * j, &q);
+                if (kq == side) {
+                    prev = q;
+                    continue;
+                }
+                if (kq == K_BOX) {
+                    slot = make_slot(SLOT_BOX, j, 0);
+                } else if (kq == 255) {
+                    atomicOr(err, 4);  // stencil leaves the storage box
+                } else {
+                    int64_t lower = prev < q ? prev : q;
+                    int64_t c = find_cp(cp, d, (int32_t)lower);
+                    if (c < 0) {
+                        atomicOr(err, 8);
+                    } else {
+                        slot = make_slot(SLOT_GHOST, j, (int)(c * cp.nsides + sidx));
+                    }
+                }
+                break;
+            }
+            slots[k * 2 * g.dim + 2 * d + t] = slot;
+        }
+}
+
+void run_ho_irr_records(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
+                        const int32_t* nodes, int64_t nirr, int32_t* slots, int32_t* irr_index, int* d_err,
+                        hipStream_t s) {
+    if (nirr == 0) return;
+    hipLaunchKernelGGL(k_ho_irr_records, dim3(cdiv(nirr, 128)), dim3(128), 0, s, g, b, labels, cp, nodes, nirr,
+                       slots, irr_index, d_err);
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Shortley-Weller rows
+// ---------------------------------------------------------------------------
+__global__ void k_sw_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags) {
+    int64_t total = b.size();
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t lab = labels[l];
+        uint8_t k = lab & KIND_MASK;
+        bool irr = false;
+        if (k == K_PLUS || k == K_MINUS) {
+            int ijk[3];
+            b.coords(l, ijk);
+            for (int d = 0; d < g.dim; ++d)
+                for (int s = -1; s <= 1; s += 2) {
+                    int64_t q;
+                    uint8_t kq = kind_at(g, b, labels, ijk, d, s, &q);
+                    if (kq != k && kq != K_BOX) irr = true;
+                }
+        }
+        flags[l] = irr ? 1 : 0;
+        if (irr) labels[l] = lab | F_SW_IRR;
+    }
+}
+
+void run_sw_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
+    hipLaunchKernelGGL(k_sw_irr_flag, dim3(blocks), dim3(256), 0, s, g, b, labels, flags);
+    IIM_LAUNCH_CHECK();
+}
+
+// 1D row of the Shortley-Weller stencil, coefficients in units of 1/h^2.
+// Side types: 0 = value (regular neighbour, Dirichlet or interface wall), 1 = Neumann wall.
+__device__ inline void sw_row_1d(int tl, double pl, int tr, double pr, double* cl, double* cc, double* cr) {
+    if (tl == 0 && tr == 0) {
+        *cl = 2.0 / (pl * (pl + pr));
+        *cc = -2.0 / (pl * pr);
+        *cr = 2.0 / (pr * (pl + pr));
+    } else if (tl == 1 && tr == 0) {
+        double c = 2.0 / (pr * (2.0 * pl + pr));
+        *cl = 0.0;
+        *cc = -c;
+        *cr = c;
+    } else if (tl == 0 && tr == 1) {
+        double c = 2.0 / (pl * (pl + 2.0 * pr));
+        *cl = c;
+        *cc = -c;
+        *cr = 0.0;
+    } else {
+        *cl = *cc = *cr = 0.0;
+    }
+}
+
+__global__ void k_sw_records(Geom g, Box b, const uint8_t* labels, const int32_t* nodes, int64_t nirr, int bc,
+                             double beta_plus, double beta_minus, double* rec64, float* rec32,
+                             int32_t* irr_index) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nirr) return;
+    int64_t l = nodes[k];
+    irr_index[l] = (int32_t)k;
+    uint8_t kf = labels[l] & KIND_MASK;
+    int ijk[3];
+    b.coords(l, ijk);
+    double xf[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < g.dim; ++d) xf[d] = node_coord(g, ijk[d]);
+    const int R = 1 + 2 * g.dim;
+    double row[7] = {0, 0, 0, 0, 0, 0, 0};
+    double ap = 0.5 / beta_plus, am = 0.5 / beta_minus;
+    for (int d = 0; d < g.dim; ++d) {
+        int type[2];
+        double psi[2], wself[2], wnb[2];
+        for (int t = 0; t < 2; ++t) {
+            int s = t ? 1 : -1;
+            int64_t q;
+            uint8_t kq = kind_at(g, b, labels, ijk, d, s, &q);
+            type[t] = 0;
+            psi[t] = 1.0;
+            wself[t] = 0.0;
+            wnb[t] = 0.0;
+            if (kq == kf) {
+                wnb[t] = 1.0;
+            } else if (kq == K_BOX) {
+                // known (zero) value at psi = 1
+            } else if (g.side == IIM_SIDE_INTERFACE) {
+                psi[t] = 0.5;
+                // u_w = (alpha^+ u_minus + alpha^- u_plus) / (alpha^+ + alpha^-)
+                double wm = ap / (ap + am), wp = am / (ap + am);
+                wself[t] = (kf == K_MINUS) ? wm : wp;
+                wnb[t] = (kf == K_MINUS) ? wp : wm;
+            } else {
+                int which;
+                double root = crossing_root(g, xf, d, s, &which);
+                double ps = fabs(root - xf[d]) / g.h;
+                psi[t] = fmax(ps, 0.5);
+                type[t] = (bc == IIM_BC_NEUMANN) ? 1 : 0;
+            }
+        }
+        double cl, cc, cr;
+        sw_row_1d(type[0], psi[0], type[1], psi[1], &cl, &cc, &cr);
+        row[0] += cc + cl * wself[0] + cr * wself[1];
+        row[1 + 2 * d] += cl * wnb[0];
+        row[2 + 2 * d] += cr * wnb[1];
+    }
+    for (int r = 0; r < R; ++r) {
+        rec64[k * R + r] = row[r];
+        rec32[k * R + r] = (float)row[r];
+    }
+}
+
+void run_sw_records(const Geom& g, const Box& b, const uint8_t* labels, const int32_t* nodes, int64_t nirr,
+                    int bc, double beta_plus, double beta_minus, double* rec64, float* rec32, int32_t* irr_index,
+                    hipStream_t s) {
+    if (nirr == 0) return;
+    hipLaunchKernelGGL(k_sw_records, dim3(cdiv(nirr, 128)), dim3(128), 0, s, g, b, labels, nodes, nirr, bc,
+                       beta_plus, beta_minus, rec64, rec32, irr_index);
+    IIM_LAUNCH_CHECK();
+}
+
+__global__ void k_fill_int(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void run_fill_int(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n == 0) return;
+    int blocks = (int)std::min<int64_t>(cdiv(n, 256), 8192);
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks), dim3(256), 0, s, p, n, v);
+    IIM_LAUNCH_CHECK();
+}
+
+// dense coarse matrix: row r of the listed unknowns; col_of[l] = column of box node l (-1 if excluded)
+__global__ void k_coarse_assemble(Box b, int dim, const uint8_t* labels, const int32_t* irr_index,
+                                  const double* rec64, const int32_t* list, const int32_t* col_of, int64_t nc,
+                                  double* A) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nc) return;
+    int64_t l = list[r];
+    for (int64_t c = 0; c < nc; ++c) A[r * nc + c] = 0.0;
+    const int R = 1 + 2 * dim;
+    bool irr = labels[l] & F_SW_IRR;
+    double diag = irr ? rec64[irr_index[l] * R] : -2.0 * dim;
+    A[r * nc + r] = diag;
+    for (int d = 0; d < dim; ++d)
+        for (int t = 0; t < 2; ++t) {
+            int64_t q = l + (t ? 1 : -1) * b.stride(d);
+            double c = irr ? rec64[irr_index[l] * R + 1 + 2 * d + t] : 1.0;
+            int32_t col = col_of[q];
+            if (c != 0.0 && col >= 0) A[r * nc + col] += c;
+        }
+}
+
+void run_coarse_assemble(const Box& b, int dim, const uint8_t* labels, const int32_t* irr_index,
+                         const double* rec64, const int32_t* list, const int32_t* col_of, int64_t nc, double* A,
+                         hipStream_t s) {
+    if (nc == 0) return;
+    hipLaunchKernelGGL(k_coarse_assemble, dim3(cdiv(nc, 64)), dim3(64), 0, s, b, dim, labels, irr_index, rec64,
+                       list, col_of, nc, A);
+    IIM_LAUNCH_CHECK();
+}
+
+// Gauss-Jordan inversion with partial pivoting, one workgroup (nc <= a few hundred).
+__global__ void __launch_bounds__(1024) k_coarse_invert(double* A, double* X, int64_t nc, int* err) {
+    __shared__ double red_v[1024];
+    __shared__ int red_i[1024];
+    __shared__ int piv_s;
+    int tid = threadIdx.x;
+    for (int64_t i = tid; i < nc * nc; i += blockDim.x) X[i] = ((i / nc) == (i % nc)) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int64_t k = 0; k < nc; ++k) {
+        double best = -1.0;
+        int bi = -1;
+        for (int64_t r = k + tid; r < nc; r += blockDim.x) {
+            double v = fabs(A[r * nc + k]);
+            if (v > best) {
+                best = v;
+                bi = (int)r;
+            }
+        }
+        red_v[tid] = best;
+        red_i[tid] = bi;
+        __syncthreads();
+        for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                double v2 = red_v[tid + off];
+                int i2 = red_i[tid + off];
+                if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 >= 0 && (red_i[tid] < 0 || i2 < red_i[tid]))) {
+                    red_v[tid] = v2;
+                    red_i[tid] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            piv_s = red_i[0];
+            if (red_i[0] < 0 || red_v[0] == 0.0) atomicOr(err, 16);
+        }
+        __syncthreads();
+        int piv = piv_s;
+        if (piv < 0) return;
+        if (piv != k) {
+            for (int64_t c = tid; c < nc; c += blockDim.x) {
+                double t = A[k * nc + c];
+                A[k * nc + c] = A[piv * nc + c];
+                A[piv * nc + c] = t;
+                t = X[k * nc + c];
+                X[k * nc + c] = X[piv * nc + c];
+                X[piv * nc + c] = t;
+            }
+        }
+        __syncthreads();
+        double inv = 1.0 / A[k * nc + k];
+        __syncthreads();
+        for (int64_t c = tid; c < nc; c += blockDim.x) {
+            A[k * nc + c] *= inv;
+            X[k * nc + c] *= inv;
+        }
+        __syncthreads();
+        for (int64_t i = tid; i < nc * nc; i += blockDim.x) {
+            int64_t r = i / nc, c = i % nc;
+            if (r == k) continue;
+            double f = A[r * nc + k];
+            if (c == k) continue;  // column k of A updated last
+            A[r * nc + c] -= f * A[k * nc + c];
+            X[r * nc + c] -= f * X[k * nc + c];
+        }
+        __syncthreads();
+        for (int64_t r = tid; r < nc; r += blockDim.x) {
+            if (r == k) continue;
+            double f = A[r * nc + k];
+            X[r * nc + k] -= f * X[k * nc + k];
+            A[r * nc + k] = 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+void run_coarse_invert(double* A, double* Ainv, int64_t nc, int* d_err, hipStream_t s) {
+    if (nc == 0) return;
+    hipLaunchKernelGGL(k_coarse_invert, dim3(1), dim3(1024), 0, s, A, Ainv, nc, d_err);
+    IIM_LAUNCH_CHECK();
+}
+
+}  // namespace iim

@@ -1,0 +1,252 @@
+"""Python binding of the HIP immersed-interface Poisson library (libiim.so).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Device arrays are torch CUDA tensors (torch supplies device
+memory and the stream); full-grid arrays are flat, contiguous, x fastest:
+node (i, j, k) at i + (n+1) j + (n+1)^2 k.  The library must be built
+(``python -m paper_2503_22455_amd.build``); importing this module without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiim.so")
+
+GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION = 0, 1, 2
+SIDE_INTERIOR, SIDE_EXTERIOR, SIDE_INTERFACE = 0, 1, 2
+BC_DIRICHLET, BC_NEUMANN, BC_JUMP = 0, 1, 2
+PREC = {"fp64": 0, "mixed32": 1, "mixed16": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+NOT_CONVERGED = 1
+
+
+class IIMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("side", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("nparams", ctypes.c_int32), ("params", ctypes.POINTER(ctypes.c_double))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("order_n", ctypes.c_int32), ("order_k", ctypes.c_int32), ("beta_plus", ctypes.c_double),
+                ("beta_minus", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
+                ("coarsest_n", ctypes.c_int32), ("precision", ctypes.c_int32), ("ls_axis_t", ctypes.c_double),
+                ("ls_axis_n", ctypes.c_double), ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("hist_len", ctypes.c_int32), ("final_rel_residual", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_apply_ms", ctypes.c_double),
+                ("t_vcycle_ms", ctypes.c_double), ("t_krylov_ms", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("levels", ctypes.c_int32), ("sides", ctypes.c_int32),
+                ("n_unknowns", ctypes.c_int64), ("n_control_points", ctypes.c_int64),
+                ("n_ls_entries", ctypes.c_int64), ("n_irregular", ctypes.c_int64),
+                ("box_lo", ctypes.c_int64 * 3), ("box_dims", ctypes.c_int64 * 3),
+                ("device_bytes", ctypes.c_int64), ("t_setup_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libiim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2503_22455_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        L.iim_last_error.restype = ctypes.c_char_p
+        L.iim_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.iim_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Geometry), ctypes.POINTER(Options), vp,
+                                 ctypes.POINTER(vp)]
+        L.iim_destroy.argtypes = [vp]
+        L.iim_destroy.restype = None
+        L.iim_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.iim_control_points.argtypes = [vp, ctypes.POINTER(i64), vp, vp]
+        L.iim_node_labels.argtypes = [vp, vp]
+        L.iim_set_boundary_data.argtypes = [vp, vp, vp, i32]
+        L.iim_set_rhs.argtypes = [vp, vp, i32]
+        L.iim_solve.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(Stats)]
+        L.iim_apply.argtypes = [vp, vp, vp, i32]
+        L.iim_vcycle.argtypes = [vp, vp, vp]
+        L.iim_ls_stencil.argtypes = [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp, i32]
+        L.iim_level_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.iim_level_labels.argtypes = [vp, i32, vp]
+        L.iim_level_op.argtypes = [vp, i32, i32, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, allow_not_converged: bool = False) -> int:
+    if rc == 0 or (allow_not_converged and rc == NOT_CONVERGED):
+        return rc
+    raise IIMError(rc, lib().iim_last_error().decode())
+
+
+def _ptr(t) -> int:
+    """Device pointer of a contiguous torch CUDA tensor."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def grid_to_flat(a: np.ndarray) -> np.ndarray:
+    """Array indexed [ix, iy(, iz)] -> flat x-fastest vector."""
+    return np.ascontiguousarray(np.asarray(a).ravel(order="F"))
+
+
+def flat_to_grid(v: np.ndarray, dim: int, n: int) -> np.ndarray:
+    return np.asarray(v).reshape((n + 1,) * dim, order="F")
+
+
+class Problem:
+    """One immersed-interface Poisson problem resident on the current device."""
+
+    def __init__(self, dim: int, n: int, geom_kind: int, geom_params, side: int, bc: int,
+                 beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 1e-10, max_iters: int = 500,
+                 restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
+                 precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None,
+                 lo: float = -1.0, hi: float = 1.0, stream=None):
+        L = lib()
+        self.dim, self.n = dim, n
+        self.side, self.bc = side, bc
+        self.total = (n + 1) ** dim
+        g = Grid(dim, n, lo, hi)
+        pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
+        geo = Geometry(geom_kind, side, bc, len(geom_params), pa)
+        o = Options()
+        L.iim_default_options(ctypes.byref(o))
+        o.beta_plus, o.beta_minus, o.rtol, o.max_iters = beta_plus, beta_minus, rtol, max_iters
+        o.restart, o.nu_pre, o.nu_post, o.coarsest_n = restart, nu_pre, nu_post, coarsest_n
+        o.precision = PREC[precision]
+        if ls_axes is not None:
+            o.ls_axis_t, o.ls_axis_n = ls_axes
+        self._h = ctypes.c_void_p()
+        s = _stream() if stream is None else stream
+        _check(L.iim_create(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(o), ctypes.c_void_p(s),
+                            ctypes.byref(self._h)))
+
+    # -- lifetime --------------------------------------------------------------
+    def close(self):
+        if self._h:
+            lib().iim_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- queries ------------------------------------------------------------------
+    def info(self) -> dict:
+        inf = Info()
+        _check(lib().iim_get_info(self._h, ctypes.byref(inf)))
+        return {k: (list(getattr(inf, k)) if k in ("box_lo", "box_dims") else getattr(inf, k))
+                for k, _ in Info._fields_}
+
+    def control_points(self) -> Tuple[np.ndarray, np.ndarray]:
+        cnt = ctypes.c_int64()
+        _check(lib().iim_control_points(self._h, ctypes.byref(cnt), None, None))
+        xyz = np.zeros((cnt.value, self.dim))
+        nrm = np.zeros((cnt.value, self.dim))
+        if cnt.value:
+            _check(lib().iim_control_points(self._h, ctypes.byref(cnt), xyz.ctypes.data, nrm.ctypes.data))
+        return xyz, nrm
+
+    def node_labels(self) -> np.ndarray:
+        out = np.zeros(self.total, dtype=np.uint8)
+        _check(lib().iim_node_labels(self._h, out.ctypes.data))
+        return out
+
+    def ls_stencil(self, cp: int, side: int = 1) -> Tuple[np.ndarray, np.ndarray]:
+        m, r = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().iim_ls_stencil(self._h, cp, side, ctypes.byref(m), ctypes.byref(r), None, None, 0))
+        idx = np.zeros(m.value, dtype=np.int64)
+        wts = np.zeros((m.value + 1, r.value))
+        _check(lib().iim_ls_stencil(self._h, cp, side, ctypes.byref(m), ctypes.byref(r), idx.ctypes.data,
+                                    wts.ctypes.data, m.value + 1))
+        return idx, wts
+
+    def level_info(self, level: int) -> Tuple[int, int]:
+        n, nu = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().iim_level_info(self._h, level, ctypes.byref(n), ctypes.byref(nu)))
+        return n.value, nu.value
+
+    def level_labels(self, level: int) -> np.ndarray:
+        n, _ = self.level_info(level)
+        out = np.zeros((n + 1) ** self.dim, dtype=np.uint8)
+        _check(lib().iim_level_labels(self._h, level, out.ctypes.data))
+        return out
+
+    # -- data ---------------------------------------------------------------------
+    def set_boundary_data(self, cp_data, box_data=None):
+        import torch
+        cpd = torch.as_tensor(np.ascontiguousarray(cp_data, dtype=np.float64).ravel()).cuda()
+        box = None if box_data is None else torch.as_tensor(np.ascontiguousarray(box_data, dtype=np.float64)).cuda()
+        _check(lib().iim_set_boundary_data(self._h, _ptr(cpd) if cpd.numel() else None,
+                                           None if box is None else _ptr(box), MEM_DEVICE))
+
+    def set_rhs(self, f):
+        import torch
+        ft = torch.as_tensor(np.ascontiguousarray(f, dtype=np.float64)).cuda() if not hasattr(f, "is_cuda") else f
+        _check(lib().iim_set_rhs(self._h, _ptr(ft), MEM_DEVICE))
+
+    # -- operations on device tensors ---------------------------------------------------
+    def apply(self, x, with_data: bool = False):
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().iim_apply(self._h, _ptr(x), _ptr(y), int(with_data)))
+        return y
+
+    def vcycle(self, v):
+        import torch
+        z = torch.empty_like(v)
+        _check(lib().iim_vcycle(self._h, _ptr(v), _ptr(z)))
+        return z
+
+    def level_op(self, level: int, op: int, in1, out):
+        _check(lib().iim_level_op(self._h, level, op, _ptr(in1), _ptr(out)))
+        return out
+
+    def solve(self, x0=None, hist_cap: int = 1000):
+        import torch
+        u = torch.empty(self.total, dtype=torch.float64, device="cuda")
+        hist = np.zeros(hist_cap)
+        st = Stats()
+        rc = lib().iim_solve(self._h, _ptr(u), None if x0 is None else _ptr(x0), hist.ctypes.data, hist_cap,
+                             ctypes.byref(st))
+        _check(rc, allow_not_converged=True)
+        stats = {k: getattr(st, k) for k, _ in Stats._fields_}
+        return u, hist[: st.hist_len].copy(), stats
+
+
+def from_workload(wl, precision: Optional[str] = None, **kw) -> Problem:
+    """Problem for a workloads.Workload description."""
+    return Problem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus,
+                   precision=precision or wl.precision, **kw)

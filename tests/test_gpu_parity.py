@@ -1,0 +1,152 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle on identical seeded
+inputs, through the C ABI.  Integer work (labels, control-point order, least-
+squares sets) must match exactly; floating point within the stated bounds."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import PLUS, MINUS
+from oracle.mg import Hierarchy
+from tests.gpu_helpers import oracle_for, gpu_for, flat, oracle_data
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "cfg1": lambda: W.cfg1_circle(64),
+    "circle-neu-ext": lambda: W.Workload("neu2", 2, 64, W.GEOM_SPHERE_UNION, W.union_params(W.small_circles_union_2d()),
+                                         W.SIDE_EXTERIOR, W.BC_NEUMANN, 1.5, 1.0, exact=W.ms_sin2pi_cos2pi()),
+    "star128": lambda: W.cfg2_star(128),
+    "star128-beta": lambda: W.cfg2_star(128, beta_plus=0.5, beta_minus=1.0),
+    "sphere24": lambda: W.cfg3_sphere(24, precision="fp64"),
+    "spheres32-neu": lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union(), precision="fp64"),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
+    wl = CASES[request.param]()
+    O = oracle_for(wl)
+    G = gpu_for(wl, precision="fp64", rtol=1e-13)
+    yield request.param, wl, O, G
+    G.close()
+
+
+def test_labels_and_control_points(pair):
+    name, wl, O, G = pair
+    lab = G.node_labels()
+    assert (lab == O.lab_flat).all()
+    xyz, nrm = G.control_points()
+    oxyz, onrm = O.cp_arrays()
+    assert xyz.shape == oxyz.shape
+    assert np.abs(xyz - oxyz).max() <= 1e-14
+    assert np.abs(nrm - onrm).max() <= 1e-12
+    info = G.info()
+    assert info["n_unknowns"] == O.unknowns.size
+
+
+def test_ls_stencils(pair):
+    name, wl, O, G = pair
+    rng = np.random.default_rng(1)
+    for c in rng.choice(O.ncp, size=min(40, O.ncp), replace=False):
+        for side in O.sides:
+            idx, wts = G.ls_stencil(int(c), side)
+            st = O.stencil(int(c), side)
+            assert list(idx) == list(st.idx), (name, c, side)
+            scale = np.abs(st.S).max()
+            assert np.abs(wts - st.S).max() <= 1e-12 * scale, (name, c, side, np.abs(wts - st.S).max() / scale)
+
+
+def test_apply(pair):
+    name, wl, O, G = pair
+    L, LG = O.assemble()
+    rng = np.random.default_rng(2)
+    x = np.zeros(O.lab_flat.size)
+    x[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    y = G.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    yo = np.zeros_like(x)
+    yo[O.unknowns] = L @ x[O.unknowns]
+    scale = abs(L).max() * np.abs(x).max()
+    assert np.abs(y - yo).max() <= 1e-13 * scale, np.abs(y - yo).max() / scale
+    # with data: L x + L_Gamma u_Gamma, and the right-hand side
+    cpd, box, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, box)
+    ug = O.data_vector(cpd, wl.box_data())
+    yd = G.apply(torch.tensor(x, device="cuda"), with_data=True).cpu().numpy()
+    yod = np.zeros_like(x)
+    yod[O.unknowns] = L @ x[O.unknowns] + LG @ ug
+    scale2 = max(scale, np.abs(LG @ ug).max())
+    assert np.abs(yd - yod).max() <= 1e-13 * scale2
+
+
+def test_level_operators(pair):
+    name, wl, O, G = pair
+    H = Hierarchy(O)
+    rng = np.random.default_rng(3)
+    nl = len(H.levels)
+    for l, lev in enumerate(H.levels):
+        n, nu = G.level_info(l)
+        assert n == lev.grid.n and nu == lev.unknowns.size
+        assert (G.level_labels(l) == lev.lab_flat).all()
+        v = np.zeros(lev.lab_flat.size)
+        v[lev.unknowns] = rng.standard_normal(lev.unknowns.size)
+        vt = torch.tensor(v, device="cuda")
+        out = torch.zeros_like(vt)
+        # operator
+        y = G.level_op(l, 0, vt, out).cpu().numpy()[lev.unknowns]
+        yo = lev.A @ v[lev.unknowns]
+        sc = abs(lev.A).max() * np.abs(v).max()
+        assert np.abs(y - yo).max() <= 1e-13 * sc, (name, l, "A")
+        # one red-black sweep from z0 with rhs b
+        z0 = np.zeros_like(v)
+        z0[lev.unknowns] = rng.standard_normal(lev.unknowns.size)
+        zt = torch.tensor(z0, device="cuda")
+        G.level_op(l, 1, vt, zt)
+        zo = z0[lev.unknowns].copy()
+        H.rbgs(l, zo, v[lev.unknowns])
+        assert np.abs(zt.cpu().numpy()[lev.unknowns] - zo).max() <= 1e-12 * (np.abs(zo).max() + 1), (name, l, "rbgs")
+        if l + 1 < nl:
+            cl = H.levels[l + 1]
+            outc = torch.zeros(cl.lab_flat.size, dtype=torch.float64, device="cuda")
+            rc = G.level_op(l, 2, vt, outc).cpu().numpy()[cl.unknowns]
+            assert np.abs(rc - H.restrict(l, v[lev.unknowns])).max() <= 1e-14 * np.abs(v).max() * 4, (name, l, "R")
+        if l > 0:
+            fl = H.levels[l - 1]
+            outf = torch.zeros(fl.lab_flat.size, dtype=torch.float64, device="cuda")
+            pf = G.level_op(l, 3, vt, outf).cpu().numpy()[fl.unknowns]
+            assert np.abs(pf - H.prolong(l, v[lev.unknowns])).max() <= 1e-14 * np.abs(v).max() * 4, (name, l, "P")
+        if l == nl - 1:
+            zc = G.level_op(l, 4, vt, torch.zeros_like(vt)).cpu().numpy()[lev.unknowns]
+            zco = H.coarse_solve(v[lev.unknowns])
+            assert np.abs(zc - zco).max() <= 1e-11 * np.abs(zco).max(), (name, "coarse")
+
+
+def test_vcycle_fp64(pair):
+    name, wl, O, G = pair
+    H = Hierarchy(O)
+    rng = np.random.default_rng(4)
+    v = np.zeros(O.lab_flat.size)
+    v[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    z = G.vcycle(torch.tensor(v, device="cuda")).cpu().numpy()[O.unknowns]
+    zo = H.precondition(v[O.unknowns])
+    assert np.abs(z - zo).max() <= 1e-12 * np.abs(zo).max(), np.abs(z - zo).max() / np.abs(zo).max()
+
+
+def test_solve_matches_direct(pair):
+    name, wl, O, G = pair
+    L, LG = O.assemble()
+    cpd, box, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, box)
+    G.set_rhs(f)
+    u, hist, st = G.solve()
+    assert st["status"] == 0, st
+    ug = O.data_vector(cpd, wl.box_data())
+    b = O.rhs(wl.rhs(O.labels), ug)
+    ud = O.direct_solve(b)
+    uu = u.cpu().numpy()[O.unknowns]
+    # the oracle's own check of the GPU solution's true residual
+    assert np.linalg.norm(b - L @ uu) <= 1e-12 * np.linalg.norm(b)
+    assert np.abs(uu - ud).max() <= 1e-11 * np.abs(ud).max(), np.abs(uu - ud).max() / np.abs(ud).max()
+    # non-unknown nodes are NaN
+    assert np.isnan(u.cpu().numpy()[O.lab_flat == 0]).all()

@@ -268,7 +268,7 @@ def cfg4_spheres(n: int = 384, count: int = 16, seed: int = 0, precision: str = 
 
 def small_spheres_union() -> List[Tuple]:
     """A resolvable-at-small-n stand-in for cfg 4 (3 spheres, radius >= 0.3)."""
-    return [((-0.35, -0.3, 0.05), 0.32), ((0.4, 0.25, -0.2), 0.3), ((0.05, 0.45, 0.5), 0.3)]
+    return [((-0.3, -0.3, 0.05), 0.3), ((0.35, 0.25, -0.2), 0.28), ((0.05, 0.38, 0.33), 0.27)]
 
 
 def small_circles_union_2d() -> List[Tuple]:
