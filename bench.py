@@ -1,0 +1,240 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X immersed-interface Poisson solver.
+
+One step = the whole hot path on one problem: device setup (labels, control
+points, FP64 least-squares fits, irregular records, SW hierarchy), boundary
+data and right-hand side, and the FGMRES + SW-multigrid solve to a true
+relative residual of 1e-10.  Inputs (boundary data sampled at the library's
+control points, f on the grid) are resident in device memory before the timed
+region.  Prints one JSON line.
+
+Default workload: 2D interface problem, 1024 x 1024, five-lobe star
+r = 0.5 + 0.1 cos(5 theta), u = e^x cos y inside / x^2 - y^2 outside, jumps from
+these, Dirichlet box, FP64 solve (the mixed-precision solve of the same problem
+is timed beside it).  Other workloads: --workload cfg1|cfg3|cfg4.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+WORKLOADS = {
+    "cfg1": lambda: W.cfg1_circle(64),
+    "cfg2": lambda: W.cfg2_star(1024),
+    "cfg3": lambda: W.cfg3_sphere(256, precision="mixed32"),
+    "cfg4": lambda: W.cfg4_spheres(384, precision="mixed16"),
+}
+DESCR = {
+    "cfg1": "2D Dirichlet circle r=0.5, 64x64, u=sin(2 pi x)cos(2 pi y)",
+    "cfg2": "2D interface star r=0.5+0.1cos(5t), 1024x1024, jumps from e^x cos y / x^2-y^2, Dirichlet box",
+    "cfg3": "3D Dirichlet sphere r=0.6, 256^3, u=sin(pi x)sin(pi y)sin(pi z)",
+    "cfg4": "3D Neumann on 16 spheres (seed 0), Dirichlet box, 384^3, u=cos(2x)sinh(y)+z^2",
+}
+HBM_PEAK_GBS = 8000.0
+# kernel id -> (name, launches per FGMRES iteration factor computed below)
+KERNELS = {0: "ho_apply", 1: "ghosts", 2: "rbgs_level0", 3: "resid_restrict_0_1", 4: "prolong_1_0", 5: "cgs_update_dot_k6"}
+
+
+def prepare(wl, torch):
+    from paper_2503_22455_amd import iim
+    P = iim.from_workload(wl, precision="fp64")
+    lab = P.node_labels()
+    xyz, nrm = P.control_points()
+    cpd = torch.tensor(np.ascontiguousarray(wl.cp_data(xyz, nrm), dtype=np.float64).ravel(), device="cuda")
+    box = torch.tensor(iim.grid_to_flat(wl.box_data()), device="cuda") if wl.side != W.SIDE_INTERIOR else None
+    f = torch.tensor(iim.grid_to_flat(wl.rhs(iim.flat_to_grid(lab, wl.dim, wl.n))), device="cuda")
+    nu = P.info()["n_unknowns"]
+    P.close()
+    return cpd, box, f, nu
+
+
+def one_step(wl, precision, cpd, box, f, torch, rtol=1e-10):
+    from paper_2503_22455_amd import iim
+    t0 = time.perf_counter()
+    P = iim.from_workload(wl, precision=precision, rtol=rtol)
+    t1 = time.perf_counter()
+    P.set_boundary_data(cpd, box)
+    P.set_rhs(f)
+    u, hist, st = P.solve()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    info = P.info()
+    P.close()
+    return t2 - t0, t1 - t0, st, info
+
+
+def kernel_roofline(wl, precision, torch, nu, reps=20):
+    """Average duration of each hot kernel (HIP events on the library's stream)
+    and its algorithmic bytes per launch."""
+    from paper_2503_22455_amd import iim
+    P = iim.from_workload(wl, precision=precision)
+    info = P.info()
+    ssz = {"fp64": 8, "mixed32": 4, "mixed16": 2}[precision]
+    tsz = 8 if precision == "fp64" else 4
+    dim = wl.dim
+    nc1 = P.level_info(1)[1] if info["levels"] > 1 else 0
+    nrows = 2 if wl.bc == W.BC_DIRICHLET else (2 if wl.bc == W.BC_NEUMANN else 3)
+    ncs = info["n_control_points"] * info["sides"]
+    k = 6
+    algo = {
+        0: 16.0 * nu,                                             # read x, write y
+        1: (8.0 * nrows + 4.0) * info["n_ls_entries"] + 8.0 * 2 * ncs,  # weights + indices + ghost writes
+        2: (2.0 * ssz + tsz) * nu,                                # read z, b; write z (both colours)
+        3: (ssz + tsz) * nu + tsz * nc1,                          # read z, b fine; write b coarse
+        4: ssz * nc1 + 2.0 * ssz * nu,                            # read coarse z; read+write fine z
+        5: 8.0 * (k + 2) * nu,                                    # read k basis vectors and w, write w
+    }
+    out = {}
+    for kid, name in KERNELS.items():
+        ms = P.time_kernel(kid, reps)
+        out[kid] = (name, ms, algo[kid])
+    P.close()
+    return out, info
+
+
+def cpu_baseline(wl, its_gpu, nu, sample_iters=3):
+    """The oracle as it stands, single-threaded, on a bounded sample of the same
+    workload: its full setup (labels, control points, fits, assembly, SW
+    hierarchy, right-hand side) plus `sample_iters` FGMRES iterations; the
+    solve time is extrapolated to the GPU's iteration count."""
+    from threadpoolctl import threadpool_limits
+    from oracle.iim import IIMProblem
+    from oracle.mg import Hierarchy
+    from oracle.krylov import fgmres
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O = IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus)
+        L, LG = O.assemble()
+        xyz, nrm = O.cp_arrays()
+        ug = O.data_vector(wl.cp_data(xyz, nrm), wl.box_data())
+        b = O.rhs(wl.rhs(O.labels), ug)
+        H = Hierarchy(O)
+        t1 = time.perf_counter()
+        fgmres(lambda v: L @ v, H.precondition, b, rtol=1e-30, max_iters=sample_iters)
+        t2 = time.perf_counter()
+    t_setup = t1 - t0
+    t_iter = (t2 - t1) / sample_iters
+    t_total = t_setup + its_gpu * t_iter
+    return {"value": nu / t_total, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle setup ({t_setup:.1f} s) + {sample_iters} FGMRES iterations "
+                       f"({t_iter:.2f} s each) on the same workload, single thread, solve extrapolated "
+                       f"to the GPU's {its_gpu} iterations"),
+            "t_setup_s": t_setup, "t_iter_s": t_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, help="override the workload's precision")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X (a multi-GPU "
+              "decomposition is designed but not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]()
+    prec = args.precision or wl.precision
+    cpd, box, f, nu = prepare(wl, torch)
+    print(f"[bench] workload {args.workload}: {nu} unknowns, precision {prec}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        one_step(wl, prec, cpd, box, f, torch)
+    torch.cuda.synchronize()
+    lat, setup, its, res = [], [], [], []
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        dt, ds, st, info = one_step(wl, prec, cpd, box, f, torch)
+        lat.append(dt)
+        setup.append(ds)
+        its.append(st["iterations"])
+        res.append(st["final_rel_residual"])
+        print(f"[bench] step {s}: {dt*1e3:.1f} ms (setup {ds*1e3:.1f} ms, {st['iterations']} its, "
+              f"res {st['final_rel_residual']:.2e})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    ms_per_step = total / args.steps * 1e3
+    value = nu * args.steps / total
+
+    # time to 1e-10 (solve only) for FP64 and mixed precision on the same problem
+    ttr = {}
+    for p in (["fp64", "mixed32", "mixed16"] if not args.no_mixed else [prec]):
+        one_step(wl, p, cpd, box, f, torch)
+        dts = []
+        itp = 0
+        for _ in range(3):
+            from paper_2503_22455_amd import iim
+            P = iim.from_workload(wl, precision=p)
+            P.set_boundary_data(cpd, box)
+            P.set_rhs(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, hist, st = P.solve()
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - t0)
+            itp = st["iterations"]
+            ok = st["final_rel_residual"] <= 1e-10
+            P.close()
+        ttr[p] = {"ms": float(np.median(dts) * 1e3), "iterations": itp, "reached": bool(ok)}
+        print(f"[bench] time-to-1e-10 {p}: {ttr[p]}", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel: measured duration x launches per iteration
+    kr, info = kernel_roofline(wl, prec, torch, nu)
+    launches = {0: 1, 1: 1, 2: 2 * 2, 3: 1, 4: 1, 5: 2}   # per FGMRES iteration (nu_pre = nu_post = 2)
+    dom = max(kr, key=lambda k: kr[k][1] * launches[k])
+    name, ms, algo_bytes = kr[dom]
+    achieved = algo_bytes / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(algo_bytes)}
+    kernels = {kr[k][0]: {"avg_us": round(kr[k][1] * 1e3, 2),
+                          "GBs": round(kr[k][2] / (kr[k][1] * 1e-3) / 1e9, 1)} for k in kr}
+    for k in kr:
+        print(f"[bench] kernel {kr[k][0]}: {kr[k][1]*1e3:.2f} us, {kr[k][2]/(kr[k][1]*1e-3)/1e9:.1f} GB/s",
+              file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, int(np.median(its)), nu)
+        print(f"[bench] cpu baseline: {cpu['value']:.3g} DOF/s", file=sys.stderr, flush=True)
+
+    lat_sorted = sorted(lat)
+    def pct(q):
+        return lat_sorted[min(len(lat_sorted) - 1, max(0, math.ceil(q * len(lat_sorted)) - 1))] * 1e3
+    out = {
+        "metric": "DOF/s and time-to-1e-10 residual (mixed vs FP64) + p50/p99 solve latency",
+        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else ("f64+f32" if prec == "mixed32" else "f64+f32/f16"),
+        "data": "synthetic",
+        "config": {"workload": DESCR[args.workload], "n": wl.n, "dim": wl.dim, "unknowns": nu,
+                   "precision": prec, "rtol": 1e-10},
+        "p50_ms": pct(0.5), "p99_ms": pct(0.99), "solves_per_s": args.steps / total,
+        "setup_ms_median": float(np.median(setup) * 1e3), "iterations": int(np.median(its)),
+        "final_rel_residual_max": float(max(res)),
+        "time_to_1e-10": ttr,
+        "roofline": roofline, "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

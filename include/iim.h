@@ -212,6 +212,17 @@ int iim_level_info(const iim_problem* p, int32_t level, int32_t* n, int64_t* n_u
 int iim_level_labels(const iim_problem* p, int32_t level, uint8_t* labels);
 int iim_level_op(iim_problem* p, int32_t level, int32_t op, const double* in1, double* out);
 
+/* Kernel timing for measurement: launches one hot-path kernel `reps` times in
+ * its production launch configuration on the handle's stream, bracketed by two
+ * HIP events on that stream, and returns the average duration per launch in
+ * *avg_ms.  The operands are the handle's own work vectors (contents are
+ * overwritten).  kernel: 0 = high-order stencil apply (level 0),
+ * 1 = ghost values, 2 = one red-black sweep on level 0 (both colours),
+ * 3 = residual + restriction 0 -> 1, 4 = prolongation 1 -> 0,
+ * 5 = fused orthogonalisation update + dots over 6 basis vectors,
+ * 6 = one whole V-cycle, 7 = one whole operator apply (ghosts + stencil). */
+int iim_time_kernel(iim_problem* p, int32_t kernel, int32_t reps, double* avg_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,8 @@ struct Problem {
     void vcycle(const double* v, double* out);
     int solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st);
     int level_op(int level, int op, const double* in1, double* out);
+    template <typename T, typename S> void launch_kernel_t(int kernel);
+    double time_kernel(int kernel, int reps);
     template <typename T, typename S> int level_op_t(int level, int op, const double* in1, double* out);
     ~Problem();
 };

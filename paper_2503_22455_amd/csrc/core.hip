@@ -643,6 +643,61 @@ int Problem::level_op_t(int l, int op, const double* in1, double* out) {
     return IIM_OK;
 }
 
+template <typename T, typename S>
+void Problem::launch_kernel_t(int kernel) {
+    const int64_t N = box.size();
+    switch (kernel) {
+        case 0: {
+            const Level& L0 = levels[0];
+            run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ghost, boxval, w,
+                         1.0 / (h * h), opt.beta_plus, opt.beta_minus, rk, wk, 0, stream);
+            break;
+        }
+        case 1: run_ghosts(ghost_dev(), rk, cpdata, 0, ghost, stream); break;
+        case 2:
+            run_rbgs<T, S>(level_dev(0), 0, (S*)levels[0].z, (const T*)levels[0].b, stream);
+            run_rbgs<T, S>(level_dev(0), 1, (S*)levels[0].z, (const T*)levels[0].b, stream);
+            break;
+        case 3:
+            if (levels.size() > 1)
+                run_resid_restrict<T, S>(level_dev(0), level_dev(1), (const S*)levels[0].z, (const T*)levels[0].b,
+                                         (T*)levels[1].b, stream);
+            break;
+        case 4:
+            if (levels.size() > 1)
+                run_prolong<T, S>(level_dev(0), level_dev(1), (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1,
+                                  (const S*)levels[1].z, (S*)levels[0].z, stream);
+            break;
+        case 5: {
+            int k = std::min(6, opt.restart);
+            run_update_dot(Vb, N, k, red_out + 192, wk, N, k, 0, red_part, red_out + 64, stream);
+            break;
+        }
+        case 6: vcycle(rk, wk); break;
+        case 7: apply_box(rk, wk, 0); break;
+        default: throw Error(IIM_E_INVALID_ARG, "unknown kernel id");
+    }
+}
+
+double Problem::time_kernel(int kernel, int reps) {
+    // operands: deterministic non-trivial contents; red_out[192..] holds zeros (update coefficients)
+    IIM_HIP(hipMemsetAsync(red_out + 192, 0, 32 * sizeof(double), stream));
+    run_copy(rhs, rk, box.size(), stream);
+    auto launch = [&]() {
+        if (opt.precision == IIM_PREC_FP64) launch_kernel_t<double, double>(kernel);
+        else if (opt.precision == IIM_PREC_MIXED32) launch_kernel_t<float, float>(kernel);
+        else launch_kernel_t<float, __half>(kernel);
+    };
+    launch();  // warm
+    IIM_HIP(hipEventRecord(ev[4], stream));
+    for (int r = 0; r < reps; ++r) launch();
+    IIM_HIP(hipEventRecord(ev[5], stream));
+    IIM_HIP(hipEventSynchronize(ev[5]));
+    float ms = 0.f;
+    IIM_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+    return (double)ms / reps;
+}
+
 int Problem::level_op(int l, int op, const double* in1, double* out) {
     if (opt.precision == IIM_PREC_FP64) return level_op_t<double, double>(l, op, in1, out);
     if (opt.precision == IIM_PREC_MIXED32) return level_op_t<float, float>(l, op, in1, out);
@@ -978,6 +1033,15 @@ int iim_level_op(iim_problem* h, int32_t level, int32_t op, const double* in1, d
         if (!h || !in1 || !out) throw Error(IIM_E_INVALID_ARG, "null argument");
         Problem& p = *h->p;
         return p.level_op(level, op, in1, out);
+    })
+}
+
+int iim_time_kernel(iim_problem* h, int32_t kernel, int32_t reps, double* avg_ms) {
+    ABI_TRY({
+        if (!h || !avg_ms || reps < 1) throw Error(IIM_E_INVALID_ARG, "bad argument");
+        Problem& p = *h->p;
+        *avg_ms = p.time_kernel(kernel, reps);
+        return IIM_OK;
     })
 }
 

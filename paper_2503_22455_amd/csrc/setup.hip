@@ -9,31 +9,59 @@ namespace iim {
 // ---------------------------------------------------------------------------
 // labels
 // ---------------------------------------------------------------------------
-__global__ void k_classify_bbox(Geom g, int* bbox, int* err, unsigned long long* count) {
+__global__ void __launch_bounds__(256) k_classify_bbox(Geom g, int* bbox, int* err, unsigned long long* count) {
+    __shared__ int sh[7][256];
     int64_t n1 = g.n + 1;
     int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    int cnt = 0, bad = 0;
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
         int ijk[3] = {(int)(l % n1), (int)((l / n1) % n1), g.dim == 3 ? (int)(l / (n1 * n1)) : 0};
         uint8_t k = node_kind(g, ijk);
         if (k == 255) {
-            atomicOr(err, 1);
+            bad = 1;
             continue;
         }
         if (k == K_PLUS || k == K_MINUS) {
             for (int d = 0; d < 3; ++d) {
-                atomicMin(&bbox[d], ijk[d]);
-                atomicMax(&bbox[3 + d], ijk[d]);
+                mn[d] = min(mn[d], ijk[d]);
+                mx[d] = max(mx[d], ijk[d]);
             }
-            atomicAdd(count, 1ull);
+            ++cnt;
         }
+    }
+    const int t = threadIdx.x;
+    for (int d = 0; d < 3; ++d) {
+        sh[d][t] = mn[d];
+        sh[3 + d][t] = mx[d];
+    }
+    sh[6][t] = cnt;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            for (int d = 0; d < 3; ++d) {
+                sh[d][t] = min(sh[d][t], sh[d][t + off]);
+                sh[3 + d][t] = max(sh[3 + d][t], sh[3 + d][t + off]);
+            }
+            sh[6][t] += sh[6][t + off];
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(err, 1);
+    if (t == 0 && sh[6][0] > 0) {
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(&bbox[d], sh[d][0]);
+            atomicMax(&bbox[3 + d], sh[3 + d][0]);
+        }
+        atomicAdd(count, (unsigned long long)sh[6][0]);
     }
 }
 
 void run_classify_bbox(const Geom& g, int* d_bbox, int* d_err, unsigned long long* d_count, hipStream_t s) {
     int64_t n1 = g.n + 1;
     int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
-    int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
+    int blocks = (int)std::min<int64_t>(cdiv(total, 256), 2048);
     hipLaunchKernelGGL(k_classify_bbox, dim3(blocks), dim3(256), 0, s, g, d_bbox, d_err, d_count);
     IIM_LAUNCH_CHECK();
 }

@@ -93,6 +93,7 @@ def lib():
         L.iim_level_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.iim_level_labels.argtypes = [vp, i32, vp]
         L.iim_level_op.argtypes = [vp, i32, i32, vp, vp]
+        L.iim_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -205,16 +206,23 @@ class Problem:
         return out
 
     # -- data ---------------------------------------------------------------------
-    def set_boundary_data(self, cp_data, box_data=None):
+    @staticmethod
+    def _dev(a):
         import torch
-        cpd = torch.as_tensor(np.ascontiguousarray(cp_data, dtype=np.float64).ravel()).cuda()
-        box = None if box_data is None else torch.as_tensor(np.ascontiguousarray(box_data, dtype=np.float64)).cuda()
+        if hasattr(a, "is_cuda") and a.is_cuda:
+            return a.contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).ravel()).cuda()
+
+    def set_boundary_data(self, cp_data, box_data=None):
+        """cp_data: one value per control point (two, j0 then j1, for jumps);
+        box_data: full-grid array (only box faces are read) or None."""
+        cpd = self._dev(cp_data)
+        box = None if box_data is None else self._dev(box_data)
         _check(lib().iim_set_boundary_data(self._h, _ptr(cpd) if cpd.numel() else None,
                                            None if box is None else _ptr(box), MEM_DEVICE))
 
     def set_rhs(self, f):
-        import torch
-        ft = torch.as_tensor(np.ascontiguousarray(f, dtype=np.float64)).cuda() if not hasattr(f, "is_cuda") else f
+        ft = self._dev(f)
         _check(lib().iim_set_rhs(self._h, _ptr(ft), MEM_DEVICE))
 
     # -- operations on device tensors ---------------------------------------------------
@@ -233,6 +241,13 @@ class Problem:
     def level_op(self, level: int, op: int, in1, out):
         _check(lib().iim_level_op(self._h, level, op, _ptr(in1), _ptr(out)))
         return out
+
+    def time_kernel(self, kernel: int, reps: int = 20) -> float:
+        """Average milliseconds per launch of one hot-path kernel (HIP events on
+        the handle's stream); see iim_time_kernel for the ids."""
+        ms = ctypes.c_double()
+        _check(lib().iim_time_kernel(self._h, kernel, reps, ctypes.byref(ms)))
+        return ms.value
 
     def solve(self, x0=None, hist_cap: int = 1000):
         import torch

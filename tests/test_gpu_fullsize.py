@@ -1,0 +1,48 @@
+"""Parity at the benchmark sizes, on outputs the oracle computes one row at a
+time: the 1024^2 interface operator and the 256^3 sphere operator, in the
+launch configuration the benchmark times."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import oracle_for, gpu_for, oracle_data
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _sampled_apply(wl, nsample, seed):
+    O = oracle_for(wl)
+    G = gpu_for(wl, precision="fp64")
+    info = G.info()
+    assert info["n_unknowns"] == O.unknowns.size
+    assert (G.node_labels() == O.lab_flat).all()
+    xyz, nrm = G.control_points()
+    oxyz, onrm = O.cp_arrays()
+    assert np.abs(xyz - oxyz).max() <= 1e-14
+    rng = np.random.default_rng(seed)
+    x = np.zeros(O.lab_flat.size)
+    x[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    cpd, box, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, box)
+    ug = O.data_vector(cpd, wl.box_data())
+    y = G.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    yd = G.apply(torch.tensor(x, device="cuda"), with_data=True).cpu().numpy()
+    # sample: irregular nodes (next to Gamma or the box) and random interior nodes
+    irr = np.nonzero(~O.regular_mask() & (O.uindex >= 0))[0]
+    nodes = np.concatenate([rng.choice(irr, size=min(nsample, irr.size), replace=False),
+                            rng.choice(O.unknowns, size=nsample, replace=False)])
+    yo = O.apply_rows(nodes, x)
+    yod = O.apply_rows(nodes, x, with_data=True, u_gamma=ug)
+    scale = 25.0 / O.grid.h ** 2 * max(O.beta.values())
+    assert np.abs(y[nodes] - yo).max() <= 1e-13 * scale
+    assert np.abs(yd[nodes] - yod).max() <= 1e-13 * (scale + np.abs(yod).max())
+    G.close()
+
+
+def test_cfg2_star_1024_sampled():
+    _sampled_apply(W.cfg2_star(1024), 300, 11)
+
+
+def test_cfg3_sphere_256_sampled():
+    _sampled_apply(W.cfg3_sphere(256, precision="fp64"), 200, 12)

@@ -1,0 +1,122 @@
+"""GPU checks of the mixed-precision preconditioner, determinism and error
+handling (all through the C ABI)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.mg import Hierarchy
+from tests.gpu_helpers import oracle_for, gpu_for, oracle_data
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed32", 2e-5), ("mixed16", 3e-2)])
+@pytest.mark.parametrize("make", [lambda: W.cfg1_circle(64), lambda: W.cfg2_star(128),
+                                  lambda: W.cfg3_sphere(24)], ids=["cfg1", "star128", "sphere24"])
+def test_vcycle_reduced_precision(make, prec, tol):
+    """FP32 V-cycle within 2e-5 of the FP64 oracle cycle (relative to max |z|);
+    FP16 iterate storage within 3e-2 (its unit round-off is 5e-4 and the
+    cycle amplifies it by the multigrid contraction constants)."""
+    wl = make()
+    O = oracle_for(wl)
+    H = Hierarchy(O)
+    G = gpu_for(wl, precision=prec)
+    rng = np.random.default_rng(5)
+    v = np.zeros(O.lab_flat.size)
+    v[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    z = G.vcycle(torch.tensor(v, device="cuda")).cpu().numpy()[O.unknowns]
+    zo = H.precondition(v[O.unknowns])
+    assert np.abs(z - zo).max() <= tol * np.abs(zo).max()
+    G.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed32", "mixed16"])
+@pytest.mark.parametrize("make", [lambda: W.cfg1_circle(64), lambda: W.cfg2_star(256),
+                                  lambda: W.cfg3_sphere(32),
+                                  lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union())],
+                         ids=["cfg1", "star256", "sphere32", "spheres32"])
+def test_mixed_solve_reaches_1e10(make, prec):
+    """The FP64 outer solve with a reduced-precision V-cycle reaches a true
+    relative residual <= 1e-10, checked with the oracle's assembled matrix, and
+    its solution agrees with the direct solve to the conditioning."""
+    wl = make()
+    O = oracle_for(wl)
+    L, LG = O.assemble()
+    cpd, box, f = oracle_data(O, wl)
+    G = gpu_for(wl, precision=prec, rtol=1e-10)
+    G.set_boundary_data(cpd, box)
+    G.set_rhs(f)
+    u, hist, st = G.solve()
+    assert st["status"] == 0, st
+    ug = O.data_vector(cpd, wl.box_data())
+    b = O.rhs(wl.rhs(O.labels), ug)
+    uu = u.cpu().numpy()[O.unknowns]
+    assert np.linalg.norm(b - L @ uu) <= 1e-10 * np.linalg.norm(b)
+    ud = O.direct_solve(b)
+    assert np.abs(uu - ud).max() <= 1e-7 * np.abs(ud).max()
+    G.close()
+
+
+def test_solves_are_bitwise_deterministic():
+    wl = W.cfg2_star(128)
+    O = oracle_for(wl)
+    cpd, box, f = oracle_data(O, wl)
+    outs = []
+    for _ in range(2):
+        G = gpu_for(wl, precision="mixed32")
+        G.set_boundary_data(cpd, box)
+        G.set_rhs(f)
+        u, hist, st = G.solve()
+        outs.append((u.cpu().numpy(), hist))
+        G.close()
+    assert np.array_equal(outs[0][0], outs[1][0], equal_nan=True)
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_restart_resumes_from_x0():
+    """FGMRES restarts from x anyway: a solve resumed from an intermediate
+    iterate reaches the same tolerance."""
+    wl = W.cfg1_circle(64)
+    O = oracle_for(wl)
+    cpd, box, f = oracle_data(O, wl)
+    G = gpu_for(wl, precision="fp64", max_iters=5)
+    G.set_boundary_data(cpd, box)
+    G.set_rhs(f)
+    u5, h5, st5 = G.solve()
+    assert st5["status"] == 1 and st5["iterations"] == 5
+    x0 = torch.nan_to_num(u5, nan=0.0)
+    G2 = gpu_for(wl, precision="fp64", rtol=1e-10)
+    G2.set_boundary_data(cpd, box)
+    G2.set_rhs(f)
+    u, h, st = G2.solve(x0=x0)
+    assert st["status"] == 0 and st["final_rel_residual"] <= 1e-10
+    G.close()
+    G2.close()
+
+
+def test_error_paths():
+    from paper_2503_22455_amd import iim
+    # under-resolved curvature: |kappa h| >= 1/4
+    with pytest.raises(iim.IIMError) as e:
+        iim.Problem(2, 16, W.GEOM_SPHERE, [0.0, 0.0, 0.2], W.SIDE_INTERIOR, W.BC_DIRICHLET)
+    assert e.value.code == -2
+    # body touching the box
+    with pytest.raises(iim.IIMError) as e:
+        iim.Problem(2, 32, W.GEOM_SPHERE, [0.0, 0.0, 1.2], W.SIDE_INTERIOR, W.BC_DIRICHLET)
+    assert e.value.code == -2
+    # a sphere 3.2 h below a Dirichlet box face leaves too few levels for a degree-4 fit
+    bad = [((-0.35, -0.3, 0.05), 0.32), ((0.4, 0.25, -0.2), 0.3), ((0.05, 0.45, 0.5), 0.3)]
+    with pytest.raises(iim.IIMError) as e:
+        gpu_for(W.cfg4_spheres(32, spheres=bad))
+    assert e.value.code == -2
+    # invalid options
+    with pytest.raises(iim.IIMError) as e:
+        iim.Problem(2, 64, W.GEOM_SPHERE, [0.0, 0.0, 0.5], W.SIDE_INTERIOR, W.BC_JUMP)
+    assert e.value.code == -1
+    with pytest.raises(iim.IIMError):
+        iim.Problem(2, 64, W.GEOM_SPHERE, [0.0, 0.0, 0.5], W.SIDE_INTERIOR, W.BC_DIRICHLET, restart=40)
+    # the library keeps working after errors
+    G = gpu_for(W.cfg1_circle(64))
+    assert G.info()["n_unknowns"] == 793
+    G.close()
