@@ -108,7 +108,11 @@ typedef struct iim_options {
     int32_t precision;  /* IIM_PREC_* */
     double ls_axis_t;   /* least-squares half-ellipse semi-axes in units of h */
     double ls_axis_n;   /*   (0 = defaults k and k - 1/2) */
-    int32_t use_graph;  /* capture the V-cycle in a HIP graph (1) or not (0) */
+    int32_t use_graph;  /* replay each FGMRES iteration as a captured HIP graph (1) or launch eagerly (0) */
+    int32_t tail_nodes; /* levels whose storage box has at most this many nodes run in one
+                           single-workgroup kernel (0 = library default; < 0 = coarse solve only) */
+    int32_t fused_smoothing; /* 1: LDS-tiled kernels fuse each level's smoothing with its
+                                transfer (2D); 0: one kernel per half-sweep and transfer */
     int32_t reserved;
 } iim_options;
 

@@ -33,9 +33,14 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# the least-squares fits keep the Householder columns in registers: their loops
+# must unroll completely
+EXTRA = {"lsq.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [_hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc()] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")

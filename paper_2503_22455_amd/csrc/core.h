@@ -37,6 +37,7 @@ struct Level {
 };
 
 constexpr int KRED = 16;  // reduction outputs per launch
+constexpr int64_t TAIL_MAX_NODES = 4096;  // levels handled by the one-workgroup tail kernel
 
 struct Problem {
     DevMem mem;
@@ -79,6 +80,12 @@ struct Problem {
     double *red_part = nullptr, *red_out = nullptr;
     double* red_scale = nullptr;
     hipEvent_t ev[8] = {};
+    bool own_stream = false;
+    int tail_first = 0;
+    bool opt_fused = true;  // LDS-tiled fused smoothing legs where available
+    TailDev* d_tail = nullptr;
+    double* hpin = nullptr;  // pinned host copy of the Hessenberg column
+    hipGraphExec_t iter_graph[16] = {};
     double t_setup_ms = 0.0;
 
     void setup();
@@ -90,6 +97,7 @@ struct Problem {
     void apply_box(const double* x, double* y, int with_data);
     template <typename T, typename S> void vcycle_t(const double* v, double* out);
     void vcycle(const double* v, double* out);
+    void iteration_body(int j, hipEvent_t* evs = nullptr);
     int solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st);
     int level_op(int level, int op, const double* in1, double* out);
     template <typename T, typename S> void launch_kernel_t(int kernel);

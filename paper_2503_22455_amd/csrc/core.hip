@@ -344,6 +344,33 @@ void Problem::setup() {
         IIM_HIP(hipMemsetAsync(L.z, 0, L.box.size() * ssz, stream));
         IIM_HIP(hipMemsetAsync(L.b, 0, L.box.size() * tsz, stream));
     }
+    // levels small enough for the single-workgroup tail kernel
+    // default: in 2D the fused LDS legs are faster than the one-workgroup tail on
+    // every level but the coarsest; in 3D small levels go to the tail
+    const int64_t tail_default = (dim == 2 && opt_fused) ? -1 : TAIL_MAX_NODES;
+    const int64_t tail_max = opt.tail_nodes == 0 ? tail_default : (int64_t)opt.tail_nodes;
+    tail_first = (int)levels.size() - 1;
+    while (tail_first > 0 && levels[tail_first - 1].box.size() <= tail_max) --tail_first;
+    {
+        TailDev T{};
+        T.first = tail_first;
+        T.last = (int)levels.size() - 1;
+        T.mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+        T.nu_pre = opt.nu_pre;
+        T.nu_post = opt.nu_post;
+        T.nc = nc;
+        T.clist = coarse_list;
+        T.Ainv = opt.precision == IIM_PREC_FP64 ? (const void*)Ainv64 : (const void*)Ainv32;
+        if (levels.size() > MAX_LEVELS) throw Error(IIM_E_INVALID_ARG, "too many multigrid levels");
+        for (size_t l = 0; l < levels.size(); ++l) {
+            T.lev[l] = level_dev((int)l);
+            T.z[l] = levels[l].z;
+            T.b[l] = levels[l].b;
+        }
+        d_tail = (TailDev*)mem.alloc(sizeof(TailDev));
+        IIM_HIP(hipMemcpyAsync(d_tail, &T, sizeof(TailDev), hipMemcpyHostToDevice, stream));
+    }
+    IIM_HIP(hipHostMalloc((void**)&hpin, 256 * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 8; ++i) IIM_HIP(hipEventCreate(&ev[i]));
     IIM_HIP(hipStreamSynchronize(stream));
     mem.release(d_err);
@@ -398,13 +425,15 @@ void Problem::apply_box(const double* x, double* y, int with_data) {
 template <typename T, typename S>
 void Problem::vcycle_t(const double* v, double* out) {
     const int nl = (int)levels.size();
+    const int t = tail_first;
     LevelDev D0 = level_dev(0);
     run_absmax(v, box.size(), red_part, red_scale, stream);
     run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
-    for (int l = 0; l < nl - 1; ++l) {
+    for (int l = 0; l < t; ++l) {
         LevelDev D = level_dev(l), C = level_dev(l + 1);
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
+        if (opt_fused && run_down_fused<T, S>(D, C, b, z, (T*)levels[l + 1].b, opt.nu_pre, stream)) continue;
         run_zero<S>(z, levels[l].box.size(), stream);
         for (int s = 0; s < opt.nu_pre; ++s) {
             run_rbgs<T, S>(D, 0, z, b, stream);
@@ -412,23 +441,20 @@ void Problem::vcycle_t(const double* v, double* out) {
         }
         run_resid_restrict<T, S>(D, C, z, b, (T*)levels[l + 1].b, stream);
     }
-    {
-        Level& Lc = levels[nl - 1];
-        run_zero<S>((S*)Lc.z, Lc.box.size(), stream);
-        const T* Ainv = std::is_same<T, double>::value ? (const T*)Ainv64 : (const T*)Ainv32;
-        run_coarse_solve<T, S>(level_dev(nl - 1), coarse_list, nc, Ainv, (const T*)Lc.b, (S*)Lc.z, stream);
-    }
+    run_tail<T, S>(dim, d_tail, stream);  // levels t..nl-1, coarse solve included
     const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
-    for (int l = nl - 2; l >= 0; --l) {
+    for (int l = t - 1; l >= 0; --l) {
         LevelDev D = level_dev(l), C = level_dev(l + 1);
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
+        if (opt_fused && run_up_fused<T, S>(D, C, mode, (const S*)levels[l + 1].z, b, z, opt.nu_post, stream)) continue;
         run_prolong<T, S>(D, C, mode, (const S*)levels[l + 1].z, z, stream);
         for (int s = 0; s < opt.nu_post; ++s) {
             run_rbgs<T, S>(D, 0, z, b, stream);
             run_rbgs<T, S>(D, 1, z, b, stream);
         }
     }
+    (void)nl;
     run_cast_out<S>(D0, (const S*)levels[0].z, red_scale + 1, out, stream);
 }
 
@@ -439,6 +465,24 @@ void Problem::vcycle(const double* v, double* out) {
         vcycle_t<float, float>(v, out);
     else
         vcycle_t<float, __half>(v, out);
+}
+
+// One inner FGMRES iteration on the device: z_j = M^{-1} v_j, w = A z_j, CGS2
+// against v_0..v_j, v_{j+1} = w / |w|, and the Hessenberg column copied to
+// pinned host memory.  Pointers are fixed per j, so it can be captured.
+void Problem::iteration_body(int j, hipEvent_t* evs) {
+    const int64_t N = box.size();
+    double* vj = Vb + (size_t)j * N;
+    double* zj = Zb + (size_t)j * N;
+    vcycle(vj, zj);
+    if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
+    apply_box(zj, wk, 0);
+    if (evs) IIM_HIP(hipEventRecord(evs[2], stream));
+    run_multidot(Vb, N, j + 1, wk, N, red_part, red_out, stream);
+    run_update_dot(Vb, N, j + 1, red_out, wk, N, j + 1, 0, red_part, red_out + 64, stream);
+    run_update_dot(Vb, N, j + 1, red_out + 64, wk, N, 0, 1, red_part, red_out + 128, stream);
+    run_normalize(wk, red_out + 128, Vb + (size_t)(j + 1) * N, N, stream);
+    IIM_HIP(hipMemcpyAsync(hpin, red_out, 3 * 64 * sizeof(double), hipMemcpyDeviceToHost, stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -463,7 +507,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
     int status = IIM_OK;
     int its = 0, cycles = 0, hl = 0;
     double true_rel = 0.0;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hbuf(3 * 64);
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
     if (bnorm == 0.0) {
         IIM_HIP(hipMemsetAsync(xk, 0, N * sizeof(double), stream));
     } else {
@@ -496,28 +540,36 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
             int k = 0;
             bool breakdown = false;
             for (int j = 0; j < m; ++j) {
-                double* vj = Vb + (size_t)j * N;
-                double* zj = Zb + (size_t)j * N;
-                IIM_HIP(hipEventRecord(ev[0], stream));
-                vcycle(vj, zj);
-                IIM_HIP(hipEventRecord(ev[1], stream));
-                apply_box(zj, wk, 0);
-                IIM_HIP(hipEventRecord(ev[2], stream));
-                // CGS2: h1 = V^T w; w -= V h1, h2 = V^T w; w -= V h2, |w|^2
-                run_multidot(Vb, N, j + 1, wk, N, red_part, red_out, stream);
-                run_update_dot(Vb, N, j + 1, red_out, wk, N, j + 1, 0, red_part, red_out + 64, stream);
-                run_update_dot(Vb, N, j + 1, red_out + 64, wk, N, 0, 1, red_part, red_out + 128, stream);
-                run_normalize(wk, red_out + 128, Vb + (size_t)(j + 1) * N, N, stream);
-                IIM_HIP(hipEventRecord(ev[3], stream));
-                IIM_HIP(hipMemcpyAsync(hbuf.data(), red_out, 3 * 64 * sizeof(double), hipMemcpyDeviceToHost, stream));
-                IIM_HIP(hipStreamSynchronize(stream));
-                float a1, a2, a3;
-                IIM_HIP(hipEventElapsedTime(&a1, ev[0], ev[1]));
-                IIM_HIP(hipEventElapsedTime(&a2, ev[1], ev[2]));
-                IIM_HIP(hipEventElapsedTime(&a3, ev[2], ev[3]));
-                t_vc += a1;
-                t_apply += a2;
-                t_kr += a3;
+                if (opt.use_graph) {
+                    if (!iter_graph[j]) {
+                        hipGraph_t g;
+                        IIM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+                        iteration_body(j);
+                        IIM_HIP(hipStreamEndCapture(stream, &g));
+                        IIM_HIP(hipGraphInstantiate(&iter_graph[j], g, nullptr, nullptr, 0));
+                        IIM_HIP(hipGraphDestroy(g));
+                    }
+                    IIM_HIP(hipEventRecord(ev[0], stream));
+                    IIM_HIP(hipGraphLaunch(iter_graph[j], stream));
+                    IIM_HIP(hipEventRecord(ev[3], stream));
+                    IIM_HIP(hipStreamSynchronize(stream));
+                    float a;
+                    IIM_HIP(hipEventElapsedTime(&a, ev[0], ev[3]));
+                    t_kr += a;
+                } else {
+                    IIM_HIP(hipEventRecord(ev[0], stream));
+                    iteration_body(j, ev);
+                    IIM_HIP(hipEventRecord(ev[3], stream));
+                    IIM_HIP(hipStreamSynchronize(stream));
+                    float a1, a2, a3;
+                    IIM_HIP(hipEventElapsedTime(&a1, ev[0], ev[1]));
+                    IIM_HIP(hipEventElapsedTime(&a2, ev[1], ev[2]));
+                    IIM_HIP(hipEventElapsedTime(&a3, ev[2], ev[3]));
+                    t_vc += a1;
+                    t_apply += a2;
+                    t_kr += a3;
+                }
+                const double* hbuf = hpin;
                 for (int i = 0; i <= j; ++i) H[i * m + j] = hbuf[i] + hbuf[64 + i];
                 const double hn = std::sqrt(hbuf[128]);
                 H[(j + 1) * m + j] = hn;
@@ -705,8 +757,13 @@ int Problem::level_op(int l, int op, const double* in1, double* out) {
 }
 
 Problem::~Problem() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& g : iter_graph)
+        if (g) (void)hipGraphExecDestroy(g);
     for (int i = 0; i < 8; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (hpin) (void)hipHostFree(hpin);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
 }  // namespace iim
@@ -752,7 +809,9 @@ int iim_default_options(iim_options* o) {
     o->precision = IIM_PREC_FP64;
     o->ls_axis_t = 0.0;
     o->ls_axis_n = 0.0;
-    o->use_graph = 0;
+    o->use_graph = 1;
+    o->tail_nodes = 0;
+    o->fused_smoothing = 1;
     return IIM_OK;
 }
 
@@ -795,6 +854,12 @@ int iim_create(const iim_grid* g, const iim_geometry* geo, const iim_options* op
         }
         auto p = std::make_unique<Problem>();
         p->stream = (hipStream_t)stream;
+        if (!p->stream) {
+            // a blocking stream of our own: ordered with the legacy default stream,
+            // and capturable (the default stream is not)
+            IIM_HIP(hipStreamCreate(&p->stream));
+            p->own_stream = true;
+        }
         p->grid = *g;
         p->opt = o;
         p->dim = g->dim;
@@ -802,6 +867,7 @@ int iim_create(const iim_grid* g, const iim_geometry* geo, const iim_options* op
         p->side = geo->side;
         p->bc = geo->bc;
         p->params.assign(geo->params, geo->params + geo->nparams);
+        p->opt_fused = o.fused_smoothing != 0;
         p->setup();
         auto* h = new iim_problem;
         h->p = std::move(p);

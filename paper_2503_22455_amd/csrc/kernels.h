@@ -109,6 +109,27 @@ void run_coarse_solve(const LevelDev& L, const int32_t* list, int64_t nc, const 
 template <typename S>
 void run_zero(S* p, int64_t n, hipStream_t s);
 
+// the levels first..last of a V-cycle (last = coarsest) in one workgroup
+constexpr int MAX_LEVELS = 16;
+struct TailDev {
+    int first, last, mode, nu_pre, nu_post;
+    int64_t nc;
+    const int32_t* clist;
+    const void* Ainv;
+    LevelDev lev[MAX_LEVELS];
+    void* z[MAX_LEVELS];
+    void* b[MAX_LEVELS];
+};
+template <typename T, typename S>
+void run_tail(int dim, const TailDev* d_tail, hipStream_t s);
+// fused legs (2D): zero + nu sweeps + residual + half-weighting; prolongation + nu sweeps.
+// Return false when the fused form does not apply (the caller launches the unfused kernels).
+template <typename T, typename S>
+bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* bc, int nu, hipStream_t s);
+template <typename T, typename S>
+bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, S* z, int nu,
+                  hipStream_t s);
+
 // casts at the precision boundary: rhs0 = scale * h2 * v / beta(node); v FP64, level-0 box
 template <typename T>
 void run_cast_in(const LevelDev& L, const double* v, const double* scale_dev, double h2, double beta_plus,

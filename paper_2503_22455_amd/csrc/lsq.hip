@@ -60,6 +60,146 @@ __device__ inline double ipow(double x, int e) {
     return r;
 }
 
+// Householder QR of the (M x PT) least-squares matrix held in registers: lane l
+// owns rows l, l + 64, ... (RPL rows).  Column indices are compile-time after
+// unrolling, so A never leaves the register file.  Returns false if the rank
+// test fails.  With want_weights, writes the stencils s = Q R^{-T} e for the
+// functionals in E (nrows <= 4) to S_out / Sc_out exactly like the scratch path.
+template <int PT, int RPL>
+__device__ bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int closest, const Box& b, const Geom& g,
+                       const double* xc, double sc, const int (*ex)[3], bool want_weights, int nrows,
+                       const double (*E)[84], double (*Y)[4], double* tauv, double (*Rs)[PT], int64_t base,
+                       int64_t nnz, int64_t cs, int32_t* idx_out, double* S_out, double* Sc_out) {
+    double A[RPL][PT];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        double xi[3] = {0.0, 0.0, 0.0};
+        const bool live = r < M;
+        if (live && r > 0) {
+            int li = list_idx[r - 1 + (r - 1 >= closest ? 1 : 0)];
+            int ijk[3];
+            b.coords(li, ijk);
+            for (int d = 0; d < dim; ++d) xi[d] = (node_coord(g, ijk[d]) - xc[d]) / sc;
+        }
+#pragma unroll
+        for (int c = 0; c < PT; ++c)
+            A[q][c] = live ? ipow(xi[0], ex[c][0]) * ipow(xi[1], ex[c][1]) * ipow(xi[2], ex[c][2]) : 0.0;
+    }
+    double rmax = 0.0, rmin = 1e300;
+#pragma unroll
+    for (int c = 0; c < PT; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+            if (lane + 64 * q > c) s += A[q][c] * A[q][c];
+        s = wave_sum(s);
+        const double alpha = __shfl(A[0][c], c, 64);
+        const double norm = sqrt(alpha * alpha + s);
+        double tau = 0.0, beta = alpha;
+        if (s != 0.0) {
+            beta = alpha >= 0.0 ? -norm : norm;
+            tau = (beta - alpha) / beta;
+            const double inv = 1.0 / (alpha - beta);
+#pragma unroll
+            for (int q = 0; q < RPL; ++q)
+                if (lane + 64 * q > c) A[q][c] *= inv;
+        }
+        if (lane == 0) tauv[c] = tau;
+        rmax = fmax(rmax, fabs(beta));
+        rmin = fmin(rmin, fabs(beta));
+        // dots with every trailing column, reduced together in chunks of 8
+#pragma unroll
+        for (int c0 = c + 1; c0 < PT; c0 += 8) {
+            double d[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                d[t] = 0.0;
+                if (c0 + t < PT) {
+#pragma unroll
+                    for (int q = 0; q < RPL; ++q)
+                        if (lane + 64 * q > c) d[t] += A[q][c] * A[q][c0 + t];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (c0 + t < PT) d[t] = wave_sum(d[t]) + __shfl(A[0][c0 + t], c, 64);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (c0 + t < PT) {
+                    const double f = tau * d[t];
+#pragma unroll
+                    for (int q = 0; q < RPL; ++q)
+                        if (lane + 64 * q > c) A[q][c0 + t] -= f * A[q][c];
+                    if (lane == c) A[0][c0 + t] -= f;
+                }
+        }
+        if (lane == c) A[0][c] = beta;
+    }
+    if (rmin < RANK_TOL * rmax) return false;
+    if (!want_weights) return true;
+    // R (upper triangle, row i held by lane i) to LDS
+#pragma unroll
+    for (int c = 0; c < PT; ++c)
+        if (lane < PT && lane <= c) Rs[lane][c] = A[0][c];
+    __syncthreads();
+    // R^T Y = E^T, one lane per functional
+    if (lane < nrows) {
+        for (int i = 0; i < PT; ++i) {
+            double acc = E[lane][i];
+            for (int l2 = 0; l2 < i; ++l2) acc -= Rs[l2][i] * Y[l2][lane];
+            Y[i][lane] = acc / Rs[i][i];
+        }
+    }
+    __syncthreads();
+    double sv[4][RPL];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int r = lane + 64 * q;
+            sv[k][q] = (k < nrows && r < PT) ? Y[r][k] : 0.0;
+        }
+    // s = Q [Y; 0]: reflectors in reverse order
+#pragma unroll
+    for (int c = PT - 1; c >= 0; --c) {
+        const double tau = tauv[c];
+        double d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            d[k] = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q)
+                if (lane + 64 * q > c) d[k] += A[q][c] * sv[k][q];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nrows) d[k] = wave_sum(d[k]) + __shfl(sv[k][0], c, 64);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nrows) {
+                const double f = tau * d[k];
+#pragma unroll
+                for (int q = 0; q < RPL; ++q)
+                    if (lane + 64 * q > c) sv[k][q] -= f * A[q][c];
+                if (lane == c) sv[k][0] -= f;
+            }
+    }
+    if (lane == 0)
+        for (int k = 0; k < nrows; ++k) Sc_out[cs * nrows + k] = sv[k][0];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        if (r >= 1 && r < M) {
+            int li = list_idx[r - 1 + (r - 1 >= closest ? 1 : 0)];
+            idx_out[base + r - 1] = li;
+            for (int k = 0; k < nrows; ++k) S_out[(int64_t)k * nnz + base + r - 1] = sv[k][q];
+        }
+    }
+    return true;
+}
+
+template <int PT, int RPL>
 __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels, CPDev cp, LSParams P, int pass,
                                            int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx_out,
                                            double* S_out, double* Sc_out, double* scratch, int* err) {
@@ -69,6 +209,7 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
     __shared__ double tauv[84];
     __shared__ double Y[84][4];
     __shared__ double E[4][84];
+    __shared__ double Rs[PT][PT];
     const int lane = threadIdx.x;
     const int K = P.order_k;
     const int p = g.dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
@@ -164,12 +305,57 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
             const int m = count - 1;
             const int M = m + 1;  // rows: x_c then the m points
             if (M < p) continue;  // too few points: grow
+            const double sc = a * g.h;
+            if (M <= 64 * RPL && p == PT) {
+                // register-resident QR (the common case)
+                if (pass == 1) {
+                    if (ptr[cs + 1] - ptr[cs] != m) {
+                        if (lane == 0) atomicOr(err, 256);
+                        break;
+                    }
+                    // evaluation functionals
+                    int acoord[3];
+                    b.coords(anode, acoord);
+                    double xa[3] = {0.0, 0.0, 0.0};
+                    for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, acoord[d]);
+                    for (int k = 0; k < P.nrows; ++k)
+                        for (int col = lane; col < p; col += 64) {
+                            double val;
+                            if (k < P.w) {
+                                double xg[3] = {xa[0], xa[1], xa[2]};
+                                xg[axis] = xa[axis] + (double)((k + 1) * adir) * g.h;
+                                double xi[3] = {0.0, 0.0, 0.0};
+                                for (int d = 0; d < g.dim; ++d) xi[d] = (xg[d] - xc[d]) / sc;
+                                val = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) * ipow(xi[2], ex[col][2]);
+                            } else {
+                                int deg = ex[col][0] + ex[col][1] + ex[col][2];
+                                val = 0.0;
+                                if (deg == 1) {
+                                    int d = ex[col][0] ? 0 : (ex[col][1] ? 1 : 2);
+                                    val = nrm[d] / sc;
+                                }
+                            }
+                            E[k][col] = val;
+                        }
+                    __syncthreads();
+                }
+                bool ok = reg_qr<PT, RPL>(M, lane, g.dim, list_idx, closest, b, g, xc, sc, ex, pass == 1, P.nrows,
+                                          E, Y, tauv, Rs, pass == 1 ? ptr[cs] : 0, pass == 1 ? ptr[ncs] : 0, cs,
+                                          idx_out, S_out, Sc_out);
+                __syncthreads();
+                if (!ok) continue;  // rank deficient: grow
+                done = true;
+                if (pass == 0 && lane == 0) {
+                    m_out[cs] = m;
+                    grow_out[cs] = grow;
+                }
+                break;
+            }
             if (M > mcap) {
                 if (lane == 0) atomicOr(err, 32);
                 break;
             }
             // assemble A (column-major), row 0 = x_c
-            const double sc = a * g.h;
             for (int r = lane; r < M; r += 64) {
                 double xi[3] = {0.0, 0.0, 0.0};
                 if (r > 0) {
@@ -314,8 +500,12 @@ void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
     int64_t ncs = cp.ncp * P.nsides;
     if (ncs == 0) return;
     int blocks = (int)std::min<int64_t>(ncs, scratch_waves);
-    hipLaunchKernelGGL(k_ls, dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr, idx, S,
-                       Sc, scratch, d_err);
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_ls<15, 2>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
+                           idx, S, Sc, scratch, d_err);
+    else
+        hipLaunchKernelGGL((k_ls<35, 4>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
+                           idx, S, Sc, scratch, d_err);
     IIM_LAUNCH_CHECK();
 }
 

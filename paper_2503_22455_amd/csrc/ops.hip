@@ -199,12 +199,9 @@ __device__ inline void sw_row(const LevelDev& L, int64_t l, uint8_t lab, const S
     *off = acc;
 }
 
+// ---- per-node bodies shared by the grid kernels and the single-workgroup tail
 template <typename T, typename S, int DIM>
-__global__ void __launch_bounds__(256) k_rbgs(LevelDev L, int colour, S* z, const T* b) {
-    int i = L.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
-    int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
-    int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
-    if (i > L.core_hi[0] || j > L.core_hi[1]) return;
+__device__ inline void rbgs_node(const LevelDev& L, int i, int j, int k, int colour, S* z, const T* b) {
     if (((i + j + k) & 1) != colour) return;
     int64_t l = L.box.idx(i, j, k);
     uint8_t lab = L.labels[l];
@@ -212,23 +209,6 @@ __global__ void __launch_bounds__(256) k_rbgs(LevelDev L, int colour, S* z, cons
     T diag, off;
     sw_row<T, S, DIM>(L, l, lab, z, &diag, &off);
     if (diag != (T)0) store_t<T, S>(z, l, (b[l] - off) / diag);
-}
-
-template <typename T, typename S, int DIM>
-__global__ void __launch_bounds__(256) k_sw_apply(LevelDev L, const S* z, T* y) {
-    int i = L.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
-    int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
-    int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
-    if (i > L.core_hi[0] || j > L.core_hi[1]) return;
-    int64_t l = L.box.idx(i, j, k);
-    uint8_t lab = L.labels[l];
-    if (!is_unknown(lab)) {
-        y[l] = (T)0;
-        return;
-    }
-    T diag, off;
-    sw_row<T, S, DIM>(L, l, lab, z, &diag, &off);
-    y[l] = diag * load_it<T, S>(z, l) + off;
 }
 
 // residual of the fine level at an in-box node (zero off the unknowns)
@@ -243,11 +223,8 @@ __device__ inline T fine_resid(const LevelDev& F, int64_t l, const S* z, const T
 
 // coarse rhs (scaled by h_c^2 = 4 h_f^2): 4 * half-weighting of the fine residual
 template <typename T, typename S, int DIM>
-__global__ void __launch_bounds__(256) k_resid_restrict(LevelDev F, LevelDev C, const S* z, const T* b, T* bc) {
-    int I = C.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
-    int J = C.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
-    int K = DIM == 3 ? C.core_lo[2] + blockIdx.z : 0;
-    if (I > C.core_hi[0] || J > C.core_hi[1]) return;
+__device__ inline void restrict_node(const LevelDev& F, const LevelDev& C, int I, int J, int K, const S* z,
+                                     const T* b, T* bc) {
     int64_t lc = C.box.idx(I, J, K);
     if (!is_unknown(C.labels[lc])) {
         bc[lc] = (T)0;
@@ -269,13 +246,10 @@ __global__ void __launch_bounds__(256) k_resid_restrict(LevelDev F, LevelDev C, 
     bc[lc] = (T)4 * acc;
 }
 
-// z_f += P z_c at fine unknowns; mode 0 = (bi/tri)linear, 1 = average of in-domain parents
+// z_f += P z_c at a fine unknown; mode 0 = (bi/tri)linear, 1 = average of in-domain parents
 template <typename T, typename S, int DIM>
-__global__ void __launch_bounds__(256) k_prolong(LevelDev F, LevelDev C, int mode, const S* zc, S* z) {
-    int i = F.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
-    int j = F.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
-    int k = DIM == 3 ? F.core_lo[2] + blockIdx.z : 0;
-    if (i > F.core_hi[0] || j > F.core_hi[1]) return;
+__device__ inline void prolong_node(const LevelDev& F, const LevelDev& C, int i, int j, int k, int mode, const S* zc,
+                                    S* z) {
     int64_t l = F.box.idx(i, j, k);
     if (!is_unknown(F.labels[l])) return;
     int f[3] = {i, j, k};
@@ -316,12 +290,393 @@ __global__ void __launch_bounds__(256) k_prolong(LevelDev F, LevelDev C, int mod
 }
 
 template <typename T, typename S>
-__global__ void k_coarse_solve(const int32_t* list, int64_t nc, const T* Ainv, const T* b, S* z) {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= nc) return;
+__device__ inline void coarse_row(const int32_t* list, int64_t nc, const T* Ainv, const T* b, S* z, int64_t r) {
     T acc = 0;
     for (int64_t c = 0; c < nc; ++c) acc += Ainv[r * nc + c] * b[list[c]];
     store_t<T, S>(z, list[r], acc);
+}
+
+// ---- grid kernels
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_rbgs(LevelDev L, int colour, S* z, const T* b) {
+    int i = L.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
+    if (i > L.core_hi[0] || j > L.core_hi[1]) return;
+    rbgs_node<T, S, DIM>(L, i, j, k, colour, z, b);
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_sw_apply(LevelDev L, const S* z, T* y) {
+    int i = L.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
+    if (i > L.core_hi[0] || j > L.core_hi[1]) return;
+    int64_t l = L.box.idx(i, j, k);
+    uint8_t lab = L.labels[l];
+    if (!is_unknown(lab)) {
+        y[l] = (T)0;
+        return;
+    }
+    T diag, off;
+    sw_row<T, S, DIM>(L, l, lab, z, &diag, &off);
+    y[l] = diag * load_it<T, S>(z, l) + off;
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_resid_restrict(LevelDev F, LevelDev C, const S* z, const T* b, T* bc) {
+    int I = C.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int J = C.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int K = DIM == 3 ? C.core_lo[2] + blockIdx.z : 0;
+    if (I > C.core_hi[0] || J > C.core_hi[1]) return;
+    restrict_node<T, S, DIM>(F, C, I, J, K, z, b, bc);
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(256) k_prolong(LevelDev F, LevelDev C, int mode, const S* zc, S* z) {
+    int i = F.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = F.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? F.core_lo[2] + blockIdx.z : 0;
+    if (i > F.core_hi[0] || j > F.core_hi[1]) return;
+    prolong_node<T, S, DIM>(F, C, i, j, k, mode, zc, z);
+}
+
+template <typename T, typename S>
+__global__ void k_coarse_solve(const int32_t* list, int64_t nc, const T* Ainv, const T* b, S* z) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nc) return;
+    coarse_row<T, S>(list, nc, Ainv, b, z, r);
+}
+
+// ---- the small levels of a V-cycle in one workgroup: levels first..last of the
+// device table, coarse solve included; barriers separate the phases.
+template <int DIM, typename F>
+__device__ inline void for_core(const LevelDev& L, F fn) {
+    const int nx = L.core_hi[0] - L.core_lo[0] + 1, ny = L.core_hi[1] - L.core_lo[1] + 1;
+    const int nz = DIM == 3 ? L.core_hi[2] - L.core_lo[2] + 1 : 1;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return;
+    const int64_t tot = (int64_t)nx * ny * nz;
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+        int i = L.core_lo[0] + (int)(t % nx);
+        int j = L.core_lo[1] + (int)((t / nx) % ny);
+        int k = DIM == 3 ? L.core_lo[2] + (int)(t / ((int64_t)nx * ny)) : 0;
+        fn(i, j, k);
+    }
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(1024) k_tail(const TailDev* __restrict__ Dp) {
+    const TailDev& D = *Dp;
+    for (int l = D.first; l < D.last; ++l) {
+        const LevelDev& L = D.lev[l];
+        S* z = (S*)D.z[l];
+        const T* b = (const T*)D.b[l];
+        for (int64_t t = threadIdx.x; t < L.box.size(); t += blockDim.x) z[t] = S(0.0f);
+        __syncthreads();
+        for (int s = 0; s < D.nu_pre; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for_core<DIM>(L, [&](int i, int j, int k) { rbgs_node<T, S, DIM>(L, i, j, k, c, z, b); });
+                __syncthreads();
+            }
+        const LevelDev& C = D.lev[l + 1];
+        T* bc = (T*)D.b[l + 1];
+        for_core<DIM>(C, [&](int i, int j, int k) { restrict_node<T, S, DIM>(L, C, i, j, k, z, b, bc); });
+        __syncthreads();
+    }
+    {
+        const LevelDev& L = D.lev[D.last];
+        S* z = (S*)D.z[D.last];
+        for (int64_t t = threadIdx.x; t < L.box.size(); t += blockDim.x) z[t] = S(0.0f);
+        __syncthreads();
+        for (int64_t r = threadIdx.x; r < D.nc; r += blockDim.x)
+            coarse_row<T, S>(D.clist, D.nc, (const T*)D.Ainv, (const T*)D.b[D.last], z, r);
+        __syncthreads();
+    }
+    for (int l = D.last - 1; l >= D.first; --l) {
+        const LevelDev& L = D.lev[l];
+        const LevelDev& C = D.lev[l + 1];
+        S* z = (S*)D.z[l];
+        const S* zc = (const S*)D.z[l + 1];
+        const T* b = (const T*)D.b[l];
+        for_core<DIM>(L, [&](int i, int j, int k) { prolong_node<T, S, DIM>(L, C, i, j, k, D.mode, zc, z); });
+        __syncthreads();
+        for (int s = 0; s < D.nu_post; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for_core<DIM>(L, [&](int i, int j, int k) { rbgs_node<T, S, DIM>(L, i, j, k, c, z, b); });
+                __syncthreads();
+            }
+    }
+}
+
+// ---- fused 2D smoothing legs with LDS tiles -------------------------------------
+// Each workgroup owns a TX x TY tile of the level's core and loads it with a halo
+// of HALO nodes.  A red-black half-sweep invalidates one more ring of the loaded
+// region, so after nh <= HALO - 2 half-sweeps the tile interior and one ring
+// around it are exact: the interior is identical to global red-black
+// Gauss-Seidel, and the residual is exact on the footprint of every coarse node
+// whose centre 2I lies in the tile.  Iterates are rounded to the storage type
+// after every update, as the unfused kernels do.
+// The load phase issues every global load of a thread before using any of them
+// (labels, b, z and record indices are read unconditionally inside the box), and
+// caches the Shortley-Weller rows of the tile's irregular nodes in LDS.
+constexpr int FTX = 32, FTY = 32, FHALO = 6;
+constexpr int FLX = FTX + 2 * FHALO, FLY = FTY + 2 * FHALO;
+constexpr int FN = FLX * FLY;
+constexpr int FTHREADS = 1024;
+constexpr int FNPT = (FN + FTHREADS - 1) / FTHREADS;
+constexpr int FREC = 320;  // irregular rows cached per tile
+constexpr int FCX = FLX / 2 + 2, FCY = FLY / 2 + 2;  // coarse parents of the loaded region
+
+template <typename T, typename S>
+__device__ inline T round_s(T v) { return (T)to_f(from_f((float)v, (S*)nullptr)); }
+template <> __device__ inline double round_s<double, double>(double v) { return v; }
+
+template <typename T>
+struct FusedLDS {
+    T zs[FLY][FLX];
+    T bs[FLY][FLX];
+    uint8_t ls[FLY][FLX];
+    int16_t slot[FLY][FLX];  // >= 0: cached row; -1 regular; -2 irregular, row read from global
+    T rec[FREC][5];
+    int nrec;
+};
+
+template <typename T>
+__device__ inline void lds_row(const LevelDev& L, const FusedLDS<T>& S, int i, int j, int lx, int ly, T* acc,
+                               T* diag) {
+    const uint8_t lab = S.ls[ly][lx];
+    if (!(lab & F_SW_IRR)) {
+        T a = (T)0;
+        a += S.zs[ly][lx + 1] + S.zs[ly][lx - 1];
+        a += S.zs[ly + 1][lx] + S.zs[ly - 1][lx];
+        *acc = a;
+        *diag = (T)(-4);
+        return;
+    }
+    const int sl = S.slot[ly][lx];
+    const T* rec = sl >= 0 ? S.rec[sl] : rec_ptr<T>(L) + (int64_t)L.irr_index[L.box.idx(i, j, 0)] * 5;
+    T a = (T)0;
+    a += rec[1] * S.zs[ly][lx - 1] + rec[2] * S.zs[ly][lx + 1];
+    a += rec[3] * S.zs[ly - 1][lx] + rec[4] * S.zs[ly + 1][lx];
+    *acc = a;
+    *diag = rec[0];
+}
+
+// one half-sweep over the loaded region (outer ring skipped: its neighbours are not loaded)
+template <typename T, typename S>
+__device__ inline void lds_half_sweep(const LevelDev& L, int x0, int y0, int colour, FusedLDS<T>& Sh) {
+    for (int t = threadIdx.x; t < (FLX - 2) * (FLY - 2); t += FTHREADS) {
+        const int lx = 1 + t % (FLX - 2), ly = 1 + t / (FLX - 2);
+        const int i = x0 - FHALO + lx, j = y0 - FHALO + ly;
+        if (((i + j) & 1) != colour) continue;
+        if (!is_unknown(Sh.ls[ly][lx])) continue;
+        T acc, diag;
+        lds_row<T>(L, Sh, i, j, lx, ly, &acc, &diag);
+        if (diag != (T)0) Sh.zs[ly][lx] = round_s<T, S>((Sh.bs[ly][lx] - acc) / diag);
+    }
+}
+
+template <typename T>
+__device__ inline T lds_resid(const LevelDev& L, const FusedLDS<T>& Sh, int i, int j, int lx, int ly) {
+    if (!is_unknown(Sh.ls[ly][lx])) return (T)0;
+    T acc, diag;
+    lds_row<T>(L, Sh, i, j, lx, ly, &acc, &diag);
+    return Sh.bs[ly][lx] - (diag * Sh.zs[ly][lx] + acc);
+}
+
+// load labels, b, z (optional) and the irregular rows of the tile into LDS
+template <typename T, typename S>
+__device__ inline void lds_load(const LevelDev& F, int x0, int y0, const S* z, const T* b, FusedLDS<T>& Sh) {
+    uint8_t labv[FNPT];
+    T bv[FNPT], zv[FNPT];
+    int32_t irr[FNPT];
+    if (threadIdx.x == 0) Sh.nrec = 0;
+#pragma unroll
+    for (int q = 0; q < FNPT; ++q) {
+        const int t = threadIdx.x + FTHREADS * q;
+        const int lx = t % FLX, ly = t / FLX;
+        const int i = x0 - FHALO + lx, j = y0 - FHALO + ly;
+        const bool inb = t < FN && i >= F.box.lo[0] && i < F.box.lo[0] + F.box.dims[0] && j >= F.box.lo[1] &&
+                         j < F.box.lo[1] + F.box.dims[1];
+        const int64_t l = inb ? F.box.idx(i, j, 0) : 0;
+        labv[q] = inb ? F.labels[l] : (uint8_t)0;
+        bv[q] = inb ? b[l] : (T)0;
+        zv[q] = (inb && z) ? load_it<T, S>(z, l) : (T)0;
+        irr[q] = inb ? F.irr_index[l] : -1;
+    }
+    __syncthreads();  // nrec = 0 visible
+#pragma unroll
+    for (int q = 0; q < FNPT; ++q) {
+        const int t = threadIdx.x + FTHREADS * q;
+        if (t >= FN) continue;
+        const int lx = t % FLX, ly = t / FLX;
+        const bool unk = is_unknown(labv[q]);
+        Sh.ls[ly][lx] = labv[q];
+        Sh.bs[ly][lx] = unk ? bv[q] : (T)0;
+        Sh.zs[ly][lx] = unk ? zv[q] : (T)0;
+        int sl = -1;
+        if (unk && (labv[q] & F_SW_IRR)) {
+            sl = atomicAdd(&Sh.nrec, 1);
+            if (sl < FREC) {
+                const T* rec = rec_ptr<T>(F) + (int64_t)irr[q] * 5;
+#pragma unroll
+                for (int r = 0; r < 5; ++r) Sh.rec[sl][r] = rec[r];
+            } else {
+                sl = -2;
+            }
+        }
+        Sh.slot[ly][lx] = (int16_t)sl;
+    }
+}
+
+// z += P zc on the loaded region (as prolong_node), the coarse parents staged in LDS
+template <typename T, typename S>
+__device__ inline void lds_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, int x0, int y0,
+                                   FusedLDS<T>& Sh, T (*cz)[FCX], uint8_t (*cl)[FCX]) {
+    const int cx0 = (x0 - FHALO) >> 1, cy0 = (y0 - FHALO) >> 1;
+    constexpr int CN = FCX * FCY;
+    constexpr int CPT = (CN + FTHREADS - 1) / FTHREADS;
+    T cv[CPT];
+    uint8_t clv[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int t = threadIdx.x + FTHREADS * q;
+        const int P0 = cx0 + t % FCX, P1 = cy0 + t / FCX;
+        const bool cin = t < CN && P0 >= C.box.lo[0] && P0 < C.box.lo[0] + C.box.dims[0] && P1 >= C.box.lo[1] &&
+                         P1 < C.box.lo[1] + C.box.dims[1];
+        const int64_t lp = cin ? C.box.idx(P0, P1, 0) : 0;
+        cv[q] = cin ? load_it<T, S>(zc, lp) : (T)0;
+        clv[q] = cin ? C.labels[lp] : (uint8_t)255;  // 255: outside the coarse box
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int t = threadIdx.x + FTHREADS * q;
+        if (t < CN) {
+            cz[t / FCX][t % FCX] = cv[q];
+            cl[t / FCX][t % FCX] = clv[q];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < FN; t += FTHREADS) {
+        const int lx = t % FLX, ly = t / FLX;
+        if (!is_unknown(Sh.ls[ly][lx])) continue;
+        const int i = x0 - FHALO + lx, j = y0 - FHALO + ly;
+        const int lo0 = i >> 1, lo1 = j >> 1;
+        const int nb0 = (i & 1) ? 2 : 1, nb1 = (j & 1) ? 2 : 1;
+        T sum = 0;
+        int cnt = 0;
+        for (int a = 0; a < nb0; ++a)
+            for (int bq = 0; bq < nb1; ++bq) {
+                const int P0 = lo0 + a - cx0, P1 = lo1 + bq - cy0;
+                const uint8_t kk = cl[P1][P0];
+                const bool cin = kk != 255;
+                T v = cin ? cz[P1][P0] : (T)0;
+                bool use = mode == 0;
+                if (mode == 1) {
+                    const uint8_t k2 = kk & KIND_MASK;
+                    use = cin && (k2 == K_PLUS || k2 == K_MINUS || k2 == K_BOX);
+                }
+                if (use) {
+                    sum += v;
+                    cnt += 1;
+                }
+            }
+        if (cnt > 0) Sh.zs[ly][lx] = round_s<T, S>(Sh.zs[ly][lx] + sum / (T)cnt);
+    }
+}
+
+template <typename T, typename S>
+__device__ inline void lds_store(const LevelDev& F, int x0, int y0, const FusedLDS<T>& Sh, S* z) {
+    for (int t = threadIdx.x; t < FTX * FTY; t += FTHREADS) {
+        const int lx = FHALO + t % FTX, ly = FHALO + t / FTX;
+        const int i = x0 - FHALO + lx, j = y0 - FHALO + ly;
+        if (i > F.core_hi[0] || j > F.core_hi[1]) continue;
+        if (is_unknown(Sh.ls[ly][lx])) store_t<T, S>(z, F.box.idx(i, j, 0), Sh.zs[ly][lx]);
+    }
+}
+
+// down leg: z = 0, nh half-sweeps (red first), write z, then bc = 4 HW(residual)
+template <typename T, typename S>
+__global__ void __launch_bounds__(FTHREADS) k_down_2d(LevelDev F, LevelDev C, const T* __restrict__ b,
+                                                      S* __restrict__ z, T* __restrict__ bc, int nh) {
+    __shared__ FusedLDS<T> Sh;
+    const int x0 = F.core_lo[0] + blockIdx.x * FTX, y0 = F.core_lo[1] + blockIdx.y * FTY;
+    lds_load<T, S>(F, x0, y0, nullptr, b, Sh);
+    __syncthreads();
+    for (int h2 = 0; h2 < nh; ++h2) {
+        lds_half_sweep<T, S>(F, x0, y0, h2 & 1, Sh);
+        __syncthreads();
+    }
+    lds_store<T, S>(F, x0, y0, Sh, z);
+    // coarse nodes whose centre 2I lies in this tile
+    const int I0 = (x0 + 1) >> 1, J0 = (y0 + 1) >> 1;
+    const int I1 = (min(x0 + FTX - 1, F.core_hi[0])) >> 1, J1 = (min(y0 + FTY - 1, F.core_hi[1])) >> 1;
+    const T w0 = (T)0.5, w1 = (T)0.125;
+    for (int t = threadIdx.x; t < (I1 - I0 + 1) * (J1 - J0 + 1); t += FTHREADS) {
+        const int I = I0 + t % (I1 - I0 + 1), J = J0 + t / (I1 - I0 + 1);
+        if (I < C.core_lo[0] || I > C.core_hi[0] || J < C.core_lo[1] || J > C.core_hi[1]) continue;
+        const int64_t lc = C.box.idx(I, J, 0);
+        if (!is_unknown(C.labels[lc])) {
+            bc[lc] = (T)0;
+            continue;
+        }
+        const int fi = 2 * I, fj = 2 * J;
+        const int lx = fi - (x0 - FHALO), ly = fj - (y0 - FHALO);
+        T acc = w0 * lds_resid<T>(F, Sh, fi, fj, lx, ly);
+        acc += w1 * (lds_resid<T>(F, Sh, fi + 1, fj, lx + 1, ly) + lds_resid<T>(F, Sh, fi - 1, fj, lx - 1, ly));
+        acc += w1 * (lds_resid<T>(F, Sh, fi, fj + 1, lx, ly + 1) + lds_resid<T>(F, Sh, fi, fj - 1, lx, ly - 1));
+        bc[lc] = (T)4 * acc;
+    }
+}
+
+// up leg: z += P zc, then nh half-sweeps (red first), write z
+template <typename T, typename S>
+__global__ void __launch_bounds__(FTHREADS) k_up_2d(LevelDev F, LevelDev C, int mode, const S* __restrict__ zc,
+                                                    const T* __restrict__ b, S* __restrict__ z, int nh) {
+    __shared__ FusedLDS<T> Sh;
+    __shared__ T cz[FCY][FCX];
+    __shared__ uint8_t cl[FCY][FCX];
+    const int x0 = F.core_lo[0] + blockIdx.x * FTX, y0 = F.core_lo[1] + blockIdx.y * FTY;
+    lds_load<T, S>(F, x0, y0, z, b, Sh);
+    lds_prolong<T, S>(F, C, mode, zc, x0, y0, Sh, cz, cl);
+    __syncthreads();
+    for (int h2 = 0; h2 < nh; ++h2) {
+        lds_half_sweep<T, S>(F, x0, y0, h2 & 1, Sh);
+        __syncthreads();
+    }
+    lds_store<T, S>(F, x0, y0, Sh, z);
+}
+
+template <typename T, typename S>
+bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* bc, int nu, hipStream_t s) {
+    if (F.dim != 2 || 2 * nu > FHALO - 2) return false;
+    const int nx = F.core_hi[0] - F.core_lo[0] + 1, ny = F.core_hi[1] - F.core_lo[1] + 1;
+    if (nx <= 0 || ny <= 0) return false;
+    hipLaunchKernelGGL((k_down_2d<T, S>), dim3(cdiv(nx, FTX), cdiv(ny, FTY)), dim3(FTHREADS), 0, s, F, C, b, z, bc,
+                       2 * nu);
+    IIM_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename T, typename S>
+bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, S* z, int nu,
+                  hipStream_t s) {
+    if (F.dim != 2 || 2 * nu > FHALO - 2) return false;
+    const int nx = F.core_hi[0] - F.core_lo[0] + 1, ny = F.core_hi[1] - F.core_lo[1] + 1;
+    if (nx <= 0 || ny <= 0) return false;
+    hipLaunchKernelGGL((k_up_2d<T, S>), dim3(cdiv(nx, FTX), cdiv(ny, FTY)), dim3(FTHREADS), 0, s, F, C, mode, zc, b,
+                       z, 2 * nu);
+    IIM_LAUNCH_CHECK();
+    return true;
+}
+
+template <typename T, typename S>
+void run_tail(int dim, const TailDev* d_tail, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL((k_tail<T, S, 2>), dim3(1), dim3(1024), 0, s, d_tail);
+    else
+        hipLaunchKernelGGL((k_tail<T, S, 3>), dim3(1), dim3(1024), 0, s, d_tail);
+    IIM_LAUNCH_CHECK();
 }
 
 template <typename S>
@@ -501,7 +856,11 @@ void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const ui
     template void run_prolong<T, S>(const LevelDev&, const LevelDev&, int, const S*, S*, hipStream_t);    \
     template void run_sw_apply<T, S>(const LevelDev&, const S*, T*, hipStream_t);                         \
     template void run_coarse_solve<T, S>(const LevelDev&, const int32_t*, int64_t, const T*, const T*, S*, \
-                                         hipStream_t);
+                                         hipStream_t);                                                    \
+    template void run_tail<T, S>(int, const TailDev*, hipStream_t);                                       \
+    template bool run_down_fused<T, S>(const LevelDev&, const LevelDev&, const T*, S*, T*, int, hipStream_t); \
+    template bool run_up_fused<T, S>(const LevelDev&, const LevelDev&, int, const S*, const T*, S*, int,    \
+                                     hipStream_t);
 INST_TS(double, double)
 INST_TS(float, float)
 INST_TS(float, __half)

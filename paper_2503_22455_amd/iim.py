@@ -46,7 +46,8 @@ class Options(ctypes.Structure):
                 ("beta_minus", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("coarsest_n", ctypes.c_int32), ("precision", ctypes.c_int32), ("ls_axis_t", ctypes.c_double),
-                ("ls_axis_n", ctypes.c_double), ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("ls_axis_n", ctypes.c_double), ("use_graph", ctypes.c_int32), ("tail_nodes", ctypes.c_int32),
+                ("fused_smoothing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -132,7 +133,8 @@ class Problem:
                  beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 1e-10, max_iters: int = 500,
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None,
-                 lo: float = -1.0, hi: float = 1.0, stream=None):
+                 lo: float = -1.0, hi: float = 1.0, use_graph: bool = True, tail_nodes: int = 0,
+                 fused_smoothing: bool = True, stream=None):
         L = lib()
         self.dim, self.n = dim, n
         self.side, self.bc = side, bc
@@ -145,10 +147,14 @@ class Problem:
         o.beta_plus, o.beta_minus, o.rtol, o.max_iters = beta_plus, beta_minus, rtol, max_iters
         o.restart, o.nu_pre, o.nu_post, o.coarsest_n = restart, nu_pre, nu_post, coarsest_n
         o.precision = PREC[precision]
+        o.use_graph = int(use_graph)
+        o.tail_nodes = int(tail_nodes)
+        o.fused_smoothing = int(fused_smoothing)
         if ls_axes is not None:
             o.ls_axis_t, o.ls_axis_n = ls_axes
         self._h = ctypes.c_void_p()
-        s = _stream() if stream is None else stream
+        # default: the library orders its own stream after the legacy default stream
+        s = 0 if stream is None else stream
         _check(L.iim_create(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(o), ctypes.c_void_p(s),
                             ctypes.byref(self._h)))
 

@@ -120,3 +120,46 @@ def test_error_paths():
     G = gpu_for(W.cfg1_circle(64))
     assert G.info()["n_unknowns"] == 793
     G.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed16"])
+def test_graph_replays_match_eager(prec):
+    """Every FGMRES iteration replays a captured HIP graph (with eager work and
+    host synchronisations between replays); each replay's Hessenberg column
+    must equal the eager run's, so the residual histories and the solutions
+    agree bit for bit."""
+    wl = W.cfg2_star(256)
+    O = oracle_for(wl)
+    cpd, box, f = oracle_data(O, wl)
+    outs = []
+    for g in (False, True, True):
+        G = gpu_for(wl, precision=prec, use_graph=g, rtol=1e-12)
+        G.set_boundary_data(cpd, box)
+        G.set_rhs(f)
+        u, hist, st = G.solve()
+        assert st["iterations"] > 11  # more than one restart cycle: graphs replayed
+        outs.append((u.cpu().numpy(), hist))
+        G.close()
+    for u, hist in outs[1:]:
+        assert np.array_equal(u, outs[0][0], equal_nan=True)
+        assert np.array_equal(hist, outs[0][1])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed32", 1e-6), ("mixed16", 1e-3)])
+@pytest.mark.parametrize("tail", [-1, 0, 100000])
+def test_fused_and_tail_kernels_match_unfused(prec, tol, tail):
+    """The LDS-tiled fused smoothing legs and the one-workgroup tail compute the
+    same V-cycle as one kernel per half-sweep and transfer."""
+    wl = W.cfg2_star(256)
+    rng = np.random.default_rng(9)
+    O = oracle_for(wl)
+    v = np.zeros(O.lab_flat.size)
+    v[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    vt = torch.tensor(v, device="cuda")
+    ref = gpu_for(wl, precision=prec, fused_smoothing=False, tail_nodes=-1)
+    z0 = ref.vcycle(vt).cpu().numpy()
+    G = gpu_for(wl, precision=prec, fused_smoothing=True, tail_nodes=tail)
+    z1 = G.vcycle(vt).cpu().numpy()
+    assert np.abs(z1 - z0).max() <= tol * np.abs(z0).max()
+    ref.close()
+    G.close()
