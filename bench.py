@@ -11,7 +11,8 @@ region.  Prints one JSON line.
 Default workload: 2D interface problem, 1024 x 1024, five-lobe star
 r = 0.5 + 0.1 cos(5 theta), u = e^x cos y inside / x^2 - y^2 outside, jumps from
 these, Dirichlet box, FP64 solve (the mixed-precision solve of the same problem
-is timed beside it).  Other workloads: --workload cfg1|cfg3|cfg4.
+is timed beside it).  Other workloads: --workload cfg1|cfg3|cfg4; --serve runs
+the request stream (continuous batching on the solve server) instead.
 """
 from __future__ import annotations
 
@@ -133,6 +134,79 @@ def cpu_baseline(wl, its_gpu, nu, sample_iters=3):
             "t_setup_s": t_setup, "t_iter_s": t_iter}
 
 
+def serve_stream(reqs, slots, budget_bytes, log_every=0):
+    """Replays a request stream against the solve server: each request is
+    submitted at its arrival time (server clock), and latency is the time from
+    submission to the finished result.  Requests carry device-side synthetic
+    data, so nothing else touches the device meanwhile."""
+    from paper_2503_22455_amd import iim
+    srv = iim.Server(budget_bytes, slots)
+    t0 = srv.clock()
+    tickets = []
+    for i, r in enumerate(reqs):
+        wl = r.workload
+        while True:
+            dt = t0 + r.arrival - srv.clock()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.002))
+        tickets.append(srv.submit(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, data_kind=1,
+                                  precision=wl.precision, rtol=1e-10))
+        if log_every and (i + 1) % log_every == 0:
+            st = srv.stats()
+            print(f"[serve] submitted {i + 1}/{len(reqs)}: running {st['running']}, queued {st['queued']}, "
+                  f"done {st['completed'] + st['failed']}", file=sys.stderr, flush=True)
+    res = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["t_finish"] - r["t_submit"] for r in res])
+    ok = [r for r in res if r["status"] == 0]
+    span = max(r["t_finish"] for r in res) - t0
+    dofs = sum(r["n_unknowns"] for r in ok)
+    return {
+        "requests": len(reqs), "completed": len(ok), "failed": len(res) - len(ok),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3), "solves_per_s": len(ok) / span, "DOF_per_s": dofs / span,
+        "span_s": span, "slots": slots, "budget_GiB": budget_bytes / 2 ** 30,
+        "peak_reserved_GiB": st["peak_bytes_reserved"] / 2 ** 30,
+        "max_rel_residual": float(max(r["rel_residual"] for r in ok)) if ok else None,
+        "max_error": float(max(r["max_error"] for r in ok)) if ok else None,
+        "iterations_mean": float(np.mean([r["iterations"] for r in ok])) if ok else None,
+    }
+
+
+def serving_main(args):
+    """The request-stream workload: 2000 requests (2D circles n in [128, 2048],
+    3D spheres n in [32, 192], mixed-precision solves to 1e-10) at Poisson
+    arrival rates swept over five levels."""
+    import torch
+    torch.cuda.set_device(0)
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    budget = int(args.serve_budget_gib * 2 ** 30)
+    levels = []
+    for lam in rates:
+        reqs = W.serving_requests(count=args.serve_count, rate=lam, seed=1)
+        print(f"[serve] rate {lam}/s: {len(reqs)} requests over {reqs[-1].arrival:.1f} s", file=sys.stderr,
+              flush=True)
+        r = serve_stream(reqs, args.serve_slots, budget, log_every=max(1, len(reqs) // 10))
+        r["rate_per_s"] = lam
+        print(f"[serve] rate {lam}/s: {json.dumps(r)}", file=sys.stderr, flush=True)
+        levels.append(r)
+    top = max(levels, key=lambda r: r["solves_per_s"])
+    out = {
+        "metric": "DOF/s and time-to-1e-10 residual (mixed vs FP64) + p50/p99 solve latency",
+        "value": top["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": len(rates) * args.serve_count,
+        "warmup": 0, "ms_per_step": 1e3 / top["solves_per_s"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": (f"request stream: {args.serve_count} Poisson arrivals per rate, 2D circle "
+                                f"n U[128,2048] / 3D sphere n U[32,192], r U[0.3,0.7], offset <= 0.2, mixed32 "
+                                f"solve to 1e-10"), "slots": args.serve_slots,
+                   "budget_GiB": args.serve_budget_gib},
+        "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "levels": levels,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,11 +216,21 @@ def main():
     ap.add_argument("--precision", default=None, help="override the workload's precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="run the request-stream workload instead")
+    ap.add_argument("--serve-count", type=int, default=2000)
+    ap.add_argument("--serve-rates", default="10,20,40,80,160")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-short", type=int, default=48,
+                    help="requests of the short saturated serving run in the default line (0: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X (a multi-GPU "
               "decomposition is designed but not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serving_main(args)
+        return
     import torch
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]()
@@ -209,6 +293,14 @@ def main():
         print(f"[bench] kernel {kr[k][0]}: {kr[k][1]*1e3:.2f} us, {kr[k][2]/(kr[k][1]*1e-3)/1e9:.1f} GB/s",
               file=sys.stderr, flush=True)
 
+    serving = None
+    if args.serve_short > 0:
+        # all requests arrive at once: the server's saturated throughput
+        reqs = W.serving_requests(count=args.serve_short, rate=1e9, seed=1)
+        serving = serve_stream(reqs, args.serve_slots, int(args.serve_budget_gib * 2 ** 30))
+        serving["arrivals"] = "all at t=0"
+        print(f"[bench] serving: {json.dumps(serving)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
@@ -231,6 +323,7 @@ def main():
         "final_rel_residual_max": float(max(res)),
         "time_to_1e-10": ttr,
         "roofline": roofline, "kernels": kernels,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -227,6 +227,69 @@ int iim_level_op(iim_problem* p, int32_t level, int32_t op, const double* in1, d
  * 6 = one whole V-cycle, 7 = one whole operator apply (ghosts + stencil). */
 int iim_time_kernel(iim_problem* p, int32_t kernel, int32_t reps, double* avg_ms);
 
+/* Synthetic manufactured data for benchmarks and serving, computed on the
+ * device at the library's own control points and nodes: kind 1 is
+ * u = sin(2 pi x) cos(2 pi y) in 2D and u = sin(pi x) sin(pi y) sin(pi z) in 3D,
+ * giving Dirichlet data u(x_c), box values u, and f = beta Lap(u) (Dirichlet
+ * boundary problems only).  Replaces the boundary data and the right-hand side. */
+int iim_set_synthetic_data(iim_problem* p, int32_t kind);
+
+/* max |u - u_exact| over the unknowns for a solution u (device full-grid array)
+ * of a problem whose data came from iim_set_synthetic_data(kind). */
+int iim_synthetic_error(iim_problem* p, int32_t kind, const double* u, double* max_err);
+
+/* ---- serving: continuous batching of independent solves on one device ----
+ * A server owns max_slots worker threads.  Each worker solves one request at a
+ * time on its own non-blocking HIP stream, so the device work of concurrent
+ * requests overlaps.  Requests are admitted in arrival (FIFO) order when a slot
+ * is free and their estimated device memory fits in what is left of
+ * budget_bytes; a request whose estimate alone exceeds the budget fails with
+ * IIM_E_BUDGET without blocking the queue. */
+typedef struct iim_server iim_server;
+
+typedef struct iim_request {
+    iim_grid grid;
+    iim_geometry geom;   /* params are copied at submission */
+    iim_options opt;
+    int32_t data_kind;   /* synthetic data family (see iim_set_synthetic_data) */
+    int32_t reserved;
+    double* u_out;       /* optional device full-grid array receiving u (NULL: not copied);
+                            must stay valid until the request completes */
+} iim_request;
+
+typedef struct iim_result {
+    int32_t done;        /* 1 once finished (successfully or not) */
+    int32_t status;      /* IIM_OK, IIM_NOT_CONVERGED or a negative error code */
+    int32_t iterations;
+    int32_t reserved;
+    double rel_residual; /* final true relative residual */
+    double max_error;    /* max |u - u_exact| over the unknowns */
+    double t_submit, t_start, t_finish; /* seconds on the server's steady clock */
+    int64_t n_unknowns;
+    int64_t device_bytes;   /* device memory the request held */
+    int64_t estimated_bytes;
+} iim_result;
+
+typedef struct iim_server_stats {
+    int64_t submitted, completed, failed, running, queued;
+    int64_t bytes_reserved, bytes_budget, peak_bytes_reserved;
+} iim_server_stats;
+
+/* budget_bytes: device memory the server may reserve for running requests;
+ * max_slots: requests solved concurrently (1..64). */
+int iim_server_create(int64_t budget_bytes, int32_t max_slots, iim_server** out);
+/* Enqueues a request; returns at once with its ticket. */
+int iim_server_submit(iim_server* s, const iim_request* req, uint64_t* ticket);
+/* Copies the request's result (done = 0 while queued or running). */
+int iim_server_poll(iim_server* s, uint64_t ticket, iim_result* res);
+/* Blocks until the request is done, then copies its result. */
+int iim_server_wait(iim_server* s, uint64_t ticket, iim_result* res);
+int iim_server_stats_get(iim_server* s, iim_server_stats* st);
+/* Seconds on the server's clock (the time base of iim_result). */
+double iim_server_clock(iim_server* s);
+/* Finishes every queued and running request, then frees the server. */
+void iim_server_destroy(iim_server* s);
+
 #ifdef __cplusplus
 }
 #endif

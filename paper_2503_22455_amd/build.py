@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiim.so")
-SOURCES = ["setup.hip", "lsq.hip", "ops.hip", "blas.hip", "core.hip"]
+SOURCES = ["setup.hip", "lsq.hip", "ops.hip", "blas.hip", "synth.hip", "core.hip", "server.hip"]
 ARCH = os.environ.get("IIM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -1,6 +1,7 @@
 // Problem state held by an iim_problem handle.
 #pragma once
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -11,14 +12,27 @@ namespace iim {
 void set_error(const std::string& m);
 const char* last_error();
 
-// owner of every device allocation of a handle
+// Owner of every device allocation of a handle.  Allocations are stream
+// ordered (hipMallocAsync / hipFreeAsync on the handle's stream) from the
+// device's default memory pool, so that setup and teardown of one handle never
+// synchronise the device while other handles are solving on other streams.
 struct DevMem {
-    std::vector<void*> ptrs;
-    size_t total = 0;
+    struct Block {
+        void* p;
+        size_t bytes;
+    };
+    std::vector<Block> blocks;
+    hipStream_t stream = nullptr;
+    size_t current = 0, peak = 0;
     void* alloc(size_t bytes);
     void release(void* p);
+    void release_all();  // stream-ordered frees of every live block
     ~DevMem();
 };
+
+// keeps freed pool memory cached in the process (set once per device)
+void configure_pool(int device);
+void trim_pool();
 
 struct Level {
     int n = 0;
@@ -85,6 +99,7 @@ struct Problem {
     bool opt_fused = true;  // LDS-tiled fused smoothing legs where available
     TailDev* d_tail = nullptr;
     double* hpin = nullptr;  // pinned host copy of the Hessenberg column
+    bool own_hpin = true;
     hipGraphExec_t iter_graph[16] = {};
     double t_setup_ms = 0.0;
 
@@ -103,7 +118,16 @@ struct Problem {
     template <typename T, typename S> void launch_kernel_t(int kernel);
     double time_kernel(int kernel, int reps);
     template <typename T, typename S> int level_op_t(int level, int op, const double* in1, double* out);
+    void synth_data(int kind);
+    double synth_error(int kind, const double* u_full);
     ~Problem();
 };
+
+// validated construction with setup (stream: NULL creates a blocking stream
+// owned by the problem); hpin: optional caller-owned pinned buffer of 256 doubles
+std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo, const iim_options* opt,
+                                      hipStream_t stream, double* hpin);
+// device bytes a problem will hold at its peak, from the request alone
+int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_options& opt);
 
 }  // namespace iim

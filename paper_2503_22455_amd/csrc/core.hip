@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "core.h"
@@ -20,32 +21,60 @@ const char* last_error() { return g_last_error.c_str(); }
 // ---------------------------------------------------------------------------
 // device memory helpers
 // ---------------------------------------------------------------------------
+void configure_pool(int device) {
+    static std::mutex mu;
+    static bool done[64] = {};
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0 || device >= 64 || done[device]) return;
+    int supported = 0;
+    IIM_HIP(hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, device));
+    if (!supported) throw Error(IIM_E_DEVICE, "the device has no stream-ordered memory pools");
+    hipMemPool_t pool;
+    IIM_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+    uint64_t keep = UINT64_MAX;
+    IIM_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    done[device] = true;
+}
+
+void trim_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+}
+
 void* DevMem::alloc(size_t bytes) {
     if (bytes == 0) bytes = 8;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         throw Error(e == hipErrorOutOfMemory ? IIM_E_BUDGET : IIM_E_DEVICE,
-                    std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+                    std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
     }
-    ptrs.push_back(p);
-    total += bytes;
+    blocks.push_back({p, bytes});
+    current += bytes;
+    peak = std::max(peak, current);
     return p;
 }
 
 void DevMem::release(void* p) {
-    for (auto& q : ptrs)
-        if (q == p) {
-            (void)hipFree(q);
-            q = nullptr;
+    for (auto& q : blocks)
+        if (q.p == p) {
+            (void)hipFreeAsync(q.p, stream);
+            current -= q.bytes;
+            q.p = nullptr;
         }
 }
 
-DevMem::~DevMem() {
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+void DevMem::release_all() {
+    for (auto& q : blocks)
+        if (q.p) (void)hipFreeAsync(q.p, stream);
+    blocks.clear();
+    current = 0;
 }
+
+DevMem::~DevMem() { release_all(); }
 
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -207,13 +236,32 @@ void Problem::setup() {
         P.mcap = dim == 2 ? 192 : 768;
         const int K = opt.order_k;
         const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
-        int64_t waves = std::min<int64_t>(std::max<int64_t>(ncs, 1), dim == 2 ? 4096 : 1024);
-        double* scratch = (double*)mem.alloc((size_t)waves * (p + 4) * P.mcap * sizeof(double));
         int32_t* d_m = (int32_t*)mem.alloc(std::max<int64_t>(ncs, 1) * sizeof(int32_t));
         int32_t* d_grow = (int32_t*)mem.alloc(std::max<int64_t>(ncs, 1) * sizeof(int32_t));
-        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, scratch, waves,
-               d_err, stream);
+        uint8_t* d_route = (uint8_t*)mem.alloc(std::max<int64_t>(ncs, 1));
+        IIM_HIP(hipMemsetAsync(d_route, 0, std::max<int64_t>(ncs, 1), stream));
+        // pass 0, register path: sizes and growth of every fit that fits in registers
+        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_err,
+               nullptr, 0, d_route, stream);
         check_err(d_err, "least-squares sizes");
+        std::vector<int32_t> hg(ncs);
+        if (ncs) IIM_HIP(hipMemcpyAsync(hg.data(), d_grow, ncs * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+        std::vector<int32_t> big;
+        for (int64_t i = 0; i < ncs; ++i)
+            if (hg[i] == -3) big.push_back((int32_t)i);
+        int32_t* d_list = nullptr;
+        double* scratch = nullptr;
+        int64_t waves = 0;
+        if (!big.empty()) {  // oversized sets: Householder on a per-wave global scratch slab
+            waves = std::min<int64_t>((int64_t)big.size(), 256);
+            scratch = (double*)mem.alloc((size_t)waves * (p + 4) * P.mcap * sizeof(double));
+            d_list = (int32_t*)mem.alloc(big.size() * sizeof(int32_t));
+            IIM_HIP(hipMemcpyAsync(d_list, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+            run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, scratch, waves,
+                   d_err, d_list, (int64_t)big.size(), d_route, stream);
+            check_err(d_err, "least-squares sizes (large sets)");
+        }
         std::vector<int32_t> hm(ncs);
         if (ncs) IIM_HIP(hipMemcpyAsync(hm.data(), d_m, ncs * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         IIM_HIP(hipStreamSynchronize(stream));
@@ -225,12 +273,17 @@ void Problem::setup() {
         ls_idx = (int32_t*)mem.alloc(nnz * sizeof(int32_t));
         ls_S = (double*)mem.alloc(nrows * nnz * sizeof(double));
         ls_Sc = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * nrows * sizeof(double));
-        run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, scratch, waves, d_err,
-               stream);
+        run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, nullptr, 0, d_err, nullptr,
+               0, d_route, stream);
+        if (!big.empty())
+            run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, scratch, waves, d_err,
+                   d_list, (int64_t)big.size(), d_route, stream);
         check_err(d_err, "least-squares fits");
-        mem.release(scratch);
+        if (scratch) mem.release(scratch);
+        if (d_list) mem.release(d_list);
         mem.release(d_m);
         mem.release(d_grow);
+        mem.release(d_route);
         // apply weights
         dcoef = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * w * sizeof(double));
         if (bc == IIM_BC_NEUMANN) {
@@ -370,7 +423,7 @@ void Problem::setup() {
         d_tail = (TailDev*)mem.alloc(sizeof(TailDev));
         IIM_HIP(hipMemcpyAsync(d_tail, &T, sizeof(TailDev), hipMemcpyHostToDevice, stream));
     }
-    IIM_HIP(hipHostMalloc((void**)&hpin, 256 * sizeof(double), hipHostMallocDefault));
+    if (!hpin) IIM_HIP(hipHostMalloc((void**)&hpin, 256 * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 8; ++i) IIM_HIP(hipEventCreate(&ev[i]));
     IIM_HIP(hipStreamSynchronize(stream));
     mem.release(d_err);
@@ -624,6 +677,124 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
 }
 
 // ---------------------------------------------------------------------------
+// manufactured data and its error (benchmarks and serving)
+// ---------------------------------------------------------------------------
+void Problem::synth_data(int kind) {
+    if (kind != 1) throw Error(IIM_E_INVALID_ARG, "unknown synthetic data kind");
+    const int64_t N = box.size();
+    run_synth_cp(kind, dim, bc, cp, opt.beta_plus, opt.beta_minus, cpdata, stream);
+    run_synth_nodes(kind, levels[0].geom, box, levels[0].labels, opt.beta_plus, opt.beta_minus, rhs, boxval, stream);
+    // b = f - L_Gamma u_Gamma, as for caller-supplied data
+    IIM_HIP(hipMemsetAsync(xk, 0, N * sizeof(double), stream));
+    apply_box(xk, wk, 1);
+    run_axpby(-1.0, wk, 1.0, rhs, N, stream);
+}
+
+double Problem::synth_error(int kind, const double* u_full) {
+    if (kind != 1) throw Error(IIM_E_INVALID_ARG, "unknown synthetic data kind");
+    unsigned long long* d = (unsigned long long*)(red_out + 250);
+    IIM_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), stream));
+    run_synth_err(kind, levels[0].geom, box, levels[0].labels, u_full, d, stream);
+    unsigned long long bits = 0;
+    IIM_HIP(hipMemcpyAsync(&bits, d, sizeof(bits), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipStreamSynchronize(stream));
+    if (bits == ~0ull) return std::nan("");
+    double v;
+    std::memcpy(&v, &bits, sizeof(v));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Device bytes of a problem at its peak, before any device work: the storage
+// boxes from a bounding box of the body (interior problems) or the whole grid,
+// control points from the number of grid lines that cross the bounding
+// spheres, least-squares entries from the largest set size of the default
+// half-ellipse.  Upper estimates; every term is listed in the same order as the
+// allocations of setup().
+// ---------------------------------------------------------------------------
+int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_options& o) {
+    const int dim = g.dim;
+    const double h = (g.hi - g.lo) / g.n;
+    const double PI = 3.14159265358979323846;
+    // bounding spheres of the body
+    std::vector<std::pair<std::vector<double>, double>> balls;
+    if (geo.kind == IIM_GEOM_SPHERE) {
+        balls.push_back({std::vector<double>(geo.params, geo.params + dim), geo.params[dim]});
+    } else if (geo.kind == IIM_GEOM_STAR2D) {
+        balls.push_back({{geo.params[0], geo.params[1]}, geo.params[2] + std::fabs(geo.params[3])});
+    } else {
+        int cnt = (int)std::llround(geo.params[0]);
+        for (int s = 0; s < cnt; ++s) {
+            const double* q = geo.params + 1 + (dim + 1) * s;
+            balls.push_back({std::vector<double>(q, q + dim), q[dim]});
+        }
+    }
+    // level-0 storage box
+    int64_t dims[3] = {1, 1, 1};
+    for (int d = 0; d < dim; ++d) {
+        int64_t lo = 0, hi = g.n;
+        if (geo.side == IIM_SIDE_INTERIOR && !balls.empty()) {
+            double a = 1e300, b = -1e300;
+            for (auto& bl : balls) {
+                a = std::min(a, bl.first[d] - bl.second);
+                b = std::max(b, bl.first[d] + bl.second);
+            }
+            lo = std::max<int64_t>(0, (int64_t)std::floor((a - g.lo) / h));
+            hi = std::min<int64_t>(g.n, (int64_t)std::ceil((b - g.lo) / h));
+        }
+        dims[d] = hi - lo + 1 + 4;
+    }
+    const int m = o.restart;
+    const int64_t tsz = o.precision == IIM_PREC_FP64 ? 8 : 4;
+    const int64_t ssz = o.precision == IIM_PREC_FP64 ? 8 : (o.precision == IIM_PREC_MIXED32 ? 4 : 2);
+    const int64_t N0 = dims[0] * dims[1] * dims[2];
+    // per node of level 0: labels, HO and SW irregular indices, 5 work vectors,
+    // the Krylov bases V (m+1) and Z (m), the V-cycle iterate and right-hand side
+    int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8 + ssz + tsz);
+    // setup transients alive together: flags, one selection output per axis and
+    // the selection workspace
+    bytes += N0 * (1 + 4 * dim) + (N0 / 64 + (1 << 20));
+    // coarse levels: labels, SW index, iterate, right-hand side
+    int64_t cd[3] = {dims[0], dims[1], dims[2]};
+    int n = g.n;
+    int64_t last = N0;
+    while (n > o.coarsest_n) {
+        n = (n + 1) / 2;
+        for (int d = 0; d < dim; ++d) cd[d] = (cd[d] - 4) / 2 + 1 + 2 + 2;
+        last = cd[0] * cd[1] * cd[2];
+        bytes += last * (1 + 4 + ssz + tsz);
+    }
+    // coarsest dense inverse (A, FP64 and FP32 inverses, column map)
+    const int64_t nc = std::min<int64_t>(last, 4096);
+    bytes += nc * nc * (8 + 8 + 4) + last * 4;
+    // control points: per line crossing of each bounding sphere
+    double ncp = 0.0;
+    for (auto& bl : balls) {
+        const double r = bl.second / h + 1.0;
+        ncp += dim == 2 ? 2.0 * 2.0 * (2.0 * r + 1.0) : 3.0 * 2.0 * PI * r * r;
+    }
+    if (geo.kind == IIM_GEOM_STAR2D) ncp *= 2.0;  // lobes lengthen the curve
+    ncp = 1.15 * ncp + 64.0;
+    const int ns = geo.side == IIM_SIDE_INTERFACE ? 2 : 1;
+    const int w = o.order_n / 2;
+    const int nrows = w + (geo.bc == IIM_BC_DIRICHLET ? 0 : 1);
+    const double mset = dim == 2 ? 56.0 : 264.0;
+    const double ncs = ncp * ns;
+    bytes += (int64_t)(ncp * (4 + 4 + 24 + 24 + 8 + 16) + ncs * (4 + 4 + 8 * w * 2 + 8 * nrows + 4 + 4 + 1 + 8));
+    bytes += (int64_t)(ncs * mset * (4 + 8 * nrows + (geo.bc == IIM_BC_NEUMANN ? 8 * w : 0)));
+    // scratch of oversized least-squares sets (one slab per wave, 256 waves at most)
+    const int K = o.order_k;
+    const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
+    bytes += (int64_t)std::min(256.0, ncs) * (p + 4) * (dim == 2 ? 192 : 768) * 8;
+    // irregular records: high-order slots (at most w nodes per crossing and side),
+    // Shortley-Weller rows in FP64 and FP32 (at most one node per crossing, all levels)
+    bytes += (int64_t)(ncs * (w * 2 * dim * 4 + 2 * (1 + 2 * dim) * 12));
+    // reductions and small tables
+    bytes += (int64_t)(KRED + 1) * RED_BLOCKS * 8 + 4096;
+    return bytes + (4 << 20);
+}
+
+// ---------------------------------------------------------------------------
 // level operations for tests (FP64 in and out, the handle's precision inside)
 // ---------------------------------------------------------------------------
 template <typename T, typename S>
@@ -756,13 +927,76 @@ int Problem::level_op(int l, int op, const double* in1, double* out) {
     return level_op_t<float, __half>(l, op, in1, out);
 }
 
+std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo, const iim_options* opt,
+                                      hipStream_t stream, double* hpin) {
+    if (!g || !geo) throw Error(IIM_E_INVALID_ARG, "null argument");
+    iim_options o;
+    if (opt) o = *opt; else iim_default_options(&o);
+    if (g->dim != 2 && g->dim != 3) throw Error(IIM_E_INVALID_ARG, "dim must be 2 or 3");
+    if (g->n < 8 || g->n > 16384) throw Error(IIM_E_INVALID_ARG, "n out of range");
+    if (!(g->hi > g->lo)) throw Error(IIM_E_INVALID_ARG, "empty domain");
+    if (o.order_n != 4 || o.order_k != 5) throw Error(IIM_E_INVALID_ARG, "only the (4,5) discretisation is built");
+    if (o.restart < 1 || o.restart > 11) throw Error(IIM_E_INVALID_ARG, "restart must be in [1, 11]");
+    if (o.coarsest_n < 2) throw Error(IIM_E_INVALID_ARG, "coarsest_n must be >= 2");
+    if (o.precision < 0 || o.precision > 2) throw Error(IIM_E_INVALID_ARG, "bad precision");
+    if (!(o.beta_plus > 0) || !(o.beta_minus > 0)) throw Error(IIM_E_INVALID_ARG, "beta must be positive");
+    if ((geo->side == IIM_SIDE_INTERFACE) != (geo->bc == IIM_BC_JUMP))
+        throw Error(IIM_E_INVALID_ARG, "jump conditions go with interface problems");
+    if (geo->kind < 0 || geo->kind > 2 || geo->side < 0 || geo->side > 2 || geo->bc < 0 || geo->bc > 2)
+        throw Error(IIM_E_INVALID_ARG, "bad geometry enums");
+    if (!geo->params) throw Error(IIM_E_INVALID_ARG, "null params");
+    if (geo->kind == IIM_GEOM_STAR2D && (g->dim != 2 || geo->nparams < 5))
+        throw Error(IIM_E_INVALID_ARG, "star needs dim 2 and 5 parameters");
+    if (geo->kind == IIM_GEOM_SPHERE && geo->nparams < g->dim + 1)
+        throw Error(IIM_E_INVALID_ARG, "sphere needs dim + 1 parameters");
+    if (geo->kind == IIM_GEOM_SPHERE_UNION &&
+        (geo->nparams < 1 || geo->nparams < 1 + (g->dim + 1) * (int)geo->params[0]))
+        throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
+    if (geo->side != IIM_SIDE_INTERIOR) {
+        // box faces must coincide on every level
+        int n = g->n;
+        while (n > o.coarsest_n) {
+            if (n % 2) throw Error(IIM_E_INVALID_ARG, "exterior/interface problems need n = m 2^L with m <= coarsest_n");
+            n /= 2;
+        }
+    }
+    int dev = 0;
+    IIM_HIP(hipGetDevice(&dev));
+    configure_pool(dev);
+    auto p = std::make_unique<Problem>();
+    p->stream = stream;
+    if (!p->stream) {
+        // a blocking stream of our own: ordered with the legacy default stream,
+        // and capturable (the default stream is not)
+        IIM_HIP(hipStreamCreate(&p->stream));
+        p->own_stream = true;
+    }
+    p->mem.stream = p->stream;
+    if (hpin) {
+        p->hpin = hpin;
+        p->own_hpin = false;
+    }
+    p->grid = *g;
+    p->opt = o;
+    p->dim = g->dim;
+    p->kind = geo->kind;
+    p->side = geo->side;
+    p->bc = geo->bc;
+    p->params.assign(geo->params, geo->params + geo->nparams);
+    p->opt_fused = o.fused_smoothing != 0;
+    p->setup();
+    return p;
+}
+
 Problem::~Problem() {
     if (stream) (void)hipStreamSynchronize(stream);
     for (auto& g : iter_graph)
         if (g) (void)hipGraphExecDestroy(g);
     for (int i = 0; i < 8; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
-    if (hpin) (void)hipHostFree(hpin);
+    if (hpin && own_hpin) (void)hipHostFree(hpin);
+    mem.release_all();
+    if (stream) (void)hipStreamSynchronize(stream);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -820,55 +1054,9 @@ const char* iim_last_error(void) { return iim::last_error(); }
 int iim_create(const iim_grid* g, const iim_geometry* geo, const iim_options* opt, void* stream, iim_problem** out) {
     ABI_TRY({
         iim::set_error("");
-        if (!g || !geo || !out) throw Error(IIM_E_INVALID_ARG, "null argument");
+        if (!out) throw Error(IIM_E_INVALID_ARG, "null argument");
         *out = nullptr;
-        iim_options o;
-        if (opt) o = *opt; else iim_default_options(&o);
-        if (g->dim != 2 && g->dim != 3) throw Error(IIM_E_INVALID_ARG, "dim must be 2 or 3");
-        if (g->n < 8 || g->n > 16384) throw Error(IIM_E_INVALID_ARG, "n out of range");
-        if (!(g->hi > g->lo)) throw Error(IIM_E_INVALID_ARG, "empty domain");
-        if (o.order_n != 4 || o.order_k != 5) throw Error(IIM_E_INVALID_ARG, "only the (4,5) discretisation is built");
-        if (o.restart < 1 || o.restart > 11) throw Error(IIM_E_INVALID_ARG, "restart must be in [1, 11]");
-        if (o.coarsest_n < 2) throw Error(IIM_E_INVALID_ARG, "coarsest_n must be >= 2");
-        if (o.precision < 0 || o.precision > 2) throw Error(IIM_E_INVALID_ARG, "bad precision");
-        if (!(o.beta_plus > 0) || !(o.beta_minus > 0)) throw Error(IIM_E_INVALID_ARG, "beta must be positive");
-        if ((geo->side == IIM_SIDE_INTERFACE) != (geo->bc == IIM_BC_JUMP))
-            throw Error(IIM_E_INVALID_ARG, "jump conditions go with interface problems");
-        if (geo->kind < 0 || geo->kind > 2 || geo->side < 0 || geo->side > 2 || geo->bc < 0 || geo->bc > 2)
-            throw Error(IIM_E_INVALID_ARG, "bad geometry enums");
-        if (geo->kind == IIM_GEOM_STAR2D && (g->dim != 2 || geo->nparams < 5))
-            throw Error(IIM_E_INVALID_ARG, "star needs dim 2 and 5 parameters");
-        if (geo->kind == IIM_GEOM_SPHERE && geo->nparams < g->dim + 1)
-            throw Error(IIM_E_INVALID_ARG, "sphere needs dim + 1 parameters");
-        if (geo->kind == IIM_GEOM_SPHERE_UNION &&
-            (geo->nparams < 1 || geo->nparams < 1 + (g->dim + 1) * (int)geo->params[0]))
-            throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
-        if (!geo->params) throw Error(IIM_E_INVALID_ARG, "null params");
-        if (geo->side != IIM_SIDE_INTERIOR) {
-            // box faces must coincide on every level
-            int n = g->n;
-            while (n > o.coarsest_n) {
-                if (n % 2) throw Error(IIM_E_INVALID_ARG, "exterior/interface problems need n = m 2^L with m <= coarsest_n");
-                n /= 2;
-            }
-        }
-        auto p = std::make_unique<Problem>();
-        p->stream = (hipStream_t)stream;
-        if (!p->stream) {
-            // a blocking stream of our own: ordered with the legacy default stream,
-            // and capturable (the default stream is not)
-            IIM_HIP(hipStreamCreate(&p->stream));
-            p->own_stream = true;
-        }
-        p->grid = *g;
-        p->opt = o;
-        p->dim = g->dim;
-        p->kind = geo->kind;
-        p->side = geo->side;
-        p->bc = geo->bc;
-        p->params.assign(geo->params, geo->params + geo->nparams);
-        p->opt_fused = o.fused_smoothing != 0;
-        p->setup();
+        auto p = make_problem(g, geo, opt, (hipStream_t)stream, nullptr);
         auto* h = new iim_problem;
         h->p = std::move(p);
         *out = h;
@@ -883,6 +1071,7 @@ void iim_destroy(iim_problem* p) {
     } catch (...) {
     }
     delete p;
+    iim::trim_pool();  // hand the freed blocks back to the device
 }
 
 int iim_get_info(const iim_problem* h, iim_info* info) {
@@ -902,7 +1091,7 @@ int iim_get_info(const iim_problem* h, iim_info* info) {
             info->box_lo[d] = p.box.lo[d];
             info->box_dims[d] = p.box.dims[d];
         }
-        info->device_bytes = (int64_t)p.mem.total;
+        info->device_bytes = (int64_t)p.mem.peak;
         info->t_setup_ms = p.t_setup_ms;
         return IIM_OK;
     })
@@ -1107,6 +1296,23 @@ int iim_time_kernel(iim_problem* h, int32_t kernel, int32_t reps, double* avg_ms
         if (!h || !avg_ms || reps < 1) throw Error(IIM_E_INVALID_ARG, "bad argument");
         Problem& p = *h->p;
         *avg_ms = p.time_kernel(kernel, reps);
+        return IIM_OK;
+    })
+}
+
+int iim_set_synthetic_data(iim_problem* h, int32_t kind) {
+    ABI_TRY({
+        if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
+        h->p->synth_data(kind);
+        IIM_HIP(hipStreamSynchronize(h->p->stream));
+        return IIM_OK;
+    })
+}
+
+int iim_synthetic_error(iim_problem* h, int32_t kind, const double* u, double* max_err) {
+    ABI_TRY({
+        if (!h || !u || !max_err) throw Error(IIM_E_INVALID_ARG, "null argument");
+        *max_err = h->p->synth_error(kind, u);
         return IIM_OK;
     })
 }

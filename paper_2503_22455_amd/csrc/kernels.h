@@ -63,9 +63,12 @@ struct LSParams {
     int mcap;                    // capacity of the per-wave scratch (rows)
 };
 // pass 0: sizes (m, growth) per control point side; pass 1: fill idx / weights
+// cs_list == nullptr: all fits by the register path (oversized ones flagged in route);
+// otherwise only the listed fits, with the global scratch (scratch_waves slabs).
 void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P,
             int pass, int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx,
-            double* S, double* Sc, double* scratch, int64_t scratch_waves, int* d_err, hipStream_t s);
+            double* S, double* Sc, double* scratch, int64_t scratch_waves, int* d_err,
+            const int32_t* cs_list, int64_t n_list, uint8_t* route, hipStream_t s);
 
 // ---- operators (ops.hip) -------------------------------------------------------
 struct GhostDev {
@@ -172,5 +175,15 @@ void run_copy(const double* x, double* y, int64_t n, hipStream_t s);
 void run_absmax(const double* x, int64_t n, double* part, double* out, hipStream_t s);
 // out[0] = <x, x>
 void run_norm2(const double* x, int64_t n, double* part, double* out, hipStream_t s);
+
+// ---- manufactured data (synth.hip) ------------------------------------------------
+void run_synth_cp(int kind, int dim, int bc, const CPDev& cp, double beta_plus, double beta_minus, double* cpdata,
+                  hipStream_t s);
+// f (box, at unknowns) and box-face values from the closed-form u
+void run_synth_nodes(int kind, const Geom& g, const Box& b, const uint8_t* labels, double beta_plus, double beta_minus,
+                     double* f, double* boxval, hipStream_t s);
+// atomically maxes the bit pattern of max |u_full - u_exact| over the unknowns into *out
+void run_synth_err(int kind, const Geom& g, const Box& b, const uint8_t* labels, const double* u,
+                   unsigned long long* out, hipStream_t s);
 
 }  // namespace iim

@@ -202,7 +202,8 @@ __device__ bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int cl
 template <int PT, int RPL>
 __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels, CPDev cp, LSParams P, int pass,
                                            int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx_out,
-                                           double* S_out, double* Sc_out, double* scratch, int* err) {
+                                           double* S_out, double* Sc_out, double* scratch, int* err,
+                                           const int32_t* cs_list, int64_t n_list, uint8_t* route) {
     __shared__ int32_t list_idx[LS_MAXC];
     __shared__ double list_r2[LS_MAXC];
     __shared__ int ex[84][3];
@@ -217,10 +218,16 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
     __syncthreads();
     const int64_t ncs = cp.ncp * P.nsides;
     const int mcap = P.mcap;
-    double* Acol = scratch + (int64_t)blockIdx.x * (int64_t)(p + 4) * mcap;  // [p][mcap] then s [4][mcap]
-    double* Scol = Acol + (int64_t)p * mcap;
+    // per-wave slab of the scratch launch: [p][mcap] columns of A, then s [4][mcap]
+    double* Acol = scratch ? scratch + (int64_t)blockIdx.x * (int64_t)(p + 4) * mcap : nullptr;
+    double* Scol = scratch ? Acol + (int64_t)p * mcap : nullptr;
 
-    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
+    // cs_list == nullptr: every fit through the register path, fits larger than it
+    // are routed (route[cs] = 1) to a second launch over cs_list with scratch
+    const int64_t nwork = cs_list ? n_list : ncs;
+    for (int64_t wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+        const int64_t cs = cs_list ? cs_list[wk] : wk;
+        if (!cs_list && pass == 1 && route[cs]) continue;
         const int64_t c = cs / P.nsides;
         const int sidx = (int)(cs % P.nsides);
         const uint8_t side = sidx == 0 ? K_PLUS : K_MINUS;
@@ -349,6 +356,15 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                     m_out[cs] = m;
                     grow_out[cs] = grow;
                 }
+                break;
+            }
+            if (!cs_list) {  // too large for registers: leave it to the scratch launch
+                if (pass == 0 && lane == 0) {
+                    route[cs] = 1;
+                    grow_out[cs] = -3;
+                    m_out[cs] = 0;
+                }
+                done = true;
                 break;
             }
             if (M > mcap) {
@@ -496,16 +512,18 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
 
 void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P, int pass,
             int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx, double* S, double* Sc,
-            double* scratch, int64_t scratch_waves, int* d_err, hipStream_t s) {
+            double* scratch, int64_t scratch_waves, int* d_err, const int32_t* cs_list, int64_t n_list,
+            uint8_t* route, hipStream_t s) {
     int64_t ncs = cp.ncp * P.nsides;
-    if (ncs == 0) return;
-    int blocks = (int)std::min<int64_t>(ncs, scratch_waves);
+    int64_t nwork = cs_list ? n_list : ncs;
+    if (nwork == 0) return;
+    int blocks = (int)std::min<int64_t>(nwork, cs_list ? scratch_waves : 4096);
     if (g.dim == 2)
         hipLaunchKernelGGL((k_ls<15, 2>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
-                           idx, S, Sc, scratch, d_err);
+                           idx, S, Sc, scratch, d_err, cs_list, n_list, route);
     else
         hipLaunchKernelGGL((k_ls<35, 4>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
-                           idx, S, Sc, scratch, d_err);
+                           idx, S, Sc, scratch, d_err, cs_list, n_list, route);
     IIM_LAUNCH_CHECK();
 }
 

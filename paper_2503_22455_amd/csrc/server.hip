@@ -1,0 +1,265 @@
+// Serving: continuous batching of independent Poisson solves on one device.
+//
+// A request queue in arrival order feeds a fixed pool of worker threads (the
+// slots).  Each worker owns one non-blocking HIP stream and one pinned host
+// buffer, and runs a whole request on that stream: setup of the handle (its
+// level hierarchy and Krylov basis stay resident for the request's lifetime),
+// manufactured data, the FGMRES solve (HIP-graph iterations), the error
+// against the closed-form solution, and stream-ordered teardown.  Requests on
+// different slots therefore overlap on the device.  Admission is FIFO against a
+// byte budget: the head of the queue starts only when a slot is free and its
+// estimated peak device bytes fit in what running requests leave of the budget.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "core.h"
+
+namespace iim {
+
+struct Job {
+    iim_request req{};
+    std::vector<double> params;
+    iim_result res{};
+};
+
+struct Server {
+    int device = 0;
+    int64_t budget = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Job*> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
+    uint64_t next_ticket = 1;
+    int64_t reserved = 0, peak = 0, submitted = 0, completed = 0, failed = 0, running = 0;
+    bool stopping = false;
+    std::vector<std::thread> workers;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double clock() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    void worker();
+    void run(Job& j, hipStream_t s, double* hpin);
+};
+
+void Server::run(Job& j, hipStream_t s, double* hpin) {
+    iim_result& r = j.res;
+    try {
+        auto p = make_problem(&j.req.grid, &j.req.geom, &j.req.opt, s, hpin);
+        r.n_unknowns = p->levels[0].nunk;
+        p->synth_data(j.req.data_kind);
+        const int64_t n1 = j.req.grid.n + 1;
+        const int64_t tot = j.req.grid.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+        double* u = j.req.u_out ? j.req.u_out : (double*)p->mem.alloc(tot * sizeof(double));
+        iim_stats st{};
+        const int status = p->solve(u, nullptr, nullptr, 0, &st);
+        r.max_error = p->synth_error(j.req.data_kind, u);
+        r.status = status;
+        r.iterations = st.iterations;
+        r.rel_residual = st.final_rel_residual;
+        r.device_bytes = (int64_t)p->mem.peak;
+        r.t_finish = clock();  // the result is complete; teardown follows
+    } catch (const Error& e) {
+        r.status = e.code;
+        r.t_finish = clock();
+    } catch (...) {
+        r.status = IIM_E_INTERNAL;
+        r.t_finish = clock();
+    }
+}
+
+void Server::worker() {
+    hipStream_t s = nullptr;
+    double* hpin = nullptr;
+    bool ok = hipSetDevice(device) == hipSuccess && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+              hipHostMalloc((void**)&hpin, 256 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+    while (true) {
+        Job* j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] {
+                return (stopping && queue.empty()) ||
+                       (!queue.empty() && reserved + queue.front()->res.estimated_bytes <= budget);
+            });
+            if (queue.empty()) break;
+            j = queue.front();
+            queue.pop_front();
+            reserved += j->res.estimated_bytes;
+            peak = std::max(peak, reserved);
+            ++running;
+            j->res.t_start = clock();
+        }
+        cv_work.notify_all();  // the new head may fit beside this one
+        if (ok)
+            run(*j, s, hpin);
+        else {
+            j->res.status = IIM_E_DEVICE;
+            j->res.t_finish = clock();
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            reserved -= j->res.estimated_bytes;
+            --running;
+            if (j->res.status < 0) ++failed; else ++completed;
+            j->res.done = 1;
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+    if (hpin) (void)hipHostFree(hpin);
+    if (s) (void)hipStreamDestroy(s);
+}
+
+// the parameter checks that must hold before the estimator reads params
+static void check_request(const iim_request& q) {
+    const iim_grid& g = q.grid;
+    const iim_geometry& geo = q.geom;
+    if (g.dim != 2 && g.dim != 3) throw Error(IIM_E_INVALID_ARG, "dim must be 2 or 3");
+    if (g.n < 8 || g.n > 16384) throw Error(IIM_E_INVALID_ARG, "n out of range");
+    if (!(g.hi > g.lo)) throw Error(IIM_E_INVALID_ARG, "empty domain");
+    if (!geo.params) throw Error(IIM_E_INVALID_ARG, "null params");
+    if (geo.kind == IIM_GEOM_SPHERE && geo.nparams < g.dim + 1)
+        throw Error(IIM_E_INVALID_ARG, "sphere needs dim + 1 parameters");
+    if (geo.kind == IIM_GEOM_STAR2D && (g.dim != 2 || geo.nparams < 5))
+        throw Error(IIM_E_INVALID_ARG, "star needs dim 2 and 5 parameters");
+    if (geo.kind == IIM_GEOM_SPHERE_UNION &&
+        (geo.nparams < 1 || geo.params[0] < 0 || geo.nparams < 1 + (g.dim + 1) * (int64_t)geo.params[0]))
+        throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
+    if (geo.kind < 0 || geo.kind > 2) throw Error(IIM_E_INVALID_ARG, "bad geometry kind");
+    if (q.data_kind != 1) throw Error(IIM_E_INVALID_ARG, "unknown synthetic data kind");
+}
+
+}  // namespace iim
+
+using namespace iim;
+
+struct iim_server {
+    Server s;
+};
+
+#define SRV_TRY(...)                                               \
+    try {                                                          \
+        __VA_ARGS__;                                               \
+    } catch (const iim::Error& e) {                                \
+        iim::set_error(e.what());                                  \
+        return e.code;                                             \
+    } catch (const std::exception& e) {                            \
+        iim::set_error(std::string("internal error: ") + e.what()); \
+        return IIM_E_INTERNAL;                                     \
+    } catch (...) {                                                \
+        iim::set_error("internal error");                          \
+        return IIM_E_INTERNAL;                                     \
+    }
+
+extern "C" {
+
+int iim_server_create(int64_t budget_bytes, int32_t max_slots, iim_server** out) {
+    SRV_TRY({
+        if (!out) throw Error(IIM_E_INVALID_ARG, "null argument");
+        *out = nullptr;
+        if (budget_bytes <= 0) throw Error(IIM_E_INVALID_ARG, "budget must be positive");
+        if (max_slots < 1 || max_slots > 64) throw Error(IIM_E_INVALID_ARG, "max_slots must be in [1, 64]");
+        auto srv = std::make_unique<iim_server>();
+        IIM_HIP(hipGetDevice(&srv->s.device));
+        configure_pool(srv->s.device);
+        srv->s.budget = budget_bytes;
+        for (int i = 0; i < max_slots; ++i) srv->s.workers.emplace_back([p = &srv->s] { p->worker(); });
+        *out = srv.release();
+        return IIM_OK;
+    })
+}
+
+int iim_server_submit(iim_server* srv, const iim_request* req, uint64_t* ticket) {
+    SRV_TRY({
+        if (!srv || !req || !ticket) throw Error(IIM_E_INVALID_ARG, "null argument");
+        check_request(*req);
+        auto j = std::make_unique<Job>();
+        j->req = *req;
+        j->params.assign(req->geom.params, req->geom.params + req->geom.nparams);
+        j->req.geom.params = j->params.data();
+        j->res.estimated_bytes = estimate_bytes(j->req.grid, j->req.geom, j->req.opt);
+        Server& s = srv->s;
+        {
+            std::lock_guard<std::mutex> lk(s.mu);
+            if (s.stopping) throw Error(IIM_E_INVALID_ARG, "server is shutting down");
+            const uint64_t id = s.next_ticket++;
+            j->res.t_submit = s.clock();
+            ++s.submitted;
+            Job* jp = j.get();
+            s.jobs.emplace(id, std::move(j));
+            if (jp->res.estimated_bytes > s.budget) {  // can never run: fail now, keep the queue moving
+                jp->res.status = IIM_E_BUDGET;
+                jp->res.t_start = jp->res.t_finish = jp->res.t_submit;
+                jp->res.done = 1;
+                ++s.failed;
+            } else {
+                s.queue.push_back(jp);
+            }
+            *ticket = id;
+        }
+        s.cv_work.notify_all();
+        s.cv_done.notify_all();
+        return IIM_OK;
+    })
+}
+
+int iim_server_poll(iim_server* srv, uint64_t ticket, iim_result* res) {
+    SRV_TRY({
+        if (!srv || !res) throw Error(IIM_E_INVALID_ARG, "null argument");
+        std::lock_guard<std::mutex> lk(srv->s.mu);
+        auto it = srv->s.jobs.find(ticket);
+        if (it == srv->s.jobs.end()) throw Error(IIM_E_INVALID_ARG, "unknown ticket");
+        *res = it->second->res;
+        return IIM_OK;
+    })
+}
+
+int iim_server_wait(iim_server* srv, uint64_t ticket, iim_result* res) {
+    SRV_TRY({
+        if (!srv || !res) throw Error(IIM_E_INVALID_ARG, "null argument");
+        std::unique_lock<std::mutex> lk(srv->s.mu);
+        auto it = srv->s.jobs.find(ticket);
+        if (it == srv->s.jobs.end()) throw Error(IIM_E_INVALID_ARG, "unknown ticket");
+        Job* j = it->second.get();
+        srv->s.cv_done.wait(lk, [&] { return j->res.done != 0; });
+        *res = j->res;
+        return IIM_OK;
+    })
+}
+
+int iim_server_stats_get(iim_server* srv, iim_server_stats* st) {
+    SRV_TRY({
+        if (!srv || !st) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Server& s = srv->s;
+        std::lock_guard<std::mutex> lk(s.mu);
+        st->submitted = s.submitted;
+        st->completed = s.completed;
+        st->failed = s.failed;
+        st->running = s.running;
+        st->queued = (int64_t)s.queue.size();
+        st->bytes_reserved = s.reserved;
+        st->bytes_budget = s.budget;
+        st->peak_bytes_reserved = s.peak;
+        return IIM_OK;
+    })
+}
+
+double iim_server_clock(iim_server* srv) { return srv ? srv->s.clock() : 0.0; }
+
+void iim_server_destroy(iim_server* srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->s.mu);
+        srv->s.stopping = true;
+    }
+    srv->s.cv_work.notify_all();
+    for (auto& t : srv->s.workers) t.join();
+    delete srv;
+    trim_pool();
+}
+
+}  // extern "C"

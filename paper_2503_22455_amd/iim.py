@@ -65,6 +65,24 @@ class Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("t_setup_ms", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("geom", Geometry), ("opt", Options), ("data_kind", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("u_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("max_error", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_finish", ctypes.c_double),
+                ("n_unknowns", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("estimated_bytes", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "running", "queued",
+                                              "bytes_reserved", "bytes_budget", "peak_bytes_reserved")]
+
+
 _lib = None
 
 
@@ -95,6 +113,18 @@ def lib():
         L.iim_level_labels.argtypes = [vp, i32, vp]
         L.iim_level_op.argtypes = [vp, i32, i32, vp, vp]
         L.iim_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
+        L.iim_set_synthetic_data.argtypes = [vp, i32]
+        L.iim_synthetic_error.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_double)]
+        u64 = ctypes.c_uint64
+        L.iim_server_create.argtypes = [i64, i32, ctypes.POINTER(vp)]
+        L.iim_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]
+        L.iim_server_poll.argtypes = [vp, u64, ctypes.POINTER(Result)]
+        L.iim_server_wait.argtypes = [vp, u64, ctypes.POINTER(Result)]
+        L.iim_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.iim_server_clock.argtypes = [vp]
+        L.iim_server_clock.restype = ctypes.c_double
+        L.iim_server_destroy.argtypes = [vp]
+        L.iim_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -126,6 +156,23 @@ def flat_to_grid(v: np.ndarray, dim: int, n: int) -> np.ndarray:
     return np.asarray(v).reshape((n + 1,) * dim, order="F")
 
 
+def make_options(beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 1e-10, max_iters: int = 500,
+                 restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
+                 precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None, use_graph: bool = True,
+                 tail_nodes: int = 0, fused_smoothing: bool = True) -> Options:
+    o = Options()
+    lib().iim_default_options(ctypes.byref(o))
+    o.beta_plus, o.beta_minus, o.rtol, o.max_iters = beta_plus, beta_minus, rtol, max_iters
+    o.restart, o.nu_pre, o.nu_post, o.coarsest_n = restart, nu_pre, nu_post, coarsest_n
+    o.precision = PREC[precision]
+    o.use_graph = int(use_graph)
+    o.tail_nodes = int(tail_nodes)
+    o.fused_smoothing = int(fused_smoothing)
+    if ls_axes is not None:
+        o.ls_axis_t, o.ls_axis_n = ls_axes
+    return o
+
+
 class Problem:
     """One immersed-interface Poisson problem resident on the current device."""
 
@@ -142,16 +189,8 @@ class Problem:
         g = Grid(dim, n, lo, hi)
         pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
         geo = Geometry(geom_kind, side, bc, len(geom_params), pa)
-        o = Options()
-        L.iim_default_options(ctypes.byref(o))
-        o.beta_plus, o.beta_minus, o.rtol, o.max_iters = beta_plus, beta_minus, rtol, max_iters
-        o.restart, o.nu_pre, o.nu_post, o.coarsest_n = restart, nu_pre, nu_post, coarsest_n
-        o.precision = PREC[precision]
-        o.use_graph = int(use_graph)
-        o.tail_nodes = int(tail_nodes)
-        o.fused_smoothing = int(fused_smoothing)
-        if ls_axes is not None:
-            o.ls_axis_t, o.ls_axis_n = ls_axes
+        o = make_options(beta_plus, beta_minus, rtol, max_iters, restart, nu_pre, nu_post, coarsest_n, precision,
+                         ls_axes, use_graph, tail_nodes, fused_smoothing)
         self._h = ctypes.c_void_p()
         # default: the library orders its own stream after the legacy default stream
         s = 0 if stream is None else stream
@@ -265,6 +304,74 @@ class Problem:
         _check(rc, allow_not_converged=True)
         stats = {k: getattr(st, k) for k, _ in Stats._fields_}
         return u, hist[: st.hist_len].copy(), stats
+
+
+    def set_synthetic_data(self, kind: int = 1):
+        """Device-side manufactured data (see iim_set_synthetic_data)."""
+        _check(lib().iim_set_synthetic_data(self._h, kind))
+
+    def synthetic_error(self, u, kind: int = 1) -> float:
+        e = ctypes.c_double()
+        _check(lib().iim_synthetic_error(self._h, kind, _ptr(u), ctypes.byref(e)))
+        return e.value
+
+
+class Server:
+    """Continuous-batching solve server on the current device (iim_server_*)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int):
+        self._s = ctypes.c_void_p()
+        self._keep = {}
+        _check(lib().iim_server_create(int(budget_bytes), int(max_slots), ctypes.byref(self._s)))
+
+    def submit(self, dim: int, n: int, geom_kind: int, geom_params, side: int = SIDE_INTERIOR,
+               bc: int = BC_DIRICHLET, data_kind: int = 1, u_out=None, lo: float = -1.0, hi: float = 1.0,
+               **opt) -> int:
+        pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
+        req = Request(Grid(dim, n, lo, hi), Geometry(geom_kind, side, bc, len(geom_params), pa), make_options(**opt),
+                      data_kind, 0, None if u_out is None else _ptr(u_out))
+        t = ctypes.c_uint64()
+        _check(lib().iim_server_submit(self._s, ctypes.byref(req), ctypes.byref(t)))
+        if u_out is not None:
+            self._keep[t.value] = u_out  # alive until the result is collected
+        return t.value
+
+    @staticmethod
+    def _dict(r: Result) -> dict:
+        return {k: getattr(r, k) for k, _ in Result._fields_}
+
+    def poll(self, ticket: int) -> dict:
+        r = Result()
+        _check(lib().iim_server_poll(self._s, ticket, ctypes.byref(r)))
+        if r.done:
+            self._keep.pop(ticket, None)
+        return self._dict(r)
+
+    def wait(self, ticket: int) -> dict:
+        r = Result()
+        _check(lib().iim_server_wait(self._s, ticket, ctypes.byref(r)))
+        self._keep.pop(ticket, None)
+        return self._dict(r)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().iim_server_stats_get(self._s, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def clock(self) -> float:
+        return lib().iim_server_clock(self._s)
+
+    def close(self):
+        if self._s:
+            lib().iim_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def from_workload(wl, precision: Optional[str] = None, **kw) -> Problem:

@@ -1,0 +1,165 @@
+"""GPU checks of device-side manufactured data and of the solve server
+(continuous batching), all through the C ABI."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import oracle_for, gpu_for, oracle_data, flat
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _same_both_sides(ms):
+    return dataclasses.replace(ms, u_minus=ms.u_plus, grad_minus=ms.grad_plus, lap_minus=ms.lap_plus)
+
+
+def _cases():
+    return {
+        "circle64-dir": W.cfg1_circle(64),
+        "circle75-dir": W.cfg1_circle(75),
+        "sphere24-dir": dataclasses.replace(W.cfg3_sphere(24), precision="fp64"),
+        "spheres32-neu": dataclasses.replace(W.cfg4_spheres(32, spheres=W.small_spheres_union()),
+                                             exact=W.ms_sin_pi_3d(), precision="fp64"),
+        "star128-jump": dataclasses.replace(W.cfg2_star(128, beta_plus=1.0, beta_minus=10.0),
+                                            exact=_same_both_sides(W.ms_sin2pi_cos2pi())),
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_synthetic_data_matches_oracle(name):
+    """Data made on the device (kind 1) give the solution of the oracle's
+    direct solve with the same manufactured u sampled on the host, and the
+    reported max error equals the one measured from the returned u."""
+    wl = _cases()[name]
+    O = oracle_for(wl)
+    cpd, box, f = oracle_data(O, wl)
+    ug = O.data_vector(cpd, wl.box_data())
+    ud = O.direct_solve(O.rhs(wl.rhs(O.labels), ug))
+    G = gpu_for(wl, rtol=1e-13, max_iters=400)
+    G.set_synthetic_data(1)
+    u, _, st = G.solve()
+    assert st["status"] == 0, st
+    uu = u.cpu().numpy()[O.unknowns]
+    assert np.abs(uu - ud).max() <= 1e-10 * np.abs(ud).max()
+    exact = flat(wl.exact_solution(O.labels))[O.unknowns]
+    err_host = np.abs(uu - exact).max()
+    err_dev = G.synthetic_error(u, 1)
+    assert abs(err_dev - err_host) <= 1e-8 * err_host + 1e-14
+    G.close()
+
+
+def _submit(srv, spec, u_out=None, **kw):
+    dim, n, params = spec
+    return srv.submit(dim, n, W.GEOM_SPHERE, params, W.SIDE_INTERIOR, W.BC_DIRICHLET, data_kind=1, u_out=u_out,
+                      precision=kw.pop("precision", "mixed32"), rtol=1e-10, **kw)
+
+
+MIX = [(2, 150, [0.1, -0.05, 0.5]), (3, 40, [0.05, 0.0, 0.1, 0.55]), (2, 333, [-0.12, 0.08, 0.62]),
+       (3, 57, [0.0, -0.1, 0.05, 0.45]), (2, 128, [0.0, 0.0, 0.3]), (3, 33, [0.1, 0.1, -0.1, 0.6]),
+       (2, 517, [0.15, 0.0, 0.41]), (3, 64, [-0.05, 0.02, 0.0, 0.66])]
+
+
+def _numel(spec):
+    return (spec[1] + 1) ** spec[0]
+
+
+def test_server_result_same_alone_and_in_mix():
+    """A request solved alone (one slot) and inside a mix of requests of other
+    sizes and dimensions on four slots gives the bitwise-identical u, the same
+    iteration count, and the same u as a plain handle; the mix overlaps."""
+    from paper_2503_22455_amd import iim
+    target = MIX[2]
+    uA = torch.empty(_numel(target), dtype=torch.float64, device="cuda")
+    s1 = iim.Server(64 << 30, 1)
+    rA = s1.wait(_submit(s1, target, uA))
+    s1.close()
+    assert rA["status"] == 0 and rA["rel_residual"] <= 1e-10, rA
+
+    uB = torch.empty_like(uA)
+    s4 = iim.Server(64 << 30, 4)
+    tickets = []
+    for spec in MIX:
+        tickets.append(_submit(s4, spec, uB if spec is target else None))
+    res = [s4.wait(t) for t in tickets]
+    st = s4.stats()
+    s4.close()
+    for r in res:
+        assert r["status"] == 0 and r["rel_residual"] <= 1e-10, r
+        assert r["max_error"] < 1e-2, r  # discretisation error; 3D n = 33 is the coarsest
+    rB = res[2]
+    assert rB["iterations"] == rA["iterations"]
+    assert torch.equal(torch.isnan(uA), torch.isnan(uB))
+    assert torch.equal(uA.nan_to_num(0.0), uB.nan_to_num(0.0))
+    assert st["completed"] == len(MIX) and st["failed"] == 0
+    # some requests ran at the same time
+    iv = sorted((r["t_start"], r["t_finish"]) for r in res)
+    assert any(iv[i + 1][0] < iv[i][1] for i in range(len(iv) - 1))
+
+    # the same request through a plain handle
+    dim, n, params = target
+    P = iim.Problem(dim, n, W.GEOM_SPHERE, params, W.SIDE_INTERIOR, W.BC_DIRICHLET, precision="mixed32", rtol=1e-10)
+    P.set_synthetic_data(1)
+    uC, _, stc = P.solve()
+    assert stc["iterations"] == rA["iterations"]
+    assert torch.equal(uA.nan_to_num(0.0), uC.nan_to_num(0.0))
+    assert abs(P.synthetic_error(uC, 1) - rA["max_error"]) == 0.0
+    P.close()
+
+
+def test_server_budget_admission():
+    """Running requests never reserve more than the budget, each request's
+    device bytes stay within its estimate, a request larger than the budget
+    fails at once with IIM_E_BUDGET, and a failing request leaves the others
+    unaffected."""
+    from paper_2503_22455_amd import iim
+    probe = iim.Server(64 << 30, 1)
+    est = {}
+    for spec in MIX:
+        r = probe.wait(_submit(probe, spec))
+        assert r["status"] == 0, r
+        assert 0 < r["device_bytes"] <= r["estimated_bytes"], r
+        est[id(spec)] = r["estimated_bytes"]
+    probe.close()
+    budget = int(1.3 * max(est.values()))
+    srv = iim.Server(budget, 4)
+    tickets = [_submit(srv, spec) for spec in MIX]
+    bad = srv.submit(2, 64, W.GEOM_SPHERE, [0.0, 0.0, 1.2], W.SIDE_INTERIOR, W.BC_DIRICHLET, data_kind=1,
+                     precision="mixed32")
+    res = [srv.wait(t) for t in tickets]
+    rbad = srv.wait(bad)
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res), res
+    assert rbad["status"] == -2, rbad
+    assert st["peak_bytes_reserved"] <= budget
+    assert st["completed"] == len(MIX) and st["failed"] == 1
+
+    tiny = iim.Server(1 << 20, 2)
+    t = _submit(tiny, MIX[0])
+    r = tiny.poll(t)
+    assert r["done"] == 1 and r["status"] == -3, r
+    st = tiny.stats()
+    tiny.close()
+    assert st["failed"] == 1 and st["completed"] == 0
+
+
+def test_server_rejects_bad_requests():
+    from paper_2503_22455_amd import iim
+    srv = iim.Server(1 << 30, 1)
+    with pytest.raises(iim.IIMError) as e:
+        srv.submit(4, 64, W.GEOM_SPHERE, [0.0, 0.0, 0.5], data_kind=1)
+    assert e.value.code == -1
+    with pytest.raises(iim.IIMError) as e:
+        srv.submit(2, 64, W.GEOM_SPHERE, [0.0, 0.5], data_kind=1)
+    assert e.value.code == -1
+    with pytest.raises(iim.IIMError) as e:
+        srv.submit(2, 64, W.GEOM_SPHERE, [0.0, 0.0, 0.5], data_kind=7)
+    assert e.value.code == -1
+    with pytest.raises(iim.IIMError):
+        iim.Server(0, 1)
+    with pytest.raises(iim.IIMError):
+        iim.Server(1 << 30, 65)
+    srv.close()
