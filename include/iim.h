@@ -224,7 +224,10 @@ int iim_level_op(iim_problem* p, int32_t level, int32_t op, const double* in1, d
  * 1 = ghost values, 2 = one red-black sweep on level 0 (both colours),
  * 3 = residual + restriction 0 -> 1, 4 = prolongation 1 -> 0,
  * 5 = fused orthogonalisation update + dots over 6 basis vectors,
- * 6 = one whole V-cycle, 7 = one whole operator apply (ghosts + stencil). */
+ * 6 = one whole V-cycle, 7 = one whole operator apply (ghosts + stencil),
+ * 8 = fused pre-smoothing + residual + restriction leg 0 -> 1 and
+ * 9 = fused prolongation + post-smoothing leg 1 -> 0 (the LDS-tiled legs the
+ * V-cycle uses in 2D; IIM_E_INVALID_ARG where they do not apply). */
 int iim_time_kernel(iim_problem* p, int32_t kernel, int32_t reps, double* avg_ms);
 
 /* Synthetic manufactured data for benchmarks and serving, computed on the

@@ -2,52 +2,73 @@
 // orthogonalisation updates, norms and multi-axpys (Sec. 4.1 of the paper
 // uses FGMRES; these are its orthogonalisation and update steps).
 //
+// Every kernel streams its vectors with 16-byte (double2) loads: vectors start
+// on 16-byte boundaries (basis vectors sit at an even leading dimension) and an
+// odd trailing element is handled by one thread.
+//
 // Reductions are deterministic: every launch uses the same grid of
-// RED_BLOCKS x RED_THREADS threads with a grid-stride loop, each block reduces
-// its threads in a fixed LDS tree, and one block adds the block partials in a
-// fixed order.  Results therefore do not depend on timing or on other work
-// sharing the device.
+// RED_BLOCKS x RED_THREADS threads with a grid-stride loop; a block reduces
+// each wavefront by a fixed xor-shuffle butterfly (lane 0's value is used) and
+// adds its RED_THREADS / 64 wavefront sums in order; a one-block second stage
+// adds the block partials in a fixed order.  Results therefore do not depend
+// on timing or on other work sharing the device.
 #include "kernels.h"
 
 namespace iim {
 
 constexpr int KCH = 12;  // vectors handled per pass (registers per thread)
+constexpr int WAVES = RED_THREADS / 64;
 
-__device__ inline void block_reduce_store(double* vals, int k, double* part, int partial_stride) {
-    __shared__ double sh[RED_THREADS];
-    for (int i = 0; i < k; ++i) {
-        sh[threadIdx.x] = vals[i];
-        __syncthreads();
-        for (int off = RED_THREADS / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-            __syncthreads();
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// part[i * RED_BLOCKS + blockIdx.x] = block sum (mode 1: max) of vals[i], i < k
+template <int K>
+__device__ inline void block_reduce_store(const double (&vals)[K], int k, double* part, int mode) {
+    __shared__ double sh[WAVES][K];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (i < k) {
+            double v = mode == 1 ? wave_max(vals[i]) : wave_sum(vals[i]);
+            if (lane == 0) sh[wv][i] = v;
         }
-        if (threadIdx.x == 0) part[(int64_t)i * partial_stride + blockIdx.x] = sh[0];
-        __syncthreads();
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        double s = sh[0][threadIdx.x];
+        for (int q = 1; q < WAVES; ++q) s = mode == 1 ? fmax(s, sh[q][threadIdx.x]) : s + sh[q][threadIdx.x];
+        part[(int64_t)threadIdx.x * RED_BLOCKS + blockIdx.x] = s;
     }
 }
 
+// Second stage, one block: out[i] = sum (mode 1: max) of the RED_BLOCKS
+// partials of value i in a fixed order, one wavefront per value; mode 1 also
+// writes out[1] = 1 / max (1 if zero).  A separate launch rather than a
+// last-block-done epilogue: the epilogue's device-scope fences cost more than
+// a launch on a device whose XCDs have separate L2 caches.
 __global__ void __launch_bounds__(RED_THREADS) k_final(const double* part, int k, double* out, int mode) {
-    __shared__ double sh[RED_THREADS];
-    for (int i = 0; i < k; ++i) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = wv; i < k; i += WAVES) {
         double v = 0.0;
-        for (int b = threadIdx.x; b < RED_BLOCKS; b += RED_THREADS) {
-            double p = part[(int64_t)i * RED_BLOCKS + b];
+        for (int bq = lane; bq < RED_BLOCKS; bq += 64) {
+            const double p = part[(int64_t)i * RED_BLOCKS + bq];
             v = mode == 1 ? fmax(v, p) : v + p;
         }
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = RED_THREADS / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off)
-                sh[threadIdx.x] = mode == 1 ? fmax(sh[threadIdx.x], sh[threadIdx.x + off])
-                                            : sh[threadIdx.x] + sh[threadIdx.x + off];
-            __syncthreads();
+        v = mode == 1 ? wave_max(v) : wave_sum(v);
+        if (lane == 0) {
+            out[i] = v;
+            if (mode == 1) out[1] = v > 0.0 ? 1.0 / v : 1.0;
         }
-        if (threadIdx.x == 0) {
-            out[i] = sh[0];
-            if (mode == 1) out[1] = sh[0] > 0.0 ? 1.0 / sh[0] : 1.0;
-        }
-        __syncthreads();
     }
 }
 
@@ -56,94 +77,186 @@ static void final_sum(const double* part, int k, double* out, hipStream_t s, int
     IIM_LAUNCH_CHECK();
 }
 
-__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* V, int64_t ld, int k0, int k,
-                                                          const double* w, int64_t n, double* part) {
+static void check_vec(const void* p, int64_t ld) {
+    if (((uintptr_t)p & 15) || (ld & 1)) throw Error(IIM_E_INTERNAL, "vector kernels need 16-byte aligned vectors");
+}
+
+__device__ inline double2 ld2(const double* base, int64_t e) { return reinterpret_cast<const double2*>(base)[e]; }
+__device__ inline void st2(double* base, int64_t e, double2 v) { reinterpret_cast<double2*>(base)[e] = v; }
+
+__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* V, int64_t ld, int k, const double* w,
+                                                          int64_t n, double* part) {
     double acc[KCH];
 #pragma unroll
     for (int i = 0; i < KCH; ++i) acc[i] = 0.0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        double we = w[e];
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 we = ld2(w, e);
 #pragma unroll
         for (int i = 0; i < KCH; ++i)
-            if (i < k) acc[i] += V[(int64_t)(k0 + i) * ld + e] * we;
+            if (i < k) {
+                const double2 v = ld2(V + (int64_t)i * ld, e);
+                acc[i] += v.x * we.x;
+                acc[i] += v.y * we.y;
+            }
     }
-    block_reduce_store(acc, k, part + (int64_t)k0 * RED_BLOCKS, RED_BLOCKS);
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) acc[i] += V[(int64_t)i * ld + n - 1] * w[n - 1];
+    }
+    block_reduce_store(acc, k, part, 0);
 }
 
 void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* part, double* out,
                   hipStream_t s) {
-    for (int k0 = 0; k0 < k; k0 += KCH) {
-        int kk = std::min(KCH, k - k0);
-        hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k0, kk, w, n, part);
-        IIM_LAUNCH_CHECK();
-    }
+    if (k < 1 || k > KCH) throw Error(IIM_E_INVALID_ARG, "multidot: 1..12 vectors");
+    check_vec(V, ld);
+    check_vec(w, 0);
+    hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, w, n, part);
+    IIM_LAUNCH_CHECK();
     final_sum(part, k, out, s);
 }
 
-// w -= sum_i h_i V_i (all k at once), then dots of the updated w
+// w -= sum_i h_i V_i (all k at once), then dots of the updated w with V_i (i < k2)
+// and, if asked, its squared norm; each basis vector is read once
 __global__ void __launch_bounds__(RED_THREADS) k_update_dot(const double* V, int64_t ld, int k, const double* h,
                                                             double* w, int64_t n, int k2, int with_norm,
                                                             double* part) {
-    double acc[KCH + 1];
+    double hh[KCH], acc[KCH + 1];
 #pragma unroll
-    for (int i = 0; i <= KCH; ++i) acc[i] = 0.0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    for (int i = 0; i < KCH; ++i) {
+        hh[i] = i < k ? h[i] : 0.0;
+        acc[i] = 0.0;
+    }
+    acc[KCH] = 0.0;
+    const int kr = k > k2 ? k : k2;
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 we = ld2(w, e);
+        double2 v[KCH];
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < kr) v[i] = ld2(V + (int64_t)i * ld, e);
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) {
+                we.x -= hh[i] * v[i].x;
+                we.y -= hh[i] * v[i].y;
+            }
+        st2(w, e, we);
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k2) {
+                acc[i] += v[i].x * we.x;
+                acc[i] += v[i].y * we.y;
+            }
+        acc[KCH] += we.x * we.x;
+        acc[KCH] += we.y * we.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t e = n - 1;
         double we = w[e];
-        for (int i = 0; i < k; ++i) we -= h[i] * V[(int64_t)i * ld + e];
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) we -= hh[i] * V[(int64_t)i * ld + e];
         w[e] = we;
 #pragma unroll
         for (int i = 0; i < KCH; ++i)
             if (i < k2) acc[i] += V[(int64_t)i * ld + e] * we;
         acc[KCH] += we * we;
     }
-    if (with_norm) acc[k2] = acc[KCH];
-    block_reduce_store(acc, k2 + (with_norm ? 1 : 0), part, RED_BLOCKS);
+    // dots in slots 0..k2-1, the norm right after them
+    double outv[KCH + 1];
+#pragma unroll
+    for (int i = 0; i <= KCH; ++i) outv[i] = (i < k2) ? acc[i] : ((i == k2) ? acc[KCH] : 0.0);
+    block_reduce_store(outv, k2 + (with_norm ? 1 : 0), part, 0);
 }
 
 void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
                     int with_norm, double* part, double* out, hipStream_t s) {
-    if (k2 > KCH) throw Error(IIM_E_INVALID_ARG, "update_dot: too many vectors");
+    if (k > KCH || k2 > KCH) throw Error(IIM_E_INVALID_ARG, "update_dot: too many vectors");
+    check_vec(V, ld);
+    check_vec(w, 0);
+    if (k2 + (with_norm ? 1 : 0) < 1) throw Error(IIM_E_INVALID_ARG, "update_dot: nothing to reduce");
     hipLaunchKernelGGL(k_update_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, n, k2, with_norm,
                        part);
     IIM_LAUNCH_CHECK();
     final_sum(part, k2 + (with_norm ? 1 : 0), out, s);
 }
 
-__global__ void k_normalize(const double* x, const double* nrm2, double* y, int64_t n) {
-    double inv = 1.0 / sqrt(*nrm2);
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        y[e] = x[e] * inv;
+static int stream_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n / 2 + 1, 256), 8192)); }
+
+__global__ void __launch_bounds__(256) k_normalize(const double* x, const double* nrm2, double* y, int64_t n) {
+    const double inv = 1.0 / sqrt(*nrm2);
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = ld2(x, e);
+        v.x *= inv;
+        v.y *= inv;
+        st2(y, e, v);
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) y[n - 1] = x[n - 1] * inv;
 }
 
 void run_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s) {
-    int blocks = (int)std::min<int64_t>(cdiv(n, 256), 4096);
-    hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, s, x, nrm2, y, n);
+    check_vec(x, 0);
+    check_vec(y, 0);
+    hipLaunchKernelGGL(k_normalize, dim3(stream_blocks(n)), dim3(256), 0, s, x, nrm2, y, n);
     IIM_LAUNCH_CHECK();
 }
 
-__global__ void k_axpy_multi(const double* Z, int64_t ld, int k, const double* y, double* x, int64_t n) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        double v = x[e];
-        for (int i = 0; i < k; ++i) v += y[i] * Z[(int64_t)i * ld + e];
-        x[e] = v;
+__global__ void __launch_bounds__(256) k_axpy_multi(const double* Z, int64_t ld, int k, const double* y, double* x,
+                                                    int64_t n) {
+    double yy[KCH];
+#pragma unroll
+    for (int i = 0; i < KCH; ++i) yy[i] = i < k ? y[i] : 0.0;
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = ld2(x, e);
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) {
+                const double2 z = ld2(Z + (int64_t)i * ld, e);
+                v.x += yy[i] * z.x;
+                v.y += yy[i] * z.y;
+            }
+        st2(x, e, v);
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double v = x[n - 1];
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) v += yy[i] * Z[(int64_t)i * ld + n - 1];
+        x[n - 1] = v;
     }
 }
 
 void run_axpy_multi(const double* Z, int64_t ld, int k, const double* y, double* x, int64_t n, hipStream_t s) {
     if (k == 0) return;
-    int blocks = (int)std::min<int64_t>(cdiv(n, 256), 4096);
-    hipLaunchKernelGGL(k_axpy_multi, dim3(blocks), dim3(256), 0, s, Z, ld, k, y, x, n);
+    if (k > KCH) throw Error(IIM_E_INVALID_ARG, "axpy_multi: too many vectors");
+    check_vec(Z, ld);
+    check_vec(x, 0);
+    hipLaunchKernelGGL(k_axpy_multi, dim3(stream_blocks(n)), dim3(256), 0, s, Z, ld, k, y, x, n);
     IIM_LAUNCH_CHECK();
 }
 
-__global__ void k_axpby(double a, const double* x, double b, double* y, int64_t n) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        y[e] = a * x[e] + b * y[e];
+__global__ void __launch_bounds__(256) k_axpby(double a, const double* x, double b, double* y, int64_t n) {
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 u = ld2(x, e);
+        double2 v = ld2(y, e);
+        v.x = a * u.x + b * v.x;
+        v.y = a * u.y + b * v.y;
+        st2(y, e, v);
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) y[n - 1] = a * x[n - 1] + b * y[n - 1];
 }
 
 void run_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s) {
-    int blocks = (int)std::min<int64_t>(cdiv(n, 256), 4096);
-    hipLaunchKernelGGL(k_axpby, dim3(blocks), dim3(256), 0, s, a, x, b, y, n);
+    check_vec(x, 0);
+    check_vec(y, 0);
+    hipLaunchKernelGGL(k_axpby, dim3(stream_blocks(n)), dim3(256), 0, s, a, x, b, y, n);
     IIM_LAUNCH_CHECK();
 }
 
@@ -152,20 +265,18 @@ void run_copy(const double* x, double* y, int64_t n, hipStream_t s) {
 }
 
 __global__ void __launch_bounds__(RED_THREADS) k_absmax(const double* x, int64_t n, double* part) {
-    __shared__ double sh[RED_THREADS];
-    double v = 0.0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        v = fmax(v, fabs(x[e]));
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = RED_THREADS / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
-        __syncthreads();
+    double v[1] = {0.0};
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 u = ld2(x, e);
+        v[0] = fmax(v[0], fmax(fabs(u.x), fabs(u.y)));
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) v[0] = fmax(v[0], fabs(x[n - 1]));
+    block_reduce_store(v, 1, part, 1);
 }
 
 void run_absmax(const double* x, int64_t n, double* part, double* out, hipStream_t s) {
+    check_vec(x, 0);
     hipLaunchKernelGGL(k_absmax, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, n, part);
     IIM_LAUNCH_CHECK();
     final_sum(part, 1, out, s, 1);
@@ -173,12 +284,18 @@ void run_absmax(const double* x, int64_t n, double* part, double* out, hipStream
 
 __global__ void __launch_bounds__(RED_THREADS) k_norm2(const double* x, int64_t n, double* part) {
     double acc[1] = {0.0};
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        acc[0] += x[e] * x[e];
-    block_reduce_store(acc, 1, part, RED_BLOCKS);
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        const double2 u = ld2(x, e);
+        acc[0] += u.x * u.x;
+        acc[0] += u.y * u.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) acc[0] += x[n - 1] * x[n - 1];
+    block_reduce_store(acc, 1, part, 0);
 }
 
 void run_norm2(const double* x, int64_t n, double* part, double* out, hipStream_t s) {
+    check_vec(x, 0);
     hipLaunchKernelGGL(k_norm2, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, n, part);
     IIM_LAUNCH_CHECK();
     final_sum(part, 1, out, s);

@@ -46,11 +46,11 @@ struct Level {
     int32_t* irr_index = nullptr;
     double* rec64 = nullptr;
     float* rec32 = nullptr;
-    void* z = nullptr;  // iterate (storage type)
+    void* z = nullptr;   // iterate (storage type)
+    void* z2 = nullptr;  // 2D: output buffer of the fused up leg (it reads z)
     void* b = nullptr;  // right-hand side (arithmetic type)
 };
 
-constexpr int KRED = 16;  // reduction outputs per launch
 constexpr int64_t TAIL_MAX_NODES = 4096;  // levels handled by the one-workgroup tail kernel
 
 struct Problem {
@@ -82,6 +82,7 @@ struct Problem {
     int64_t ho_nirr = 0;
     int32_t* ho_irr_index = nullptr;
     int32_t* ho_slots = nullptr;
+    int32_t* ho_nodes = nullptr;  // their storage indices
     // multigrid
     std::vector<Level> levels;
     int64_t nc = 0;
@@ -90,7 +91,8 @@ struct Problem {
     float* Ainv32 = nullptr;
     // solve vectors (level-0 box)
     double *boxval = nullptr, *rhs = nullptr, *xk = nullptr, *rk = nullptr, *wk = nullptr;
-    double *Vb = nullptr, *Zb = nullptr;
+    double *Vb = nullptr, *Zb = nullptr;  // Krylov bases, vector i at + i * ldv
+    int64_t ldv = 0;                        // box size rounded up to 64 doubles
     double *red_part = nullptr, *red_out = nullptr;
     double* red_scale = nullptr;
     hipEvent_t ev[8] = {};
@@ -110,6 +112,8 @@ struct Problem {
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;
     void apply_box(const double* x, double* y, int with_data);
+    template <typename T, typename S> bool down_leg(int l);
+    template <typename T, typename S> const S* up_leg(int l, const S* zres);
     template <typename T, typename S> void vcycle_t(const double* v, double* out);
     void vcycle(const double* v, double* out);
     void iteration_body(int j, hipEvent_t* evs = nullptr);

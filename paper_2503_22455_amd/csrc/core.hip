@@ -311,6 +311,9 @@ void Problem::setup() {
         ho_slots = (int32_t*)mem.alloc(std::max<int64_t>(ho_nirr, 1) * 2 * dim * sizeof(int32_t));
         run_ho_irr_records(L0.geom, box, L0.labels, cp, nodes, ho_nirr, ho_slots, ho_irr_index, d_err, stream);
         check_err(d_err, "irregular records");
+        ho_nodes = (int32_t*)mem.alloc(std::max<int64_t>(ho_nirr, 1) * sizeof(int32_t));
+        if (ho_nirr)
+            IIM_HIP(hipMemcpyAsync(ho_nodes, nodes, ho_nirr * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
         mem.release(nodes);
         mem.release(flags);
     }
@@ -380,12 +383,14 @@ void Problem::setup() {
     xk = (double*)mem.alloc(N * sizeof(double));
     rk = (double*)mem.alloc(N * sizeof(double));
     wk = (double*)mem.alloc(N * sizeof(double));
-    Vb = (double*)mem.alloc((size_t)(m + 1) * N * sizeof(double));
-    Zb = (double*)mem.alloc((size_t)m * N * sizeof(double));
+    ldv = (N + 63) / 64 * 64;
+    Vb = (double*)mem.alloc((size_t)(m + 1) * ldv * sizeof(double));
+    Zb = (double*)mem.alloc((size_t)m * ldv * sizeof(double));
     for (double* p : {boxval, rhs, xk, rk, wk}) IIM_HIP(hipMemsetAsync(p, 0, N * sizeof(double), stream));
-    IIM_HIP(hipMemsetAsync(Vb, 0, (size_t)(m + 1) * N * sizeof(double), stream));
-    IIM_HIP(hipMemsetAsync(Zb, 0, (size_t)m * N * sizeof(double), stream));
-    red_part = (double*)mem.alloc((size_t)(KRED + 1) * RED_BLOCKS * sizeof(double));
+    IIM_HIP(hipMemsetAsync(Vb, 0, (size_t)(m + 1) * ldv * sizeof(double), stream));
+    IIM_HIP(hipMemsetAsync(Zb, 0, (size_t)m * ldv * sizeof(double), stream));
+    red_part = (double*)mem.alloc((size_t)RED_PART_DOUBLES * sizeof(double));
+    IIM_HIP(hipMemsetAsync(red_part, 0, (size_t)RED_PART_DOUBLES * sizeof(double), stream));
     red_out = (double*)mem.alloc(4 * 64 * sizeof(double));
     IIM_HIP(hipMemsetAsync(red_out, 0, 4 * 64 * sizeof(double), stream));
     red_scale = (double*)mem.alloc(2 * sizeof(double));
@@ -396,6 +401,10 @@ void Problem::setup() {
         L.b = mem.alloc(L.box.size() * tsz);
         IIM_HIP(hipMemsetAsync(L.z, 0, L.box.size() * ssz, stream));
         IIM_HIP(hipMemsetAsync(L.b, 0, L.box.size() * tsz, stream));
+        if (dim == 2 && opt_fused) {
+            L.z2 = mem.alloc(L.box.size() * ssz);
+            IIM_HIP(hipMemsetAsync(L.z2, 0, L.box.size() * ssz, stream));
+        }
     }
     // levels small enough for the single-workgroup tail kernel
     // default: in 2D the fused LDS legs are faster than the one-workgroup tail on
@@ -471,8 +480,32 @@ GhostDev Problem::ghost_dev() const {
 void Problem::apply_box(const double* x, double* y, int with_data) {
     run_ghosts(ghost_dev(), x, cpdata, with_data, ghost, stream);
     const Level& L0 = levels[0];
-    run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ghost, boxval, w, 1.0 / (h * h),
+    run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost, boxval,
+                 w, 1.0 / (h * h),
                  opt.beta_plus, opt.beta_minus, x, y, with_data, stream);
+}
+
+// fused pre-smoothing from a zero iterate + residual + restriction on level l
+// (2D, one LDS-tiled kernel); false when it does not apply
+template <typename T, typename S>
+bool Problem::down_leg(int l) {
+    if (!opt_fused || dim != 2) return false;
+    return run_down_fused<T, S>(level_dev(l), level_dev(l + 1), (const T*)levels[l].b, (S*)levels[l].z,
+                                (T*)levels[l + 1].b, opt.nu_pre, stream);
+}
+
+// fused prolongation + post-smoothing on level l (2D, one LDS-tiled kernel
+// reading z and writing z2); returns the buffer holding the result, or nullptr
+// when it does not apply
+template <typename T, typename S>
+const S* Problem::up_leg(int l, const S* zres) {
+    if (!opt_fused || dim != 2 || !levels[l].z2) return nullptr;
+    const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+    S* z2 = (S*)levels[l].z2;
+    return run_up_fused<T, S>(level_dev(l), level_dev(l + 1), mode, zres, (const T*)levels[l].b,
+                              (const S*)levels[l].z, z2, opt.nu_post, stream)
+               ? z2
+               : nullptr;
 }
 
 template <typename T, typename S>
@@ -483,10 +516,10 @@ void Problem::vcycle_t(const double* v, double* out) {
     run_absmax(v, box.size(), red_part, red_scale, stream);
     run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
     for (int l = 0; l < t; ++l) {
+        if (down_leg<T, S>(l)) continue;
         LevelDev D = level_dev(l), C = level_dev(l + 1);
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
-        if (opt_fused && run_down_fused<T, S>(D, C, b, z, (T*)levels[l + 1].b, opt.nu_pre, stream)) continue;
         run_zero<S>(z, levels[l].box.size(), stream);
         for (int s = 0; s < opt.nu_pre; ++s) {
             run_rbgs<T, S>(D, 0, z, b, stream);
@@ -496,19 +529,24 @@ void Problem::vcycle_t(const double* v, double* out) {
     }
     run_tail<T, S>(dim, d_tail, stream);  // levels t..nl-1, coarse solve included
     const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+    const S* zres = (const S*)levels[t].z;  // result of the level below the current one
     for (int l = t - 1; l >= 0; --l) {
+        if (const S* r = up_leg<T, S>(l, zres)) {
+            zres = r;
+            continue;
+        }
         LevelDev D = level_dev(l), C = level_dev(l + 1);
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
-        if (opt_fused && run_up_fused<T, S>(D, C, mode, (const S*)levels[l + 1].z, b, z, opt.nu_post, stream)) continue;
-        run_prolong<T, S>(D, C, mode, (const S*)levels[l + 1].z, z, stream);
+        run_prolong<T, S>(D, C, mode, zres, z, stream);
         for (int s = 0; s < opt.nu_post; ++s) {
             run_rbgs<T, S>(D, 0, z, b, stream);
             run_rbgs<T, S>(D, 1, z, b, stream);
         }
+        zres = z;
     }
     (void)nl;
-    run_cast_out<S>(D0, (const S*)levels[0].z, red_scale + 1, out, stream);
+    run_cast_out<S>(D0, zres, red_scale + 1, out, stream);
 }
 
 void Problem::vcycle(const double* v, double* out) {
@@ -525,16 +563,16 @@ void Problem::vcycle(const double* v, double* out) {
 // pinned host memory.  Pointers are fixed per j, so it can be captured.
 void Problem::iteration_body(int j, hipEvent_t* evs) {
     const int64_t N = box.size();
-    double* vj = Vb + (size_t)j * N;
-    double* zj = Zb + (size_t)j * N;
+    double* vj = Vb + (size_t)j * ldv;
+    double* zj = Zb + (size_t)j * ldv;
     vcycle(vj, zj);
     if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
     apply_box(zj, wk, 0);
     if (evs) IIM_HIP(hipEventRecord(evs[2], stream));
-    run_multidot(Vb, N, j + 1, wk, N, red_part, red_out, stream);
-    run_update_dot(Vb, N, j + 1, red_out, wk, N, j + 1, 0, red_part, red_out + 64, stream);
-    run_update_dot(Vb, N, j + 1, red_out + 64, wk, N, 0, 1, red_part, red_out + 128, stream);
-    run_normalize(wk, red_out + 128, Vb + (size_t)(j + 1) * N, N, stream);
+    run_multidot(Vb, ldv, j + 1, wk, N, red_part, red_out, stream);
+    run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 0, red_part, red_out + 64, stream);
+    run_update_dot(Vb, ldv, j + 1, red_out + 64, wk, N, 0, 1, red_part, red_out + 128, stream);
+    run_normalize(wk, red_out + 128, Vb + (size_t)(j + 1) * ldv, N, stream);
     IIM_HIP(hipMemcpyAsync(hpin, red_out, 3 * 64 * sizeof(double), hipMemcpyDeviceToHost, stream));
 }
 
@@ -658,7 +696,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
                 y[i] = acc / H[i * m + i];
             }
             IIM_HIP(hipMemcpyAsync(red_out + 192, y.data(), k * sizeof(double), hipMemcpyHostToDevice, stream));
-            run_axpy_multi(Zb, N, k, red_out + 192, xk, N, stream);
+            run_axpy_multi(Zb, ldv, k, red_out + 192, xk, N, stream);
         }
     }
     if (u_full) run_box_to_full(dim, grid.n, box, xk, levels[0].labels, std::nan(""), u_full, stream);
@@ -750,7 +788,8 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     const int64_t N0 = dims[0] * dims[1] * dims[2];
     // per node of level 0: labels, HO and SW irregular indices, 5 work vectors,
     // the Krylov bases V (m+1) and Z (m), the V-cycle iterate and right-hand side
-    int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8 + ssz + tsz);
+    const int64_t zbufs = (dim == 2 && o.fused_smoothing) ? 2 : 1;  // second iterate buffer of the fused 2D legs
+    int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8 + zbufs * ssz + tsz) + (2 * m + 1) * 64 * 8;
     // setup transients alive together: flags, one selection output per axis and
     // the selection workspace
     bytes += N0 * (1 + 4 * dim) + (N0 / 64 + (1 << 20));
@@ -762,7 +801,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
         n = (n + 1) / 2;
         for (int d = 0; d < dim; ++d) cd[d] = (cd[d] - 4) / 2 + 1 + 2 + 2;
         last = cd[0] * cd[1] * cd[2];
-        bytes += last * (1 + 4 + ssz + tsz);
+        bytes += last * (1 + 4 + zbufs * ssz + tsz);
     }
     // coarsest dense inverse (A, FP64 and FP32 inverses, column map)
     const int64_t nc = std::min<int64_t>(last, 4096);
@@ -788,9 +827,9 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     bytes += (int64_t)std::min(256.0, ncs) * (p + 4) * (dim == 2 ? 192 : 768) * 8;
     // irregular records: high-order slots (at most w nodes per crossing and side),
     // Shortley-Weller rows in FP64 and FP32 (at most one node per crossing, all levels)
-    bytes += (int64_t)(ncs * (w * 2 * dim * 4 + 2 * (1 + 2 * dim) * 12));
+    bytes += (int64_t)(ncs * (w * (2 * dim + 1) * 4 + 2 * (1 + 2 * dim) * 12));
     // reductions and small tables
-    bytes += (int64_t)(KRED + 1) * RED_BLOCKS * 8 + 4096;
+    bytes += RED_PART_DOUBLES * 8 + 4096;
     return bytes + (4 << 20);
 }
 
@@ -872,7 +911,8 @@ void Problem::launch_kernel_t(int kernel) {
     switch (kernel) {
         case 0: {
             const Level& L0 = levels[0];
-            run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ghost, boxval, w,
+            run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost,
+                         boxval, w,
                          1.0 / (h * h), opt.beta_plus, opt.beta_minus, rk, wk, 0, stream);
             break;
         }
@@ -893,11 +933,19 @@ void Problem::launch_kernel_t(int kernel) {
             break;
         case 5: {
             int k = std::min(6, opt.restart);
-            run_update_dot(Vb, N, k, red_out + 192, wk, N, k, 0, red_part, red_out + 64, stream);
+            run_update_dot(Vb, ldv, k, red_out + 192, wk, N, k, 0, red_part, red_out + 64, stream);
             break;
         }
         case 6: vcycle(rk, wk); break;
         case 7: apply_box(rk, wk, 0); break;
+        case 8:
+        case 9: {
+            // the fused legs of level 0 (1 -> 0 reads level 1's iterate as the coarse result)
+            if (levels.size() < 2 || tail_first < 1) throw Error(IIM_E_INVALID_ARG, "no fused leg on this problem");
+            bool ok = kernel == 8 ? down_leg<T, S>(0) : up_leg<T, S>(0, (const S*)levels[1].z) != nullptr;
+            if (!ok) throw Error(IIM_E_INVALID_ARG, "no fused leg on this problem");
+            break;
+        }
         default: throw Error(IIM_E_INVALID_ARG, "unknown kernel id");
     }
 }

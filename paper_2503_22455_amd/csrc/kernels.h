@@ -84,9 +84,9 @@ struct GhostDev {
 void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
                 hipStream_t s);
 void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
-                  const int32_t* irr_index, const int32_t* slots, const double* ghost, const double* boxval,
-                  int w, double inv_h2, double beta_plus, double beta_minus, const double* x, double* y,
-                  int with_data, hipStream_t s);
+                  const int32_t* irr_index, const int32_t* slots, const int32_t* irr_nodes, int64_t nirr,
+                  const double* ghost, const double* boxval, int w, double inv_h2, double beta_plus,
+                  double beta_minus, const double* x, double* y, int with_data, hipStream_t s);
 
 // V-cycle kernels; T = arithmetic type, S = iterate storage type
 struct LevelDev {
@@ -130,8 +130,8 @@ void run_tail(int dim, const TailDev* d_tail, hipStream_t s);
 template <typename T, typename S>
 bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* bc, int nu, hipStream_t s);
 template <typename T, typename S>
-bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, S* z, int nu,
-                  hipStream_t s);
+bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, const S* z_in, S* z_out,
+                  int nu, hipStream_t s);
 
 // casts at the precision boundary: rhs0 = scale * h2 * v / beta(node); v FP64, level-0 box
 template <typename T>
@@ -155,8 +155,11 @@ void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const ui
 
 // ---- vector kernels (blas.hip) ---------------------------------------------------
 // Deterministic reductions: a fixed grid of RED_BLOCKS blocks, per-block partials
-// combined in a fixed order by a single-block second stage.
-constexpr int RED_BLOCKS = 512;
+// combined in a fixed order by a one-block second stage.
+constexpr int RED_BLOCKS = 1024;
+constexpr int KRED = 16;  // values per reduction launch
+// reduction workspace: (KRED + 1) * RED_BLOCKS partials
+constexpr int64_t RED_PART_DOUBLES = (int64_t)(KRED + 1) * RED_BLOCKS;
 constexpr int RED_THREADS = 256;
 // out[i] = <V_i, w> for i < k; V_i = V + i * ld
 void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* part, double* out,

@@ -71,36 +71,16 @@ void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int wi
 // ---------------------------------------------------------------------------
 // high-order apply: y = beta/h^2 sum_d sum_j a_|j| u~(i + j e_d)
 // ---------------------------------------------------------------------------
+// contribution of the off-centre points of an irregular node (label flag
+// F_HO_IRR): per axis and direction, grid values up to the first crossing, then
+// ghost values (or box data with extrapolation past a box face)
 template <int DIM>
-__global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, const uint8_t* __restrict__ labels,
-                                                  const int32_t* __restrict__ irr_index,
-                                                  const int32_t* __restrict__ slots, const double* __restrict__ ghost,
-                                                  const double* __restrict__ boxval, int w, double inv_h2, double bp,
-                                                  double bm, const double* __restrict__ x, double* __restrict__ y,
-                                                  int with_data) {
-    int i = clo.x + blockIdx.x * blockDim.x + threadIdx.x;
-    int j = clo.y + blockIdx.y * blockDim.y + threadIdx.y;
-    int k = DIM == 3 ? clo.z + blockIdx.z : 0;
-    if (i > chi.x || j > chi.y) return;
-    const int64_t l = b.idx(i, j, k);
-    const uint8_t lab = labels[l];
-    const uint8_t kind = lab & KIND_MASK;
-    if (kind != K_PLUS && kind != K_MINUS) {
-        y[l] = 0.0;
-        return;
-    }
-    const double beta = (kind == K_PLUS) ? bp : bm;
+__device__ inline double ho_irregular(const Box& b, int64_t l, uint8_t kind, const uint8_t* __restrict__ labels,
+                                      const int32_t* __restrict__ rec, const double* __restrict__ ghost,
+                                      const double* __restrict__ boxval, int w, const double* __restrict__ x,
+                                      int with_data) {
     const int64_t st[3] = {1, (int64_t)b.dims[0], (int64_t)b.dims[0] * b.dims[1]};
-    const double xc = x[l];
-    double acc = (double)DIM * A0 * xc;
-    if (!(lab & F_HO_IRR)) {
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-            acc += A1 * (x[l + st[d]] + x[l - st[d]]) + A2 * (x[l + 2 * st[d]] + x[l - 2 * st[d]]);
-        y[l] = beta * inv_h2 * acc;
-        return;
-    }
-    const int32_t* rec = slots + (int64_t)irr_index[l] * 2 * DIM;
+    double acc = 0.0;
     for (int d = 0; d < DIM; ++d)
         for (int t = 0; t < 2; ++t) {
             const int dir = t ? 1 : -1;
@@ -136,25 +116,212 @@ __global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, con
             }
             acc += A1 * v[0] + A2 * v[1];
         }
+    return acc;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, const uint8_t* __restrict__ labels,
+                                                  const int32_t* __restrict__ irr_index,
+                                                  const int32_t* __restrict__ slots, const double* __restrict__ ghost,
+                                                  const double* __restrict__ boxval, int w, double inv_h2, double bp,
+                                                  double bm, const double* __restrict__ x, double* __restrict__ y,
+                                                  int with_data) {
+    int i = clo.x + blockIdx.x * blockDim.x + threadIdx.x;
+    int j = clo.y + blockIdx.y * blockDim.y + threadIdx.y;
+    int k = DIM == 3 ? clo.z + blockIdx.z : 0;
+    if (i > chi.x || j > chi.y) return;
+    const int64_t l = b.idx(i, j, k);
+    const uint8_t lab = labels[l];
+    const uint8_t kind = lab & KIND_MASK;
+    if (kind != K_PLUS && kind != K_MINUS) {
+        y[l] = 0.0;
+        return;
+    }
+    const double beta = (kind == K_PLUS) ? bp : bm;
+    const int64_t st[3] = {1, (int64_t)b.dims[0], (int64_t)b.dims[0] * b.dims[1]};
+    const double xc = x[l];
+    double acc = (double)DIM * A0 * xc;
+    if (!(lab & F_HO_IRR)) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            acc += A1 * (x[l + st[d]] + x[l - st[d]]) + A2 * (x[l + 2 * st[d]] + x[l - 2 * st[d]]);
+        y[l] = beta * inv_h2 * acc;
+        return;
+    }
+    acc += ho_irregular<DIM>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, w, x,
+                             with_data);
     y[l] = beta * inv_h2 * acc;
 }
 
+// Block index -> tile index such that each XCD (blocks are dealt to the 8 XCDs
+// round robin) receives one contiguous run of tiles: neighbouring tiles then
+// share that XCD's L2.
+__device__ inline int xcd_tile(int bid, int nb) {
+    const int xcd = bid & 7, idx = bid >> 3, per = nb >> 3, rem = nb & 7;
+    return xcd * per + min(xcd, rem) + idx;
+}
+
+// 3D apply of the regular unknowns, marching along z.  A block of 64 x 4
+// threads owns a 64 x 16 tile of (x, y) columns (each thread 4 rows) and a
+// chunk of zc planes.  The z-neighbours of each column stay in a register
+// queue; the x/y neighbours of the current plane come from an LDS copy of the
+// tile with a 2-node halo.  Every load is issued at least one plane ahead of
+// its use (interior values one plane, halo values and labels three), so the
+// loads of a plane overlap the work on the previous ones.  Irregular nodes
+// are left to k_ho_irregular.
+constexpr int ZM_TX = 64, ZM_RY = 4, ZM_TY = 4 * ZM_RY, ZM_LA = 3;
+
+__global__ void __launch_bounds__(256, 4) k_ho_apply3_zm(Box b, int3 clo, int3 chi, int ntx, int nty, int zc,
+                                                      const uint8_t* __restrict__ labels, double inv_h2, double bp,
+                                                      double bm, const double* __restrict__ x,
+                                                      double* __restrict__ y) {
+    __shared__ double tile[ZM_TY + 4][ZM_TX + 4];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+    const int i0 = clo.x + tx * ZM_TX, j0 = clo.y + ty * ZM_TY;
+    const int i = i0 + lane;
+    const int zs = clo.z + tz * zc, ze = min(zs + zc - 1, chi.z);
+    const int bxh = b.lo[0] + b.dims[0] - 1, byh = b.lo[1] + b.dims[1] - 1, bzh = b.lo[2] + b.dims[2] - 1;
+    // in-box loads (the box holds the core with a 2-node margin; beyond it in x/y: 0)
+    auto ldx = [&](int ii, int jj, int kk) -> double {
+        return (ii <= bxh && jj <= byh) ? x[b.idx(ii, jj, kk)] : 0.0;
+    };
+    auto ldl = [&](int jj, int kk) -> int { return (i <= bxh && jj <= byh) ? (int)labels[b.idx(i, jj, kk)] : 0; };
+    // x-halo duty: lanes 0-3 load tile columns 0, 1, 66, 67 of the thread's rows;
+    // y-halo duty: wavefront wy loads tile row 0, 1, 18 or 19
+    const int hcol = lane < 2 ? lane : ZM_TX + lane;
+    const int hi = i0 - 2 + hcol;
+    const int hr = wy < 2 ? wy : ZM_TY + wy;
+    const int hj = j0 - 2 + hr;
+    double q[ZM_RY][6];   // planes z-2 .. z+3
+    double hx[ZM_LA][ZM_RY], hy[ZM_LA];  // planes z .. z+2
+    uint32_t lb[ZM_LA];                   // labels of the 4 rows, one byte each
+#pragma unroll
+    for (int r = 0; r < ZM_RY; ++r)
+#pragma unroll
+        for (int d = 0; d < 5; ++d) q[r][d] = ldx(i, j0 + wy + 4 * r, zs - 2 + d);
+#pragma unroll
+    for (int s = 0; s < ZM_LA; ++s) {
+        const int zz = min(zs + s, bzh);
+        lb[s] = 0;
+#pragma unroll
+        for (int r = 0; r < ZM_RY; ++r) {
+            hx[s][r] = lane < 4 ? ldx(hi, j0 + wy + 4 * r, zz) : 0.0;
+            lb[s] |= (uint32_t)ldl(j0 + wy + 4 * r, zz) << (8 * r);
+        }
+        hy[s] = ldx(i, hj, zz);
+    }
+    for (int z = zs; z <= ze; ++z) {
+        const int zp = min(z + ZM_LA, bzh);  // clamped planes are never used
+        double hxn[ZM_RY], hyn;
+        uint32_t lbn = 0;
+#pragma unroll
+        for (int r = 0; r < ZM_RY; ++r) {
+            q[r][5] = ldx(i, j0 + wy + 4 * r, zp);
+            hxn[r] = lane < 4 ? ldx(hi, j0 + wy + 4 * r, zp) : 0.0;
+            lbn |= (uint32_t)ldl(j0 + wy + 4 * r, zp) << (8 * r);
+        }
+        hyn = ldx(i, hj, zp);
+#pragma unroll
+        for (int r = 0; r < ZM_RY; ++r) {
+            tile[wy + 4 * r + 2][lane + 2] = q[r][2];
+            if (lane < 4) tile[wy + 4 * r + 2][hcol] = hx[0][r];
+        }
+        tile[hr][lane + 2] = hy[0];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ZM_RY; ++r) {
+            const int j = j0 + wy + 4 * r;
+            const uint8_t lab = (uint8_t)(lb[0] >> (8 * r));
+            const uint8_t kind = lab & KIND_MASK;
+            if (i <= chi.x && j <= chi.y && !(lab & F_HO_IRR)) {
+                const int64_t l = b.idx(i, j, z);
+                if (kind != K_PLUS && kind != K_MINUS) {
+                    y[l] = 0.0;
+                } else {
+                    const int tr = wy + 4 * r + 2, tc = lane + 2;
+                    double acc = 3.0 * A0 * q[r][2];
+                    acc += A1 * (tile[tr][tc + 1] + tile[tr][tc - 1]) + A2 * (tile[tr][tc + 2] + tile[tr][tc - 2]);
+                    acc += A1 * (tile[tr + 1][tc] + tile[tr - 1][tc]) + A2 * (tile[tr + 2][tc] + tile[tr - 2][tc]);
+                    acc += A1 * (q[r][3] + q[r][1]) + A2 * (q[r][4] + q[r][0]);
+                    y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ZM_RY; ++r) {
+#pragma unroll
+            for (int d = 0; d < 5; ++d) q[r][d] = q[r][d + 1];
+#pragma unroll
+            for (int s = 0; s < ZM_LA - 1; ++s) hx[s][r] = hx[s + 1][r];
+            hx[ZM_LA - 1][r] = hxn[r];
+        }
+#pragma unroll
+        for (int s = 0; s < ZM_LA - 1; ++s) {
+            hy[s] = hy[s + 1];
+            lb[s] = lb[s + 1];
+        }
+        hy[ZM_LA - 1] = hyn;
+        lb[ZM_LA - 1] = lbn;
+    }
+}
+
+// irregular nodes of the high-order apply, one thread each, from their list
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ho_irregular(Box b, const int32_t* __restrict__ nodes, int64_t nirr,
+                                                      const uint8_t* __restrict__ labels,
+                                                      const int32_t* __restrict__ irr_index,
+                                                      const int32_t* __restrict__ slots,
+                                                      const double* __restrict__ ghost,
+                                                      const double* __restrict__ boxval, int w, double inv_h2,
+                                                      double bp, double bm, const double* __restrict__ x,
+                                                      double* __restrict__ y, int with_data) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nirr) return;
+    const int64_t l = nodes[t];
+    const uint8_t kind = labels[l] & KIND_MASK;
+    double acc = (double)DIM * A0 * x[l];
+    acc += ho_irregular<DIM>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, w, x,
+                             with_data);
+    y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
+}
+
 void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
-                  const int32_t* irr_index, const int32_t* slots, const double* ghost, const double* boxval, int w,
-                  double inv_h2, double beta_plus, double beta_minus, const double* x, double* y, int with_data,
-                  hipStream_t s) {
+                  const int32_t* irr_index, const int32_t* slots, const int32_t* irr_nodes, int64_t nirr,
+                  const double* ghost, const double* boxval, int w, double inv_h2, double beta_plus,
+                  double beta_minus, const double* x, double* y, int with_data, hipStream_t s) {
     int3 lo = make_int3(core_lo[0], core_lo[1], core_lo[2]);
     int3 hi = make_int3(core_hi[0], core_hi[1], core_hi[2]);
     int nx = hi.x - lo.x + 1, ny = hi.y - lo.y + 1, nz = hi.z - lo.z + 1;
     if (nx <= 0 || ny <= 0 || nz <= 0) return;
+    if (dim == 3) {
+        // the z-march reads planes zs-2 .. ze+2 and columns/rows up to 2 past the
+        // core: the storage box has that margin
+        for (int d = 0; d < 3; ++d)
+            if (core_lo[d] - 2 < b.lo[d] || core_hi[d] + 2 > b.lo[d] + b.dims[d] - 1)
+                throw Error(IIM_E_INTERNAL, "apply: storage box lacks the 2-node margin");
+        const int ntx = cdiv(nx, ZM_TX), nty = cdiv(ny, ZM_TY);
+        const int64_t cols = (int64_t)ntx * nty;
+        // chunks of 8..16 planes, shorter when the tiles are too few to fill the device
+        int zc = (int)std::max<int64_t>(8, std::min<int64_t>(16, cols * nz / 2048));
+        const int nzc = cdiv(nz, zc);
+        const int64_t nb = cols * nzc;
+        hipLaunchKernelGGL(k_ho_apply3_zm, dim3((unsigned)nb), dim3(256), 0, s, b, lo, hi, ntx, nty, zc, labels,
+                           inv_h2, beta_plus, beta_minus, x, y);
+        IIM_LAUNCH_CHECK();
+        if (nirr > 0) {
+            hipLaunchKernelGGL(k_ho_irregular<3>, dim3(cdiv(nirr, 256)), dim3(256), 0, s, b, irr_nodes, nirr, labels,
+                               irr_index, slots, ghost, boxval, w, inv_h2, beta_plus, beta_minus, x, y, with_data);
+            IIM_LAUNCH_CHECK();
+        }
+        return;
+    }
     dim3 blk(64, 4, 1);
-    dim3 grd(cdiv(nx, 64), cdiv(ny, 4), dim == 3 ? nz : 1);
-    if (dim == 2)
-        hipLaunchKernelGGL(k_ho_apply<2>, grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval, w, inv_h2,
-                           beta_plus, beta_minus, x, y, with_data);
-    else
-        hipLaunchKernelGGL(k_ho_apply<3>, grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval, w, inv_h2,
-                           beta_plus, beta_minus, x, y, with_data);
+    dim3 grd(cdiv(nx, 64), cdiv(ny, 4), 1);
+    hipLaunchKernelGGL(k_ho_apply<2>, grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval, w, inv_h2,
+                       beta_plus, beta_minus, x, y, with_data);
     IIM_LAUNCH_CHECK();
 }
 
@@ -246,33 +413,33 @@ __device__ inline void restrict_node(const LevelDev& F, const LevelDev& C, int I
     bc[lc] = (T)4 * acc;
 }
 
-// z_f += P z_c at a fine unknown; mode 0 = (bi/tri)linear, 1 = average of in-domain parents
+// (P z_c)(i, j, k) at a fine unknown; mode 0 = (bi/tri)linear, 1 = average of
+// in-domain parents.  Returns false when no parent contributes.
 template <typename T, typename S, int DIM>
-__device__ inline void prolong_node(const LevelDev& F, const LevelDev& C, int i, int j, int k, int mode, const S* zc,
-                                    S* z) {
-    int64_t l = F.box.idx(i, j, k);
-    if (!is_unknown(F.labels[l])) return;
-    int f[3] = {i, j, k};
-    int lo[3], nb[3];
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = f[d] >> 1;  // floor for non-negative indices
-        nb[d] = (d < DIM && (f[d] & 1)) ? 2 : 1;
-    }
+__device__ inline bool prolong_corr(const LevelDev& C, int i, int j, int k, int mode, const S* zc, T* corr) {
+    // parents: floor(f/2) and, along axes where f is odd, floor(f/2) + 1
+    const int li = i >> 1, lj = j >> 1, lk = k >> 1;
+    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (DIM == 3 && (k & 1)) ? 2 : 1;
     T sum = 0;
     int cnt = 0;
-    for (int a = 0; a < nb[0]; ++a)
-        for (int bq = 0; bq < nb[1]; ++bq)
-            for (int cq = 0; cq < nb[2]; ++cq) {
-                int P[3] = {lo[0] + a, lo[1] + bq, lo[2] + cq};
-                bool inb = true;
-                for (int d = 0; d < 3; ++d) inb = inb && P[d] >= C.box.lo[d] && P[d] < C.box.lo[d] + C.box.dims[d];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+            for (int cq = 0; cq < (DIM == 3 ? 2 : 1); ++cq) {
+                if (a >= ni || bq >= nj || cq >= nk) continue;
+                const int P0 = li + a, P1 = lj + bq, P2 = lk + cq;
+                const bool inb = P0 >= C.box.lo[0] && P0 < C.box.lo[0] + C.box.dims[0] && P1 >= C.box.lo[1] &&
+                                 P1 < C.box.lo[1] + C.box.dims[1] && P2 >= C.box.lo[2] &&
+                                 P2 < C.box.lo[2] + C.box.dims[2];
                 T v = 0;
                 bool use = mode == 0;
                 if (inb) {
-                    int64_t lp = C.box.idx(P[0], P[1], P[2]);
+                    const int64_t lp = C.box.idx(P0, P1, P2);
                     v = load_it<T, S>(zc, lp);
                     if (mode == 1) {
-                        uint8_t kk = C.labels[lp] & KIND_MASK;
+                        const uint8_t kk = C.labels[lp] & KIND_MASK;
                         use = kk == K_PLUS || kk == K_MINUS || kk == K_BOX;
                     }
                 } else if (mode == 1) {
@@ -283,10 +450,19 @@ __device__ inline void prolong_node(const LevelDev& F, const LevelDev& C, int i,
                     cnt += 1;
                 }
             }
-    if (cnt > 0) {
-        T corr = sum / (T)cnt;
-        store_t<T, S>(z, l, load_it<T, S>(z, l) + corr);
-    }
+    if (cnt == 0) return false;
+    *corr = sum / (T)cnt;
+    return true;
+}
+
+// z_f += P z_c at a fine unknown
+template <typename T, typename S, int DIM>
+__device__ inline void prolong_node(const LevelDev& F, const LevelDev& C, int i, int j, int k, int mode, const S* zc,
+                                    S* z) {
+    int64_t l = F.box.idx(i, j, k);
+    if (!is_unknown(F.labels[l])) return;
+    T corr;
+    if (prolong_corr<T, S, DIM>(C, i, j, k, mode, zc, &corr)) store_t<T, S>(z, l, load_it<T, S>(z, l) + corr);
 }
 
 template <typename T, typename S>
@@ -629,15 +805,18 @@ __global__ void __launch_bounds__(FTHREADS) k_down_2d(LevelDev F, LevelDev C, co
     }
 }
 
-// up leg: z += P zc, then nh half-sweeps (red first), write z
+// up leg: z_out = smoothed (z_in + P zc), nh half-sweeps (red first).  z_in and
+// z_out are distinct: a tile's halo is read from z_in while neighbouring tiles
+// write their results, so the result does not depend on block timing.
 template <typename T, typename S>
 __global__ void __launch_bounds__(FTHREADS) k_up_2d(LevelDev F, LevelDev C, int mode, const S* __restrict__ zc,
-                                                    const T* __restrict__ b, S* __restrict__ z, int nh) {
+                                                    const T* __restrict__ b, const S* __restrict__ z_in,
+                                                    S* __restrict__ z, int nh) {
     __shared__ FusedLDS<T> Sh;
     __shared__ T cz[FCY][FCX];
     __shared__ uint8_t cl[FCY][FCX];
     const int x0 = F.core_lo[0] + blockIdx.x * FTX, y0 = F.core_lo[1] + blockIdx.y * FTY;
-    lds_load<T, S>(F, x0, y0, z, b, Sh);
+    lds_load<T, S>(F, x0, y0, z_in, b, Sh);
     lds_prolong<T, S>(F, C, mode, zc, x0, y0, Sh, cz, cl);
     __syncthreads();
     for (int h2 = 0; h2 < nh; ++h2) {
@@ -659,13 +838,14 @@ bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* b
 }
 
 template <typename T, typename S>
-bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, S* z, int nu,
-                  hipStream_t s) {
+bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, const S* z_in, S* z_out,
+                  int nu, hipStream_t s) {
     if (F.dim != 2 || 2 * nu > FHALO - 2) return false;
+    if ((const void*)z_in == (const void*)z_out) throw Error(IIM_E_INTERNAL, "fused up leg needs distinct buffers");
     const int nx = F.core_hi[0] - F.core_lo[0] + 1, ny = F.core_hi[1] - F.core_lo[1] + 1;
     if (nx <= 0 || ny <= 0) return false;
     hipLaunchKernelGGL((k_up_2d<T, S>), dim3(cdiv(nx, FTX), cdiv(ny, FTY)), dim3(FTHREADS), 0, s, F, C, mode, zc, b,
-                       z, 2 * nu);
+                       z_in, z_out, 2 * nu);
     IIM_LAUNCH_CHECK();
     return true;
 }
@@ -859,7 +1039,7 @@ void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const ui
                                          hipStream_t);                                                    \
     template void run_tail<T, S>(int, const TailDev*, hipStream_t);                                       \
     template bool run_down_fused<T, S>(const LevelDev&, const LevelDev&, const T*, S*, T*, int, hipStream_t); \
-    template bool run_up_fused<T, S>(const LevelDev&, const LevelDev&, int, const S*, const T*, S*, int,    \
+    template bool run_up_fused<T, S>(const LevelDev&, const LevelDev&, int, const S*, const T*, const S*, S*, int, \
                                      hipStream_t);
 INST_TS(double, double)
 INST_TS(float, float)

@@ -163,3 +163,26 @@ def test_fused_and_tail_kernels_match_unfused(prec, tol, tail):
     assert np.abs(z1 - z0).max() <= tol * np.abs(z0).max()
     ref.close()
     G.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed32", 1e-6)])
+def test_fused_legs_on_a_grid_larger_than_the_device(prec, tol):
+    """At 1024^2 the fused legs launch more tiles than the device holds at
+    once; the up leg reads its halo from a buffer no tile writes, so the cycle
+    still equals the unfused one, and two cycles are bitwise identical."""
+    wl = W.cfg2_star(1024)
+    G = gpu_for(wl, precision=prec, fused_smoothing=True)
+    lab = G.node_labels()
+    unk = (lab == 1) | (lab == 2)
+    rng = np.random.default_rng(11)
+    v = np.zeros(lab.size)
+    v[unk] = rng.standard_normal(int(unk.sum()))
+    vt = torch.tensor(v, device="cuda")
+    z1 = G.vcycle(vt).cpu().numpy()
+    z2 = G.vcycle(vt).cpu().numpy()
+    assert np.array_equal(z1, z2)
+    ref = gpu_for(wl, precision=prec, fused_smoothing=False, tail_nodes=-1)
+    z0 = ref.vcycle(vt).cpu().numpy()
+    assert np.abs(z1 - z0).max() <= tol * np.abs(z0).max()
+    ref.close()
+    G.close()

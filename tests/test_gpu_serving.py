@@ -21,6 +21,9 @@ def _cases():
         "circle64-dir": W.cfg1_circle(64),
         "circle75-dir": W.cfg1_circle(75),
         "sphere24-dir": dataclasses.replace(W.cfg3_sphere(24), precision="fp64"),
+        # smallest request of the serving mix: kappa h = 0.21, close to the 1/4 limit
+        "sphere32-r03": W.Workload("sphere32_r03", 3, 32, W.GEOM_SPHERE, [0.05, -0.1, 0.08, 0.3], W.SIDE_INTERIOR,
+                                   W.BC_DIRICHLET, exact=W.ms_sin_pi_3d(), precision="fp64"),
         "spheres32-neu": dataclasses.replace(W.cfg4_spheres(32, spheres=W.small_spheres_union()),
                                              exact=W.ms_sin_pi_3d(), precision="fp64"),
         "star128-jump": dataclasses.replace(W.cfg2_star(128, beta_plus=1.0, beta_minus=10.0),
