@@ -43,6 +43,34 @@ DESCR = {
     "cfg4": "3D Neumann on 16 spheres (seed 0), Dirichlet box, 384^3, u=cos(2x)sinh(y)+z^2",
 }
 HBM_PEAK_GBS = 8000.0
+
+# Bytes beyond L2 per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch; `python3 bench.py --probe-kernel 5`), each
+# scaled by what the same counter reads for a plain copy of 2^26 doubles
+# (512 MiB each way: FETCH_SIZE reads 262158.9 KiB, WRITE_SIZE 524288 KiB).
+# Keyed by workload and kernel id; valid only while the kernel's source text
+# hashes to `sha` (otherwise the roofline reports traffic null).
+TRAFFIC = {
+    ("cfg2", 5): {"fetch_kib": 28913.6875, "fetch_scale": 524288.0 / 262158.9, "write_kib": 8432.09375,
+                  "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/blas.hip",
+                  "begin": "__global__ void __launch_bounds__(RED_THREADS) k_update_dot(",
+                  "end": "void run_update_dot_stage1(", "sha": "b443d0108009ce3b"},
+}
+
+
+def kernel_source_sha(entry):
+    import hashlib
+    text = open(os.path.join(ROOT, entry["src"])).read()
+    a = text.index(entry["begin"])
+    b = text.index(entry["end"], a)
+    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
+
+
+def measured_traffic(workload, kid):
+    e = TRAFFIC.get((workload, kid))
+    if e is None or e["sha"] is None or kernel_source_sha(e) != e["sha"]:
+        return None
+    return e["fetch_kib"] * 1024.0 * e["fetch_scale"] + e["write_kib"] * 1024.0 * e["write_scale"]
 # kernel id -> (name, launches per FGMRES iteration factor computed below)
 KERNELS = {0: "ho_apply", 1: "ghosts", 2: "rbgs_level0", 3: "resid_restrict_0_1", 4: "prolong_1_0", 5: "cgs_update_dot_k6"}
 
@@ -232,6 +260,27 @@ def serving_main(args):
     print(json.dumps(out))
 
 
+def counter_probe(args):
+    """Launches for hardware-counter runs (rocprofv3 --pmc): the workload's
+    kernel `--probe-kernel` (iim_time_kernel id) `--probe-reps` times in its
+    bench configuration, then a plain device copy of 2^26 doubles three times as
+    the known-size reference for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    torch.cuda.set_device(0)
+    from paper_2503_22455_amd import iim
+    wl = WORKLOADS[args.workload]()
+    P = iim.from_workload(wl, precision=args.precision or wl.precision)
+    P.time_kernel(args.probe_kernel, args.probe_reps)
+    P.close()
+    x = torch.rand(1 << 26, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": args.workload, "kernel": args.probe_kernel, "reps": args.probe_reps + 1,
+                      "copy_bytes_each_way": 8 << 26}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +296,9 @@ def main():
     ap.add_argument("--serve-capacity-count", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--probe-kernel", type=int, default=None,
+                    help="counter-probe mode: launch this kernel id and a reference copy, nothing else")
+    ap.add_argument("--probe-reps", type=int, default=10)
     ap.add_argument("--serve-short", type=int, default=48,
                     help="requests of the short saturated serving run in the default line (0: none)")
     args = ap.parse_args()
@@ -256,6 +308,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serving_main(args)
+        return
+    if args.probe_kernel is not None:
+        counter_probe(args)
         return
     import torch
     torch.cuda.set_device(0)
@@ -310,8 +365,10 @@ def main():
     dom = max(kr, key=lambda k: kr[k][1] * launches[k])
     name, ms, algo_bytes = kr[dom]
     achieved = algo_bytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic), "kernel": name,
                 "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(algo_bytes)}
     kernels = {kr[k][0]: {"avg_us": round(kr[k][1] * 1e3, 2),
                           "GBs": round(kr[k][2] / (kr[k][1] * 1e-3) / 1e9, 1)} for k in kr}

@@ -220,10 +220,12 @@ int iim_level_op(iim_problem* p, int32_t level, int32_t op, const double* in1, d
  * its production launch configuration on the handle's stream, bracketed by two
  * HIP events on that stream, and returns the average duration per launch in
  * *avg_ms.  The operands are the handle's own work vectors (contents are
- * overwritten).  kernel: 0 = high-order stencil apply (level 0),
- * 1 = ghost values, 2 = one red-black sweep on level 0 (both colours),
+ * overwritten).  kernel: 0 = high-order stencil apply kernel (level 0; in 3D
+ * the regular nodes, 11 = the 3D irregular-node kernel), 1 = ghost values,
+ * 2 = one red-black sweep on level 0 (both colours, two launches),
  * 3 = residual + restriction 0 -> 1, 4 = prolongation 1 -> 0,
- * 5 = fused orthogonalisation update + dots over 6 basis vectors,
+ * 5 = orthogonalisation update + dots over 6 basis vectors (the streaming
+ * first stage; the one-block second stage is not included),
  * 6 = one whole V-cycle, 7 = one whole operator apply (ghosts + stencil),
  * 8 = fused pre-smoothing + residual + restriction leg 0 -> 1 and
  * 9 = fused prolongation + post-smoothing leg 1 -> 0 (the LDS-tiled legs the

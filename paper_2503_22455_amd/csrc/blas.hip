@@ -173,6 +173,16 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_dot(const double* V, int
     block_reduce_store(outv, k2 + (with_norm ? 1 : 0), part, 0);
 }
 
+void run_update_dot_stage1(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
+                           int with_norm, double* part, hipStream_t s) {
+    if (k > KCH || k2 > KCH) throw Error(IIM_E_INVALID_ARG, "update_dot: too many vectors");
+    check_vec(V, ld);
+    check_vec(w, 0);
+    hipLaunchKernelGGL(k_update_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, n, k2, with_norm,
+                       part);
+    IIM_LAUNCH_CHECK();
+}
+
 void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
                     int with_norm, double* part, double* out, hipStream_t s) {
     if (k > KCH || k2 > KCH) throw Error(IIM_E_INVALID_ARG, "update_dot: too many vectors");

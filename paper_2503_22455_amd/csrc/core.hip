@@ -909,11 +909,12 @@ template <typename T, typename S>
 void Problem::launch_kernel_t(int kernel) {
     const int64_t N = box.size();
     switch (kernel) {
-        case 0: {
+        case 0:
+        case 11: {
             const Level& L0 = levels[0];
             run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost,
-                         boxval, w,
-                         1.0 / (h * h), opt.beta_plus, opt.beta_minus, rk, wk, 0, stream);
+                         boxval, w, 1.0 / (h * h), opt.beta_plus, opt.beta_minus, rk, wk, 0, stream,
+                         kernel == 0 ? 1 : 2);
             break;
         }
         case 1: run_ghosts(ghost_dev(), rk, cpdata, 0, ghost, stream); break;
@@ -933,7 +934,7 @@ void Problem::launch_kernel_t(int kernel) {
             break;
         case 5: {
             int k = std::min(6, opt.restart);
-            run_update_dot(Vb, ldv, k, red_out + 192, wk, N, k, 0, red_part, red_out + 64, stream);
+            run_update_dot_stage1(Vb, ldv, k, red_out + 192, wk, N, k, 0, red_part, stream);
             break;
         }
         case 6: vcycle(rk, wk); break;

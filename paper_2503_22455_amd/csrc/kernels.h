@@ -83,10 +83,11 @@ struct GhostDev {
 };
 void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
                 hipStream_t s);
+// part: 0 = the whole apply, 1 = the stencil kernel alone, 2 = the 3D irregular-node kernel alone
 void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
                   const int32_t* irr_index, const int32_t* slots, const int32_t* irr_nodes, int64_t nirr,
                   const double* ghost, const double* boxval, int w, double inv_h2, double beta_plus,
-                  double beta_minus, const double* x, double* y, int with_data, hipStream_t s);
+                  double beta_minus, const double* x, double* y, int with_data, hipStream_t s, int part = 0);
 
 // V-cycle kernels; T = arithmetic type, S = iterate storage type
 struct LevelDev {
@@ -167,6 +168,9 @@ void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n
 // w -= sum_{i<k} h[i] V_i; then out[i] = <V_i, w> for i < k2 and out[k2] = <w, w> (if with_norm)
 void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
                     int with_norm, double* part, double* out, hipStream_t s);
+// the streaming first stage of run_update_dot alone (block partials in part)
+void run_update_dot_stage1(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
+                           int with_norm, double* part, hipStream_t s);
 // y = x / sqrt(*nrm2)
 void run_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
 // x += sum_{i<k} y[i] Z_i  (y on the device)

@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(256) k_ho_irregular(Box b, const int32_t* __re
 void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
                   const int32_t* irr_index, const int32_t* slots, const int32_t* irr_nodes, int64_t nirr,
                   const double* ghost, const double* boxval, int w, double inv_h2, double beta_plus,
-                  double beta_minus, const double* x, double* y, int with_data, hipStream_t s) {
+                  double beta_minus, const double* x, double* y, int with_data, hipStream_t s, int part) {
     int3 lo = make_int3(core_lo[0], core_lo[1], core_lo[2]);
     int3 hi = make_int3(core_hi[0], core_hi[1], core_hi[2]);
     int nx = hi.x - lo.x + 1, ny = hi.y - lo.y + 1, nz = hi.z - lo.z + 1;
@@ -308,16 +308,19 @@ void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi,
         int zc = (int)std::max<int64_t>(8, std::min<int64_t>(16, cols * nz / 2048));
         const int nzc = cdiv(nz, zc);
         const int64_t nb = cols * nzc;
-        hipLaunchKernelGGL(k_ho_apply3_zm, dim3((unsigned)nb), dim3(256), 0, s, b, lo, hi, ntx, nty, zc, labels,
-                           inv_h2, beta_plus, beta_minus, x, y);
-        IIM_LAUNCH_CHECK();
-        if (nirr > 0) {
+        if (part != 2) {
+            hipLaunchKernelGGL(k_ho_apply3_zm, dim3((unsigned)nb), dim3(256), 0, s, b, lo, hi, ntx, nty, zc, labels,
+                               inv_h2, beta_plus, beta_minus, x, y);
+            IIM_LAUNCH_CHECK();
+        }
+        if (nirr > 0 && part != 1) {
             hipLaunchKernelGGL(k_ho_irregular<3>, dim3(cdiv(nirr, 256)), dim3(256), 0, s, b, irr_nodes, nirr, labels,
                                irr_index, slots, ghost, boxval, w, inv_h2, beta_plus, beta_minus, x, y, with_data);
             IIM_LAUNCH_CHECK();
         }
         return;
     }
+    if (part == 2) return;  // 2D: irregular nodes are inside the one stencil kernel
     dim3 blk(64, 4, 1);
     dim3 grd(cdiv(nx, 64), cdiv(ny, 4), 1);
     hipLaunchKernelGGL(k_ho_apply<2>, grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval, w, inv_h2,
