@@ -153,7 +153,10 @@ int iim_default_options(iim_options* opt);
 int iim_create(const iim_grid* grid, const iim_geometry* geom, const iim_options* opt,
                void* stream, iim_problem** out);
 
-/* Releases all device memory of the handle (NULL is ignored). */
+/* Releases all device memory of the handle (NULL is ignored).  Device memory
+ * comes from the device's default stream-ordered memory pool; freed blocks stay
+ * cached in that pool for later handles of the process (iim_server_destroy
+ * hands unused blocks back to the device). */
 void iim_destroy(iim_problem* p);
 
 /* Thread-local message of the last failing call ("" if none). */

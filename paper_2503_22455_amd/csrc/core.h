@@ -106,9 +106,6 @@ struct Problem {
     double t_setup_ms = 0.0;
 
     void setup();
-    void build_level_labels(Level& L, int pad);
-    int64_t select(const uint8_t* flags, int64_t n, int32_t* out);
-    void check_err(int* d_err, const char* what);
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;
     void apply_box(const double* x, double* y, int with_data);

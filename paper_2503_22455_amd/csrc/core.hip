@@ -100,127 +100,133 @@ static Box make_box(int dim, const int* mn, const int* mx, int pad, bool empty) 
     return b;
 }
 
-// classify a level's full grid and build its storage box and labels
-void Problem::build_level_labels(Level& L, int pad) {
-    int* d_bbox = (int*)mem.alloc(8 * sizeof(int));
-    int h_init[8] = {1 << 30, 1 << 30, 1 << 30, -(1 << 30), -(1 << 30), -(1 << 30), 0, 0};
-    IIM_HIP(hipMemcpyAsync(d_bbox, h_init, sizeof(h_init), hipMemcpyHostToDevice, stream));
-    unsigned long long* d_cnt = (unsigned long long*)mem.alloc(sizeof(unsigned long long));
-    IIM_HIP(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), stream));
-    run_classify_bbox(L.geom, d_bbox, d_bbox + 6, d_cnt, stream);
-    int h_bbox[8];
-    unsigned long long cnt = 0;
-    IIM_HIP(hipMemcpyAsync(h_bbox, d_bbox, sizeof(h_bbox), hipMemcpyDeviceToHost, stream));
-    IIM_HIP(hipMemcpyAsync(&cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, stream));
-    IIM_HIP(hipStreamSynchronize(stream));
-    mem.release(d_bbox);
-    mem.release(d_cnt);
-    if (h_bbox[6]) throw Error(IIM_E_GEOMETRY_UNRESOLVED, "the immersed body touches the domain box");
-    L.nunk = (int64_t)cnt;
-    bool empty = cnt == 0;
-    int mn[3] = {h_bbox[0], h_bbox[1], dim == 3 ? h_bbox[2] : 0};
-    int mx[3] = {h_bbox[3], h_bbox[4], dim == 3 ? h_bbox[5] : 0};
-    L.box = make_box(dim, mn, mx, pad, empty);
-    for (int d = 0; d < 3; ++d) {
-        L.core_lo[d] = empty ? 1 : (d < dim ? mn[d] : 0);
-        L.core_hi[d] = empty ? 0 : (d < dim ? mx[d] : 0);
-    }
-    if (L.box.size() > (int64_t)INT32_MAX) throw Error(IIM_E_BUDGET, "storage box exceeds 2^31 nodes");
-    L.labels = (uint8_t*)mem.alloc(L.box.size());
-    run_box_labels(L.geom, L.box, L.labels, stream);
+// Throws if any error bit is set in the host copy of the device error word.
+static void raise_setup_error(int h, const char* what) {
+    if (!h) return;
+    std::string m = std::string(what) + " failed (code " + std::to_string(h) + ")";
+    if (h & 2) m += ": |kappa h| >= 1/4 at a control point";
+    if (h & (4 | 8)) m += ": irregular node without its crossing";
+    if (h & 32) m += ": least-squares set exceeds its capacity";
+    if (h & 128) m += ": least-squares fit rank deficient after growth";
+    if (h & 16) m += ": singular coarse-level matrix";
+    throw Error(IIM_E_GEOMETRY_UNRESOLVED, m);
 }
 
-// flagged-node selection with a temporary buffer
-int64_t Problem::select(const uint8_t* flags, int64_t n, int32_t* out) {
-    size_t tb = select_tmp_bytes(n);
-    void* tmp = mem.alloc(tb);
-    int64_t* d_count = (int64_t*)mem.alloc(sizeof(int64_t));
-    int64_t c = select_flagged(flags, n, out, tmp, tb, d_count, stream);
-    mem.release(tmp);
-    mem.release(d_count);
-    return c;
-}
-
-void Problem::check_err(int* d_err, const char* what) {
-    int h = 0;
-    IIM_HIP(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, stream));
-    IIM_HIP(hipStreamSynchronize(stream));
-    if (h) {
-        std::string m = std::string(what) + " failed (code " + std::to_string(h) + ")";
-        if (h & 2) m += ": |kappa h| >= 1/4 at a control point";
-        if (h & 32) m += ": least-squares set exceeds its capacity";
-        if (h & 128) m += ": least-squares fit rank deficient after growth";
-        if (h & 16) m += ": singular coarse-level matrix";
-        throw Error(IIM_E_GEOMETRY_UNRESOLVED, m);
-    }
-}
-
+// Setup on the device.  The stages are batched so that the host waits for the
+// device only where a size or an error decides what comes next (six waits):
+// level bounding boxes; control-point counts; least-squares set sizes;
+// irregular-node counts of every level; the coarsest level's rows; the end.
 void Problem::setup() {
     const double t0 = now_ms();
     w = opt.order_n / 2;
     h = (grid.hi - grid.lo) / grid.n;
     nsides = (side == IIM_SIDE_INTERFACE) ? 2 : 1;
+    // small device scalars: [0] error bits, [1..] counts written by selections
+    constexpr int NSC = 64;
+    int64_t* d_sc = (int64_t*)mem.alloc(NSC * sizeof(int64_t));
+    IIM_HIP(hipMemsetAsync(d_sc, 0, NSC * sizeof(int64_t), stream));
+    int* d_err = (int*)d_sc;
+    int64_t h_sc[NSC];
+    auto read_sc = [&](int count) {
+        IIM_HIP(hipMemcpyAsync(h_sc, d_sc, count * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+    };
+    auto err_bits = [&]() { return (int)(h_sc[0] & 0xffffffff); };
     d_params = (double*)mem.alloc(params.size() * sizeof(double));
     IIM_HIP(hipMemcpyAsync(d_params, params.data(), params.size() * sizeof(double), hipMemcpyHostToDevice, stream));
-    int* d_err = (int*)mem.alloc(sizeof(int));
-    IIM_HIP(hipMemsetAsync(d_err, 0, sizeof(int), stream));
 
-    // ---- levels and their labels
+    // ---- levels: bounding boxes of the unknowns of every level at once  [wait 1]
     std::vector<int> sizes{grid.n};
     while (sizes.back() > opt.coarsest_n) sizes.push_back((sizes.back() + 1) / 2);
-    levels.resize(sizes.size());
-    for (size_t l = 0; l < sizes.size(); ++l) {
-        Level& L = levels[l];
-        L.n = sizes[l];
-        L.h = h * (double)(1 << l);
-        L.geom = Geom{kind, side, dim, L.n, grid.lo, L.h, d_params};
-        build_level_labels(L, l == 0 ? 2 : 1);
+    const int nl = (int)sizes.size();
+    if (nl > MAX_LEVELS || nl + 8 > NSC) throw Error(IIM_E_INVALID_ARG, "too many multigrid levels");
+    levels.resize(nl);
+    {
+        std::vector<int> h_bb(8 * nl);
+        for (int l = 0; l < nl; ++l) {
+            const int init[8] = {1 << 30, 1 << 30, 1 << 30, -(1 << 30), -(1 << 30), -(1 << 30), 0, 0};
+            std::copy(init, init + 8, h_bb.begin() + 8 * l);
+        }
+        int* d_bb = (int*)mem.alloc(8 * nl * sizeof(int));
+        unsigned long long* d_cnt = (unsigned long long*)mem.alloc(nl * sizeof(unsigned long long));
+        IIM_HIP(hipMemcpyAsync(d_bb, h_bb.data(), 8 * nl * sizeof(int), hipMemcpyHostToDevice, stream));
+        IIM_HIP(hipMemsetAsync(d_cnt, 0, nl * sizeof(unsigned long long), stream));
+        for (int l = 0; l < nl; ++l) {
+            Level& L = levels[l];
+            L.n = sizes[l];
+            L.h = h * (double)(1 << l);
+            L.geom = Geom{kind, side, dim, L.n, grid.lo, L.h, d_params};
+            run_classify_bbox(L.geom, d_bb + 8 * l, d_bb + 8 * l + 6, d_cnt + l, stream);
+        }
+        std::vector<unsigned long long> h_cnt(nl);
+        IIM_HIP(hipMemcpyAsync(h_bb.data(), d_bb, 8 * nl * sizeof(int), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipMemcpyAsync(h_cnt.data(), d_cnt, nl * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+        mem.release(d_bb);
+        mem.release(d_cnt);
+        for (int l = 0; l < nl; ++l) {
+            Level& L = levels[l];
+            const int* bb = h_bb.data() + 8 * l;
+            if (bb[6]) throw Error(IIM_E_GEOMETRY_UNRESOLVED, "the immersed body touches the domain box");
+            L.nunk = (int64_t)h_cnt[l];
+            const bool empty = h_cnt[l] == 0;
+            int mn[3] = {bb[0], bb[1], dim == 3 ? bb[2] : 0};
+            int mx[3] = {bb[3], bb[4], dim == 3 ? bb[5] : 0};
+            L.box = make_box(dim, mn, mx, l == 0 ? 2 : 1, empty);
+            for (int d = 0; d < 3; ++d) {
+                L.core_lo[d] = empty ? 1 : (d < dim ? mn[d] : 0);
+                L.core_hi[d] = empty ? 0 : (d < dim ? mx[d] : 0);
+            }
+            if (L.box.size() > (int64_t)INT32_MAX) throw Error(IIM_E_BUDGET, "storage box exceeds 2^31 nodes");
+            L.labels = (uint8_t*)mem.alloc(L.box.size());
+            run_box_labels(L.geom, L.box, L.labels, stream);
+        }
     }
     Level& L0 = levels[0];
     if (L0.nunk == 0) throw Error(IIM_E_INVALID_ARG, "the problem has no unknowns");
     box = L0.box;
+    // one selection workspace for every flagged-node selection (stream ordered)
+    size_t sel_bytes = select_tmp_bytes(box.size());
+    void* sel_tmp = mem.alloc(sel_bytes);
+    uint8_t* flags = (uint8_t*)mem.alloc(box.size());
 
-    // ---- control points (level 0)
+    // ---- control points (level 0): crossings of each axis  [wait 2]
     {
-        uint8_t* flags = (uint8_t*)mem.alloc(box.size());
-        std::vector<int32_t*> per_axis;
-        std::vector<int64_t> counts;
+        std::vector<int32_t*> per_axis(dim);
         for (int a = 0; a < dim; ++a) {
             run_cp_flags(L0.geom, box, L0.labels, a, flags, stream);
-            int32_t* tmp = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
-            counts.push_back(select(flags, box.size(), tmp));
-            per_axis.push_back(tmp);
+            per_axis[a] = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
+            select_flagged_async(flags, box.size(), per_axis[a], sel_tmp, sel_bytes, d_sc + 1 + a, stream);
         }
+        read_sc(1 + dim);
         int64_t ncp = 0;
         cp.axis_start[0] = 0;
         for (int a = 0; a < 3; ++a) {
-            if (a < dim) ncp += counts[a];
+            if (a < dim) ncp += h_sc[1 + a];
             cp.axis_start[a + 1] = (int)ncp;
         }
         cp.ncp = ncp;
         cp.nsides = nsides;
-        cp.lower = (int32_t*)mem.alloc(ncp * sizeof(int32_t));
-        cp.axis = (int32_t*)mem.alloc(ncp * sizeof(int32_t));
-        cp.a = (int32_t*)mem.alloc(ncp * nsides * sizeof(int32_t));
-        cp.dir = (int32_t*)mem.alloc(ncp * nsides * sizeof(int32_t));
-        cp.x = (double*)mem.alloc(3 * ncp * sizeof(double));
-        cp.n = (double*)mem.alloc(3 * ncp * sizeof(double));
-        cp.kappa = (double*)mem.alloc(ncp * sizeof(double));
-        std::vector<int32_t> axes(ncp);
+        cp.lower = (int32_t*)mem.alloc(std::max<int64_t>(ncp, 1) * sizeof(int32_t));
+        cp.axis = (int32_t*)mem.alloc(std::max<int64_t>(ncp, 1) * sizeof(int32_t));
+        cp.a = (int32_t*)mem.alloc(std::max<int64_t>(ncp, 1) * nsides * sizeof(int32_t));
+        cp.dir = (int32_t*)mem.alloc(std::max<int64_t>(ncp, 1) * nsides * sizeof(int32_t));
+        cp.x = (double*)mem.alloc(3 * std::max<int64_t>(ncp, 1) * sizeof(double));
+        cp.n = (double*)mem.alloc(3 * std::max<int64_t>(ncp, 1) * sizeof(double));
+        cp.kappa = (double*)mem.alloc(std::max<int64_t>(ncp, 1) * sizeof(double));
         for (int a = 0; a < dim; ++a) {
-            IIM_HIP(hipMemcpyAsync(cp.lower + cp.axis_start[a], per_axis[a], counts[a] * sizeof(int32_t),
-                                   hipMemcpyDeviceToDevice, stream));
-            for (int64_t i = cp.axis_start[a]; i < cp.axis_start[a + 1]; ++i) axes[i] = a;
+            const int64_t c = h_sc[1 + a];
+            if (c) {
+                IIM_HIP(hipMemcpyAsync(cp.lower + cp.axis_start[a], per_axis[a], c * sizeof(int32_t),
+                                       hipMemcpyDeviceToDevice, stream));
+                run_fill_int(cp.axis + cp.axis_start[a], c, a, stream);
+            }
+            mem.release(per_axis[a]);
         }
-        IIM_HIP(hipMemcpyAsync(cp.axis, axes.data(), ncp * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-        IIM_HIP(hipStreamSynchronize(stream));
-        for (auto p : per_axis) mem.release(p);
-        mem.release(flags);
         run_cp_compute(L0.geom, box, L0.labels, cp, d_err, stream);
-        check_err(d_err, "control points");
     }
 
-    // ---- least-squares stencils (FP64)
+    // ---- least-squares stencils (FP64): sizes  [wait 3], then the fits
     const int64_t ncs = cp.ncp * nsides;
     nrows = w + ((bc == IIM_BC_DIRICHLET) ? 0 : 1);
     {
@@ -236,20 +242,22 @@ void Problem::setup() {
         P.mcap = dim == 2 ? 192 : 768;
         const int K = opt.order_k;
         const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
-        int32_t* d_m = (int32_t*)mem.alloc(std::max<int64_t>(ncs, 1) * sizeof(int32_t));
-        int32_t* d_grow = (int32_t*)mem.alloc(std::max<int64_t>(ncs, 1) * sizeof(int32_t));
-        uint8_t* d_route = (uint8_t*)mem.alloc(std::max<int64_t>(ncs, 1));
-        IIM_HIP(hipMemsetAsync(d_route, 0, std::max<int64_t>(ncs, 1), stream));
+        const int64_t ncs1 = std::max<int64_t>(ncs, 1);
+        int32_t* d_mg = (int32_t*)mem.alloc(2 * ncs1 * sizeof(int32_t));  // sizes, then growth
+        int32_t* d_m = d_mg;
+        int32_t* d_grow = d_mg + ncs1;
+        uint8_t* d_route = (uint8_t*)mem.alloc(ncs1);
+        IIM_HIP(hipMemsetAsync(d_route, 0, ncs1, stream));
         // pass 0, register path: sizes and growth of every fit that fits in registers
         run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_err,
                nullptr, 0, d_route, stream);
-        check_err(d_err, "least-squares sizes");
-        std::vector<int32_t> hg(ncs);
-        if (ncs) IIM_HIP(hipMemcpyAsync(hg.data(), d_grow, ncs * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        IIM_HIP(hipStreamSynchronize(stream));
+        std::vector<int32_t> hmg(2 * ncs1);
+        IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, 2 * ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        read_sc(1);
+        raise_setup_error(err_bits(), "control points and least-squares sizes");
         std::vector<int32_t> big;
         for (int64_t i = 0; i < ncs; ++i)
-            if (hg[i] == -3) big.push_back((int32_t)i);
+            if (hmg[ncs1 + i] == -3) big.push_back((int32_t)i);
         int32_t* d_list = nullptr;
         double* scratch = nullptr;
         int64_t waves = 0;
@@ -260,34 +268,31 @@ void Problem::setup() {
             IIM_HIP(hipMemcpyAsync(d_list, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
             run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, scratch, waves,
                    d_err, d_list, (int64_t)big.size(), d_route, stream);
-            check_err(d_err, "least-squares sizes (large sets)");
+            IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+            read_sc(1);
+            raise_setup_error(err_bits(), "least-squares sizes (large sets)");
         }
-        std::vector<int32_t> hm(ncs);
-        if (ncs) IIM_HIP(hipMemcpyAsync(hm.data(), d_m, ncs * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        IIM_HIP(hipStreamSynchronize(stream));
         h_ptr.assign(ncs + 1, 0);
-        for (int64_t i = 0; i < ncs; ++i) h_ptr[i + 1] = h_ptr[i] + hm[i];
+        for (int64_t i = 0; i < ncs; ++i) h_ptr[i + 1] = h_ptr[i] + hmg[i];
         nnz = h_ptr[ncs];
         ls_ptr = (int64_t*)mem.alloc((ncs + 1) * sizeof(int64_t));
         IIM_HIP(hipMemcpyAsync(ls_ptr, h_ptr.data(), (ncs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-        ls_idx = (int32_t*)mem.alloc(nnz * sizeof(int32_t));
-        ls_S = (double*)mem.alloc(nrows * nnz * sizeof(double));
-        ls_Sc = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * nrows * sizeof(double));
+        ls_idx = (int32_t*)mem.alloc(std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+        ls_S = (double*)mem.alloc(std::max<int64_t>(nrows * nnz, 1) * sizeof(double));
+        ls_Sc = (double*)mem.alloc(ncs1 * nrows * sizeof(double));
         run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, nullptr, 0, d_err, nullptr,
                0, d_route, stream);
         if (!big.empty())
             run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, scratch, waves, d_err,
                    d_list, (int64_t)big.size(), d_route, stream);
-        check_err(d_err, "least-squares fits");
         if (scratch) mem.release(scratch);
         if (d_list) mem.release(d_list);
-        mem.release(d_m);
-        mem.release(d_grow);
+        mem.release(d_mg);
         mem.release(d_route);
         // apply weights
-        dcoef = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * w * sizeof(double));
+        dcoef = (double*)mem.alloc(ncs1 * w * sizeof(double));
         if (bc == IIM_BC_NEUMANN) {
-            W_apply = (double*)mem.alloc(w * nnz * sizeof(double));
+            W_apply = (double*)mem.alloc(std::max<int64_t>(w * nnz, 1) * sizeof(double));
             nrows_apply = w;
         } else {
             W_apply = ls_S;
@@ -295,60 +300,65 @@ void Problem::setup() {
         }
         run_apply_weights(bc, ls_ptr, ncs, w, nrows, ls_S, ls_Sc, opt.beta_plus, nnz,
                           bc == IIM_BC_NEUMANN ? W_apply : nullptr, dcoef, stream);
-        ghost = (double*)mem.alloc(std::max<int64_t>(ncs, 1) * w * sizeof(double));
+        ghost = (double*)mem.alloc(ncs1 * w * sizeof(double));
         cpdata = (double*)mem.alloc(std::max<int64_t>(cp.ncp, 1) * 2 * sizeof(double));
         IIM_HIP(hipMemsetAsync(cpdata, 0, std::max<int64_t>(cp.ncp, 1) * 2 * sizeof(double), stream));
     }
 
-    // ---- irregular high-order nodes
+    // ---- irregular nodes: high-order (level 0) and Shortley-Weller (every level),
+    // selected together  [wait 4]
+    int32_t* ho_sel = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
+    run_ho_irr_flag(L0.geom, box, L0.labels, flags, stream);
+    select_flagged_async(flags, box.size(), ho_sel, sel_tmp, sel_bytes, d_sc + 4, stream);
+    std::vector<int32_t*> sw_sel(nl);
+    for (int l = 0; l < nl; ++l) {
+        Level& L = levels[l];
+        const int64_t bs = L.box.size();
+        run_sw_irr_flag(L.geom, L.box, L.labels, flags, stream);
+        sw_sel[l] = (int32_t*)mem.alloc(bs * sizeof(int32_t));
+        select_flagged_async(flags, bs, sw_sel[l], sel_tmp, sel_bytes, d_sc + 8 + l, stream);
+    }
+    read_sc(8 + nl);
+    raise_setup_error(err_bits(), "least-squares fits");
+    mem.release(flags);
+    mem.release(sel_tmp);
     {
-        uint8_t* flags = (uint8_t*)mem.alloc(box.size());
-        run_ho_irr_flag(L0.geom, box, L0.labels, flags, stream);
-        int32_t* nodes = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
-        ho_nirr = select(flags, box.size(), nodes);
+        ho_nirr = h_sc[4];
         ho_irr_index = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
         run_fill_int(ho_irr_index, box.size(), -1, stream);
         ho_slots = (int32_t*)mem.alloc(std::max<int64_t>(ho_nirr, 1) * 2 * dim * sizeof(int32_t));
-        run_ho_irr_records(L0.geom, box, L0.labels, cp, nodes, ho_nirr, ho_slots, ho_irr_index, d_err, stream);
-        check_err(d_err, "irregular records");
+        run_ho_irr_records(L0.geom, box, L0.labels, cp, ho_sel, ho_nirr, ho_slots, ho_irr_index, d_err, stream);
         ho_nodes = (int32_t*)mem.alloc(std::max<int64_t>(ho_nirr, 1) * sizeof(int32_t));
         if (ho_nirr)
-            IIM_HIP(hipMemcpyAsync(ho_nodes, nodes, ho_nirr * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
-        mem.release(nodes);
-        mem.release(flags);
+            IIM_HIP(hipMemcpyAsync(ho_nodes, ho_sel, ho_nirr * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
+        mem.release(ho_sel);
     }
-
-    // ---- Shortley-Weller rows on every level
-    for (size_t l = 0; l < levels.size(); ++l) {
+    const int R = 1 + 2 * dim;
+    for (int l = 0; l < nl; ++l) {
         Level& L = levels[l];
-        int64_t bs = L.box.size();
-        uint8_t* flags = (uint8_t*)mem.alloc(bs);
-        run_sw_irr_flag(L.geom, L.box, L.labels, flags, stream);
-        int32_t* nodes = (int32_t*)mem.alloc(bs * sizeof(int32_t));
-        L.nirr = select(flags, bs, nodes);
+        const int64_t bs = L.box.size();
+        L.nirr = h_sc[8 + l];
         L.irr_index = (int32_t*)mem.alloc(bs * sizeof(int32_t));
         run_fill_int(L.irr_index, bs, -1, stream);
-        const int R = 1 + 2 * dim;
         L.rec64 = (double*)mem.alloc(std::max<int64_t>(L.nirr, 1) * R * sizeof(double));
         L.rec32 = (float*)mem.alloc(std::max<int64_t>(L.nirr, 1) * R * sizeof(float));
-        run_sw_records(L.geom, L.box, L.labels, nodes, L.nirr, bc, opt.beta_plus, opt.beta_minus, L.rec64, L.rec32,
-                       L.irr_index, stream);
-        mem.release(nodes);
-        mem.release(flags);
+        run_sw_records(L.geom, L.box, L.labels, sw_sel[l], L.nirr, bc, opt.beta_plus, opt.beta_minus, L.rec64,
+                       L.rec32, L.irr_index, stream);
+        mem.release(sw_sel[l]);
     }
 
-    // ---- coarsest level: dense inverse of the scaled SW matrix
+    // ---- coarsest level: dense inverse of the scaled SW matrix  [wait 5]
     {
         Level& Lc = levels.back();
         int64_t bs = Lc.box.size();
-        const int R = 1 + 2 * dim;
         std::vector<uint8_t> lab(bs);
         std::vector<int32_t> irr(bs);
         std::vector<double> rec(std::max<int64_t>(Lc.nirr, 1) * R);
         IIM_HIP(hipMemcpyAsync(lab.data(), Lc.labels, bs, hipMemcpyDeviceToHost, stream));
         IIM_HIP(hipMemcpyAsync(irr.data(), Lc.irr_index, bs * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         IIM_HIP(hipMemcpyAsync(rec.data(), Lc.rec64, rec.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
-        IIM_HIP(hipStreamSynchronize(stream));
+        read_sc(1);
+        raise_setup_error(err_bits(), "irregular records");
         std::vector<int32_t> list, col_of(bs, -1);
         for (int64_t l = 0; l < bs; ++l) {
             if (!is_unknown(lab[l])) continue;
@@ -368,42 +378,49 @@ void Problem::setup() {
         Ainv32 = (float*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(float));
         run_coarse_assemble(Lc.box, dim, Lc.labels, Lc.irr_index, Lc.rec64, coarse_list, d_col, nc, A, stream);
         run_coarse_invert(A, Ainv64, nc, d_err, stream);
-        check_err(d_err, "coarse inverse");
         run_convert<double, float>(Ainv64, Ainv32, nc * nc, 1.0, stream);
-        IIM_HIP(hipStreamSynchronize(stream));
         mem.release(A);
         mem.release(d_col);
     }
 
-    // ---- solve buffers
+    // ---- solve buffers: one zeroed block for the level-0 vectors and the
+    // Krylov bases, one for the V-cycle vectors of every level
     const int64_t N = box.size();
     const int m = opt.restart;
-    boxval = (double*)mem.alloc(N * sizeof(double));
-    rhs = (double*)mem.alloc(N * sizeof(double));
-    xk = (double*)mem.alloc(N * sizeof(double));
-    rk = (double*)mem.alloc(N * sizeof(double));
-    wk = (double*)mem.alloc(N * sizeof(double));
     ldv = (N + 63) / 64 * 64;
-    Vb = (double*)mem.alloc((size_t)(m + 1) * ldv * sizeof(double));
-    Zb = (double*)mem.alloc((size_t)m * ldv * sizeof(double));
-    for (double* p : {boxval, rhs, xk, rk, wk}) IIM_HIP(hipMemsetAsync(p, 0, N * sizeof(double), stream));
-    IIM_HIP(hipMemsetAsync(Vb, 0, (size_t)(m + 1) * ldv * sizeof(double), stream));
-    IIM_HIP(hipMemsetAsync(Zb, 0, (size_t)m * ldv * sizeof(double), stream));
-    red_part = (double*)mem.alloc((size_t)RED_PART_DOUBLES * sizeof(double));
-    IIM_HIP(hipMemsetAsync(red_part, 0, (size_t)RED_PART_DOUBLES * sizeof(double), stream));
-    red_out = (double*)mem.alloc(4 * 64 * sizeof(double));
-    IIM_HIP(hipMemsetAsync(red_out, 0, 4 * 64 * sizeof(double), stream));
-    red_scale = (double*)mem.alloc(2 * sizeof(double));
-    size_t tsz = opt.precision == IIM_PREC_FP64 ? sizeof(double) : sizeof(float);
-    size_t ssz = opt.precision == IIM_PREC_FP64 ? 8 : (opt.precision == IIM_PREC_MIXED32 ? 4 : 2);
-    for (Level& L : levels) {
-        L.z = mem.alloc(L.box.size() * ssz);
-        L.b = mem.alloc(L.box.size() * tsz);
-        IIM_HIP(hipMemsetAsync(L.z, 0, L.box.size() * ssz, stream));
-        IIM_HIP(hipMemsetAsync(L.b, 0, L.box.size() * tsz, stream));
-        if (dim == 2 && opt_fused) {
-            L.z2 = mem.alloc(L.box.size() * ssz);
-            IIM_HIP(hipMemsetAsync(L.z2, 0, L.box.size() * ssz, stream));
+    {
+        double* blk = (double*)mem.alloc((size_t)(2 * m + 6) * ldv * sizeof(double));
+        IIM_HIP(hipMemsetAsync(blk, 0, (size_t)(2 * m + 6) * ldv * sizeof(double), stream));
+        boxval = blk;
+        rhs = blk + ldv;
+        xk = blk + 2 * ldv;
+        rk = blk + 3 * ldv;
+        wk = blk + 4 * ldv;
+        Vb = blk + 5 * ldv;
+        Zb = Vb + (size_t)(m + 1) * ldv;
+    }
+    red_part = (double*)mem.alloc((size_t)(RED_PART_DOUBLES + 4 * 64 + 2) * sizeof(double));
+    IIM_HIP(hipMemsetAsync(red_part, 0, (size_t)(RED_PART_DOUBLES + 4 * 64 + 2) * sizeof(double), stream));
+    red_out = red_part + RED_PART_DOUBLES;
+    red_scale = red_out + 4 * 64;
+    const size_t tsz = opt.precision == IIM_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t ssz = opt.precision == IIM_PREC_FP64 ? 8 : (opt.precision == IIM_PREC_MIXED32 ? 4 : 2);
+    {
+        const bool two = dim == 2 && opt_fused;
+        auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+        size_t total = 0;
+        for (Level& L : levels) total += up256(L.box.size() * ssz) * (two ? 2 : 1) + up256(L.box.size() * tsz);
+        char* blk = (char*)mem.alloc(total);
+        IIM_HIP(hipMemsetAsync(blk, 0, total, stream));
+        for (Level& L : levels) {
+            L.z = blk;
+            blk += up256(L.box.size() * ssz);
+            L.b = blk;
+            blk += up256(L.box.size() * tsz);
+            if (two) {
+                L.z2 = blk;
+                blk += up256(L.box.size() * ssz);
+            }
         }
     }
     // levels small enough for the single-workgroup tail kernel
@@ -411,21 +428,20 @@ void Problem::setup() {
     // every level but the coarsest; in 3D small levels go to the tail
     const int64_t tail_default = (dim == 2 && opt_fused) ? -1 : TAIL_MAX_NODES;
     const int64_t tail_max = opt.tail_nodes == 0 ? tail_default : (int64_t)opt.tail_nodes;
-    tail_first = (int)levels.size() - 1;
+    tail_first = nl - 1;
     while (tail_first > 0 && levels[tail_first - 1].box.size() <= tail_max) --tail_first;
     {
         TailDev T{};
         T.first = tail_first;
-        T.last = (int)levels.size() - 1;
+        T.last = nl - 1;
         T.mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
         T.nu_pre = opt.nu_pre;
         T.nu_post = opt.nu_post;
         T.nc = nc;
         T.clist = coarse_list;
         T.Ainv = opt.precision == IIM_PREC_FP64 ? (const void*)Ainv64 : (const void*)Ainv32;
-        if (levels.size() > MAX_LEVELS) throw Error(IIM_E_INVALID_ARG, "too many multigrid levels");
-        for (size_t l = 0; l < levels.size(); ++l) {
-            T.lev[l] = level_dev((int)l);
+        for (int l = 0; l < nl; ++l) {
+            T.lev[l] = level_dev(l);
             T.z[l] = levels[l].z;
             T.b[l] = levels[l].b;
         }
@@ -434,8 +450,9 @@ void Problem::setup() {
     }
     if (!hpin) IIM_HIP(hipHostMalloc((void**)&hpin, 256 * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 8; ++i) IIM_HIP(hipEventCreate(&ev[i]));
-    IIM_HIP(hipStreamSynchronize(stream));
-    mem.release(d_err);
+    read_sc(1);  // [wait 6]
+    raise_setup_error(err_bits(), "coarse inverse");
+    mem.release(d_sc);
     t_setup_ms = now_ms() - t0;
 }
 
@@ -1120,7 +1137,6 @@ void iim_destroy(iim_problem* p) {
     } catch (...) {
     }
     delete p;
-    iim::trim_pool();  // hand the freed blocks back to the device
 }
 
 int iim_get_info(const iim_problem* h, iim_info* info) {

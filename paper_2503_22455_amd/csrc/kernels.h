@@ -16,8 +16,10 @@ void run_box_labels(const Geom& g, const Box& b, uint8_t* labels, hipStream_t s)
 void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, int axis, uint8_t* flags,
                   hipStream_t s);
 // indices l with flags[l] != 0, in increasing order; returns the count (synchronises)
-int64_t select_flagged(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
-                       int64_t* d_count, hipStream_t s);
+// indices (0..n-1) of the flagged entries into out, their number into *d_count;
+// stream ordered, no host wait
+void select_flagged_async(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
+                          int64_t* d_count, hipStream_t s);
 size_t select_tmp_bytes(int64_t n);
 
 struct CPDev {

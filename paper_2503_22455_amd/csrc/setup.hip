@@ -124,14 +124,13 @@ size_t select_tmp_bytes(int64_t n) {
     return bytes;
 }
 
-int64_t select_flagged(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
-                       int64_t* d_count, hipStream_t s) {
+void select_flagged_async(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
+                          int64_t* d_count, hipStream_t s) {
     hipcub::CountingInputIterator<int32_t> it(0);
+    size_t need = 0;
+    IIM_HIP(hipcub::DeviceSelect::Flagged(nullptr, need, it, flags, out, d_count, (int)n, s));
+    if (need > tmp_bytes) throw Error(IIM_E_INTERNAL, "selection workspace too small");
     IIM_HIP(hipcub::DeviceSelect::Flagged(tmp, tmp_bytes, it, flags, out, d_count, (int)n, s));
-    int64_t cnt = 0;
-    IIM_HIP(hipMemcpyAsync(&cnt, d_count, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    IIM_HIP(hipStreamSynchronize(s));
-    return cnt;
 }
 
 __global__ void k_cp_compute(Geom g, Box b, const uint8_t* labels, CPDev cp, int* err) {
