@@ -248,8 +248,13 @@ void Problem::setup() {
         int32_t* d_grow = d_mg + ncs1;
         uint8_t* d_route = (uint8_t*)mem.alloc(ncs1);
         IIM_HIP(hipMemsetAsync(d_route, 0, ncs1, stream));
-        // pass 0, register path: sizes and growth of every fit that fits in registers
-        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_err,
+        // one pass over the register path: sizes, growth and the weights, the
+        // weights into fixed segments of a staging area (compacted below)
+        const int seg = ls_segment(dim);
+        int32_t* st_idx = (int32_t*)mem.alloc(ncs1 * seg * sizeof(int32_t));
+        double* st_S = (double*)mem.alloc((size_t)nrows * ncs1 * seg * sizeof(double));
+        ls_Sc = (double*)mem.alloc(ncs1 * nrows * sizeof(double));
+        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, st_idx, st_S, ls_Sc, nullptr, 0, d_err,
                nullptr, 0, d_route, stream);
         std::vector<int32_t> hmg(2 * ncs1);
         IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, 2 * ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
@@ -279,9 +284,9 @@ void Problem::setup() {
         IIM_HIP(hipMemcpyAsync(ls_ptr, h_ptr.data(), (ncs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
         ls_idx = (int32_t*)mem.alloc(std::max<int64_t>(nnz, 1) * sizeof(int32_t));
         ls_S = (double*)mem.alloc(std::max<int64_t>(nrows * nnz, 1) * sizeof(double));
-        ls_Sc = (double*)mem.alloc(ncs1 * nrows * sizeof(double));
-        run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, nullptr, 0, d_err, nullptr,
-               0, d_route, stream);
+        run_ls_compact(ncs, seg, nrows, d_m, d_route, ls_ptr, st_idx, st_S, ls_idx, ls_S, stream);
+        mem.release(st_idx);
+        mem.release(st_S);
         if (!big.empty())
             run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, scratch, waves, d_err,
                    d_list, (int64_t)big.size(), d_route, stream);
@@ -838,6 +843,8 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     const double ncs = ncp * ns;
     bytes += (int64_t)(ncp * (4 + 4 + 24 + 24 + 8 + 16) + ncs * (4 + 4 + 8 * w * 2 + 8 * nrows + 4 + 4 + 1 + 8));
     bytes += (int64_t)(ncs * mset * (4 + 8 * nrows + (geo.bc == IIM_BC_NEUMANN ? 8 * w : 0)));
+    // staging of the fits: a fixed segment of 64 * (rows per lane) entries per fit
+    bytes += (int64_t)(ncs * (dim == 2 ? 128 : 256) * (4 + 8 * nrows));
     // scratch of oversized least-squares sets (one slab per wave, 256 waves at most)
     const int K = o.order_k;
     const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;

@@ -65,6 +65,13 @@ struct LSParams {
     int mcap;                    // capacity of the per-wave scratch (rows)
 };
 // pass 0: sizes (m, growth) per control point side; pass 1: fill idx / weights
+// entries per fit of the staging layout of pass 0 (64 lanes x rows per lane)
+int ls_segment(int dim);
+// staging -> CSR for the register-path fits (route[cs] == 0)
+void run_ls_compact(int64_t ncs, int seg, int nrows, const int32_t* m, const uint8_t* route, const int64_t* ptr,
+                    const int32_t* st_idx, const double* st_S, int32_t* idx, double* S, hipStream_t s);
+// pass 0 with idx/S/Sc set (register path only) also writes the weights in the
+// staging layout (segments of ls_segment(dim) entries); pass 1 writes CSR.
 // cs_list == nullptr: all fits by the register path (oversized ones flagged in route);
 // otherwise only the listed fits, with the global scratch (scratch_waves slabs).
 void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P,

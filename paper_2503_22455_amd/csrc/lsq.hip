@@ -315,11 +315,12 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
             const double sc = a * g.h;
             if (M <= 64 * RPL && p == PT) {
                 // register-resident QR (the common case)
-                if (pass == 1) {
-                    if (ptr[cs + 1] - ptr[cs] != m) {
-                        if (lane == 0) atomicOr(err, 256);
-                        break;
-                    }
+                const bool stage = pass == 0 && idx_out != nullptr;
+                if (pass == 1 && ptr[cs + 1] - ptr[cs] != m) {
+                    if (lane == 0) atomicOr(err, 256);
+                    break;
+                }
+                if (pass == 1 || stage) {
                     // evaluation functionals
                     int acoord[3];
                     b.coords(anode, acoord);
@@ -346,9 +347,12 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                         }
                     __syncthreads();
                 }
-                bool ok = reg_qr<PT, RPL>(M, lane, g.dim, list_idx, closest, b, g, xc, sc, ex, pass == 1, P.nrows,
-                                          E, Y, tauv, Rs, pass == 1 ? ptr[cs] : 0, pass == 1 ? ptr[ncs] : 0, cs,
-                                          idx_out, S_out, Sc_out);
+                // pass 1 writes into the CSR arrays; pass 0 with idx_out set writes into a
+                // staging layout with a fixed segment of 64 * RPL entries per fit
+                const int64_t seg = 64 * RPL;
+                bool ok = reg_qr<PT, RPL>(M, lane, g.dim, list_idx, closest, b, g, xc, sc, ex, pass == 1 || stage,
+                                          P.nrows, E, Y, tauv, Rs, pass == 1 ? ptr[cs] : cs * seg,
+                                          pass == 1 ? ptr[ncs] : ncs * seg, cs, idx_out, S_out, Sc_out);
                 __syncthreads();
                 if (!ok) continue;  // rank deficient: grow
                 done = true;
@@ -509,6 +513,35 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
         __syncthreads();
     }
 }
+
+// staging (fixed segments of seg entries per fit) -> CSR, for the fits of the
+// register path (route[cs] == 0); one wavefront per fit
+__global__ void __launch_bounds__(256) k_ls_compact(int64_t ncs, int seg, int nrows, const int32_t* m,
+                                                    const uint8_t* route, const int64_t* ptr, const int32_t* st_idx,
+                                                    const double* st_S, int32_t* idx, double* S) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nnz = ptr[ncs], snz = ncs * (int64_t)seg;
+    for (int64_t cs = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64; cs < ncs;
+         cs += (int64_t)gridDim.x * blockDim.x / 64) {
+        if (route[cs]) continue;
+        const int64_t src = cs * seg, dst = ptr[cs];
+        for (int r = lane; r < m[cs]; r += 64) {
+            idx[dst + r] = st_idx[src + r];
+            for (int k = 0; k < nrows; ++k) S[(int64_t)k * nnz + dst + r] = st_S[(int64_t)k * snz + src + r];
+        }
+    }
+}
+
+void run_ls_compact(int64_t ncs, int seg, int nrows, const int32_t* m, const uint8_t* route, const int64_t* ptr,
+                    const int32_t* st_idx, const double* st_S, int32_t* idx, double* S, hipStream_t s) {
+    if (ncs == 0) return;
+    const int blocks = (int)std::min<int64_t>(cdiv(ncs * 64, 256), 8192);
+    hipLaunchKernelGGL(k_ls_compact, dim3(blocks), dim3(256), 0, s, ncs, seg, nrows, m, route, ptr, st_idx, st_S, idx,
+                       S);
+    IIM_LAUNCH_CHECK();
+}
+
+int ls_segment(int dim) { return dim == 2 ? 64 * 2 : 64 * 4; }
 
 void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P, int pass,
             int32_t* m_out, int32_t* grow_out, const int64_t* ptr, int32_t* idx, double* S, double* Sc,
