@@ -10,30 +10,51 @@
 namespace iim {
 
 // ---------------------------------------------------------------------------
-// ghost values: one 16-lane group per control point (all its sides)
+// ghost values: one group of GLN lanes per control point (all its sides); the
+// group width follows the mean least-squares set size (16 lanes in 2D, a whole
+// wavefront for the ~200-point 3D sets), rows and sides are compile-time
 // ---------------------------------------------------------------------------
-constexpr int GL = 16;
-
-__global__ void __launch_bounds__(256) k_ghosts(GhostDev G, const double* x, const double* cpdata, int with_data,
-                                                double* ghost) {
-    const int lane = threadIdx.x % GL;
-    const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / GL;
-    if (c >= G.ncp) return;  // whole 16-lane groups exit together
-    double dots[2][4];
-    for (int s = 0; s < G.nsides; ++s) {
-        int64_t cs = c * G.nsides + s;
-        int64_t b0 = G.ptr[cs], b1 = G.ptr[cs + 1];
-        for (int k = 0; k < 4; ++k) dots[s][k] = 0.0;
-        for (int64_t a = b0 + lane; a < b1; a += GL) {
-            double xv = x[G.idx[a]];
-            for (int k = 0; k < G.nrows; ++k) dots[s][k] += G.W[k * G.nnz + a] * xv;
+template <int NS, int NR, int GLN>
+__global__ void __launch_bounds__(256) k_ghosts(GhostDev G, const double* __restrict__ x,
+                                                const double* __restrict__ cpdata, int with_data,
+                                                double* __restrict__ ghost) {
+    const int lane = threadIdx.x % GLN;
+    const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / GLN;
+    if (c >= G.ncp) return;  // whole groups exit together
+    double dots[NS][NR];
+#pragma unroll
+    for (int sd = 0; sd < NS; ++sd) {
+        const int64_t cs = c * NS + sd;
+        const int64_t b0 = G.ptr[cs], b1 = G.ptr[cs + 1];
+        double acc[2][NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[0][k] = acc[1][k] = 0.0;
+        int64_t a = b0 + lane;
+        // two entries per step so that twice the gathers are in flight
+        for (; a + GLN < b1; a += 2 * GLN) {
+            const double x0 = x[G.idx[a]], x1 = x[G.idx[a + GLN]];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                acc[0][k] += G.W[k * G.nnz + a] * x0;
+                acc[1][k] += G.W[k * G.nnz + a + GLN] * x1;
+            }
         }
-        for (int k = 0; k < G.nrows; ++k)
-            for (int off = GL / 2; off > 0; off >>= 1) dots[s][k] += __shfl_xor(dots[s][k], off, GL);
+        if (a < b1) {
+            const double x0 = x[G.idx[a]];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[0][k] += G.W[k * G.nnz + a] * x0;
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            double v = acc[0][k] + acc[1][k];
+#pragma unroll
+            for (int off = GLN / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, GLN);
+            dots[sd][k] = v;
+        }
     }
     if (lane != 0) return;
     const int w = G.w;
-    if (G.bc != IIM_BC_JUMP) {
+    if (NS == 1) {
         for (int j = 0; j < w; ++j) {
             double gv = dots[0][j];
             if (with_data) gv += G.dcoef[c * w + j] * cpdata[c];
@@ -42,30 +63,51 @@ __global__ void __launch_bounds__(256) k_ghosts(GhostDev G, const double* x, con
         return;
     }
     // interface: Sec. 2.2 closed form with D = beta+ s_c+ - beta- s_c-
-    const int R = G.nrows;  // w ghosts + normal derivative
-    const double* scp = G.Sc + (c * 2 + 0) * R;
-    const double* scm = G.Sc + (c * 2 + 1) * R;
-    double bp = G.beta_plus, bm = G.beta_minus;
-    double D = bp * scp[w] - bm * scm[w];
-    double ubar = -(bp * dots[0][w] - bm * dots[1][w]) / D;
+    const double* scp = G.Sc + (c * 2 + 0) * NR;
+    const double* scm = G.Sc + (c * 2 + 1) * NR;
+    const double bp = G.beta_plus, bm = G.beta_minus;
+    const double D = bp * scp[w] - bm * scm[w];
+    const double ubar = -(bp * dots[0][w] - bm * dots[NS - 1][w]) / D;
     double Up = ubar, Um = ubar;
     if (with_data) {
-        double j0 = cpdata[2 * c], j1 = cpdata[2 * c + 1];
+        const double j0 = cpdata[2 * c], j1 = cpdata[2 * c + 1];
         Up += (j1 - bm * scm[w] * j0) / D;
         Um += (j1 - bp * scp[w] * j0) / D;
     }
     for (int j = 0; j < w; ++j) {
         ghost[(c * 2 + 0) * w + j] = scp[j] * Up + dots[0][j];
-        ghost[(c * 2 + 1) * w + j] = scm[j] * Um + dots[1][j];
+        ghost[(c * 2 + 1) * w + j] = scm[j] * Um + dots[NS - 1][j];
     }
+}
+
+template <int NS, int NR>
+static void launch_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
+                          hipStream_t s) {
+    const double mean_m = (double)G.nnz / (double)(G.ncp * NS);
+    const int gln = mean_m > 96.0 ? 64 : (mean_m > 40.0 ? 32 : 16);
+    const int64_t threads = G.ncp * gln;
+    if (gln == 64)
+        hipLaunchKernelGGL((k_ghosts<NS, NR, 64>), dim3(cdiv(threads, 256)), dim3(256), 0, s, G, x, cpdata, with_data,
+                           ghost);
+    else if (gln == 32)
+        hipLaunchKernelGGL((k_ghosts<NS, NR, 32>), dim3(cdiv(threads, 256)), dim3(256), 0, s, G, x, cpdata, with_data,
+                           ghost);
+    else
+        hipLaunchKernelGGL((k_ghosts<NS, NR, 16>), dim3(cdiv(threads, 256)), dim3(256), 0, s, G, x, cpdata, with_data,
+                           ghost);
+    IIM_LAUNCH_CHECK();
 }
 
 void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
                 hipStream_t s) {
     if (G.ncp == 0) return;
-    int64_t threads = G.ncp * GL;
-    hipLaunchKernelGGL(k_ghosts, dim3(cdiv(threads, 256)), dim3(256), 0, s, G, x, cpdata, with_data, ghost);
-    IIM_LAUNCH_CHECK();
+    if (G.w != 2) throw Error(IIM_E_INTERNAL, "ghost kernel built for w = 2");
+    if (G.nsides == 1 && G.nrows == 2)
+        launch_ghosts<1, 2>(G, x, cpdata, with_data, ghost, s);
+    else if (G.nsides == 2 && G.nrows == 3)
+        launch_ghosts<2, 3>(G, x, cpdata, with_data, ghost, s);
+    else
+        throw Error(IIM_E_INTERNAL, "ghost kernel: unsupported rows/sides");
 }
 
 // ---------------------------------------------------------------------------
