@@ -39,7 +39,7 @@ __device__ inline void block_reduce_store(const double (&vals)[K], int k, double
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         if (i < k) {
-            double v = mode == 1 ? wave_max(vals[i]) : wave_sum(vals[i]);
+            double v = mode == 1 ? wave_max_valu(vals[i]) : wave_sum_valu(vals[i]);
             if (lane == 0) sh[wv][i] = v;
         }
     }
@@ -51,29 +51,39 @@ __device__ inline void block_reduce_store(const double (&vals)[K], int k, double
     }
 }
 
-// Second stage, one block: out[i] = sum (mode 1: max) of the RED_BLOCKS
-// partials of value i in a fixed order, one wavefront per value; mode 1 also
-// writes out[1] = 1 / max (1 if zero).  A separate launch rather than a
-// last-block-done epilogue: the epilogue's device-scope fences cost more than
-// a launch on a device whose XCDs have separate L2 caches.
-__global__ void __launch_bounds__(RED_THREADS) k_final(const double* part, int k, double* out, int mode) {
+// Second stage, one block of RED_BLOCKS threads: thread t loads partial t of
+// every value at once, wavefronts reduce on the VALU, the RED_BLOCKS / 64
+// wavefront results are added in order.  out[i] = sum (mode 1: max) of the
+// partials of value i; mode 1 also writes out[1] = 1 / max (1 if zero).  A
+// separate launch rather than a last-block-done epilogue: the epilogue's
+// device-scope fences cost more than a launch on a device whose XCDs have
+// separate L2 caches.
+constexpr int FIN_WAVES = RED_BLOCKS / 64;
+
+__global__ void __launch_bounds__(RED_BLOCKS) k_final(const double* part, int k, double* out, int mode) {
+    __shared__ double sh[FIN_WAVES][KCH + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = wv; i < k; i += WAVES) {
-        double v = 0.0;
-        for (int bq = lane; bq < RED_BLOCKS; bq += 64) {
-            const double p = part[(int64_t)i * RED_BLOCKS + bq];
-            v = mode == 1 ? fmax(v, p) : v + p;
+    double p[KCH + 1];
+#pragma unroll
+    for (int i = 0; i <= KCH; ++i) p[i] = i < k ? part[(int64_t)i * RED_BLOCKS + threadIdx.x] : 0.0;
+#pragma unroll
+    for (int i = 0; i <= KCH; ++i)
+        if (i < k) {
+            const double v = mode == 1 ? wave_max_valu(p[i]) : wave_sum_valu(p[i]);
+            if (lane == 0) sh[wv][i] = v;
         }
-        v = mode == 1 ? wave_max(v) : wave_sum(v);
-        if (lane == 0) {
-            out[i] = v;
-            if (mode == 1) out[1] = v > 0.0 ? 1.0 / v : 1.0;
-        }
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        double v = sh[0][threadIdx.x];
+        for (int q = 1; q < FIN_WAVES; ++q) v = mode == 1 ? fmax(v, sh[q][threadIdx.x]) : v + sh[q][threadIdx.x];
+        out[threadIdx.x] = v;
+        if (mode == 1) out[1] = v > 0.0 ? 1.0 / v : 1.0;
     }
 }
 
 static void final_sum(const double* part, int k, double* out, hipStream_t s, int mode = 0) {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(RED_THREADS), 0, s, part, k, out, mode);
+    if (k < 1 || k > KCH + 1) throw Error(IIM_E_INVALID_ARG, "reduction: 1..13 values");
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RED_BLOCKS), 0, s, part, k, out, mode);
     IIM_LAUNCH_CHECK();
 }
 

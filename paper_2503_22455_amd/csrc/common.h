@@ -300,6 +300,48 @@ __host__ __device__ inline int make_slot(int type, int j, int cs) { return type 
 // 4th-order central second-derivative coefficients a_0, a_1, a_2
 constexpr double A0 = -2.5, A1 = 4.0 / 3.0, A2 = -1.0 / 12.0;
 
+// ---------------------------------------------------------------------------
+// wavefront reductions
+// ---------------------------------------------------------------------------
+// Wavefront sum on the VALU: DPP moves of the two 32-bit halves (quad
+// permutes, row rotations, then the row broadcasts that gather the four
+// 16-lane rows into lane 63), read back from lane 63.  All 64 lanes must be
+// active.  The order of the additions is fixed, so the result is deterministic.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_copy(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+// value of lane `lane` (wavefront-uniform) in every lane
+__device__ inline double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+__device__ inline double wave_sum_valu(double v) {
+    v += dpp_copy<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_copy<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_copy<0x124, 0xf>(v);  // row_ror 4
+    v += dpp_copy<0x128, 0xf>(v);  // row_ror 8: every lane holds its row's sum
+    v += dpp_copy<0x142, 0xa>(v);  // row_bcast 15 into rows 1 and 3
+    v += dpp_copy<0x143, 0xc>(v);  // row_bcast 31 into rows 2 and 3
+    return lane_value(v, 63);
+}
+// the same for the maximum of non-negative values (lanes outside a row mask read 0)
+__device__ inline double wave_max_valu(double v) {
+    v = fmax(v, dpp_copy<0xB1, 0xf>(v));
+    v = fmax(v, dpp_copy<0x4E, 0xf>(v));
+    v = fmax(v, dpp_copy<0x124, 0xf>(v));
+    v = fmax(v, dpp_copy<0x128, 0xf>(v));
+    v = fmax(v, dpp_copy<0x142, 0xa>(v));
+    v = fmax(v, dpp_copy<0x143, 0xc>(v));
+    return lane_value(v, 63);
+}
+
+
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace iim

@@ -52,6 +52,8 @@ struct Level {
 };
 
 constexpr int64_t TAIL_MAX_NODES = 4096;  // levels handled by the one-workgroup tail kernel
+constexpr int HCOL = 3 * 64;               // doubles of one Hessenberg column record (two CGS passes + norm)
+constexpr int HPIN_DOUBLES = 12 * HCOL;    // one record per inner iteration (restart <= 11)
 
 struct Problem {
     DevMem mem;
@@ -100,9 +102,10 @@ struct Problem {
     int tail_first = 0;
     bool opt_fused = true;  // LDS-tiled fused smoothing legs where available
     TailDev* d_tail = nullptr;
-    double* hpin = nullptr;  // pinned host copy of the Hessenberg column
+    double* hpin = nullptr;  // pinned host copies of the Hessenberg columns, HCOL doubles per iteration
     bool own_hpin = true;
     hipGraphExec_t iter_graph[16] = {};
+    hipEvent_t iter_done[2] = {};  // end of inner iteration j, alternating by parity
     double t_setup_ms = 0.0;
 
     void setup();
@@ -125,7 +128,7 @@ struct Problem {
 };
 
 // validated construction with setup (stream: NULL creates a blocking stream
-// owned by the problem); hpin: optional caller-owned pinned buffer of 256 doubles
+// owned by the problem); hpin: optional caller-owned pinned buffer of HPIN_DOUBLES doubles
 std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo, const iim_options* opt,
                                       hipStream_t stream, double* hpin);
 // device bytes a problem will hold at its peak, from the request alone

@@ -453,8 +453,9 @@ void Problem::setup() {
         d_tail = (TailDev*)mem.alloc(sizeof(TailDev));
         IIM_HIP(hipMemcpyAsync(d_tail, &T, sizeof(TailDev), hipMemcpyHostToDevice, stream));
     }
-    if (!hpin) IIM_HIP(hipHostMalloc((void**)&hpin, 256 * sizeof(double), hipHostMallocDefault));
+    if (!hpin) IIM_HIP(hipHostMalloc((void**)&hpin, HPIN_DOUBLES * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 8; ++i) IIM_HIP(hipEventCreate(&ev[i]));
+    for (int i = 0; i < 2; ++i) IIM_HIP(hipEventCreateWithFlags(&iter_done[i], hipEventDisableTiming));
     read_sc(1);  // [wait 6]
     raise_setup_error(err_bits(), "coarse inverse");
     mem.release(d_sc);
@@ -595,7 +596,7 @@ void Problem::iteration_body(int j, hipEvent_t* evs) {
     run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 0, red_part, red_out + 64, stream);
     run_update_dot(Vb, ldv, j + 1, red_out + 64, wk, N, 0, 1, red_part, red_out + 128, stream);
     run_normalize(wk, red_out + 128, Vb + (size_t)(j + 1) * ldv, N, stream);
-    IIM_HIP(hipMemcpyAsync(hpin, red_out, 3 * 64 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipMemcpyAsync(hpin + (size_t)j * HCOL, red_out, HCOL * sizeof(double), hipMemcpyDeviceToHost, stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -652,23 +653,32 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
             gv[0] = beta;
             int k = 0;
             bool breakdown = false;
+            // Iteration j+1 needs only device data of iteration j, so in graph mode
+            // it is queued before the host reads column j: the host's wait and
+            // its Givens update overlap the next iteration.  A queued iteration
+            // past convergence writes only basis vectors the update never reads.
+            auto capture = [&](int jj) {
+                if (iter_graph[jj]) return;
+                hipGraph_t g;
+                IIM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+                iteration_body(jj);
+                IIM_HIP(hipStreamEndCapture(stream, &g));
+                IIM_HIP(hipGraphInstantiate(&iter_graph[jj], g, nullptr, nullptr, 0));
+                IIM_HIP(hipGraphDestroy(g));
+            };
+            auto enqueue = [&](int jj) {
+                capture(jj);
+                IIM_HIP(hipGraphLaunch(iter_graph[jj], stream));
+                IIM_HIP(hipEventRecord(iter_done[jj & 1], stream));
+            };
+            if (opt.use_graph) {
+                IIM_HIP(hipEventRecord(ev[0], stream));
+                enqueue(0);
+            }
             for (int j = 0; j < m; ++j) {
                 if (opt.use_graph) {
-                    if (!iter_graph[j]) {
-                        hipGraph_t g;
-                        IIM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
-                        iteration_body(j);
-                        IIM_HIP(hipStreamEndCapture(stream, &g));
-                        IIM_HIP(hipGraphInstantiate(&iter_graph[j], g, nullptr, nullptr, 0));
-                        IIM_HIP(hipGraphDestroy(g));
-                    }
-                    IIM_HIP(hipEventRecord(ev[0], stream));
-                    IIM_HIP(hipGraphLaunch(iter_graph[j], stream));
-                    IIM_HIP(hipEventRecord(ev[3], stream));
-                    IIM_HIP(hipStreamSynchronize(stream));
-                    float a;
-                    IIM_HIP(hipEventElapsedTime(&a, ev[0], ev[3]));
-                    t_kr += a;
+                    if (j + 1 < m && its + 1 < opt.max_iters) enqueue(j + 1);
+                    IIM_HIP(hipEventSynchronize(iter_done[j & 1]));  // recorded after graph j, before j+1
                 } else {
                     IIM_HIP(hipEventRecord(ev[0], stream));
                     iteration_body(j, ev);
@@ -682,7 +692,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
                     t_apply += a2;
                     t_kr += a3;
                 }
-                const double* hbuf = hpin;
+                const double* hbuf = hpin + (size_t)j * HCOL;
                 for (int i = 0; i <= j; ++i) H[i * m + j] = hbuf[i] + hbuf[64 + i];
                 const double hn = std::sqrt(hbuf[128]);
                 H[(j + 1) * m + j] = hn;
@@ -707,6 +717,14 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
                 const double est = std::fabs(gv[j + 1]) / bnorm;
                 if (hist && hl < hist_cap) hist[hl++] = est;
                 if (est <= opt.rtol || its >= opt.max_iters || hn == 0.0) break;
+            }
+            if (opt.use_graph) {
+                // wait for the cycle's last queued iteration before the update
+                IIM_HIP(hipEventRecord(ev[3], stream));
+                IIM_HIP(hipEventSynchronize(ev[3]));
+                float a;
+                IIM_HIP(hipEventElapsedTime(&a, ev[0], ev[3]));
+                t_kr += a;
             }
             if (breakdown) {
                 status = IIM_E_BREAKDOWN;
@@ -1067,6 +1085,8 @@ Problem::~Problem() {
         if (g) (void)hipGraphExecDestroy(g);
     for (int i = 0; i < 8; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 2; ++i)
+        if (iter_done[i]) (void)hipEventDestroy(iter_done[i]);
     if (hpin && own_hpin) (void)hipHostFree(hpin);
     mem.release_all();
     if (stream) (void)hipStreamSynchronize(stream);
