@@ -100,6 +100,7 @@ struct Problem {
     hipEvent_t ev[8] = {};
     bool own_stream = false;
     int tail_first = 0;
+    int64_t tail_lds_bytes = 0;  // > 0: the tail levels run in that much LDS
     bool opt_fused = true;  // LDS-tiled fused smoothing legs where available
     TailDev* d_tail = nullptr;
     double* hpin = nullptr;  // pinned host copies of the Hessenberg columns, HCOL doubles per iteration

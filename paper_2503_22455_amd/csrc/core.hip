@@ -431,10 +431,18 @@ void Problem::setup() {
     // levels small enough for the single-workgroup tail kernel
     // default: in 2D the fused LDS legs are faster than the one-workgroup tail on
     // every level but the coarsest; in 3D small levels go to the tail
-    const int64_t tail_default = (dim == 2 && opt_fused) ? -1 : TAIL_MAX_NODES;
+    const int64_t tail_default = TAIL_MAX_NODES;
     const int64_t tail_max = opt.tail_nodes == 0 ? tail_default : (int64_t)opt.tail_nodes;
     tail_first = nl - 1;
     while (tail_first > 0 && levels[tail_first - 1].box.size() <= tail_max) --tail_first;
+    // the tail runs in LDS when its levels' vectors fit
+    {
+        int64_t off = 0;
+        auto up16 = [](int64_t v) { return (v + 15) / 16 * 16; };
+        for (int l = tail_first; l < nl; ++l) off += up16(levels[l].box.size() * ssz) + up16(levels[l].box.size() * tsz);
+        tail_lds_bytes = off <= TAIL_LDS_MAX ? off : 0;
+        if (tail_lds_bytes) enable_tail_lds();
+    }
     {
         TailDev T{};
         T.first = tail_first;
@@ -445,10 +453,19 @@ void Problem::setup() {
         T.nc = nc;
         T.clist = coarse_list;
         T.Ainv = opt.precision == IIM_PREC_FP64 ? (const void*)Ainv64 : (const void*)Ainv32;
+        int64_t off = 0;
+        auto up16 = [](int64_t v) { return (v + 15) / 16 * 16; };
         for (int l = 0; l < nl; ++l) {
             T.lev[l] = level_dev(l);
             T.z[l] = levels[l].z;
             T.b[l] = levels[l].b;
+            T.lds_z[l] = T.lds_b[l] = 0;
+            if (l >= tail_first) {
+                T.lds_z[l] = off;
+                off += up16(levels[l].box.size() * ssz);
+                T.lds_b[l] = off;
+                off += up16(levels[l].box.size() * tsz);
+            }
         }
         d_tail = (TailDev*)mem.alloc(sizeof(TailDev));
         IIM_HIP(hipMemcpyAsync(d_tail, &T, sizeof(TailDev), hipMemcpyHostToDevice, stream));
@@ -550,7 +567,7 @@ void Problem::vcycle_t(const double* v, double* out) {
         }
         run_resid_restrict<T, S>(D, C, z, b, (T*)levels[l + 1].b, stream);
     }
-    run_tail<T, S>(dim, d_tail, stream);  // levels t..nl-1, coarse solve included
+    run_tail<T, S>(dim, d_tail, tail_lds_bytes, stream);  // levels t..nl-1, coarse solve included
     const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
     const S* zres = (const S*)levels[t].z;  // result of the level below the current one
     for (int l = t - 1; l >= 0; --l) {

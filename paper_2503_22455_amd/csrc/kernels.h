@@ -15,8 +15,7 @@ void run_box_labels(const Geom& g, const Box& b, uint8_t* labels, hipStream_t s)
 // crossing flags along one axis: flags[l] = 1 if the segment (l, l + e_axis) carries a control point
 void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, int axis, uint8_t* flags,
                   hipStream_t s);
-// indices l with flags[l] != 0, in increasing order; returns the count (synchronises)
-// indices (0..n-1) of the flagged entries into out, their number into *d_count;
+// indices (0..n-1) of the flagged entries, in increasing order, into out, their number into *d_count;
 // stream ordered, no host wait
 void select_flagged_async(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
                           int64_t* d_count, hipStream_t s);
@@ -64,7 +63,6 @@ struct LSParams {
     int max_grow;
     int mcap;                    // capacity of the per-wave scratch (rows)
 };
-// pass 0: sizes (m, growth) per control point side; pass 1: fill idx / weights
 // entries per fit of the staging layout of pass 0 (64 lanes x rows per lane)
 int ls_segment(int dim);
 // staging -> CSR for the register-path fits (route[cs] == 0)
@@ -72,6 +70,7 @@ void run_ls_compact(int64_t ncs, int seg, int nrows, const int32_t* m, const uin
                     const int32_t* st_idx, const double* st_S, int32_t* idx, double* S, hipStream_t s);
 // pass 0 with idx/S/Sc set (register path only) also writes the weights in the
 // staging layout (segments of ls_segment(dim) entries); pass 1 writes CSR.
+// pass 0: sizes (m, growth) per control point side; pass 1: fill idx / weights.
 // cs_list == nullptr: all fits by the register path (oversized ones flagged in route);
 // otherwise only the listed fits, with the global scratch (scratch_waves slabs).
 void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P,
@@ -132,9 +131,15 @@ struct TailDev {
     LevelDev lev[MAX_LEVELS];
     void* z[MAX_LEVELS];
     void* b[MAX_LEVELS];
+    int64_t lds_z[MAX_LEVELS], lds_b[MAX_LEVELS];  // byte offsets of the LDS copies
 };
+// dynamic LDS the LDS-resident tail may request
+constexpr int64_t TAIL_LDS_MAX = 144 * 1024;
+// lds_bytes > 0: the LDS-resident tail with that much dynamic LDS (layout in
+// TailDev::lds_z / lds_b); 0: the tail on global memory
 template <typename T, typename S>
-void run_tail(int dim, const TailDev* d_tail, hipStream_t s);
+void run_tail(int dim, const TailDev* d_tail, int64_t lds_bytes, hipStream_t s);
+void enable_tail_lds();
 // fused legs (2D): zero + nu sweeps + residual + half-weighting; prolongation + nu sweeps.
 // Return false when the fused form does not apply (the caller launches the unfused kernels).
 template <typename T, typename S>

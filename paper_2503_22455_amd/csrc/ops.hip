@@ -5,6 +5,8 @@
 // unknowns (x fastest); nodes that are not unknowns hold zero, so regular
 // stencils need no masks.  Nodes whose stencil differs from the constant one
 // carry a flag in their label byte and an index into a compact record list.
+#include <mutex>
+
 #include "kernels.h"
 
 namespace iim {
@@ -629,6 +631,71 @@ __global__ void __launch_bounds__(1024) k_tail(const TailDev* __restrict__ Dp) {
     }
 }
 
+// The same tail with every vector of its levels in LDS: b of the first tail
+// level is copied in, the cycle over the tail levels runs on LDS arrays (labels
+// and Shortley-Weller rows are read from global memory, where they stay
+// cached), and z of the first tail level is copied out for the prolongation
+// onto the finer level.  The vectors of level l start at byte D.lds_z[l] and
+// D.lds_b[l] of the dynamic LDS area.
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(1024) k_tail_lds(const TailDev* __restrict__ Dp) {
+    extern __shared__ __align__(16) char tail_smem[];
+    const TailDev& D = *Dp;
+    auto zl = [&](int l) { return (S*)(tail_smem + D.lds_z[l]); };
+    auto bl = [&](int l) { return (T*)(tail_smem + D.lds_b[l]); };
+    {
+        const int64_t n0 = D.lev[D.first].box.size();
+        const T* bg = (const T*)D.b[D.first];
+        for (int64_t t = threadIdx.x; t < n0; t += blockDim.x) bl(D.first)[t] = bg[t];
+        for (int l = D.first + 1; l <= D.last; ++l)
+            for (int64_t t = threadIdx.x; t < D.lev[l].box.size(); t += blockDim.x) bl(l)[t] = (T)0;
+    }
+    for (int l = D.first; l < D.last; ++l) {
+        const LevelDev& L = D.lev[l];
+        S* z = zl(l);
+        const T* b = bl(l);
+        for (int64_t t = threadIdx.x; t < L.box.size(); t += blockDim.x) z[t] = S(0.0f);
+        __syncthreads();
+        for (int s = 0; s < D.nu_pre; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for_core<DIM>(L, [&](int i, int j, int k) { rbgs_node<T, S, DIM>(L, i, j, k, c, z, b); });
+                __syncthreads();
+            }
+        const LevelDev& C = D.lev[l + 1];
+        T* bc = bl(l + 1);
+        for_core<DIM>(C, [&](int i, int j, int k) { restrict_node<T, S, DIM>(L, C, i, j, k, z, b, bc); });
+        __syncthreads();
+    }
+    {
+        const LevelDev& L = D.lev[D.last];
+        S* z = zl(D.last);
+        for (int64_t t = threadIdx.x; t < L.box.size(); t += blockDim.x) z[t] = S(0.0f);
+        __syncthreads();
+        for (int64_t r = threadIdx.x; r < D.nc; r += blockDim.x)
+            coarse_row<T, S>(D.clist, D.nc, (const T*)D.Ainv, bl(D.last), z, r);
+        __syncthreads();
+    }
+    for (int l = D.last - 1; l >= D.first; --l) {
+        const LevelDev& L = D.lev[l];
+        const LevelDev& C = D.lev[l + 1];
+        S* z = zl(l);
+        const S* zc = zl(l + 1);
+        const T* b = bl(l);
+        for_core<DIM>(L, [&](int i, int j, int k) { prolong_node<T, S, DIM>(L, C, i, j, k, D.mode, zc, z); });
+        __syncthreads();
+        for (int s = 0; s < D.nu_post; ++s)
+            for (int c = 0; c < 2; ++c) {
+                for_core<DIM>(L, [&](int i, int j, int k) { rbgs_node<T, S, DIM>(L, i, j, k, c, z, b); });
+                __syncthreads();
+            }
+    }
+    {
+        const int64_t n0 = D.lev[D.first].box.size();
+        S* zg = (S*)D.z[D.first];
+        for (int64_t t = threadIdx.x; t < n0; t += blockDim.x) zg[t] = zl(D.first)[t];
+    }
+}
+
 // ---- fused 2D smoothing legs with LDS tiles -------------------------------------
 // Each workgroup owns a TX x TY tile of the level's core and loads it with a halo
 // of HALO nodes.  A red-black half-sweep invalidates one more ring of the loaded
@@ -896,12 +963,31 @@ bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, c
 }
 
 template <typename T, typename S>
-void run_tail(int dim, const TailDev* d_tail, hipStream_t s) {
-    if (dim == 2)
+void run_tail(int dim, const TailDev* d_tail, int64_t lds_bytes, hipStream_t s) {
+    if (lds_bytes > 0) {
+        if (lds_bytes > TAIL_LDS_MAX) throw Error(IIM_E_INTERNAL, "tail: LDS request too large");
+        if (dim == 2)
+            hipLaunchKernelGGL((k_tail_lds<T, S, 2>), dim3(1), dim3(1024), (unsigned)lds_bytes, s, d_tail);
+        else
+            hipLaunchKernelGGL((k_tail_lds<T, S, 3>), dim3(1), dim3(1024), (unsigned)lds_bytes, s, d_tail);
+    } else if (dim == 2) {
         hipLaunchKernelGGL((k_tail<T, S, 2>), dim3(1), dim3(1024), 0, s, d_tail);
-    else
+    } else {
         hipLaunchKernelGGL((k_tail<T, S, 3>), dim3(1), dim3(1024), 0, s, d_tail);
+    }
     IIM_LAUNCH_CHECK();
+}
+
+// lets every LDS-resident tail instantiation request TAIL_LDS_MAX bytes (once per process)
+void enable_tail_lds() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const void* fns[] = {(const void*)k_tail_lds<double, double, 2>, (const void*)k_tail_lds<double, double, 3>,
+                             (const void*)k_tail_lds<float, float, 2>,   (const void*)k_tail_lds<float, float, 3>,
+                             (const void*)k_tail_lds<float, __half, 2>,  (const void*)k_tail_lds<float, __half, 3>};
+        for (const void* f : fns)
+            IIM_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TAIL_LDS_MAX));
+    });
 }
 
 template <typename S>
@@ -1082,7 +1168,7 @@ void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const ui
     template void run_sw_apply<T, S>(const LevelDev&, const S*, T*, hipStream_t);                         \
     template void run_coarse_solve<T, S>(const LevelDev&, const int32_t*, int64_t, const T*, const T*, S*, \
                                          hipStream_t);                                                    \
-    template void run_tail<T, S>(int, const TailDev*, hipStream_t);                                       \
+    template void run_tail<T, S>(int, const TailDev*, int64_t, hipStream_t);                              \
     template bool run_down_fused<T, S>(const LevelDev&, const LevelDev&, const T*, S*, T*, int, hipStream_t); \
     template bool run_up_fused<T, S>(const LevelDev&, const LevelDev&, int, const S*, const T*, const S*, S*, int, \
                                      hipStream_t);
