@@ -113,7 +113,9 @@ typedef struct iim_options {
                            single-workgroup kernel (0 = library default; < 0 = coarse solve only) */
     int32_t fused_smoothing; /* 1: LDS-tiled kernels fuse each level's smoothing with its
                                 transfer (2D); 0: one kernel per half-sweep and transfer */
-    int32_t reserved;
+    int32_t colour_split;    /* 1: 3D multigrid levels above the single-workgroup kernel keep
+                                their vectors split by red-black colour (contiguous rows per
+                                colour); 0: storage-box order.  Results are identical. */
 } iim_options;
 
 typedef struct iim_stats {

@@ -49,6 +49,11 @@ struct Level {
     void* z = nullptr;   // iterate (storage type)
     void* z2 = nullptr;  // 2D: output buffer of the fused up leg (it reads z)
     void* b = nullptr;  // right-hand side (arithmetic type)
+    // layout of z, z2 and b: 0 = storage box; 1 = colour-split (3D levels
+    // above the tail), hx entries per box row and colour, half per colour
+    int split = 0, hx = 0;
+    int64_t half = 0;
+    int64_t vsize() const { return split ? 2 * half : box.size(); }
 };
 
 constexpr int64_t TAIL_MAX_NODES = 4096;  // levels handled by the one-workgroup tail kernel
@@ -102,6 +107,7 @@ struct Problem {
     int tail_first = 0;
     int64_t tail_lds_bytes = 0;  // > 0: the tail levels run in that much LDS
     bool opt_fused = true;  // LDS-tiled fused smoothing legs where available
+    bool opt_split = true;  // colour-split vectors on 3D grid levels
     TailDev* d_tail = nullptr;
     double* hpin = nullptr;  // pinned host copies of the Hessenberg columns, HCOL doubles per iteration
     bool own_hpin = true;

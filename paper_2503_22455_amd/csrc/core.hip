@@ -410,24 +410,6 @@ void Problem::setup() {
     red_scale = red_out + 4 * 64;
     const size_t tsz = opt.precision == IIM_PREC_FP64 ? sizeof(double) : sizeof(float);
     const size_t ssz = opt.precision == IIM_PREC_FP64 ? 8 : (opt.precision == IIM_PREC_MIXED32 ? 4 : 2);
-    {
-        const bool two = dim == 2 && opt_fused;
-        auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
-        size_t total = 0;
-        for (Level& L : levels) total += up256(L.box.size() * ssz) * (two ? 2 : 1) + up256(L.box.size() * tsz);
-        char* blk = (char*)mem.alloc(total);
-        IIM_HIP(hipMemsetAsync(blk, 0, total, stream));
-        for (Level& L : levels) {
-            L.z = blk;
-            blk += up256(L.box.size() * ssz);
-            L.b = blk;
-            blk += up256(L.box.size() * tsz);
-            if (two) {
-                L.z2 = blk;
-                blk += up256(L.box.size() * ssz);
-            }
-        }
-    }
     // levels small enough for the single-workgroup tail kernel
     // default: in 2D the fused LDS legs are faster than the one-workgroup tail on
     // every level but the coarsest; in 3D small levels go to the tail
@@ -435,6 +417,32 @@ void Problem::setup() {
     const int64_t tail_max = opt.tail_nodes == 0 ? tail_default : (int64_t)opt.tail_nodes;
     tail_first = nl - 1;
     while (tail_first > 0 && levels[tail_first - 1].box.size() <= tail_max) --tail_first;
+    // 3D grid levels keep their vectors colour-split: a red-black half-sweep then
+    // reads and writes whole contiguous colour rows
+    for (int l = 0; l < nl; ++l) {
+        Level& L = levels[l];
+        L.split = dim == 3 && l < tail_first && opt_split;
+        L.hx = (L.box.dims[0] + 1) / 2;
+        L.half = (int64_t)L.hx * L.box.dims[1] * L.box.dims[2];
+    }
+    {
+        const bool two = dim == 2 && opt_fused;
+        auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+        size_t total = 0;
+        for (Level& L : levels) total += up256(L.vsize() * ssz) * (two ? 2 : 1) + up256(L.vsize() * tsz);
+        char* blk = (char*)mem.alloc(total);
+        IIM_HIP(hipMemsetAsync(blk, 0, total, stream));  // entries of no node stay zero for good
+        for (Level& L : levels) {
+            L.z = blk;
+            blk += up256(L.vsize() * ssz);
+            L.b = blk;
+            blk += up256(L.vsize() * tsz);
+            if (two) {
+                L.z2 = blk;
+                blk += up256(L.vsize() * ssz);
+            }
+        }
+    }
     // the tail runs in LDS when its levels' vectors fit
     {
         int64_t off = 0;
@@ -493,6 +501,9 @@ LevelDev Problem::level_dev(int l) const {
     D.irr_index = L.irr_index;
     D.rec64 = L.rec64;
     D.rec32 = L.rec32;
+    D.split = L.split;
+    D.hx = L.hx;
+    D.half = L.half;
     return D;
 }
 
@@ -560,7 +571,7 @@ void Problem::vcycle_t(const double* v, double* out) {
         LevelDev D = level_dev(l), C = level_dev(l + 1);
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
-        run_zero<S>(z, levels[l].box.size(), stream);
+        run_zero<S>(z, levels[l].vsize(), stream);
         for (int s = 0; s < opt.nu_pre; ++s) {
             run_rbgs<T, S>(D, 0, z, b, stream);
             run_rbgs<T, S>(D, 1, z, b, stream);
@@ -846,7 +857,9 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     // per node of level 0: labels, HO and SW irregular indices, 5 work vectors,
     // the Krylov bases V (m+1) and Z (m), the V-cycle iterate and right-hand side
     const int64_t zbufs = (dim == 2 && o.fused_smoothing) ? 2 : 1;  // second iterate buffer of the fused 2D legs
-    int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8 + zbufs * ssz + tsz) + (2 * m + 1) * 64 * 8;
+    // entries of a level vector: colour-split 3D levels round each box row up to even
+    auto vec = [&](const int64_t* d) { return dim == 3 ? 2 * ((d[0] + 1) / 2) * d[1] * d[2] : d[0] * d[1] * d[2]; };
+    int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8) + vec(dims) * (zbufs * ssz + tsz) + (2 * m + 1) * 64 * 8;
     // setup transients alive together: flags, one selection output per axis and
     // the selection workspace
     bytes += N0 * (1 + 4 * dim) + (N0 / 64 + (1 << 20));
@@ -858,7 +871,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
         n = (n + 1) / 2;
         for (int d = 0; d < dim; ++d) cd[d] = (cd[d] - 4) / 2 + 1 + 2 + 2;
         last = cd[0] * cd[1] * cd[2];
-        bytes += last * (1 + 4 + zbufs * ssz + tsz);
+        bytes += last * (1 + 4) + vec(cd) * (zbufs * ssz + tsz);
     }
     // coarsest dense inverse (A, FP64 and FP32 inverses, column map)
     const int64_t nc = std::min<int64_t>(last, 4096);
@@ -903,64 +916,70 @@ int Problem::level_op_t(int l, int op, const double* in1, double* out) {
     if (op == 3 && l == 0) throw Error(IIM_E_INVALID_ARG, "no finer level");
     if (op == 4 && l != nl - 1) throw Error(IIM_E_INVALID_ARG, "coarse solve only on the coarsest level");
     if (op < 0 || op > 4) throw Error(IIM_E_INVALID_ARG, "bad op");
+    std::vector<void*> tmp;
+    auto alloc = [&](int64_t n, size_t sz) {
+        void* p = mem.alloc((size_t)std::max<int64_t>(n, 1) * sz);
+        IIM_HIP(hipMemsetAsync(p, 0, (size_t)std::max<int64_t>(n, 1) * sz, stream));
+        tmp.push_back(p);
+        return p;
+    };
+    // grid function (full grid, FP64) -> level vector of type U (level layout, scaled)
+    auto to_level = [&](int lv, const double* full, double scale, auto* dst) {
+        using U = std::remove_pointer_t<decltype(dst)>;
+        const Level& L = levels[lv];
+        const LevelDev D = level_dev(lv);
+        double* box64 = (double*)alloc(L.box.size(), sizeof(double));
+        double* lev64 = (double*)alloc(L.vsize(), sizeof(double));
+        run_full_to_box(dim, L.n, L.box, full, box64, L.labels, 1, stream);
+        run_box_to_level<double>(D, box64, lev64, stream);
+        run_convert<double, U>(lev64, dst, L.vsize(), scale, stream);
+    };
+    // level vector of type U -> grid function (zero off the level's unknowns)
+    auto from_level = [&](int lv, const auto* src, double scale, double* full) {
+        using U = std::remove_const_t<std::remove_pointer_t<decltype(src)>>;
+        const Level& L = levels[lv];
+        const LevelDev D = level_dev(lv);
+        double* lev64 = (double*)alloc(L.vsize(), sizeof(double));
+        double* box64 = (double*)alloc(L.box.size(), sizeof(double));
+        run_convert<U, double>(src, lev64, L.vsize(), scale, stream);
+        run_level_to_box<double>(D, lev64, box64, stream);
+        run_box_to_full(dim, L.n, L.box, box64, L.labels, 0.0, full, stream);
+    };
     Level& L = levels[l];
-    const int64_t bs = L.box.size();
+    const int64_t vs = L.vsize();
     const double h2 = L.h * L.h;
-    double* t64 = (double*)mem.alloc(bs * sizeof(double));
-    T* tb = (T*)mem.alloc(bs * sizeof(T));
-    S* tz = (S*)mem.alloc(bs * sizeof(S));
-    run_full_to_box(dim, L.n, L.box, in1, t64, L.labels, 1, stream);
-    LevelDev D = level_dev(l);
+    T* tb = (T*)alloc(vs, sizeof(T));
+    S* tz = (S*)alloc(vs, sizeof(S));
+    const LevelDev D = level_dev(l);
+    const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
     if (op == 0) {  // out = A_l in1
-        run_convert<double, S>(t64, tz, bs, 1.0, stream);
+        to_level(l, in1, 1.0, tz);
         run_sw_apply<T, S>(D, tz, tb, stream);
-        run_convert<T, double>(tb, t64, bs, 1.0 / h2, stream);
-        run_box_to_full(dim, L.n, L.box, t64, L.labels, 0.0, out, stream);
+        from_level(l, (const T*)tb, 1.0 / h2, out);
     } else if (op == 1) {  // one red-black sweep on out with right-hand side in1
-        run_convert<double, T>(t64, tb, bs, h2, stream);
-        run_full_to_box(dim, L.n, L.box, out, t64, L.labels, 1, stream);
-        run_convert<double, S>(t64, tz, bs, 1.0, stream);
+        to_level(l, in1, h2, tb);
+        to_level(l, out, 1.0, tz);
         run_rbgs<T, S>(D, 0, tz, tb, stream);
         run_rbgs<T, S>(D, 1, tz, tb, stream);
-        run_convert<S, double>(tz, t64, bs, 1.0, stream);
-        run_box_to_full(dim, L.n, L.box, t64, L.labels, 0.0, out, stream);
+        from_level(l, (const S*)tz, 1.0, out);
     } else if (op == 2) {  // out(l+1) = half-weighting of in1
-        Level& C = levels[l + 1];
-        run_convert<double, T>(t64, tb, bs, 1.0, stream);
-        run_zero<S>(tz, bs, stream);
-        T* cb = (T*)mem.alloc(C.box.size() * sizeof(T));
-        double* c64 = (double*)mem.alloc(C.box.size() * sizeof(double));
+        to_level(l, in1, 1.0, tb);
+        T* cb = (T*)alloc(levels[l + 1].vsize(), sizeof(T));
         run_resid_restrict<T, S>(D, level_dev(l + 1), tz, tb, cb, stream);
-        run_convert<T, double>(cb, c64, C.box.size(), 0.25, stream);
-        run_box_to_full(dim, C.n, C.box, c64, C.labels, 0.0, out, stream);
-        IIM_HIP(hipStreamSynchronize(stream));
-        mem.release(cb);
-        mem.release(c64);
+        from_level(l + 1, (const T*)cb, 0.25, out);
     } else if (op == 3) {  // out(l-1) = prolongation of in1
-        Level& F = levels[l - 1];
-        run_convert<double, S>(t64, tz, bs, 1.0, stream);
-        S* fz = (S*)mem.alloc(F.box.size() * sizeof(S));
-        double* f64 = (double*)mem.alloc(F.box.size() * sizeof(double));
-        run_zero<S>(fz, F.box.size(), stream);
-        const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+        to_level(l, in1, 1.0, tz);
+        S* fz = (S*)alloc(levels[l - 1].vsize(), sizeof(S));
         run_prolong<T, S>(level_dev(l - 1), D, mode, tz, fz, stream);
-        run_convert<S, double>(fz, f64, F.box.size(), 1.0, stream);
-        run_box_to_full(dim, F.n, F.box, f64, F.labels, 0.0, out, stream);
-        IIM_HIP(hipStreamSynchronize(stream));
-        mem.release(fz);
-        mem.release(f64);
+        from_level(l - 1, (const S*)fz, 1.0, out);
     } else {  // coarse direct solve
-        run_convert<double, T>(t64, tb, bs, h2, stream);
-        run_zero<S>(tz, bs, stream);
+        to_level(l, in1, h2, tb);
         const T* Ainv = std::is_same<T, double>::value ? (const T*)Ainv64 : (const T*)Ainv32;
         run_coarse_solve<T, S>(D, coarse_list, nc, Ainv, tb, tz, stream);
-        run_convert<S, double>(tz, t64, bs, 1.0, stream);
-        run_box_to_full(dim, L.n, L.box, t64, L.labels, 0.0, out, stream);
+        from_level(l, (const S*)tz, 1.0, out);
     }
     IIM_HIP(hipStreamSynchronize(stream));
-    mem.release(t64);
-    mem.release(tb);
-    mem.release(tz);
+    for (void* p : tmp) mem.release(p);
     return IIM_OK;
 }
 
@@ -1092,6 +1111,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     p->bc = geo->bc;
     p->params.assign(geo->params, geo->params + geo->nparams);
     p->opt_fused = o.fused_smoothing != 0;
+    p->opt_split = o.colour_split != 0;
     p->setup();
     return p;
 }
@@ -1156,6 +1176,7 @@ int iim_default_options(iim_options* o) {
     o->use_graph = 1;
     o->tail_nodes = 0;
     o->fused_smoothing = 1;
+    o->colour_split = 1;
     return IIM_OK;
 }
 

@@ -106,7 +106,20 @@ struct LevelDev {
     const int32_t* irr_index;
     const double* rec64;
     const float* rec32;
+    // Layout of the level's z and b.  split = 0: the storage box, x fastest.
+    // split = 1 (3D grid levels): two colour arrays of `half` entries each; node
+    // (i, j, k) of colour c = (i + j + k) & 1 sits at c * half + r * hx + (a >> 1),
+    // r = (j - lo_y) + dims_y (k - lo_z) its box row and a = i - lo_x, hx = (dims_x + 1) / 2.
+    int split, hx;
+    int64_t half;
 };
+// entries of a level vector and the index of node (i, j, k) in it
+__host__ __device__ inline int64_t vsize(const LevelDev& L) { return L.split ? 2 * L.half : L.box.size(); }
+__host__ __device__ inline int64_t vidx(const LevelDev& L, int i, int j, int k) {
+    if (!L.split) return L.box.idx(i, j, k);
+    const int64_t r = (int64_t)(j - L.box.lo[1]) + (int64_t)L.box.dims[1] * (k - L.box.lo[2]);
+    return (int64_t)((i + j + k) & 1) * L.half + r * L.hx + ((i - L.box.lo[0]) >> 1);
+}
 template <typename T, typename S>
 void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s);
 template <typename T, typename S>
@@ -120,6 +133,11 @@ void run_coarse_solve(const LevelDev& L, const int32_t* list, int64_t nc, const 
                       hipStream_t s);
 template <typename S>
 void run_zero(S* p, int64_t n, hipStream_t s);
+// level-vector layout conversions (identity copies for split = 0)
+template <typename U>
+void run_box_to_level(const LevelDev& L, const U* boxed, U* lev, hipStream_t s);
+template <typename U>
+void run_level_to_box(const LevelDev& L, const U* lev, U* boxed, hipStream_t s);
 
 // the levels first..last of a V-cycle (last = coarsest) in one workgroup
 constexpr int MAX_LEVELS = 16;

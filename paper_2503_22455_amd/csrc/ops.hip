@@ -394,20 +394,42 @@ template <typename T, typename S> __device__ inline void store_t(S* p, int64_t i
 }
 template <> __device__ inline void store_t<double, double>(double* p, int64_t i, double v) { p[i] = v; }
 
-// (A' z)(l) and the diagonal at an unknown l; off-diagonal sum returned in *off
+// (A' z) and the diagonal at the unknown (i, j, k) (box index l, label lab);
+// off-diagonal sum returned in *off.  Neighbour z in the level's layout.
 template <typename T, typename S, int DIM>
-__device__ inline void sw_row(const LevelDev& L, int64_t l, uint8_t lab, const S* z, T* diag, T* off) {
-    const int64_t st[3] = {1, (int64_t)L.box.dims[0], (int64_t)L.box.dims[0] * L.box.dims[1]};
+__device__ inline void sw_row(const LevelDev& L, int i, int j, int k, int64_t l, uint8_t lab, const S* z, T* diag,
+                              T* off) {
+    int64_t nm[3], np[3];  // indices of the neighbours (d, -) and (d, +)
+    if (!L.split) {
+        const int64_t st[3] = {1, (int64_t)L.box.dims[0], (int64_t)L.box.dims[0] * L.box.dims[1]};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            nm[d] = l - st[d];
+            np[d] = l + st[d];
+        }
+    } else {
+        // neighbours have the other colour: rows r, r +- 1, r +- dims_y of that array
+        const int a = i - L.box.lo[0];
+        const int64_t r = (int64_t)(j - L.box.lo[1]) + (int64_t)L.box.dims[1] * (k - L.box.lo[2]);
+        const int64_t base = (int64_t)(((i + j + k) & 1) ^ 1) * L.half + r * L.hx;
+        const int64_t ry = L.hx, rz = (int64_t)L.hx * L.box.dims[1];
+        nm[0] = base + ((a - 1) >> 1);
+        np[0] = base + ((a + 1) >> 1);
+        nm[1] = base - ry + (a >> 1);
+        np[1] = base + ry + (a >> 1);
+        nm[2] = base - rz + (a >> 1);
+        np[2] = base + rz + (a >> 1);
+    }
     T acc = 0;
     if (!(lab & F_SW_IRR)) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) acc += load_it<T, S>(z, l + st[d]) + load_it<T, S>(z, l - st[d]);
+        for (int d = 0; d < DIM; ++d) acc += load_it<T, S>(z, np[d]) + load_it<T, S>(z, nm[d]);
         *diag = (T)(-2 * DIM);
     } else {
         const T* rec = rec_ptr<T>(L) + (int64_t)L.irr_index[l] * (1 + 2 * DIM);
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
-            acc += rec[1 + 2 * d] * load_it<T, S>(z, l - st[d]) + rec[2 + 2 * d] * load_it<T, S>(z, l + st[d]);
+            acc += rec[1 + 2 * d] * load_it<T, S>(z, nm[d]) + rec[2 + 2 * d] * load_it<T, S>(z, np[d]);
         *diag = rec[0];
     }
     *off = acc;
@@ -417,47 +439,52 @@ __device__ inline void sw_row(const LevelDev& L, int64_t l, uint8_t lab, const S
 template <typename T, typename S, int DIM>
 __device__ inline void rbgs_node(const LevelDev& L, int i, int j, int k, int colour, S* z, const T* b) {
     if (((i + j + k) & 1) != colour) return;
-    int64_t l = L.box.idx(i, j, k);
-    uint8_t lab = L.labels[l];
+    const int64_t l = L.box.idx(i, j, k);
+    const uint8_t lab = L.labels[l];
     if (!is_unknown(lab)) return;
     T diag, off;
-    sw_row<T, S, DIM>(L, l, lab, z, &diag, &off);
-    if (diag != (T)0) store_t<T, S>(z, l, (b[l] - off) / diag);
+    sw_row<T, S, DIM>(L, i, j, k, l, lab, z, &diag, &off);
+    const int64_t v = vidx(L, i, j, k);
+    if (diag != (T)0) store_t<T, S>(z, v, (b[v] - off) / diag);
 }
 
 // residual of the fine level at an in-box node (zero off the unknowns)
 template <typename T, typename S, int DIM>
-__device__ inline T fine_resid(const LevelDev& F, int64_t l, const S* z, const T* b) {
-    uint8_t lab = F.labels[l];
+__device__ inline T fine_resid(const LevelDev& F, int i, int j, int k, const S* z, const T* b) {
+    const int64_t l = F.box.idx(i, j, k);
+    const uint8_t lab = F.labels[l];
     if (!is_unknown(lab)) return (T)0;
     T diag, off;
-    sw_row<T, S, DIM>(F, l, lab, z, &diag, &off);
-    return b[l] - (diag * load_it<T, S>(z, l) + off);
+    sw_row<T, S, DIM>(F, i, j, k, l, lab, z, &diag, &off);
+    const int64_t v = vidx(F, i, j, k);
+    return b[v] - (diag * load_it<T, S>(z, v) + off);
 }
 
 // coarse rhs (scaled by h_c^2 = 4 h_f^2): 4 * half-weighting of the fine residual
 template <typename T, typename S, int DIM>
 __device__ inline void restrict_node(const LevelDev& F, const LevelDev& C, int I, int J, int K, const S* z,
                                      const T* b, T* bc) {
-    int64_t lc = C.box.idx(I, J, K);
+    const int64_t lc = C.box.idx(I, J, K), vc = vidx(C, I, J, K);
     if (!is_unknown(C.labels[lc])) {
-        bc[lc] = (T)0;
+        bc[vc] = (T)0;
         return;
     }
-    const int64_t st[3] = {1, (int64_t)F.box.dims[0], (int64_t)F.box.dims[0] * F.box.dims[1]};
     const int f2[3] = {2 * I, 2 * J, 2 * K};
     for (int d = 0; d < DIM; ++d)
         if (f2[d] - 1 < F.box.lo[d] || f2[d] + 1 >= F.box.lo[d] + F.box.dims[d]) {
-            bc[lc] = (T)0;  // cannot happen: a coarse unknown is a fine unknown
+            bc[vc] = (T)0;  // cannot happen: a coarse unknown is a fine unknown
             return;
         }
-    int64_t lf = F.box.idx(2 * I, 2 * J, 2 * K);
     const T w0 = (T)0.5, w1 = DIM == 2 ? (T)0.125 : (T)(1.0 / 12.0);
-    T acc = w0 * fine_resid<T, S, DIM>(F, lf, z, b);
+    T acc = w0 * fine_resid<T, S, DIM>(F, f2[0], f2[1], f2[2], z, b);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d)
-        acc += w1 * (fine_resid<T, S, DIM>(F, lf + st[d], z, b) + fine_resid<T, S, DIM>(F, lf - st[d], z, b));
-    bc[lc] = (T)4 * acc;
+    for (int d = 0; d < DIM; ++d) {
+        int p[3] = {f2[0], f2[1], f2[2]}, m[3] = {f2[0], f2[1], f2[2]};
+        p[d] += 1;
+        m[d] -= 1;
+        acc += w1 * (fine_resid<T, S, DIM>(F, p[0], p[1], p[2], z, b) + fine_resid<T, S, DIM>(F, m[0], m[1], m[2], z, b));
+    }
+    bc[vc] = (T)4 * acc;
 }
 
 // (P z_c)(i, j, k) at a fine unknown; mode 0 = (bi/tri)linear, 1 = average of
@@ -484,7 +511,7 @@ __device__ inline bool prolong_corr(const LevelDev& C, int i, int j, int k, int 
                 bool use = mode == 0;
                 if (inb) {
                     const int64_t lp = C.box.idx(P0, P1, P2);
-                    v = load_it<T, S>(zc, lp);
+                    v = load_it<T, S>(zc, vidx(C, P0, P1, P2));
                     if (mode == 1) {
                         const uint8_t kk = C.labels[lp] & KIND_MASK;
                         use = kk == K_PLUS || kk == K_MINUS || kk == K_BOX;
@@ -506,10 +533,11 @@ __device__ inline bool prolong_corr(const LevelDev& C, int i, int j, int k, int 
 template <typename T, typename S, int DIM>
 __device__ inline void prolong_node(const LevelDev& F, const LevelDev& C, int i, int j, int k, int mode, const S* zc,
                                     S* z) {
-    int64_t l = F.box.idx(i, j, k);
+    const int64_t l = F.box.idx(i, j, k);
     if (!is_unknown(F.labels[l])) return;
     T corr;
-    if (prolong_corr<T, S, DIM>(C, i, j, k, mode, zc, &corr)) store_t<T, S>(z, l, load_it<T, S>(z, l) + corr);
+    const int64_t v = vidx(F, i, j, k);
+    if (prolong_corr<T, S, DIM>(C, i, j, k, mode, zc, &corr)) store_t<T, S>(z, v, load_it<T, S>(z, v) + corr);
 }
 
 template <typename T, typename S>
@@ -535,15 +563,28 @@ __global__ void __launch_bounds__(256) k_sw_apply(LevelDev L, const S* z, T* y) 
     int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
     int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
     if (i > L.core_hi[0] || j > L.core_hi[1]) return;
-    int64_t l = L.box.idx(i, j, k);
-    uint8_t lab = L.labels[l];
+    const int64_t l = L.box.idx(i, j, k), v = vidx(L, i, j, k);
+    const uint8_t lab = L.labels[l];
     if (!is_unknown(lab)) {
-        y[l] = (T)0;
+        y[v] = (T)0;
         return;
     }
     T diag, off;
-    sw_row<T, S, DIM>(L, l, lab, z, &diag, &off);
-    y[l] = diag * load_it<T, S>(z, l) + off;
+    sw_row<T, S, DIM>(L, i, j, k, l, lab, z, &diag, &off);
+    y[v] = diag * load_it<T, S>(z, v) + off;
+}
+
+// half-sweep on a colour-split 3D level: threads walk the colour's entries of
+// each box row contiguously (x of the colour's nodes = lo_x + 2 m + offset)
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, S* z, const T* b) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = L.core_lo[2] + blockIdx.z;
+    if (j > L.core_hi[1] || m >= L.hx) return;
+    const int i = L.box.lo[0] + 2 * m + ((colour ^ (L.box.lo[0] + j + k)) & 1);
+    if (i < L.core_lo[0] || i > L.core_hi[0]) return;
+    rbgs_node<T, S, 3>(L, i, j, k, colour, z, b);
 }
 
 template <typename T, typename S, int DIM>
@@ -1005,6 +1046,14 @@ static inline void level_grid(const LevelDev& L, dim3* grd, dim3* blk) {
 
 template <typename T, typename S>
 void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s) {
+    if (L.split) {
+        const int ny = L.core_hi[1] - L.core_lo[1] + 1, nz = L.core_hi[2] - L.core_lo[2] + 1;
+        if (ny <= 0 || nz <= 0 || L.hx <= 0) return;
+        hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3(cdiv(L.hx, 64), cdiv(ny, 4), nz), dim3(64, 4), 0, s, L, colour,
+                           z, b);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
     dim3 g, k;
     level_grid(L, &g, &k);
     if (L.dim == 2)
@@ -1075,7 +1124,13 @@ __global__ void k_cast_in(LevelDev L, const double* v, const double* scale, doub
         double val = 0.0;
         if (kk == K_PLUS) val = sc * h2 * v[l] / bp;
         else if (kk == K_MINUS) val = sc * h2 * v[l] / bm;
-        rhs[l] = (T)val;
+        int64_t dst = l;
+        if (L.split) {
+            int ijk[3];
+            L.box.coords(l, ijk);
+            dst = vidx(L, ijk[0], ijk[1], ijk[2]);
+        }
+        rhs[dst] = (T)val;
     }
 }
 
@@ -1084,7 +1139,13 @@ __global__ void k_cast_out(LevelDev L, const S* z, const double* scale, double* 
     int64_t n = L.box.size();
     double inv = 1.0 / *scale;
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x) {
-        double val = is_unknown(L.labels[l]) ? (double)load_it<double, S>(z, l) * inv : 0.0;
+        int64_t src = l;
+        if (L.split) {
+            int ijk[3];
+            L.box.coords(l, ijk);
+            src = vidx(L, ijk[0], ijk[1], ijk[2]);
+        }
+        double val = is_unknown(L.labels[l]) ? (double)load_it<double, S>(z, src) * inv : 0.0;
         out[l] = val;
     }
 }
@@ -1103,6 +1164,42 @@ void run_cast_out(const LevelDev& L, const S* z, const double* scale_dev, double
     hipLaunchKernelGGL((k_cast_out<S>), dim3(blocks), dim3(256), 0, s, L, z, scale_dev, out);
     IIM_LAUNCH_CHECK();
 }
+
+// ---------------------------------------------------------------------------
+// storage box <-> level layout
+// ---------------------------------------------------------------------------
+template <typename U>
+__global__ void k_box_level(LevelDev L, const U* src, U* dst, int to_level) {
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L.box.size();
+         l += (int64_t)gridDim.x * blockDim.x) {
+        int ijk[3];
+        L.box.coords(l, ijk);
+        const int64_t v = vidx(L, ijk[0], ijk[1], ijk[2]);
+        if (to_level) dst[v] = src[l];
+        else dst[l] = src[v];
+    }
+}
+
+template <typename U>
+void run_box_to_level(const LevelDev& L, const U* boxed, U* lev, hipStream_t s) {
+    if (L.split) IIM_HIP(hipMemsetAsync(lev, 0, vsize(L) * sizeof(U), s));  // entries of no node stay zero
+    const int blocks = (int)std::min<int64_t>(cdiv(L.box.size(), 256), 4096);
+    hipLaunchKernelGGL((k_box_level<U>), dim3(blocks), dim3(256), 0, s, L, boxed, lev, 1);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename U>
+void run_level_to_box(const LevelDev& L, const U* lev, U* boxed, hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>(cdiv(L.box.size(), 256), 4096);
+    hipLaunchKernelGGL((k_box_level<U>), dim3(blocks), dim3(256), 0, s, L, lev, boxed, 0);
+    IIM_LAUNCH_CHECK();
+}
+template void run_box_to_level<double>(const LevelDev&, const double*, double*, hipStream_t);
+template void run_box_to_level<float>(const LevelDev&, const float*, float*, hipStream_t);
+template void run_box_to_level<__half>(const LevelDev&, const __half*, __half*, hipStream_t);
+template void run_level_to_box<double>(const LevelDev&, const double*, double*, hipStream_t);
+template void run_level_to_box<float>(const LevelDev&, const float*, float*, hipStream_t);
+template void run_level_to_box<__half>(const LevelDev&, const __half*, __half*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // full grid <-> storage box

@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("coarsest_n", ctypes.c_int32), ("precision", ctypes.c_int32), ("ls_axis_t", ctypes.c_double),
                 ("ls_axis_n", ctypes.c_double), ("use_graph", ctypes.c_int32), ("tail_nodes", ctypes.c_int32),
-                ("fused_smoothing", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fused_smoothing", ctypes.c_int32), ("colour_split", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -159,7 +159,7 @@ def flat_to_grid(v: np.ndarray, dim: int, n: int) -> np.ndarray:
 def make_options(beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 1e-10, max_iters: int = 500,
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None, use_graph: bool = True,
-                 tail_nodes: int = 0, fused_smoothing: bool = True) -> Options:
+                 tail_nodes: int = 0, fused_smoothing: bool = True, colour_split: bool = True) -> Options:
     o = Options()
     lib().iim_default_options(ctypes.byref(o))
     o.beta_plus, o.beta_minus, o.rtol, o.max_iters = beta_plus, beta_minus, rtol, max_iters
@@ -168,6 +168,7 @@ def make_options(beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 
     o.use_graph = int(use_graph)
     o.tail_nodes = int(tail_nodes)
     o.fused_smoothing = int(fused_smoothing)
+    o.colour_split = int(colour_split)
     if ls_axes is not None:
         o.ls_axis_t, o.ls_axis_n = ls_axes
     return o
@@ -181,7 +182,7 @@ class Problem:
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None,
                  lo: float = -1.0, hi: float = 1.0, use_graph: bool = True, tail_nodes: int = 0,
-                 fused_smoothing: bool = True, stream=None):
+                 fused_smoothing: bool = True, colour_split: bool = True, stream=None):
         L = lib()
         self.dim, self.n = dim, n
         self.side, self.bc = side, bc
@@ -190,7 +191,7 @@ class Problem:
         pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
         geo = Geometry(geom_kind, side, bc, len(geom_params), pa)
         o = make_options(beta_plus, beta_minus, rtol, max_iters, restart, nu_pre, nu_post, coarsest_n, precision,
-                         ls_axes, use_graph, tail_nodes, fused_smoothing)
+                         ls_axes, use_graph, tail_nodes, fused_smoothing, colour_split)
         self._h = ctypes.c_void_p()
         # default: the library orders its own stream after the legacy default stream
         s = 0 if stream is None else stream

@@ -21,14 +21,17 @@ CASES = {
     "star128-beta": lambda: W.cfg2_star(128, beta_plus=0.5, beta_minus=1.0),
     "sphere24": lambda: W.cfg3_sphere(24, precision="fp64"),
     "spheres32-neu": lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union(), precision="fp64"),
+    # every level but the coarsest on the grid kernels (colour-split vectors in 3D)
+    "spheres32-neu-deep": lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union(), precision="fp64"),
 }
+OPTIONS = {"spheres32-neu-deep": dict(tail_nodes=-1)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def pair(request):
     wl = CASES[request.param]()
     O = oracle_for(wl)
-    G = gpu_for(wl, precision="fp64", rtol=1e-13)
+    G = gpu_for(wl, precision="fp64", rtol=1e-13, **OPTIONS.get(request.param, {}))
     yield request.param, wl, O, G
     G.close()
 
