@@ -421,9 +421,9 @@ void Problem::setup() {
     // reads and writes whole contiguous colour rows
     for (int l = 0; l < nl; ++l) {
         Level& L = levels[l];
-        L.split = dim == 3 && l < tail_first && opt_split;
         L.hx = (L.box.dims[0] + 1) / 2;
         L.half = (int64_t)L.hx * L.box.dims[1] * L.box.dims[2];
+        L.split = dim == 3 && l < tail_first && opt_split && 2 * L.half <= (int64_t)INT32_MAX;
     }
     {
         const bool two = dim == 2 && opt_fused;

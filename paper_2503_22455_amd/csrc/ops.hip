@@ -394,6 +394,25 @@ template <typename T, typename S> __device__ inline void store_t(S* p, int64_t i
 }
 template <> __device__ inline void store_t<double, double>(double* p, int64_t i, double v) { p[i] = v; }
 
+// Shortley-Weller row at an unknown from its neighbour values: diagonal and
+// off-diagonal sum (zm[d], zp[d] = z at the neighbours (d, -) and (d, +))
+template <typename T, int DIM>
+__device__ inline void sw_combine(const LevelDev& L, int64_t l, uint8_t lab, const T* zm, const T* zp, T* diag,
+                                  T* off) {
+    T acc = 0;
+    if (!(lab & F_SW_IRR)) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) acc += zp[d] + zm[d];
+        *diag = (T)(-2 * DIM);
+    } else {
+        const T* rec = rec_ptr<T>(L) + (int64_t)L.irr_index[l] * (1 + 2 * DIM);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) acc += rec[1 + 2 * d] * zm[d] + rec[2 + 2 * d] * zp[d];
+        *diag = rec[0];
+    }
+    *off = acc;
+}
+
 // (A' z) and the diagonal at the unknown (i, j, k) (box index l, label lab);
 // off-diagonal sum returned in *off.  Neighbour z in the level's layout.
 template <typename T, typename S, int DIM>
@@ -420,19 +439,13 @@ __device__ inline void sw_row(const LevelDev& L, int i, int j, int k, int64_t l,
         nm[2] = base - rz + (a >> 1);
         np[2] = base + rz + (a >> 1);
     }
-    T acc = 0;
-    if (!(lab & F_SW_IRR)) {
+    T zm[3], zp[3];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) acc += load_it<T, S>(z, np[d]) + load_it<T, S>(z, nm[d]);
-        *diag = (T)(-2 * DIM);
-    } else {
-        const T* rec = rec_ptr<T>(L) + (int64_t)L.irr_index[l] * (1 + 2 * DIM);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-            acc += rec[1 + 2 * d] * load_it<T, S>(z, nm[d]) + rec[2 + 2 * d] * load_it<T, S>(z, np[d]);
-        *diag = rec[0];
+    for (int d = 0; d < DIM; ++d) {
+        zm[d] = load_it<T, S>(z, nm[d]);
+        zp[d] = load_it<T, S>(z, np[d]);
     }
-    *off = acc;
+    sw_combine<T, DIM>(L, l, lab, zm, zp, diag, off);
 }
 
 // ---- per-node bodies shared by the grid kernels and the single-workgroup tail
@@ -575,7 +588,9 @@ __global__ void __launch_bounds__(256) k_sw_apply(LevelDev L, const S* z, T* y) 
 }
 
 // half-sweep on a colour-split 3D level: threads walk the colour's entries of
-// each box row contiguously (x of the colour's nodes = lo_x + 2 m + offset)
+// each box row contiguously (x of the colour's nodes = lo_x + 2 m + offset).
+// Every load is issued before the first use (the neighbours of a core node are
+// in the box), and offsets are 32-bit (level vectors hold < 2^31 entries).
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, S* z, const T* b) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
@@ -584,7 +599,28 @@ __global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, S* z
     if (j > L.core_hi[1] || m >= L.hx) return;
     const int i = L.box.lo[0] + 2 * m + ((colour ^ (L.box.lo[0] + j + k)) & 1);
     if (i < L.core_lo[0] || i > L.core_hi[0]) return;
-    rbgs_node<T, S, 3>(L, i, j, k, colour, z, b);
+    const int a = i - L.box.lo[0];
+    const int r = (j - L.box.lo[1]) + L.box.dims[1] * (k - L.box.lo[2]);
+    const int l = a + L.box.dims[0] * r;
+    const int own = colour * (int)L.half + r * L.hx + m;
+    const int base = (colour ^ 1) * (int)L.half + r * L.hx;
+    const int ry = L.hx, rz = L.hx * L.box.dims[1];
+    const uint8_t lab = L.labels[l];
+    const T bv = b[own];
+    T zm[3], zp[3];
+    zm[0] = load_it<T, S>(z, base + ((a - 1) >> 1));
+    zp[0] = load_it<T, S>(z, base + ((a + 1) >> 1));
+    zm[1] = load_it<T, S>(z, base - ry + m);
+    zp[1] = load_it<T, S>(z, base + ry + m);
+    zm[2] = load_it<T, S>(z, base - rz + m);
+    zp[2] = load_it<T, S>(z, base + rz + m);
+    // keep the loads ahead of the label test (the compiler would otherwise sink
+    // them below it and serialise two memory round trips)
+    asm volatile("" ::"v"(bv), "v"(zm[0]), "v"(zp[0]), "v"(zm[1]), "v"(zp[1]), "v"(zm[2]), "v"(zp[2]));
+    if (!is_unknown(lab)) return;
+    T diag, off;
+    sw_combine<T, 3>(L, l, lab, zm, zp, &diag, &off);
+    if (diag != (T)0) store_t<T, S>(z, own, (bv - off) / diag);
 }
 
 template <typename T, typename S, int DIM>
@@ -603,6 +639,161 @@ __global__ void __launch_bounds__(256) k_prolong(LevelDev F, LevelDev C, int mod
     int k = DIM == 3 ? F.core_lo[2] + blockIdx.z : 0;
     if (i > F.core_hi[0] || j > F.core_hi[1]) return;
     prolong_node<T, S, DIM>(F, C, i, j, k, mode, zc, z);
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// 3D prolongation by coarse cells: the thread of cell (I, J, K) loads the cell's
+// eight coarse corners once and corrects the fine nodes 2I + {0,1}, 2J + {0,1},
+// 2K + {0,1} (all inside the fine box).  Same parents, weights and summation
+// order as prolong_corr.  Every load is issued before the first test.
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, int mode, int I0, int J0, int K0,
+                                                        int nI, int nJ, const S* zc, S* z) {
+    const int I = I0 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = J0 + blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = K0 + blockIdx.z;
+    if (I >= I0 + nI || J >= J0 + nJ) return;
+    T v[2][2][2];
+    uint8_t clab[2][2][2];
+    bool inb[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+            for (int cq = 0; cq < 2; ++cq) {
+                const int P[3] = {I + a, J + bq, K + cq};
+                int Q[3];
+                bool in = true;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    in = in && P[d] >= C.box.lo[d] && P[d] < C.box.lo[d] + C.box.dims[d];
+                    Q[d] = clampi(P[d], C.box.lo[d], C.box.lo[d] + C.box.dims[d] - 1);
+                }
+                inb[a][bq][cq] = in;
+                v[a][bq][cq] = load_it<T, S>(zc, vidx(C, Q[0], Q[1], Q[2]));
+                clab[a][bq][cq] = mode == 1 ? C.labels[C.box.idx(Q[0], Q[1], Q[2])] : (uint8_t)0;
+            }
+    uint8_t flab[2][2][2];
+    T fz[2][2][2];
+#pragma unroll
+    for (int fc = 0; fc < 2; ++fc)
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+            for (int fa = 0; fa < 2; ++fa) {
+                const int i = 2 * I + fa, j = 2 * J + fb, k = 2 * K + fc;
+                flab[fa][fb][fc] = F.labels[F.box.idx(i, j, k)];
+                fz[fa][fb][fc] = load_it<T, S>(z, vidx(F, i, j, k));
+            }
+    asm volatile("" ::"v"(v[0][0][0]), "v"(v[1][1][1]), "v"(fz[0][0][0]), "v"(fz[1][1][1]));
+    bool use[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+            for (int cq = 0; cq < 2; ++cq) {
+                const uint8_t kk = clab[a][bq][cq] & KIND_MASK;
+                use[a][bq][cq] = mode == 0 || (inb[a][bq][cq] && (kk == K_PLUS || kk == K_MINUS || kk == K_BOX));
+                if (!inb[a][bq][cq]) v[a][bq][cq] = 0;
+            }
+#pragma unroll
+    for (int fc = 0; fc < 2; ++fc)
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb)
+#pragma unroll
+            for (int fa = 0; fa < 2; ++fa) {
+                const int i = 2 * I + fa, j = 2 * J + fb, k = 2 * K + fc;
+                if (i < F.core_lo[0] || i > F.core_hi[0] || j < F.core_lo[1] || j > F.core_hi[1] ||
+                    k < F.core_lo[2] || k > F.core_hi[2])
+                    continue;
+                if (!is_unknown(flab[fa][fb][fc])) continue;
+                T sum = 0;
+                int cnt = 0;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+                        for (int cq = 0; cq < 2; ++cq) {
+                            if (a > fa || bq > fb || cq > fc) continue;
+                            if (use[a][bq][cq]) {
+                                sum += v[a][bq][cq];
+                                cnt += 1;
+                            }
+                        }
+                if (cnt == 0) continue;
+                store_t<T, S>(z, vidx(F, i, j, k), fz[fa][fb][fc] + sum / (T)cnt);
+            }
+}
+
+// 3D residual + restriction: the thread of coarse node (I, J, K) evaluates the
+// fine residual at c = (2I, 2J, 2K) and its six neighbours from the 25 fine
+// values they share, loaded once and all before the first test.  Coordinates
+// are clamped into the fine box; a clamped value is only ever used by a node
+// that is not an unknown (an unknown's neighbours lie in the box), whose
+// residual is zero.  Same weights and summation order as restrict_node.
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, const S* z, const T* b, T* bc) {
+    const int I = C.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = C.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = C.core_lo[2] + blockIdx.z;
+    if (I > C.core_hi[0] || J > C.core_hi[1] || K > C.core_hi[2]) return;
+    const int c[3] = {2 * I, 2 * J, 2 * K};
+    int X[3][5];  // clamped coordinates c[d] - 2 .. c[d] + 2
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int o = 0; o < 5; ++o) X[d][o] = clampi(c[d] + o - 2, F.box.lo[d], F.box.lo[d] + F.box.dims[d] - 1);
+    auto zat = [&](int ox, int oy, int oz) { return load_it<T, S>(z, vidx(F, X[0][ox + 2], X[1][oy + 2], X[2][oz + 2])); };
+    // the seven residual nodes: 0 = c, 1 + 2d = c + e_d, 2 + 2d = c - e_d
+    const int off[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    const uint8_t labc = C.labels[C.box.idx(I, J, K)];
+    uint8_t lab[7];
+    T bv[7], zc[7], zm[7][3], zp[7][3];
+    int lbox[7];
+#pragma unroll
+    for (int n = 0; n < 7; ++n) {
+        const int ox = off[n][0], oy = off[n][1], oz = off[n][2];
+        const int xi = X[0][ox + 2], yi = X[1][oy + 2], zi = X[2][oz + 2];
+        lbox[n] = (int)F.box.idx(xi, yi, zi);
+        lab[n] = F.labels[lbox[n]];
+        bv[n] = b[vidx(F, xi, yi, zi)];
+        zc[n] = zat(ox, oy, oz);
+        zm[n][0] = zat(ox - 1, oy, oz);
+        zp[n][0] = zat(ox + 1, oy, oz);
+        zm[n][1] = zat(ox, oy - 1, oz);
+        zp[n][1] = zat(ox, oy + 1, oz);
+        zm[n][2] = zat(ox, oy, oz - 1);
+        zp[n][2] = zat(ox, oy, oz + 1);
+    }
+    asm volatile("" ::"v"(bv[0]), "v"(zc[0]), "v"(zm[1][0]), "v"(zp[2][0]), "v"(zm[5][2]), "v"(zp[6][2]));
+    const int64_t vc = vidx(C, I, J, K);
+    bool inside = is_unknown(labc);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        inside = inside && c[d] - 1 >= F.box.lo[d] && c[d] + 1 < F.box.lo[d] + F.box.dims[d];
+    if (!inside) {
+        bc[vc] = (T)0;
+        return;
+    }
+    T r[7];
+#pragma unroll
+    for (int n = 0; n < 7; ++n) {
+        r[n] = (T)0;
+        if (is_unknown(lab[n])) {
+            T diag, offd;
+            sw_combine<T, 3>(F, lbox[n], lab[n], zm[n], zp[n], &diag, &offd);
+            r[n] = bv[n] - (diag * zc[n] + offd);
+        }
+    }
+    const T w0 = (T)0.5, w1 = (T)(1.0 / 12.0);
+    T acc = w0 * r[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc += w1 * (r[1 + 2 * d] + r[2 + 2 * d]);
+    bc[vc] = (T)4 * acc;
 }
 
 template <typename T, typename S>
@@ -1081,18 +1272,28 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
     if (F.dim == 2)
         hipLaunchKernelGGL((k_resid_restrict<T, S, 2>), g, k, 0, s, F, C, z, b, bc);
     else
-        hipLaunchKernelGGL((k_resid_restrict<T, S, 3>), g, k, 0, s, F, C, z, b, bc);
+        hipLaunchKernelGGL((k_restrict3<T, S>), g, k, 0, s, F, C, z, b, bc);
     IIM_LAUNCH_CHECK();
 }
 
 template <typename T, typename S>
 void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S* z, hipStream_t s) {
+    if (F.dim == 3) {
+        // coarse cells whose fine nodes meet the fine core
+        int c0[3], nc[3];
+        for (int d = 0; d < 3; ++d) {
+            c0[d] = F.core_lo[d] >> 1;
+            nc[d] = (F.core_hi[d] >> 1) - c0[d] + 1;
+            if (F.core_hi[d] < F.core_lo[d]) return;
+        }
+        hipLaunchKernelGGL((k_prolong_cells<T, S>), dim3(cdiv(nc[0], 64), cdiv(nc[1], 4), nc[2]), dim3(64, 4), 0, s,
+                           F, C, mode, c0[0], c0[1], c0[2], nc[0], nc[1], zc, z);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
     dim3 g, k;
     level_grid(F, &g, &k);
-    if (F.dim == 2)
-        hipLaunchKernelGGL((k_prolong<T, S, 2>), g, k, 0, s, F, C, mode, zc, z);
-    else
-        hipLaunchKernelGGL((k_prolong<T, S, 3>), g, k, 0, s, F, C, mode, zc, z);
+    hipLaunchKernelGGL((k_prolong<T, S, 2>), g, k, 0, s, F, C, mode, zc, z);
     IIM_LAUNCH_CHECK();
 }
 
