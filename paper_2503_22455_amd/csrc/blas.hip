@@ -205,6 +205,71 @@ void run_update_dot(const double* V, int64_t ld, int k, const double* h, double*
     final_sum(part, k2 + (with_norm ? 1 : 0), out, s);
 }
 
+// Second classical Gram-Schmidt pass fused with the normalisation:
+//   y = (w - sum_i h_i V_i) / sqrt(nrm2),  nrm2 = h[k] - sum_i h_i^2,
+// where h[0..k-1] = V^T w and h[k] = |w|^2 come from the pass that made w.  With
+// V orthonormal, |w - V h|^2 = |w|^2 - |h|^2 (Pythagoras); after a first pass h
+// is a rounding-level correction, so the difference does not cancel.  nrm2 is
+// floored at 0 (then y is not finite and the solver takes it as a breakdown)
+// and written to *nrm2_out; block maxima of |y| go to part (the V-cycle's
+// scaling of y is then one second-stage launch away).
+__global__ void __launch_bounds__(RED_THREADS) k_update_scale(const double* V, int64_t ld, int k, const double* h,
+                                                              const double* w, double* y, int64_t n, double* nrm2_out,
+                                                              double* part) {
+    double hh[KCH];
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < KCH; ++i) {
+        hh[i] = i < k ? h[i] : 0.0;
+        ss += hh[i] * hh[i];
+    }
+    const double nrm2 = fmax(h[k] - ss, 0.0);
+    const double inv = 1.0 / sqrt(nrm2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nrm2_out = nrm2;
+    double mx[1] = {0.0};
+    const int64_t np = n >> 1;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 we = ld2(w, e);
+        double2 v[KCH];
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) v[i] = ld2(V + (int64_t)i * ld, e);
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) {
+                we.x -= hh[i] * v[i].x;
+                we.y -= hh[i] * v[i].y;
+            }
+        we.x *= inv;
+        we.y *= inv;
+        st2(y, e, we);
+        mx[0] = fmax(mx[0], fmax(fabs(we.x), fabs(we.y)));
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t e = n - 1;
+        double we = w[e];
+#pragma unroll
+        for (int i = 0; i < KCH; ++i)
+            if (i < k) we -= hh[i] * V[(int64_t)i * ld + e];
+        we *= inv;
+        y[e] = we;
+        mx[0] = fmax(mx[0], fabs(we));
+    }
+    block_reduce_store(mx, 1, part, 1);
+}
+
+void run_update_scale(const double* V, int64_t ld, int k, const double* h, const double* w, double* y, int64_t n,
+                      double* nrm2_out, double* part, double* scale_out, hipStream_t s) {
+    if (k < 1 || k > KCH) throw Error(IIM_E_INVALID_ARG, "update_scale: 1..12 vectors");
+    check_vec(V, ld);
+    check_vec(w, 0);
+    check_vec(y, 0);
+    hipLaunchKernelGGL(k_update_scale, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, y, n, nrm2_out,
+                       part);
+    IIM_LAUNCH_CHECK();
+    final_sum(part, 1, scale_out, s, 1);
+}
+
 static int stream_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n / 2 + 1, 256), 8192)); }
 
 __global__ void __launch_bounds__(256) k_normalize(const double* x, const double* nrm2, double* y, int64_t n) {

@@ -121,8 +121,9 @@ struct Problem {
     void apply_box(const double* x, double* y, int with_data);
     template <typename T, typename S> bool down_leg(int l);
     template <typename T, typename S> const S* up_leg(int l, const S* zres);
-    template <typename T, typename S> void vcycle_t(const double* v, double* out);
-    void vcycle(const double* v, double* out);
+    // scaled: red_scale already holds max |v| (the fused orthogonalisation wrote it)
+    template <typename T, typename S> void vcycle_t(const double* v, double* out, bool scaled);
+    void vcycle(const double* v, double* out, bool scaled = false);
     void iteration_body(int j, hipEvent_t* evs = nullptr);
     int solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st);
     int level_op(int level, int op, const double* in1, double* out);

@@ -560,11 +560,11 @@ const S* Problem::up_leg(int l, const S* zres) {
 }
 
 template <typename T, typename S>
-void Problem::vcycle_t(const double* v, double* out) {
+void Problem::vcycle_t(const double* v, double* out, bool scaled) {
     const int nl = (int)levels.size();
     const int t = tail_first;
     LevelDev D0 = level_dev(0);
-    run_absmax(v, box.size(), red_part, red_scale, stream);
+    if (!scaled) run_absmax(v, box.size(), red_part, red_scale, stream);
     run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
     for (int l = 0; l < t; ++l) {
         if (down_leg<T, S>(l)) continue;
@@ -600,13 +600,13 @@ void Problem::vcycle_t(const double* v, double* out) {
     run_cast_out<S>(D0, zres, red_scale + 1, out, stream);
 }
 
-void Problem::vcycle(const double* v, double* out) {
+void Problem::vcycle(const double* v, double* out, bool scaled) {
     if (opt.precision == IIM_PREC_FP64)
-        vcycle_t<double, double>(v, out);
+        vcycle_t<double, double>(v, out, scaled);
     else if (opt.precision == IIM_PREC_MIXED32)
-        vcycle_t<float, float>(v, out);
+        vcycle_t<float, float>(v, out, scaled);
     else
-        vcycle_t<float, __half>(v, out);
+        vcycle_t<float, __half>(v, out, scaled);
 }
 
 // One inner FGMRES iteration on the device: z_j = M^{-1} v_j, w = A z_j, CGS2
@@ -616,14 +616,16 @@ void Problem::iteration_body(int j, hipEvent_t* evs) {
     const int64_t N = box.size();
     double* vj = Vb + (size_t)j * ldv;
     double* zj = Zb + (size_t)j * ldv;
-    vcycle(vj, zj);
+    vcycle(vj, zj, j > 0);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
     if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
     apply_box(zj, wk, 0);
     if (evs) IIM_HIP(hipEventRecord(evs[2], stream));
+    // CGS2: h = V^T w; w -= V h with h' = V^T w and |w|^2 in the same pass; then
+    // v_{j+1} = (w - V h') / |w - V h'|, the norm by Pythagoras
     run_multidot(Vb, ldv, j + 1, wk, N, red_part, red_out, stream);
-    run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 0, red_part, red_out + 64, stream);
-    run_update_dot(Vb, ldv, j + 1, red_out + 64, wk, N, 0, 1, red_part, red_out + 128, stream);
-    run_normalize(wk, red_out + 128, Vb + (size_t)(j + 1) * ldv, N, stream);
+    run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 1, red_part, red_out + 64, stream);
+    run_update_scale(Vb, ldv, j + 1, red_out + 64, wk, Vb + (size_t)(j + 1) * ldv, N, red_out + 128, red_part,
+                     red_scale, stream);
     IIM_HIP(hipMemcpyAsync(hpin + (size_t)j * HCOL, red_out, HCOL * sizeof(double), hipMemcpyDeviceToHost, stream));
 }
 

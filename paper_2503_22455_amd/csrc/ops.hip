@@ -205,6 +205,16 @@ __device__ inline int xcd_tile(int bid, int nb) {
     return xcd * per + min(xcd, rem) + idx;
 }
 
+// (x, y, z) block coordinates of a one-dimensional launch of gx * gy * gz
+// blocks, taken in XCD-contiguous order (x fastest)
+struct Blk3 {
+    int x, y, z;
+};
+__device__ inline Blk3 xcd_block3(int gx, int gy) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    return {t % gx, (t / gx) % gy, t / (gx * gy)};
+}
+
 // 3D apply of the regular unknowns, marching along z.  A block of 64 x 4
 // threads owns a 64 x 16 tile of (x, y) columns (each thread 4 rows) and a
 // chunk of zc planes.  The z-neighbours of each column stay in a register
@@ -592,10 +602,11 @@ __global__ void __launch_bounds__(256) k_sw_apply(LevelDev L, const S* z, T* y) 
 // Every load is issued before the first use (the neighbours of a core node are
 // in the box), and offsets are 32-bit (level vectors hold < 2^31 entries).
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, S* z, const T* b) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = L.core_lo[2] + blockIdx.z;
+__global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, int gx, int gy, S* z, const T* b) {
+    const Blk3 B = xcd_block3(gx, gy);
+    const int m = B.x * 64 + (threadIdx.x & 63);
+    const int j = L.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
+    const int k = L.core_lo[2] + B.z;
     if (j > L.core_hi[1] || m >= L.hx) return;
     const int i = L.box.lo[0] + 2 * m + ((colour ^ (L.box.lo[0] + j + k)) & 1);
     if (i < L.core_lo[0] || i > L.core_hi[0]) return;
@@ -650,9 +661,10 @@ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > 
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, int mode, int I0, int J0, int K0,
                                                         int nI, int nJ, const S* zc, S* z) {
-    const int I = I0 + blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = J0 + blockIdx.y * blockDim.y + threadIdx.y;
-    const int K = K0 + blockIdx.z;
+    const Blk3 B = xcd_block3((nI + 63) / 64, (nJ + 3) / 4);
+    const int I = I0 + B.x * 64 + (threadIdx.x & 63);
+    const int J = J0 + B.y * 4 + (threadIdx.x >> 6);
+    const int K = K0 + B.z;
     if (I >= I0 + nI || J >= J0 + nJ) return;
     T v[2][2][2];
     uint8_t clab[2][2][2];
@@ -736,10 +748,12 @@ __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, i
 // that is not an unknown (an unknown's neighbours lie in the box), whose
 // residual is zero.  Same weights and summation order as restrict_node.
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, const S* z, const T* b, T* bc) {
-    const int I = C.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = C.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
-    const int K = C.core_lo[2] + blockIdx.z;
+__global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int gx, int gy, const S* z, const T* b,
+                                                    T* bc) {
+    const Blk3 B = xcd_block3(gx, gy);
+    const int I = C.core_lo[0] + B.x * 64 + (threadIdx.x & 63);
+    const int J = C.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
+    const int K = C.core_lo[2] + B.z;
     if (I > C.core_hi[0] || J > C.core_hi[1] || K > C.core_hi[2]) return;
     const int c[3] = {2 * I, 2 * J, 2 * K};
     int X[3][5];  // clamped coordinates c[d] - 2 .. c[d] + 2
@@ -1240,8 +1254,8 @@ void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s) {
     if (L.split) {
         const int ny = L.core_hi[1] - L.core_lo[1] + 1, nz = L.core_hi[2] - L.core_lo[2] + 1;
         if (ny <= 0 || nz <= 0 || L.hx <= 0) return;
-        hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3(cdiv(L.hx, 64), cdiv(ny, 4), nz), dim3(64, 4), 0, s, L, colour,
-                           z, b);
+        const int gx = cdiv(L.hx, 64), gy = cdiv(ny, 4);
+        hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, colour, gx, gy, z, b);
         IIM_LAUNCH_CHECK();
         return;
     }
@@ -1272,7 +1286,8 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
     if (F.dim == 2)
         hipLaunchKernelGGL((k_resid_restrict<T, S, 2>), g, k, 0, s, F, C, z, b, bc);
     else
-        hipLaunchKernelGGL((k_restrict3<T, S>), g, k, 0, s, F, C, z, b, bc);
+        hipLaunchKernelGGL((k_restrict3<T, S>), dim3(g.x * g.y * g.z), dim3(256), 0, s, F, C, (int)g.x, (int)g.y, z, b,
+                           bc);
     IIM_LAUNCH_CHECK();
 }
 
@@ -1286,7 +1301,7 @@ void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S*
             nc[d] = (F.core_hi[d] >> 1) - c0[d] + 1;
             if (F.core_hi[d] < F.core_lo[d]) return;
         }
-        hipLaunchKernelGGL((k_prolong_cells<T, S>), dim3(cdiv(nc[0], 64), cdiv(nc[1], 4), nc[2]), dim3(64, 4), 0, s,
+        hipLaunchKernelGGL((k_prolong_cells<T, S>), dim3(cdiv(nc[0], 64) * cdiv(nc[1], 4) * nc[2]), dim3(256), 0, s,
                            F, C, mode, c0[0], c0[1], c0[2], nc[0], nc[1], zc, z);
         IIM_LAUNCH_CHECK();
         return;
@@ -1325,13 +1340,7 @@ __global__ void k_cast_in(LevelDev L, const double* v, const double* scale, doub
         double val = 0.0;
         if (kk == K_PLUS) val = sc * h2 * v[l] / bp;
         else if (kk == K_MINUS) val = sc * h2 * v[l] / bm;
-        int64_t dst = l;
-        if (L.split) {
-            int ijk[3];
-            L.box.coords(l, ijk);
-            dst = vidx(L, ijk[0], ijk[1], ijk[2]);
-        }
-        rhs[dst] = (T)val;
+        rhs[l] = (T)val;
     }
 }
 
@@ -1340,20 +1349,75 @@ __global__ void k_cast_out(LevelDev L, const S* z, const double* scale, double* 
     int64_t n = L.box.size();
     double inv = 1.0 / *scale;
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < n; l += (int64_t)gridDim.x * blockDim.x) {
-        int64_t src = l;
-        if (L.split) {
-            int ijk[3];
-            L.box.coords(l, ijk);
-            src = vidx(L, ijk[0], ijk[1], ijk[2]);
-        }
-        double val = is_unknown(L.labels[l]) ? (double)load_it<double, S>(z, src) * inv : 0.0;
+        double val = is_unknown(L.labels[l]) ? (double)load_it<double, S>(z, l) * inv : 0.0;
         out[l] = val;
     }
+}
+
+// Colour-split level: a block covers 64 entries of two box rows in both
+// colours (wavefront g: colour g & 1, row 2 * pair + (g >> 1)), so the
+// box-order reads and writes of a row are shared by two wavefronts of a block.
+struct SplitEntry {
+    bool ok;     // entry inside the vector
+    bool node;   // entry holds a node of the box
+    int64_t l;   // box index of that node
+    int64_t v;   // index in the level vector
+};
+__device__ inline SplitEntry split_entry(const LevelDev& L, int gxm) {
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int chunk = blockIdx.x % gxm, pair = blockIdx.x / gxm;
+    const int m = chunk * 64 + lane, r = 2 * pair + (g >> 1), colour = g & 1;
+    const int nrows = L.box.dims[1] * L.box.dims[2];
+    SplitEntry e{false, false, 0, 0};
+    if (m >= L.hx || r >= nrows) return e;
+    const int j = L.box.lo[1] + r % L.box.dims[1], k = L.box.lo[2] + r / L.box.dims[1];
+    const int a = 2 * m + ((colour ^ (L.box.lo[0] + j + k)) & 1);
+    e.ok = true;
+    e.node = a < L.box.dims[0];
+    e.l = (int64_t)a + (int64_t)L.box.dims[0] * r;
+    e.v = (int64_t)colour * L.half + (int64_t)r * L.hx + m;
+    return e;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cast_in_split(LevelDev L, int gxm, const double* v, const double* scale,
+                                                       double h2, double bp, double bm, T* rhs) {
+    const SplitEntry e = split_entry(L, gxm);
+    if (!e.ok) return;
+    double val = 0.0;
+    if (e.node) {
+        const uint8_t kk = L.labels[e.l] & KIND_MASK;
+        const double sc = *scale;
+        if (kk == K_PLUS) val = sc * h2 * v[e.l] / bp;
+        else if (kk == K_MINUS) val = sc * h2 * v[e.l] / bm;
+    }
+    rhs[e.v] = (T)val;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_cast_out_split(LevelDev L, int gxm, const S* z, const double* scale,
+                                                        double* out) {
+    const SplitEntry e = split_entry(L, gxm);
+    if (!e.ok || !e.node) return;
+    const double inv = 1.0 / *scale;
+    out[e.l] = is_unknown(L.labels[e.l]) ? (double)load_it<double, S>(z, e.v) * inv : 0.0;
+}
+
+static inline int split_blocks(const LevelDev& L, int* gxm) {
+    *gxm = cdiv(L.hx, 64);
+    return *gxm * cdiv((int64_t)L.box.dims[1] * L.box.dims[2], 2);
 }
 
 template <typename T>
 void run_cast_in(const LevelDev& L, const double* v, const double* scale_dev, double h2, double bp, double bm, T* rhs,
                  hipStream_t s) {
+    if (L.split) {
+        int gxm;
+        const int nb = split_blocks(L, &gxm);
+        hipLaunchKernelGGL((k_cast_in_split<T>), dim3(nb), dim3(256), 0, s, L, gxm, v, scale_dev, h2, bp, bm, rhs);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
     int blocks = (int)std::min<int64_t>(cdiv(L.box.size(), 256), 4096);
     hipLaunchKernelGGL((k_cast_in<T>), dim3(blocks), dim3(256), 0, s, L, v, scale_dev, h2, bp, bm, rhs);
     IIM_LAUNCH_CHECK();
@@ -1361,6 +1425,13 @@ void run_cast_in(const LevelDev& L, const double* v, const double* scale_dev, do
 
 template <typename S>
 void run_cast_out(const LevelDev& L, const S* z, const double* scale_dev, double* out, hipStream_t s) {
+    if (L.split) {
+        int gxm;
+        const int nb = split_blocks(L, &gxm);
+        hipLaunchKernelGGL((k_cast_out_split<S>), dim3(nb), dim3(256), 0, s, L, gxm, z, scale_dev, out);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
     int blocks = (int)std::min<int64_t>(cdiv(L.box.size(), 256), 4096);
     hipLaunchKernelGGL((k_cast_out<S>), dim3(blocks), dim3(256), 0, s, L, z, scale_dev, out);
     IIM_LAUNCH_CHECK();
