@@ -108,7 +108,10 @@ typedef struct iim_options {
     int32_t precision;  /* IIM_PREC_* */
     double ls_axis_t;   /* least-squares half-ellipse semi-axes in units of h */
     double ls_axis_n;   /*   (0 = defaults k and k - 1/2) */
-    int32_t use_graph;  /* replay each FGMRES iteration as a captured HIP graph (1) or launch eagerly (0) */
+    int32_t use_graph;  /* launching of the FGMRES iterations: 2 (default) eager launches, iteration
+                           j+1 queued before the host reads column j; 1 the same with each
+                           iteration replayed as a captured HIP graph; 0 eager, one iteration at
+                           a time, with the per-phase GPU times of iim_stats filled in */
     int32_t tail_nodes; /* levels whose storage box has at most this many nodes run in one
                            single-workgroup kernel (0 = library default; < 0 = coarse solve only) */
     int32_t fused_smoothing; /* 1: LDS-tiled kernels fuse each level's smoothing with its
@@ -125,9 +128,10 @@ typedef struct iim_stats {
     int32_t hist_len;      /* entries written to the history */
     double final_rel_residual; /* true ||b - L u|| / ||b|| at exit */
     double t_solve_ms;     /* wall time of the solve (host clock) */
-    double t_apply_ms;     /* GPU time in the high-order operator */
-    double t_vcycle_ms;    /* GPU time in the preconditioner */
-    double t_krylov_ms;    /* GPU time in orthogonalisation and updates */
+    double t_apply_ms;     /* GPU time in the high-order operator (use_graph = 0 only) */
+    double t_vcycle_ms;    /* GPU time in the preconditioner (use_graph = 0 only) */
+    double t_krylov_ms;    /* GPU time in orthogonalisation and updates (use_graph = 0);
+                              otherwise the GPU time of the whole restart cycles */
 } iim_stats;
 
 typedef struct iim_info {
@@ -155,10 +159,11 @@ int iim_default_options(iim_options* opt);
 int iim_create(const iim_grid* grid, const iim_geometry* geom, const iim_options* opt,
                void* stream, iim_problem** out);
 
-/* Releases all device memory of the handle (NULL is ignored).  Device memory
- * comes from the device's default stream-ordered memory pool; freed blocks stay
- * cached in that pool for later handles of the process (iim_server_destroy
- * hands unused blocks back to the device). */
+/* Waits for the handle's stream, then releases all its device memory (NULL is
+ * ignored).  Device memory comes from the device's default stream-ordered
+ * memory pool; released blocks stay cached in the process for later handles on
+ * the same device (iim_server_destroy hands idle blocks back to the device, and
+ * an allocation that finds the device full does so before it fails). */
 void iim_destroy(iim_problem* p);
 
 /* Thread-local message of the last failing call ("" if none). */

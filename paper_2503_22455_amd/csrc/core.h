@@ -16,22 +16,32 @@ const char* last_error();
 // ordered (hipMallocAsync / hipFreeAsync on the handle's stream) from the
 // device's default memory pool, so that setup and teardown of one handle never
 // synchronise the device while other handles are solving on other streams.
+// Device memory of one handle.  Blocks come from a process-wide cache of idle
+// blocks (per device) or, when none fits, from the device's stream-ordered
+// pool.  A block the handle releases while alive is kept for the handle's own
+// later allocations (its work is ordered on the handle's one stream); when the
+// handle ends, after its stream has drained, all its blocks return to the
+// process cache.  hipMallocAsync / hipFreeAsync calls cost tens to hundreds of
+// microseconds each, which dominated setup and teardown of small problems.
 struct DevMem {
     struct Block {
         void* p;
-        size_t bytes;
+        size_t bytes;  // size of the block (>= the request)
     };
-    std::vector<Block> blocks;
+    std::vector<Block> blocks;  // live
+    std::vector<Block> spare;   // released by this handle, reusable by it
     hipStream_t stream = nullptr;
-    size_t current = 0, peak = 0;
+    int device = 0;
+    size_t current = 0, peak = 0;  // bytes of live blocks
     void* alloc(size_t bytes);
     void release(void* p);
-    void release_all();  // stream-ordered frees of every live block
+    void release_all();  // drains the stream, then hands every block to the process cache
     ~DevMem();
 };
 
 // keeps freed pool memory cached in the process (set once per device)
 void configure_pool(int device);
+// frees the process cache of idle blocks of the current device and trims its pool
 void trim_pool();
 
 struct Level {

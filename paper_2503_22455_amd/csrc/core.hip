@@ -5,6 +5,7 @@
 #include <type_traits>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -36,41 +37,100 @@ void configure_pool(int device) {
     done[device] = true;
 }
 
+// process-wide idle blocks, per device, by size
+static std::mutex g_cache_mu;
+static std::multimap<size_t, void*> g_cache[64];
+
+// a cached block of `have` bytes serves a request of `want` bytes when the
+// excess stays small (exact sizes recur: the same problem set up again)
+static bool fits(size_t have, size_t want) { return have >= want && have - want <= want / 16 + 65536; }
+
+static size_t cache_free_all(int dev) {
+    std::multimap<size_t, void*> take;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        take.swap(g_cache[dev]);
+    }
+    size_t n = 0;
+    for (auto& kv : take) {
+        (void)hipFreeAsync(kv.second, nullptr);  // idle blocks: no pending work
+        n += kv.first;
+    }
+    if (n) (void)hipStreamSynchronize(nullptr);  // back in the pool before anyone allocates again
+    return n;
+}
+
 void trim_pool() {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    cache_free_all(dev);
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
 }
 
 void* DevMem::alloc(size_t bytes) {
-    if (bytes == 0) bytes = 8;
+    bytes = (std::max<size_t>(bytes, 8) + 255) / 256 * 256;
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, bytes, stream);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error(e == hipErrorOutOfMemory ? IIM_E_BUDGET : IIM_E_DEVICE,
-                    std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    size_t got = 0;
+    // the handle's own released blocks first, then the process cache (best fit)
+    size_t best = SIZE_MAX;
+    for (size_t i = 0; i < spare.size(); ++i)
+        if (fits(spare[i].bytes, bytes) && (best == SIZE_MAX || spare[i].bytes < spare[best].bytes)) best = i;
+    if (best != SIZE_MAX) {
+        p = spare[best].p;
+        got = spare[best].bytes;
+        spare.erase(spare.begin() + best);
+    } else if (device >= 0 && device < 64) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache[device].lower_bound(bytes);
+        if (it != g_cache[device].end() && fits(it->first, bytes)) {
+            p = it->second;
+            got = it->first;
+            g_cache[device].erase(it);
+        }
     }
-    blocks.push_back({p, bytes});
-    current += bytes;
+    if (!p) {
+        hipError_t e = hipMallocAsync(&p, bytes, stream);
+        if (e == hipErrorOutOfMemory && device >= 0 && device < 64 && cache_free_all(device) > 0) {
+            (void)hipGetLastError();
+            e = hipMallocAsync(&p, bytes, stream);  // idle cached blocks returned to the device first
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(e == hipErrorOutOfMemory ? IIM_E_BUDGET : IIM_E_DEVICE,
+                        std::string("hipMallocAsync(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        }
+        got = bytes;
+    }
+    blocks.push_back({p, got});
+    current += got;
     peak = std::max(peak, current);
     return p;
 }
 
 void DevMem::release(void* p) {
-    for (auto& q : blocks)
-        if (q.p == p) {
-            (void)hipFreeAsync(q.p, stream);
-            current -= q.bytes;
-            q.p = nullptr;
+    for (size_t i = 0; i < blocks.size(); ++i)
+        if (blocks[i].p == p) {
+            current -= blocks[i].bytes;
+            spare.push_back(blocks[i]);
+            blocks.erase(blocks.begin() + i);
+            return;
         }
 }
 
 void DevMem::release_all() {
-    for (auto& q : blocks)
-        if (q.p) (void)hipFreeAsync(q.p, stream);
+    if (blocks.empty() && spare.empty()) return;
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (device >= 0 && device < 64) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (auto& q : blocks) g_cache[device].emplace(q.bytes, q.p);
+        for (auto& q : spare) g_cache[device].emplace(q.bytes, q.p);
+    } else {
+        for (auto& q : blocks) (void)hipFreeAsync(q.p, stream);
+        for (auto& q : spare) (void)hipFreeAsync(q.p, stream);
+    }
     blocks.clear();
+    spare.clear();
     current = 0;
 }
 
@@ -143,27 +203,25 @@ void Problem::setup() {
     levels.resize(nl);
     {
         std::vector<int> h_bb(8 * nl);
-        for (int l = 0; l < nl; ++l) {
-            const int init[8] = {1 << 30, 1 << 30, 1 << 30, -(1 << 30), -(1 << 30), -(1 << 30), 0, 0};
-            std::copy(init, init + 8, h_bb.begin() + 8 * l);
-        }
         int* d_bb = (int*)mem.alloc(8 * nl * sizeof(int));
         unsigned long long* d_cnt = (unsigned long long*)mem.alloc(nl * sizeof(unsigned long long));
-        IIM_HIP(hipMemcpyAsync(d_bb, h_bb.data(), 8 * nl * sizeof(int), hipMemcpyHostToDevice, stream));
-        IIM_HIP(hipMemsetAsync(d_cnt, 0, nl * sizeof(unsigned long long), stream));
+        int* d_part = (int*)mem.alloc(classify_part_ints(nl) * sizeof(int));
+        GeomSet G{};
         for (int l = 0; l < nl; ++l) {
             Level& L = levels[l];
             L.n = sizes[l];
             L.h = h * (double)(1 << l);
             L.geom = Geom{kind, side, dim, L.n, grid.lo, L.h, d_params};
-            run_classify_bbox(L.geom, d_bb + 8 * l, d_bb + 8 * l + 6, d_cnt + l, stream);
+            G.g[l] = L.geom;
         }
+        run_classify_levels(G, nl, d_part, d_bb, d_cnt, stream);
         std::vector<unsigned long long> h_cnt(nl);
         IIM_HIP(hipMemcpyAsync(h_bb.data(), d_bb, 8 * nl * sizeof(int), hipMemcpyDeviceToHost, stream));
         IIM_HIP(hipMemcpyAsync(h_cnt.data(), d_cnt, nl * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
         IIM_HIP(hipStreamSynchronize(stream));
         mem.release(d_bb);
         mem.release(d_cnt);
+        mem.release(d_part);
         for (int l = 0; l < nl; ++l) {
             Level& L = levels[l];
             const int* bb = h_bb.data() + 8 * l;
@@ -696,17 +754,22 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
                 IIM_HIP(hipGraphInstantiate(&iter_graph[jj], g, nullptr, nullptr, 0));
                 IIM_HIP(hipGraphDestroy(g));
             };
+            const bool pipelined = opt.use_graph != 0;
             auto enqueue = [&](int jj) {
-                capture(jj);
-                IIM_HIP(hipGraphLaunch(iter_graph[jj], stream));
+                if (opt.use_graph == 1) {
+                    capture(jj);
+                    IIM_HIP(hipGraphLaunch(iter_graph[jj], stream));
+                } else {
+                    iteration_body(jj);
+                }
                 IIM_HIP(hipEventRecord(iter_done[jj & 1], stream));
             };
-            if (opt.use_graph) {
+            if (pipelined) {
                 IIM_HIP(hipEventRecord(ev[0], stream));
                 enqueue(0);
             }
             for (int j = 0; j < m; ++j) {
-                if (opt.use_graph) {
+                if (pipelined) {
                     if (j + 1 < m && its + 1 < opt.max_iters) enqueue(j + 1);
                     IIM_HIP(hipEventSynchronize(iter_done[j & 1]));  // recorded after graph j, before j+1
                 } else {
@@ -748,7 +811,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
                 if (hist && hl < hist_cap) hist[hl++] = est;
                 if (est <= opt.rtol || its >= opt.max_iters || hn == 0.0) break;
             }
-            if (opt.use_graph) {
+            if (pipelined) {
                 // wait for the cycle's last queued iteration before the update
                 IIM_HIP(hipEventRecord(ev[3], stream));
                 IIM_HIP(hipEventSynchronize(ev[3]));
@@ -1066,6 +1129,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     if (!(g->hi > g->lo)) throw Error(IIM_E_INVALID_ARG, "empty domain");
     if (o.order_n != 4 || o.order_k != 5) throw Error(IIM_E_INVALID_ARG, "only the (4,5) discretisation is built");
     if (o.restart < 1 || o.restart > 11) throw Error(IIM_E_INVALID_ARG, "restart must be in [1, 11]");
+    if (o.use_graph < 0 || o.use_graph > 2) throw Error(IIM_E_INVALID_ARG, "use_graph must be 0, 1 or 2");
     if (o.coarsest_n < 2) throw Error(IIM_E_INVALID_ARG, "coarsest_n must be >= 2");
     if (o.precision < 0 || o.precision > 2) throw Error(IIM_E_INVALID_ARG, "bad precision");
     if (!(o.beta_plus > 0) || !(o.beta_minus > 0)) throw Error(IIM_E_INVALID_ARG, "beta must be positive");
@@ -1101,6 +1165,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
         p->own_stream = true;
     }
     p->mem.stream = p->stream;
+    p->mem.device = dev;
     if (hpin) {
         p->hpin = hpin;
         p->own_hpin = false;
@@ -1175,7 +1240,7 @@ int iim_default_options(iim_options* o) {
     o->precision = IIM_PREC_FP64;
     o->ls_axis_t = 0.0;
     o->ls_axis_n = 0.0;
-    o->use_graph = 1;
+    o->use_graph = 2;
     o->tail_nodes = 0;
     o->fused_smoothing = 1;
     o->colour_split = 1;

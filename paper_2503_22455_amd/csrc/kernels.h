@@ -6,11 +6,18 @@
 namespace iim {
 
 // ---- setup (setup.hip) -----------------------------------------------------
-// Classify every node of the level's full grid; bbox = {min x,y,z, max x,y,z}
-// of the unknowns (atomics on integers: order independent), err != 0 when the
-// body touches the box, count = number of unknowns.
-void run_classify_bbox(const Geom& g, int* d_bbox, int* d_err, unsigned long long* d_count,
-                       hipStream_t s);
+// Classify every node of the full grid of levels 0..nl-1 (two launches, no
+// atomics): bbox[8 l ..] = {min x,y,z, max x,y,z} of level l's unknowns and,
+// at [8 l + 6], != 0 when the body touches the box; count[l] = its unknowns.
+// d_part: classify_part_ints(nl) ints of scratch.
+constexpr int MAX_LEVELS = 16;  // multigrid levels of a problem
+constexpr int CLASSIFY_BLOCKS = 512;
+struct GeomSet {
+    Geom g[MAX_LEVELS];
+};
+int classify_part_ints(int nl);
+void run_classify_levels(const GeomSet& G, int nl, int* d_part, int* d_bbox, unsigned long long* d_count,
+                         hipStream_t s);
 void run_box_labels(const Geom& g, const Box& b, uint8_t* labels, hipStream_t s);
 // crossing flags along one axis: flags[l] = 1 if the segment (l, l + e_axis) carries a control point
 void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, int axis, uint8_t* flags,
@@ -140,7 +147,6 @@ template <typename U>
 void run_level_to_box(const LevelDev& L, const U* lev, U* boxed, hipStream_t s);
 
 // the levels first..last of a V-cycle (last = coarsest) in one workgroup
-constexpr int MAX_LEVELS = 16;
 struct TailDev {
     int first, last, mode, nu_pre, nu_post;
     int64_t nc;

@@ -9,16 +9,21 @@ namespace iim {
 // ---------------------------------------------------------------------------
 // labels
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_classify_bbox(Geom g, int* bbox, int* err, unsigned long long* count) {
-    __shared__ int sh[7][256];
-    int64_t n1 = g.n + 1;
-    int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+// Pass 1, one launch for every level (blockIdx.y = level): each block
+// classifies a grid-stride share of the level's nodes and writes its partial
+// {min x,y,z, max x,y,z, touches-the-box flag, unknown count} to part.
+__global__ void __launch_bounds__(256) k_classify_levels(GeomSet G, int* part) {
+    __shared__ int sh[8][256];
+    const Geom& g = G.g[blockIdx.y];
+    const int64_t n1 = g.n + 1;
+    const int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
     int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
     int cnt = 0, bad = 0;
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
-        int ijk[3] = {(int)(l % n1), (int)((l / n1) % n1), g.dim == 3 ? (int)(l / (n1 * n1)) : 0};
-        uint8_t k = node_kind(g, ijk);
+        const int64_t q = l / n1;
+        int ijk[3] = {(int)(l - q * n1), (int)(q % n1), g.dim == 3 ? (int)(q / n1) : 0};
+        const uint8_t k = node_kind(g, ijk);
         if (k == 255) {
             bad = 1;
             continue;
@@ -36,7 +41,8 @@ __global__ void __launch_bounds__(256) k_classify_bbox(Geom g, int* bbox, int* e
         sh[d][t] = mn[d];
         sh[3 + d][t] = mx[d];
     }
-    sh[6][t] = cnt;
+    sh[6][t] = bad;
+    sh[7][t] = cnt;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (t < off) {
@@ -44,25 +50,56 @@ __global__ void __launch_bounds__(256) k_classify_bbox(Geom g, int* bbox, int* e
                 sh[d][t] = min(sh[d][t], sh[d][t + off]);
                 sh[3 + d][t] = max(sh[3 + d][t], sh[3 + d][t + off]);
             }
-            sh[6][t] += sh[6][t + off];
+            sh[6][t] |= sh[6][t + off];
+            sh[7][t] += sh[7][t + off];
         }
         __syncthreads();
     }
-    if (bad) atomicOr(err, 1);
-    if (t == 0 && sh[6][0] > 0) {
-        for (int d = 0; d < 3; ++d) {
-            atomicMin(&bbox[d], sh[d][0]);
-            atomicMax(&bbox[3 + d], sh[3 + d][0]);
-        }
-        atomicAdd(count, (unsigned long long)sh[6][0]);
-    }
+    if (t < 8) part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 8 + t] = sh[t][0];
 }
 
-void run_classify_bbox(const Geom& g, int* d_bbox, int* d_err, unsigned long long* d_count, hipStream_t s) {
-    int64_t n1 = g.n + 1;
-    int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
-    int blocks = (int)std::min<int64_t>(cdiv(total, 256), 2048);
-    hipLaunchKernelGGL(k_classify_bbox, dim3(blocks), dim3(256), 0, s, g, d_bbox, d_err, d_count);
+// Pass 2, one block per level: bbox[8 l + 0..6] and count[l] from the partials
+__global__ void __launch_bounds__(256) k_classify_reduce(const int* part, int nb, int* bbox,
+                                                         unsigned long long* count) {
+    __shared__ int sh[7][256];
+    __shared__ unsigned long long shc[256];
+    const int t = threadIdx.x;
+    int v[7] = {1 << 30, 1 << 30, 1 << 30, -(1 << 30), -(1 << 30), -(1 << 30), 0};
+    unsigned long long c = 0;
+    for (int b = t; b < nb; b += blockDim.x) {
+        const int* q = part + ((int64_t)blockIdx.x * nb + b) * 8;
+        for (int d = 0; d < 3; ++d) {
+            v[d] = min(v[d], q[d]);
+            v[3 + d] = max(v[3 + d], q[3 + d]);
+        }
+        v[6] |= q[6];
+        c += (unsigned long long)q[7];
+    }
+    for (int d = 0; d < 7; ++d) sh[d][t] = v[d];
+    shc[t] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            for (int d = 0; d < 3; ++d) {
+                sh[d][t] = min(sh[d][t], sh[d][t + off]);
+                sh[3 + d][t] = max(sh[3 + d][t], sh[3 + d][t + off]);
+            }
+            sh[6][t] |= sh[6][t + off];
+            shc[t] += shc[t + off];
+        }
+        __syncthreads();
+    }
+    if (t < 7) bbox[8 * blockIdx.x + t] = sh[t][0];
+    if (t == 0) count[blockIdx.x] = shc[0];
+}
+
+int classify_part_ints(int nl) { return nl * CLASSIFY_BLOCKS * 8; }
+
+void run_classify_levels(const GeomSet& G, int nl, int* d_part, int* d_bbox, unsigned long long* d_count,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_classify_levels, dim3(CLASSIFY_BLOCKS, nl), dim3(256), 0, s, G, d_part);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_classify_reduce, dim3(nl), dim3(256), 0, s, d_part, CLASSIFY_BLOCKS, d_bbox, d_count);
     IIM_LAUNCH_CHECK();
 }
 

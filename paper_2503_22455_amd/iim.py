@@ -158,7 +158,7 @@ def flat_to_grid(v: np.ndarray, dim: int, n: int) -> np.ndarray:
 
 def make_options(beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 1e-10, max_iters: int = 500,
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
-                 precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None, use_graph: bool = True,
+                 precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None, use_graph: int = 2,
                  tail_nodes: int = 0, fused_smoothing: bool = True, colour_split: bool = True) -> Options:
     o = Options()
     lib().iim_default_options(ctypes.byref(o))
@@ -181,7 +181,7 @@ class Problem:
                  beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 1e-10, max_iters: int = 500,
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None,
-                 lo: float = -1.0, hi: float = 1.0, use_graph: bool = True, tail_nodes: int = 0,
+                 lo: float = -1.0, hi: float = 1.0, use_graph: int = 2, tail_nodes: int = 0,
                  fused_smoothing: bool = True, colour_split: bool = True, stream=None):
         L = lib()
         self.dim, self.n = dim, n
