@@ -126,6 +126,7 @@ struct Problem {
     double t_setup_ms = 0.0;
 
     void setup();
+    LevelSet level_set() const;
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;
     void apply_box(const double* x, double* y, int with_data);

@@ -68,6 +68,52 @@ void trim_pool() {
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
 }
 
+// Library-owned streams and pinned Hessenberg buffers of ended handles, kept
+// for later handles (creating either costs about a tenth of a millisecond).
+static std::mutex g_res_mu;
+static std::vector<std::pair<int, hipStream_t>> g_streams;
+static std::vector<double*> g_hpins;
+
+static hipStream_t take_stream(int dev) {
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        for (size_t i = 0; i < g_streams.size(); ++i)
+            if (g_streams[i].first == dev) {
+                hipStream_t s = g_streams[i].second;
+                g_streams.erase(g_streams.begin() + i);
+                return s;
+            }
+    }
+    // a blocking stream: ordered with the legacy default stream, and capturable
+    hipStream_t s = nullptr;
+    IIM_HIP(hipStreamCreate(&s));
+    return s;
+}
+
+static void give_stream(int dev, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    g_streams.push_back({dev, s});
+}
+
+static double* take_hpin() {
+    {
+        std::lock_guard<std::mutex> lk(g_res_mu);
+        if (!g_hpins.empty()) {
+            double* p = g_hpins.back();
+            g_hpins.pop_back();
+            return p;
+        }
+    }
+    double* p = nullptr;
+    IIM_HIP(hipHostMalloc((void**)&p, HPIN_DOUBLES * sizeof(double), hipHostMallocDefault));
+    return p;
+}
+
+static void give_hpin(double* p) {
+    std::lock_guard<std::mutex> lk(g_res_mu);
+    g_hpins.push_back(p);
+}
+
 void* DevMem::alloc(size_t bytes) {
     bytes = (std::max<size_t>(bytes, 8) + 255) / 256 * 256;
     void* p = nullptr;
@@ -237,25 +283,27 @@ void Problem::setup() {
             }
             if (L.box.size() > (int64_t)INT32_MAX) throw Error(IIM_E_BUDGET, "storage box exceeds 2^31 nodes");
             L.labels = (uint8_t*)mem.alloc(L.box.size());
-            run_box_labels(L.geom, L.box, L.labels, stream);
         }
+        run_box_labels(level_set(), nl, stream);
     }
     Level& L0 = levels[0];
     if (L0.nunk == 0) throw Error(IIM_E_INVALID_ARG, "the problem has no unknowns");
     box = L0.box;
-    // one selection workspace for every flagged-node selection (stream ordered)
-    size_t sel_bytes = select_tmp_bytes(box.size());
-    void* sel_tmp = mem.alloc(sel_bytes);
-    uint8_t* flags = (uint8_t*)mem.alloc(box.size());
+    // scratch of the flagged-node selections (stream ordered)
+    int* sel_part = (int*)mem.alloc(SEL_BLOCKS * SEL_MAX * sizeof(int));
 
     // ---- control points (level 0): crossings of each axis  [wait 2]
     {
+        uint8_t* flags = (uint8_t*)mem.alloc(dim * box.size());
+        run_cp_flags(L0.geom, box, L0.labels, flags, stream);
         std::vector<int32_t*> per_axis(dim);
+        SelItem items[3];
         for (int a = 0; a < dim; ++a) {
-            run_cp_flags(L0.geom, box, L0.labels, a, flags, stream);
             per_axis[a] = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
-            select_flagged_async(flags, box.size(), per_axis[a], sel_tmp, sel_bytes, d_sc + 1 + a, stream);
+            items[a] = SelItem{flags + a * box.size(), box.size(), per_axis[a], d_sc + 1 + a};
         }
+        select_flagged_multi(items, dim, sel_part, stream);
+        mem.release(flags);
         read_sc(1 + dim);
         int64_t ncp = 0;
         cp.axis_start[0] = 0;
@@ -370,21 +418,30 @@ void Problem::setup() {
 
     // ---- irregular nodes: high-order (level 0) and Shortley-Weller (every level),
     // selected together  [wait 4]
-    int32_t* ho_sel = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
-    run_ho_irr_flag(L0.geom, box, L0.labels, flags, stream);
-    select_flagged_async(flags, box.size(), ho_sel, sel_tmp, sel_bytes, d_sc + 4, stream);
     std::vector<int32_t*> sw_sel(nl);
-    for (int l = 0; l < nl; ++l) {
-        Level& L = levels[l];
-        const int64_t bs = L.box.size();
-        run_sw_irr_flag(L.geom, L.box, L.labels, flags, stream);
-        sw_sel[l] = (int32_t*)mem.alloc(bs * sizeof(int32_t));
-        select_flagged_async(flags, bs, sw_sel[l], sel_tmp, sel_bytes, d_sc + 8 + l, stream);
+    int32_t* ho_sel = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
+    {
+        LevelSet S = level_set();
+        int64_t nflags = box.size();  // high-order flags first, then each level's SW flags
+        for (int l = 0; l < nl; ++l) {
+            S.off[l] = nflags;
+            nflags += levels[l].box.size();
+        }
+        uint8_t* flags = (uint8_t*)mem.alloc(nflags);
+        run_ho_irr_flag(L0.geom, box, L0.labels, flags, stream);
+        run_sw_irr_flag(S, nl, flags, stream);
+        std::vector<SelItem> items;
+        items.push_back(SelItem{flags, box.size(), ho_sel, d_sc + 4});
+        for (int l = 0; l < nl; ++l) {
+            sw_sel[l] = (int32_t*)mem.alloc(levels[l].box.size() * sizeof(int32_t));
+            items.push_back(SelItem{flags + S.off[l], levels[l].box.size(), sw_sel[l], d_sc + 8 + l});
+        }
+        select_flagged_multi(items.data(), (int)items.size(), sel_part, stream);
+        mem.release(flags);
     }
     read_sc(8 + nl);
     raise_setup_error(err_bits(), "least-squares fits");
-    mem.release(flags);
-    mem.release(sel_tmp);
+    mem.release(sel_part);
     {
         ho_nirr = h_sc[4];
         ho_irr_index = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
@@ -536,7 +593,7 @@ void Problem::setup() {
         d_tail = (TailDev*)mem.alloc(sizeof(TailDev));
         IIM_HIP(hipMemcpyAsync(d_tail, &T, sizeof(TailDev), hipMemcpyHostToDevice, stream));
     }
-    if (!hpin) IIM_HIP(hipHostMalloc((void**)&hpin, HPIN_DOUBLES * sizeof(double), hipHostMallocDefault));
+    if (!hpin) hpin = take_hpin();
     for (int i = 0; i < 8; ++i) IIM_HIP(hipEventCreate(&ev[i]));
     for (int i = 0; i < 2; ++i) IIM_HIP(hipEventCreateWithFlags(&iter_done[i], hipEventDisableTiming));
     read_sc(1);  // [wait 6]
@@ -563,6 +620,17 @@ LevelDev Problem::level_dev(int l) const {
     D.hx = L.hx;
     D.half = L.half;
     return D;
+}
+
+LevelSet Problem::level_set() const {
+    LevelSet S{};
+    for (size_t l = 0; l < levels.size() && l < (size_t)MAX_LEVELS; ++l) {
+        S.g[l] = levels[l].geom;
+        S.b[l] = levels[l].box;
+        S.labels[l] = levels[l].labels;
+        S.off[l] = 0;
+    }
+    return S;
 }
 
 GhostDev Problem::ghost_dev() const {
@@ -925,9 +993,9 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     // entries of a level vector: colour-split 3D levels round each box row up to even
     auto vec = [&](const int64_t* d) { return dim == 3 ? 2 * ((d[0] + 1) / 2) * d[1] * d[2] : d[0] * d[1] * d[2]; };
     int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8) + vec(dims) * (zbufs * ssz + tsz) + (2 * m + 1) * 64 * 8;
-    // setup transients alive together: flags, one selection output per axis and
-    // the selection workspace
-    bytes += N0 * (1 + 4 * dim) + (N0 / 64 + (1 << 20));
+    // setup transients alive together: the crossing flags and one selection
+    // output per axis, the selections' scratch
+    bytes += N0 * 5 * dim + SEL_BLOCKS * SEL_MAX * 4;
     // coarse levels: labels, SW index, iterate, right-hand side
     int64_t cd[3] = {dims[0], dims[1], dims[2]};
     int n = g.n;
@@ -1161,7 +1229,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     if (!p->stream) {
         // a blocking stream of our own: ordered with the legacy default stream,
         // and capturable (the default stream is not)
-        IIM_HIP(hipStreamCreate(&p->stream));
+        p->stream = take_stream(dev);
         p->own_stream = true;
     }
     p->mem.stream = p->stream;
@@ -1191,10 +1259,10 @@ Problem::~Problem() {
         if (ev[i]) (void)hipEventDestroy(ev[i]);
     for (int i = 0; i < 2; ++i)
         if (iter_done[i]) (void)hipEventDestroy(iter_done[i]);
-    if (hpin && own_hpin) (void)hipHostFree(hpin);
+    if (hpin && own_hpin) give_hpin(hpin);
     mem.release_all();
     if (stream) (void)hipStreamSynchronize(stream);
-    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    if (own_stream && stream) give_stream(mem.device, stream);
 }
 
 }  // namespace iim

@@ -18,15 +18,33 @@ struct GeomSet {
 int classify_part_ints(int nl);
 void run_classify_levels(const GeomSet& G, int nl, int* d_part, int* d_bbox, unsigned long long* d_count,
                          hipStream_t s);
-void run_box_labels(const Geom& g, const Box& b, uint8_t* labels, hipStream_t s);
-// crossing flags along one axis: flags[l] = 1 if the segment (l, l + e_axis) carries a control point
-void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, int axis, uint8_t* flags,
-                  hipStream_t s);
-// indices (0..n-1) of the flagged entries, in increasing order, into out, their number into *d_count;
-// stream ordered, no host wait
-void select_flagged_async(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
-                          int64_t* d_count, hipStream_t s);
-size_t select_tmp_bytes(int64_t n);
+// the levels of a problem, for kernels that treat all of them in one launch
+// (blockIdx.y = level); off[l] = offset of level l in a per-level flag array
+struct LevelSet {
+    Geom g[MAX_LEVELS];
+    Box b[MAX_LEVELS];
+    uint8_t* labels[MAX_LEVELS];
+    int64_t off[MAX_LEVELS];
+};
+// labels of every level's storage box
+void run_box_labels(const LevelSet& S, int nl, hipStream_t s);
+// crossing flags of every axis: flags[a * N + l] = 1 if the segment (l, l + e_a)
+// carries a control point (N = box size)
+void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, uint8_t* flags, hipStream_t s);
+// Flagged selections: out = indices (0..n-1) of the nonzero flags in increasing
+// order, *count = their number; up to SEL_MAX selections in three launches,
+// stream ordered, no host wait; d_part: SEL_BLOCKS * k ints of scratch.
+constexpr int SEL_MAX = 20, SEL_BLOCKS = 256;
+struct SelItem {
+    const uint8_t* flags;
+    int64_t n;
+    int32_t* out;
+    int64_t* count;
+};
+struct SelSet {
+    SelItem it[SEL_MAX];
+};
+void select_flagged_multi(const SelItem* items, int k, int* d_part, hipStream_t s);
 
 struct CPDev {
     int64_t ncp;
@@ -49,9 +67,10 @@ void run_ho_irr_records(const Geom& g, const Box& b, const uint8_t* labels, cons
                         const int32_t* nodes, int64_t nirr, int32_t* slots, int32_t* irr_index,
                         int* d_err, hipStream_t s);
 
-// Shortley-Weller rows of one level: flags of irregular unknowns, then their rows
+// Shortley-Weller rows: flags of the irregular unknowns of every level (at
+// flags + S.off[l]), then per level their rows
 // rec[k * (1 + 2 dim)] = {diag, coefficient of neighbour (d, -), (d, +), ...} scaled by h^2
-void run_sw_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s);
+void run_sw_irr_flag(const LevelSet& S, int nl, uint8_t* flags, hipStream_t s);
 void run_sw_records(const Geom& g, const Box& b, const uint8_t* labels, const int32_t* nodes,
                     int64_t nirr, int bc, double beta_plus, double beta_minus, double* rec64,
                     float* rec32, int32_t* irr_index, hipStream_t s);

@@ -1,6 +1,6 @@
 // Setup kernels: node labels, control points, irregular-node records and the
 // Shortley-Weller hierarchy (Sec. 2.1 and 3.1-3.3 of the paper).
-#include <hipcub/hipcub.hpp>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -103,7 +103,10 @@ void run_classify_levels(const GeomSet& G, int nl, int* d_part, int* d_bbox, uns
     IIM_LAUNCH_CHECK();
 }
 
-__global__ void k_box_labels(Geom g, Box b, uint8_t* labels) {
+__global__ void k_box_labels(LevelSet S) {
+    const Geom& g = S.g[blockIdx.y];
+    const Box& b = S.b[blockIdx.y];
+    uint8_t* labels = S.labels[blockIdx.y];
     int64_t total = b.size();
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
@@ -116,9 +119,9 @@ __global__ void k_box_labels(Geom g, Box b, uint8_t* labels) {
     }
 }
 
-void run_box_labels(const Geom& g, const Box& b, uint8_t* labels, hipStream_t s) {
-    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
-    hipLaunchKernelGGL(k_box_labels, dim3(blocks), dim3(256), 0, s, g, b, labels);
+void run_box_labels(const LevelSet& S, int nl, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(S.b[0].size(), 256), 4096);
+    hipLaunchKernelGGL(k_box_labels, dim3(blocks, nl), dim3(256), 0, s, S);
     IIM_LAUNCH_CHECK();
 }
 
@@ -133,9 +136,11 @@ __device__ inline bool crossing_pair(uint8_t la, uint8_t lb, int side) {
     return (la == K_PLUS && lb == K_INACTIVE) || (la == K_INACTIVE && lb == K_PLUS);
 }
 
-__global__ void k_cp_flags(Geom g, Box b, const uint8_t* labels, int axis, uint8_t* flags) {
+__global__ void k_cp_flags(Geom g, Box b, const uint8_t* labels, uint8_t* flags_all) {
+    const int axis = blockIdx.y;
     int64_t total = b.size();
     int64_t st = b.stride(axis);
+    uint8_t* flags = flags_all + axis * total;
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
         int ijk[3];
@@ -147,27 +152,92 @@ __global__ void k_cp_flags(Geom g, Box b, const uint8_t* labels, int axis, uint8
     }
 }
 
-void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, int axis, uint8_t* flags, hipStream_t s) {
-    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
-    hipLaunchKernelGGL(k_cp_flags, dim3(blocks), dim3(256), 0, s, g, b, labels, axis, flags);
+void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, uint8_t* flags, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 4096);
+    hipLaunchKernelGGL(k_cp_flags, dim3(blocks, g.dim), dim3(256), 0, s, g, b, labels, flags);
     IIM_LAUNCH_CHECK();
 }
 
-size_t select_tmp_bytes(int64_t n) {
-    size_t bytes = 0;
-    hipcub::CountingInputIterator<int32_t> it(0);
-    hipcub::DeviceSelect::Flagged(nullptr, bytes, it, (const uint8_t*)nullptr, (int32_t*)nullptr,
-                                  (int64_t*)nullptr, (int)n);
-    return bytes;
+// ---------------------------------------------------------------------------
+// flagged selections, several at once, in three launches: per-block counts,
+// one scan per selection, an ordered scatter (ballot prefix within wavefronts)
+// ---------------------------------------------------------------------------
+__device__ inline void sel_chunk(int64_t n, int b, int64_t* lo, int64_t* hi) {
+    const int64_t c = (n + SEL_BLOCKS - 1) / SEL_BLOCKS;
+    *lo = min(n, (int64_t)b * c);
+    *hi = min(n, *lo + c);
 }
 
-void select_flagged_async(const uint8_t* flags, int64_t n, int32_t* out, void* tmp, size_t tmp_bytes,
-                          int64_t* d_count, hipStream_t s) {
-    hipcub::CountingInputIterator<int32_t> it(0);
-    size_t need = 0;
-    IIM_HIP(hipcub::DeviceSelect::Flagged(nullptr, need, it, flags, out, d_count, (int)n, s));
-    if (need > tmp_bytes) throw Error(IIM_E_INTERNAL, "selection workspace too small");
-    IIM_HIP(hipcub::DeviceSelect::Flagged(tmp, tmp_bytes, it, flags, out, d_count, (int)n, s));
+__global__ void __launch_bounds__(256) k_sel_count(SelSet S, int* part) {
+    __shared__ int sh[256];
+    const SelItem& it = S.it[blockIdx.y];
+    int64_t lo, hi;
+    sel_chunk(it.n, blockIdx.x, &lo, &hi);
+    int c = 0;
+    for (int64_t l = lo + threadIdx.x; l < hi; l += blockDim.x) c += it.flags[l] != 0;
+    const int t = threadIdx.x;
+    sh[t] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    if (t == 0) part[blockIdx.y * SEL_BLOCKS + blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(SEL_BLOCKS) k_sel_scan(SelSet S, int* part) {
+    __shared__ int sh[SEL_BLOCKS];
+    int* p = part + blockIdx.x * SEL_BLOCKS;
+    const int t = threadIdx.x;
+    const int v = p[t];
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SEL_BLOCKS; off <<= 1) {
+        const int a = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    p[t] = sh[t] - v;  // first output slot of block t
+    if (t == SEL_BLOCKS - 1) *S.it[blockIdx.x].count = sh[t];
+}
+
+__global__ void __launch_bounds__(256) k_sel_scatter(SelSet S, const int* part) {
+    __shared__ int wsum[4];
+    const SelItem& it = S.it[blockIdx.y];
+    int64_t lo, hi;
+    sel_chunk(it.n, blockIdx.x, &lo, &hi);
+    int base = part[blockIdx.y * SEL_BLOCKS + blockIdx.x];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int64_t t0 = lo; t0 < hi; t0 += 256) {
+        const int64_t l = t0 + t;
+        const bool f = l < hi && it.flags[l] != 0;
+        const uint64_t m = __ballot(f);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[w] = __popcll(m);
+        __syncthreads();
+        int off = 0;
+        for (int q = 0; q < w; ++q) off += wsum[q];
+        const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (f) it.out[base + off + pre] = (int32_t)l;
+        base += tot;
+        __syncthreads();
+    }
+}
+
+void select_flagged_multi(const SelItem* items, int k, int* d_part, hipStream_t s) {
+    if (k < 1 || k > SEL_MAX) throw Error(IIM_E_INTERNAL, "selection count out of range");
+    SelSet S{};
+    for (int i = 0; i < k; ++i) {
+        if (items[i].n < 0 || items[i].n > (int64_t)INT32_MAX) throw Error(IIM_E_INTERNAL, "selection too long");
+        S.it[i] = items[i];
+    }
+    hipLaunchKernelGGL(k_sel_count, dim3(SEL_BLOCKS, k), dim3(256), 0, s, S, d_part);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_scan, dim3(k), dim3(SEL_BLOCKS), 0, s, S, d_part);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_scatter, dim3(SEL_BLOCKS, k), dim3(256), 0, s, S, (const int*)d_part);
+    IIM_LAUNCH_CHECK();
 }
 
 __global__ void k_cp_compute(Geom g, Box b, const uint8_t* labels, CPDev cp, int* err) {
@@ -328,7 +398,11 @@ void run_ho_irr_records(const Geom& g, const Box& b, const uint8_t* labels, cons
 // ---------------------------------------------------------------------------
 // Shortley-Weller rows
 // ---------------------------------------------------------------------------
-__global__ void k_sw_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags) {
+__global__ void k_sw_irr_flag(LevelSet S, uint8_t* flags_all) {
+    const Geom& g = S.g[blockIdx.y];
+    const Box& b = S.b[blockIdx.y];
+    uint8_t* labels = S.labels[blockIdx.y];
+    uint8_t* flags = flags_all + S.off[blockIdx.y];
     int64_t total = b.size();
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
@@ -350,9 +424,9 @@ __global__ void k_sw_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags) {
     }
 }
 
-void run_sw_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s) {
-    int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
-    hipLaunchKernelGGL(k_sw_irr_flag, dim3(blocks), dim3(256), 0, s, g, b, labels, flags);
+void run_sw_irr_flag(const LevelSet& S, int nl, uint8_t* flags, hipStream_t s) {
+    int blocks = (int)std::min<int64_t>(cdiv(S.b[0].size(), 256), 4096);
+    hipLaunchKernelGGL(k_sw_irr_flag, dim3(blocks, nl), dim3(256), 0, s, S, flags);
     IIM_LAUNCH_CHECK();
 }
 
@@ -561,8 +635,100 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* A, double* X, in
     }
 }
 
+// The same elimination with A and X resident in LDS (nc <= COARSE_LDS_NC): the
+// steps, pivots and arithmetic of k_coarse_invert, without a device-memory round
+// trip per step; the pivot search runs in one wavefront.
+constexpr int COARSE_LDS_NC = 90;
+__global__ void __launch_bounds__(1024) k_coarse_invert_lds(double* Ag, double* Xg, int nc, int* err) {
+    extern __shared__ double lds[];
+    double* A = lds;
+    double* X = lds + nc * nc;
+    __shared__ int piv_s;
+    const int tid = threadIdx.x, n2 = nc * nc;
+    for (int i = tid; i < n2; i += blockDim.x) {
+        A[i] = Ag[i];
+        X[i] = (i / nc == i % nc) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+        if (tid < 64) {
+            double best = -1.0;
+            int bi = -1;
+            for (int r = k + tid; r < nc; r += 64) {
+                const double v = fabs(A[r * nc + k]);
+                if (v > best) {
+                    best = v;
+                    bi = r;
+                }
+            }
+            // largest magnitude, the smallest row among equals
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const double v2 = __shfl_xor(best, off, 64);
+                const int i2 = __shfl_xor(bi, off, 64);
+                if (v2 > best || (v2 == best && i2 >= 0 && (bi < 0 || i2 < bi))) {
+                    best = v2;
+                    bi = i2;
+                }
+            }
+            if (tid == 0) {
+                piv_s = bi;
+                if (bi < 0 || best == 0.0) atomicOr(err, 16);
+            }
+        }
+        __syncthreads();
+        const int piv = piv_s;
+        if (piv < 0) break;
+        if (piv != k) {
+            for (int c = tid; c < nc; c += blockDim.x) {
+                double t = A[k * nc + c];
+                A[k * nc + c] = A[piv * nc + c];
+                A[piv * nc + c] = t;
+                t = X[k * nc + c];
+                X[k * nc + c] = X[piv * nc + c];
+                X[piv * nc + c] = t;
+            }
+            __syncthreads();
+        }
+        const double inv = 1.0 / A[k * nc + k];
+        __syncthreads();
+        for (int c = tid; c < nc; c += blockDim.x) {
+            A[k * nc + c] *= inv;
+            X[k * nc + c] *= inv;
+        }
+        __syncthreads();
+        for (int i = tid; i < n2; i += blockDim.x) {
+            const int r = i / nc, c = i - r * nc;
+            if (r == k || c == k) continue;  // column k of A updated last
+            const double f = A[r * nc + k];
+            A[r * nc + c] -= f * A[k * nc + c];
+            X[r * nc + c] -= f * X[k * nc + c];
+        }
+        __syncthreads();
+        for (int r = tid; r < nc; r += blockDim.x) {
+            if (r == k) continue;
+            const double f = A[r * nc + k];
+            X[r * nc + k] -= f * X[k * nc + k];
+            A[r * nc + k] = 0.0;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < n2; i += blockDim.x) Xg[i] = X[i];
+}
+
 void run_coarse_invert(double* A, double* Ainv, int64_t nc, int* d_err, hipStream_t s) {
     if (nc == 0) return;
+    if (nc <= COARSE_LDS_NC) {
+        static std::once_flag once;
+        std::call_once(once, [] {
+            IIM_HIP(hipFuncSetAttribute((const void*)k_coarse_invert_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        2 * COARSE_LDS_NC * COARSE_LDS_NC * (int)sizeof(double)));
+        });
+        hipLaunchKernelGGL(k_coarse_invert_lds, dim3(1), dim3(1024), 2 * nc * nc * sizeof(double), s, A, Ainv, (int)nc,
+                           d_err);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
     hipLaunchKernelGGL(k_coarse_invert, dim3(1), dim3(1024), 0, s, A, Ainv, nc, d_err);
     IIM_LAUNCH_CHECK();
 }
