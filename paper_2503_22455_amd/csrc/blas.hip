@@ -60,7 +60,8 @@ __device__ inline void block_reduce_store(const double (&vals)[K], int k, double
 // separate L2 caches.
 constexpr int FIN_WAVES = RED_BLOCKS / 64;
 
-__global__ void __launch_bounds__(RED_BLOCKS) k_final(const double* part, int k, double* out, int mode) {
+__global__ void __launch_bounds__(RED_BLOCKS) k_final(const double* part, int k, double* out, int mode,
+                                                       double* host_out) {
     __shared__ double sh[FIN_WAVES][KCH + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double p[KCH + 1];
@@ -77,13 +78,15 @@ __global__ void __launch_bounds__(RED_BLOCKS) k_final(const double* part, int k,
         double v = sh[0][threadIdx.x];
         for (int q = 1; q < FIN_WAVES; ++q) v = mode == 1 ? fmax(v, sh[q][threadIdx.x]) : v + sh[q][threadIdx.x];
         out[threadIdx.x] = v;
+        if (host_out) host_out[threadIdx.x] = v;  // pinned host copy (zero-copy)
         if (mode == 1) out[1] = v > 0.0 ? 1.0 / v : 1.0;
     }
 }
 
-static void final_sum(const double* part, int k, double* out, hipStream_t s, int mode = 0) {
+static void final_sum(const double* part, int k, double* out, hipStream_t s, int mode = 0,
+                      double* host_out = nullptr) {
     if (k < 1 || k > KCH + 1) throw Error(IIM_E_INVALID_ARG, "reduction: 1..13 values");
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(RED_BLOCKS), 0, s, part, k, out, mode);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RED_BLOCKS), 0, s, part, k, out, mode, host_out);
     IIM_LAUNCH_CHECK();
 }
 
@@ -119,13 +122,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* V, int64
 }
 
 void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* part, double* out,
-                  hipStream_t s) {
+                  hipStream_t s, double* host_out) {
     if (k < 1 || k > KCH) throw Error(IIM_E_INVALID_ARG, "multidot: 1..12 vectors");
     check_vec(V, ld);
     check_vec(w, 0);
     hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, w, n, part);
     IIM_LAUNCH_CHECK();
-    final_sum(part, k, out, s);
+    final_sum(part, k, out, s, 0, host_out);
 }
 
 // w -= sum_i h_i V_i (all k at once), then dots of the updated w with V_i (i < k2)
@@ -194,7 +197,7 @@ void run_update_dot_stage1(const double* V, int64_t ld, int k, const double* h, 
 }
 
 void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
-                    int with_norm, double* part, double* out, hipStream_t s) {
+                    int with_norm, double* part, double* out, hipStream_t s, double* host_out) {
     if (k > KCH || k2 > KCH) throw Error(IIM_E_INVALID_ARG, "update_dot: too many vectors");
     check_vec(V, ld);
     check_vec(w, 0);
@@ -202,7 +205,7 @@ void run_update_dot(const double* V, int64_t ld, int k, const double* h, double*
     hipLaunchKernelGGL(k_update_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, n, k2, with_norm,
                        part);
     IIM_LAUNCH_CHECK();
-    final_sum(part, k2 + (with_norm ? 1 : 0), out, s);
+    final_sum(part, k2 + (with_norm ? 1 : 0), out, s, 0, host_out);
 }
 
 // Second classical Gram-Schmidt pass fused with the normalisation:
@@ -215,7 +218,7 @@ void run_update_dot(const double* V, int64_t ld, int k, const double* h, double*
 // scaling of y is then one second-stage launch away).
 __global__ void __launch_bounds__(RED_THREADS) k_update_scale(const double* V, int64_t ld, int k, const double* h,
                                                               const double* w, double* y, int64_t n, double* nrm2_out,
-                                                              double* part) {
+                                                              double* nrm2_host, double* part) {
     double hh[KCH];
     double ss = 0.0;
 #pragma unroll
@@ -225,7 +228,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_scale(const double* V, i
     }
     const double nrm2 = fmax(h[k] - ss, 0.0);
     const double inv = 1.0 / sqrt(nrm2);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *nrm2_out = nrm2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *nrm2_out = nrm2;
+        if (nrm2_host) *nrm2_host = nrm2;
+    }
     double mx[1] = {0.0};
     const int64_t np = n >> 1;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
@@ -259,13 +265,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_scale(const double* V, i
 }
 
 void run_update_scale(const double* V, int64_t ld, int k, const double* h, const double* w, double* y, int64_t n,
-                      double* nrm2_out, double* part, double* scale_out, hipStream_t s) {
+                      double* nrm2_out, double* part, double* scale_out, hipStream_t s, double* nrm2_host) {
     if (k < 1 || k > KCH) throw Error(IIM_E_INVALID_ARG, "update_scale: 1..12 vectors");
     check_vec(V, ld);
     check_vec(w, 0);
     check_vec(y, 0);
     hipLaunchKernelGGL(k_update_scale, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, y, n, nrm2_out,
-                       part);
+                       nrm2_host, part);
     IIM_LAUNCH_CHECK();
     final_sum(part, 1, scale_out, s, 1);
 }

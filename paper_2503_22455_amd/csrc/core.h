@@ -119,7 +119,7 @@ struct Problem {
     bool opt_fused = true;  // LDS-tiled fused smoothing legs where available
     bool opt_split = true;  // colour-split vectors on 3D grid levels
     TailDev* d_tail = nullptr;
-    double* hpin = nullptr;  // pinned host copies of the Hessenberg columns, HCOL doubles per iteration
+    double* hpin = nullptr;  // Hessenberg column records, HCOL doubles per iteration, written by kernels
     bool own_hpin = true;
     hipGraphExec_t iter_graph[16] = {};
     hipEvent_t iter_done[2] = {};  // end of inner iteration j, alternating by parity
@@ -130,11 +130,12 @@ struct Problem {
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;
     void apply_box(const double* x, double* y, int with_data);
-    template <typename T, typename S> bool down_leg(int l);
-    template <typename T, typename S> const S* up_leg(int l, const S* zres);
-    // scaled: red_scale already holds max |v| (the fused orthogonalisation wrote it)
-    template <typename T, typename S> void vcycle_t(const double* v, double* out, bool scaled);
-    void vcycle(const double* v, double* out, bool scaled = false);
+    template <typename T, typename S> bool down_leg(int l, const CastInArgs* cast);
+    template <typename T, typename S> const S* up_leg(int l, const S* zres, double* out);
+    // scaled: red_scale already holds max |v| (the fused orthogonalisation wrote it);
+    // out_basis: out is zero off the core (a Krylov basis column)
+    template <typename T, typename S> void vcycle_t(const double* v, double* out, bool scaled, bool out_basis);
+    void vcycle(const double* v, double* out, bool scaled = false, bool out_basis = false);
     void iteration_body(int j, hipEvent_t* evs = nullptr);
     int solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st);
     int level_op(int level, int op, const double* in1, double* out);
@@ -147,7 +148,8 @@ struct Problem {
 };
 
 // validated construction with setup (stream: NULL creates a blocking stream
-// owned by the problem); hpin: optional caller-owned pinned buffer of HPIN_DOUBLES doubles
+// owned by the problem); hpin: optional caller-owned fine-grained pinned buffer
+// (hipHostMallocCoherent) of HPIN_DOUBLES doubles
 std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo, const iim_options* opt,
                                       hipStream_t stream, double* hpin);
 // device bytes a problem will hold at its peak, from the request alone

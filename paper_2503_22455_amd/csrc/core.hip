@@ -105,7 +105,8 @@ static double* take_hpin() {
         }
     }
     double* p = nullptr;
-    IIM_HIP(hipHostMalloc((void**)&p, HPIN_DOUBLES * sizeof(double), hipHostMallocDefault));
+    // fine-grained: kernels write the Hessenberg records into it directly
+    IIM_HIP(hipHostMalloc((void**)&p, HPIN_DOUBLES * sizeof(double), hipHostMallocCoherent));
     return p;
 }
 
@@ -665,35 +666,45 @@ void Problem::apply_box(const double* x, double* y, int with_data) {
 // fused pre-smoothing from a zero iterate + residual + restriction on level l
 // (2D, one LDS-tiled kernel); false when it does not apply
 template <typename T, typename S>
-bool Problem::down_leg(int l) {
+bool Problem::down_leg(int l, const CastInArgs* cast) {
     if (!opt_fused || dim != 2) return false;
     return run_down_fused<T, S>(level_dev(l), level_dev(l + 1), (const T*)levels[l].b, (S*)levels[l].z,
-                                (T*)levels[l + 1].b, opt.nu_pre, stream);
+                                (T*)levels[l + 1].b, opt.nu_pre, stream, cast);
 }
 
 // fused prolongation + post-smoothing on level l (2D, one LDS-tiled kernel
 // reading z and writing z2); returns the buffer holding the result, or nullptr
 // when it does not apply
 template <typename T, typename S>
-const S* Problem::up_leg(int l, const S* zres) {
+const S* Problem::up_leg(int l, const S* zres, double* out) {
     if (!opt_fused || dim != 2 || !levels[l].z2) return nullptr;
     const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
     S* z2 = (S*)levels[l].z2;
     return run_up_fused<T, S>(level_dev(l), level_dev(l + 1), mode, zres, (const T*)levels[l].b,
-                              (const S*)levels[l].z, z2, opt.nu_post, stream)
+                              (const S*)levels[l].z, z2, opt.nu_post, stream, out, out ? red_scale + 1 : nullptr)
                ? z2
                : nullptr;
 }
 
 template <typename T, typename S>
-void Problem::vcycle_t(const double* v, double* out, bool scaled) {
+void Problem::vcycle_t(const double* v, double* out, bool scaled, bool out_basis) {
     const int nl = (int)levels.size();
     const int t = tail_first;
     LevelDev D0 = level_dev(0);
     if (!scaled) run_absmax(v, box.size(), red_part, red_scale, stream);
-    run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
+    // the first fused leg makes level 0's right-hand side from v itself
+    const CastInArgs cast{v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus};
+    bool have_b = false;
+    auto cast_in = [&]() {
+        if (!have_b) run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
+        have_b = true;
+    };
     for (int l = 0; l < t; ++l) {
-        if (down_leg<T, S>(l)) continue;
+        if (down_leg<T, S>(l, l == 0 ? &cast : nullptr)) {
+            have_b = true;
+            continue;
+        }
+        cast_in();
         LevelDev D = level_dev(l), C = level_dev(l + 1);
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
@@ -704,12 +715,17 @@ void Problem::vcycle_t(const double* v, double* out, bool scaled) {
         }
         run_resid_restrict<T, S>(D, C, z, b, (T*)levels[l + 1].b, stream);
     }
+    cast_in();  // every level in the tail
     run_tail<T, S>(dim, d_tail, tail_lds_bytes, stream);  // levels t..nl-1, coarse solve included
     const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
     const S* zres = (const S*)levels[t].z;  // result of the level below the current one
+    bool have_out = false;
     for (int l = t - 1; l >= 0; --l) {
-        if (const S* r = up_leg<T, S>(l, zres)) {
+        // a basis column is zero off the core, so the last fused leg may write it directly
+        double* o = (l == 0 && out_basis) ? out : nullptr;
+        if (const S* r = up_leg<T, S>(l, zres, o)) {
             zres = r;
+            have_out = o != nullptr;
             continue;
         }
         LevelDev D = level_dev(l), C = level_dev(l + 1);
@@ -723,16 +739,16 @@ void Problem::vcycle_t(const double* v, double* out, bool scaled) {
         zres = z;
     }
     (void)nl;
-    run_cast_out<S>(D0, zres, red_scale + 1, out, stream);
+    if (!have_out) run_cast_out<S>(D0, zres, red_scale + 1, out, stream);
 }
 
-void Problem::vcycle(const double* v, double* out, bool scaled) {
+void Problem::vcycle(const double* v, double* out, bool scaled, bool out_basis) {
     if (opt.precision == IIM_PREC_FP64)
-        vcycle_t<double, double>(v, out, scaled);
+        vcycle_t<double, double>(v, out, scaled, out_basis);
     else if (opt.precision == IIM_PREC_MIXED32)
-        vcycle_t<float, float>(v, out, scaled);
+        vcycle_t<float, float>(v, out, scaled, out_basis);
     else
-        vcycle_t<float, __half>(v, out, scaled);
+        vcycle_t<float, __half>(v, out, scaled, out_basis);
 }
 
 // One inner FGMRES iteration on the device: z_j = M^{-1} v_j, w = A z_j, CGS2
@@ -742,17 +758,18 @@ void Problem::iteration_body(int j, hipEvent_t* evs) {
     const int64_t N = box.size();
     double* vj = Vb + (size_t)j * ldv;
     double* zj = Zb + (size_t)j * ldv;
-    vcycle(vj, zj, j > 0);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
+    vcycle(vj, zj, j > 0, true);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
     if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
     apply_box(zj, wk, 0);
     if (evs) IIM_HIP(hipEventRecord(evs[2], stream));
     // CGS2: h = V^T w; w -= V h with h' = V^T w and |w|^2 in the same pass; then
     // v_{j+1} = (w - V h') / |w - V h'|, the norm by Pythagoras
-    run_multidot(Vb, ldv, j + 1, wk, N, red_part, red_out, stream);
-    run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 1, red_part, red_out + 64, stream);
+    // the column's record also goes straight to pinned host memory (no copy)
+    double* rec = hpin + (size_t)j * HCOL;
+    run_multidot(Vb, ldv, j + 1, wk, N, red_part, red_out, stream, rec);
+    run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 1, red_part, red_out + 64, stream, rec + 64);
     run_update_scale(Vb, ldv, j + 1, red_out + 64, wk, Vb + (size_t)(j + 1) * ldv, N, red_out + 128, red_part,
-                     red_scale, stream);
-    IIM_HIP(hipMemcpyAsync(hpin + (size_t)j * HCOL, red_out, HCOL * sizeof(double), hipMemcpyDeviceToHost, stream));
+                     red_scale, stream, rec + 128);
 }
 
 // ---------------------------------------------------------------------------
@@ -1154,7 +1171,7 @@ void Problem::launch_kernel_t(int kernel) {
         case 9: {
             // the fused legs of level 0 (1 -> 0 reads level 1's iterate as the coarse result)
             if (levels.size() < 2 || tail_first < 1) throw Error(IIM_E_INVALID_ARG, "no fused leg on this problem");
-            bool ok = kernel == 8 ? down_leg<T, S>(0) : up_leg<T, S>(0, (const S*)levels[1].z) != nullptr;
+            bool ok = kernel == 8 ? down_leg<T, S>(0, nullptr) : up_leg<T, S>(0, (const S*)levels[1].z, nullptr) != nullptr;
             if (!ok) throw Error(IIM_E_INVALID_ARG, "no fused leg on this problem");
             break;
         }

@@ -185,11 +185,20 @@ void run_tail(int dim, const TailDev* d_tail, int64_t lds_bytes, hipStream_t s);
 void enable_tail_lds();
 // fused legs (2D): zero + nu sweeps + residual + half-weighting; prolongation + nu sweeps.
 // Return false when the fused form does not apply (the caller launches the unfused kernels).
+// cast: the down leg also makes b from the FP64 input v (as run_cast_in, b is then
+// written); out: the up leg writes the FP64 output (as run_cast_out, on the core
+// only) instead of z_out.
+struct CastInArgs {
+    const double* v;
+    const double* scale;  // device: 1 / max |v|
+    double h2, bp, bm;
+};
 template <typename T, typename S>
-bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* bc, int nu, hipStream_t s);
+bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* bc, int nu, hipStream_t s,
+                    const CastInArgs* cast = nullptr);
 template <typename T, typename S>
 bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, const S* z_in, S* z_out,
-                  int nu, hipStream_t s);
+                  int nu, hipStream_t s, double* out = nullptr, const double* out_scale = nullptr);
 
 // casts at the precision boundary: rhs0 = scale * h2 * v / beta(node); v FP64, level-0 box
 template <typename T>
@@ -221,10 +230,10 @@ constexpr int64_t RED_PART_DOUBLES = (int64_t)(KRED + 1) * RED_BLOCKS;
 constexpr int RED_THREADS = 256;
 // out[i] = <V_i, w> for i < k; V_i = V + i * ld
 void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* part, double* out,
-                  hipStream_t s);
+                  hipStream_t s, double* host_out = nullptr);
 // w -= sum_{i<k} h[i] V_i; then out[i] = <V_i, w> for i < k2 and out[k2] = <w, w> (if with_norm)
 void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
-                    int with_norm, double* part, double* out, hipStream_t s);
+                    int with_norm, double* part, double* out, hipStream_t s, double* host_out = nullptr);
 // the streaming first stage of run_update_dot alone (block partials in part)
 void run_update_dot_stage1(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
                            int with_norm, double* part, hipStream_t s);
@@ -233,7 +242,7 @@ void run_normalize(const double* x, const double* nrm2, double* y, int64_t n, hi
 // y = (w - V h) / sqrt(h[k] - |h|^2) (second CGS pass + normalisation; h[k] = |w|^2);
 // the squared norm to *nrm2_out, max |y| and its reciprocal to scale_out[0..1]
 void run_update_scale(const double* V, int64_t ld, int k, const double* h, const double* w, double* y, int64_t n,
-                      double* nrm2_out, double* part, double* scale_out, hipStream_t s);
+                      double* nrm2_out, double* part, double* scale_out, hipStream_t s, double* nrm2_host = nullptr);
 // x += sum_{i<k} y[i] Z_i  (y on the device)
 void run_axpy_multi(const double* Z, int64_t ld, int k, const double* y, double* x, int64_t n, hipStream_t s);
 // y = a x + b y

@@ -975,6 +975,15 @@ struct FusedLDS {
     int nrec;
 };
 
+// the FP64 input of a V-cycle and its scaling (run_cast_in), for the first leg
+template <typename T>
+struct CastInT {
+    const double* v = nullptr;
+    const double* scale = nullptr;
+    double h2 = 0, bp = 1, bm = 1;
+    T* b_out = nullptr;
+};
+
 template <typename T>
 __device__ inline void lds_row(const LevelDev& L, const FusedLDS<T>& S, int i, int j, int lx, int ly, T* acc,
                                T* diag) {
@@ -1018,9 +1027,12 @@ __device__ inline T lds_resid(const LevelDev& L, const FusedLDS<T>& Sh, int i, i
     return Sh.bs[ly][lx] - (diag * Sh.zs[ly][lx] + acc);
 }
 
-// load labels, b, z (optional) and the irregular rows of the tile into LDS
+// load labels, b, z (optional) and the irregular rows of the tile into LDS.
+// With C.v set, b is made from the FP64 vector instead (as run_cast_in does)
+// and the tile's own nodes of it are written to b for the later legs.
 template <typename T, typename S>
-__device__ inline void lds_load(const LevelDev& F, int x0, int y0, const S* z, const T* b, FusedLDS<T>& Sh) {
+__device__ inline void lds_load(const LevelDev& F, int x0, int y0, const S* z, const T* b, FusedLDS<T>& Sh,
+                                const CastInT<T>& C = CastInT<T>{}) {
     uint8_t labv[FNPT];
     T bv[FNPT], zv[FNPT];
     int32_t irr[FNPT];
@@ -1034,7 +1046,20 @@ __device__ inline void lds_load(const LevelDev& F, int x0, int y0, const S* z, c
                          j < F.box.lo[1] + F.box.dims[1];
         const int64_t l = inb ? F.box.idx(i, j, 0) : 0;
         labv[q] = inb ? F.labels[l] : (uint8_t)0;
-        bv[q] = inb ? b[l] : (T)0;
+        if (C.v) {
+            double val = 0.0;
+            if (inb) {
+                const uint8_t kk = labv[q] & KIND_MASK;
+                const double vl = C.v[l], sc = *C.scale;
+                if (kk == K_PLUS) val = sc * C.h2 * vl / C.bp;
+                else if (kk == K_MINUS) val = sc * C.h2 * vl / C.bm;
+            }
+            bv[q] = (T)val;
+            if (inb && lx >= FHALO && lx < FHALO + FTX && ly >= FHALO && ly < FHALO + FTY)
+                C.b_out[l] = bv[q];  // this tile's nodes: each written by one tile
+        } else {
+            bv[q] = inb ? b[l] : (T)0;
+        }
         zv[q] = (inb && z) ? load_it<T, S>(z, l) : (T)0;
         irr[q] = inb ? F.irr_index[l] : -1;
     }
@@ -1063,17 +1088,16 @@ __device__ inline void lds_load(const LevelDev& F, int x0, int y0, const S* z, c
     }
 }
 
-// z += P zc on the loaded region (as prolong_node), the coarse parents staged in LDS
+// coarse parents of the loaded region: fetched into registers first (so the
+// loads overlap the tile's own), then staged in LDS
+constexpr int FCPT = (FCX * FCY + FTHREADS - 1) / FTHREADS;
 template <typename T, typename S>
-__device__ inline void lds_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, int x0, int y0,
-                                   FusedLDS<T>& Sh, T (*cz)[FCX], uint8_t (*cl)[FCX]) {
+__device__ inline void prolong_fetch(const LevelDev& C, const S* zc, int x0, int y0, T (&cv)[FCPT],
+                                     uint8_t (&clv)[FCPT]) {
     const int cx0 = (x0 - FHALO) >> 1, cy0 = (y0 - FHALO) >> 1;
     constexpr int CN = FCX * FCY;
-    constexpr int CPT = (CN + FTHREADS - 1) / FTHREADS;
-    T cv[CPT];
-    uint8_t clv[CPT];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
+    for (int q = 0; q < FCPT; ++q) {
         const int t = threadIdx.x + FTHREADS * q;
         const int P0 = cx0 + t % FCX, P1 = cy0 + t / FCX;
         const bool cin = t < CN && P0 >= C.box.lo[0] && P0 < C.box.lo[0] + C.box.dims[0] && P1 >= C.box.lo[1] &&
@@ -1082,8 +1106,16 @@ __device__ inline void lds_prolong(const LevelDev& F, const LevelDev& C, int mod
         cv[q] = cin ? load_it<T, S>(zc, lp) : (T)0;
         clv[q] = cin ? C.labels[lp] : (uint8_t)255;  // 255: outside the coarse box
     }
+}
+
+// z += P zc on the loaded region (as prolong_node), the coarse parents staged in LDS
+template <typename T, typename S>
+__device__ inline void lds_prolong(int mode, int x0, int y0, FusedLDS<T>& Sh, const T (&cv)[FCPT],
+                                   const uint8_t (&clv)[FCPT], T (*cz)[FCX], uint8_t (*cl)[FCX]) {
+    const int cx0 = (x0 - FHALO) >> 1, cy0 = (y0 - FHALO) >> 1;
+    constexpr int CN = FCX * FCY;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
+    for (int q = 0; q < FCPT; ++q) {
         const int t = threadIdx.x + FTHREADS * q;
         if (t < CN) {
             cz[t / FCX][t % FCX] = cv[q];
@@ -1129,30 +1161,49 @@ __device__ inline void lds_store(const LevelDev& F, int x0, int y0, const FusedL
     }
 }
 
+// the tile's core nodes as the V-cycle's FP64 output (as run_cast_out does:
+// out = z / scale at unknowns, 0 elsewhere; nodes outside the core untouched)
+template <typename T, typename S>
+__device__ inline void lds_store_out(const LevelDev& F, int x0, int y0, const FusedLDS<T>& Sh, double* out,
+                                     const double* scale) {
+    const double inv = 1.0 / *scale;
+    for (int t = threadIdx.x; t < FTX * FTY; t += FTHREADS) {
+        const int lx = FHALO + t % FTX, ly = FHALO + t / FTX;
+        const int i = x0 - FHALO + lx, j = y0 - FHALO + ly;
+        if (i > F.core_hi[0] || j > F.core_hi[1]) continue;
+        out[F.box.idx(i, j, 0)] = is_unknown(Sh.ls[ly][lx]) ? (double)Sh.zs[ly][lx] * inv : 0.0;
+    }
+}
+
 // down leg: z = 0, nh half-sweeps (red first), write z, then bc = 4 HW(residual)
 template <typename T, typename S>
 __global__ void __launch_bounds__(FTHREADS) k_down_2d(LevelDev F, LevelDev C, const T* __restrict__ b,
-                                                      S* __restrict__ z, T* __restrict__ bc, int nh) {
+                                                      S* __restrict__ z, T* __restrict__ bc, int nh, CastInT<T> cin) {
     __shared__ FusedLDS<T> Sh;
     const int x0 = F.core_lo[0] + blockIdx.x * FTX, y0 = F.core_lo[1] + blockIdx.y * FTY;
-    lds_load<T, S>(F, x0, y0, nullptr, b, Sh);
+    // coarse nodes whose centre 2I lies in this tile (at most FTX/2 x FTY/2 <= FTHREADS);
+    // their labels are fetched with the tile's loads
+    const int I0 = (x0 + 1) >> 1, J0 = (y0 + 1) >> 1;
+    const int I1 = (min(x0 + FTX - 1, F.core_hi[0])) >> 1, J1 = (min(y0 + FTY - 1, F.core_hi[1])) >> 1;
+    const int nI = I1 - I0 + 1, nJ = J1 - J0 + 1;
+    const int tI = I0 + (int)threadIdx.x % max(nI, 1), tJ = J0 + (int)threadIdx.x / max(nI, 1);
+    const bool mine = (int)threadIdx.x < nI * nJ && tI >= C.core_lo[0] && tI <= C.core_hi[0] &&
+                      tJ >= C.core_lo[1] && tJ <= C.core_hi[1];
+    const uint8_t clab = mine ? C.labels[C.box.idx(tI, tJ, 0)] : (uint8_t)0;
+    lds_load<T, S>(F, x0, y0, nullptr, b, Sh, cin);
     __syncthreads();
     for (int h2 = 0; h2 < nh; ++h2) {
         lds_half_sweep<T, S>(F, x0, y0, h2 & 1, Sh);
         __syncthreads();
     }
     lds_store<T, S>(F, x0, y0, Sh, z);
-    // coarse nodes whose centre 2I lies in this tile
-    const int I0 = (x0 + 1) >> 1, J0 = (y0 + 1) >> 1;
-    const int I1 = (min(x0 + FTX - 1, F.core_hi[0])) >> 1, J1 = (min(y0 + FTY - 1, F.core_hi[1])) >> 1;
     const T w0 = (T)0.5, w1 = (T)0.125;
-    for (int t = threadIdx.x; t < (I1 - I0 + 1) * (J1 - J0 + 1); t += FTHREADS) {
-        const int I = I0 + t % (I1 - I0 + 1), J = J0 + t / (I1 - I0 + 1);
-        if (I < C.core_lo[0] || I > C.core_hi[0] || J < C.core_lo[1] || J > C.core_hi[1]) continue;
+    if (mine) {
+        const int I = tI, J = tJ;
         const int64_t lc = C.box.idx(I, J, 0);
-        if (!is_unknown(C.labels[lc])) {
+        if (!is_unknown(clab)) {
             bc[lc] = (T)0;
-            continue;
+            return;
         }
         const int fi = 2 * I, fj = 2 * J;
         const int lx = fi - (x0 - FHALO), ly = fj - (y0 - FHALO);
@@ -1169,41 +1220,58 @@ __global__ void __launch_bounds__(FTHREADS) k_down_2d(LevelDev F, LevelDev C, co
 template <typename T, typename S>
 __global__ void __launch_bounds__(FTHREADS) k_up_2d(LevelDev F, LevelDev C, int mode, const S* __restrict__ zc,
                                                     const T* __restrict__ b, const S* __restrict__ z_in,
-                                                    S* __restrict__ z, int nh) {
+                                                    S* __restrict__ z, int nh, double* __restrict__ out,
+                                                    const double* __restrict__ out_scale) {
     __shared__ FusedLDS<T> Sh;
     __shared__ T cz[FCY][FCX];
     __shared__ uint8_t cl[FCY][FCX];
     const int x0 = F.core_lo[0] + blockIdx.x * FTX, y0 = F.core_lo[1] + blockIdx.y * FTY;
+    T cv[FCPT];
+    uint8_t clv[FCPT];
+    prolong_fetch<T, S>(C, zc, x0, y0, cv, clv);
     lds_load<T, S>(F, x0, y0, z_in, b, Sh);
-    lds_prolong<T, S>(F, C, mode, zc, x0, y0, Sh, cz, cl);
+    lds_prolong<T, S>(mode, x0, y0, Sh, cv, clv, cz, cl);
     __syncthreads();
     for (int h2 = 0; h2 < nh; ++h2) {
         lds_half_sweep<T, S>(F, x0, y0, h2 & 1, Sh);
         __syncthreads();
     }
-    lds_store<T, S>(F, x0, y0, Sh, z);
+    if (out)
+        lds_store_out<T, S>(F, x0, y0, Sh, out, out_scale);
+    else
+        lds_store<T, S>(F, x0, y0, Sh, z);
 }
 
 template <typename T, typename S>
-bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* bc, int nu, hipStream_t s) {
+bool run_down_fused(const LevelDev& F, const LevelDev& C, const T* b, S* z, T* bc, int nu, hipStream_t s,
+                    const CastInArgs* cast) {
     if (F.dim != 2 || 2 * nu > FHALO - 2) return false;
     const int nx = F.core_hi[0] - F.core_lo[0] + 1, ny = F.core_hi[1] - F.core_lo[1] + 1;
     if (nx <= 0 || ny <= 0) return false;
+    CastInT<T> cin;
+    if (cast) {
+        cin.v = cast->v;
+        cin.scale = cast->scale;
+        cin.h2 = cast->h2;
+        cin.bp = cast->bp;
+        cin.bm = cast->bm;
+        cin.b_out = const_cast<T*>(b);
+    }
     hipLaunchKernelGGL((k_down_2d<T, S>), dim3(cdiv(nx, FTX), cdiv(ny, FTY)), dim3(FTHREADS), 0, s, F, C, b, z, bc,
-                       2 * nu);
+                       2 * nu, cin);
     IIM_LAUNCH_CHECK();
     return true;
 }
 
 template <typename T, typename S>
 bool run_up_fused(const LevelDev& F, const LevelDev& C, int mode, const S* zc, const T* b, const S* z_in, S* z_out,
-                  int nu, hipStream_t s) {
+                  int nu, hipStream_t s, double* out, const double* out_scale) {
     if (F.dim != 2 || 2 * nu > FHALO - 2) return false;
     if ((const void*)z_in == (const void*)z_out) throw Error(IIM_E_INTERNAL, "fused up leg needs distinct buffers");
     const int nx = F.core_hi[0] - F.core_lo[0] + 1, ny = F.core_hi[1] - F.core_lo[1] + 1;
     if (nx <= 0 || ny <= 0) return false;
     hipLaunchKernelGGL((k_up_2d<T, S>), dim3(cdiv(nx, FTX), cdiv(ny, FTY)), dim3(FTHREADS), 0, s, F, C, mode, zc, b,
-                       z_in, z_out, 2 * nu);
+                       z_in, z_out, 2 * nu, out, out_scale);
     IIM_LAUNCH_CHECK();
     return true;
 }
@@ -1538,9 +1606,10 @@ void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const ui
     template void run_coarse_solve<T, S>(const LevelDev&, const int32_t*, int64_t, const T*, const T*, S*, \
                                          hipStream_t);                                                    \
     template void run_tail<T, S>(int, const TailDev*, int64_t, hipStream_t);                              \
-    template bool run_down_fused<T, S>(const LevelDev&, const LevelDev&, const T*, S*, T*, int, hipStream_t); \
+    template bool run_down_fused<T, S>(const LevelDev&, const LevelDev&, const T*, S*, T*, int, hipStream_t,      \
+                                       const CastInArgs*);                                                           \
     template bool run_up_fused<T, S>(const LevelDev&, const LevelDev&, int, const S*, const T*, const S*, S*, int, \
-                                     hipStream_t);
+                                     hipStream_t, double*, const double*);
 INST_TS(double, double)
 INST_TS(float, float)
 INST_TS(float, __half)

@@ -76,7 +76,7 @@ void Server::worker() {
     hipStream_t s = nullptr;
     double* hpin = nullptr;
     bool ok = hipSetDevice(device) == hipSuccess && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
-              hipHostMalloc((void**)&hpin, HPIN_DOUBLES * sizeof(double), hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc((void**)&hpin, HPIN_DOUBLES * sizeof(double), hipHostMallocCoherent) == hipSuccess;
     while (true) {
         Job* j = nullptr;
         {
