@@ -699,21 +699,32 @@ void Problem::vcycle_t(const double* v, double* out, bool scaled, bool out_basis
         if (!have_b) run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
         have_b = true;
     };
+    // 3D colour-split levels start their pre-smoothing without a zero pass: the
+    // first colour-0 half-sweep from zero (z = b / diag) is done by the pass that
+    // makes b (the cast on level 0, the restriction below it)
+    bool started = false;  // level l's iterate already holds its first half-sweep
     for (int l = 0; l < t; ++l) {
         if (down_leg<T, S>(l, l == 0 ? &cast : nullptr)) {
             have_b = true;
             continue;
         }
-        cast_in();
         LevelDev D = level_dev(l), C = level_dev(l + 1);
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
-        run_zero<S>(z, levels[l].vsize(), stream);
+        const bool fuse = D.split && opt.nu_pre > 0;
+        if (l == 0 && fuse && !have_b) {
+            run_cast_sweep0<T, S>(D, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, b, z, stream);
+            have_b = started = true;
+        }
+        cast_in();
+        if (!started) run_zero<S>(z, levels[l].vsize(), stream);
         for (int s = 0; s < opt.nu_pre; ++s) {
-            run_rbgs<T, S>(D, 0, z, b, stream);
+            if (!(s == 0 && started)) run_rbgs<T, S>(D, 0, z, b, stream);
             run_rbgs<T, S>(D, 1, z, b, stream);
         }
-        run_resid_restrict<T, S>(D, C, z, b, (T*)levels[l + 1].b, stream);
+        const bool next = dim == 3 && l + 1 < t && level_dev(l + 1).split && opt.nu_pre > 0;
+        run_resid_restrict<T, S>(D, C, z, b, (T*)levels[l + 1].b, stream, next ? (S*)levels[l + 1].z : nullptr);
+        started = next;
     }
     cast_in();  // every level in the tail
     run_tail<T, S>(dim, d_tail, tail_lds_bytes, stream);  // levels t..nl-1, coarse solve included
@@ -732,9 +743,16 @@ void Problem::vcycle_t(const double* v, double* out, bool scaled, bool out_basis
         S* z = (S*)levels[l].z;
         T* b = (T*)levels[l].b;
         run_prolong<T, S>(D, C, mode, zres, z, stream);
+        // the last half-sweep on a colour-split level 0 may write a basis column directly
+        const bool fuse_out = l == 0 && out_basis && D.split && opt.nu_post > 0;
         for (int s = 0; s < opt.nu_post; ++s) {
             run_rbgs<T, S>(D, 0, z, b, stream);
-            run_rbgs<T, S>(D, 1, z, b, stream);
+            if (fuse_out && s == opt.nu_post - 1) {
+                run_rbgs_out<T, S>(D, z, b, out, red_scale + 1, stream);
+                have_out = true;
+            } else {
+                run_rbgs<T, S>(D, 1, z, b, stream);
+            }
         }
         zres = z;
     }

@@ -149,7 +149,8 @@ __host__ __device__ inline int64_t vidx(const LevelDev& L, int i, int j, int k) 
 template <typename T, typename S>
 void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s);
 template <typename T, typename S>
-void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const T* b, T* bc, hipStream_t s);
+void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const T* b, T* bc, hipStream_t s,
+                        S* zc0 = nullptr);  // zc0 (3D): also the coarse iterate after its first half-sweep from zero
 template <typename T, typename S>
 void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S* z, hipStream_t s);
 template <typename T, typename S>
@@ -206,6 +207,13 @@ void run_cast_in(const LevelDev& L, const double* v, const double* scale_dev, do
                  double beta_minus, T* rhs, hipStream_t s);
 template <typename S>
 void run_cast_out(const LevelDev& L, const S* z, const double* scale_dev, double* out, hipStream_t s);
+// colour-split 3D level 0: run_cast_in + zero iterate + the colour-0 half-sweep in one pass
+template <typename T, typename S>
+void run_cast_sweep0(const LevelDev& L, const double* v, const double* scale_dev, double h2, double bp, double bm,
+                     T* b, S* z, hipStream_t s);
+// colour-split 3D level 0: the colour-1 half-sweep + run_cast_out in one pass (out zero off the core rows)
+template <typename T, typename S>
+void run_rbgs_out(const LevelDev& L, const S* z, const T* b, double* out, const double* scale_dev, hipStream_t s);
 
 // apply weights from the raw stencils (Neumann closure folded in) and data coefficients
 void run_apply_weights(int bc, const int64_t* ptr, int64_t ncs, int w, int nrows, const double* S, const double* Sc,

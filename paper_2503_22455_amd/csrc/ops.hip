@@ -403,6 +403,10 @@ template <typename T, typename S> __device__ inline void store_t(S* p, int64_t i
     p[i] = from_f((float)v, (S*)nullptr);
 }
 template <> __device__ inline void store_t<double, double>(double* p, int64_t i, double v) { p[i] = v; }
+// v rounded to the storage type S (kept in T)
+template <typename T, typename S>
+__device__ inline T round_s(T v) { return (T)to_f(from_f((float)v, (S*)nullptr)); }
+template <> __device__ inline double round_s<double, double>(double v) { return v; }
 
 // Shortley-Weller row at an unknown from its neighbour values: diagonal and
 // off-diagonal sum (zm[d], zp[d] = z at the neighbours (d, -) and (d, +))
@@ -749,7 +753,7 @@ __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, i
 // residual is zero.  Same weights and summation order as restrict_node.
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int gx, int gy, const S* z, const T* b,
-                                                    T* bc) {
+                                                    T* bc, S* zc0) {
     const Blk3 B = xcd_block3(gx, gy);
     const int I = C.core_lo[0] + B.x * 64 + (threadIdx.x & 63);
     const int J = C.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
@@ -791,6 +795,7 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
         inside = inside && c[d] - 1 >= F.box.lo[d] && c[d] + 1 < F.box.lo[d] + F.box.dims[d];
     if (!inside) {
         bc[vc] = (T)0;
+        if (zc0) store_t<T, S>(zc0, vc, (T)0);
         return;
     }
     T r[7];
@@ -807,7 +812,103 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
     T acc = w0 * r[0];
 #pragma unroll
     for (int d = 0; d < 3; ++d) acc += w1 * (r[1 + 2 * d] + r[2 + 2 * d]);
-    bc[vc] = (T)4 * acc;
+    const T bval = (T)4 * acc;
+    bc[vc] = bval;
+    if (zc0) {
+        // the coarse level's first half-sweep (colour 0) from a zero iterate: the
+        // neighbours are zero, so z = b / diag at colour-0 unknowns and 0 elsewhere
+        T zv = (T)0;
+        if (((I + J + K) & 1) == 0) {
+            const T diag = (labc & F_SW_IRR) ? rec_ptr<T>(C)[(int64_t)C.irr_index[C.box.idx(I, J, K)] * 7] : (T)(-6);
+            if (diag != (T)0) zv = bval / diag;
+        }
+        store_t<T, S>(zc0, vc, zv);
+    }
+}
+
+// The first steps of the level-0 pre-smoothing of a colour-split level in one
+// pass: the cast of the FP64 input (as run_cast_in), the zero iterate and the
+// colour-0 half-sweep from it (z = b / diag at colour-0 unknowns: every
+// neighbour is zero).  A thread owns the two nodes 2m, 2m + 1 of a box row (one
+// of each colour); every row of the box is covered, padding entries included.
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_cast_sweep0(LevelDev L, int gxm, const double* v, const double* scale,
+                                                     double h2, double bp, double bm, T* b, S* z) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = (blockIdx.x % gxm) * 64 + lane, r = 4 * (blockIdx.x / gxm) + wv;
+    const int nrows = L.box.dims[1] * L.box.dims[2];
+    if (m >= L.hx || r >= nrows) return;
+    const int j = L.box.lo[1] + r % L.box.dims[1], k = L.box.lo[2] + r / L.box.dims[1];
+    const int par = (L.box.lo[0] + j + k) & 1;  // colour of node a = 2m
+    const double sc = *scale;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int a = 2 * m + q, colour = par ^ q;
+        const int64_t e = (int64_t)colour * L.half + (int64_t)r * L.hx + m;
+        double val = 0.0;
+        uint8_t lab = 0;
+        int64_t l = 0;
+        if (a < L.box.dims[0]) {
+            l = (int64_t)a + (int64_t)L.box.dims[0] * r;
+            lab = L.labels[l];
+            const uint8_t kk = lab & KIND_MASK;
+            if (kk == K_PLUS) val = sc * h2 * v[l] / bp;
+            else if (kk == K_MINUS) val = sc * h2 * v[l] / bm;
+        }
+        const T bv = (T)val;
+        b[e] = bv;
+        T zv = (T)0;
+        if (colour == 0 && is_unknown(lab)) {
+            const T diag = (lab & F_SW_IRR) ? rec_ptr<T>(L)[(int64_t)L.irr_index[l] * 7] : (T)(-6);
+            if (diag != (T)0) zv = bv / diag;
+        }
+        store_t<T, S>(z, e, zv);
+    }
+}
+
+// The last level-0 post-smoothing half-sweep (colour 1) of a colour-split level
+// writing the V-cycle's FP64 output instead of z (as run_cast_out: z / scale at
+// unknowns, 0 elsewhere) for both nodes of each pair 2m, 2m + 1 of the core's
+// rows.  The output is zero off those rows already (a Krylov basis column).
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_rbgs_split_out(LevelDev L, int gx, int gy, const S* z, const T* b,
+                                                        double* out, const double* scale) {
+    const Blk3 B = xcd_block3(gx, gy);
+    const int m = B.x * 64 + (threadIdx.x & 63);
+    const int j = L.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
+    const int k = L.core_lo[2] + B.z;
+    if (j > L.core_hi[1] || m >= L.hx) return;
+    const int p1 = (1 ^ (L.box.lo[0] + j + k)) & 1;
+    const int a1 = 2 * m + p1, a0 = 2 * m + (p1 ^ 1);  // colour-1 node and its colour-0 partner
+    const int r = (j - L.box.lo[1]) + L.box.dims[1] * (k - L.box.lo[2]);
+    const int row = L.box.dims[0] * r;
+    const double inv = 1.0 / *scale;
+    if (a0 < L.box.dims[0]) {
+        const uint8_t lab0 = L.labels[row + a0];
+        out[row + a0] = is_unknown(lab0) ? (double)load_it<T, S>(z, r * L.hx + m) * inv : 0.0;
+    }
+    if (a1 >= L.box.dims[0]) return;
+    const int i = L.box.lo[0] + a1;
+    const uint8_t lab = L.labels[row + a1];
+    double o = 0.0;
+    if (i >= L.core_lo[0] && i <= L.core_hi[0] && is_unknown(lab)) {
+        const int own = (int)L.half + r * L.hx + m;
+        const int ry = L.hx, rz = L.hx * L.box.dims[1];
+        const int base = r * L.hx;  // colour-0 array, row r
+        T zm[3], zp[3];
+        zm[0] = load_it<T, S>(z, base + ((a1 - 1) >> 1));
+        zp[0] = load_it<T, S>(z, base + ((a1 + 1) >> 1));
+        zm[1] = load_it<T, S>(z, base - ry + m);
+        zp[1] = load_it<T, S>(z, base + ry + m);
+        zm[2] = load_it<T, S>(z, base - rz + m);
+        zp[2] = load_it<T, S>(z, base + rz + m);
+        const T bv = b[own];
+        T diag, off;
+        sw_combine<T, 3>(L, row + a1, lab, zm, zp, &diag, &off);
+        const T zn = diag != (T)0 ? round_s<T, S>((bv - off) / diag) : load_it<T, S>(z, own);
+        o = (double)zn * inv;
+    }
+    out[row + a1] = o;
 }
 
 template <typename T, typename S>
@@ -961,9 +1062,6 @@ constexpr int FNPT = (FN + FTHREADS - 1) / FTHREADS;
 constexpr int FREC = 320;  // irregular rows cached per tile
 constexpr int FCX = FLX / 2 + 2, FCY = FLY / 2 + 2;  // coarse parents of the loaded region
 
-template <typename T, typename S>
-__device__ inline T round_s(T v) { return (T)to_f(from_f((float)v, (S*)nullptr)); }
-template <> __device__ inline double round_s<double, double>(double v) { return v; }
 
 template <typename T>
 struct FusedLDS {
@@ -1348,14 +1446,15 @@ void run_sw_apply(const LevelDev& L, const S* z, T* y, hipStream_t s) {
 }
 
 template <typename T, typename S>
-void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const T* b, T* bc, hipStream_t s) {
+void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const T* b, T* bc, hipStream_t s, S* zc0) {
+    if (zc0 && F.dim != 3) throw Error(IIM_E_INTERNAL, "coarse iterate start is built for 3D levels");
     dim3 g, k;
     level_grid(C, &g, &k);
     if (F.dim == 2)
         hipLaunchKernelGGL((k_resid_restrict<T, S, 2>), g, k, 0, s, F, C, z, b, bc);
     else
         hipLaunchKernelGGL((k_restrict3<T, S>), dim3(g.x * g.y * g.z), dim3(256), 0, s, F, C, (int)g.x, (int)g.y, z, b,
-                           bc);
+                           bc, zc0);
     IIM_LAUNCH_CHECK();
 }
 
@@ -1505,6 +1604,27 @@ void run_cast_out(const LevelDev& L, const S* z, const double* scale_dev, double
     IIM_LAUNCH_CHECK();
 }
 
+template <typename T, typename S>
+void run_cast_sweep0(const LevelDev& L, const double* v, const double* scale_dev, double h2, double bp, double bm,
+                     T* b, S* z, hipStream_t s) {
+    if (!L.split || L.dim != 3) throw Error(IIM_E_INTERNAL, "cast + first half-sweep needs a colour-split 3D level");
+    const int gxm = cdiv(L.hx, 64);
+    const int nb = gxm * cdiv((int64_t)L.box.dims[1] * L.box.dims[2], 4);
+    hipLaunchKernelGGL((k_cast_sweep0<T, S>), dim3(nb), dim3(256), 0, s, L, gxm, v, scale_dev, h2, bp, bm, b, z);
+    IIM_LAUNCH_CHECK();
+}
+
+template <typename T, typename S>
+void run_rbgs_out(const LevelDev& L, const S* z, const T* b, double* out, const double* scale_dev, hipStream_t s) {
+    if (!L.split || L.dim != 3) throw Error(IIM_E_INTERNAL, "half-sweep with output needs a colour-split 3D level");
+    const int ny = L.core_hi[1] - L.core_lo[1] + 1, nz = L.core_hi[2] - L.core_lo[2] + 1;
+    if (ny <= 0 || nz <= 0 || L.hx <= 0) return;
+    const int gx = cdiv(L.hx, 64), gy = cdiv(ny, 4);
+    hipLaunchKernelGGL((k_rbgs_split_out<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, gx, gy, z, b, out,
+                       scale_dev);
+    IIM_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------------------
 // storage box <-> level layout
 // ---------------------------------------------------------------------------
@@ -1600,9 +1720,12 @@ void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const ui
 #define INST_TS(T, S)                                                                                     \
     template void run_rbgs<T, S>(const LevelDev&, int, S*, const T*, hipStream_t);                        \
     template void run_resid_restrict<T, S>(const LevelDev&, const LevelDev&, const S*, const T*, T*,      \
-                                           hipStream_t);                                                  \
+                                           hipStream_t, S*);                                              \
     template void run_prolong<T, S>(const LevelDev&, const LevelDev&, int, const S*, S*, hipStream_t);    \
     template void run_sw_apply<T, S>(const LevelDev&, const S*, T*, hipStream_t);                         \
+    template void run_cast_sweep0<T, S>(const LevelDev&, const double*, const double*, double, double, double, T*, \
+                                        S*, hipStream_t);                                                             \
+    template void run_rbgs_out<T, S>(const LevelDev&, const S*, const T*, double*, const double*, hipStream_t);     \
     template void run_coarse_solve<T, S>(const LevelDev&, const int32_t*, int64_t, const T*, const T*, S*, \
                                          hipStream_t);                                                    \
     template void run_tail<T, S>(int, const TailDev*, int64_t, hipStream_t);                              \
