@@ -45,12 +45,17 @@ DESCR = {
 HBM_PEAK_GBS = 8000.0
 
 # Bytes beyond L2 per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch; `python3 bench.py --probe-kernel 5`), each
-# scaled by what the same counter reads for a plain copy of 2^26 doubles
-# (512 MiB each way: FETCH_SIZE reads 262158.9 KiB, WRITE_SIZE 524288 KiB).
+# WRITE_SIZE, KiB per dispatch; `python3 bench.py --probe-kernel <id>`), each
+# scaled by what the same counter reads, in the same run, for a plain copy of
+# 2^26 doubles (512 MiB each way: FETCH_SIZE reads about 262160 KiB, WRITE_SIZE
+# 524288 KiB).
 # Keyed by workload and kernel id; valid only while the kernel's source text
 # hashes to `sha` (otherwise the roofline reports traffic null).
 TRAFFIC = {
+    ("cfg2", 9): {"fetch_kib": 26335.738636, "fetch_scale": 524288.0 / 262161.4375, "write_kib": 8943.03125,
+                  "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/ops.hip",
+                  "begin": "constexpr int FTX = 32, FTY = 32, FHALO = 6;",
+                  "end": "bool run_down_fused(const LevelDev& F", "sha": "ccba1c890744fce2"},
     ("cfg2", 5): {"fetch_kib": 28913.6875, "fetch_scale": 524288.0 / 262158.9, "write_kib": 8432.09375,
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/blas.hip",
                   "begin": "__global__ void __launch_bounds__(RED_THREADS) k_update_dot(",
