@@ -63,6 +63,7 @@ struct Level {
     // above the tail), hx entries per box row and colour, half per colour
     int split = 0, hx = 0;
     int64_t half = 0;
+    uint8_t* lab_split = nullptr;  // labels in the colour-split layout
     int64_t vsize() const { return split ? 2 * half : box.size(); }
 };
 

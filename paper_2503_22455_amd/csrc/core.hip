@@ -537,9 +537,13 @@ void Problem::setup() {
     // reads and writes whole contiguous colour rows
     for (int l = 0; l < nl; ++l) {
         Level& L = levels[l];
-        L.hx = (L.box.dims[0] + 1) / 2;
+        L.hx = ((L.box.dims[0] + 1) / 2 + 3) / 4 * 4;
         L.half = (int64_t)L.hx * L.box.dims[1] * L.box.dims[2];
         L.split = dim == 3 && l < tail_first && opt_split && 2 * L.half <= (int64_t)INT32_MAX;
+        if (L.split) {
+            L.lab_split = (uint8_t*)mem.alloc(2 * L.half);
+            run_box_to_level<uint8_t>(level_dev(l), L.labels, L.lab_split, stream);
+        }
     }
     {
         const bool two = dim == 2 && opt_fused;
@@ -620,6 +624,7 @@ LevelDev Problem::level_dev(int l) const {
     D.split = L.split;
     D.hx = L.hx;
     D.half = L.half;
+    D.lab_split = L.lab_split;
     return D;
 }
 
@@ -1026,8 +1031,13 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     // the Krylov bases V (m+1) and Z (m), the V-cycle iterate and right-hand side
     const int64_t zbufs = (dim == 2 && o.fused_smoothing) ? 2 : 1;  // second iterate buffer of the fused 2D legs
     // entries of a level vector: colour-split 3D levels round each box row up to even
-    auto vec = [&](const int64_t* d) { return dim == 3 ? 2 * ((d[0] + 1) / 2) * d[1] * d[2] : d[0] * d[1] * d[2]; };
-    int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8) + vec(dims) * (zbufs * ssz + tsz) + (2 * m + 1) * 64 * 8;
+    auto vec = [&](const int64_t* d) {
+        return dim == 3 ? 2 * (((d[0] + 1) / 2 + 3) / 4 * 4) * d[1] * d[2] : d[0] * d[1] * d[2];
+    };
+    // (3D: the colour-split labels, one byte per vector entry)
+    const int64_t lsplit = dim == 3 ? 1 : 0;
+    int64_t bytes = N0 * (1 + 4 + 4 + 5 * 8 + (2 * m + 1) * 8) + vec(dims) * (zbufs * ssz + tsz + lsplit) +
+                    (2 * m + 1) * 64 * 8;
     // setup transients alive together: the crossing flags and one selection
     // output per axis, the selections' scratch
     bytes += N0 * 5 * dim + SEL_BLOCKS * SEL_MAX * 4;
@@ -1039,7 +1049,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
         n = (n + 1) / 2;
         for (int d = 0; d < dim; ++d) cd[d] = (cd[d] - 4) / 2 + 1 + 2 + 2;
         last = cd[0] * cd[1] * cd[2];
-        bytes += last * (1 + 4) + vec(cd) * (zbufs * ssz + tsz);
+        bytes += last * (1 + 4) + vec(cd) * (zbufs * ssz + tsz + lsplit);
     }
     // coarsest dense inverse (A, FP64 and FP32 inverses, column map)
     const int64_t nc = std::min<int64_t>(last, 4096);

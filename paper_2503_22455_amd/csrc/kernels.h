@@ -135,9 +135,13 @@ struct LevelDev {
     // Layout of the level's z and b.  split = 0: the storage box, x fastest.
     // split = 1 (3D grid levels): two colour arrays of `half` entries each; node
     // (i, j, k) of colour c = (i + j + k) & 1 sits at c * half + r * hx + (a >> 1),
-    // r = (j - lo_y) + dims_y (k - lo_z) its box row and a = i - lo_x, hx = (dims_x + 1) / 2.
+    // r = (j - lo_y) + dims_y (k - lo_z) its box row and a = i - lo_x; hx is
+    // (dims_x + 1) / 2 rounded up to a multiple of 4 (16-byte aligned rows of
+    // four entries).  lab_split holds the labels in the same layout (0 at
+    // entries of no node).
     int split, hx;
     int64_t half;
+    const uint8_t* lab_split;
 };
 // entries of a level vector and the index of node (i, j, k) in it
 __host__ __device__ inline int64_t vsize(const LevelDev& L) { return L.split ? 2 * L.half : L.box.size(); }

@@ -601,12 +601,92 @@ __global__ void __launch_bounds__(256) k_sw_apply(LevelDev L, const S* z, T* y) 
     y[v] = diag * load_it<T, S>(z, v) + off;
 }
 
-// half-sweep on a colour-split 3D level: threads walk the colour's entries of
-// each box row contiguously (x of the colour's nodes = lo_x + 2 m + offset).
+// levels with at least this many entries per colour take four entries per thread
+// in their half-sweeps (enough threads remain to fill the device)
+constexpr int64_t SPLIT4_MIN_ENTRIES = 1 << 20;
+
+// four consecutive entries of a level vector (16-byte aligned: the entry index is
+// a multiple of 4 and rows hold a multiple of 4 entries), converted to T
+template <typename S>
+struct alignas(4 * sizeof(S)) Vec4 {
+    S v[4];
+};
+template <typename T, typename S>
+__device__ inline void ld4(const S* p, int e, T (&out)[4]) {
+    const Vec4<S> q = *reinterpret_cast<const Vec4<S>*>(p + e);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) out[u] = load_it<T, S>(q.v, u);
+}
+
+// Half-sweep on a colour-split 3D level.  A thread owns four consecutive
+// entries m0..m0+3 of its colour in one box row (nodes x = lo + 2m + parity of
+// the row) and loads, as 16-byte vectors, their labels, right-hand sides and
+// the other colour's entries in the rows beside them (y +- 1, z +- 1) and in
+// their own row (plus one entry at either end for the x-neighbours).  Every load
+// is issued before the first test (the neighbours of core rows lie in the box).
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, int gx, int gy, S* z, const T* b) {
+    const Blk3 B = xcd_block3(gx, gy);
+    const int m0 = 4 * (B.x * 64 + (threadIdx.x & 63));
+    const int j = L.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
+    const int k = L.core_lo[2] + B.z;
+    if (j > L.core_hi[1] || m0 >= L.hx) return;
+    const int p = (colour ^ (L.box.lo[0] + j + k)) & 1;  // node of entry m: x offset a = 2m + p
+    const int r = (j - L.box.lo[1]) + L.box.dims[1] * (k - L.box.lo[2]);
+    const int own = colour * (int)L.half + r * L.hx + m0;
+    const int oth = (colour ^ 1) * (int)L.half + r * L.hx + m0;
+    const int ry = L.hx, rz = L.hx * L.box.dims[1];
+    const uint32_t lab4 = *reinterpret_cast<const uint32_t*>(L.lab_split + own);
+    T bv[4], c4[4], ym[4], yp[4], zmv[4], zpv[4];
+    ld4<T, T>(b, own, bv);
+    ld4<T, S>(z, oth, c4);
+    ld4<T, S>(z, oth - ry, ym);
+    ld4<T, S>(z, oth + ry, yp);
+    ld4<T, S>(z, oth - rz, zmv);
+    ld4<T, S>(z, oth + rz, zpv);
+    const T cm = load_it<T, S>(z, oth - 1), cp = load_it<T, S>(z, oth + 4);  // in the box: core rows
+    asm volatile("" ::"v"(lab4), "v"(bv[0]), "v"(c4[0]), "v"(ym[0]), "v"(yp[0]), "v"(zmv[0]), "v"(zpv[0]), "v"(cm),
+                 "v"(cp));
+    T out[4];
+    int done = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint8_t lab = (uint8_t)(lab4 >> (8 * u));
+        const int a = 2 * (m0 + u) + p, i = L.box.lo[0] + a;
+        out[u] = (T)0;
+        if (i < L.core_lo[0] || i > L.core_hi[0] || !is_unknown(lab)) continue;
+        T zm[3], zp[3];
+        zm[0] = p ? c4[u] : (u == 0 ? cm : c4[u - 1]);  // entry (a - 1) >> 1
+        zp[0] = p ? (u == 3 ? cp : c4[u + 1]) : c4[u];  // entry (a + 1) >> 1
+        zm[1] = ym[u];
+        zp[1] = yp[u];
+        zm[2] = zmv[u];
+        zp[2] = zpv[u];
+        T diag, off;
+        sw_combine<T, 3>(L, (int64_t)a + (int64_t)L.box.dims[0] * r, lab, zm, zp, &diag, &off);
+        if (diag == (T)0) continue;
+        out[u] = (bv[u] - off) / diag;
+        done |= 1 << u;
+    }
+    if (done == 15) {
+        Vec4<S> q;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) store_t<T, S>(q.v, u, out[u]);
+        *reinterpret_cast<Vec4<S>*>(z + own) = q;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (done & (1 << u)) store_t<T, S>(z, own + u, out[u]);
+    }
+}
+
+// Half-sweep on a colour-split 3D level, one entry per thread (levels too small
+// to fill the device with four entries per thread): threads walk the colour's
+// entries of each box row contiguously (x of the colour's nodes = lo_x + 2 m + offset).
 // Every load is issued before the first use (the neighbours of a core node are
 // in the box), and offsets are 32-bit (level vectors hold < 2^31 entries).
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, int gx, int gy, S* z, const T* b) {
+__global__ void __launch_bounds__(256) k_rbgs_split1(LevelDev L, int colour, int gx, int gy, S* z, const T* b) {
     const Blk3 B = xcd_block3(gx, gy);
     const int m = B.x * 64 + (threadIdx.x & 63);
     const int j = L.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
@@ -1420,8 +1500,14 @@ void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s) {
     if (L.split) {
         const int ny = L.core_hi[1] - L.core_lo[1] + 1, nz = L.core_hi[2] - L.core_lo[2] + 1;
         if (ny <= 0 || nz <= 0 || L.hx <= 0) return;
-        const int gx = cdiv(L.hx, 64), gy = cdiv(ny, 4);
-        hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, colour, gx, gy, z, b);
+        if (L.hx % 4 || !L.lab_split) throw Error(IIM_E_INTERNAL, "colour-split rows must hold a multiple of 4");
+        if (L.half >= SPLIT4_MIN_ENTRIES) {
+            const int gx = cdiv(L.hx / 4, 64), gy = cdiv(ny, 4);
+            hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, colour, gx, gy, z, b);
+        } else {
+            const int gx = cdiv(L.hx, 64), gy = cdiv(ny, 4);
+            hipLaunchKernelGGL((k_rbgs_split1<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, colour, gx, gy, z, b);
+        }
         IIM_LAUNCH_CHECK();
         return;
     }
@@ -1654,6 +1740,7 @@ void run_level_to_box(const LevelDev& L, const U* lev, U* boxed, hipStream_t s) 
     hipLaunchKernelGGL((k_box_level<U>), dim3(blocks), dim3(256), 0, s, L, lev, boxed, 0);
     IIM_LAUNCH_CHECK();
 }
+template void run_box_to_level<uint8_t>(const LevelDev&, const uint8_t*, uint8_t*, hipStream_t);
 template void run_box_to_level<double>(const LevelDev&, const double*, double*, hipStream_t);
 template void run_box_to_level<float>(const LevelDev&, const float*, float*, hipStream_t);
 template void run_box_to_level<__half>(const LevelDev&, const __half*, __half*, hipStream_t);
