@@ -31,7 +31,7 @@ OPTIONS = {"spheres32-neu-deep": dict(tail_nodes=-1)}
 def pair(request):
     wl = CASES[request.param]()
     O = oracle_for(wl)
-    G = gpu_for(wl, precision="fp64", rtol=1e-13, **OPTIONS.get(request.param, {}))
+    G = gpu_for(wl, precision="fp64", rtol=1e-14, **OPTIONS.get(request.param, {}))
     yield request.param, wl, O, G
     G.close()
 
@@ -148,8 +148,10 @@ def test_solve_matches_direct(pair):
     b = O.rhs(wl.rhs(O.labels), ug)
     ud = O.direct_solve(b)
     uu = u.cpu().numpy()[O.unknowns]
-    # the oracle's own check of the GPU solution's true residual
-    assert np.linalg.norm(b - L @ uu) <= 1e-12 * np.linalg.norm(b)
-    assert np.abs(uu - ud).max() <= 1e-11 * np.abs(ud).max(), np.abs(uu - ud).max() / np.abs(ud).max()
+    # the oracle's own check of the GPU solution's true residual, and the
+    # all-FP64 solution against the oracle's direct solve to 1e-12 relative
+    # (solved to rtol 1e-14: the measured errors are 1e-14 .. 1.3e-13)
+    assert np.linalg.norm(b - L @ uu) <= 1e-13 * np.linalg.norm(b)
+    assert np.abs(uu - ud).max() <= 1e-12 * np.abs(ud).max(), np.abs(uu - ud).max() / np.abs(ud).max()
     # non-unknown nodes are NaN
     assert np.isnan(u.cpu().numpy()[O.lab_flat == 0]).all()
