@@ -152,3 +152,47 @@ def test_dirichlet_3d_converges():
     orders, es = _order(lambda n: W.Workload("s", 3, n, W.GEOM_SPHERE, [0.01, 0.02, -0.01, 0.6], 0, 0,
                                             exact=W.ms_sin_pi_3d()), [24, 32])
     assert orders[0] > 2.5 and es[-1] < 2e-3, (orders, es)
+
+
+# ---- sixth order, (n, k) = (6, 7): the next discretisation of the paper (2D) ----
+
+@pytest.mark.parametrize("case", PATCH[:3], ids=[c[0] for c in PATCH[:3]])
+def test_patch_order6(case):
+    """With data from a polynomial of degree <= k - 1 = 6 the (6,7) equations hold
+    to round-off: the order-6 central stencil, the degree-6 least-squares ghosts
+    and the degree-6 box extrapolation are all exact on it."""
+    name, dim, n, kind, params, side, bc, bp, bm = case
+    rng = np.random.default_rng(7)
+    poly = lambda: W.ms_polynomial({e: rng.uniform(-1, 1) for e in monomial_exponents(dim, 6)}, dim)
+    ms = poly()
+    if side == W.SIDE_INTERFACE:
+        m2 = poly()
+        ms = W.Manufactured(ms.u_plus, ms.grad_plus, ms.lap_plus, m2.u_plus, m2.grad_plus, m2.lap_plus)
+    wl = W.Workload(name, dim, n, kind, params, side, bc, bp, bm, exact=ms)
+    P, L, LG, ug, b = _setup(wl, order_n=6, order_k=7)
+    uex = P.from_full(np.nan_to_num(wl.exact_solution(P.labels)))
+    res = L @ uex - b
+    scale = abs(L).max() * np.abs(uex).max()
+    assert np.abs(res).max() <= 1e-11 * scale
+
+
+def _err6(wl):
+    P, L, LG, ug, b = _setup(wl, order_n=6, order_k=7)
+    x = P.direct_solve(b)
+    return np.abs(x - P.from_full(wl.exact_solution(P.labels))).max()
+
+
+def test_dirichlet_order6():
+    """Sixth-order convergence of the solution (the paper's (6,7) scheme)."""
+    ns = [32, 64, 128]
+    es = [_err6(W.Workload("d", 2, n, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0, exact=_sol2d())) for n in ns]
+    orders = [np.log(es[i] / es[i + 1]) / np.log(ns[i + 1] / ns[i]) for i in range(2)]
+    assert orders[-1] > 5.7 and min(orders) > 5.0, (orders, es)
+
+
+def test_neumann_order6():
+    ns = [64, 128, 256]
+    es = [_err6(W.Workload("n", 2, n, W.GEOM_SPHERE_UNION, W.union_params(W.small_circles_union_2d()), 1, 1,
+                           exact=_sol2d())) for n in ns]
+    orders = [np.log(es[i] / es[i + 1]) / np.log(ns[i + 1] / ns[i]) for i in range(2)]
+    assert orders[-1] > 5.5 and min(orders) > 5.2, (orders, es)
