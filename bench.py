@@ -118,7 +118,8 @@ def kernel_roofline(wl, precision, torch, nu, reps=20):
     tsz = 8 if precision == "fp64" else 4
     dim = wl.dim
     nc1 = P.level_info(1)[1] if info["levels"] > 1 else 0
-    nrows = 2 if wl.bc == W.BC_DIRICHLET else (2 if wl.bc == W.BC_NEUMANN else 3)
+    w = wl.order[0] // 2
+    nrows = w + 1 if wl.bc == W.BC_JUMP else w  # ghost rows per entry (Neumann rows pre-combined)
     ncs = info["n_control_points"] * info["sides"]
     k = 6
     algo = {
@@ -157,7 +158,8 @@ def cpu_baseline(wl, its_gpu, nu, sample_iters=3):
     from oracle.krylov import fgmres
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        O = IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus)
+        O = IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus,
+                       order_n=wl.order[0], order_k=wl.order[1])
         L, LG = O.assemble()
         xyz, nrm = O.cp_arrays()
         ug = O.data_vector(wl.cp_data(xyz, nrm), wl.box_data())
@@ -293,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, help="override the workload's precision")
+    ap.add_argument("--order", type=int, default=4, choices=(4, 6),
+                    help="interior order of the discretisation: 4 = the (4,5) scheme, 6 = (6,7) (2D workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the request-stream workload instead")
@@ -321,6 +325,11 @@ def main():
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]()
     prec = args.precision or wl.precision
+    if args.order == 6:
+        if wl.dim != 2:
+            print("bench.py: the (6,7) scheme is built for 2D workloads", file=sys.stderr)
+            sys.exit(2)
+        wl.order = (6, 7)
     cpd, box, f, nu = prepare(wl, torch)
     print(f"[bench] workload {args.workload}: {nu} unknowns, precision {prec}", file=sys.stderr, flush=True)
 
@@ -404,7 +413,8 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == "fp64" else ("f64+f32" if prec == "mixed32" else "f64+f32/f16"),
         "data": "synthetic",
-        "config": {"workload": DESCR[args.workload], "n": wl.n, "dim": wl.dim, "unknowns": nu,
+        "config": {"workload": DESCR[args.workload] + (", (6,7) scheme" if args.order == 6 else ""),
+                   "n": wl.n, "dim": wl.dim, "unknowns": nu, "order": list(wl.order),
                    "precision": prec, "rtol": 1e-10},
         "p50_ms": pct(0.5), "p99_ms": pct(0.99), "solves_per_s": args.steps / total,
         "setup_ms_median": float(np.median(setup) * 1e3), "iterations": int(np.median(its)),

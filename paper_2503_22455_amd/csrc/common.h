@@ -300,6 +300,24 @@ __host__ __device__ inline int make_slot(int type, int j, int cs) { return type 
 // 4th-order central second-derivative coefficients a_0, a_1, a_2
 constexpr double A0 = -2.5, A1 = 4.0 / 3.0, A2 = -1.0 / 12.0;
 
+// central second-derivative coefficient a_j of order 2W (W = 2: 4th order,
+// W = 3: 6th order)
+template <int W>
+__host__ __device__ constexpr double ho_a(int j) {
+    return W == 2 ? (j == 0 ? -2.5 : j == 1 ? 4.0 / 3.0 : -1.0 / 12.0)
+                  : (j == 0 ? -49.0 / 18.0 : j == 1 ? 1.5 : j == 2 ? -3.0 / 20.0 : 1.0 / 90.0);
+}
+
+// Lagrange weight of point t (t = 0 the box face, t = 1 .. 2W the nodes behind
+// it) of the degree-2W polynomial through them, evaluated s steps beyond the face
+template <int W>
+__host__ __device__ constexpr double ho_ext(int s, int t) {
+    constexpr double e2[5] = {5, -10, 10, -5, 1};
+    constexpr double e31[7] = {7, -21, 35, -35, 21, -7, 1};
+    constexpr double e32[7] = {28, -112, 210, -224, 140, -48, 7};
+    return W == 2 ? e2[t] : (s == 1 ? e31[t] : e32[t]);
+}
+
 // ---------------------------------------------------------------------------
 // wavefront reductions
 // ---------------------------------------------------------------------------

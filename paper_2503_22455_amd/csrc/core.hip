@@ -277,7 +277,7 @@ void Problem::setup() {
             const bool empty = h_cnt[l] == 0;
             int mn[3] = {bb[0], bb[1], dim == 3 ? bb[2] : 0};
             int mx[3] = {bb[3], bb[4], dim == 3 ? bb[5] : 0};
-            L.box = make_box(dim, mn, mx, l == 0 ? 2 : 1, empty);
+            L.box = make_box(dim, mn, mx, l == 0 ? w : 1, empty);  // level 0: the stencil's reach
             for (int d = 0; d < 3; ++d) {
                 L.core_lo[d] = empty ? 1 : (d < dim ? mn[d] : 0);
                 L.core_hi[d] = empty ? 0 : (d < dim ? mx[d] : 0);
@@ -429,7 +429,7 @@ void Problem::setup() {
             nflags += levels[l].box.size();
         }
         uint8_t* flags = (uint8_t*)mem.alloc(nflags);
-        run_ho_irr_flag(L0.geom, box, L0.labels, flags, stream);
+        run_ho_irr_flag(L0.geom, box, L0.labels, flags, w, stream);
         run_sw_irr_flag(S, nl, flags, stream);
         std::vector<SelItem> items;
         items.push_back(SelItem{flags, box.size(), ho_sel, d_sc + 4});
@@ -448,7 +448,7 @@ void Problem::setup() {
         ho_irr_index = (int32_t*)mem.alloc(box.size() * sizeof(int32_t));
         run_fill_int(ho_irr_index, box.size(), -1, stream);
         ho_slots = (int32_t*)mem.alloc(std::max<int64_t>(ho_nirr, 1) * 2 * dim * sizeof(int32_t));
-        run_ho_irr_records(L0.geom, box, L0.labels, cp, ho_sel, ho_nirr, ho_slots, ho_irr_index, d_err, stream);
+        run_ho_irr_records(L0.geom, box, L0.labels, cp, ho_sel, ho_nirr, ho_slots, ho_irr_index, w, d_err, stream);
         ho_nodes = (int32_t*)mem.alloc(std::max<int64_t>(ho_nirr, 1) * sizeof(int32_t));
         if (ho_nirr)
             IIM_HIP(hipMemcpyAsync(ho_nodes, ho_sel, ho_nirr * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
@@ -1021,7 +1021,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
             lo = std::max<int64_t>(0, (int64_t)std::floor((a - g.lo) / h));
             hi = std::min<int64_t>(g.n, (int64_t)std::ceil((b - g.lo) / h));
         }
-        dims[d] = hi - lo + 1 + 4;
+        dims[d] = hi - lo + 1 + 2 * (o.order_n / 2);  // level-0 padding: the stencil's reach
     }
     const int m = o.restart;
     const int64_t tsz = o.precision == IIM_PREC_FP64 ? 8 : 4;
@@ -1065,7 +1065,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     const int ns = geo.side == IIM_SIDE_INTERFACE ? 2 : 1;
     const int w = o.order_n / 2;
     const int nrows = w + (geo.bc == IIM_BC_DIRICHLET ? 0 : 1);
-    const double mset = dim == 2 ? 56.0 : 264.0;
+    const double mset = dim == 2 ? (o.order_k == 7 ? 112.0 : 56.0) : 264.0;
     const double ncs = ncp * ns;
     bytes += (int64_t)(ncp * (4 + 4 + 24 + 24 + 8 + 16) + ncs * (4 + 4 + 8 * w * 2 + 8 * nrows + 4 + 4 + 1 + 8));
     bytes += (int64_t)(ncs * mset * (4 + 8 * nrows + (geo.bc == IIM_BC_NEUMANN ? 8 * w : 0)));
@@ -1240,7 +1240,9 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     if (g->dim != 2 && g->dim != 3) throw Error(IIM_E_INVALID_ARG, "dim must be 2 or 3");
     if (g->n < 8 || g->n > 16384) throw Error(IIM_E_INVALID_ARG, "n out of range");
     if (!(g->hi > g->lo)) throw Error(IIM_E_INVALID_ARG, "empty domain");
-    if (o.order_n != 4 || o.order_k != 5) throw Error(IIM_E_INVALID_ARG, "only the (4,5) discretisation is built");
+    const bool o45 = o.order_n == 4 && o.order_k == 5, o67 = o.order_n == 6 && o.order_k == 7;
+    if (!o45 && !(o67 && g->dim == 2))
+        throw Error(IIM_E_INVALID_ARG, "built discretisations: (4,5) in 2D and 3D, (6,7) in 2D");
     if (o.restart < 1 || o.restart > 11) throw Error(IIM_E_INVALID_ARG, "restart must be in [1, 11]");
     if (o.use_graph < 0 || o.use_graph > 2) throw Error(IIM_E_INVALID_ARG, "use_graph must be 0, 1 or 2");
     if (o.coarsest_n < 2) throw Error(IIM_E_INVALID_ARG, "coarsest_n must be >= 2");

@@ -62,9 +62,10 @@ void run_cp_compute(const Geom& g, const Box& b, const uint8_t* labels, const CP
                     int* d_err, hipStream_t s);
 
 // high-order irregular nodes (level 0)
-void run_ho_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s);
+// (w = stencil half-width: nodes whose stencil reaches another side or the box)
+void run_ho_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, int w, hipStream_t s);
 void run_ho_irr_records(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
-                        const int32_t* nodes, int64_t nirr, int32_t* slots, int32_t* irr_index,
+                        const int32_t* nodes, int64_t nirr, int32_t* slots, int32_t* irr_index, int w,
                         int* d_err, hipStream_t s);
 
 // Shortley-Weller rows: flags of the irregular unknowns of every level (at

@@ -552,7 +552,10 @@ void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
     int64_t nwork = cs_list ? n_list : ncs;
     if (nwork == 0) return;
     int blocks = (int)std::min<int64_t>(nwork, cs_list ? scratch_waves : 4096);
-    if (g.dim == 2)
+    if (g.dim == 2 && P.order_k == 7)
+        hipLaunchKernelGGL((k_ls<28, 2>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
+                           idx, S, Sc, scratch, d_err, cs_list, n_list, route);
+    else if (g.dim == 2)
         hipLaunchKernelGGL((k_ls<15, 2>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
                            idx, S, Sc, scratch, d_err, cs_list, n_list, route);
     else

@@ -103,11 +103,15 @@ static void launch_ghosts(const GhostDev& G, const double* x, const double* cpda
 void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
                 hipStream_t s) {
     if (G.ncp == 0) return;
-    if (G.w != 2) throw Error(IIM_E_INTERNAL, "ghost kernel built for w = 2");
-    if (G.nsides == 1 && G.nrows == 2)
+    // rows: w ghosts (one side), w ghosts + the normal derivative (interfaces)
+    if (G.nsides == 1 && G.nrows == G.w && G.w == 2)
         launch_ghosts<1, 2>(G, x, cpdata, with_data, ghost, s);
-    else if (G.nsides == 2 && G.nrows == 3)
+    else if (G.nsides == 2 && G.nrows == G.w + 1 && G.w == 2)
         launch_ghosts<2, 3>(G, x, cpdata, with_data, ghost, s);
+    else if (G.nsides == 1 && G.nrows == G.w && G.w == 3)
+        launch_ghosts<1, 3>(G, x, cpdata, with_data, ghost, s);
+    else if (G.nsides == 2 && G.nrows == G.w + 1 && G.w == 3)
+        launch_ghosts<2, 4>(G, x, cpdata, with_data, ghost, s);
     else
         throw Error(IIM_E_INTERNAL, "ghost kernel: unsupported rows/sides");
 }
@@ -118,10 +122,10 @@ void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int wi
 // contribution of the off-centre points of an irregular node (label flag
 // F_HO_IRR): per axis and direction, grid values up to the first crossing, then
 // ghost values (or box data with extrapolation past a box face)
-template <int DIM>
+template <int DIM, int W>
 __device__ inline double ho_irregular(const Box& b, int64_t l, uint8_t kind, const uint8_t* __restrict__ labels,
                                       const int32_t* __restrict__ rec, const double* __restrict__ ghost,
-                                      const double* __restrict__ boxval, int w, const double* __restrict__ x,
+                                      const double* __restrict__ boxval, const double* __restrict__ x,
                                       int with_data) {
     const int64_t st[3] = {1, (int64_t)b.dims[0], (int64_t)b.dims[0] * b.dims[1]};
     double acc = 0.0;
@@ -131,8 +135,8 @@ __device__ inline double ho_irregular(const Box& b, int64_t l, uint8_t kind, con
             const int64_t sd = dir * st[d];
             const int slot = rec[2 * d + t];
             const int type = slot_type(slot), j0 = slot_j(slot);
-            double v[2];
-            for (int jj = 1; jj <= 2; ++jj) {
+            double v[W];
+            for (int jj = 1; jj <= W; ++jj) {
                 const int64_t q = l + jj * sd;
                 double val;
                 if (type == SLOT_REG || jj < j0) {
@@ -144,30 +148,34 @@ __device__ inline double ho_irregular(const Box& b, int64_t l, uint8_t kind, con
                     else if (kq == K_BOX)
                         val = with_data ? boxval[q] : 0.0;
                     else
-                        val = ghost[(int64_t)slot_cs(slot) * w + (jj - j0)];
+                        val = ghost[(int64_t)slot_cs(slot) * W + (jj - j0)];
                 } else {  // box face at offset j0
                     const int64_t face = l + j0 * sd;
                     const double fv = with_data ? boxval[face] : 0.0;
                     if (jj == j0) {
                         val = fv;
                     } else {
-                        // degree-4 Lagrange extrapolation one step beyond the face
-                        val = 5.0 * fv - 10.0 * x[face - sd] + 10.0 * x[face - 2 * sd] - 5.0 * x[face - 3 * sd] +
-                              x[face - 4 * sd];
+                        // degree-2W Lagrange extrapolation jj - j0 steps beyond the face
+                        const int sb = jj - j0;
+                        val = ho_ext<W>(sb, 0) * fv;
+#pragma unroll
+                        for (int u = 1; u <= 2 * W; ++u) val += ho_ext<W>(sb, u) * x[face - u * sd];
                     }
                 }
                 v[jj - 1] = val;
             }
-            acc += A1 * v[0] + A2 * v[1];
+            double tw = ho_a<W>(1) * v[0] + ho_a<W>(2) * v[1];
+            if (W == 3) tw += ho_a<W>(3) * v[W - 1];
+            acc += tw;
         }
     return acc;
 }
 
-template <int DIM>
+template <int DIM, int W>
 __global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, const uint8_t* __restrict__ labels,
                                                   const int32_t* __restrict__ irr_index,
                                                   const int32_t* __restrict__ slots, const double* __restrict__ ghost,
-                                                  const double* __restrict__ boxval, int w, double inv_h2, double bp,
+                                                  const double* __restrict__ boxval, double inv_h2, double bp,
                                                   double bm, const double* __restrict__ x, double* __restrict__ y,
                                                   int with_data) {
     int i = clo.x + blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,16 +192,19 @@ __global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, con
     const double beta = (kind == K_PLUS) ? bp : bm;
     const int64_t st[3] = {1, (int64_t)b.dims[0], (int64_t)b.dims[0] * b.dims[1]};
     const double xc = x[l];
-    double acc = (double)DIM * A0 * xc;
+    double acc = (double)DIM * ho_a<W>(0) * xc;
     if (!(lab & F_HO_IRR)) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d)
-            acc += A1 * (x[l + st[d]] + x[l - st[d]]) + A2 * (x[l + 2 * st[d]] + x[l - 2 * st[d]]);
+        for (int d = 0; d < DIM; ++d) {
+            double tw = ho_a<W>(1) * (x[l + st[d]] + x[l - st[d]]) + ho_a<W>(2) * (x[l + 2 * st[d]] + x[l - 2 * st[d]]);
+            if (W == 3) tw += ho_a<W>(3) * (x[l + 3 * st[d]] + x[l - 3 * st[d]]);
+            acc += tw;
+        }
         y[l] = beta * inv_h2 * acc;
         return;
     }
-    acc += ho_irregular<DIM>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, w, x,
-                             with_data);
+    acc += ho_irregular<DIM, W>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, x,
+                                with_data);
     y[l] = beta * inv_h2 * acc;
 }
 
@@ -337,8 +348,8 @@ __global__ void __launch_bounds__(256) k_ho_irregular(Box b, const int32_t* __re
     const int64_t l = nodes[t];
     const uint8_t kind = labels[l] & KIND_MASK;
     double acc = (double)DIM * A0 * x[l];
-    acc += ho_irregular<DIM>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, w, x,
-                             with_data);
+    acc += ho_irregular<DIM, 2>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, x,
+                                with_data);
     y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
 }
 
@@ -377,8 +388,14 @@ void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi,
     if (part == 2) return;  // 2D: irregular nodes are inside the one stencil kernel
     dim3 blk(64, 4, 1);
     dim3 grd(cdiv(nx, 64), cdiv(ny, 4), 1);
-    hipLaunchKernelGGL(k_ho_apply<2>, grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval, w, inv_h2,
-                       beta_plus, beta_minus, x, y, with_data);
+    if (w == 2)
+        hipLaunchKernelGGL((k_ho_apply<2, 2>), grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval,
+                           inv_h2, beta_plus, beta_minus, x, y, with_data);
+    else if (w == 3)
+        hipLaunchKernelGGL((k_ho_apply<2, 3>), grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval,
+                           inv_h2, beta_plus, beta_minus, x, y, with_data);
+    else
+        throw Error(IIM_E_INTERNAL, "apply: stencil half-width must be 2 or 3");
     IIM_LAUNCH_CHECK();
 }
 

@@ -316,7 +316,7 @@ __device__ inline uint8_t kind_at(const Geom& g, const Box& b, const uint8_t* la
     return labels[*l] & KIND_MASK;
 }
 
-__global__ void k_ho_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags) {
+__global__ void k_ho_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags, int w) {
     int64_t total = b.size();
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
@@ -327,7 +327,7 @@ __global__ void k_ho_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags) {
             int ijk[3];
             b.coords(l, ijk);
             for (int d = 0; d < g.dim && !irr; ++d)
-                for (int s = -2; s <= 2; ++s) {
+                for (int s = -w; s <= w; ++s) {
                     if (s == 0) continue;
                     int64_t q;
                     if (kind_at(g, b, labels, ijk, d, s, &q) != k) irr = true;
@@ -338,15 +338,15 @@ __global__ void k_ho_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags) {
     }
 }
 
-void run_ho_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, hipStream_t s) {
+void run_ho_irr_flag(const Geom& g, const Box& b, uint8_t* labels, uint8_t* flags, int w, hipStream_t s) {
     int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 8192);
-    hipLaunchKernelGGL(k_ho_irr_flag, dim3(blocks), dim3(256), 0, s, g, b, labels, flags);
+    hipLaunchKernelGGL(k_ho_irr_flag, dim3(blocks), dim3(256), 0, s, g, b, labels, flags, w);
     IIM_LAUNCH_CHECK();
 }
 
 // One record per irregular node: 2*dim slots, slot (d, dir) at 2d + (dir > 0).
 __global__ void k_ho_irr_records(Geom g, Box b, const uint8_t* labels, CPDev cp, const int32_t* nodes,
-                                 int64_t nirr, int32_t* slots, int32_t* irr_index, int* err) {
+                                 int64_t nirr, int32_t* slots, int32_t* irr_index, int w, int* err) {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= nirr) return;
     int64_t l = nodes[k];
@@ -360,7 +360,7 @@ __global__ void k_ho_irr_records(Geom g, Box b, const uint8_t* labels, CPDev cp,
             int dir = t ? 1 : -1;
             int slot = make_slot(SLOT_REG, 0, 0);
             int64_t prev = l;
-            for (int j = 1; j <= 2; ++j) {
+            for (int j = 1; j <= w; ++j) {
                 int64_t q;
                 uint8_t kq = kind_at(g, b, labels, ijk, d, dir * j, &q);
                 if (kq == side) {
@@ -387,11 +387,11 @@ __global__ void k_ho_irr_records(Geom g, Box b, const uint8_t* labels, CPDev cp,
 }
 
 void run_ho_irr_records(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
-                        const int32_t* nodes, int64_t nirr, int32_t* slots, int32_t* irr_index, int* d_err,
+                        const int32_t* nodes, int64_t nirr, int32_t* slots, int32_t* irr_index, int w, int* d_err,
                         hipStream_t s) {
     if (nirr == 0) return;
     hipLaunchKernelGGL(k_ho_irr_records, dim3(cdiv(nirr, 128)), dim3(128), 0, s, g, b, labels, cp, nodes, nirr,
-                       slots, irr_index, d_err);
+                       slots, irr_index, w, d_err);
     IIM_LAUNCH_CHECK();
 }
 

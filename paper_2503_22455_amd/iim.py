@@ -159,9 +159,11 @@ def flat_to_grid(v: np.ndarray, dim: int, n: int) -> np.ndarray:
 def make_options(beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 1e-10, max_iters: int = 500,
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None, use_graph: int = 2,
-                 tail_nodes: int = 0, fused_smoothing: bool = True, colour_split: bool = True) -> Options:
+                 tail_nodes: int = 0, fused_smoothing: bool = True, colour_split: bool = True,
+                 order: Tuple[int, int] = (4, 5)) -> Options:
     o = Options()
     lib().iim_default_options(ctypes.byref(o))
+    o.order_n, o.order_k = int(order[0]), int(order[1])
     o.beta_plus, o.beta_minus, o.rtol, o.max_iters = beta_plus, beta_minus, rtol, max_iters
     o.restart, o.nu_pre, o.nu_post, o.coarsest_n = restart, nu_pre, nu_post, coarsest_n
     o.precision = PREC[precision]
@@ -182,7 +184,8 @@ class Problem:
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None,
                  lo: float = -1.0, hi: float = 1.0, use_graph: int = 2, tail_nodes: int = 0,
-                 fused_smoothing: bool = True, colour_split: bool = True, stream=None):
+                 fused_smoothing: bool = True, colour_split: bool = True, order: Tuple[int, int] = (4, 5),
+                 stream=None):
         L = lib()
         self.dim, self.n = dim, n
         self.side, self.bc = side, bc
@@ -191,7 +194,7 @@ class Problem:
         pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
         geo = Geometry(geom_kind, side, bc, len(geom_params), pa)
         o = make_options(beta_plus, beta_minus, rtol, max_iters, restart, nu_pre, nu_post, coarsest_n, precision,
-                         ls_axes, use_graph, tail_nodes, fused_smoothing, colour_split)
+                         ls_axes, use_graph, tail_nodes, fused_smoothing, colour_split, order)
         self._h = ctypes.c_void_p()
         # default: the library orders its own stream after the legacy default stream
         s = 0 if stream is None else stream
@@ -377,5 +380,6 @@ class Server:
 
 def from_workload(wl, precision: Optional[str] = None, **kw) -> Problem:
     """Problem for a workloads.Workload description."""
+    kw.setdefault("order", tuple(getattr(wl, "order", (4, 5))))
     return Problem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus,
                    precision=precision or wl.precision, **kw)

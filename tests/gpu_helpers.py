@@ -6,8 +6,8 @@ import workloads as W
 from oracle.iim import IIMProblem
 
 
-def oracle_for(wl):
-    return IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus)
+def oracle_for(wl, **kw):
+    return IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus, **kw)
 
 
 def gpu_for(wl, **kw):

@@ -31,17 +31,23 @@ def test_vcycle_reduced_precision(make, prec, tol):
     G.close()
 
 
+def _order6(wl):
+    wl.order = (6, 7)
+    return wl
+
+
 @pytest.mark.parametrize("prec", ["mixed32", "mixed16"])
 @pytest.mark.parametrize("make", [lambda: W.cfg1_circle(64), lambda: W.cfg2_star(256),
                                   lambda: W.cfg3_sphere(32),
-                                  lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union())],
-                         ids=["cfg1", "star256", "sphere32", "spheres32"])
+                                  lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union()),
+                                  lambda: _order6(W.cfg2_star(256))],
+                         ids=["cfg1", "star256", "sphere32", "spheres32", "star256-o6"])
 def test_mixed_solve_reaches_1e10(make, prec):
     """The FP64 outer solve with a reduced-precision V-cycle reaches a true
     relative residual <= 1e-10, checked with the oracle's assembled matrix, and
     its solution agrees with the direct solve to the conditioning."""
     wl = make()
-    O = oracle_for(wl)
+    O = oracle_for(wl, order_n=wl.order[0], order_k=wl.order[1])
     L, LG = O.assemble()
     cpd, box, f = oracle_data(O, wl)
     G = gpu_for(wl, precision=prec, rtol=1e-10)

@@ -23,14 +23,30 @@ CASES = {
     "spheres32-neu": lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union(), precision="fp64"),
     # every level but the coarsest on the grid kernels (colour-split vectors in 3D)
     "spheres32-neu-deep": lambda: W.cfg4_spheres(32, spheres=W.small_spheres_union(), precision="fp64"),
+    # the sixth-order (6,7) scheme (2D): Dirichlet, Neumann with box faces, interface
+    "cfg1-o6": lambda: W.cfg1_circle(64),
+    "circle-neu-ext-o6": lambda: W.Workload("neu2", 2, 64, W.GEOM_SPHERE_UNION,
+                                            W.union_params(W.small_circles_union_2d()), W.SIDE_EXTERIOR,
+                                            W.BC_NEUMANN, 1.5, 1.0, exact=W.ms_sin2pi_cos2pi()),
+    "star128-o6": lambda: W.cfg2_star(128, beta_plus=0.5, beta_minus=1.0),
 }
-OPTIONS = {"spheres32-neu-deep": dict(tail_nodes=-1)}
+OPTIONS = {"spheres32-neu-deep": dict(tail_nodes=-1), "cfg1-o6": dict(order=(6, 7)),
+           "circle-neu-ext-o6": dict(order=(6, 7)), "star128-o6": dict(order=(6, 7))}
+ORACLE_OPTIONS = {k: dict(order_n=v["order"][0], order_k=v["order"][1]) for k, v in OPTIONS.items() if "order" in v}
+# Tolerances of the fits and the apply.  The degree-6 least-squares matrix of the
+# (6,7) scheme (monomials up to xi^6, |xi| <= 7) is far worse conditioned than
+# the degree-4 one (xi^4, |xi| <= 5): the oracle's and the device's independent
+# Householder QRs agree to 7e-14 (relative to the largest weight) at (4,5) and to
+# 5e-12 at (6,7), the apply to 3e-14 and 9e-13 of |L| |x| (measured).  The
+# solution tolerance stays 1e-12 (measured 1.6e-13 at (6,7)).
+TOL_LS = {k: 2e-11 for k in ORACLE_OPTIONS}
+TOL_APPLY = {k: 1e-11 for k in ORACLE_OPTIONS}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def pair(request):
     wl = CASES[request.param]()
-    O = oracle_for(wl)
+    O = oracle_for(wl, **ORACLE_OPTIONS.get(request.param, {}))
     G = gpu_for(wl, precision="fp64", rtol=1e-14, **OPTIONS.get(request.param, {}))
     yield request.param, wl, O, G
     G.close()
@@ -58,7 +74,8 @@ def test_ls_stencils(pair):
             st = O.stencil(int(c), side)
             assert list(idx) == list(st.idx), (name, c, side)
             scale = np.abs(st.S).max()
-            assert np.abs(wts - st.S).max() <= 1e-12 * scale, (name, c, side, np.abs(wts - st.S).max() / scale)
+            assert np.abs(wts - st.S).max() <= TOL_LS.get(name, 1e-12) * scale, (
+                name, c, side, np.abs(wts - st.S).max() / scale)
 
 
 def test_apply(pair):
@@ -71,7 +88,8 @@ def test_apply(pair):
     yo = np.zeros_like(x)
     yo[O.unknowns] = L @ x[O.unknowns]
     scale = abs(L).max() * np.abs(x).max()
-    assert np.abs(y - yo).max() <= 1e-13 * scale, np.abs(y - yo).max() / scale
+    tol = TOL_APPLY.get(name, 1e-13)
+    assert np.abs(y - yo).max() <= tol * scale, np.abs(y - yo).max() / scale
     # with data: L x + L_Gamma u_Gamma, and the right-hand side
     cpd, box, f = oracle_data(O, wl)
     G.set_boundary_data(cpd, box)
@@ -80,7 +98,7 @@ def test_apply(pair):
     yod = np.zeros_like(x)
     yod[O.unknowns] = L @ x[O.unknowns] + LG @ ug
     scale2 = max(scale, np.abs(LG @ ug).max())
-    assert np.abs(yd - yod).max() <= 1e-13 * scale2
+    assert np.abs(yd - yod).max() <= tol * scale2
 
 
 def test_level_operators(pair):

@@ -54,6 +54,7 @@ class Workload:
     exact: Optional[Manufactured] = None
     precision: str = "fp64"       # fp64 | mixed32 | mixed16
     note: str = ""
+    order: Tuple[int, int] = (4, 5)  # (n, k): the (4,5) scheme, or (6,7) in 2D
 
     # -- data sampling (pure evaluation of the manufactured solution) ----------
     def cp_data(self, xyz: np.ndarray, normal: np.ndarray) -> np.ndarray:
