@@ -13,6 +13,11 @@ The Shortley-Weller operator is rediscretised on every level from the level
 set; a direct solve is used on the coarsest level (n <= 8).  One V-cycle with a
 zero initial guess is the preconditioner.
 
+Cycle option (Sec. 3.3 and the 2D multigrid results of Sec. 3): gamma = 2 gives
+the W-cycle, which visits each coarser level twice per visit of the level above
+(Trottenberg's cycle index gamma); the second visit starts from the iterate the
+first one left.  gamma = 1 is the V-cycle.
+
 Readings: vertex-centred coarsening (coarse node I = fine node 2I, ceil(n/2)
 intervals); half-weighting stencils 1/8 [0 1 0; 1 4 1; 0 1 0] in 2D and centre
 1/2, faces 1/12 in 3D; red (even index sum) before black; V(2,2); box-face nodes
@@ -21,7 +26,11 @@ solve excludes rows with a zero diagonal (their value stays zero).
 
 Parity: pinned by the Dirichlet V-cycle contraction (rho < 0.1, independent of
 n), by transfer operators reproducing constants away from Gamma, and by the
-FGMRES solution matching the direct solve (tests/test_oracle_mg.py).
+FGMRES solution matching the direct solve (tests/test_oracle_mg.py).  The
+W-cycle is pinned by its identity with the V-cycle on two levels (the coarse
+solve is exact, so the second visit changes nothing), by a contraction no
+worse than the V-cycle's, by the cycle from a non-zero start equalling that
+start plus the cycle of the residual, and by FGMRES reaching the direct solve.
 """
 from __future__ import annotations
 
@@ -45,11 +54,13 @@ def level_sizes(n: int, coarsest: int = 8) -> List[int]:
 
 
 class Hierarchy:
-    def __init__(self, prob, coarsest: int = 8, nu_pre: int = 2, nu_post: int = 2):
-        """prob: an IIMProblem (provides grid, geometry, side, bc, beta)."""
+    def __init__(self, prob, coarsest: int = 8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1):
+        """prob: an IIMProblem (provides grid, geometry, side, bc, beta);
+        gamma: cycle index (1 = V-cycle, 2 = W-cycle)."""
         self.prob = prob
         self.dim = prob.dim
         self.nu_pre, self.nu_post = nu_pre, nu_post
+        self.gamma = gamma
         self.sizes = level_sizes(prob.n, coarsest)
         self.levels: List[SWLevel] = []
         for l, nl in enumerate(self.sizes):
@@ -143,23 +154,36 @@ class Hierarchy:
         return z
 
     # -- cycle ---------------------------------------------------------------------------
-    def vcycle_level(self, l: int, b: np.ndarray) -> np.ndarray:
+    def cycle_level(self, l: int, b: np.ndarray, z0: np.ndarray = None) -> np.ndarray:
+        """One multigrid cycle of index gamma on level l for A_l z = b, from z0
+        (zero if None): pre-smoothing, restriction of the residual, gamma
+        cycles on level l + 1 (the first from zero, each later one from the
+        previous one's result), prolongation and correction, post-smoothing.
+        The coarsest level is solved directly whatever the start."""
         if l == len(self.levels) - 1:
             return self.coarse_solve(b)
         lev = self.levels[l]
-        z = np.zeros(b.size)
+        z = np.zeros(b.size) if z0 is None else np.array(z0, dtype=np.float64)
         for _ in range(self.nu_pre):
             self.rbgs(l, z, b)
         r = b - lev.A @ z
-        zc = self.vcycle_level(l + 1, self.restrict(l, r))
+        bc = self.restrict(l, r)
+        zc = None
+        for _ in range(self.gamma):
+            zc = self.cycle_level(l + 1, bc, zc)
         z += self.prolong(l + 1, zc)
         for _ in range(self.nu_post):
             self.rbgs(l, z, b)
         return z
 
+    def vcycle_level(self, l: int, b: np.ndarray) -> np.ndarray:
+        """One cycle (of the hierarchy's index gamma) from a zero start."""
+        return self.cycle_level(l, b)
+
     def precondition(self, v: np.ndarray) -> np.ndarray:
-        """z = M^{-1} v: one V-cycle on Lap z = v / beta (v on the level-0 unknowns,
-        which coincide with the high-order unknowns)."""
+        """z = M^{-1} v: one cycle (V for gamma = 1, W for gamma = 2) on
+        Lap z = v / beta (v on the level-0 unknowns, which coincide with the
+        high-order unknowns)."""
         lev0 = self.levels[0]
         beta = np.where(lev0.lab_flat[lev0.unknowns] == MINUS,
                         self.prob.beta[MINUS], self.prob.beta[PLUS])
