@@ -8,7 +8,9 @@ and the periodic eigenvalues are lambda(k) = -sum_i sigma(k_i h) / h^2.
 Table 1 gives sigma_max = 4, 16/3, 272/45 for orders 2, 4, 6.
 
 Parity: pinned by Table 1 (tests/golden/sigma_max.txt) and by the closed-form
-periodic spectrum against a dense eigen-solve (tests/test_oracle_fd.py).
+periodic spectrum against a dense eigen-solve (tests/test_oracle_fd.py).  The
+first-derivative stencils are pinned by their Taylor conditions, solved afresh
+in exact arithmetic in the test.
 """
 from fractions import Fraction
 
@@ -20,6 +22,25 @@ _STENCILS = {
     4: [Fraction(-5, 2), Fraction(4, 3), Fraction(-1, 12)],
     6: [Fraction(-49, 18), Fraction(3, 2), Fraction(-3, 20), Fraction(1, 90)],
 }
+
+
+# one side of the antisymmetric central first-derivative stencil of order n:
+# g_1, ..., g_w with  du/dx ~ sum_j g_j (u_{+j} - u_{-j}) / h  (the gradient
+# post-processing of Sec. 2.3 uses the same half-width w as the Laplacian)
+_FIRST = {
+    2: [Fraction(1, 2)],
+    4: [Fraction(2, 3), Fraction(-1, 12)],
+    6: [Fraction(3, 4), Fraction(-3, 20), Fraction(1, 60)],
+}
+
+
+def first_stencil(order: int):
+    """Coefficients [g_1, ..., g_w] of the order-n central first derivative."""
+    return [float(v) for v in _FIRST[order]]
+
+
+def first_stencil_exact(order: int):
+    return list(_FIRST[order])
 
 
 def stencil(order: int):

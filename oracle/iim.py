@@ -26,9 +26,17 @@ Data vector u_Gamma: per control point ubar or qbar (or j0, j1 interleaved),
 followed by one value per grid node (flat, x fastest) of which only the box-face
 entries are used.
 
+Post-processing (Sec. 2.4): grad u at the unknowns by the order-n central
+first derivative with the same extension (grad_row, gradient), and the
+boundary quantity left open by the condition at every control point
+(boundary_quantity).
+
 Parity: pinned by the patch test (the operator is exact on polynomials of degree
 <= k-1 with matching data), by the order-n convergence of the solution and by
-the spectrum bounds of Sec. 2.5 (tests/test_oracle_iim.py).
+the spectrum bounds of Sec. 2.5 (tests/test_oracle_iim.py).  The gradient and
+the boundary quantity are pinned by patch tests (exact on polynomials of degree
+<= n, resp. <= k-1, given exact nodal values) and by their order-n convergence
+on solved problems (tests/test_oracle_post.py).
 """
 from __future__ import annotations
 
@@ -40,7 +48,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import INACTIVE, PLUS, MINUS, BOX
-from .fd import stencil, half_width
+from .fd import stencil, first_stencil, half_width
 from .geometry import (Grid, make_geometry, node_labels, control_points, check_curvature,
                        GeometryUnresolved, SIDE_INTERIOR, SIDE_EXTERIOR, SIDE_INTERFACE)
 from .lsq import ls_stencil, default_axes
@@ -75,6 +83,7 @@ class IIMProblem:
         self.order_n, self.order_k = order_n, order_k
         self.w = half_width(order_n)
         self.a = stencil(order_n)
+        self.g = first_stencil(order_n)
         self.axes = axes if axes is not None else default_axes(dim, order_k)
         self.labels = node_labels(self.grid, self.geom, side)
         self.lab_flat = self.labels.ravel(order="F")
@@ -102,6 +111,53 @@ class IIMProblem:
             self._st[key] = ls_stencil(self.grid, self.lab_flat, self.cps[c], side,
                                        self.order_k, self.w, need_d, self.axes)
         return self._st[key]
+
+    def stencil_d(self, c: int, side: int):
+        """The fit of control point c with the normal-derivative row (column
+        w of S) also for Dirichlet problems, whose ghosts do not need it."""
+        if self.bc in (BC_NEUMANN, BC_JUMP):
+            return self.stencil(c, side)
+        key = ("d", c, side)
+        if key not in self._st:
+            self._st[key] = ls_stencil(self.grid, self.lab_flat, self.cps[c], side,
+                                       self.order_k, self.w, True, self.axes)
+        return self._st[key]
+
+    def boundary_quantity(self, u: np.ndarray, u_gamma: np.ndarray) -> np.ndarray:
+        """The boundary quantity the condition leaves open, one value per
+        control point (Sec. 2.4, boundary-quantity convergence):
+          Dirichlet  du/dn(x_c) = s_c ubar + sum_i s_i u_i, s the normal-
+                     derivative stencil of the fit;
+          Neumann    u(x_c) = (qbar - beta sum_i s_i u_i) / (beta s_c);
+          interface  du+/dn(x_c) = s+_c u+(x_c) + sum_i s+_i u+_i, with u+(x_c)
+                     from the interface closure.
+        n is the control point's normal (from Omega^- into Omega^+)."""
+        uf = np.zeros(self.lab_flat.size)
+        uf[self.unknowns] = u
+        w = self.w
+        out = np.empty(self.ncp)
+        for c in range(self.ncp):
+            if self.bc == BC_DIRICHLET:
+                st = self.stencil_d(c, PLUS)
+                sn = st.S[:, w]
+                out[c] = sn[0] * u_gamma[c] + sum(sn[1 + a] * uf[f] for a, f in enumerate(st.idx))
+            elif self.bc == BC_NEUMANN:
+                st = self.stencil(c, PLUS)
+                sn = st.S[:, w]
+                beta = self.beta[PLUS]
+                out[c] = (u_gamma[c] - beta * sum(sn[1 + a] * uf[f] for a, f in enumerate(st.idx))) / (beta * sn[0])
+            else:
+                stp, stm = self.stencil(c, PLUS), self.stencil(c, MINUS)
+                snp, snm = stp.S[:, w], stm.S[:, w]
+                bp, bm = self.beta[PLUS], self.beta[MINUS]
+                D = bp * snp[0] - bm * snm[0]
+                sp_u = sum(snp[1 + a] * uf[f] for a, f in enumerate(stp.idx))
+                sm_u = sum(snm[1 + a] * uf[f] for a, f in enumerate(stm.idx))
+                ubar = -(bp * sp_u - bm * sm_u) / D
+                j0, j1 = u_gamma[2 * c], u_gamma[2 * c + 1]
+                up = ubar + (j1 - bm * snm[0] * j0) / D
+                out[c] = snp[0] * up + sp_u
+        return out
 
     def ghost(self, c: int, side: int, j: int) -> Tuple[Dict[int, float], Dict[int, float]]:
         """Ghost value j (1..w) of control point c on `side` as a linear
@@ -154,6 +210,63 @@ class IIMProblem:
             return None
         return f + s * self.strides[d]
 
+    def _half_line(self, f: int, side: int, d: int, dr: int, wts, coef, data) -> None:
+        """Adds sum_{j=1..w} wts[j] u~(f + dr j e_d) to (coef, data): u~ is the
+        extended function of the 1D stencil of node f on `side` (grid values on
+        the side, the least-squares polynomial of the first crossing beyond it,
+        box data and extrapolation past a box face)."""
+        state, c, j0, face, jf = "u", None, None, None, None
+        prev = f
+        for j in range(1, self.w + 1):
+            q = self._step(f, d, dr * j)
+            wj = wts[j]
+            if state == "u":
+                if q is None:
+                    raise GeometryUnresolved("stencil leaves the grid")
+                lab = self.lab_flat[q]
+                if lab == side:
+                    coef[q] += wj
+                elif lab == BOX:
+                    state, face, jf = "box", q, j
+                    data[self.ncp_data + q] += wj
+                else:
+                    key = (d, min(prev, q))
+                    c = self.seg[key]
+                    assert self.cps[c].a[side] == prev
+                    state, j0 = "ghost", j
+                    gc, gd = self.ghost(c, side, j - j0 + 1)
+                    for k2, v in gc.items():
+                        coef[k2] += wj * v
+                    for k2, v in gd.items():
+                        data[k2] += wj * v
+            elif state == "ghost":
+                # the extended function is u itself wherever the point is
+                # back on the stencil's side (a thin sliver of the other
+                # side); p_c of the first crossing elsewhere
+                if q is not None and self.lab_flat[q] == side:
+                    coef[q] += wj
+                    prev = q
+                    continue
+                if q is not None and self.lab_flat[q] == BOX:
+                    data[self.ncp_data + q] += wj
+                    prev = q
+                    continue
+                gc, gd = self.ghost(c, side, j - j0 + 1)
+                for k2, v in gc.items():
+                    coef[k2] += wj * v
+                for k2, v in gd.items():
+                    data[k2] += wj * v
+            else:  # beyond a box face: 1D extrapolation
+                s = j - jf
+                lw = lagrange_extrapolation(self.order_k, s)
+                data[self.ncp_data + face] += wj * lw[0]
+                for t in range(1, self.order_k):
+                    node = self._step(face, d, -dr * t)
+                    if node is None or self.lab_flat[node] != side:
+                        raise GeometryUnresolved("box extrapolation line leaves the side")
+                    coef[node] += wj * lw[t]
+            prev = q
+
     def row(self, f: int) -> Tuple[Dict[int, float], Dict[int, float]]:
         """Row of unknown node f: (grid coefficients, data coefficients)."""
         side = int(self.lab_flat[f])
@@ -163,60 +276,38 @@ class IIMProblem:
         coef: Dict[int, float] = defaultdict(float)
         data: Dict[int, float] = defaultdict(float)
         coef[f] += beta * self.dim * self.a[0] / h2
+        wts = [0.0] + [beta * self.a[j] / h2 for j in range(1, self.w + 1)]
         for d in range(self.dim):
             for dr in (1, -1):
-                state, c, j0, face, jf = "u", None, None, None, None
-                prev = f
-                for j in range(1, self.w + 1):
-                    q = self._step(f, d, dr * j)
-                    wj = beta * self.a[j] / h2
-                    if state == "u":
-                        if q is None:
-                            raise GeometryUnresolved("stencil leaves the grid")
-                        lab = self.lab_flat[q]
-                        if lab == side:
-                            coef[q] += wj
-                        elif lab == BOX:
-                            state, face, jf = "box", q, j
-                            data[self.ncp_data + q] += wj
-                        else:
-                            key = (d, min(prev, q))
-                            c = self.seg[key]
-                            assert self.cps[c].a[side] == prev
-                            state, j0 = "ghost", j
-                            gc, gd = self.ghost(c, side, j - j0 + 1)
-                            for k2, v in gc.items():
-                                coef[k2] += wj * v
-                            for k2, v in gd.items():
-                                data[k2] += wj * v
-                    elif state == "ghost":
-                        # the extended function is u itself wherever the point is
-                        # back on the stencil's side (a thin sliver of the other
-                        # side); p_c of the first crossing elsewhere
-                        if q is not None and self.lab_flat[q] == side:
-                            coef[q] += wj
-                            prev = q
-                            continue
-                        if q is not None and self.lab_flat[q] == BOX:
-                            data[self.ncp_data + q] += wj
-                            prev = q
-                            continue
-                        gc, gd = self.ghost(c, side, j - j0 + 1)
-                        for k2, v in gc.items():
-                            coef[k2] += wj * v
-                        for k2, v in gd.items():
-                            data[k2] += wj * v
-                    else:  # beyond a box face: 1D extrapolation
-                        s = j - jf
-                        lw = lagrange_extrapolation(self.order_k, s)
-                        data[self.ncp_data + face] += wj * lw[0]
-                        for t in range(1, self.order_k):
-                            node = self._step(face, d, -dr * t)
-                            if node is None or self.lab_flat[node] != side:
-                                raise GeometryUnresolved("box extrapolation line leaves the side")
-                            coef[node] += wj * lw[t]
-                    prev = q
+                self._half_line(f, side, d, dr, wts, coef, data)
         return coef, data
+
+    def grad_row(self, f: int, d: int) -> Tuple[Dict[int, float], Dict[int, float]]:
+        """d/dx_d of u at unknown node f (the gradient post-processing of
+        Sec. 2.3): the central first-derivative stencil of order n along axis
+        d, with the same immersed-interface extension as the Laplacian, so the
+        boundary conditions enter through the ghost values."""
+        side = int(self.lab_flat[f])
+        assert side in (PLUS, MINUS)
+        h = self.grid.h
+        coef: Dict[int, float] = defaultdict(float)
+        data: Dict[int, float] = defaultdict(float)
+        for dr in (1, -1):
+            wts = [0.0] + [dr * self.g[j - 1] / h for j in range(1, self.w + 1)]
+            self._half_line(f, side, d, dr, wts, coef, data)
+        return coef, data
+
+    def gradient(self, u: np.ndarray, u_gamma: np.ndarray) -> np.ndarray:
+        """grad u at every unknown, shape (unknowns, dim), from the unknowns u
+        and the data vector u_Gamma."""
+        uf = np.zeros(self.lab_flat.size)
+        uf[self.unknowns] = u
+        out = np.empty((self.unknowns.size, self.dim))
+        for r, f in enumerate(self.unknowns):
+            for d in range(self.dim):
+                coef, data = self.grad_row(int(f), d)
+                out[r, d] = sum(c * uf[q] for q, c in coef.items()) + sum(c * u_gamma[q] for q, c in data.items())
+        return out
 
     # -- assembly ----------------------------------------------------------------
     def regular_mask(self) -> np.ndarray:

@@ -1,0 +1,137 @@
+"""Pins for the post-processing of a solution (Sec. 2.4): grad u at the
+unknowns by the order-n central first derivative with the immersed-interface
+extension, and the boundary quantity the condition leaves open (du/dn for
+Dirichlet, u for Neumann, du+/dn on an interface).
+  * patch tests: given exact nodal values of a polynomial, the gradient is
+    exact for degree <= n (Taylor order of the stencil; the ghosts are exact
+    for degree <= k-1 = n), the boundary quantity for degree <= k-1;
+  * convergence at order n on solved manufactured problems (the paper's
+    boundary-quantity and gradient figures)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.iim import IIMProblem
+from oracle.lsq import monomial_exponents
+
+
+def _setup(wl, order=(4, 5)):
+    P = IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc,
+                   wl.beta_plus, wl.beta_minus, order_n=order[0], order_k=order[1])
+    xyz, nrm = P.cp_arrays()
+    ug = P.data_vector(wl.cp_data(xyz, nrm), wl.box_data())
+    return P, ug, xyz, nrm
+
+
+def _exact_grad(wl, P):
+    X = [x.ravel(order="F")[P.unknowns] for x in wl.node_coords()]
+    lab = P.lab_flat[P.unknowns]
+    gp = np.stack([np.asarray(g) * np.ones_like(X[0]) for g in wl.exact.grad_plus(*X)], axis=1)
+    if wl.exact.grad_minus is None:
+        return gp
+    gm = np.stack([np.asarray(g) * np.ones_like(X[0]) for g in wl.exact.grad_minus(*X)], axis=1)
+    return np.where((lab == 2)[:, None], gm, gp)
+
+
+def _exact_bq(wl, xyz, nrm):
+    X = [xyz[:, d] for d in range(wl.dim)]
+    if wl.bc == W.BC_NEUMANN:
+        return np.asarray(wl.exact.u_plus(*X)) * np.ones(len(xyz))
+    g = wl.exact.grad_plus(*X)
+    return sum(np.asarray(g[d]) * nrm[:, d] for d in range(wl.dim))
+
+
+def _poly(dim, deg, seed):
+    rng = np.random.default_rng(seed)
+    return W.ms_polynomial({e: rng.uniform(-1, 1) for e in monomial_exponents(dim, deg)}, dim)
+
+
+PATCH = [
+    ("dirichlet-2d", 2, 48, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0, 1.0, 1.0, (4, 5)),
+    ("neumann-2d-exterior-box", 2, 64, W.GEOM_SPHERE_UNION, W.union_params(W.small_circles_union_2d()), 1, 1,
+     2.0, 1.0, (4, 5)),
+    ("interface-2d", 2, 128, W.GEOM_STAR2D, [0.0, 0.0, 0.5, 0.1, 5], 2, 2, 0.5, 1.0, (4, 5)),
+    ("dirichlet-3d", 3, 16, W.GEOM_SPHERE, [0.01, 0.02, -0.01, 0.6], 0, 0, 1.0, 1.0, (4, 5)),
+    ("dirichlet-2d-o6", 2, 64, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0, 1.0, 1.0, (6, 7)),
+    ("interface-2d-o6", 2, 128, W.GEOM_STAR2D, [0.0, 0.0, 0.5, 0.1, 5], 2, 2, 0.5, 1.0, (6, 7)),
+]
+
+
+@pytest.mark.parametrize("case", PATCH, ids=[c[0] for c in PATCH])
+def test_patch(case):
+    name, dim, n, kind, params, side, bc, bp, bm, order = case
+    deg = order[0]  # = k - 1: exact for both the gradient and the boundary quantity
+    ms = _poly(dim, deg, 1)
+    if side == W.SIDE_INTERFACE:
+        m2 = _poly(dim, deg, 2)
+        ms = W.Manufactured(ms.u_plus, ms.grad_plus, ms.lap_plus, m2.u_plus, m2.grad_plus, m2.lap_plus)
+    wl = W.Workload(name, dim, n, kind, params, side, bc, bp, bm, exact=ms)
+    P, ug, xyz, nrm = _setup(wl, order)
+    uex = P.from_full(np.nan_to_num(wl.exact_solution(P.labels)))
+    g = P.gradient(uex, ug)
+    ge = _exact_grad(wl, P)
+    assert np.abs(g - ge).max() <= 1e-9 * np.abs(ge).max(), np.abs(g - ge).max() / np.abs(ge).max()
+    q = P.boundary_quantity(uex, ug)
+    qe = _exact_bq(wl, xyz, nrm)
+    assert np.abs(q - qe).max() <= 1e-9 * np.abs(qe).max(), np.abs(q - qe).max() / np.abs(qe).max()
+
+
+def test_patch_fails_one_degree_higher():
+    """The gradient stencil of order n is not exact for degree n + 1: the
+    patch test above is not passing by accident."""
+    ms = W.ms_polynomial({(5, 0): 1.0}, 2)
+    wl = W.Workload("d", 2, 48, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0, exact=ms)
+    P, ug, xyz, nrm = _setup(wl)
+    uex = P.from_full(np.nan_to_num(wl.exact_solution(P.labels)))
+    g = P.gradient(uex, ug)
+    assert np.abs(g - _exact_grad(wl, P)).max() > 1e-6
+
+
+def _errors(wl, order):
+    P, ug, xyz, nrm = _setup(wl, order)
+    L, LG = P.assemble()
+    b = P.rhs(wl.rhs(P.labels), ug)
+    u = P.direct_solve(b)
+    eg = np.abs(P.gradient(u, ug) - _exact_grad(wl, P)).max()
+    eq = np.abs(P.boundary_quantity(u, ug) - _exact_bq(wl, xyz, nrm)).max()
+    return eg, eq
+
+
+def _orders(make, ns, order=(4, 5)):
+    e = [_errors(make(n), order) for n in ns]
+    og = [np.log(e[i][0] / e[i + 1][0]) / np.log(ns[i + 1] / ns[i]) for i in range(len(ns) - 1)]
+    oq = [np.log(e[i][1] / e[i + 1][1]) / np.log(ns[i + 1] / ns[i]) for i in range(len(ns) - 1)]
+    return og, oq, e
+
+
+def _sol2d():
+    m = W.ms_paper_interface()
+    return W.Manufactured(m.u_minus, m.grad_minus, m.lap_minus)
+
+
+def test_dirichlet_converges_at_order4():
+    og, oq, e = _orders(lambda n: W.Workload("d", 2, n, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0,
+                                             exact=_sol2d()), [64, 128, 256])
+    assert min(og) > 3.5 and min(oq) > 3.5, (og, oq, e)
+
+
+def test_neumann_converges_at_order4():
+    og, oq, e = _orders(lambda n: W.Workload("n", 2, n, W.GEOM_SPHERE_UNION,
+                                             W.union_params(W.small_circles_union_2d()), 1, 1,
+                                             exact=_sol2d()), [64, 128, 256])
+    assert og[-1] > 3.5 and oq[-1] > 3.5, (og, oq, e)
+
+
+def test_interface_converges_at_order4_paper_case():
+    og, oq, e = _orders(lambda n: W.Workload("i", 2, n, W.GEOM_STAR2D, [0.0, 0.0, 0.5, 0.1, 5], 2, 2,
+                                             0.5, 1.0, exact=W.ms_paper_interface()), [128, 256, 512])
+    assert min(og) > 3.5 and min(oq) > 3.5, (og, oq, e)
+
+
+def test_dirichlet_converges_at_order6():
+    """(6,7): measured rates 5.7, 5.3 (gradient) and 5.2, 5.7 (du/dn) over
+    n = 64, 128, 256, still pre-asymptotic; above 5 separates them from the
+    fourth-order scheme."""
+    og, oq, e = _orders(lambda n: W.Workload("d", 2, n, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0,
+                                             exact=_sol2d()), [64, 128, 256], order=(6, 7))
+    assert min(og) > 5.0 and min(oq) > 5.0, (og, oq, e)
