@@ -131,7 +131,7 @@ def kernel_roofline(wl, precision, torch, nu, reps=20):
         5: 8.0 * (k + 2) * nu,                                    # read k basis vectors and w, write w
     }
     ids = dict(KERNELS)
-    if dim == 2:
+    if dim == 2 and getattr(wl, "cycle", "V") == "V":
         # the production V-cycle runs the fused LDS legs on level 0 in 2D (one
         # kernel each): down = read b, write z and the coarse b; up = read coarse
         # z, b, z, write z
@@ -164,7 +164,7 @@ def cpu_baseline(wl, its_gpu, nu, sample_iters=3):
         xyz, nrm = O.cp_arrays()
         ug = O.data_vector(wl.cp_data(xyz, nrm), wl.box_data())
         b = O.rhs(wl.rhs(O.labels), ug)
-        H = Hierarchy(O)
+        H = Hierarchy(O, gamma=2 if getattr(wl, "cycle", "V") == "W" else 1)
         t1 = time.perf_counter()
         fgmres(lambda v: L @ v, H.precondition, b, rtol=1e-30, max_iters=sample_iters)
         t2 = time.perf_counter()
@@ -297,6 +297,9 @@ def main():
     ap.add_argument("--precision", default=None, help="override the workload's precision")
     ap.add_argument("--order", type=int, default=4, choices=(4, 6),
                     help="interior order of the discretisation: 4 = the (4,5) scheme, 6 = (6,7) (2D workloads)")
+    ap.add_argument("--orthogonalisation", type=int, default=1, choices=(0, 1),
+                    help="Arnoldi step: 1 one Gram-Schmidt pass, a second only where needed; 0 two passes")
+    ap.add_argument("--cycle", default="V", choices=("V", "W"), help="the preconditioner's multigrid cycle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the request-stream workload instead")
@@ -330,6 +333,8 @@ def main():
             print("bench.py: the (6,7) scheme is built for 2D workloads", file=sys.stderr)
             sys.exit(2)
         wl.order = (6, 7)
+    wl.orthogonalisation = args.orthogonalisation
+    wl.cycle = args.cycle
     cpd, box, f, nu = prepare(wl, torch)
     print(f"[bench] workload {args.workload}: {nu} unknowns, precision {prec}", file=sys.stderr, flush=True)
 
@@ -352,14 +357,19 @@ def main():
     value = nu * args.steps / total
 
     # time to 1e-10 (solve only) for FP64 and mixed precision on the same problem
+    # (and, for the workload's precision, with the other Arnoldi variant)
     ttr = {}
-    for p in (["fp64", "mixed32", "mixed16"] if not args.no_mixed else [prec]):
+    other = 1 - args.orthogonalisation
+    runs = [(p, args.orthogonalisation) for p in (["fp64", "mixed32", "mixed16"] if not args.no_mixed else [prec])]
+    runs.append((prec, other))
+    for p, orth in runs:
+        key = p if orth == args.orthogonalisation else f"{p}+{'cgs2' if orth == 0 else 'cgs1'}"
         one_step(wl, p, cpd, box, f, torch)
         dts = []
         itp = 0
         for _ in range(3):
             from paper_2503_22455_amd import iim
-            P = iim.from_workload(wl, precision=p)
+            P = iim.from_workload(wl, precision=p, orthogonalisation=orth)
             P.set_boundary_data(cpd, box)
             P.set_rhs(f)
             torch.cuda.synchronize()
@@ -368,10 +378,12 @@ def main():
             torch.cuda.synchronize()
             dts.append(time.perf_counter() - t0)
             itp = st["iterations"]
+            sp = st["second_passes"]
             ok = st["final_rel_residual"] <= 1e-10
             P.close()
-        ttr[p] = {"ms": float(np.median(dts) * 1e3), "iterations": itp, "reached": bool(ok)}
-        print(f"[bench] time-to-1e-10 {p}: {ttr[p]}", file=sys.stderr, flush=True)
+        ttr[key] = {"ms": float(np.median(dts) * 1e3), "iterations": itp, "second_gs_passes": sp,
+                    "reached": bool(ok)}
+        print(f"[bench] time-to-1e-10 {key}: {ttr[key]}", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel: measured duration x launches per iteration
     kr, info = kernel_roofline(wl, prec, torch, nu)
@@ -415,7 +427,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCR[args.workload] + (", (6,7) scheme" if args.order == 6 else ""),
                    "n": wl.n, "dim": wl.dim, "unknowns": nu, "order": list(wl.order),
-                   "precision": prec, "rtol": 1e-10},
+                   "precision": prec, "rtol": 1e-10,
+                   "arnoldi": "CGS, second pass where needed" if args.orthogonalisation else "CGS2",
+                   "cycle": args.cycle},
         "p50_ms": pct(0.5), "p99_ms": pct(0.99), "solves_per_s": args.steps / total,
         "setup_ms_median": float(np.median(setup) * 1e3), "iterations": int(np.median(its)),
         "final_rel_residual_max": float(max(res)),

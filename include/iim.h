@@ -101,7 +101,7 @@ typedef struct iim_options {
     double beta_minus;  /* coefficient in Omega^- (interfaces) */
     double rtol;        /* stop when ||b - L u||_2 / ||b||_2 <= rtol */
     int32_t max_iters;  /* total FGMRES iterations */
-    int32_t restart;    /* FGMRES restart length (<= 32) */
+    int32_t restart;    /* FGMRES restart length (1..11) */
     int32_t nu_pre;     /* red-black Gauss-Seidel sweeps before / after */
     int32_t nu_post;    /*   the coarse-grid correction                 */
     int32_t coarsest_n; /* direct solve once n_level <= coarsest_n */
@@ -119,6 +119,16 @@ typedef struct iim_options {
     int32_t colour_split;    /* 1: 3D multigrid levels above the single-workgroup kernel keep
                                 their vectors split by red-black colour (contiguous rows per
                                 colour); 0: storage-box order.  Results are identical. */
+    int32_t orthogonalisation; /* Arnoldi step of FGMRES (Sec. 4.1): 1 (default) classical
+                                Gram-Schmidt, one pass, with a second pass only when the first
+                                leaves less than 1e-2 of |w| (the decision is taken on the
+                                device); 0 two passes every iteration (CGS2) */
+    int32_t cycle_gamma;     /* multigrid cycle of the preconditioner (Sec. 3.3): 1 (default)
+                                V-cycle; 2 W-cycle (each coarser level visited twice per visit
+                                of the level above, the second visit from the first one's
+                                iterate).  The W-cycle runs one kernel per half-sweep and
+                                transfer on every level (no fused legs, coarse solve alone in
+                                the one-workgroup kernel). */
 } iim_options;
 
 typedef struct iim_stats {
@@ -132,6 +142,8 @@ typedef struct iim_stats {
     double t_vcycle_ms;    /* GPU time in the preconditioner (use_graph = 0 only) */
     double t_krylov_ms;    /* GPU time in orthogonalisation and updates (use_graph = 0);
                               otherwise the GPU time of the whole restart cycles */
+    int32_t second_passes; /* Arnoldi steps that took a second Gram-Schmidt pass */
+    int32_t reserved;
 } iim_stats;
 
 typedef struct iim_info {
@@ -202,14 +214,31 @@ int iim_solve(iim_problem* p, double* u, const double* x0, double* hist, int32_t
  * at the unknowns, 0 elsewhere.  x, y: device full-grid arrays. */
 int iim_apply(iim_problem* p, const double* x, double* y, int32_t with_data);
 
-/* z = M^{-1} v, one V-cycle with zero initial guess on Lap z = v / beta
- * (Sec. 3.3), in the handle's precision.  v, z: device full-grid arrays. */
+/* z = M^{-1} v, one multigrid cycle (V, or W if cycle_gamma = 2) with zero
+ * initial guess on Lap z = v / beta (Sec. 3.3), in the handle's precision.
+ * v, z: device full-grid arrays. */
 int iim_vcycle(iim_problem* p, const double* v, double* z);
+
+/* Post-processing of a solution (Sec. 2.4), with the boundary data last given
+ * by iim_set_boundary_data.  u: device full-grid array (values read at the
+ * unknowns only).
+ * grad: device array of dim * (n+1)^dim doubles, component d at offset
+ * d * (n+1)^dim: du/dx_d at every unknown by the order-n central first
+ * derivative over the same extended function as the operator (ghost values
+ * from the fits, box data and extrapolation past box faces), NaN elsewhere. */
+int iim_gradient(iim_problem* p, const double* u, double* grad);
+
+/* q: device array of n_control_points doubles (control-point order of
+ * iim_control_points): the boundary quantity the condition leaves open, by the
+ * normal-derivative row of each fit: du/dn for Dirichlet, u for Neumann
+ * (the closure), du+/dn for interfaces (u+ at x_c from the closure); n is the
+ * control point's unit normal from Omega^- into Omega^+. */
+int iim_boundary_quantity(iim_problem* p, const double* u, double* q);
 
 /* Least-squares stencil of control point cp on side (1 = Omega^+, 2 = Omega^-):
  * m grid points (full-grid flat indices in idx) and the (m+1) x r weights in
  * weights[row * r + col] (row 0 multiplies u(x_c); columns: ghosts 1..w, then
- * the normal derivative when present).  Host buffers of capacity cap rows;
+ * the normal derivative, r = w + 1).  Host buffers of capacity cap rows;
  * returns the sizes in *m and *r. */
 int iim_ls_stencil(const iim_problem* p, int64_t cp, int32_t side, int32_t* m, int32_t* r,
                    int64_t* idx, double* weights, int32_t cap);

@@ -60,10 +60,43 @@ __device__ inline void block_reduce_store(const double (&vals)[K], int k, double
 // separate L2 caches.
 constexpr int FIN_WAVES = RED_BLOCKS / 64;
 
+// Whether a classical Gram-Schmidt step needs its second pass.  g[0..k-1] =
+// V^T w and g[k] = |w|^2 from the first pass; with rho^2 = |w|^2 - |V^T w|^2
+// the norm left after one pass, the first pass alone leaves the new basis
+// vector orthogonal to about eps |w| / rho and the Pythagorean norm accurate to
+// about eps |w|^2 / rho^2.  The second pass is taken when rho < 1e-2 |w|,
+// which bounds these by about 2e-14 and 2e-12 (a NaN also takes it, and then
+// reaches the solver as a breakdown).  Every caller evaluates the same sum in
+// the same order, so all blocks and the second stage agree.
+constexpr double CGS_REFINE_TAU2 = 1e-4;
+
+__device__ inline bool cgs_refine(const double* g, int k) {
+    double ss = 0.0;
+    for (int i = 0; i < k; ++i) ss += g[i] * g[i];
+    const double w2 = g[k];
+    return !(w2 - ss >= CGS_REFINE_TAU2 * w2);
+}
+
+// gate (optional): the first-pass record g of a conditional second pass.  When
+// cgs_refine(g, kg) is false the pass's first stage wrote nothing; this stage
+// then hands the first pass on unchanged (out[0..kg] = g[0..kg]) and records a
+// zero correction (host_out[0..kg-1] = 0).  host_out[63] records whether the
+// pass ran (1) or not (0).
 __global__ void __launch_bounds__(RED_BLOCKS) k_final(const double* part, int k, double* out, int mode,
-                                                       double* host_out) {
+                                                       double* host_out, const double* gate, int kg) {
     __shared__ double sh[FIN_WAVES][KCH + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (gate) {
+        const bool refine = cgs_refine(gate, kg);
+        if (host_out && threadIdx.x == 0) host_out[63] = refine ? 1.0 : 0.0;
+        if (!refine) {
+            if ((int)threadIdx.x <= kg) {
+                out[threadIdx.x] = gate[threadIdx.x];
+                if (host_out) host_out[threadIdx.x] = (int)threadIdx.x < kg ? 0.0 : gate[kg];
+            }
+            return;
+        }
+    }
     double p[KCH + 1];
 #pragma unroll
     for (int i = 0; i <= KCH; ++i) p[i] = i < k ? part[(int64_t)i * RED_BLOCKS + threadIdx.x] : 0.0;
@@ -84,9 +117,9 @@ __global__ void __launch_bounds__(RED_BLOCKS) k_final(const double* part, int k,
 }
 
 static void final_sum(const double* part, int k, double* out, hipStream_t s, int mode = 0,
-                      double* host_out = nullptr) {
+                      double* host_out = nullptr, const double* gate = nullptr, int kg = 0) {
     if (k < 1 || k > KCH + 1) throw Error(IIM_E_INVALID_ARG, "reduction: 1..13 values");
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(RED_BLOCKS), 0, s, part, k, out, mode, host_out);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RED_BLOCKS), 0, s, part, k, out, mode, host_out, gate, kg);
     IIM_LAUNCH_CHECK();
 }
 
@@ -97,11 +130,12 @@ static void check_vec(const void* p, int64_t ld) {
 __device__ inline double2 ld2(const double* base, int64_t e) { return reinterpret_cast<const double2*>(base)[e]; }
 __device__ inline void st2(double* base, int64_t e, double2 v) { reinterpret_cast<double2*>(base)[e] = v; }
 
+// dots of w with V_i (i < k) and, if asked, |w|^2 right after them
 __global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* V, int64_t ld, int k, const double* w,
-                                                          int64_t n, double* part) {
-    double acc[KCH];
+                                                          int64_t n, int with_norm, double* part) {
+    double acc[KCH + 1];
 #pragma unroll
-    for (int i = 0; i < KCH; ++i) acc[i] = 0.0;
+    for (int i = 0; i <= KCH; ++i) acc[i] = 0.0;
     const int64_t np = n >> 1;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np; e += (int64_t)gridDim.x * blockDim.x) {
         const double2 we = ld2(w, e);
@@ -112,30 +146,40 @@ __global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* V, int64
                 acc[i] += v.x * we.x;
                 acc[i] += v.y * we.y;
             }
+        acc[KCH] += we.x * we.x;
+        acc[KCH] += we.y * we.y;
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const double we = w[n - 1];
 #pragma unroll
         for (int i = 0; i < KCH; ++i)
-            if (i < k) acc[i] += V[(int64_t)i * ld + n - 1] * w[n - 1];
+            if (i < k) acc[i] += V[(int64_t)i * ld + n - 1] * we;
+        acc[KCH] += we * we;
     }
-    block_reduce_store(acc, k, part, 0);
+    double outv[KCH + 1];
+#pragma unroll
+    for (int i = 0; i <= KCH; ++i) outv[i] = (i < k) ? acc[i] : ((i == k) ? acc[KCH] : 0.0);
+    block_reduce_store(outv, k + (with_norm ? 1 : 0), part, 0);
 }
 
 void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* part, double* out,
-                  hipStream_t s, double* host_out) {
+                  hipStream_t s, double* host_out, int with_norm) {
     if (k < 1 || k > KCH) throw Error(IIM_E_INVALID_ARG, "multidot: 1..12 vectors");
     check_vec(V, ld);
     check_vec(w, 0);
-    hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, w, n, part);
+    hipLaunchKernelGGL(k_multidot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, w, n, with_norm, part);
     IIM_LAUNCH_CHECK();
-    final_sum(part, k, out, s, 0, host_out);
+    final_sum(part, k + (with_norm ? 1 : 0), out, s, 0, host_out);
 }
 
 // w -= sum_i h_i V_i (all k at once), then dots of the updated w with V_i (i < k2)
 // and, if asked, its squared norm; each basis vector is read once
 __global__ void __launch_bounds__(RED_THREADS) k_update_dot(const double* V, int64_t ld, int k, const double* h,
                                                             double* w, int64_t n, int k2, int with_norm,
-                                                            double* part) {
+                                                            double* part, int gated) {
+    // a gated pass (h = the first pass's record: k dots and |w|^2) runs only
+    // when that pass left too little of w (the same test in every block)
+    if (gated && !cgs_refine(h, k)) return;
     double hh[KCH], acc[KCH + 1];
 #pragma unroll
     for (int i = 0; i < KCH; ++i) {
@@ -192,27 +236,30 @@ void run_update_dot_stage1(const double* V, int64_t ld, int k, const double* h, 
     check_vec(V, ld);
     check_vec(w, 0);
     hipLaunchKernelGGL(k_update_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, n, k2, with_norm,
-                       part);
+                       part, 0);
     IIM_LAUNCH_CHECK();
 }
 
 void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
-                    int with_norm, double* part, double* out, hipStream_t s, double* host_out) {
+                    int with_norm, double* part, double* out, hipStream_t s, double* host_out, bool gated) {
     if (k > KCH || k2 > KCH) throw Error(IIM_E_INVALID_ARG, "update_dot: too many vectors");
     check_vec(V, ld);
     check_vec(w, 0);
     if (k2 + (with_norm ? 1 : 0) < 1) throw Error(IIM_E_INVALID_ARG, "update_dot: nothing to reduce");
+    if (gated && (k2 != k || !with_norm)) throw Error(IIM_E_INVALID_ARG, "update_dot: a gated pass is a full CGS pass");
     hipLaunchKernelGGL(k_update_dot, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, n, k2, with_norm,
-                       part);
+                       part, gated ? 1 : 0);
     IIM_LAUNCH_CHECK();
-    final_sum(part, k2 + (with_norm ? 1 : 0), out, s, 0, host_out);
+    final_sum(part, k2 + (with_norm ? 1 : 0), out, s, 0, host_out, gated ? h : nullptr, k);
 }
 
-// Second classical Gram-Schmidt pass fused with the normalisation:
+// Last classical Gram-Schmidt update fused with the normalisation:
 //   y = (w - sum_i h_i V_i) / sqrt(nrm2),  nrm2 = h[k] - sum_i h_i^2,
-// where h[0..k-1] = V^T w and h[k] = |w|^2 come from the pass that made w.  With
-// V orthonormal, |w - V h|^2 = |w|^2 - |h|^2 (Pythagoras); after a first pass h
-// is a rounding-level correction, so the difference does not cancel.  nrm2 is
+// where h[0..k-1] = V^T w and h[k] = |w|^2 come from the pass that read w.  With
+// V orthonormal, |w - V h|^2 = |w|^2 - |h|^2 (Pythagoras).  After a first
+// update h is a rounding-level correction and the difference does not cancel;
+// as the only update it is used only when |h|^2 <= (1 - 1e-4) |w|^2 (see
+// cgs_refine), so at most four decimal digits cancel.  nrm2 is
 // floored at 0 (then y is not finite and the solver takes it as a breakdown)
 // and written to *nrm2_out; block maxima of |y| go to part (the V-cycle's
 // scaling of y is then one second-stage launch away).

@@ -308,6 +308,13 @@ __host__ __device__ constexpr double ho_a(int j) {
                   : (j == 0 ? -49.0 / 18.0 : j == 1 ? 1.5 : j == 2 ? -3.0 / 20.0 : 1.0 / 90.0);
 }
 
+// central first derivative of order 2W (half-width W): du/dx ~ sum_j g_j
+// (u_{+j} - u_{-j}) / h, j = 1..W (the gradient post-processing)
+template <int W>
+__host__ __device__ constexpr double ho_g(int j) {
+    return W == 2 ? (j == 1 ? 2.0 / 3.0 : -1.0 / 12.0) : (j == 1 ? 0.75 : j == 2 ? -3.0 / 20.0 : 1.0 / 60.0);
+}
+
 // Lagrange weight of point t (t = 0 the box face, t = 1 .. 2W the nodes behind
 // it) of the degree-2W polynomial through them, evaluated s steps beyond the face
 template <int W>

@@ -136,6 +136,8 @@ struct Problem {
     // scaled: red_scale already holds max |v| (the fused orthogonalisation wrote it);
     // out_basis: out is zero off the core (a Krylov basis column)
     template <typename T, typename S> void vcycle_t(const double* v, double* out, bool scaled, bool out_basis);
+    template <typename T, typename S> void wcycle_t(const double* v, double* out, bool scaled);
+    template <typename T, typename S> void wvisit(int l, bool zero_start);
     void vcycle(const double* v, double* out, bool scaled = false, bool out_basis = false);
     void iteration_body(int j, hipEvent_t* evs = nullptr);
     int solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st);

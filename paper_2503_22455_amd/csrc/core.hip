@@ -335,7 +335,11 @@ void Problem::setup() {
 
     // ---- least-squares stencils (FP64): sizes  [wait 3], then the fits
     const int64_t ncs = cp.ncp * nsides;
-    nrows = w + ((bc == IIM_BC_DIRICHLET) ? 0 : 1);
+    // rows: the w ghost functionals, then the normal derivative at x_c (the
+    // Neumann and interface closures use it; for Dirichlet problems it serves
+    // the boundary-quantity post-processing only, and the apply reads rows
+    // 0..w-1, which sit at the same addresses)
+    nrows = w + 1;
     {
         LSParams P;
         P.dim = dim;
@@ -408,7 +412,7 @@ void Problem::setup() {
             nrows_apply = w;
         } else {
             W_apply = ls_S;
-            nrows_apply = nrows;
+            nrows_apply = bc == IIM_BC_DIRICHLET ? w : nrows;
         }
         run_apply_weights(bc, ls_ptr, ncs, w, nrows, ls_S, ls_Sc, opt.beta_plus, nnz,
                           bc == IIM_BC_NEUMANN ? W_apply : nullptr, dcoef, stream);
@@ -532,7 +536,10 @@ void Problem::setup() {
     const int64_t tail_default = TAIL_MAX_NODES;
     const int64_t tail_max = opt.tail_nodes == 0 ? tail_default : (int64_t)opt.tail_nodes;
     tail_first = nl - 1;
-    while (tail_first > 0 && levels[tail_first - 1].box.size() <= tail_max) --tail_first;
+    // the W-cycle visits every level from the host; the one-workgroup kernel
+    // then holds the coarse solve only
+    if (opt.cycle_gamma == 1)
+        while (tail_first > 0 && levels[tail_first - 1].box.size() <= tail_max) --tail_first;
     // 3D grid levels keep their vectors colour-split: a red-black half-sweep then
     // reads and writes whole contiguous colour rows
     for (int l = 0; l < nl; ++l) {
@@ -765,17 +772,63 @@ void Problem::vcycle_t(const double* v, double* out, bool scaled, bool out_basis
     if (!have_out) run_cast_out<S>(D0, zres, red_scale + 1, out, stream);
 }
 
-void Problem::vcycle(const double* v, double* out, bool scaled, bool out_basis) {
-    if (opt.precision == IIM_PREC_FP64)
-        vcycle_t<double, double>(v, out, scaled, out_basis);
-    else if (opt.precision == IIM_PREC_MIXED32)
-        vcycle_t<float, float>(v, out, scaled, out_basis);
-    else
-        vcycle_t<float, __half>(v, out, scaled, out_basis);
+// One visit of level l in a W-cycle (cycle index 2): pre-smoothing from zero or
+// from the iterate the previous visit left, residual + restriction, two visits
+// of level l + 1 (the first from zero), prolongation + correction,
+// post-smoothing.  The coarse solve ignores its start, so a second visit of the
+// coarsest level would return the same iterate and is not made.  Every level
+// runs its unfused kernels, which take any start.
+template <typename T, typename S>
+void Problem::wvisit(int l, bool zero_start) {
+    const int nl = (int)levels.size();
+    if (l == nl - 1) {
+        run_tail<T, S>(dim, d_tail, tail_lds_bytes, stream);  // coarse solve only (tail_first = nl - 1)
+        return;
+    }
+    LevelDev D = level_dev(l), C = level_dev(l + 1);
+    S* z = (S*)levels[l].z;
+    T* b = (T*)levels[l].b;
+    if (zero_start) run_zero<S>(z, levels[l].vsize(), stream);
+    for (int s = 0; s < opt.nu_pre; ++s) {
+        run_rbgs<T, S>(D, 0, z, b, stream);
+        run_rbgs<T, S>(D, 1, z, b, stream);
+    }
+    run_resid_restrict<T, S>(D, C, z, b, (T*)levels[l + 1].b, stream);
+    wvisit<T, S>(l + 1, true);
+    if (l + 1 < nl - 1) wvisit<T, S>(l + 1, false);
+    const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+    run_prolong<T, S>(D, C, mode, (const S*)levels[l + 1].z, z, stream);
+    for (int s = 0; s < opt.nu_post; ++s) {
+        run_rbgs<T, S>(D, 0, z, b, stream);
+        run_rbgs<T, S>(D, 1, z, b, stream);
+    }
 }
 
-// One inner FGMRES iteration on the device: z_j = M^{-1} v_j, w = A z_j, CGS2
-// against v_0..v_j, v_{j+1} = w / |w|, and the Hessenberg column copied to
+template <typename T, typename S>
+void Problem::wcycle_t(const double* v, double* out, bool scaled) {
+    LevelDev D0 = level_dev(0);
+    if (!scaled) run_absmax(v, box.size(), red_part, red_scale, stream);
+    run_cast_in<T>(D0, v, red_scale + 1, h * h, opt.beta_plus, opt.beta_minus, (T*)levels[0].b, stream);
+    wvisit<T, S>(0, true);
+    run_cast_out<S>(D0, (const S*)levels[0].z, red_scale + 1, out, stream);
+}
+
+void Problem::vcycle(const double* v, double* out, bool scaled, bool out_basis) {
+    const bool w = opt.cycle_gamma == 2;
+    if (opt.precision == IIM_PREC_FP64) {
+        if (w) wcycle_t<double, double>(v, out, scaled);
+        else vcycle_t<double, double>(v, out, scaled, out_basis);
+    } else if (opt.precision == IIM_PREC_MIXED32) {
+        if (w) wcycle_t<float, float>(v, out, scaled);
+        else vcycle_t<float, float>(v, out, scaled, out_basis);
+    } else {
+        if (w) wcycle_t<float, __half>(v, out, scaled);
+        else vcycle_t<float, __half>(v, out, scaled, out_basis);
+    }
+}
+
+// One inner FGMRES iteration on the device: z_j = M^{-1} v_j, w = A z_j,
+// classical Gram-Schmidt against v_0..v_j, v_{j+1} = w / |w|, and the Hessenberg column copied to
 // pinned host memory.  Pointers are fixed per j, so it can be captured.
 void Problem::iteration_body(int j, hipEvent_t* evs) {
     const int64_t N = box.size();
@@ -785,19 +838,24 @@ void Problem::iteration_body(int j, hipEvent_t* evs) {
     if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
     apply_box(zj, wk, 0);
     if (evs) IIM_HIP(hipEventRecord(evs[2], stream));
-    // CGS2: h = V^T w; w -= V h with h' = V^T w and |w|^2 in the same pass; then
-    // v_{j+1} = (w - V h') / |w - V h'|, the norm by Pythagoras
-    // the column's record also goes straight to pinned host memory (no copy)
+    // Classical Gram-Schmidt: h = V^T w (with |w|^2 when the second pass is
+    // conditional); the second pass w -= V h with h' = V^T w and |w|^2 in the
+    // same sweep, every iteration (CGS2) or only when the first pass left less
+    // than 1e-2 of |w| (decided on the device, so launches stay queued); then
+    // v_{j+1} = (w - V h') / |w - V h'|, the norm by Pythagoras.  The column's
+    // record goes straight to pinned host memory (no copy).
     double* rec = hpin + (size_t)j * HCOL;
-    run_multidot(Vb, ldv, j + 1, wk, N, red_part, red_out, stream, rec);
-    run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 1, red_part, red_out + 64, stream, rec + 64);
+    const bool gated = opt.orthogonalisation == 1;
+    run_multidot(Vb, ldv, j + 1, wk, N, red_part, red_out, stream, rec, gated ? 1 : 0);
+    run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 1, red_part, red_out + 64, stream, rec + 64, gated);
     run_update_scale(Vb, ldv, j + 1, red_out + 64, wk, Vb + (size_t)(j + 1) * ldv, N, red_out + 128, red_part,
                      red_scale, stream, rec + 128);
 }
 
 // ---------------------------------------------------------------------------
-// FGMRES(m), right preconditioned, classical Gram-Schmidt with one
-// re-orthogonalisation; Givens rotations on the host.
+// FGMRES(m), right preconditioned, classical Gram-Schmidt with a second pass
+// every iteration or only where the first loses orthogonality; Givens
+// rotations on the host.
 // ---------------------------------------------------------------------------
 int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st) {
     const double t0 = now_ms();
@@ -815,7 +873,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
     IIM_HIP(hipStreamSynchronize(stream));
     const double bnorm = std::sqrt(bnorm2);
     int status = IIM_OK;
-    int its = 0, cycles = 0, hl = 0;
+    int its = 0, cycles = 0, hl = 0, second_passes = 0;
     double true_rel = 0.0;
     std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
     if (bnorm == 0.0) {
@@ -895,6 +953,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
                 }
                 const double* hbuf = hpin + (size_t)j * HCOL;
                 for (int i = 0; i <= j; ++i) H[i * m + j] = hbuf[i] + hbuf[64 + i];
+                if (opt.orthogonalisation == 0 || hbuf[64 + 63] != 0.0) ++second_passes;
                 const double hn = std::sqrt(hbuf[128]);
                 H[(j + 1) * m + j] = hn;
                 if (!(hn == hn)) {
@@ -946,6 +1005,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
     S.iterations = its;
     S.cycles = cycles;
     S.hist_len = hl;
+    S.second_passes = second_passes;
     S.final_rel_residual = true_rel;
     S.t_solve_ms = now_ms() - t0;
     S.t_apply_ms = t_apply;
@@ -1064,7 +1124,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     ncp = 1.15 * ncp + 64.0;
     const int ns = geo.side == IIM_SIDE_INTERFACE ? 2 : 1;
     const int w = o.order_n / 2;
-    const int nrows = w + (geo.bc == IIM_BC_DIRICHLET ? 0 : 1);
+    const int nrows = w + 1;
     const double mset = dim == 2 ? (o.order_k == 7 ? 112.0 : 56.0) : 264.0;
     const double ncs = ncp * ns;
     bytes += (int64_t)(ncp * (4 + 4 + 24 + 24 + 8 + 16) + ncs * (4 + 4 + 8 * w * 2 + 8 * nrows + 4 + 4 + 1 + 8));
@@ -1245,6 +1305,9 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
         throw Error(IIM_E_INVALID_ARG, "built discretisations: (4,5) in 2D and 3D, (6,7) in 2D");
     if (o.restart < 1 || o.restart > 11) throw Error(IIM_E_INVALID_ARG, "restart must be in [1, 11]");
     if (o.use_graph < 0 || o.use_graph > 2) throw Error(IIM_E_INVALID_ARG, "use_graph must be 0, 1 or 2");
+    if (o.orthogonalisation < 0 || o.orthogonalisation > 1)
+        throw Error(IIM_E_INVALID_ARG, "orthogonalisation must be 0 or 1");
+    if (o.cycle_gamma < 1 || o.cycle_gamma > 2) throw Error(IIM_E_INVALID_ARG, "cycle_gamma must be 1 (V) or 2 (W)");
     if (o.coarsest_n < 2) throw Error(IIM_E_INVALID_ARG, "coarsest_n must be >= 2");
     if (o.precision < 0 || o.precision > 2) throw Error(IIM_E_INVALID_ARG, "bad precision");
     if (!(o.beta_plus > 0) || !(o.beta_minus > 0)) throw Error(IIM_E_INVALID_ARG, "beta must be positive");
@@ -1292,7 +1355,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     p->side = geo->side;
     p->bc = geo->bc;
     p->params.assign(geo->params, geo->params + geo->nparams);
-    p->opt_fused = o.fused_smoothing != 0;
+    p->opt_fused = o.fused_smoothing != 0 && o.cycle_gamma == 1;  // the fused legs start from zero
     p->opt_split = o.colour_split != 0;
     p->setup();
     return p;
@@ -1359,6 +1422,8 @@ int iim_default_options(iim_options* o) {
     o->tail_nodes = 0;
     o->fused_smoothing = 1;
     o->colour_split = 1;
+    o->orthogonalisation = 1;
+    o->cycle_gamma = 1;
     return IIM_OK;
 }
 
@@ -1531,6 +1596,46 @@ int iim_vcycle(iim_problem* h, const double* v, double* z) {
         run_full_to_box(p.dim, p.grid.n, p.box, v, p.rk, p.levels[0].labels, 1, p.stream);
         p.vcycle(p.rk, p.wk);
         run_box_to_full(p.dim, p.grid.n, p.box, p.wk, p.levels[0].labels, 0.0, z, p.stream);
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        return IIM_OK;
+    })
+}
+
+int iim_gradient(iim_problem* h, const double* u, double* grad) {
+    ABI_TRY({
+        if (!h || !u || !grad) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        const int64_t n1 = p.grid.n + 1;
+        const int64_t total = p.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+        run_fill(grad, p.dim * total, std::nan(""), p.stream);
+        run_full_to_box(p.dim, p.grid.n, p.box, u, p.rk, p.levels[0].labels, 1, p.stream);
+        run_ghosts(p.ghost_dev(), p.rk, p.cpdata, 1, p.ghost, p.stream);
+        const Level& L0 = p.levels[0];
+        run_ho_gradient(p.dim, p.box, L0.core_lo, L0.core_hi, p.grid.n, L0.labels, p.ho_irr_index, p.ho_slots, p.ghost,
+                        p.boxval, p.w, 1.0 / p.h, p.rk, grad, p.stream);
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        return IIM_OK;
+    })
+}
+
+int iim_boundary_quantity(iim_problem* h, const double* u, double* q) {
+    ABI_TRY({
+        if (!h || !u || !q) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        run_full_to_box(p.dim, p.grid.n, p.box, u, p.rk, p.levels[0].labels, 1, p.stream);
+        BQDev B;
+        B.bc = p.bc;
+        B.nsides = p.nsides;
+        B.w = p.w;
+        B.nrows = p.nrows;
+        B.beta_plus = p.opt.beta_plus;
+        B.beta_minus = p.opt.beta_minus;
+        B.ptr = p.ls_ptr;
+        B.idx = p.ls_idx;
+        B.Sd = p.ls_S + (size_t)p.w * p.nnz;
+        B.Sc = p.ls_Sc;
+        B.ncp = p.cp.ncp;
+        run_boundary_quantity(B, p.rk, p.cpdata, q, p.stream);
         IIM_HIP(hipStreamSynchronize(p.stream));
         return IIM_OK;
     })

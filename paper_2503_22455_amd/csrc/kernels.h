@@ -227,6 +227,25 @@ void run_apply_weights(int bc, const int64_t* ptr, int64_t ncs, int w, int nrows
 template <typename A, typename B>
 void run_convert(const A* a, B* b, int64_t n, double scale, hipStream_t s);
 
+// ---- post-processing of a solution (Sec. 2.4) -------------------------------------
+// grad[d * (n+1)^dim + f] = d/dx_d u at every unknown f (order-2w central first
+// derivative over the extended function; ghost values of x must be current)
+void run_ho_gradient(int dim, const Box& b, const int* core_lo, const int* core_hi, int n, const uint8_t* labels,
+                     const int32_t* irr_index, const int32_t* slots, const double* ghost, const double* boxval, int w,
+                     double inv_h, const double* x, double* grad, hipStream_t s);
+struct BQDev {
+    int bc, nsides, w, nrows;      // nrows: rows of the fits (w ghosts + the normal derivative)
+    double beta_plus, beta_minus;
+    const int64_t* ptr;            // [ncs + 1]
+    const int32_t* idx;            // [nnz] storage-box indices
+    const double* Sd;              // [nnz] the normal-derivative row of the fits
+    const double* Sc;              // [ncs][nrows] weights of u(x_c)
+    int64_t ncp;
+};
+// q[c]: du/dn (Dirichlet), u (Neumann) or du+/dn (interface) at control point c
+void run_boundary_quantity(const BQDev& B, const double* x, const double* cpdata, double* q, hipStream_t s);
+void run_fill(double* p, int64_t n, double v, hipStream_t s);
+
 // full grid <-> storage box
 void run_full_to_box(int dim, int n, const Box& b, const double* full, double* boxed, const uint8_t* labels,
                      int only_unknowns, hipStream_t s);
@@ -241,18 +260,22 @@ constexpr int KRED = 16;  // values per reduction launch
 // reduction workspace: (KRED + 1) * RED_BLOCKS partials
 constexpr int64_t RED_PART_DOUBLES = (int64_t)(KRED + 1) * RED_BLOCKS;
 constexpr int RED_THREADS = 256;
-// out[i] = <V_i, w> for i < k; V_i = V + i * ld
+// out[i] = <V_i, w> for i < k; V_i = V + i * ld; out[k] = <w, w> if with_norm
 void run_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* part, double* out,
-                  hipStream_t s, double* host_out = nullptr);
-// w -= sum_{i<k} h[i] V_i; then out[i] = <V_i, w> for i < k2 and out[k2] = <w, w> (if with_norm)
+                  hipStream_t s, double* host_out = nullptr, int with_norm = 0);
+// w -= sum_{i<k} h[i] V_i; then out[i] = <V_i, w> for i < k2 and out[k2] = <w, w> (if with_norm).
+// gated: h is a first Gram-Schmidt pass's record (k dots, then |w|^2) and the pass runs only when
+// that pass left too little of w; otherwise w is untouched, out[0..k] = h[0..k] and host_out
+// records a zero correction.  host_out[63] = 1 if the pass ran, 0 if not.
 void run_update_dot(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
-                    int with_norm, double* part, double* out, hipStream_t s, double* host_out = nullptr);
+                    int with_norm, double* part, double* out, hipStream_t s, double* host_out = nullptr,
+                    bool gated = false);
 // the streaming first stage of run_update_dot alone (block partials in part)
 void run_update_dot_stage1(const double* V, int64_t ld, int k, const double* h, double* w, int64_t n, int k2,
                            int with_norm, double* part, hipStream_t s);
 // y = x / sqrt(*nrm2)
 void run_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
-// y = (w - V h) / sqrt(h[k] - |h|^2) (second CGS pass + normalisation; h[k] = |w|^2);
+// y = (w - V h) / sqrt(h[k] - |h|^2) (last CGS pass + normalisation; h[k] = |w|^2);
 // the squared norm to *nrm2_out, max |y| and its reciprocal to scale_out[0..1]
 void run_update_scale(const double* V, int64_t ld, int k, const double* h, const double* w, double* y, int64_t n,
                       double* nrm2_out, double* part, double* scale_out, hipStream_t s, double* nrm2_host = nullptr);

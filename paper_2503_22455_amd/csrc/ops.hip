@@ -119,9 +119,47 @@ void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int wi
 // ---------------------------------------------------------------------------
 // high-order apply: y = beta/h^2 sum_d sum_j a_|j| u~(i + j e_d)
 // ---------------------------------------------------------------------------
-// contribution of the off-centre points of an irregular node (label flag
-// F_HO_IRR): per axis and direction, grid values up to the first crossing, then
-// ghost values (or box data with extrapolation past a box face)
+// values u~(l + jj sd), jj = 1..W, of the extended function along one half-line
+// of an irregular node (label flag F_HO_IRR), from its slot record: grid values
+// up to the first crossing, then ghost values (or box data with extrapolation
+// past a box face)
+template <int W>
+__device__ inline void ho_half_line(int64_t l, int64_t sd, int slot, uint8_t kind,
+                                    const uint8_t* __restrict__ labels, const double* __restrict__ ghost,
+                                    const double* __restrict__ boxval, const double* __restrict__ x, int with_data,
+                                    double (&v)[W]) {
+    const int type = slot_type(slot), j0 = slot_j(slot);
+    for (int jj = 1; jj <= W; ++jj) {
+        const int64_t q = l + jj * sd;
+        double val;
+        if (type == SLOT_REG || jj < j0) {
+            val = x[q];
+        } else if (type == SLOT_GHOST) {
+            uint8_t kq = labels[q] & KIND_MASK;
+            if (kq == kind)
+                val = x[q];  // back on the stencil's side beyond a sliver
+            else if (kq == K_BOX)
+                val = with_data ? boxval[q] : 0.0;
+            else
+                val = ghost[(int64_t)slot_cs(slot) * W + (jj - j0)];
+        } else {  // box face at offset j0
+            const int64_t face = l + j0 * sd;
+            const double fv = with_data ? boxval[face] : 0.0;
+            if (jj == j0) {
+                val = fv;
+            } else {
+                // degree-2W Lagrange extrapolation jj - j0 steps beyond the face
+                const int sb = jj - j0;
+                val = ho_ext<W>(sb, 0) * fv;
+#pragma unroll
+                for (int u = 1; u <= 2 * W; ++u) val += ho_ext<W>(sb, u) * x[face - u * sd];
+            }
+        }
+        v[jj - 1] = val;
+    }
+}
+
+// contribution of the off-centre points of an irregular node
 template <int DIM, int W>
 __device__ inline double ho_irregular(const Box& b, int64_t l, uint8_t kind, const uint8_t* __restrict__ labels,
                                       const int32_t* __restrict__ rec, const double* __restrict__ ghost,
@@ -132,38 +170,8 @@ __device__ inline double ho_irregular(const Box& b, int64_t l, uint8_t kind, con
     for (int d = 0; d < DIM; ++d)
         for (int t = 0; t < 2; ++t) {
             const int dir = t ? 1 : -1;
-            const int64_t sd = dir * st[d];
-            const int slot = rec[2 * d + t];
-            const int type = slot_type(slot), j0 = slot_j(slot);
             double v[W];
-            for (int jj = 1; jj <= W; ++jj) {
-                const int64_t q = l + jj * sd;
-                double val;
-                if (type == SLOT_REG || jj < j0) {
-                    val = x[q];
-                } else if (type == SLOT_GHOST) {
-                    uint8_t kq = labels[q] & KIND_MASK;
-                    if (kq == kind)
-                        val = x[q];  // back on the stencil's side beyond a sliver
-                    else if (kq == K_BOX)
-                        val = with_data ? boxval[q] : 0.0;
-                    else
-                        val = ghost[(int64_t)slot_cs(slot) * W + (jj - j0)];
-                } else {  // box face at offset j0
-                    const int64_t face = l + j0 * sd;
-                    const double fv = with_data ? boxval[face] : 0.0;
-                    if (jj == j0) {
-                        val = fv;
-                    } else {
-                        // degree-2W Lagrange extrapolation jj - j0 steps beyond the face
-                        const int sb = jj - j0;
-                        val = ho_ext<W>(sb, 0) * fv;
-#pragma unroll
-                        for (int u = 1; u <= 2 * W; ++u) val += ho_ext<W>(sb, u) * x[face - u * sd];
-                    }
-                }
-                v[jj - 1] = val;
-            }
+            ho_half_line<W>(l, dir * st[d], rec[2 * d + t], kind, labels, ghost, boxval, x, with_data, v);
             double tw = ho_a<W>(1) * v[0] + ho_a<W>(2) * v[1];
             if (W == 3) tw += ho_a<W>(3) * v[W - 1];
             acc += tw;
@@ -396,6 +404,142 @@ void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi,
                            inv_h2, beta_plus, beta_minus, x, y, with_data);
     else
         throw Error(IIM_E_INTERNAL, "apply: stencil half-width must be 2 or 3");
+    IIM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// post-processing of a solution (Sec. 2.4 of the paper)
+// ---------------------------------------------------------------------------
+// grad u at the unknowns: per axis the central first derivative of order 2W
+// over the extended function (the Laplacian's ghost values and box
+// extrapolation), written to grad[d * total + full-grid index]; one thread per
+// node of the core, nodes that are no unknowns are left alone.
+template <int DIM, int W>
+__global__ void __launch_bounds__(256) k_ho_gradient(Box b, int3 clo, int3 chi, int n, const uint8_t* __restrict__ labels,
+                                                     const int32_t* __restrict__ irr_index,
+                                                     const int32_t* __restrict__ slots, const double* __restrict__ ghost,
+                                                     const double* __restrict__ boxval, double inv_h,
+                                                     const double* __restrict__ x, double* __restrict__ grad,
+                                                     int64_t total) {
+    const int i = clo.x + blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = clo.y + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? clo.z + (int)blockIdx.z : 0;
+    if (i > chi.x || j > chi.y) return;
+    if (i < 0 || i > n || j < 0 || j > n || k < 0 || k > n) return;
+    const int64_t l = b.idx(i, j, k);
+    const uint8_t lab = labels[l];
+    const uint8_t kind = lab & KIND_MASK;
+    if (kind != K_PLUS && kind != K_MINUS) return;
+    const int64_t f = i + (int64_t)(n + 1) * (j + (int64_t)(n + 1) * k);
+    const int64_t st[3] = {1, (int64_t)b.dims[0], (int64_t)b.dims[0] * b.dims[1]};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        double vp[W], vm[W];
+        if (lab & F_HO_IRR) {
+            const int32_t* rec = slots + (int64_t)irr_index[l] * 2 * DIM;
+            ho_half_line<W>(l, -st[d], rec[2 * d + 0], kind, labels, ghost, boxval, x, 1, vm);
+            ho_half_line<W>(l, st[d], rec[2 * d + 1], kind, labels, ghost, boxval, x, 1, vp);
+        } else {
+#pragma unroll
+            for (int jj = 1; jj <= W; ++jj) {
+                vp[jj - 1] = x[l + jj * st[d]];
+                vm[jj - 1] = x[l - jj * st[d]];
+            }
+        }
+        double g = 0.0;
+#pragma unroll
+        for (int jj = 1; jj <= W; ++jj) g += ho_g<W>(jj) * (vp[jj - 1] - vm[jj - 1]);
+        grad[(int64_t)d * total + f] = g * inv_h;
+    }
+}
+
+void run_ho_gradient(int dim, const Box& b, const int* core_lo, const int* core_hi, int n, const uint8_t* labels,
+                     const int32_t* irr_index, const int32_t* slots, const double* ghost, const double* boxval, int w,
+                     double inv_h, const double* x, double* grad, hipStream_t s) {
+    const int3 lo = make_int3(core_lo[0], core_lo[1], core_lo[2]);
+    const int3 hi = make_int3(core_hi[0], core_hi[1], core_hi[2]);
+    const int nx = hi.x - lo.x + 1, ny = hi.y - lo.y + 1, nz = dim == 3 ? hi.z - lo.z + 1 : 1;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return;
+    // every stencil point of a core node lies in the storage box (w-node margin)
+    for (int d = 0; d < dim; ++d)
+        if (core_lo[d] - w < b.lo[d] || core_hi[d] + w > b.lo[d] + b.dims[d] - 1)
+            throw Error(IIM_E_INTERNAL, "gradient: storage box lacks the stencil margin");
+    const int64_t total = dim == 2 ? (int64_t)(n + 1) * (n + 1) : (int64_t)(n + 1) * (n + 1) * (n + 1);
+    const dim3 blk(64, 4, 1);
+    const dim3 grd(cdiv(nx, 64), cdiv(ny, 4), nz);
+    if (dim == 3 && w == 2)
+        hipLaunchKernelGGL((k_ho_gradient<3, 2>), grd, blk, 0, s, b, lo, hi, n, labels, irr_index, slots, ghost,
+                           boxval, inv_h, x, grad, total);
+    else if (dim == 2 && w == 2)
+        hipLaunchKernelGGL((k_ho_gradient<2, 2>), grd, blk, 0, s, b, lo, hi, n, labels, irr_index, slots, ghost,
+                           boxval, inv_h, x, grad, total);
+    else if (dim == 2 && w == 3)
+        hipLaunchKernelGGL((k_ho_gradient<2, 3>), grd, blk, 0, s, b, lo, hi, n, labels, irr_index, slots, ghost,
+                           boxval, inv_h, x, grad, total);
+    else
+        throw Error(IIM_E_INTERNAL, "gradient: unsupported dimension / half-width");
+    IIM_LAUNCH_CHECK();
+}
+
+// The boundary quantity the condition leaves open, one value per control
+// point: with s the fit's normal-derivative row (row w of S, its u(x_c)
+// weight s_c) and dot = sum_i s_i u_i over the fit's nodes,
+//   Dirichlet  du/dn(x_c) = s_c ubar + dot;
+//   Neumann    u(x_c) = (qbar - beta+ dot) / (beta+ s_c);
+//   interface  du+/dn(x_c) = s+_c u+(x_c) + dot+, u+(x_c) from the closure
+//              (D = beta+ s+_c - beta- s-_c).
+// GLN lanes per control point gather the dot products.
+template <int NS, int GLN>
+__global__ void __launch_bounds__(256) k_boundary_quantity(BQDev B, const double* __restrict__ x,
+                                                           const double* __restrict__ cpdata, double* __restrict__ q) {
+    const int lane = threadIdx.x % GLN;
+    const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / GLN;
+    if (c >= B.ncp) return;  // whole groups exit together
+    double dots[NS];
+#pragma unroll
+    for (int sd = 0; sd < NS; ++sd) {
+        const int64_t cs = c * NS + sd;
+        double acc = 0.0;
+        for (int64_t a = B.ptr[cs] + lane; a < B.ptr[cs + 1]; a += GLN) acc += B.Sd[a] * x[B.idx[a]];
+#pragma unroll
+        for (int off = GLN / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, GLN);
+        dots[sd] = acc;
+    }
+    if (lane != 0) return;
+    const int nr = B.nrows, w = B.w;
+    const double bp = B.beta_plus;
+    if (NS == 1) {
+        const double scn = B.Sc[c * nr + w];
+        q[c] = B.bc == IIM_BC_DIRICHLET ? scn * cpdata[c] + dots[0] : (cpdata[c] - bp * dots[0]) / (bp * scn);
+        return;
+    }
+    const double bm = B.beta_minus;
+    const double scp = B.Sc[(c * 2 + 0) * nr + w], scm = B.Sc[(c * 2 + 1) * nr + w];
+    const double D = bp * scp - bm * scm;
+    const double ubar = -(bp * dots[0] - bm * dots[NS - 1]) / D;
+    const double up = ubar + (cpdata[2 * c + 1] - bm * scm * cpdata[2 * c]) / D;
+    q[c] = scp * up + dots[0];
+}
+
+void run_boundary_quantity(const BQDev& B, const double* x, const double* cpdata, double* q, hipStream_t s) {
+    if (B.ncp == 0) return;
+    if (B.nrows != B.w + 1) throw Error(IIM_E_INTERNAL, "boundary quantity: the fits lack the derivative row");
+    const int64_t threads = B.ncp * 64;
+    if (B.nsides == 1)
+        hipLaunchKernelGGL((k_boundary_quantity<1, 64>), dim3(cdiv(threads, 256)), dim3(256), 0, s, B, x, cpdata, q);
+    else
+        hipLaunchKernelGGL((k_boundary_quantity<2, 64>), dim3(cdiv(threads, 256)), dim3(256), 0, s, B, x, cpdata, q);
+    IIM_LAUNCH_CHECK();
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void run_fill(double* p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>(cdiv(n, 256), 4096)), dim3(256), 0, s, p, n, v);
     IIM_LAUNCH_CHECK();
 }
 

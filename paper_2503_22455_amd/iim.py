@@ -47,14 +47,16 @@ class Options(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("coarsest_n", ctypes.c_int32), ("precision", ctypes.c_int32), ("ls_axis_t", ctypes.c_double),
                 ("ls_axis_n", ctypes.c_double), ("use_graph", ctypes.c_int32), ("tail_nodes", ctypes.c_int32),
-                ("fused_smoothing", ctypes.c_int32), ("colour_split", ctypes.c_int32)]
+                ("fused_smoothing", ctypes.c_int32), ("colour_split", ctypes.c_int32),
+                ("orthogonalisation", ctypes.c_int32), ("cycle_gamma", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
                 ("hist_len", ctypes.c_int32), ("final_rel_residual", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_apply_ms", ctypes.c_double),
-                ("t_vcycle_ms", ctypes.c_double), ("t_krylov_ms", ctypes.c_double)]
+                ("t_vcycle_ms", ctypes.c_double), ("t_krylov_ms", ctypes.c_double),
+                ("second_passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -108,6 +110,8 @@ def lib():
         L.iim_solve.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(Stats)]
         L.iim_apply.argtypes = [vp, vp, vp, i32]
         L.iim_vcycle.argtypes = [vp, vp, vp]
+        L.iim_gradient.argtypes = [vp, vp, vp]
+        L.iim_boundary_quantity.argtypes = [vp, vp, vp]
         L.iim_ls_stencil.argtypes = [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp, i32]
         L.iim_level_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.iim_level_labels.argtypes = [vp, i32, vp]
@@ -160,7 +164,7 @@ def make_options(beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 
                  restart: int = 10, nu_pre: int = 2, nu_post: int = 2, coarsest_n: int = 8,
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None, use_graph: int = 2,
                  tail_nodes: int = 0, fused_smoothing: bool = True, colour_split: bool = True,
-                 order: Tuple[int, int] = (4, 5)) -> Options:
+                 order: Tuple[int, int] = (4, 5), orthogonalisation: int = 1, cycle: str = "V") -> Options:
     o = Options()
     lib().iim_default_options(ctypes.byref(o))
     o.order_n, o.order_k = int(order[0]), int(order[1])
@@ -171,6 +175,8 @@ def make_options(beta_plus: float = 1.0, beta_minus: float = 1.0, rtol: float = 
     o.tail_nodes = int(tail_nodes)
     o.fused_smoothing = int(fused_smoothing)
     o.colour_split = int(colour_split)
+    o.orthogonalisation = int(orthogonalisation)
+    o.cycle_gamma = {"V": 1, "W": 2}[cycle.upper()]
     if ls_axes is not None:
         o.ls_axis_t, o.ls_axis_n = ls_axes
     return o
@@ -185,7 +191,7 @@ class Problem:
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None,
                  lo: float = -1.0, hi: float = 1.0, use_graph: int = 2, tail_nodes: int = 0,
                  fused_smoothing: bool = True, colour_split: bool = True, order: Tuple[int, int] = (4, 5),
-                 stream=None):
+                 orthogonalisation: int = 1, cycle: str = "V", stream=None):
         L = lib()
         self.dim, self.n = dim, n
         self.side, self.bc = side, bc
@@ -194,7 +200,8 @@ class Problem:
         pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
         geo = Geometry(geom_kind, side, bc, len(geom_params), pa)
         o = make_options(beta_plus, beta_minus, rtol, max_iters, restart, nu_pre, nu_post, coarsest_n, precision,
-                         ls_axes, use_graph, tail_nodes, fused_smoothing, colour_split, order)
+                         ls_axes, use_graph, tail_nodes, fused_smoothing, colour_split, order,
+                         orthogonalisation, cycle)
         self._h = ctypes.c_void_p()
         # default: the library orders its own stream after the legacy default stream
         s = 0 if stream is None else stream
@@ -286,6 +293,23 @@ class Problem:
         z = torch.empty_like(v)
         _check(lib().iim_vcycle(self._h, _ptr(v), _ptr(z)))
         return z
+
+    def gradient(self, u):
+        """grad u at the unknowns (order-n central first derivative over the
+        extended function), shape (dim, (n+1)^dim) on the device, NaN
+        elsewhere; u a full-grid device array (a solution of this problem)."""
+        import torch
+        g = torch.empty((self.dim, u.numel()), dtype=torch.float64, device=u.device)
+        _check(lib().iim_gradient(self._h, _ptr(u), _ptr(g)))
+        return g
+
+    def boundary_quantity(self, u):
+        """Per control point: du/dn (Dirichlet), u (Neumann) or du+/dn
+        (interface) from the fits' normal-derivative rows."""
+        import torch
+        q = torch.empty(max(int(self.info()["n_control_points"]), 1), dtype=torch.float64, device=u.device)
+        _check(lib().iim_boundary_quantity(self._h, _ptr(u), _ptr(q)))
+        return q[: int(self.info()["n_control_points"])]
 
     def level_op(self, level: int, op: int, in1, out):
         _check(lib().iim_level_op(self._h, level, op, _ptr(in1), _ptr(out)))
@@ -381,5 +405,7 @@ class Server:
 def from_workload(wl, precision: Optional[str] = None, **kw) -> Problem:
     """Problem for a workloads.Workload description."""
     kw.setdefault("order", tuple(getattr(wl, "order", (4, 5))))
+    kw.setdefault("orthogonalisation", int(getattr(wl, "orthogonalisation", 1)))
+    kw.setdefault("cycle", str(getattr(wl, "cycle", "V")))
     return Problem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus,
                    precision=precision or wl.precision, **kw)

@@ -31,3 +31,50 @@ def test_library_exports_every_symbol():
     L = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(L, n)]
     assert not missing, missing
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the Python binding mirrors has the header's size and field
+    offsets (a C program built from include/iim.h with the host compiler prints
+    them; nothing is loaded onto a GPU)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    from paper_2503_22455_amd import iim
+    mirrors = {"iim_grid": iim.Grid, "iim_geometry": iim.Geometry, "iim_options": iim.Options,
+               "iim_stats": iim.Stats, "iim_info": iim.Info, "iim_request": iim.Request,
+               "iim_result": iim.Result, "iim_server_stats": iim.ServerStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "iim.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    import ctypes as C
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_default_options():
+    """iim_default_options (a host-only call) fills the documented defaults."""
+    if not os.path.exists(LIB):
+        pytest.skip("libiim.so not built in this checkout")
+    from paper_2503_22455_amd import iim
+    o = iim.make_options()
+    assert (o.order_n, o.order_k, o.restart, o.nu_pre, o.nu_post, o.coarsest_n) == (4, 5, 10, 2, 2, 8)
+    assert o.rtol == 1e-10 and o.use_graph == 2 and o.colour_split == 1 and o.fused_smoothing == 1
+    assert o.orthogonalisation == 1

@@ -71,7 +71,7 @@ def test_ls_stencils(pair):
     for c in rng.choice(O.ncp, size=min(40, O.ncp), replace=False):
         for side in O.sides:
             idx, wts = G.ls_stencil(int(c), side)
-            st = O.stencil(int(c), side)
+            st = O.stencil_d(int(c), side)  # ghosts, then the normal derivative (every condition)
             assert list(idx) == list(st.idx), (name, c, side)
             scale = np.abs(st.S).max()
             assert np.abs(wts - st.S).max() <= TOL_LS.get(name, 1e-12) * scale, (
@@ -173,3 +173,32 @@ def test_solve_matches_direct(pair):
     assert np.abs(uu - ud).max() <= 1e-12 * np.abs(ud).max(), np.abs(uu - ud).max() / np.abs(ud).max()
     # non-unknown nodes are NaN
     assert np.isnan(u.cpu().numpy()[O.lab_flat == 0]).all()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "circle-neu-ext", "star128-beta", "sphere24", "spheres32-neu"])
+def test_wcycle_fp64(name):
+    """The W-cycle preconditioner (cycle index 2) against the oracle's W-cycle,
+    and the FP64 solve it preconditions against the oracle's direct solve."""
+    wl = CASES[name]()
+    O = oracle_for(wl)
+    G = gpu_for(wl, precision="fp64", rtol=1e-14, cycle="W")
+    H = Hierarchy(O, gamma=2)
+    rng = np.random.default_rng(4)
+    v = np.zeros(O.lab_flat.size)
+    v[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    z = G.vcycle(torch.tensor(v, device="cuda")).cpu().numpy()[O.unknowns]
+    zo = H.precondition(v[O.unknowns])
+    assert np.abs(z - zo).max() <= 1e-12 * np.abs(zo).max(), np.abs(z - zo).max() / np.abs(zo).max()
+    L, LG = O.assemble()
+    cpd, box, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, box)
+    G.set_rhs(f)
+    u, hist, st = G.solve()
+    assert st["status"] == 0, st
+    ug = O.data_vector(cpd, wl.box_data())
+    b = O.rhs(wl.rhs(O.labels), ug)
+    uu = u.cpu().numpy()[O.unknowns]
+    assert np.linalg.norm(b - L @ uu) <= 1e-13 * np.linalg.norm(b)
+    ud = O.direct_solve(b)
+    assert np.abs(uu - ud).max() <= 1e-12 * np.abs(ud).max(), np.abs(uu - ud).max() / np.abs(ud).max()
+    G.close()

@@ -55,6 +55,8 @@ class Workload:
     precision: str = "fp64"       # fp64 | mixed32 | mixed16
     note: str = ""
     order: Tuple[int, int] = (4, 5)  # (n, k): the (4,5) scheme, or (6,7) in 2D
+    orthogonalisation: int = 1       # solver's Arnoldi step: 1 CGS + second pass where needed, 0 CGS2
+    cycle: str = "V"                 # preconditioner's multigrid cycle: V or W
 
     # -- data sampling (pure evaluation of the manufactured solution) ----------
     def cp_data(self, xyz: np.ndarray, normal: np.ndarray) -> np.ndarray:
