@@ -48,7 +48,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, KiB per dispatch; `python3 bench.py --probe-kernel <id>`), each
 # scaled by what the same counter reads, in the same run, for a plain copy of
 # 2^26 doubles (512 MiB each way: FETCH_SIZE reads about 262160 KiB, WRITE_SIZE
-# 524288 KiB).
+# 524288 KiB; the median of the three copies, the first finding part of its
+# source in the caches).
 # Keyed by workload and kernel id; valid only while the kernel's source text
 # hashes to `sha` (otherwise the roofline reports traffic null).
 TRAFFIC = {
@@ -56,10 +57,14 @@ TRAFFIC = {
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/ops.hip",
                   "begin": "constexpr int FTX = 32, FTY = 32, FHALO = 6;",
                   "end": "bool run_down_fused(const LevelDev& F", "sha": "ccba1c890744fce2"},
-    ("cfg2", 5): {"fetch_kib": 28913.6875, "fetch_scale": 524288.0 / 262158.9, "write_kib": 8432.09375,
+    ("cfg4", 5): {"fetch_kib": 1584937.0909, "fetch_scale": 524288.0 / 262156.0, "write_kib": 453031.2017,
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/blas.hip",
                   "begin": "__global__ void __launch_bounds__(RED_THREADS) k_update_dot(",
-                  "end": "void run_update_dot_stage1(", "sha": "b443d0108009ce3b"},
+                  "end": "void run_update_dot_stage1(", "sha": "bfaf805153a63909"},
+    ("cfg3", 1): {"fetch_kib": 319979.3920, "fetch_scale": 524288.0 / 262156.0, "write_kib": 1744.9432,
+                  "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/ops.hip",
+                  "begin": "__global__ void __launch_bounds__(256) k_ghosts(",
+                  "end": "static void launch_ghosts(", "sha": "758c691f69cf7445"},
 }
 
 
