@@ -301,7 +301,7 @@ def main():
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, help="override the workload's precision")
     ap.add_argument("--order", type=int, default=4, choices=(4, 6),
-                    help="interior order of the discretisation: 4 = the (4,5) scheme, 6 = (6,7) (2D workloads)")
+                    help="interior order of the discretisation: 4 = the (4,5) scheme, 6 = the (6,7) scheme")
     ap.add_argument("--orthogonalisation", type=int, default=1, choices=(0, 1),
                     help="Arnoldi step: 1 one Gram-Schmidt pass, a second only where needed; 0 two passes")
     ap.add_argument("--cycle", default="V", choices=("V", "W"), help="the preconditioner's multigrid cycle")
@@ -334,9 +334,6 @@ def main():
     wl = WORKLOADS[args.workload]()
     prec = args.precision or wl.precision
     if args.order == 6:
-        if wl.dim != 2:
-            print("bench.py: the (6,7) scheme is built for 2D workloads", file=sys.stderr)
-            sys.exit(2)
         wl.order = (6, 7)
     wl.orthogonalisation = args.orthogonalisation
     wl.cycle = args.cycle

@@ -95,8 +95,9 @@ typedef struct iim_geometry {
 } iim_geometry;
 
 typedef struct iim_options {
-    int32_t order_n;    /* interior order n: 4 (default), or 6 in 2D (Sec. 2.1: the (6,7) scheme) */
-    int32_t order_k;    /* least-squares order k, n + 1: 5 (default) or 7 with n = 6 */
+    int32_t order_n;    /* interior order n: 4 (default), or 6 (Sec. 2.1: the (6,7) scheme) */
+    int32_t order_k;    /* least-squares order k, n + 1: 5 (default) or 7 with n = 6; in 3D
+                           the degree-6 fits (84 columns) run on the global-memory QR path */
     double beta_plus;   /* coefficient in Omega^+ */
     double beta_minus;  /* coefficient in Omega^- (interfaces) */
     double rtol;        /* stop when ||b - L u||_2 / ||b||_2 <= rtol */

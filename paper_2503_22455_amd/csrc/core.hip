@@ -1125,7 +1125,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     const int ns = geo.side == IIM_SIDE_INTERFACE ? 2 : 1;
     const int w = o.order_n / 2;
     const int nrows = w + 1;
-    const double mset = dim == 2 ? (o.order_k == 7 ? 112.0 : 56.0) : 264.0;
+    const double mset = dim == 2 ? (o.order_k == 7 ? 112.0 : 56.0) : (o.order_k == 7 ? 700.0 : 264.0);
     const double ncs = ncp * ns;
     bytes += (int64_t)(ncp * (4 + 4 + 24 + 24 + 8 + 16) + ncs * (4 + 4 + 8 * w * 2 + 8 * nrows + 4 + 4 + 1 + 8));
     bytes += (int64_t)(ncs * mset * (4 + 8 * nrows + (geo.bc == IIM_BC_NEUMANN ? 8 * w : 0)));
@@ -1301,8 +1301,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     if (g->n < 8 || g->n > 16384) throw Error(IIM_E_INVALID_ARG, "n out of range");
     if (!(g->hi > g->lo)) throw Error(IIM_E_INVALID_ARG, "empty domain");
     const bool o45 = o.order_n == 4 && o.order_k == 5, o67 = o.order_n == 6 && o.order_k == 7;
-    if (!o45 && !(o67 && g->dim == 2))
-        throw Error(IIM_E_INVALID_ARG, "built discretisations: (4,5) in 2D and 3D, (6,7) in 2D");
+    if (!o45 && !o67) throw Error(IIM_E_INVALID_ARG, "built discretisations: (4,5) and (6,7)");
     if (o.restart < 1 || o.restart > 11) throw Error(IIM_E_INVALID_ARG, "restart must be in [1, 11]");
     if (o.use_graph < 0 || o.use_graph > 2) throw Error(IIM_E_INVALID_ARG, "use_graph must be 0, 1 or 2");
     if (o.orthogonalisation < 0 || o.orthogonalisation > 1)

@@ -369,6 +369,20 @@ void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi,
     int3 hi = make_int3(core_hi[0], core_hi[1], core_hi[2]);
     int nx = hi.x - lo.x + 1, ny = hi.y - lo.y + 1, nz = hi.z - lo.z + 1;
     if (nx <= 0 || ny <= 0 || nz <= 0) return;
+    if (dim == 3 && w == 3) {
+        // the sixth-order scheme in 3D: one thread per node, irregular nodes
+        // inside the same kernel (the z-march below is written for a 2-node reach)
+        if (part == 2) return;
+        for (int d = 0; d < 3; ++d)
+            if (core_lo[d] - 3 < b.lo[d] || core_hi[d] + 3 > b.lo[d] + b.dims[d] - 1)
+                throw Error(IIM_E_INTERNAL, "apply: storage box lacks the 3-node margin");
+        const dim3 blk(64, 4, 1);
+        const dim3 grd(cdiv(nx, 64), cdiv(ny, 4), nz);
+        hipLaunchKernelGGL((k_ho_apply<3, 3>), grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval,
+                           inv_h2, beta_plus, beta_minus, x, y, with_data);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
     if (dim == 3) {
         // the z-march reads planes zs-2 .. ze+2 and columns/rows up to 2 past the
         // core: the storage box has that margin
@@ -469,6 +483,9 @@ void run_ho_gradient(int dim, const Box& b, const int* core_lo, const int* core_
     const dim3 grd(cdiv(nx, 64), cdiv(ny, 4), nz);
     if (dim == 3 && w == 2)
         hipLaunchKernelGGL((k_ho_gradient<3, 2>), grd, blk, 0, s, b, lo, hi, n, labels, irr_index, slots, ghost,
+                           boxval, inv_h, x, grad, total);
+    else if (dim == 3 && w == 3)
+        hipLaunchKernelGGL((k_ho_gradient<3, 3>), grd, blk, 0, s, b, lo, hi, n, labels, irr_index, slots, ghost,
                            boxval, inv_h, x, grad, total);
     else if (dim == 2 && w == 2)
         hipLaunchKernelGGL((k_ho_gradient<2, 2>), grd, blk, 0, s, b, lo, hi, n, labels, irr_index, slots, ghost,

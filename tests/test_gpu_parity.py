@@ -29,9 +29,14 @@ CASES = {
                                             W.union_params(W.small_circles_union_2d()), W.SIDE_EXTERIOR,
                                             W.BC_NEUMANN, 1.5, 1.0, exact=W.ms_sin2pi_cos2pi()),
     "star128-o6": lambda: W.cfg2_star(128, beta_plus=0.5, beta_minus=1.0),
+    # the (6,7) scheme in 3D: Dirichlet inside a sphere; Neumann outside one, with box faces
+    "sphere24-o6": lambda: W.cfg3_sphere(24, precision="fp64"),
+    "sphere-neu-ext24-o6": lambda: W.Workload("neu3", 3, 24, W.GEOM_SPHERE, [0.02, -0.01, 0.03, 0.45],
+                                              W.SIDE_EXTERIOR, W.BC_NEUMANN, 1.0, 1.0, exact=W.ms_cos_sinh()),
 }
 OPTIONS = {"spheres32-neu-deep": dict(tail_nodes=-1), "cfg1-o6": dict(order=(6, 7)),
-           "circle-neu-ext-o6": dict(order=(6, 7)), "star128-o6": dict(order=(6, 7))}
+           "circle-neu-ext-o6": dict(order=(6, 7)), "star128-o6": dict(order=(6, 7)),
+           "sphere24-o6": dict(order=(6, 7)), "sphere-neu-ext24-o6": dict(order=(6, 7))}
 ORACLE_OPTIONS = {k: dict(order_n=v["order"][0], order_k=v["order"][1]) for k, v in OPTIONS.items() if "order" in v}
 # Tolerances of the fits and the apply.  The degree-6 least-squares matrix of the
 # (6,7) scheme (monomials up to xi^6, |xi| <= 7) is far worse conditioned than

@@ -15,7 +15,8 @@ torch = pytest.importorskip("torch")
 # their largest weight; ghost values are sums of ~50-100 such terms and enter
 # the gradient divided by h.
 TOL = {k: 1e-9 for k in ORACLE_OPTIONS}
-POST_CASES = ["cfg1", "circle-neu-ext", "star128-beta", "sphere24", "spheres32-neu", "cfg1-o6", "star128-o6"]
+POST_CASES = ["cfg1", "circle-neu-ext", "star128-beta", "sphere24", "spheres32-neu", "cfg1-o6", "star128-o6",
+              "sphere24-o6"]
 
 
 @pytest.mark.parametrize("name", POST_CASES)

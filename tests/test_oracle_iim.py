@@ -196,3 +196,32 @@ def test_neumann_order6():
                            exact=_sol2d())) for n in ns]
     orders = [np.log(es[i] / es[i + 1]) / np.log(ns[i + 1] / ns[i]) for i in range(2)]
     assert orders[-1] > 5.5 and min(orders) > 5.2, (orders, es)
+
+
+# ---- sixth order in 3D: 84-column fits, half-width 3 -----------------------------------
+
+PATCH_3D_O6 = [
+    ("dirichlet-3d", 3, 16, W.GEOM_SPHERE, [0.01, 0.02, -0.01, 0.6], 0, 0, 1.0, 1.0),
+    ("neumann-3d-exterior-box", 3, 24, W.GEOM_SPHERE, [0.02, -0.01, 0.03, 0.45], 1, 1, 1.0, 1.0),
+]
+
+
+@pytest.mark.parametrize("case", PATCH_3D_O6, ids=[c[0] for c in PATCH_3D_O6])
+def test_patch_order6_3d(case):
+    """3D (6,7): degree-6 data (84 monomials) satisfy the discrete equations to
+    round-off, through the 84-column fits, the 19-point stencil and, outside
+    the sphere, the degree-6 box extrapolation."""
+    _patch6(case)
+
+
+def _patch6(case):
+    name, dim, n, kind, params, side, bc, bp, bm = case
+    rng = np.random.default_rng(7)
+    ms = W.ms_polynomial({e: rng.uniform(-1, 1) for e in monomial_exponents(dim, 6)}, dim)
+    wl = W.Workload(name, dim, n, kind, params, side, bc, bp, bm, exact=ms)
+    P, L, LG, ug, b = _setup(wl, order_n=6, order_k=7)
+    uex = P.from_full(np.nan_to_num(wl.exact_solution(P.labels)))
+    res = L @ uex - b
+    scale = abs(L).max() * np.abs(uex).max()
+    assert np.abs(res).max() <= 1e-10 * scale, np.abs(res).max() / scale
+
