@@ -68,6 +68,7 @@ struct Level {
 };
 
 constexpr int64_t TAIL_MAX_NODES = 4096;  // levels handled by the one-workgroup tail kernel
+constexpr int64_t LS_SCRATCH_WAVES = 2048;  // waves of the global-memory least-squares path
 constexpr int HCOL = 3 * 64;               // doubles of one Hessenberg column record (two CGS passes + norm)
 constexpr int HPIN_DOUBLES = 12 * HCOL;    // one record per inner iteration (restart <= 11)
 

@@ -378,7 +378,10 @@ void Problem::setup() {
         double* scratch = nullptr;
         int64_t waves = 0;
         if (!big.empty()) {  // oversized sets: Householder on a per-wave global scratch slab
-            waves = std::min<int64_t>((int64_t)big.size(), 256);
+            // each wave works through its fits one global-memory round trip at a
+            // time: eight waves per CU hide those latencies (3D degree-6 fits,
+            // all on this path, take 1.1 GB of slabs)
+            waves = std::min<int64_t>((int64_t)big.size(), LS_SCRATCH_WAVES);
             scratch = (double*)mem.alloc((size_t)waves * (p + 4) * P.mcap * sizeof(double));
             d_list = (int32_t*)mem.alloc(big.size() * sizeof(int32_t));
             IIM_HIP(hipMemcpyAsync(d_list, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
@@ -1131,10 +1134,10 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     bytes += (int64_t)(ncs * mset * (4 + 8 * nrows + (geo.bc == IIM_BC_NEUMANN ? 8 * w : 0)));
     // staging of the fits: a fixed segment of 64 * (rows per lane) entries per fit
     bytes += (int64_t)(ncs * (dim == 2 ? 128 : 256) * (4 + 8 * nrows));
-    // scratch of oversized least-squares sets (one slab per wave, 256 waves at most)
+    // scratch of oversized least-squares sets (one slab per wave, LS_SCRATCH_WAVES at most)
     const int K = o.order_k;
     const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
-    bytes += (int64_t)std::min(256.0, ncs) * (p + 4) * (dim == 2 ? 192 : 768) * 8;
+    bytes += (int64_t)std::min((double)LS_SCRATCH_WAVES, ncs) * (p + 4) * (dim == 2 ? 192 : 768) * 8;
     // irregular records: high-order slots (at most w nodes per crossing and side),
     // Shortley-Weller rows in FP64 and FP32 (at most one node per crossing, all levels)
     bytes += (int64_t)(ncs * (w * (2 * dim + 1) * 4 + 2 * (1 + 2 * dim) * 12));
