@@ -15,14 +15,16 @@
  * The normal n at a control point points from Omega^- into Omega^+ (into the
  * solved region for boundary problems).
  *
- * The discretisation is the (n, k) = (4, 5) immersed-interface method
- * (Sec. 2.1-2.3): dimension-split 4th-order central differences with
- * least-squares ghost values at every crossing of a grid line with Gamma.
- * The system L_Omega u + L_Gamma u_Gamma = f is solved matrix-free by
- * right-preconditioned FGMRES(restart) (Sec. 4.1) with one Shortley-Weller
- * multigrid V-cycle as preconditioner (Sec. 3.1, 3.3).  The operator, the
- * Krylov basis, dot products and least-squares fits are FP64; the V-cycle runs
- * in FP64, FP32, or FP32 with FP16 storage of its iterates.
+ * The discretisation is the (n, k) = (4, 5) immersed-interface method, or the
+ * (6, 7) one (Sec. 2.1-2.3): dimension-split central differences of order n
+ * with least-squares ghost values (degree k - 1) at every crossing of a grid
+ * line with Gamma.  The system L_Omega u + L_Gamma u_Gamma = f is solved
+ * matrix-free by right-preconditioned FGMRES(restart) (Sec. 4.1) with one
+ * Shortley-Weller multigrid cycle (V, or W) as preconditioner (Sec. 3.1,
+ * 3.3).  The operator, the Krylov basis, dot products and least-squares fits
+ * are FP64; the cycle runs in FP64, FP32, or FP32 with FP16 storage of its
+ * iterates.  A solution can be post-processed into its gradient and the
+ * boundary quantity its condition leaves open (Sec. 2.4).
  *
  * Conventions for every call:
  *   - return 0 on success, IIM_NOT_CONVERGED (> 0) when a solve stopped at
@@ -233,13 +235,15 @@ int iim_gradient(iim_problem* p, const double* u, double* grad);
  * iim_control_points): the boundary quantity the condition leaves open, by the
  * normal-derivative row of each fit: du/dn for Dirichlet, u for Neumann
  * (the closure), du+/dn for interfaces (u+ at x_c from the closure); n is the
- * control point's unit normal from Omega^- into Omega^+. */
+ * control point's unit normal from Omega^- into Omega^+.  Dirichlet fits carry
+ * no such row: the first call fits every control point once more with it
+ * (device memory then held by the handle). */
 int iim_boundary_quantity(iim_problem* p, const double* u, double* q);
 
 /* Least-squares stencil of control point cp on side (1 = Omega^+, 2 = Omega^-):
  * m grid points (full-grid flat indices in idx) and the (m+1) x r weights in
  * weights[row * r + col] (row 0 multiplies u(x_c); columns: ghosts 1..w, then
- * the normal derivative, r = w + 1).  Host buffers of capacity cap rows;
+ * the normal derivative for Neumann and interface problems).  Host buffers of capacity cap rows;
  * returns the sizes in *m and *r. */
 int iim_ls_stencil(const iim_problem* p, int64_t cp, int32_t side, int32_t* m, int32_t* r,
                    int64_t* idx, double* weights, int32_t cap);

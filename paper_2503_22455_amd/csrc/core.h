@@ -93,6 +93,13 @@ struct Problem {
     int32_t* ls_idx = nullptr;
     double* ls_S = nullptr;   // [nrows][nnz] raw weights of the grid points
     double* ls_Sc = nullptr;  // [ncs][nrows] weights of u(x_c)
+    // fits with the normal-derivative row, made on first use when the setup's
+    // fits lack it (Dirichlet): same layout with w + 1 rows
+    int64_t* nd_ptr = nullptr;
+    int32_t* nd_idx = nullptr;
+    double* nd_S = nullptr;
+    double* nd_Sc = nullptr;
+    int64_t nd_nnz = 0;
     double* W_apply = nullptr;
     double* dcoef = nullptr;
     double* ghost = nullptr;
@@ -128,6 +135,9 @@ struct Problem {
     double t_setup_ms = 0.0;
 
     void setup();
+    void fit_stencils(int nr, int* d_err, int64_t*& ptr_out, int32_t*& idx_out, double*& S_out, double*& Sc_out,
+                      std::vector<int64_t>& hptr, int64_t& nz);
+    void ensure_normal_rows();
     LevelSet level_set() const;
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;

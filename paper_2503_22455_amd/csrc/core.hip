@@ -219,10 +219,112 @@ static void raise_setup_error(int h, const char* what) {
     throw Error(IIM_E_GEOMETRY_UNRESOLVED, m);
 }
 
+// Least-squares fits of every control point and side with nr rows (the w ghost
+// functionals, then the normal derivative at x_c when nr = w + 1): sizes and
+// growth on the register path, oversized sets on the global-memory path, then
+// the weights, compacted.  Outputs: ptr_out [ncs + 1], idx_out [nnz], S_out
+// [nr][nnz], Sc_out [ncs][nr] and the host copy of the pointers; d_err: the
+// device error word.  The pass is deterministic: a second call returns the
+// same sets.
+void Problem::fit_stencils(int nr, int* d_err, int64_t*& ptr_out, int32_t*& idx_out, double*& S_out,
+                           double*& Sc_out, std::vector<int64_t>& hptr, int64_t& nz) {
+    const Level& L0 = levels[0];
+    const int64_t ncs = cp.ncp * nsides;
+    int err_bits = 0;
+    auto read_err = [&]() {
+        IIM_HIP(hipMemcpyAsync(&err_bits, d_err, sizeof(int), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+    };
+    LSParams P;
+    P.dim = dim;
+    P.order_k = opt.order_k;
+    P.w = w;
+    P.nrows = nr;
+    P.nsides = nsides;
+    P.a0 = opt.ls_axis_t > 0 ? opt.ls_axis_t : (double)opt.order_k;
+    P.b0 = opt.ls_axis_n > 0 ? opt.ls_axis_n : opt.order_k - 0.5;
+    P.max_grow = 6;
+    P.mcap = dim == 2 ? 192 : 768;
+    const int K = opt.order_k;
+    const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
+    const int64_t ncs1 = std::max<int64_t>(ncs, 1);
+    int32_t* d_mg = (int32_t*)mem.alloc(2 * ncs1 * sizeof(int32_t));  // sizes, then growth
+    int32_t* d_m = d_mg;
+    int32_t* d_grow = d_mg + ncs1;
+    uint8_t* d_route = (uint8_t*)mem.alloc(ncs1);
+    IIM_HIP(hipMemsetAsync(d_route, 0, ncs1, stream));
+    // one pass over the register path: sizes, growth and the weights, the
+    // weights into fixed segments of a staging area (compacted below)
+    const int seg = ls_segment(dim);
+    int32_t* st_idx = (int32_t*)mem.alloc(ncs1 * seg * sizeof(int32_t));
+    double* st_S = (double*)mem.alloc((size_t)nr * ncs1 * seg * sizeof(double));
+    Sc_out = (double*)mem.alloc(ncs1 * nr * sizeof(double));
+    run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, st_idx, st_S, Sc_out, nullptr, 0, d_err,
+           nullptr, 0, d_route, stream);
+    std::vector<int32_t> hmg(2 * ncs1);
+    IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, 2 * ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    read_err();
+    raise_setup_error(err_bits, "control points and least-squares sizes");
+    std::vector<int32_t> big;
+    for (int64_t i = 0; i < ncs; ++i)
+        if (hmg[ncs1 + i] == -3) big.push_back((int32_t)i);
+    int32_t* d_list = nullptr;
+    double* scratch = nullptr;
+    int64_t waves = 0;
+    if (!big.empty()) {  // oversized sets: Householder on a per-wave global scratch slab
+        // each wave works through its fits one global-memory round trip at a
+        // time: eight waves per CU hide those latencies (3D degree-6 fits,
+        // all on this path, take 1.1 GB of slabs)
+        waves = std::min<int64_t>((int64_t)big.size(), LS_SCRATCH_WAVES);
+        scratch = (double*)mem.alloc((size_t)waves * (p + 4) * P.mcap * sizeof(double));
+        d_list = (int32_t*)mem.alloc(big.size() * sizeof(int32_t));
+        IIM_HIP(hipMemcpyAsync(d_list, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, scratch, waves,
+               d_err, d_list, (int64_t)big.size(), d_route, stream);
+        IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        read_err();
+        raise_setup_error(err_bits, "least-squares sizes (large sets)");
+    }
+    hptr.assign(ncs + 1, 0);
+    for (int64_t i = 0; i < ncs; ++i) hptr[i + 1] = hptr[i] + hmg[i];
+    nz = hptr[ncs];
+    ptr_out = (int64_t*)mem.alloc((ncs + 1) * sizeof(int64_t));
+    IIM_HIP(hipMemcpyAsync(ptr_out, hptr.data(), (ncs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    idx_out = (int32_t*)mem.alloc(std::max<int64_t>(nz, 1) * sizeof(int32_t));
+    S_out = (double*)mem.alloc(std::max<int64_t>(nr * nz, 1) * sizeof(double));
+    run_ls_compact(ncs, seg, nr, d_m, d_route, ptr_out, st_idx, st_S, idx_out, S_out, stream);
+    mem.release(st_idx);
+    mem.release(st_S);
+    if (!big.empty())
+        run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ptr_out, idx_out, S_out, Sc_out, scratch, waves, d_err,
+               d_list, (int64_t)big.size(), d_route, stream);
+    if (scratch) mem.release(scratch);
+    if (d_list) mem.release(d_list);
+    mem.release(d_mg);
+    mem.release(d_route);
+}
+
 // Setup on the device.  The stages are batched so that the host waits for the
 // device only where a size or an error decides what comes next (six waits):
 // level bounding boxes; control-point counts; least-squares set sizes;
 // irregular-node counts of every level; the coarsest level's rows; the end.
+// The normal-derivative row of every fit for problems whose setup fitted only
+// the ghost rows (Dirichlet): the fits once more with w + 1 rows, kept for
+// later calls.  The sets are those of the setup (the pass is deterministic).
+void Problem::ensure_normal_rows() {
+    if (nrows == w + 1 || nd_S) return;
+    int* d_err = (int*)mem.alloc(sizeof(int64_t));
+    IIM_HIP(hipMemsetAsync(d_err, 0, sizeof(int64_t), stream));
+    std::vector<int64_t> hp;
+    fit_stencils(w + 1, d_err, nd_ptr, nd_idx, nd_S, nd_Sc, hp, nd_nnz);
+    int err = 0;
+    IIM_HIP(hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipStreamSynchronize(stream));
+    mem.release(d_err);
+    raise_setup_error(err, "least-squares fits with the normal-derivative row");
+    if (hp != h_ptr) throw Error(IIM_E_INTERNAL, "normal-derivative fits: the sets differ from the setup's");
+}
+
 void Problem::setup() {
     const double t0 = now_ms();
     w = opt.order_n / 2;
@@ -335,79 +437,13 @@ void Problem::setup() {
 
     // ---- least-squares stencils (FP64): sizes  [wait 3], then the fits
     const int64_t ncs = cp.ncp * nsides;
-    // rows: the w ghost functionals, then the normal derivative at x_c (the
-    // Neumann and interface closures use it; for Dirichlet problems it serves
-    // the boundary-quantity post-processing only, and the apply reads rows
-    // 0..w-1, which sit at the same addresses)
-    nrows = w + 1;
+    // rows: the w ghost functionals, then the normal derivative at x_c, which the
+    // Neumann and interface closures use; Dirichlet problems fit it only when the
+    // boundary-quantity post-processing first asks (fit_stencils once more)
+    nrows = w + ((bc == IIM_BC_DIRICHLET) ? 0 : 1);
     {
-        LSParams P;
-        P.dim = dim;
-        P.order_k = opt.order_k;
-        P.w = w;
-        P.nrows = nrows;
-        P.nsides = nsides;
-        P.a0 = opt.ls_axis_t > 0 ? opt.ls_axis_t : (double)opt.order_k;
-        P.b0 = opt.ls_axis_n > 0 ? opt.ls_axis_n : opt.order_k - 0.5;
-        P.max_grow = 6;
-        P.mcap = dim == 2 ? 192 : 768;
-        const int K = opt.order_k;
-        const int p = dim == 2 ? K * (K + 1) / 2 : K * (K + 1) * (K + 2) / 6;
+        fit_stencils(nrows, d_err, ls_ptr, ls_idx, ls_S, ls_Sc, h_ptr, nnz);
         const int64_t ncs1 = std::max<int64_t>(ncs, 1);
-        int32_t* d_mg = (int32_t*)mem.alloc(2 * ncs1 * sizeof(int32_t));  // sizes, then growth
-        int32_t* d_m = d_mg;
-        int32_t* d_grow = d_mg + ncs1;
-        uint8_t* d_route = (uint8_t*)mem.alloc(ncs1);
-        IIM_HIP(hipMemsetAsync(d_route, 0, ncs1, stream));
-        // one pass over the register path: sizes, growth and the weights, the
-        // weights into fixed segments of a staging area (compacted below)
-        const int seg = ls_segment(dim);
-        int32_t* st_idx = (int32_t*)mem.alloc(ncs1 * seg * sizeof(int32_t));
-        double* st_S = (double*)mem.alloc((size_t)nrows * ncs1 * seg * sizeof(double));
-        ls_Sc = (double*)mem.alloc(ncs1 * nrows * sizeof(double));
-        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, st_idx, st_S, ls_Sc, nullptr, 0, d_err,
-               nullptr, 0, d_route, stream);
-        std::vector<int32_t> hmg(2 * ncs1);
-        IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, 2 * ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        read_sc(1);
-        raise_setup_error(err_bits(), "control points and least-squares sizes");
-        std::vector<int32_t> big;
-        for (int64_t i = 0; i < ncs; ++i)
-            if (hmg[ncs1 + i] == -3) big.push_back((int32_t)i);
-        int32_t* d_list = nullptr;
-        double* scratch = nullptr;
-        int64_t waves = 0;
-        if (!big.empty()) {  // oversized sets: Householder on a per-wave global scratch slab
-            // each wave works through its fits one global-memory round trip at a
-            // time: eight waves per CU hide those latencies (3D degree-6 fits,
-            // all on this path, take 1.1 GB of slabs)
-            waves = std::min<int64_t>((int64_t)big.size(), LS_SCRATCH_WAVES);
-            scratch = (double*)mem.alloc((size_t)waves * (p + 4) * P.mcap * sizeof(double));
-            d_list = (int32_t*)mem.alloc(big.size() * sizeof(int32_t));
-            IIM_HIP(hipMemcpyAsync(d_list, big.data(), big.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-            run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, nullptr, nullptr, nullptr, scratch, waves,
-                   d_err, d_list, (int64_t)big.size(), d_route, stream);
-            IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-            read_sc(1);
-            raise_setup_error(err_bits(), "least-squares sizes (large sets)");
-        }
-        h_ptr.assign(ncs + 1, 0);
-        for (int64_t i = 0; i < ncs; ++i) h_ptr[i + 1] = h_ptr[i] + hmg[i];
-        nnz = h_ptr[ncs];
-        ls_ptr = (int64_t*)mem.alloc((ncs + 1) * sizeof(int64_t));
-        IIM_HIP(hipMemcpyAsync(ls_ptr, h_ptr.data(), (ncs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-        ls_idx = (int32_t*)mem.alloc(std::max<int64_t>(nnz, 1) * sizeof(int32_t));
-        ls_S = (double*)mem.alloc(std::max<int64_t>(nrows * nnz, 1) * sizeof(double));
-        run_ls_compact(ncs, seg, nrows, d_m, d_route, ls_ptr, st_idx, st_S, ls_idx, ls_S, stream);
-        mem.release(st_idx);
-        mem.release(st_S);
-        if (!big.empty())
-            run_ls(L0.geom, box, L0.labels, cp, P, 1, d_m, d_grow, ls_ptr, ls_idx, ls_S, ls_Sc, scratch, waves, d_err,
-                   d_list, (int64_t)big.size(), d_route, stream);
-        if (scratch) mem.release(scratch);
-        if (d_list) mem.release(d_list);
-        mem.release(d_mg);
-        mem.release(d_route);
         // apply weights
         dcoef = (double*)mem.alloc(ncs1 * w * sizeof(double));
         if (bc == IIM_BC_NEUMANN) {
@@ -415,7 +451,7 @@ void Problem::setup() {
             nrows_apply = w;
         } else {
             W_apply = ls_S;
-            nrows_apply = bc == IIM_BC_DIRICHLET ? w : nrows;
+            nrows_apply = nrows;
         }
         run_apply_weights(bc, ls_ptr, ncs, w, nrows, ls_S, ls_Sc, opt.beta_plus, nnz,
                           bc == IIM_BC_NEUMANN ? W_apply : nullptr, dcoef, stream);
@@ -1127,7 +1163,7 @@ int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_opt
     ncp = 1.15 * ncp + 64.0;
     const int ns = geo.side == IIM_SIDE_INTERFACE ? 2 : 1;
     const int w = o.order_n / 2;
-    const int nrows = w + 1;
+    const int nrows = w + (geo.bc == IIM_BC_DIRICHLET ? 0 : 1);
     const double mset = dim == 2 ? (o.order_k == 7 ? 112.0 : 56.0) : (o.order_k == 7 ? 700.0 : 264.0);
     const double ncs = ncp * ns;
     bytes += (int64_t)(ncp * (4 + 4 + 24 + 24 + 8 + 16) + ncs * (4 + 4 + 8 * w * 2 + 8 * nrows + 4 + 4 + 1 + 8));
@@ -1624,18 +1660,20 @@ int iim_boundary_quantity(iim_problem* h, const double* u, double* q) {
     ABI_TRY({
         if (!h || !u || !q) throw Error(IIM_E_INVALID_ARG, "null argument");
         Problem& p = *h->p;
+        p.ensure_normal_rows();
         run_full_to_box(p.dim, p.grid.n, p.box, u, p.rk, p.levels[0].labels, 1, p.stream);
         BQDev B;
         B.bc = p.bc;
         B.nsides = p.nsides;
         B.w = p.w;
-        B.nrows = p.nrows;
+        B.nrows = p.w + 1;
         B.beta_plus = p.opt.beta_plus;
         B.beta_minus = p.opt.beta_minus;
-        B.ptr = p.ls_ptr;
-        B.idx = p.ls_idx;
-        B.Sd = p.ls_S + (size_t)p.w * p.nnz;
-        B.Sc = p.ls_Sc;
+        const bool own = p.nrows == p.w + 1;  // the setup's fits already carry the row
+        B.ptr = own ? p.ls_ptr : p.nd_ptr;
+        B.idx = own ? p.ls_idx : p.nd_idx;
+        B.Sd = own ? p.ls_S + (size_t)p.w * p.nnz : p.nd_S + (size_t)p.w * p.nd_nnz;
+        B.Sc = own ? p.ls_Sc : p.nd_Sc;
         B.ncp = p.cp.ncp;
         run_boundary_quantity(B, p.rk, p.cpdata, q, p.stream);
         IIM_HIP(hipStreamSynchronize(p.stream));

@@ -76,7 +76,7 @@ def test_ls_stencils(pair):
     for c in rng.choice(O.ncp, size=min(40, O.ncp), replace=False):
         for side in O.sides:
             idx, wts = G.ls_stencil(int(c), side)
-            st = O.stencil_d(int(c), side)  # ghosts, then the normal derivative (every condition)
+            st = O.stencil(int(c), side)  # ghosts, then the normal derivative (Neumann, interface)
             assert list(idx) == list(st.idx), (name, c, side)
             scale = np.abs(st.S).max()
             assert np.abs(wts - st.S).max() <= TOL_LS.get(name, 1e-12) * scale, (
