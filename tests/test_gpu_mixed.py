@@ -122,9 +122,24 @@ def test_error_paths():
     assert e.value.code == -1
     with pytest.raises(iim.IIMError):
         iim.Problem(2, 64, W.GEOM_SPHERE, [0.0, 0.0, 0.5], W.SIDE_INTERIOR, W.BC_DIRICHLET, restart=40)
-    # the library keeps working after errors
+    with pytest.raises(iim.IIMError) as e:
+        iim.Problem(2, 64, W.GEOM_SPHERE, [0.0, 0.0, 0.5], W.SIDE_INTERIOR, W.BC_DIRICHLET, orthogonalisation=2)
+    assert e.value.code == -1
+    # an out-of-range cycle index through the C ABI itself
+    import ctypes
+    o = iim.make_options()
+    o.cycle_gamma = 3
+    g = iim.Grid(2, 64, -1.0, 1.0)
+    pa = (ctypes.c_double * 3)(0.0, 0.0, 0.5)
+    geo = iim.Geometry(W.GEOM_SPHERE, W.SIDE_INTERIOR, W.BC_DIRICHLET, 3, pa)
+    h = ctypes.c_void_p()
+    assert iim.lib().iim_create(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(o), None, ctypes.byref(h)) == -1
+    assert b"cycle_gamma" in iim.lib().iim_last_error()
+    # the library keeps working after errors; the post-processing calls reject null buffers
     G = gpu_for(W.cfg1_circle(64))
     assert G.info()["n_unknowns"] == 793
+    assert iim.lib().iim_gradient(G._h, None, None) == -1
+    assert iim.lib().iim_boundary_quantity(G._h, None, None) == -1
     G.close()
 
 
