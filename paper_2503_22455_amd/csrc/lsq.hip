@@ -19,6 +19,7 @@
 namespace iim {
 
 constexpr int LS_MAXC = 1024;  // candidates kept per set (LDS list)
+constexpr int LS_RROWS = 12;   // rows per lane of a register-held column (768 = the 3D slab height)
 constexpr double SET_TOL = 1e-12;
 constexpr double RANK_TOL = 1e-10;
 
@@ -390,38 +391,99 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                                                    ipow(xi[2], ex[col][2]);
             }
             __syncthreads();
-            // Householder QR
+            // Householder QR in panels of QP columns.  A panel is factored
+            // column by column in the slab; its reflectors are then applied
+            // to every later column held in registers (rows r = lane + 64 i),
+            // one load and one store per column and panel instead of one per
+            // reflector.  Each dot product is summed per lane over the same
+            // rows in the same order as a column-at-a-time sweep whose lane L
+            // takes rows col + 1 + L + 64 k, and its partials are moved to
+            // those lanes before the wavefront sum, so the factors are the
+            // same bit for bit.
             double rmax = 0.0, rmin = 1e300;
-            for (int col = 0; col < p; ++col) {
-                double* v = Acol + (int64_t)col * mcap;
-                double s = 0.0;
-                for (int r = col + 1 + lane; r < M; r += 64) s += v[r] * v[r];
-                s = wave_sum(s);
-                double alpha = v[col];
-                double norm = sqrt(alpha * alpha + s);
-                double tau = 0.0, beta = alpha;
-                if (s != 0.0) {
-                    beta = alpha >= 0.0 ? -norm : norm;
-                    tau = (beta - alpha) / beta;
-                    double inv = 1.0 / (alpha - beta);
-                    for (int r = col + 1 + lane; r < M; r += 64) v[r] *= inv;
-                }
-                __syncthreads();
-                if (lane == 0) {
-                    v[col] = beta;
-                    tauv[col] = tau;
-                }
-                rmax = fmax(rmax, fabs(beta));
-                rmin = fmin(rmin, fabs(beta));
-                for (int c2 = col + 1; c2 < p; ++c2) {
-                    double* u = Acol + (int64_t)c2 * mcap;
-                    double dot = 0.0;
-                    for (int r = col + 1 + lane; r < M; r += 64) dot += v[r] * u[r];
-                    dot = wave_sum(dot) + u[col];
-                    double f = tau * dot;
+            constexpr int QP = 4;
+            for (int c0 = 0; c0 < p; c0 += QP) {
+                const int pe = min(c0 + QP, p);
+                for (int col = c0; col < pe; ++col) {
+                    double* v = Acol + (int64_t)col * mcap;
+                    double s = 0.0;
+                    for (int r = col + 1 + lane; r < M; r += 64) s += v[r] * v[r];
+                    s = wave_sum(s);
+                    double alpha = v[col];
+                    double norm = sqrt(alpha * alpha + s);
+                    double tau = 0.0, beta = alpha;
+                    if (s != 0.0) {
+                        beta = alpha >= 0.0 ? -norm : norm;
+                        tau = (beta - alpha) / beta;
+                        double inv = 1.0 / (alpha - beta);
+                        for (int r = col + 1 + lane; r < M; r += 64) v[r] *= inv;
+                    }
                     __syncthreads();
-                    if (lane == 0) u[col] -= f;
-                    for (int r = col + 1 + lane; r < M; r += 64) u[r] -= f * v[r];
+                    if (lane == 0) {
+                        v[col] = beta;
+                        tauv[col] = tau;
+                    }
+                    rmax = fmax(rmax, fabs(beta));
+                    rmin = fmin(rmin, fabs(beta));
+                    for (int c2 = col + 1; c2 < pe; ++c2) {  // the rest of the panel
+                        double* u = Acol + (int64_t)c2 * mcap;
+                        double dot = 0.0;
+                        for (int r = col + 1 + lane; r < M; r += 64) dot += v[r] * u[r];
+                        dot = wave_sum(dot) + u[col];
+                        double f = tau * dot;
+                        __syncthreads();
+                        if (lane == 0) u[col] -= f;
+                        for (int r = col + 1 + lane; r < M; r += 64) u[r] -= f * v[r];
+                    }
+                    __syncthreads();
+                }
+                if (pe >= p) break;
+                double vv[QP][LS_RROWS];
+#pragma unroll
+                for (int t = 0; t < QP; ++t)
+#pragma unroll
+                    for (int i = 0; i < LS_RROWS; ++i) {
+                        const int r = lane + 64 * i;
+                        vv[t][i] = (c0 + t < pe && r < M) ? Acol[(int64_t)(c0 + t) * mcap + r] : 0.0;
+                    }
+                for (int c2 = pe; c2 < p; ++c2) {
+                    double* u = Acol + (int64_t)c2 * mcap;
+                    double uu[LS_RROWS];
+#pragma unroll
+                    for (int i = 0; i < LS_RROWS; ++i) {
+                        const int r = lane + 64 * i;
+                        uu[i] = r < M ? u[r] : 0.0;
+                    }
+#pragma unroll
+                    for (int t = 0; t < QP; ++t) {
+                        const int col = c0 + t;
+                        if (col >= pe) break;
+                        double part = 0.0;
+#pragma unroll
+                        for (int i = 0; i < LS_RROWS; ++i) {
+                            const int r = lane + 64 * i;
+                            if (r > col && r < M) part += vv[t][i] * uu[i];
+                        }
+                        // lane L of the column sweep summed rows col + 1 + L + 64 k
+                        part = __shfl(part, (lane + col + 1) & 63, 64);
+                        double ucol = 0.0;
+#pragma unroll
+                        for (int i = 0; i < LS_RROWS; ++i)
+                            if (i == (col >> 6)) ucol = uu[i];
+                        ucol = __shfl(ucol, col & 63, 64);
+                        const double f = tauv[col] * (wave_sum(part) + ucol);
+#pragma unroll
+                        for (int i = 0; i < LS_RROWS; ++i) {
+                            const int r = lane + 64 * i;
+                            if (r == col) uu[i] -= f;
+                            else if (r > col && r < M) uu[i] -= f * vv[t][i];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < LS_RROWS; ++i) {
+                        const int r = lane + 64 * i;
+                        if (r < M) u[r] = uu[i];
+                    }
                 }
                 __syncthreads();
             }
