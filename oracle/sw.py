@@ -26,7 +26,9 @@ Box-face nodes are regular neighbours holding their (zero) value.
 
 Parity: the 1D rows are pinned by exactness on {1, x, x^2}; the unshifted
 Dirichlet discretisation by its second-order convergence; the shifted operator
-itself is parity unpinned beyond the multigrid convergence checks.
+by invariants only (M-matrix signs, row sums fixed by its walls, a diagonal
+bounded by the shift) and the multigrid convergence checks: its entries are
+otherwise parity unpinned.
 """
 from __future__ import annotations
 

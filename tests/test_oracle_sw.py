@@ -1,7 +1,9 @@
 """Pins for the Shortley-Weller rows (Sec. 3.1): every 1D row is exact on
 {1, x, x^2} (this is what fixes the coefficients uniquely; it also exposes the
-misprinted denominators of Neumann case (b)), and the unshifted Dirichlet
-discretisation converges at second order."""
+misprinted denominators of Neumann case (b)), the unshifted Dirichlet
+discretisation converges at second order, and the shifted operator on every
+multigrid level has an M-matrix sign pattern, row sums fixed by where its
+walls sit, and a diagonal bounded by the shift."""
 import numpy as np
 import pytest
 
@@ -57,3 +59,69 @@ def test_unshifted_dirichlet_second_order():
         errs.append(np.abs(u - ms.u_plus(*xf)).max())
     orders = [np.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert min(orders[1:]) > 1.8, (orders, errs)
+
+
+# -- the shifted operator on every level: sign structure and row sums ----------------
+
+from oracle import PLUS, MINUS, BOX  # noqa: E402
+from oracle.iim import IIMProblem  # noqa: E402
+from oracle.mg import Hierarchy  # noqa: E402
+
+SHIFTED = [
+    ("dirichlet-interior-2d", 2, 64, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0, 1.0, 1.0),
+    ("dirichlet-exterior-2d", 2, 64, W.GEOM_SPHERE_UNION, W.union_params(W.small_circles_union_2d()), 1, 0, 1.0, 1.0),
+    ("neumann-exterior-2d", 2, 64, W.GEOM_SPHERE_UNION, W.union_params(W.small_circles_union_2d()), 1, 1, 1.0, 1.0),
+    ("interface-2d", 2, 128, W.GEOM_STAR2D, [0.0, 0.0, 0.5, 0.1, 5], 2, 2, 0.5, 1.0),
+    ("dirichlet-interior-3d", 3, 24, W.GEOM_SPHERE, [0.01, 0.02, -0.01, 0.6], 0, 0, 1.0, 1.0),
+    ("neumann-exterior-3d", 3, 24, W.GEOM_SPHERE, [0.02, -0.01, 0.03, 0.45], 1, 1, 1.0, 1.0),
+]
+
+
+@pytest.mark.parametrize("case", SHIFTED, ids=[c[0] for c in SHIFTED])
+def test_shifted_operator_sign_structure_and_row_sums(case):
+    """On every level of the hierarchy the shifted SW matrix has a non-positive
+    diagonal and non-negative off-diagonal entries (an M-matrix pattern), and
+    its row sums follow from where each row's neighbours sit: a Dirichlet wall
+    or a box face moves its coefficient to the data side, so the row sum is
+    strictly negative; a Neumann wall or an interface link (weights summing to
+    one) keeps the row consistent on constants, so an interior row sums to 0."""
+    name, dim, n, kind, params, side, bc, bp, bm = case
+    P = IIMProblem(dim, n, kind, params, side, bc, bp, bm)
+    H = Hierarchy(P)
+    for l, lev in enumerate(H.levels):
+        A = lev.A.tocsr()
+        d = A.diagonal()
+        off = A.copy()
+        off.setdiag(0.0)
+        off.eliminate_zeros()
+        assert (d <= 0.0).all(), (name, l)
+        assert (off.data >= 0.0).all(), (name, l)
+        rs = A @ np.ones(A.shape[0])
+        scale = np.abs(d).max()
+        lab = lev.lab_flat
+        nn = lev.grid.n + 1
+        touch_dir = np.zeros(lev.unknowns.size, dtype=bool)  # a neighbour that takes data off the matrix
+        for r, f in enumerate(lev.unknowns):
+            idx = np.unravel_index(f, (nn,) * dim, order="F")
+            for ax in range(dim):
+                for s in (-1, 1):
+                    j = list(idx)
+                    j[ax] += s
+                    q = np.ravel_multi_index(tuple(j), (nn,) * dim, order="F")
+                    lq = lab[q]
+                    if lq == BOX or (lq != lab[f] and bc == 0 and side != 2):
+                        touch_dir[r] = True
+        assert (rs[touch_dir] < -1e-12 * scale).all(), (name, l)
+        assert np.abs(rs[~touch_dir]).max() <= 1e-12 * scale, (name, l, np.abs(rs[~touch_dir]).max() / scale)
+        # the intersection shift (every wall at least h/2 away) bounds the
+        # diagonal: a 1D row weighs 2 / (psi- psi+ h^2) <= 8 / h^2 per axis
+        h2 = lev.grid.h ** 2
+        assert np.abs(d).max() <= 8.0 * dim / h2 * (1 + 1e-12), (name, l)
+
+
+def test_unshifted_operator_exceeds_the_shift_bound():
+    """Without the shift, walls closer than h/2 make the diagonal exceed
+    8 dim / h^2 on the same geometry: the bound above is the shift's doing."""
+    P = IIMProblem(2, 64, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0)
+    lev = SWLevel(P.grid, P.geom, 0, 0, 1.0, 1.0, shift=False)
+    assert np.abs(lev.A.diagonal()).max() > 8.0 * 2 / P.grid.h ** 2
