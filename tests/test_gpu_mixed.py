@@ -143,8 +143,8 @@ def test_error_paths():
     G.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed16"])
-def test_graph_replays_match_eager(prec):
+@pytest.mark.parametrize("prec,cycle", [("fp64", "V"), ("mixed16", "V"), ("fp64", "W")])
+def test_graph_replays_match_eager(prec, cycle):
     """Every FGMRES iteration replays a captured HIP graph (with eager work and
     host synchronisations between replays), or is launched eagerly one
     iteration ahead of the host; each Hessenberg column must equal the
@@ -155,7 +155,7 @@ def test_graph_replays_match_eager(prec):
     cpd, box, f = oracle_data(O, wl)
     outs = []
     for g in (0, 1, 1, 2):
-        G = gpu_for(wl, precision=prec, use_graph=g, rtol=1e-12)
+        G = gpu_for(wl, precision=prec, use_graph=g, rtol=1e-12, cycle=cycle)
         G.set_boundary_data(cpd, box)
         G.set_rhs(f)
         u, hist, st = G.solve()
