@@ -235,16 +235,19 @@ __device__ inline Blk3 xcd_block3(int gx, int gy) {
 }
 
 // 3D apply of the regular unknowns, marching along z.  A block of 64 x 4
-// threads owns a 64 x 16 tile of (x, y) columns (each thread 4 rows) and a
-// chunk of zc planes.  The z-neighbours of each column stay in a register
+// threads owns a 64 x (4 ZM_RY) tile of (x, y) columns (each thread ZM_RY
+// rows) and a chunk of zc planes.  One row per thread keeps the kernel at 62
+// registers, eight waves per SIMD: twice the loads in flight of four rows at
+// four waves (the march is bound by the loads it has in flight).  The z-neighbours of each column stay in a register
 // queue; the x/y neighbours of the current plane come from an LDS copy of the
 // tile with a 2-node halo.  Every load is issued at least one plane ahead of
 // its use (interior values one plane, halo values and labels three), so the
 // loads of a plane overlap the work on the previous ones.  Irregular nodes
 // are left to k_ho_irregular.
-constexpr int ZM_TX = 64, ZM_RY = 4, ZM_TY = 4 * ZM_RY, ZM_LA = 3;
+// ZM_LA is also the depth of the z queue (planes z - 2 .. z + ZM_LA): it stays 3
+constexpr int ZM_TX = 64, ZM_RY = 1, ZM_TY = 4 * ZM_RY, ZM_LA = 3;
 
-__global__ void __launch_bounds__(256, 4) k_ho_apply3_zm(Box b, int3 clo, int3 chi, int ntx, int nty, int zc,
+__global__ void __launch_bounds__(256, 8) k_ho_apply3_zm(Box b, int3 clo, int3 chi, int ntx, int nty, int zc,
                                                       const uint8_t* __restrict__ labels, double inv_h2, double bp,
                                                       double bm, const double* __restrict__ x,
                                                       double* __restrict__ y) {
@@ -262,14 +265,14 @@ __global__ void __launch_bounds__(256, 4) k_ho_apply3_zm(Box b, int3 clo, int3 c
     };
     auto ldl = [&](int jj, int kk) -> int { return (i <= bxh && jj <= byh) ? (int)labels[b.idx(i, jj, kk)] : 0; };
     // x-halo duty: lanes 0-3 load tile columns 0, 1, 66, 67 of the thread's rows;
-    // y-halo duty: wavefront wy loads tile row 0, 1, 18 or 19
+    // y-halo duty: wavefront wy loads tile row 0, 1, ZM_TY + 2 or ZM_TY + 3
     const int hcol = lane < 2 ? lane : ZM_TX + lane;
     const int hi = i0 - 2 + hcol;
     const int hr = wy < 2 ? wy : ZM_TY + wy;
     const int hj = j0 - 2 + hr;
     double q[ZM_RY][6];   // planes z-2 .. z+3
     double hx[ZM_LA][ZM_RY], hy[ZM_LA];  // planes z .. z+2
-    uint32_t lb[ZM_LA];                   // labels of the 4 rows, one byte each
+    uint32_t lb[ZM_LA];                   // labels of the ZM_RY rows, one byte each
 #pragma unroll
     for (int r = 0; r < ZM_RY; ++r)
 #pragma unroll
