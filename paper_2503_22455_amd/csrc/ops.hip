@@ -234,24 +234,30 @@ __device__ inline Blk3 xcd_block3(int gx, int gy) {
     return {t % gx, (t / gx) % gy, t / (gx * gy)};
 }
 
-// 3D apply of the regular unknowns, marching along z.  A block of 64 x 4
-// threads owns a 64 x (4 ZM_RY) tile of (x, y) columns (each thread ZM_RY
-// rows) and a chunk of zc planes.  One row per thread keeps the kernel at 62
-// registers, eight waves per SIMD: twice the loads in flight of four rows at
-// four waves (the march is bound by the loads it has in flight).  The z-neighbours of each column stay in a register
-// queue; the x/y neighbours of the current plane come from an LDS copy of the
-// tile with a 2-node halo.  Every load is issued at least one plane ahead of
-// its use (interior values one plane, halo values and labels three), so the
-// loads of a plane overlap the work on the previous ones.  Irregular nodes
-// are left to k_ho_irregular.
-// ZM_LA is also the depth of the z queue (planes z - 2 .. z + ZM_LA): it stays 3
-constexpr int ZM_TX = 64, ZM_RY = 1, ZM_TY = 4 * ZM_RY, ZM_LA = 3;
+// 3D apply of the regular unknowns, marching along z, for stencil half-width
+// W (2: the (4,5) scheme, 3: the (6,7) scheme).  A block of 64 x 4 threads
+// owns a 64 x (4 ZM_RY) tile of (x, y) columns (each thread ZM_RY rows) and a
+// chunk of zc planes.  The z-neighbours of each column stay in a register
+// queue (planes z - W .. z + W + 1); the x/y neighbours of the current plane
+// come from an LDS copy of the tile with a W-node halo.  Every load is issued
+// at least one plane ahead of its use (interior values one plane, halo values
+// and labels W + 1), so the loads of a plane overlap the work on the previous
+// ones.  One row per thread keeps the kernel at about 60 registers, eight
+// waves per SIMD at W = 2 (six at W = 3, whose longer queue would spill at
+// eight): twice the loads in flight of four rows at four waves (the march is
+// bound by the loads it has in flight).  Irregular nodes are left to
+// k_ho_irregular.
+constexpr int ZM_TX = 64, ZM_RY = 1, ZM_TY = 4 * ZM_RY;
 
-__global__ void __launch_bounds__(256, 8) k_ho_apply3_zm(Box b, int3 clo, int3 chi, int ntx, int nty, int zc,
+template <int W>
+__global__ void __launch_bounds__(256, W == 2 ? 8 : 6) k_ho_apply3_zm(Box b, int3 clo, int3 chi, int ntx, int nty, int zc,
                                                       const uint8_t* __restrict__ labels, double inv_h2, double bp,
                                                       double bm, const double* __restrict__ x,
                                                       double* __restrict__ y) {
-    __shared__ double tile[ZM_TY + 4][ZM_TX + 4];
+    constexpr int LA = W + 1;             // lookahead of the halo and label loads (planes)
+    constexpr int NQ = 2 * W + 2;         // z queue: planes z - W .. z + W + 1
+    constexpr int NHY = (2 * W + 3) / 4;  // y-halo rows per wavefront
+    __shared__ double tile[ZM_TY + 2 * W][ZM_TX + 2 * W];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
@@ -259,52 +265,62 @@ __global__ void __launch_bounds__(256, 8) k_ho_apply3_zm(Box b, int3 clo, int3 c
     const int i = i0 + lane;
     const int zs = clo.z + tz * zc, ze = min(zs + zc - 1, chi.z);
     const int bxh = b.lo[0] + b.dims[0] - 1, byh = b.lo[1] + b.dims[1] - 1, bzh = b.lo[2] + b.dims[2] - 1;
-    // in-box loads (the box holds the core with a 2-node margin; beyond it in x/y: 0)
+    // in-box loads (the box holds the core with a W-node margin; beyond it in x/y: 0)
     auto ldx = [&](int ii, int jj, int kk) -> double {
         return (ii <= bxh && jj <= byh) ? x[b.idx(ii, jj, kk)] : 0.0;
     };
     auto ldl = [&](int jj, int kk) -> int { return (i <= bxh && jj <= byh) ? (int)labels[b.idx(i, jj, kk)] : 0; };
-    // x-halo duty: lanes 0-3 load tile columns 0, 1, 66, 67 of the thread's rows;
-    // y-halo duty: wavefront wy loads tile row 0, 1, ZM_TY + 2 or ZM_TY + 3
-    const int hcol = lane < 2 ? lane : ZM_TX + lane;
-    const int hi = i0 - 2 + hcol;
-    const int hr = wy < 2 ? wy : ZM_TY + wy;
-    const int hj = j0 - 2 + hr;
-    double q[ZM_RY][6];   // planes z-2 .. z+3
-    double hx[ZM_LA][ZM_RY], hy[ZM_LA];  // planes z .. z+2
-    uint32_t lb[ZM_LA];                   // labels of the ZM_RY rows, one byte each
+    // x-halo duty: lanes 0 .. 2W-1 load tile columns 0 .. W-1 and ZM_TX+W .. ZM_TX+2W-1
+    // of the thread's rows; y-halo duty: halo row k (rows 0 .. W-1, then
+    // ZM_TY+W .. ZM_TY+2W-1) is loaded by wavefront k % 4, as its slot k / 4
+    const int hcol = lane < W ? lane : ZM_TX + lane;
+    const int hi = i0 - W + hcol;
+    int hr[NHY], hj[NHY];
+#pragma unroll
+    for (int u = 0; u < NHY; ++u) {
+        const int k = wy + 4 * u;
+        hr[u] = k < 2 * W ? (k < W ? k : ZM_TY + k) : -1;
+        hj[u] = j0 - W + hr[u];
+    }
+    double q[ZM_RY][NQ];
+    double hx[LA][ZM_RY], hy[LA][NHY];  // planes z .. z + W
+    uint32_t lb[LA];                    // labels of the ZM_RY rows, one byte each
 #pragma unroll
     for (int r = 0; r < ZM_RY; ++r)
 #pragma unroll
-        for (int d = 0; d < 5; ++d) q[r][d] = ldx(i, j0 + wy + 4 * r, zs - 2 + d);
+        for (int d = 0; d < NQ - 1; ++d) q[r][d] = ldx(i, j0 + wy + 4 * r, zs - W + d);
 #pragma unroll
-    for (int s = 0; s < ZM_LA; ++s) {
+    for (int s = 0; s < LA; ++s) {
         const int zz = min(zs + s, bzh);
         lb[s] = 0;
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
-            hx[s][r] = lane < 4 ? ldx(hi, j0 + wy + 4 * r, zz) : 0.0;
+            hx[s][r] = lane < 2 * W ? ldx(hi, j0 + wy + 4 * r, zz) : 0.0;
             lb[s] |= (uint32_t)ldl(j0 + wy + 4 * r, zz) << (8 * r);
         }
-        hy[s] = ldx(i, hj, zz);
+#pragma unroll
+        for (int u = 0; u < NHY; ++u) hy[s][u] = hr[u] >= 0 ? ldx(i, hj[u], zz) : 0.0;
     }
     for (int z = zs; z <= ze; ++z) {
-        const int zp = min(z + ZM_LA, bzh);  // clamped planes are never used
-        double hxn[ZM_RY], hyn;
+        const int zp = min(z + LA, bzh);  // clamped planes are never used
+        double hxn[ZM_RY], hyn[NHY];
         uint32_t lbn = 0;
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
-            q[r][5] = ldx(i, j0 + wy + 4 * r, zp);
-            hxn[r] = lane < 4 ? ldx(hi, j0 + wy + 4 * r, zp) : 0.0;
+            q[r][NQ - 1] = ldx(i, j0 + wy + 4 * r, zp);
+            hxn[r] = lane < 2 * W ? ldx(hi, j0 + wy + 4 * r, zp) : 0.0;
             lbn |= (uint32_t)ldl(j0 + wy + 4 * r, zp) << (8 * r);
         }
-        hyn = ldx(i, hj, zp);
+#pragma unroll
+        for (int u = 0; u < NHY; ++u) hyn[u] = hr[u] >= 0 ? ldx(i, hj[u], zp) : 0.0;
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
-            tile[wy + 4 * r + 2][lane + 2] = q[r][2];
-            if (lane < 4) tile[wy + 4 * r + 2][hcol] = hx[0][r];
+            tile[wy + 4 * r + W][lane + W] = q[r][W];
+            if (lane < 2 * W) tile[wy + 4 * r + W][hcol] = hx[0][r];
         }
-        tile[hr][lane + 2] = hy[0];
+#pragma unroll
+        for (int u = 0; u < NHY; ++u)
+            if (hr[u] >= 0) tile[hr[u]][lane + W] = hy[0][u];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
@@ -316,11 +332,20 @@ __global__ void __launch_bounds__(256, 8) k_ho_apply3_zm(Box b, int3 clo, int3 c
                 if (kind != K_PLUS && kind != K_MINUS) {
                     y[l] = 0.0;
                 } else {
-                    const int tr = wy + 4 * r + 2, tc = lane + 2;
-                    double acc = 3.0 * A0 * q[r][2];
-                    acc += A1 * (tile[tr][tc + 1] + tile[tr][tc - 1]) + A2 * (tile[tr][tc + 2] + tile[tr][tc - 2]);
-                    acc += A1 * (tile[tr + 1][tc] + tile[tr - 1][tc]) + A2 * (tile[tr + 2][tc] + tile[tr - 2][tc]);
-                    acc += A1 * (q[r][3] + q[r][1]) + A2 * (q[r][4] + q[r][0]);
+                    const int tr = wy + 4 * r + W, tc = lane + W;
+                    double acc;
+                    if constexpr (W == 2) {
+                        acc = 3.0 * A0 * q[r][2];
+                        acc += A1 * (tile[tr][tc + 1] + tile[tr][tc - 1]) + A2 * (tile[tr][tc + 2] + tile[tr][tc - 2]);
+                        acc += A1 * (tile[tr + 1][tc] + tile[tr - 1][tc]) + A2 * (tile[tr + 2][tc] + tile[tr - 2][tc]);
+                        acc += A1 * (q[r][3] + q[r][1]) + A2 * (q[r][4] + q[r][0]);
+                    } else {
+                        acc = 3.0 * ho_a<W>(0) * q[r][W];
+#pragma unroll
+                        for (int jj = 1; jj <= W; ++jj)
+                            acc += ho_a<W>(jj) * ((tile[tr][tc + jj] + tile[tr][tc - jj]) +
+                                                  (tile[tr + jj][tc] + tile[tr - jj][tc]) + (q[r][W + jj] + q[r][W - jj]));
+                    }
                     y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
                 }
             }
@@ -329,23 +354,25 @@ __global__ void __launch_bounds__(256, 8) k_ho_apply3_zm(Box b, int3 clo, int3 c
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
 #pragma unroll
-            for (int d = 0; d < 5; ++d) q[r][d] = q[r][d + 1];
+            for (int d = 0; d < NQ - 1; ++d) q[r][d] = q[r][d + 1];
 #pragma unroll
-            for (int s = 0; s < ZM_LA - 1; ++s) hx[s][r] = hx[s + 1][r];
-            hx[ZM_LA - 1][r] = hxn[r];
+            for (int s = 0; s < LA - 1; ++s) hx[s][r] = hx[s + 1][r];
+            hx[LA - 1][r] = hxn[r];
         }
 #pragma unroll
-        for (int s = 0; s < ZM_LA - 1; ++s) {
-            hy[s] = hy[s + 1];
+        for (int s = 0; s < LA - 1; ++s) {
+#pragma unroll
+            for (int u = 0; u < NHY; ++u) hy[s][u] = hy[s + 1][u];
             lb[s] = lb[s + 1];
         }
-        hy[ZM_LA - 1] = hyn;
-        lb[ZM_LA - 1] = lbn;
+#pragma unroll
+        for (int u = 0; u < NHY; ++u) hy[LA - 1][u] = hyn[u];
+        lb[LA - 1] = lbn;
     }
 }
 
 // irregular nodes of the high-order apply, one thread each, from their list
-template <int DIM>
+template <int DIM, int W>
 __global__ void __launch_bounds__(256) k_ho_irregular(Box b, const int32_t* __restrict__ nodes, int64_t nirr,
                                                       const uint8_t* __restrict__ labels,
                                                       const int32_t* __restrict__ irr_index,
@@ -358,8 +385,8 @@ __global__ void __launch_bounds__(256) k_ho_irregular(Box b, const int32_t* __re
     if (t >= nirr) return;
     const int64_t l = nodes[t];
     const uint8_t kind = labels[l] & KIND_MASK;
-    double acc = (double)DIM * A0 * x[l];
-    acc += ho_irregular<DIM, 2>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, x,
+    double acc = (double)DIM * ho_a<W>(0) * x[l];
+    acc += ho_irregular<DIM, W>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, x,
                                 with_data);
     y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
 }
@@ -372,26 +399,13 @@ void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi,
     int3 hi = make_int3(core_hi[0], core_hi[1], core_hi[2]);
     int nx = hi.x - lo.x + 1, ny = hi.y - lo.y + 1, nz = hi.z - lo.z + 1;
     if (nx <= 0 || ny <= 0 || nz <= 0) return;
-    if (dim == 3 && w == 3) {
-        // the sixth-order scheme in 3D: one thread per node, irregular nodes
-        // inside the same kernel (the z-march below is written for a 2-node reach)
-        if (part == 2) return;
-        for (int d = 0; d < 3; ++d)
-            if (core_lo[d] - 3 < b.lo[d] || core_hi[d] + 3 > b.lo[d] + b.dims[d] - 1)
-                throw Error(IIM_E_INTERNAL, "apply: storage box lacks the 3-node margin");
-        const dim3 blk(64, 4, 1);
-        const dim3 grd(cdiv(nx, 64), cdiv(ny, 4), nz);
-        hipLaunchKernelGGL((k_ho_apply<3, 3>), grd, blk, 0, s, b, lo, hi, labels, irr_index, slots, ghost, boxval,
-                           inv_h2, beta_plus, beta_minus, x, y, with_data);
-        IIM_LAUNCH_CHECK();
-        return;
-    }
     if (dim == 3) {
-        // the z-march reads planes zs-2 .. ze+2 and columns/rows up to 2 past the
+        // the z-march reads planes zs-w .. ze+w and columns/rows up to w past the
         // core: the storage box has that margin
+        if (w != 2 && w != 3) throw Error(IIM_E_INTERNAL, "apply: stencil half-width must be 2 or 3");
         for (int d = 0; d < 3; ++d)
-            if (core_lo[d] - 2 < b.lo[d] || core_hi[d] + 2 > b.lo[d] + b.dims[d] - 1)
-                throw Error(IIM_E_INTERNAL, "apply: storage box lacks the 2-node margin");
+            if (core_lo[d] - w < b.lo[d] || core_hi[d] + w > b.lo[d] + b.dims[d] - 1)
+                throw Error(IIM_E_INTERNAL, "apply: storage box lacks the stencil margin");
         const int ntx = cdiv(nx, ZM_TX), nty = cdiv(ny, ZM_TY);
         const int64_t cols = (int64_t)ntx * nty;
         // chunks of 8..16 planes, shorter when the tiles are too few to fill the device
@@ -399,13 +413,23 @@ void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi,
         const int nzc = cdiv(nz, zc);
         const int64_t nb = cols * nzc;
         if (part != 2) {
-            hipLaunchKernelGGL(k_ho_apply3_zm, dim3((unsigned)nb), dim3(256), 0, s, b, lo, hi, ntx, nty, zc, labels,
-                               inv_h2, beta_plus, beta_minus, x, y);
+            if (w == 2)
+                hipLaunchKernelGGL((k_ho_apply3_zm<2>), dim3((unsigned)nb), dim3(256), 0, s, b, lo, hi, ntx, nty, zc,
+                                   labels, inv_h2, beta_plus, beta_minus, x, y);
+            else
+                hipLaunchKernelGGL((k_ho_apply3_zm<3>), dim3((unsigned)nb), dim3(256), 0, s, b, lo, hi, ntx, nty, zc,
+                                   labels, inv_h2, beta_plus, beta_minus, x, y);
             IIM_LAUNCH_CHECK();
         }
         if (nirr > 0 && part != 1) {
-            hipLaunchKernelGGL(k_ho_irregular<3>, dim3(cdiv(nirr, 256)), dim3(256), 0, s, b, irr_nodes, nirr, labels,
-                               irr_index, slots, ghost, boxval, w, inv_h2, beta_plus, beta_minus, x, y, with_data);
+            if (w == 2)
+                hipLaunchKernelGGL((k_ho_irregular<3, 2>), dim3(cdiv(nirr, 256)), dim3(256), 0, s, b, irr_nodes, nirr,
+                                   labels, irr_index, slots, ghost, boxval, w, inv_h2, beta_plus, beta_minus, x, y,
+                                   with_data);
+            else
+                hipLaunchKernelGGL((k_ho_irregular<3, 3>), dim3(cdiv(nirr, 256)), dim3(256), 0, s, b, irr_nodes, nirr,
+                                   labels, irr_index, slots, ghost, boxval, w, inv_h2, beta_plus, beta_minus, x, y,
+                                   with_data);
             IIM_LAUNCH_CHECK();
         }
         return;
