@@ -295,3 +295,51 @@ def test_wcycle_solve_reaches_1e10(make, prec):
         its[cyc] = st["iterations"]
         G.close()
     assert its["W"] <= its["V"], its
+
+
+class _FP16Stored(Hierarchy):
+    """The oracle's V-cycle with its iterates rounded to IEEE half precision
+    after every half-sweep and every cycle, on inputs scaled to max |v| = 1:
+    an emulation of FP16 iterate storage in FP64 arithmetic."""
+
+    @staticmethod
+    def _r(v):
+        return v.astype(np.float16).astype(np.float64)
+
+    def rbgs(self, l, z, b):
+        lev = self.levels[l]
+        A, D = lev.A, lev.diag
+        for c in (0, 1):
+            rows = np.nonzero((self.colour[l] == c) & (D != 0.0))[0]
+            z[rows] = (b[rows] - A[rows] @ z + D[rows] * z[rows]) / D[rows]
+            z[rows] = self._r(z[rows])
+
+    def cycle_level(self, l, b, z0=None):
+        return self._r(super().cycle_level(l, b, z0))
+
+    def precondition(self, v):
+        s = np.abs(v).max()
+        return super().precondition(v / s) * s
+
+
+def test_fp16_storage_iteration_count_matches_emulation():
+    """The FP16-storage V-cycle costs FGMRES iterations as the grid refines
+    (star interface: 29 -> 29 at 256^2, 30 -> 32 at 512^2, 31 -> 42 at 1024^2
+    in the emulation, 31 -> 42 on the device at 1024^2).  At 512^2 the device's
+    count (FP32 arithmetic, FP16 storage) is the emulation's within 3."""
+    from oracle.krylov import fgmres
+    wl = W.cfg2_star(512)
+    O = oracle_for(wl)
+    L, LG = O.assemble()
+    cpd, box, f = oracle_data(O, wl)
+    ug = O.data_vector(cpd, wl.box_data())
+    b = O.rhs(wl.rhs(O.labels), ug)
+    _, _, its_emul, conv = fgmres(lambda v: L @ v, _FP16Stored(O).precondition, b, rtol=1e-10, max_iters=200)
+    assert conv
+    G = gpu_for(wl, precision="mixed16", rtol=1e-10)
+    G.set_boundary_data(cpd, box)
+    G.set_rhs(f)
+    u, hist, st = G.solve()
+    G.close()
+    assert st["status"] == 0
+    assert abs(st["iterations"] - its_emul) <= 3, (st["iterations"], its_emul)
