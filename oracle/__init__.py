@@ -17,6 +17,7 @@ Poisson equation with boundary and interface conditions", JCP 2025):
   sw.py        Shortley-Weller discretizations with intersection shifting (Sec. 3.1)
   mg.py        geometric multigrid V-cycle on the SW operator (Sec. 3.3)
   krylov.py    right-preconditioned FGMRES(m) (Sec. 4.1)
+  singular.py  the bordered system of pure-Neumann problems (Sec. 2.3)
 
 Every function is written for a reader checking it against the paper by eye:
 no blocking, fusion or reordering beyond what the definitions state.

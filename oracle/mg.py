@@ -22,7 +22,11 @@ Readings: vertex-centred coarsening (coarse node I = fine node 2I, ceil(n/2)
 intervals); half-weighting stencils 1/8 [0 1 0; 1 4 1; 0 1 0] in 2D and centre
 1/2, faces 1/12 in 3D; red (even index sum) before black; V(2,2); box-face nodes
 hold zero and count as in-domain for the averaging interpolation; the coarse
-solve excludes rows with a zero diagonal (their value stays zero).
+solve excludes rows with a zero diagonal (their value stays zero).  For a
+singular problem (interior domain, Neumann boundary) the coarsest matrix
+annihilates constants too; it is bordered like the fine system, [A 1; 1^T 0],
+and the coarse solve returns the first block of the bordered solution with a
+zero last entry on the right (the coarse values then sum to zero).
 
 Parity: pinned by the Dirichlet V-cycle contraction (rho < 0.1, independent of
 n), by transfer operators reproducing constants away from Gamma, and by the
@@ -42,7 +46,7 @@ import numpy as np
 import scipy.linalg
 
 from . import INACTIVE, PLUS, MINUS, BOX
-from .geometry import Grid, SIDE_INTERFACE
+from .geometry import Grid, SIDE_INTERFACE, SIDE_INTERIOR
 from .sw import SWLevel, BC_DIRICHLET, BC_NEUMANN, BC_JUMP
 
 
@@ -80,6 +84,14 @@ class Hierarchy:
         lc = self.levels[-1]
         self.coarse_rows = np.nonzero(lc.diag != 0.0)[0]
         Ad = lc.A.toarray()[np.ix_(self.coarse_rows, self.coarse_rows)]
+        self.bordered = prob.side == SIDE_INTERIOR and prob.bc == BC_NEUMANN
+        if self.bordered and Ad.size:
+            nc = Ad.shape[0]
+            Ab = np.zeros((nc + 1, nc + 1))
+            Ab[:nc, :nc] = Ad
+            Ab[:nc, nc] = 1.0
+            Ab[nc, :nc] = 1.0
+            Ad = Ab
         self.coarse_lu = scipy.linalg.lu_factor(Ad) if Ad.size else None
 
     # -- smoother ------------------------------------------------------------------
@@ -150,7 +162,11 @@ class Hierarchy:
     def coarse_solve(self, b: np.ndarray) -> np.ndarray:
         z = np.zeros(b.size)
         if self.coarse_lu is not None:
-            z[self.coarse_rows] = scipy.linalg.lu_solve(self.coarse_lu, b[self.coarse_rows])
+            rhs = b[self.coarse_rows]
+            if self.bordered:
+                rhs = np.concatenate([rhs, [0.0]])
+            sol = scipy.linalg.lu_solve(self.coarse_lu, rhs)
+            z[self.coarse_rows] = sol[:self.coarse_rows.size]
         return z
 
     # -- cycle ---------------------------------------------------------------------------

@@ -152,6 +152,18 @@ def ms_star_interface() -> Manufactured:
     return Manufactured(up, gp, lp, um, gm, lm)
 
 
+def ms_shifted_trig() -> Manufactured:
+    """u = sin(2 pi x + 0.7) cos(2 pi y - 0.4): no symmetry about the origin,
+    so a pure-Neumann problem on a centred body has a non-trivial discrete
+    compatibility shift."""
+    a, c = 0.7, -0.4
+    u = lambda x, y: np.sin(TWO_PI * x + a) * np.cos(TWO_PI * y + c)
+    g = lambda x, y: (TWO_PI * np.cos(TWO_PI * x + a) * np.cos(TWO_PI * y + c),
+                      -TWO_PI * np.sin(TWO_PI * x + a) * np.sin(TWO_PI * y + c))
+    lap = lambda x, y: -2.0 * TWO_PI ** 2 * u(x, y)
+    return Manufactured(u, g, lap)
+
+
 def ms_cos_sinh() -> Manufactured:
     """u = cos(2x) sinh(y) + z^2."""
     u = lambda x, y, z: np.cos(2 * x) * np.sinh(y) + z * z
