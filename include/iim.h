@@ -146,7 +146,10 @@ typedef struct iim_stats {
     double t_krylov_ms;    /* GPU time in orthogonalisation and updates (use_graph = 0);
                               otherwise the GPU time of the whole restart cycles */
     int32_t second_passes; /* Arnoldi steps that took a second Gram-Schmidt pass */
-    int32_t reserved;
+    int32_t bordered;      /* 1: a singular pure-Neumann problem, solved as the bordered
+                              system (Sec. 2.3); 0 otherwise */
+    double shift_alpha;    /* bordered solves: the shift alpha that moves b into the range
+                              of L (the discrete integrability defect); 0 otherwise */
 } iim_stats;
 
 typedef struct iim_info {
@@ -209,7 +212,14 @@ int iim_set_rhs(iim_problem* p, const double* f, int32_t mem_kind);
 /* FGMRES solve.  u: device full-grid array receiving the solution (NaN at nodes
  * that are not unknowns).  x0: device full-grid initial guess or NULL (zero).
  * hist: host array of hist_cap doubles receiving the relative residual estimate
- * after every iteration (may be NULL).  st: may be NULL. */
+ * after every iteration (may be NULL).  st: may be NULL.
+ * Singular problems (Sec. 2.3): an interior domain (IIM_SIDE_INTERIOR) with a
+ * Neumann boundary never reaches the box faces, so L 1 = 0 and u is fixed only
+ * up to a constant.  The solver then works on the bordered system
+ * [L 1; 1^T 0] [u; alpha] = [b; 0]: the returned unknowns sum to zero, the
+ * residual is that of the bordered system, st->shift_alpha receives alpha and
+ * st->bordered is 1.  The multigrid preconditioner borders its coarsest
+ * Shortley-Weller matrix the same way and passes alpha through unchanged. */
 int iim_solve(iim_problem* p, double* u, const double* x0, double* hist, int32_t hist_cap,
               iim_stats* st);
 

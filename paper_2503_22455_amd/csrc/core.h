@@ -78,6 +78,10 @@ struct Problem {
     iim_grid grid{};
     iim_options opt{};
     int dim = 2, kind = 0, side = 0, bc = 0, nsides = 1, w = 2;
+    // interior domain with a Neumann boundary: L 1 = 0, solved as the bordered
+    // system [L 1; 1^T 0] [u; alpha] = [b; 0]; Krylov vectors then carry alpha
+    // in entry box.size()
+    bool singular = false;
     double h = 0.0;
     std::vector<double> params;
     double* d_params = nullptr;
@@ -142,6 +146,11 @@ struct Problem {
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;
     void apply_box(const double* x, double* y, int with_data);
+    // the solver's operator: L x, bordered for a singular problem
+    void apply_op(const double* x, double* y);
+    // the solver's preconditioner: one cycle, identity on alpha when bordered
+    void precondition(const double* v, double* z, bool scaled = false, bool out_basis = false);
+    int64_t krylov_len() const { return box.size() + (singular ? 1 : 0); }
     template <typename T, typename S> bool down_leg(int l, const CastInArgs* cast);
     template <typename T, typename S> const S* up_leg(int l, const S* zres, double* out);
     // scaled: red_scale already holds max |v| (the fused orthogonalisation wrote it);

@@ -541,7 +541,32 @@ void Problem::setup() {
         Ainv64 = (double*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(double));
         Ainv32 = (float*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(float));
         run_coarse_assemble(Lc.box, dim, Lc.labels, Lc.irr_index, Lc.rec64, coarse_list, d_col, nc, A, stream);
-        run_coarse_invert(A, Ainv64, nc, d_err, stream);
+        if (singular && nc) {
+            // the coarsest SW matrix annihilates constants as the fine operator
+            // does: invert the bordered [A 1; 1^T 0] and keep its leading block,
+            // which maps b to the coarse values of the bordered solution of
+            // [b; 0] (they sum to zero)
+            const int64_t nb = nc + 1;
+            std::vector<double> Ah(nc * nc), Ab(nb * nb, 0.0);
+            IIM_HIP(hipMemcpyAsync(Ah.data(), A, nc * nc * sizeof(double), hipMemcpyDeviceToHost, stream));
+            IIM_HIP(hipStreamSynchronize(stream));
+            for (int64_t r = 0; r < nc; ++r) {
+                for (int64_t c = 0; c < nc; ++c) Ab[r * nb + c] = Ah[r * nc + c];
+                Ab[r * nb + nc] = 1.0;
+                Ab[nc * nb + r] = 1.0;
+            }
+            double* Bd = (double*)mem.alloc(nb * nb * sizeof(double));
+            double* Bi = (double*)mem.alloc(nb * nb * sizeof(double));
+            IIM_HIP(hipMemcpyAsync(Bd, Ab.data(), nb * nb * sizeof(double), hipMemcpyHostToDevice, stream));
+            run_coarse_invert(Bd, Bi, nb, d_err, stream);
+            IIM_HIP(hipMemcpy2DAsync(Ainv64, nc * sizeof(double), Bi, nb * sizeof(double), nc * sizeof(double), nc,
+                                     hipMemcpyDeviceToDevice, stream));
+            IIM_HIP(hipStreamSynchronize(stream));
+            mem.release(Bi);
+            mem.release(Bd);
+        } else {
+            run_coarse_invert(A, Ainv64, nc, d_err, stream);
+        }
         run_convert<double, float>(Ainv64, Ainv32, nc * nc, 1.0, stream);
         mem.release(A);
         mem.release(d_col);
@@ -551,7 +576,7 @@ void Problem::setup() {
     // Krylov bases, one for the V-cycle vectors of every level
     const int64_t N = box.size();
     const int m = opt.restart;
-    ldv = (N + 63) / 64 * 64;
+    ldv = (krylov_len() + 63) / 64 * 64;
     {
         double* blk = (double*)mem.alloc((size_t)(2 * m + 6) * ldv * sizeof(double));
         IIM_HIP(hipMemsetAsync(blk, 0, (size_t)(2 * m + 6) * ldv * sizeof(double), stream));
@@ -714,6 +739,16 @@ void Problem::apply_box(const double* x, double* y, int with_data) {
                  opt.beta_plus, opt.beta_minus, x, y, with_data, stream);
 }
 
+void Problem::apply_op(const double* x, double* y) {
+    apply_box(x, y, 0);
+    if (singular) run_border(x, levels[0].labels, box.size(), y, red_part, stream);
+}
+
+void Problem::precondition(const double* v, double* z, bool scaled, bool out_basis) {
+    vcycle(v, z, scaled, out_basis);
+    if (singular) run_copy_scalar(v + box.size(), z + box.size(), stream);
+}
+
 // fused pre-smoothing from a zero iterate + residual + restriction on level l
 // (2D, one LDS-tiled kernel); false when it does not apply
 template <typename T, typename S>
@@ -870,12 +905,12 @@ void Problem::vcycle(const double* v, double* out, bool scaled, bool out_basis) 
 // classical Gram-Schmidt against v_0..v_j, v_{j+1} = w / |w|, and the Hessenberg column copied to
 // pinned host memory.  Pointers are fixed per j, so it can be captured.
 void Problem::iteration_body(int j, hipEvent_t* evs) {
-    const int64_t N = box.size();
+    const int64_t N = krylov_len();
     double* vj = Vb + (size_t)j * ldv;
     double* zj = Zb + (size_t)j * ldv;
-    vcycle(vj, zj, j > 0, true);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
+    precondition(vj, zj, j > 0, true);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
     if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
-    apply_box(zj, wk, 0);
+    apply_op(zj, wk);
     if (evs) IIM_HIP(hipEventRecord(evs[2], stream));
     // Classical Gram-Schmidt: h = V^T w (with |w|^2 when the second pass is
     // conditional); the second pass w -= V h with h' = V^T w and |w|^2 in the
@@ -898,13 +933,14 @@ void Problem::iteration_body(int j, hipEvent_t* evs) {
 // ---------------------------------------------------------------------------
 int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st) {
     const double t0 = now_ms();
-    const int64_t N = box.size();
+    const int64_t N = krylov_len();  // the box, plus alpha for a singular problem
     const int m = opt.restart;
     iim_stats S{};
     float t_apply = 0.f, t_vc = 0.f, t_kr = 0.f;
-    if (x0_full)
+    if (x0_full) {
         run_full_to_box(dim, grid.n, box, x0_full, xk, levels[0].labels, 1, stream);
-    else
+        if (singular) run_fill(xk + box.size(), 1, 0.0, stream);  // alpha starts at zero
+    } else
         IIM_HIP(hipMemsetAsync(xk, 0, N * sizeof(double), stream));
     double bnorm2;
     run_norm2(rhs, N, red_part, red_out, stream);
@@ -920,7 +956,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
     } else {
         while (true) {
             // true residual r = b - A x
-            apply_box(xk, wk, 0);
+            apply_op(xk, wk);
             run_copy(rhs, rk, N, stream);
             run_axpby(-1.0, wk, 1.0, rk, N, stream);
             double rn2;
@@ -1039,7 +1075,10 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
         }
     }
     if (u_full) run_box_to_full(dim, grid.n, box, xk, levels[0].labels, std::nan(""), u_full, stream);
+    if (singular)
+        IIM_HIP(hipMemcpyAsync(&S.shift_alpha, xk + box.size(), sizeof(double), hipMemcpyDeviceToHost, stream));
     IIM_HIP(hipStreamSynchronize(stream));
+    S.bordered = singular ? 1 : 0;
     S.status = status;
     S.iterations = its;
     S.cycles = cycles;
@@ -1392,6 +1431,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     p->kind = geo->kind;
     p->side = geo->side;
     p->bc = geo->bc;
+    p->singular = geo->side == IIM_SIDE_INTERIOR && geo->bc == IIM_BC_NEUMANN;
     p->params.assign(geo->params, geo->params + geo->nparams);
     p->opt_fused = o.fused_smoothing != 0 && o.cycle_gamma == 1;  // the fused legs start from zero
     p->opt_split = o.colour_split != 0;

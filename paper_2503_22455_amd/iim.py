@@ -56,7 +56,8 @@ class Stats(ctypes.Structure):
                 ("hist_len", ctypes.c_int32), ("final_rel_residual", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("t_apply_ms", ctypes.c_double),
                 ("t_vcycle_ms", ctypes.c_double), ("t_krylov_ms", ctypes.c_double),
-                ("second_passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("second_passes", ctypes.c_int32), ("bordered", ctypes.c_int32),
+                ("shift_alpha", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
