@@ -35,12 +35,16 @@ WORKLOADS = {
     "cfg2": lambda: W.cfg2_star(1024),
     "cfg3": lambda: W.cfg3_sphere(256, precision="mixed32"),
     "cfg4": lambda: W.cfg4_spheres(384, precision="mixed32"),
+    "neu2d": lambda: W.singular_star(1024),
+    "neu3d": lambda: W.singular_sphere(256, precision="mixed32"),
 }
 DESCR = {
     "cfg1": "2D Dirichlet circle r=0.5, 64x64, u=sin(2 pi x)cos(2 pi y)",
     "cfg2": "2D interface star r=0.5+0.1cos(5t), 1024x1024, jumps from e^x cos y / x^2-y^2, Dirichlet box",
     "cfg3": "3D Dirichlet sphere r=0.6, 256^3, u=sin(pi x)sin(pi y)sin(pi z)",
     "cfg4": "3D Neumann on 16 spheres (seed 0), Dirichlet box, 384^3, u=cos(2x)sinh(y)+z^2",
+    "neu2d": "2D singular pure-Neumann star interior (bordered system), 1024x1024, u=sin(2 pi x+0.7)cos(2 pi y-0.4)",
+    "neu3d": "3D singular pure-Neumann sphere r=0.6 off centre (bordered system), 256^3, u=cos(2x)sinh(y)+z^2",
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -385,6 +389,8 @@ def main():
             P.close()
         ttr[key] = {"ms": float(np.median(dts) * 1e3), "iterations": itp, "second_gs_passes": sp,
                     "reached": bool(ok)}
+        if st["bordered"]:
+            ttr[key]["shift_alpha"] = st["shift_alpha"]
         print(f"[bench] time-to-1e-10 {key}: {ttr[key]}", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel: measured duration x launches per iteration

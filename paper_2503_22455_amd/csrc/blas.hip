@@ -440,15 +440,20 @@ void run_norm2(const double* x, int64_t n, double* part, double* out, hipStream_
 }
 
 // Bordered operator of a singular pure-Neumann problem (Sec. 2.3: the system
-// [L 1; 1^T 0] [u; alpha]).  After y = L x over the box, this adds the shift
-// alpha = x[n] to every unknown of y and writes y[n] = sum of x over the
-// unknowns (deterministic: fixed grid, fixed reduction order).  labels: level-0
-// box labels; n: box size, so x and y hold n + 1 entries.
-__global__ void __launch_bounds__(RED_THREADS) k_border(const double* x, const uint8_t* labels, int64_t n,
-                                                        double* y, double* part) {
+// [L 1; 1^T 0] [u; alpha] = [b; gamma]).  After y = L x over the box, this adds
+// the shift alpha to every unknown of y and writes y[n] = sum of x over the
+// unknowns (deterministic: fixed grid, fixed reduction order).  alpha is read
+// from *alpha_src and stored into x[n]: the preconditioner is the identity on
+// alpha, so z_j inherits it from v_j here instead of in a launch of its own
+// (alpha_src = x + n when x already holds it).  labels: level-0 box labels;
+// n: box size, so x and y hold n + 1 entries.
+__global__ void __launch_bounds__(RED_THREADS) k_border(double* x, const double* alpha_src, const uint8_t* labels,
+                                                        int64_t n, double* y, double* part) {
     double acc[1] = {0.0};
-    const double alpha = x[n];
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double alpha = *alpha_src;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t0 == 0 && alpha_src != x + n) x[n] = alpha;
+    for (int64_t e = t0; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         if (is_unknown(labels[e])) {
             acc[0] += x[e];
             y[e] += alpha;
@@ -457,19 +462,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_border(const double* x, const u
     block_reduce_store(acc, 1, part, 0);
 }
 
-void run_border(const double* x, const uint8_t* labels, int64_t n, double* y, double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_border, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, labels, n, y, part);
+void run_border(double* x, const double* alpha_src, const uint8_t* labels, int64_t n, double* y, double* part,
+                hipStream_t s) {
+    hipLaunchKernelGGL(k_border, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, x, alpha_src, labels, n, y, part);
     IIM_LAUNCH_CHECK();
     final_sum(part, 1, y + n, s);
-}
-
-__global__ void k_copy_scalar(const double* x, double* y) {
-    if (threadIdx.x == 0) *y = *x;
-}
-
-void run_copy_scalar(const double* x, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(64), 0, s, x, y);
-    IIM_LAUNCH_CHECK();
 }
 
 }  // namespace iim

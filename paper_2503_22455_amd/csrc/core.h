@@ -146,10 +146,9 @@ struct Problem {
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;
     void apply_box(const double* x, double* y, int with_data);
-    // the solver's operator: L x, bordered for a singular problem
-    void apply_op(const double* x, double* y);
-    // the solver's preconditioner: one cycle, identity on alpha when bordered
-    void precondition(const double* v, double* z, bool scaled = false, bool out_basis = false);
+    // the solver's operator: L x, bordered for a singular problem; alpha_src
+    // (bordered only) is where x's alpha comes from, x + box.size() by default
+    void apply_op(double* x, double* y, const double* alpha_src = nullptr);
     int64_t krylov_len() const { return box.size() + (singular ? 1 : 0); }
     template <typename T, typename S> bool down_leg(int l, const CastInArgs* cast);
     template <typename T, typename S> const S* up_leg(int l, const S* zres, double* out);

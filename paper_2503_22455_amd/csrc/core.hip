@@ -739,14 +739,12 @@ void Problem::apply_box(const double* x, double* y, int with_data) {
                  opt.beta_plus, opt.beta_minus, x, y, with_data, stream);
 }
 
-void Problem::apply_op(const double* x, double* y) {
+void Problem::apply_op(double* x, double* y, const double* alpha_src) {
     apply_box(x, y, 0);
-    if (singular) run_border(x, levels[0].labels, box.size(), y, red_part, stream);
-}
-
-void Problem::precondition(const double* v, double* z, bool scaled, bool out_basis) {
-    vcycle(v, z, scaled, out_basis);
-    if (singular) run_copy_scalar(v + box.size(), z + box.size(), stream);
+    if (singular) {
+        const int64_t n = box.size();
+        run_border(x, alpha_src ? alpha_src : x + n, levels[0].labels, n, y, red_part, stream);
+    }
 }
 
 // fused pre-smoothing from a zero iterate + residual + restriction on level l
@@ -908,9 +906,10 @@ void Problem::iteration_body(int j, hipEvent_t* evs) {
     const int64_t N = krylov_len();
     double* vj = Vb + (size_t)j * ldv;
     double* zj = Zb + (size_t)j * ldv;
-    precondition(vj, zj, j > 0, true);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
+    vcycle(vj, zj, j > 0, true);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
     if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
-    apply_op(zj, wk);
+    // bordered: the preconditioner is the identity on alpha, so z_j takes v_j's
+    apply_op(zj, wk, vj + box.size());
     if (evs) IIM_HIP(hipEventRecord(evs[2], stream));
     // Classical Gram-Schmidt: h = V^T w (with |w|^2 when the second pass is
     // conditional); the second pass w -= V h with h' = V^T w and |w|^2 in the

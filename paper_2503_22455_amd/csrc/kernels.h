@@ -284,9 +284,10 @@ void run_axpy_multi(const double* Z, int64_t ld, int k, const double* y, double*
 // y = a x + b y
 void run_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t s);
 void run_copy(const double* x, double* y, int64_t n, hipStream_t s);
-// y[unknowns] += x[n]; y[n] = sum of x over the unknowns (bordered singular system)
-void run_border(const double* x, const uint8_t* labels, int64_t n, double* y, double* part, hipStream_t s);
-void run_copy_scalar(const double* x, double* y, hipStream_t s);
+// bordered singular system: x[n] = *alpha_src; y[unknowns] += x[n]; y[n] = sum of
+// x over the unknowns
+void run_border(double* x, const double* alpha_src, const uint8_t* labels, int64_t n, double* y, double* part,
+                hipStream_t s);
 // out[0] = max |x|, out[1] = 1 / max|x| (1 if zero)
 void run_absmax(const double* x, int64_t n, double* part, double* out, hipStream_t s);
 // out[0] = <x, x>

@@ -281,6 +281,20 @@ def cfg4_spheres(n: int = 384, count: int = 16, seed: int = 0, precision: str = 
                     note=f"{len(sp)} spheres, seed {seed}")
 
 
+def singular_star(n: int = 1024, precision: str = "fp64") -> Workload:
+    """2D pure-Neumann problem inside the star r = 0.5 + 0.1 cos 5t: singular,
+    solved through the bordered system; u = sin(2 pi x + 0.7) cos(2 pi y - 0.4)."""
+    return Workload("singular_star_neumann", 2, n, GEOM_STAR2D, [0.0, 0.0, 0.5, 0.1, 5.0],
+                    SIDE_INTERIOR, BC_NEUMANN, exact=ms_shifted_trig(), precision=precision)
+
+
+def singular_sphere(n: int = 256, precision: str = "mixed32") -> Workload:
+    """3D pure-Neumann problem inside the sphere r = 0.6 centred at
+    (0.05, -0.1, 0.03): singular; u = cos(2x) sinh(y) + z^2."""
+    return Workload("singular_sphere_neumann", 3, n, GEOM_SPHERE, [0.05, -0.1, 0.03, 0.6],
+                    SIDE_INTERIOR, BC_NEUMANN, exact=ms_cos_sinh(), precision=precision)
+
+
 def small_spheres_union() -> List[Tuple]:
     """A resolvable-at-small-n stand-in for cfg 4 (3 spheres, radius >= 0.3)."""
     return [((-0.3, -0.3, 0.05), 0.3), ((0.35, 0.25, -0.2), 0.28), ((0.05, 0.38, 0.33), 0.27)]
