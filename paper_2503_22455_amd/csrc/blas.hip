@@ -261,11 +261,13 @@ void run_update_dot(const double* V, int64_t ld, int k, const double* h, double*
 // as the only update it is used only when |h|^2 <= (1 - 1e-4) |w|^2 (see
 // cgs_refine), so at most four decimal digits cancel.  nrm2 is
 // floored at 0 (then y is not finite and the solver takes it as a breakdown)
-// and written to *nrm2_out; block maxima of |y| go to part (the V-cycle's
-// scaling of y is then one second-stage launch away).
+// and written to *nrm2_out; block maxima of |y| over its first n_max entries
+// go to part (the V-cycle's scaling of y is then one second-stage launch
+// away; a bordered vector's last entry, alpha, is not an input of the cycle
+// and stays out of its scale).
 __global__ void __launch_bounds__(RED_THREADS) k_update_scale(const double* V, int64_t ld, int k, const double* h,
-                                                              const double* w, double* y, int64_t n, double* nrm2_out,
-                                                              double* nrm2_host, double* part) {
+                                                              const double* w, double* y, int64_t n, int64_t n_max,
+                                                              double* nrm2_out, double* nrm2_host, double* part) {
     double hh[KCH];
     double ss = 0.0;
 #pragma unroll
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_scale(const double* V, i
         we.x *= inv;
         we.y *= inv;
         st2(y, e, we);
-        mx[0] = fmax(mx[0], fmax(fabs(we.x), fabs(we.y)));
+        mx[0] = fmax(mx[0], fmax(2 * e < n_max ? fabs(we.x) : 0.0, 2 * e + 1 < n_max ? fabs(we.y) : 0.0));
     }
     if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         const int64_t e = n - 1;
@@ -306,19 +308,21 @@ __global__ void __launch_bounds__(RED_THREADS) k_update_scale(const double* V, i
             if (i < k) we -= hh[i] * V[(int64_t)i * ld + e];
         we *= inv;
         y[e] = we;
-        mx[0] = fmax(mx[0], fabs(we));
+        if (e < n_max) mx[0] = fmax(mx[0], fabs(we));
     }
     block_reduce_store(mx, 1, part, 1);
 }
 
 void run_update_scale(const double* V, int64_t ld, int k, const double* h, const double* w, double* y, int64_t n,
-                      double* nrm2_out, double* part, double* scale_out, hipStream_t s, double* nrm2_host) {
+                      double* nrm2_out, double* part, double* scale_out, hipStream_t s, double* nrm2_host,
+                      int64_t n_max) {
+    if (n_max < 0 || n_max > n) n_max = n;
     if (k < 1 || k > KCH) throw Error(IIM_E_INVALID_ARG, "update_scale: 1..12 vectors");
     check_vec(V, ld);
     check_vec(w, 0);
     check_vec(y, 0);
-    hipLaunchKernelGGL(k_update_scale, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, y, n, nrm2_out,
-                       nrm2_host, part);
+    hipLaunchKernelGGL(k_update_scale, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, V, ld, k, h, w, y, n, n_max,
+                       nrm2_out, nrm2_host, part);
     IIM_LAUNCH_CHECK();
     final_sum(part, 1, scale_out, s, 1);
 }

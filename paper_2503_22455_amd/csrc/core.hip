@@ -921,8 +921,9 @@ void Problem::iteration_body(int j, hipEvent_t* evs) {
     const bool gated = opt.orthogonalisation == 1;
     run_multidot(Vb, ldv, j + 1, wk, N, red_part, red_out, stream, rec, gated ? 1 : 0);
     run_update_dot(Vb, ldv, j + 1, red_out, wk, N, j + 1, 1, red_part, red_out + 64, stream, rec + 64, gated);
+    // the next cycle's input scale comes from the box entries only, as for v_0
     run_update_scale(Vb, ldv, j + 1, red_out + 64, wk, Vb + (size_t)(j + 1) * ldv, N, red_out + 128, red_part,
-                     red_scale, stream, rec + 128);
+                     red_scale, stream, rec + 128, box.size());
 }
 
 // ---------------------------------------------------------------------------

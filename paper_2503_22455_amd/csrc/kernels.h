@@ -276,9 +276,11 @@ void run_update_dot_stage1(const double* V, int64_t ld, int k, const double* h, 
 // y = x / sqrt(*nrm2)
 void run_normalize(const double* x, const double* nrm2, double* y, int64_t n, hipStream_t s);
 // y = (w - V h) / sqrt(h[k] - |h|^2) (last CGS pass + normalisation; h[k] = |w|^2);
-// the squared norm to *nrm2_out, max |y| and its reciprocal to scale_out[0..1]
+// the squared norm to *nrm2_out, max |y| over y's first n_max entries (all n if
+// n_max < 0) and its reciprocal to scale_out[0..1]
 void run_update_scale(const double* V, int64_t ld, int k, const double* h, const double* w, double* y, int64_t n,
-                      double* nrm2_out, double* part, double* scale_out, hipStream_t s, double* nrm2_host = nullptr);
+                      double* nrm2_out, double* part, double* scale_out, hipStream_t s, double* nrm2_host = nullptr,
+                      int64_t n_max = -1);
 // x += sum_{i<k} y[i] Z_i  (y on the device)
 void run_axpy_multi(const double* Z, int64_t ld, int k, const double* y, double* x, int64_t n, hipStream_t s);
 // y = a x + b y
