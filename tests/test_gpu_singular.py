@@ -140,3 +140,34 @@ def test_nonsingular_problems_are_not_bordered():
     _, _, st = G.solve()
     assert st["status"] == 0 and st["bordered"] == 0 and st["shift_alpha"] == 0.0, st
     G.close()
+
+
+def test_fp16_storage_iterations_follow_emulation():
+    """FP16 iterate storage costs the bordered solve iterations on the 2D
+    singular star as the grid refines, as it does for non-singular problems:
+    the oracle's cycle with its iterates rounded to half precision gives
+    39 -> 39, 40 -> 48 and 41 -> 143 iterations at 256^2, 512^2 and 1024^2.
+    At 512^2 the device (FP32 arithmetic, FP16 storage) stays near the
+    emulation's count, and the FP64 counts agree."""
+    from tests.test_gpu_mixed import _FP16Stored
+    _announce("fp16 singular emulation")
+    wl = W.singular_star(512)
+    O = oracle_for(wl)
+    L, _ = O.assemble()
+    cpd, _, f = oracle_data(O, wl)
+    b = O.rhs(wl.rhs(O.labels), O.data_vector(cpd))
+    _, _, its64, ok64 = S.fgmres_solve(O, Hierarchy(O), b, rtol=1e-10, max_iters=400)
+    _, _, its16, ok16 = S.fgmres_solve(O, _FP16Stored(O), b, rtol=1e-10, max_iters=400)
+    assert ok64 and ok16 and its16 > its64
+    counts = {}
+    for prec in ("fp64", "mixed16"):
+        G = gpu_for(wl, precision=prec, rtol=1e-10)
+        G.set_boundary_data(cpd, None)
+        G.set_rhs(f)
+        _, _, st = G.solve()
+        G.close()
+        assert st["status"] == 0 and st["bordered"] == 1, st
+        counts[prec] = st["iterations"]
+    print("singular star 512^2 iterations: oracle", its64, its16, "device", counts, file=sys.stderr, flush=True)
+    assert abs(counts["fp64"] - its64) <= 1, (counts, its64)
+    assert abs(counts["mixed16"] - its16) <= max(4, its16 // 4), (counts, its16)
