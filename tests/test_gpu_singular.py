@@ -171,3 +171,33 @@ def test_fp16_storage_iterations_follow_emulation():
     print("singular star 512^2 iterations: oracle", its64, its16, "device", counts, file=sys.stderr, flush=True)
     assert abs(counts["fp64"] - its64) <= 1, (counts, its64)
     assert abs(counts["mixed16"] - its16) <= max(4, its16 // 4), (counts, its16)
+
+
+@pytest.mark.parametrize("name", ["circle-neu64", "sphere-neu24"])
+def test_bordered_wcycle(name):
+    """The W-cycle (cycle index 2) on a singular problem: every coarse visit
+    ends in the bordered coarse solve.  Its cycle against the oracle's, and the
+    bordered solve it preconditions against the bordered direct solve."""
+    _announce("bordered W-cycle", name)
+    wl = CASES[name]()
+    O = oracle_for(wl)
+    G = gpu_for(wl, precision="fp64", rtol=1e-12, cycle="W")
+    H = Hierarchy(O, gamma=2)
+    rng = np.random.default_rng(9)
+    v = np.zeros(O.lab_flat.size)
+    v[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    z = G.vcycle(torch.tensor(v, device="cuda")).cpu().numpy()[O.unknowns]
+    zo = H.precondition(v[O.unknowns])
+    assert np.abs(z - zo).max() <= 1e-11 * np.abs(zo).max(), np.abs(z - zo).max() / np.abs(zo).max()
+    O.assemble()
+    cpd, _, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, None)
+    G.set_rhs(f)
+    u, _, st = G.solve()
+    assert st["status"] == 0 and st["bordered"] == 1, st
+    b = O.rhs(wl.rhs(O.labels), O.data_vector(cpd))
+    ud, ad = S.direct_solve(O, b)
+    uu = u.cpu().numpy()[O.unknowns]
+    assert np.abs(uu - ud).max() <= 1e-10 * np.abs(ud).max()
+    assert abs(st["shift_alpha"] - ad) <= 1e-10 * np.abs(b).max()
+    G.close()
