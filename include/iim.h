@@ -294,7 +294,10 @@ int iim_time_kernel(iim_problem* p, int32_t kernel, int32_t reps, double* avg_ms
 int iim_set_synthetic_data(iim_problem* p, int32_t kind);
 
 /* max |u - u_exact| over the unknowns for a solution u (device full-grid array)
- * of a problem whose data came from iim_set_synthetic_data(kind). */
+ * of a problem whose data came from iim_set_synthetic_data(kind).  For a singular
+ * (bordered) problem, whose u is fixed only up to a constant, the mean of
+ * u - u_exact over the unknowns is removed first (Sec. 2.3 compares singular
+ * solutions mean-free). */
 int iim_synthetic_error(iim_problem* p, int32_t kind, const double* u, double* max_err);
 
 /* ---- serving: continuous batching of independent solves on one device ----

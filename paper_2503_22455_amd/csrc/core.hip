@@ -1110,8 +1110,23 @@ void Problem::synth_data(int kind) {
 double Problem::synth_error(int kind, const double* u_full) {
     if (kind != 1) throw Error(IIM_E_INVALID_ARG, "unknown synthetic data kind");
     unsigned long long* d = (unsigned long long*)(red_out + 250);
+    // a singular problem's u is fixed only up to a constant: its error is
+    // measured after removing the mean of u - u_exact over the unknowns
+    double shift = 0.0;
+    if (singular) {
+        const int nb = run_synth_diff_sum(kind, levels[0].geom, box, levels[0].labels, u_full, red_part, stream);
+        std::vector<double> part(2 * (size_t)nb);
+        IIM_HIP(hipMemcpyAsync(part.data(), red_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+        IIM_HIP(hipStreamSynchronize(stream));
+        double sum = 0.0, cnt = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            sum += part[2 * i];
+            cnt += part[2 * i + 1];
+        }
+        if (cnt > 0.0) shift = sum / cnt;
+    }
     IIM_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), stream));
-    run_synth_err(kind, levels[0].geom, box, levels[0].labels, u_full, d, stream);
+    run_synth_err(kind, levels[0].geom, box, levels[0].labels, u_full, d, stream, shift);
     unsigned long long bits = 0;
     IIM_HIP(hipMemcpyAsync(&bits, d, sizeof(bits), hipMemcpyDeviceToHost, stream));
     IIM_HIP(hipStreamSynchronize(stream));

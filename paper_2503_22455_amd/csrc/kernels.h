@@ -303,6 +303,11 @@ void run_synth_nodes(int kind, const Geom& g, const Box& b, const uint8_t* label
                      double* f, double* boxval, hipStream_t s);
 // atomically maxes the bit pattern of max |u_full - u_exact| over the unknowns into *out
 void run_synth_err(int kind, const Geom& g, const Box& b, const uint8_t* labels, const double* u,
-                   unsigned long long* out, hipStream_t s);
+                   unsigned long long* out, hipStream_t s,
+                   double shift = 0.0);
+// per-block sums of u - u_exact and counts over the unknowns into part[2 * blocks];
+// returns the block count (at most 2048)
+int run_synth_diff_sum(int kind, const Geom& g, const Box& b, const uint8_t* labels, const double* u, double* part,
+                       hipStream_t s);
 
 }  // namespace iim

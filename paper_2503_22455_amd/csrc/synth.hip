@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_synth_nodes(int kind, Geom g, Box b, co
 
 // per-block max |u - u_exact| over the unknowns (u is a full-grid array)
 __global__ void __launch_bounds__(256) k_synth_err(int kind, Geom g, Box b, const uint8_t* labels, const double* u,
-                                                   unsigned long long* out) {
+                                                   double shift, unsigned long long* out) {
     __shared__ double red[256];
     double m = 0.0;
     const int64_t n1 = g.n + 1;
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(256) k_synth_err(int kind, Geom g, Box b, cons
         double x[3] = {0.0, 0.0, 0.0};
         for (int d = 0; d < g.dim; ++d) x[d] = node_coord(g, ijk[d]);
         const int64_t f = ijk[0] + n1 * (ijk[1] + n1 * (int64_t)ijk[2]);
-        double d = fabs(u[f] - exact(kind, g.dim, x).u);
+        double d = fabs(u[f] - exact(kind, g.dim, x).u - shift);
         m = (d > m || d != d) ? d : m;  // NaN propagates
     }
     red[threadIdx.x] = m;
@@ -119,7 +119,50 @@ __global__ void __launch_bounds__(256) k_synth_err(int kind, Geom g, Box b, cons
     }
 }
 
+// Per-block sum of u - u_exact over the unknowns and of their count:
+// part[2 blockIdx.x] and part[2 blockIdx.x + 1] (fixed tree order), for the
+// mean that a singular problem's error is taken relative to.
+__global__ void __launch_bounds__(256) k_synth_diff_sum(int kind, Geom g, Box b, const uint8_t* labels,
+                                                        const double* u, double* part) {
+    __shared__ double rs[256], rc[256];
+    double sum = 0.0, cnt = 0.0;
+    const int64_t n1 = g.n + 1;
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < b.size();
+         l += (int64_t)gridDim.x * blockDim.x) {
+        if (!is_unknown(labels[l])) continue;
+        int ijk[3];
+        b.coords(l, ijk);
+        double x[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < g.dim; ++d) x[d] = node_coord(g, ijk[d]);
+        const int64_t f = ijk[0] + n1 * (ijk[1] + n1 * (int64_t)ijk[2]);
+        sum += u[f] - exact(kind, g.dim, x).u;
+        cnt += 1.0;
+    }
+    rs[threadIdx.x] = sum;
+    rc[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            rs[threadIdx.x] += rs[threadIdx.x + st];
+            rc[threadIdx.x] += rc[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = rs[0];
+        part[2 * blockIdx.x + 1] = rc[0];
+    }
+}
+
 }  // namespace
+
+int run_synth_diff_sum(int kind, const Geom& g, const Box& b, const uint8_t* labels, const double* u, double* part,
+                       hipStream_t s) {
+    const int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 2048);
+    hipLaunchKernelGGL(k_synth_diff_sum, dim3(blocks), dim3(256), 0, s, kind, g, b, labels, u, part);
+    IIM_LAUNCH_CHECK();
+    return blocks;
+}
 
 void run_synth_cp(int kind, int dim, int bc, const CPDev& cp, double beta_plus, double beta_minus, double* cpdata,
                   hipStream_t s) {
@@ -137,9 +180,9 @@ void run_synth_nodes(int kind, const Geom& g, const Box& b, const uint8_t* label
 }
 
 void run_synth_err(int kind, const Geom& g, const Box& b, const uint8_t* labels, const double* u,
-                   unsigned long long* out, hipStream_t s) {
+                   unsigned long long* out, hipStream_t s, double shift) {
     int blocks = (int)std::min<int64_t>(cdiv(b.size(), 256), 2048);
-    hipLaunchKernelGGL(k_synth_err, dim3(blocks), dim3(256), 0, s, kind, g, b, labels, u, out);
+    hipLaunchKernelGGL(k_synth_err, dim3(blocks), dim3(256), 0, s, kind, g, b, labels, u, shift, out);
     IIM_LAUNCH_CHECK();
 }
 

@@ -201,3 +201,26 @@ def test_bordered_wcycle(name):
     assert np.abs(uu - ud).max() <= 1e-10 * np.abs(ud).max()
     assert abs(st["shift_alpha"] - ad) <= 1e-10 * np.abs(b).max()
     G.close()
+
+
+@pytest.mark.parametrize("name", ["circle-neu64", "sphere-neu24"])
+def test_synthetic_error_is_mean_free(name):
+    """Device-made manufactured data on a singular problem: the library's error
+    is max |u - u_exact - mean(u - u_exact)| over the unknowns, the host's
+    mean-free error of the same u, and small (the solution is accurate up to
+    its constant)."""
+    _announce("synthetic mean-free error", name)
+    wl = CASES[name]()
+    O = oracle_for(wl)
+    G = gpu_for(wl, precision="fp64", rtol=1e-12)
+    G.set_synthetic_data(1)
+    u, _, st = G.solve()
+    assert st["status"] == 0 and st["bordered"] == 1, st
+    err = G.synthetic_error(u)
+    ex = W.ms_sin2pi_cos2pi() if wl.dim == 2 else W.ms_sin_pi_3d()
+    X = [c.ravel(order="F")[O.unknowns] for c in wl.node_coords()]
+    d = u.cpu().numpy()[O.unknowns] - ex.u_plus(*X)
+    host = np.abs(d - d.mean()).max()
+    assert abs(err - host) <= 1e-12 * max(host, 1e-300) + 1e-15, (err, host)
+    assert host < 2e-2 and np.abs(d).max() > 0.0
+    G.close()
