@@ -28,9 +28,13 @@ annihilates constants too; it is bordered like the fine system, [A 1; 1^T 0],
 and the coarse solve returns the first block of the bordered solution with a
 zero last entry on the right (the coarse values then sum to zero).
 
-Parity: pinned by the Dirichlet V-cycle contraction (rho < 0.1, independent of
-n), by transfer operators reproducing constants away from Gamma, and by the
-FGMRES solution matching the direct solve (tests/test_oracle_mg.py).  The
+Parity: pinned by the Dirichlet V-cycle contraction on the standard (unshifted)
+SW operator (rho < 0.09, independent of n, the rate the paper quotes), by the
+shifted cycle staying fast and n-independent, by transfer operators reproducing
+constants away from Gamma, by the averaging interpolation equalling the
+multilinear one wherever every parent lies in the domain and reproducing
+constants wherever one does, and by the FGMRES solution matching the direct
+solve (tests/test_oracle_mg.py).  The
 W-cycle is pinned by its identity with the V-cycle on two levels (the coarse
 solve is exact, so the second visit changes nothing), by a contraction no
 worse than the V-cycle's, by the cycle from a non-zero start equalling that
@@ -58,9 +62,13 @@ def level_sizes(n: int, coarsest: int = 8) -> List[int]:
 
 
 class Hierarchy:
-    def __init__(self, prob, coarsest: int = 8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1):
+    def __init__(self, prob, coarsest: int = 8, nu_pre: int = 2, nu_post: int = 2, gamma: int = 1,
+                 shift: bool = True):
         """prob: an IIMProblem (provides grid, geometry, side, bc, beta);
-        gamma: cycle index (1 = V-cycle, 2 = W-cycle)."""
+        gamma: cycle index (1 = V-cycle, 2 = W-cycle); shift: the intersection
+        shift of Sec. 3.2 on every level (the preconditioner's setting; False
+        gives the standard Shortley-Weller operator whose cycle the paper
+        quotes from Trottenberg et al.)."""
         self.prob = prob
         self.dim = prob.dim
         self.nu_pre, self.nu_post = nu_pre, nu_post
@@ -70,7 +78,7 @@ class Hierarchy:
         for l, nl in enumerate(self.sizes):
             g = Grid(prob.dim, nl, prob.grid.h * 2 ** l)
             self.levels.append(SWLevel(g, prob.geom, prob.side, prob.bc,
-                                       prob.beta[PLUS], prob.beta[MINUS], shift=True))
+                                       prob.beta[PLUS], prob.beta[MINUS], shift=shift))
         if prob.side == SIDE_INTERFACE or prob.bc == BC_DIRICHLET:
             self.mode = "linear"
         else:

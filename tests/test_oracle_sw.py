@@ -125,3 +125,49 @@ def test_unshifted_operator_exceeds_the_shift_bound():
     P = IIMProblem(2, 64, W.GEOM_SPHERE, [0.013, -0.021, 0.55], 0, 0)
     lev = SWLevel(P.grid, P.geom, 0, 0, 1.0, 1.0, shift=False)
     assert np.abs(lev.A.diagonal()).max() > 8.0 * 2 / P.grid.h ** 2
+
+
+def test_interface_wall_value_on_a_flat_interface(monkeypatch):
+    """The interface rows' wall value (Sec. 3.1, with the interface shifted to
+    the midpoint): on a flat interface x = x0 that already lies halfway between
+    two grid columns the shift changes nothing, and for a piecewise-linear u
+    with [u] = 0 and beta^+ du^+/dx = beta^- du^-/dx the flux-continuity wall
+    value is exact, so every row of A u vanishes to round-off (A is the plain
+    Laplacian of each side).  beta^-/beta^+ = 2 makes the slopes differ, so
+    exchanging alpha^+ and alpha^- leaves an O(1/h) residual next to the
+    interface.  The interface plane meets the box, which the library's labels
+    reject; the test builds its own labels (x <= x0: Omega^-, box faces:
+    known values)."""
+    from oracle import PLUS, MINUS, BOX
+    import oracle.sw as S
+
+    n = 32
+    h = 2.0 / n
+    x0 = -1.0 + 13.5 * h
+
+    def flat_labels(grid, geom, side):
+        X = grid.node_coords()
+        lab = np.where(X[0] <= x0, MINUS, PLUS).astype(np.uint8)
+        for d in range(grid.dim):
+            idx = [slice(None)] * grid.dim
+            for end in (0, grid.n):
+                idx[d] = end
+                lab[tuple(idx)] = BOX
+        return lab
+
+    monkeypatch.setattr(S, "node_labels", flat_labels)
+    for dim in (2, 3):
+        grid = Grid(dim, n)
+        lev = SWLevel(grid, None, 2, 2, beta_plus=1.0, beta_minus=2.0, shift=True)
+        X = [c.ravel(order="F")[lev.unknowns] for c in grid.node_coords()]
+        a_minus = 0.7
+        a_plus = a_minus * 2.0 / 1.0     # beta^+ u'^+ = beta^- u'^-
+        u = np.where(X[0] <= x0, a_minus * (X[0] - x0), a_plus * (X[0] - x0)) + 0.3 + 0.2 * X[1]
+        r = lev.A @ u
+        # rows whose stencil reaches a box face see the face value 0, not u
+        ijk = np.array([grid.unflat(int(f)) for f in lev.unknowns])
+        away = np.all((ijk >= 2) & (ijk <= n - 2), axis=1)
+        scale = np.abs(lev.A).max() * np.abs(u).max()
+        assert np.abs(r[away]).max() <= 1e-13 * scale, (dim, np.abs(r[away]).max() / scale)
+        near = away & (np.abs(X[0] - x0) < h)
+        assert near.sum() >= 2 * (n - 3) ** (dim - 1)
