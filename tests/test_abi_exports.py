@@ -78,3 +78,34 @@ def test_default_options():
     assert (o.order_n, o.order_k, o.restart, o.nu_pre, o.nu_post, o.coarsest_n) == (4, 5, 10, 2, 2, 8)
     assert o.rtol == 1e-10 and o.use_graph == 2 and o.colour_split == 1 and o.fused_smoothing == 1
     assert o.orthogonalisation == 1
+
+
+def test_disconnected_interior_neumann_union_is_rejected():
+    """A singular problem is bordered with one constant (Sec. 2.3), which pins
+    the null space of a connected domain only: iim_create rejects the interior
+    of two disjoint spheres with a Neumann condition before touching the
+    device, and lets the interior of two overlapping ones through that check
+    (a host-only path: no GPU is needed to see the rejection)."""
+    if not os.path.exists(LIB):
+        pytest.skip("libiim.so not built in this checkout")
+    from paper_2503_22455_amd import iim
+    L = iim.lib()
+
+    def create(spheres):
+        params = [float(len(spheres))]
+        for c, r in spheres:
+            params += list(c) + [r]
+        pa = (ctypes.c_double * len(params))(*params)
+        g = iim.Grid(3, 32, -1.0, 1.0)
+        geo = iim.Geometry(iim.GEOM_SPHERE_UNION, iim.SIDE_INTERIOR, iim.BC_NEUMANN, len(params), pa)
+        o = iim.make_options()
+        h = ctypes.c_void_p()
+        rc = L.iim_create(ctypes.byref(g), ctypes.byref(geo), ctypes.byref(o), None, ctypes.byref(h))
+        if rc == 0:
+            L.iim_destroy(h)
+        return rc, L.iim_last_error().decode()
+
+    rc, msg = create([((-0.4, 0.0, 0.0), 0.3), ((0.4, 0.0, 0.0), 0.3)])
+    assert rc == -1 and "not connected" in msg, (rc, msg)
+    rc, msg = create([((-0.2, 0.0, 0.0), 0.3), ((0.2, 0.0, 0.0), 0.3)])
+    assert "not connected" not in msg, (rc, msg)

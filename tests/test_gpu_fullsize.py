@@ -93,3 +93,168 @@ def test_singular_sphere_256_bordered_sampled():
     scale = 25.0 / O.grid.h ** 2
     assert np.abs(r).max() <= 1e-10 * bnorm + 1e-12 * scale * np.abs(uu).max(), (np.abs(r).max(), bnorm)
     G.close()
+
+
+# ---------------------------------------------------------------------------
+# the 16-sphere Neumann configuration at 384^3, as benchmarked
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cfg4_pair():
+    import sys
+    print("case: cfg4 16 spheres 384^3 (oracle set-up ~40 s)", file=sys.stderr, flush=True)
+    wl = W.cfg4_spheres(384, precision="mixed32")
+    O = oracle_for(wl)
+    G = gpu_for(wl, precision="mixed32", rtol=1e-10)
+    yield wl, O, G
+    G.close()
+
+
+def test_cfg4_384_labels_points_stencils(cfg4_pair):
+    """Labels bit for bit, x_c to 1e-14 and 40 sampled least-squares stencils
+    (sets exactly, weights to 1e-12 of the largest) at 384^3 (Sec. 2.1)."""
+    wl, O, G = cfg4_pair
+    assert (G.node_labels() == O.lab_flat).all()
+    xyz, nrm = G.control_points()
+    oxyz, onrm = O.cp_arrays()
+    assert xyz.shape == oxyz.shape
+    assert np.abs(xyz - oxyz).max() <= 1e-14
+    assert np.abs(nrm - onrm).max() <= 1e-12
+    assert G.info()["n_unknowns"] == O.unknowns.size
+    rng = np.random.default_rng(21)
+    for c in rng.choice(O.ncp, size=40, replace=False):
+        idx, wts = G.ls_stencil(int(c), 1)
+        st = O.stencil(int(c), 1)
+        assert list(idx) == list(st.idx), c
+        assert np.abs(wts - st.S).max() <= 1e-12 * np.abs(st.S).max(), c
+
+
+def test_cfg4_384_sampled_apply(cfg4_pair):
+    """300 operator rows (150 irregular, 150 anywhere), without and with the
+    boundary data, computed by the oracle one row at a time (Sec. 2.1, 2.3)."""
+    wl, O, G = cfg4_pair
+    rng = np.random.default_rng(22)
+    x = np.zeros(O.lab_flat.size)
+    x[O.unknowns] = rng.standard_normal(O.unknowns.size)
+    cpd, box, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, box)
+    ug = O.data_vector(cpd, wl.box_data())
+    xt = torch.tensor(x, device="cuda")
+    y = G.apply(xt).cpu().numpy()
+    yd = G.apply(xt, with_data=True).cpu().numpy()
+    del xt
+    irr = np.nonzero(~O.regular_mask() & (O.uindex >= 0))[0]
+    nodes = np.concatenate([rng.choice(irr, size=150, replace=False), rng.choice(O.unknowns, size=150, replace=False)])
+    yo = O.apply_rows(nodes, x)
+    yod = O.apply_rows(nodes, x, with_data=True, u_gamma=ug)
+    scale = 25.0 / O.grid.h ** 2
+    assert np.abs(y[nodes] - yo).max() <= 1e-13 * scale
+    assert np.abs(yd[nodes] - yod).max() <= 1e-13 * (scale + np.abs(yod).max())
+
+
+def test_cfg4_384_mixed_solve_residual_rows(cfg4_pair):
+    """The benchmarked solve (FP64 outer, FP32 V-cycle) reaches 1e-10, and the
+    oracle's own rows of f - L u - L_Gamma u_Gamma at 300 sampled unknowns are
+    within 1e-10 ||b|| (plus the round-off of one row)."""
+    wl, O, G = cfg4_pair
+    cpd, box, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, box)
+    G.set_rhs(f)
+    u, _, st = G.solve()
+    assert st["status"] == 0 and st["final_rel_residual"] <= 1e-10, st
+    uf = np.nan_to_num(u.cpu().numpy())
+    del u
+    lg = G.apply(torch.zeros(O.lab_flat.size, dtype=torch.float64, device="cuda"), with_data=True).cpu().numpy()
+    bnorm = np.linalg.norm((f - lg)[O.unknowns])
+    ug = O.data_vector(cpd, wl.box_data())
+    rng = np.random.default_rng(23)
+    irr = np.nonzero(~O.regular_mask() & (O.uindex >= 0))[0]
+    nodes = np.concatenate([rng.choice(irr, size=150, replace=False), rng.choice(O.unknowns, size=150, replace=False)])
+    r = f[nodes] - O.apply_rows(nodes, uf, with_data=True, u_gamma=ug)
+    scale = 25.0 / O.grid.h ** 2
+    assert np.abs(r).max() <= 1e-10 * bnorm + 1e-13 * scale * np.abs(uf).max(), (np.abs(r).max(), bnorm)
+
+
+# ---------------------------------------------------------------------------
+# the four-entries-per-thread 3D half-sweep (levels with >= 2^20 entries per
+# colour): a 3-sphere Neumann union at 128^3, whose 133^3 level-0 box holds
+# 1.18 M entries per colour
+# ---------------------------------------------------------------------------
+def test_four_entry_sweep_vcycle_against_oracle():
+    """Level 0 of this problem takes the four-entry half-sweep.  One red-black
+    sweep and the whole V-cycle (Sec. 3.3) in FP64 match the oracle's to 1e-12;
+    the FP32 cycle to 2e-5; colour-split and storage-box layouts give the
+    same cycle bit for bit."""
+    import sys
+    from oracle.mg import Hierarchy
+    print("case: 3-sphere Neumann union 128^3, four-entry half-sweep", file=sys.stderr, flush=True)
+    wl = W.cfg4_spheres(128, spheres=W.small_spheres_union(), precision="fp64")
+    O = oracle_for(wl)
+    H = Hierarchy(O)
+    G = gpu_for(wl, precision="fp64")
+    info = G.info()
+    half = -(-info["box_dims"][0] // 2) * info["box_dims"][1] * info["box_dims"][2]
+    assert half >= 1 << 20, half
+    rng = np.random.default_rng(31)
+    lev = H.levels[0]
+    v = np.zeros(lev.lab_flat.size)
+    v[lev.unknowns] = rng.standard_normal(lev.unknowns.size)
+    z0 = np.zeros_like(v)
+    z0[lev.unknowns] = rng.standard_normal(lev.unknowns.size)
+    zt = torch.tensor(z0, device="cuda")
+    G.level_op(0, 1, torch.tensor(v, device="cuda"), zt)
+    zo = z0[lev.unknowns].copy()
+    H.rbgs(0, zo, v[lev.unknowns])
+    assert np.abs(zt.cpu().numpy()[lev.unknowns] - zo).max() <= 1e-12 * (np.abs(zo).max() + 1)
+    vt = torch.tensor(v, device="cuda")
+    z64 = G.vcycle(vt).cpu().numpy()
+    zo = H.precondition(v[O.unknowns])
+    err = np.abs(z64[O.unknowns] - zo).max() / np.abs(zo).max()
+    assert err <= 1e-12, err
+    G.close()
+    Gb = gpu_for(wl, precision="fp64", colour_split=False)
+    assert torch.equal(Gb.vcycle(vt).cpu(), torch.tensor(z64)), "colour-split and box layouts differ"
+    Gb.close()
+    G32 = gpu_for(wl, precision="mixed32")
+    z32 = G32.vcycle(vt).cpu().numpy()[O.unknowns]
+    err32 = np.abs(z32 - zo).max() / np.abs(zo).max()
+    assert err32 <= 2e-5, err32
+    G32.close()
+
+
+# ---------------------------------------------------------------------------
+# the 1024^2 interface star in all-FP64 against the oracle's direct solve
+# ---------------------------------------------------------------------------
+def test_cfg2_star_1024_fp64_solution_matches_direct():
+    """The all-FP64 solve of the benchmarked 1024^2 interface problem, iterated
+    to rtol 1e-14, against the oracle's sparse direct solve of the assembled
+    system (Sec. 2.2, 2.3), refined once: within 1e-12 of max |u| (condition
+    number about 6e5; the direct solve takes about a minute with a
+    minimum-degree ordering)."""
+    import sys
+    import scipy.sparse.linalg as spla
+    print("case: cfg2 star 1024^2 FP64 vs direct solve", file=sys.stderr, flush=True)
+    wl = W.cfg2_star(1024)
+    O = oracle_for(wl)
+    G = gpu_for(wl, precision="fp64", rtol=1e-14, max_iters=400)
+    L, LG = O.assemble()
+    cpd, box, f = oracle_data(O, wl)
+    G.set_boundary_data(cpd, box)
+    G.set_rhs(f)
+    u, _, st = G.solve()
+    assert st["status"] == 0, st
+    uu = u.cpu().numpy()[O.unknowns]
+    G.close()
+    ug = O.data_vector(cpd, wl.box_data())
+    b = O.rhs(wl.rhs(O.labels), ug)
+    assert np.linalg.norm(b - L @ uu) <= 1e-13 * np.linalg.norm(b)
+    # one step of iterative refinement: the factorisation alone leaves the
+    # direct solution 1.8e-12 (relative to max |u|) from the refined one, whose
+    # further corrections are 3e-14 (measured)
+    lu = spla.splu(L.tocsc(), permc_spec="MMD_AT_PLUS_A", options=dict(SymmetricMode=True))
+    ud = lu.solve(b)
+    ud = ud + lu.solve(b - L @ ud)
+    assert np.linalg.norm(b - L @ ud) <= 1e-14 * np.linalg.norm(b)
+    err = np.abs(uu - ud).max() / np.abs(ud).max()
+    print(f"cfg2 1024^2 FP64: {st['iterations']} its, rel res {st['final_rel_residual']:.2e}, "
+          f"max|u - u_direct|/max|u_direct| = {err:.2e}", file=sys.stderr, flush=True)
+    assert err <= 1e-12, err

@@ -46,7 +46,8 @@ def test_bordered_solve_matches_oracle(name):
     wl = CASES[name]()
     O = oracle_for(wl, order_n=wl.order[0], order_k=wl.order[1])
     assert S.is_singular(O)
-    G = gpu_for(wl, precision="fp64", rtol=1e-12)
+    # the bordered FP64 residual floors at about 1.7e-14 (measured on the star)
+    G = gpu_for(wl, precision="fp64", rtol=3e-14, max_iters=600)
     H = Hierarchy(O)
     rng = np.random.default_rng(8)
     v = np.zeros(O.lab_flat.size)
@@ -65,10 +66,15 @@ def test_bordered_solve_matches_oracle(name):
     uu = u.cpu().numpy()[O.unknowns]
     alpha = st["shift_alpha"]
     r = np.concatenate([b - L @ uu - alpha, [-uu.sum()]])
-    assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(b), np.linalg.norm(r) / np.linalg.norm(b)
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(b), np.linalg.norm(r) / np.linalg.norm(b)
     ud, ad = S.direct_solve(O, b)
-    assert np.abs(uu - ud).max() <= 1e-10 * np.abs(ud).max(), np.abs(uu - ud).max() / np.abs(ud).max()
-    assert abs(alpha - ad) <= 1e-10 * np.abs(b).max(), (alpha, ad)
+    # all-FP64, solved to its residual floor: u within 1e-12 of the bordered
+    # direct solve, as for the non-singular cases
+    eu = np.abs(uu - ud).max() / np.abs(ud).max()
+    ea = abs(alpha - ad) / np.abs(b).max()
+    _announce(f"{name}: {st['iterations']} its, u rel err {eu:.2e}, alpha err / max|b| {ea:.2e}")
+    assert eu <= 1e-12, eu
+    assert ea <= 1e-12, (alpha, ad)
     assert abs(ad) > 1e-6  # the shift is really exercised
     # the mean-free error is the oracle's
     ue = O.from_full(wl.exact_solution(O.labels))
