@@ -8,11 +8,13 @@ relative residual of 1e-10.  Inputs (boundary data sampled at the library's
 control points, f on the grid) are resident in device memory before the timed
 region.  Prints one JSON line.
 
-Default workload: 2D interface problem, 1024 x 1024, five-lobe star
-r = 0.5 + 0.1 cos(5 theta), u = e^x cos y inside / x^2 - y^2 outside, jumps from
-these, Dirichlet box, FP64 solve (the mixed-precision solve of the same problem
-is timed beside it).  Other workloads: --workload cfg1|cfg3|cfg4; --serve runs
-the request stream (continuous batching on the solve server) instead.
+Default workload: the largest single-GPU configuration, 3D Neumann problem on
+the exterior of 16 spheres (seed 0) with a Dirichlet box, 384^3 (54.9 million
+unknowns), FP64 operator and Krylov with an FP32 V-cycle; the FP64 and the
+FP16-storage V-cycles of the same problem are timed beside it.  The 1024^2
+interface star (all FP64) is reported as a secondary key.  Other workloads:
+--workload cfg1|cfg2|cfg3|neu2d|neu3d; --serve runs the request stream
+(continuous batching on the solve server) instead.
 """
 from __future__ import annotations
 
@@ -156,15 +158,43 @@ def kernel_roofline(wl, precision, torch, nu, reps=20):
     return out, info
 
 
-def cpu_baseline(wl, its_gpu, nu, sample_iters=3):
-    """The oracle as it stands, single-threaded, on a bounded sample of the same
-    workload: its full setup (labels, control points, fits, assembly, SW
-    hierarchy, right-hand side) plus `sample_iters` FGMRES iterations; the
-    solve time is extrapolated to the GPU's iteration count."""
+def cpu_info():
+    """Host CPU model and counts from lscpu (empty fields if it is missing)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except Exception:
+        out = ""
+    for ln in out.splitlines():
+        k, _, v = ln.partition(":")
+        k, v = k.strip(), v.strip()
+        if k in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+            info[k] = v
+    return {"model": info.get("Model name"), "sockets": info.get("Socket(s)"),
+            "cores_per_socket": info.get("Core(s) per socket"), "threads_per_core": info.get("Thread(s) per core"),
+            "cpus": info.get("CPU(s)"), "os_cpu_count": os.cpu_count()}
+
+
+# the oracle's smallest resolvable size of each workload's geometry for the
+# CPU baseline sample (its |kappa h| < 1/4 check), where the full size does
+# not fit a bench run: at 384^3 its assembly alone would take hours
+CPU_SAMPLE = {"cfg4": lambda: W.cfg4_spheres(128, precision="mixed32")}
+
+
+def cpu_baseline(wl, its_gpu, sample_iters=2):
+    """The oracle as it stands, on a bounded sample of the same workload: its
+    full setup (labels, control points, fits, assembly, SW hierarchy,
+    right-hand side) on one thread, then `sample_iters` FGMRES iterations on one
+    thread and again on every thread the process may use; the solve is
+    extrapolated to the GPU's iteration count.  The setup is a Python loop of
+    small least-squares solves that more threads do not speed up, so it is
+    timed once, on one thread."""
     from threadpoolctl import threadpool_limits
     from oracle.iim import IIMProblem
     from oracle.mg import Hierarchy
     from oracle.krylov import fgmres
+    threads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
     with threadpool_limits(1):
         t0 = time.perf_counter()
         O = IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus,
@@ -175,16 +205,23 @@ def cpu_baseline(wl, its_gpu, nu, sample_iters=3):
         b = O.rhs(wl.rhs(O.labels), ug)
         H = Hierarchy(O, gamma=2 if getattr(wl, "cycle", "V") == "W" else 1)
         t1 = time.perf_counter()
-        fgmres(lambda v: L @ v, H.precondition, b, rtol=1e-30, max_iters=sample_iters)
-        t2 = time.perf_counter()
+    t_iter = {}
+    for th in sorted({1, threads}):
+        with threadpool_limits(th):
+            ta = time.perf_counter()
+            fgmres(lambda v: L @ v, H.precondition, b, rtol=1e-30, max_iters=sample_iters)
+            t_iter[th] = (time.perf_counter() - ta) / sample_iters
+    nu = int(O.unknowns.size)
     t_setup = t1 - t0
-    t_iter = (t2 - t1) / sample_iters
-    t_total = t_setup + its_gpu * t_iter
-    return {"value": nu / t_total, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle setup ({t_setup:.1f} s) + {sample_iters} FGMRES iterations "
-                       f"({t_iter:.2f} s each) on the same workload, single thread, solve extrapolated "
-                       f"to the GPU's {its_gpu} iterations"),
-            "t_setup_s": t_setup, "t_iter_s": t_iter}
+    val = {th: nu / (t_setup + its_gpu * t) for th, t in t_iter.items()}
+    return {"value": val[threads], "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle on the same geometry and data at n = {wl.n} ({nu} unknowns): setup "
+                       f"({t_setup:.1f} s, one thread) + {sample_iters} FGMRES iterations "
+                       f"({t_iter[threads]:.2f} s each on {threads} threads, {t_iter[1]:.2f} s on one), "
+                       f"solve extrapolated to the GPU's {its_gpu} iterations"),
+            "extrapolated": True, "n": wl.n, "unknowns": nu, "t_setup_s": t_setup,
+            "t_iter_s": t_iter[threads], "single_thread": {"value": val[1], "t_iter_s": t_iter[1]},
+            "cpu": cpu_info()}
 
 
 def nearest_rank(values, q):
@@ -302,7 +339,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg4", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, help="override the workload's precision")
     ap.add_argument("--order", type=int, default=4, choices=(4, 6),
                     help="interior order of the discretisation: 4 = the (4,5) scheme, 6 = the (6,7) scheme")
@@ -310,6 +347,8 @@ def main():
                     help="Arnoldi step: 1 one Gram-Schmidt pass, a second only where needed; 0 two passes")
     ap.add_argument("--cycle", default="V", choices=("V", "W"), help="the preconditioner's multigrid cycle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--secondary", type=int, default=1,
+                    help="1: also measure the 1024^2 interface star (all FP64) as a secondary key")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the request-stream workload instead")
     ap.add_argument("--serve-count", type=int, default=2000)
@@ -341,74 +380,19 @@ def main():
         wl.order = (6, 7)
     wl.orthogonalisation = args.orthogonalisation
     wl.cycle = args.cycle
-    cpd, box, f, nu = prepare(wl, torch)
-    print(f"[bench] workload {args.workload}: {nu} unknowns, precision {prec}", file=sys.stderr, flush=True)
+    m = measure(args.workload, wl, prec, args.steps, args.warmup, torch, orth=args.orthogonalisation,
+                mixed=not args.no_mixed, roofline=True)
 
-    for _ in range(args.warmup):
-        one_step(wl, prec, cpd, box, f, torch)
-    torch.cuda.synchronize()
-    lat, setup, its, res = [], [], [], []
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        dt, ds, st, info = one_step(wl, prec, cpd, box, f, torch)
-        lat.append(dt)
-        setup.append(ds)
-        its.append(st["iterations"])
-        res.append(st["final_rel_residual"])
-        print(f"[bench] step {s}: {dt*1e3:.1f} ms (setup {ds*1e3:.1f} ms, {st['iterations']} its, "
-              f"res {st['final_rel_residual']:.2e})", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    ms_per_step = total / args.steps * 1e3
-    value = nu * args.steps / total
-
-    # time to 1e-10 (solve only) for FP64 and mixed precision on the same problem
-    # (and, for the workload's precision, with the other Arnoldi variant)
-    ttr = {}
-    other = 1 - args.orthogonalisation
-    runs = [(p, args.orthogonalisation) for p in (["fp64", "mixed32", "mixed16"] if not args.no_mixed else [prec])]
-    runs.append((prec, other))
-    for p, orth in runs:
-        key = p if orth == args.orthogonalisation else f"{p}+{'cgs2' if orth == 0 else 'cgs1'}"
-        one_step(wl, p, cpd, box, f, torch)
-        dts = []
-        itp = 0
-        for _ in range(3):
-            from paper_2503_22455_amd import iim
-            P = iim.from_workload(wl, precision=p, orthogonalisation=orth)
-            P.set_boundary_data(cpd, box)
-            P.set_rhs(f)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            u, hist, st = P.solve()
-            torch.cuda.synchronize()
-            dts.append(time.perf_counter() - t0)
-            itp = st["iterations"]
-            sp = st["second_passes"]
-            ok = st["final_rel_residual"] <= 1e-10
-            P.close()
-        ttr[key] = {"ms": float(np.median(dts) * 1e3), "iterations": itp, "second_gs_passes": sp,
-                    "reached": bool(ok)}
-        if st["bordered"]:
-            ttr[key]["shift_alpha"] = st["shift_alpha"]
-        print(f"[bench] time-to-1e-10 {key}: {ttr[key]}", file=sys.stderr, flush=True)
-
-    # roofline of the dominant kernel: measured duration x launches per iteration
-    kr, info = kernel_roofline(wl, prec, torch, nu)
-    launches = {0: 1, 1: 1, 2: 2 * 2, 3: 1, 4: 1, 5: 2, 8: 1, 9: 1}   # per FGMRES iteration (nu_pre = nu_post = 2)
-    dom = max(kr, key=lambda k: kr[k][1] * launches[k])
-    name, ms, algo_bytes = kr[dom]
-    achieved = algo_bytes / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, dom)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else int(traffic), "kernel": name,
-                "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(algo_bytes)}
-    kernels = {kr[k][0]: {"avg_us": round(kr[k][1] * 1e3, 2),
-                          "GBs": round(kr[k][2] / (kr[k][1] * 1e-3) / 1e9, 1)} for k in kr}
-    for k in kr:
-        print(f"[bench] kernel {kr[k][0]}: {kr[k][1]*1e3:.2f} us, {kr[k][2]/(kr[k][1]*1e-3)/1e9:.1f} GB/s",
-              file=sys.stderr, flush=True)
+    secondary = {}
+    if args.secondary and args.workload != "cfg2":
+        # the 1024^2 interface star, all FP64, the paper's 2D interface case
+        w2 = WORKLOADS["cfg2"]()
+        m2 = measure("cfg2", w2, w2.precision, max(3, args.steps // 2), 1, torch, orth=1, mixed=True,
+                     roofline=False, mixed16=False, other_arnoldi=False)
+        secondary["cfg2"] = {"workload": DESCR["cfg2"], "value": m2["value"], "unit": "DOF/s",
+                             "ms_per_step": m2["ms_per_step"], "unknowns": m2["nu"], "precision": w2.precision,
+                             "iterations": m2["iterations"], "time_to_1e-10": m2["ttr"],
+                             "note": "working set inside the 256 MB last-level cache: DOF/s only, no HBM fraction"}
 
     serving = None
     if args.serve_short > 0:
@@ -421,32 +405,123 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, int(np.median(its)), nu)
-        print(f"[bench] cpu baseline: {cpu['value']:.3g} DOF/s", file=sys.stderr, flush=True)
+        ws = wl
+        if args.workload in CPU_SAMPLE:
+            ws = CPU_SAMPLE[args.workload]()
+            ws.order, ws.cycle = wl.order, wl.cycle
+        cpu = cpu_baseline(ws, m["iterations"])
+        print(f"[bench] cpu baseline: {cpu['value']:.3g} DOF/s ({cpu['sample']})", file=sys.stderr, flush=True)
+        if "cfg2" in secondary:
+            c2 = cpu_baseline(WORKLOADS["cfg2"](), secondary["cfg2"]["iterations"])
+            secondary["cfg2"]["cpu_baseline"] = c2
+            print(f"[bench] cpu baseline cfg2: {c2['value']:.3g} DOF/s", file=sys.stderr, flush=True)
 
-    lat_sorted = sorted(lat)
-    def pct(q):
-        return lat_sorted[min(len(lat_sorted) - 1, max(0, math.ceil(q * len(lat_sorted)) - 1))] * 1e3
+    dtype = "f64" if prec == "fp64" else ("f64+f32" if prec == "mixed32" else "f64+f32/f16")
+    config = {"workload": DESCR[args.workload] + (", (6,7) scheme" if args.order == 6 else ""),
+              "n": wl.n, "dim": wl.dim, "unknowns": m["nu"], "order": list(wl.order),
+              "precision": prec, "rtol": 1e-10,
+              "arnoldi": "CGS, second pass where needed" if args.orthogonalisation else "CGS2",
+              "cycle": args.cycle}
+    if args.workload == "cfg4" and prec != "mixed16":
+        config["precision_note"] = PRECISION_NOTE_CFG4
     out = {
         "metric": "DOF/s and time-to-1e-10 residual (mixed vs FP64) + p50/p99 solve latency",
-        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else ("f64+f32" if prec == "mixed32" else "f64+f32/f16"),
-        "data": "synthetic",
-        "config": {"workload": DESCR[args.workload] + (", (6,7) scheme" if args.order == 6 else ""),
-                   "n": wl.n, "dim": wl.dim, "unknowns": nu, "order": list(wl.order),
-                   "precision": prec, "rtol": 1e-10,
-                   "arnoldi": "CGS, second pass where needed" if args.orthogonalisation else "CGS2",
-                   "cycle": args.cycle},
-        "p50_ms": pct(0.5), "p99_ms": pct(0.99), "solves_per_s": args.steps / total,
-        "setup_ms_median": float(np.median(setup) * 1e3), "iterations": int(np.median(its)),
-        "final_rel_residual_max": float(max(res)),
-        "time_to_1e-10": ttr,
-        "roofline": roofline, "kernels": kernels,
+        "value": m["value"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic", "config": config,
+        "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"], "solves_per_s": m["solves_per_s"],
+        "setup_ms_median": m["setup_ms_median"], "iterations": m["iterations"],
+        "final_rel_residual_max": m["final_rel_residual_max"],
+        "time_to_1e-10": m["ttr"],
+        "roofline": m["roofline"], "kernels": m["kernels"],
+        "secondary": secondary or None,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+PRECISION_NOTE_CFG4 = (
+    "this configuration names FP16 smoother storage; with it the outer solve needs about five times the "
+    "iterations and is slower to 1e-10 than with the FP32 V-cycle, so the FP32 V-cycle is the default (FP16 "
+    "storage is kept only where the outer iteration count holds); the FP16-storage solve is timed under "
+    "time_to_1e-10.mixed16")
+
+
+def measure(name, wl, prec, steps, warmup, torch, orth=1, mixed=True, roofline=True, mixed16=True,
+            other_arnoldi=True):
+    """Steps of the whole path (setup + data + solve) on one workload, the
+    solve's time to 1e-10 in each V-cycle precision, and the kernels' rooflines."""
+    cpd, box, f, nu = prepare(wl, torch)
+    print(f"[bench] workload {name}: {nu} unknowns, precision {prec}", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        one_step(wl, prec, cpd, box, f, torch)
+    torch.cuda.synchronize()
+    lat, setup, its, res = [], [], [], []
+    t_start = time.perf_counter()
+    for s in range(steps):
+        dt, ds, st, info = one_step(wl, prec, cpd, box, f, torch)
+        lat.append(dt)
+        setup.append(ds)
+        its.append(st["iterations"])
+        res.append(st["final_rel_residual"])
+        print(f"[bench] {name} step {s}: {dt*1e3:.1f} ms (setup {ds*1e3:.1f} ms, {st['iterations']} its, "
+              f"res {st['final_rel_residual']:.2e})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    out = {"nu": nu, "value": nu * steps / total, "ms_per_step": total / steps * 1e3,
+           "solves_per_s": steps / total, "setup_ms_median": float(np.median(setup) * 1e3),
+           "iterations": int(np.median(its)), "final_rel_residual_max": float(max(res)),
+           "p50_ms": nearest_rank(lat, 0.5) * 1e3, "p99_ms": nearest_rank(lat, 0.99) * 1e3}
+
+    # time to 1e-10 (solve only) for FP64 and mixed precision on the same problem
+    # (and, for the workload's precision, with the other Arnoldi variant)
+    ttr = {}
+    precs = ["fp64", "mixed32"] + (["mixed16"] if mixed16 else []) if mixed else [prec]
+    runs = [(p, orth) for p in precs]
+    if other_arnoldi:
+        runs.append((prec, 1 - orth))
+    from paper_2503_22455_amd import iim
+    for p, o in runs:
+        key = p if o == orth else f"{p}+{'cgs2' if o == 0 else 'cgs1'}"
+        one_step(wl, p, cpd, box, f, torch)
+        dts = []
+        for _ in range(3):
+            P = iim.from_workload(wl, precision=p, orthogonalisation=o)
+            P.set_boundary_data(cpd, box)
+            P.set_rhs(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, hist, st = P.solve()
+            torch.cuda.synchronize()
+            dts.append(time.perf_counter() - t0)
+            P.close()
+        ttr[key] = {"ms": float(np.median(dts) * 1e3), "iterations": st["iterations"],
+                    "second_gs_passes": st["second_passes"], "reached": bool(st["final_rel_residual"] <= 1e-10)}
+        if st["bordered"]:
+            ttr[key]["shift_alpha"] = st["shift_alpha"]
+        print(f"[bench] {name} time-to-1e-10 {key}: {ttr[key]}", file=sys.stderr, flush=True)
+    out["ttr"] = ttr
+    if not roofline:
+        return out
+
+    # roofline of the dominant kernel: measured duration x launches per iteration
+    kr, info = kernel_roofline(wl, prec, torch, nu)
+    launches = {0: 1, 1: 1, 2: 2 * 2, 3: 1, 4: 1, 5: 2, 8: 1, 9: 1}   # per FGMRES iteration (nu_pre = nu_post = 2)
+    dom = max(kr, key=lambda k: kr[k][1] * launches[k])
+    kname, ms, algo_bytes = kr[dom]
+    achieved = algo_bytes / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(name, dom)
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": None if traffic is None else int(traffic), "kernel": kname,
+                       "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes_per_launch": int(algo_bytes)}
+    out["kernels"] = {kr[k][0]: {"avg_us": round(kr[k][1] * 1e3, 2),
+                                 "GBs": round(kr[k][2] / (kr[k][1] * 1e-3) / 1e9, 1)} for k in kr}
+    for k in kr:
+        print(f"[bench] kernel {kr[k][0]}: {kr[k][1]*1e3:.2f} us, {kr[k][2]/(kr[k][1]*1e-3)/1e9:.1f} GB/s",
+              file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":

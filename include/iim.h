@@ -306,40 +306,73 @@ int iim_synthetic_error(iim_problem* p, int32_t kind, const double* u, double* m
  * requests overlaps.  Requests are admitted in arrival (FIFO) order when a slot
  * is free and their estimated device memory fits in what is left of
  * budget_bytes; a request whose estimate alone exceeds the budget fails with
- * IIM_E_BUDGET without blocking the queue. */
+ * IIM_E_BUDGET without blocking the queue.  Every request keeps its level
+ * hierarchy and Krylov basis resident on the device until it completes.
+ * Unless disabled at creation, the small coarse levels of the V-cycles
+ * (Sec. 3.3: the levels below the finest ones, coarse solve included, which
+ * one workgroup handles) of all requests that reach them together run as one
+ * batched launch, one workgroup per request; each request's result is bit for
+ * bit the one it gets alone. */
 typedef struct iim_server iim_server;
 
 typedef struct iim_request {
     iim_grid grid;
     iim_geometry geom;   /* params are copied at submission */
     iim_options opt;
-    int32_t data_kind;   /* synthetic data family (see iim_set_synthetic_data) */
-    int32_t reserved;
+    int32_t data_kind;   /* 0: the caller's data (f, cp_data, box_data below);
+                            1: synthetic family 1 (see iim_set_synthetic_data) */
+    int32_t mem_kind;    /* IIM_MEM_* of f, cp_data and box_data */
     double* u_out;       /* optional device full-grid array receiving u (NULL: not copied);
                             must stay valid until the request completes */
+    /* data_kind 0 (Sec. 2.1-2.3; read when the request starts, so they must stay
+       valid until it completes): */
+    const double* f;        /* full-grid source term, read at the unknowns */
+    const double* cp_data;  /* one value per control point (two, j0 then j1, for interfaces), in
+                               the order of iim_control_points for the same grid and geometry */
+    const double* box_data; /* full-grid box-face values, or NULL (no face bounds the domain) */
+    int64_t n_cp_data;      /* doubles in cp_data; the request fails with IIM_E_INVALID_ARG
+                               unless it matches the problem's control points */
+    double* hist;           /* optional host array of hist_cap doubles receiving the relative
+                               residual estimate after every iteration; valid until completion */
+    int32_t hist_cap;
+    int32_t reserved;
 } iim_request;
 
 typedef struct iim_result {
     int32_t done;        /* 1 once finished (successfully or not) */
     int32_t status;      /* IIM_OK, IIM_NOT_CONVERGED or a negative error code */
     int32_t iterations;
-    int32_t reserved;
+    int32_t hist_len;    /* entries written to the request's hist */
     double rel_residual; /* final true relative residual */
-    double max_error;    /* max |u - u_exact| over the unknowns */
+    double max_error;    /* synthetic data: max |u - u_exact| over the unknowns (mean-free for
+                            singular problems); caller data: 0 */
     double t_submit, t_start, t_finish; /* seconds on the server's steady clock */
     int64_t n_unknowns;
     int64_t device_bytes;   /* device memory the request held */
     int64_t estimated_bytes;
+    double shift_alpha;     /* singular (bordered) problems: alpha; 0 otherwise */
 } iim_result;
 
 typedef struct iim_server_stats {
     int64_t submitted, completed, failed, running, queued;
     int64_t bytes_reserved, bytes_budget, peak_bytes_reserved;
+    int64_t tail_batches;   /* batched coarse-level launches */
+    int64_t tail_jobs;      /* V-cycle tails they ran (tail_jobs / tail_batches = mean batch size) */
 } iim_server_stats;
 
+typedef struct iim_server_options {
+    int32_t batch_tails;     /* 1 (default): batch the V-cycle tails of requests solving
+                                together; 0: every request launches its own */
+    int32_t batch_window_us; /* longest wait of a tail for the other solving requests to
+                                reach theirs before the batch launches (default 100) */
+} iim_server_options;
+
 /* budget_bytes: device memory the server may reserve for running requests;
- * max_slots: requests solved concurrently (1..64). */
+ * max_slots: requests solved concurrently (1..64).  iim_server_create uses the
+ * default options. */
 int iim_server_create(int64_t budget_bytes, int32_t max_slots, iim_server** out);
+int iim_server_create_ex(int64_t budget_bytes, int32_t max_slots, const iim_server_options* opt,
+                         iim_server** out);
 /* Enqueues a request; returns at once with its ticket. */
 int iim_server_submit(iim_server* s, const iim_request* req, uint64_t* ticket);
 /* Copies the request's result (done = 0 while queued or running). */

@@ -27,16 +27,21 @@ followed by one value per grid node (flat, x fastest) of which only the box-face
 entries are used.
 
 Post-processing (Sec. 2.4): grad u at the unknowns by the order-n central
-first derivative with the same extension (grad_row, gradient), and the
+first derivative with the same extension (grad_row, gradient), the
 boundary quantity left open by the condition at every control point
-(boundary_quantity).
+(boundary_quantity), and the gradient of the solved side's fit at every
+control point (wall_gradient: the wall derivatives from which the potential-flow
+application of Sec. 4.4.2 recovers the wall velocity and C_p).
 
 Parity: pinned by the patch test (the operator is exact on polynomials of degree
 <= k-1 with matching data), by the order-n convergence of the solution and by
 the spectrum bounds of Sec. 2.5 (tests/test_oracle_iim.py).  The gradient and
 the boundary quantity are pinned by patch tests (exact on polynomials of degree
 <= n, resp. <= k-1, given exact nodal values) and by their order-n convergence
-on solved problems (tests/test_oracle_post.py).
+on solved problems; the wall gradient by a patch test (exact on degree k-1),
+by its normal component equalling the Neumann datum for any nodal values, and
+by the pressure coefficient of potential flow past a cylinder converging at
+order 4 to its closed form (tests/test_oracle_post.py).
 """
 from __future__ import annotations
 
@@ -122,6 +127,51 @@ class IIMProblem:
             self._st[key] = ls_stencil(self.grid, self.lab_flat, self.cps[c], side,
                                        self.order_k, self.w, True, self.axes)
         return self._st[key]
+
+    def stencil_g(self, c: int, side: int):
+        """The fit of control point c with the normal-derivative row (column
+        w) and the Cartesian derivative rows d/dx_d (columns w+1..w+dim)."""
+        key = ("g", c, side)
+        if key not in self._st:
+            self._st[key] = ls_stencil(self.grid, self.lab_flat, self.cps[c], side,
+                                       self.order_k, self.w, True, self.axes, with_grad=True)
+        return self._st[key]
+
+    def wall_gradient(self, u: np.ndarray, u_gamma: np.ndarray) -> np.ndarray:
+        """Gradient of the solved side's fit at every control point, (ncp, dim)
+        (the wall derivatives of Sec. 4.4.2): grad p_c(x_c) = s_c U_c + sum_i
+        s_i u_i with the Cartesian derivative rows s of the fit and U_c the
+        fit's value at x_c,
+          Dirichlet  U_c = ubar;
+          Neumann    U_c = (qbar - beta sum_i s^n_i u_i) / (beta s^n_c), the
+                     closure of the normal row s^n;
+          interface  U_c = u+(x_c) from the interface closure (the Omega^+ fit).
+        """
+        uf = np.zeros(self.lab_flat.size)
+        uf[self.unknowns] = u
+        w, dim = self.w, self.dim
+        out = np.empty((self.ncp, dim))
+        for c in range(self.ncp):
+            st = self.stencil_g(c, PLUS)
+            sn = st.S[:, w]
+            su = lambda col: sum(st.S[1 + a, col] * uf[f] for a, f in enumerate(st.idx))
+            if self.bc == BC_DIRICHLET:
+                uc = u_gamma[c]
+            elif self.bc == BC_NEUMANN:
+                beta = self.beta[PLUS]
+                uc = (u_gamma[c] - beta * su(w)) / (beta * sn[0])
+            else:
+                stm = self.stencil_g(c, MINUS)
+                snm = stm.S[:, w]
+                bp, bm = self.beta[PLUS], self.beta[MINUS]
+                D = bp * sn[0] - bm * snm[0]
+                sm_u = sum(snm[1 + a] * uf[f] for a, f in enumerate(stm.idx))
+                ubar = -(bp * su(w) - bm * sm_u) / D
+                j0, j1 = u_gamma[2 * c], u_gamma[2 * c + 1]
+                uc = ubar + (j1 - bm * snm[0] * j0) / D
+            for d in range(dim):
+                out[c, d] = st.S[0, w + 1 + d] * uc + su(w + 1 + d)
+        return out
 
     def boundary_quantity(self, u: np.ndarray, u_gamma: np.ndarray) -> np.ndarray:
         """The boundary quantity the condition leaves open, one value per

@@ -135,16 +135,25 @@ def normal_derivative_functional(n: np.ndarray, h_scale: float, exps) -> np.ndar
     return e
 
 
+def cartesian_derivative_functional(d: int, dim: int, h_scale: float, exps) -> np.ndarray:
+    """d/dx_d of the monomials at xi = 0 (the gradient of the fit at x_c,
+    component d): the normal-derivative functional along the unit vector e_d."""
+    e_d = np.zeros(dim)
+    e_d[d] = 1.0
+    return normal_derivative_functional(e_d, h_scale, exps)
+
+
 class LSStencil:
     """Weights of one control point on one side.
     idx: flat indices of the m grid points; S: (m+1, r) weights whose row 0
-    multiplies u(x_c); columns 0..w-1 are the ghosts j = 1..w and column w
-    (when present) the normal derivative along n (without beta)."""
+    multiplies u(x_c); columns 0..w-1 are the ghosts j = 1..w, column w
+    (when present) the normal derivative along n (without beta), and columns
+    w+1..w+dim (when asked for) the Cartesian derivatives d/dx_d at x_c."""
     __slots__ = ("idx", "S", "a", "b", "rdiag")
 
 
 def ls_stencil(grid, labels_flat, cp, side: int, order_k: int, w: int, with_deriv: bool,
-               axes: Tuple[float, float]) -> LSStencil:
+               axes: Tuple[float, float], with_grad: bool = False) -> LSStencil:
     dim = grid.dim
     h = grid.h
     exps = monomial_exponents(dim, order_k - 1)
@@ -163,8 +172,11 @@ def ls_stencil(grid, labels_flat, cp, side: int, order_k: int, w: int, with_deri
                 xg = xa.copy()
                 xg[cp.axis] = xa[cp.axis] + j * step * h
                 rows.append(value_functional(xg, cp.x, scale, exps))
-            if with_deriv:
+            if with_deriv or with_grad:
                 rows.append(normal_derivative_functional(cp.n, scale, exps))
+            if with_grad:
+                for d in range(dim):
+                    rows.append(cartesian_derivative_functional(d, dim, scale, exps))
             S, rdiag = fit_weights(cp.x, pts, np.array(rows), scale, exps)
             if rdiag.min() >= RANK_TOL * rdiag.max():
                 st = LSStencil()

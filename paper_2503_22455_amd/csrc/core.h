@@ -44,6 +44,17 @@ void configure_pool(int device);
 // frees the process cache of idle blocks of the current device and trims its pool
 void trim_pool();
 
+struct Problem;
+// Runs the tail of a problem's V-cycle (the levels from tail_first down, coarse
+// solve included) in place of the problem's own launch, for instance batched
+// with the tails of other problems.  Called on the host thread that enqueues
+// the problem's work; on return the tail is ordered after everything enqueued
+// before on p.stream and before everything enqueued after.
+struct TailRunner {
+    virtual void run(Problem& p) = 0;
+    virtual ~TailRunner() = default;
+};
+
 struct Level {
     int n = 0;
     double h = 0.0;
@@ -135,6 +146,8 @@ struct Problem {
     double* hpin = nullptr;  // Hessenberg column records, HCOL doubles per iteration, written by kernels
     bool own_hpin = true;
     hipGraphExec_t iter_graph[16] = {};
+    hipGraphExec_t pre_graph[16] = {};  // with a tail runner: iteration parts before the tail
+    TailRunner* tail_runner = nullptr;  // not owned
     hipEvent_t iter_done[2] = {};  // end of inner iteration j, alternating by parity
     double t_setup_ms = 0.0;
 
@@ -154,16 +167,21 @@ struct Problem {
     template <typename T, typename S> const S* up_leg(int l, const S* zres, double* out);
     // scaled: red_scale already holds max |v| (the fused orthogonalisation wrote it);
     // out_basis: out is zero off the core (a Krylov basis column)
-    template <typename T, typename S> void vcycle_t(const double* v, double* out, bool scaled, bool out_basis);
+    // part 0: the whole cycle; 1: down to the tail (exclusive); 2: from the
+    // tail's result up (parts 1 and 2 leave the tail to the caller)
+    template <typename T, typename S> void vcycle_t(const double* v, double* out, bool scaled, bool out_basis, int part);
+    template <typename T, typename S> void vcycle_down(const double* v, bool scaled);
     template <typename T, typename S> void wcycle_t(const double* v, double* out, bool scaled);
     template <typename T, typename S> void wvisit(int l, bool zero_start);
-    void vcycle(const double* v, double* out, bool scaled = false, bool out_basis = false);
-    void iteration_body(int j, hipEvent_t* evs = nullptr);
+    void vcycle(const double* v, double* out, bool scaled = false, bool out_basis = false, int part = 0);
+    void iteration_body(int j, hipEvent_t* evs = nullptr, int part = 0);
     int solve(double* u_full, const double* x0_full, double* hist, int hist_cap, iim_stats* st);
     int level_op(int level, int op, const double* in1, double* out);
     template <typename T, typename S> void launch_kernel_t(int kernel);
     double time_kernel(int kernel, int reps);
     template <typename T, typename S> int level_op_t(int level, int op, const double* in1, double* out);
+    void set_boundary_data(const double* cp_data, const double* box_data, int mem_kind);
+    void set_rhs(const double* f, int mem_kind);
     void synth_data(int kind);
     double synth_error(int kind, const double* u_full);
     ~Problem();
@@ -174,6 +192,9 @@ struct Problem {
 // (hipHostMallocCoherent) of HPIN_DOUBLES doubles
 std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo, const iim_options* opt,
                                       hipStream_t stream, double* hpin);
+// rejects (IIM_E_INVALID_ARG) an interior Neumann sphere union whose interior
+// is not connected: the bordered system fixes only one constant
+void check_singular_connected(const iim_grid& g, const iim_geometry& geo);
 // device bytes a problem will hold at its peak, from the request alone
 int64_t estimate_bytes(const iim_grid& g, const iim_geometry& geo, const iim_options& opt);
 

@@ -771,8 +771,54 @@ const S* Problem::up_leg(int l, const S* zres, double* out) {
 }
 
 template <typename T, typename S>
-void Problem::vcycle_t(const double* v, double* out, bool scaled, bool out_basis) {
+void Problem::vcycle_t(const double* v, double* out, bool scaled, bool out_basis, int part) {
     const int nl = (int)levels.size();
+    const int t = tail_first;
+    LevelDev D0 = level_dev(0);
+    if (part != 2) vcycle_down<T, S>(v, scaled);
+    if (part == 0) {
+        if (tail_runner)
+            tail_runner->run(*this);
+        else
+            run_tail<T, S>(dim, d_tail, tail_lds_bytes, stream);  // levels t..nl-1, coarse solve included
+    }
+    if (part == 1) return;
+    const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
+    const S* zres = (const S*)levels[t].z;  // result of the level below the current one
+    bool have_out = false;
+    for (int l = t - 1; l >= 0; --l) {
+        // a basis column is zero off the core, so the last fused leg may write it directly
+        double* o = (l == 0 && out_basis) ? out : nullptr;
+        if (const S* r = up_leg<T, S>(l, zres, o)) {
+            zres = r;
+            have_out = o != nullptr;
+            continue;
+        }
+        LevelDev D = level_dev(l), C = level_dev(l + 1);
+        S* z = (S*)levels[l].z;
+        T* b = (T*)levels[l].b;
+        run_prolong<T, S>(D, C, mode, zres, z, stream);
+        // the last half-sweep on a colour-split level 0 may write a basis column directly
+        const bool fuse_out = l == 0 && out_basis && D.split && opt.nu_post > 0;
+        for (int s = 0; s < opt.nu_post; ++s) {
+            run_rbgs<T, S>(D, 0, z, b, stream);
+            if (fuse_out && s == opt.nu_post - 1) {
+                run_rbgs_out<T, S>(D, z, b, out, red_scale + 1, stream);
+                have_out = true;
+            } else {
+                run_rbgs<T, S>(D, 1, z, b, stream);
+            }
+        }
+        zres = z;
+    }
+    (void)nl;
+    if (!have_out) run_cast_out<S>(D0, zres, red_scale + 1, out, stream);
+}
+
+// the levels above the tail of a V-cycle: input scaling and cast, then per
+// level pre-smoothing from zero, residual and restriction
+template <typename T, typename S>
+void Problem::vcycle_down(const double* v, bool scaled) {
     const int t = tail_first;
     LevelDev D0 = level_dev(0);
     if (!scaled) run_absmax(v, box.size(), red_part, red_scale, stream);
@@ -811,37 +857,6 @@ void Problem::vcycle_t(const double* v, double* out, bool scaled, bool out_basis
         started = next;
     }
     cast_in();  // every level in the tail
-    run_tail<T, S>(dim, d_tail, tail_lds_bytes, stream);  // levels t..nl-1, coarse solve included
-    const int mode = (side == IIM_SIDE_INTERFACE || bc == IIM_BC_DIRICHLET) ? 0 : 1;
-    const S* zres = (const S*)levels[t].z;  // result of the level below the current one
-    bool have_out = false;
-    for (int l = t - 1; l >= 0; --l) {
-        // a basis column is zero off the core, so the last fused leg may write it directly
-        double* o = (l == 0 && out_basis) ? out : nullptr;
-        if (const S* r = up_leg<T, S>(l, zres, o)) {
-            zres = r;
-            have_out = o != nullptr;
-            continue;
-        }
-        LevelDev D = level_dev(l), C = level_dev(l + 1);
-        S* z = (S*)levels[l].z;
-        T* b = (T*)levels[l].b;
-        run_prolong<T, S>(D, C, mode, zres, z, stream);
-        // the last half-sweep on a colour-split level 0 may write a basis column directly
-        const bool fuse_out = l == 0 && out_basis && D.split && opt.nu_post > 0;
-        for (int s = 0; s < opt.nu_post; ++s) {
-            run_rbgs<T, S>(D, 0, z, b, stream);
-            if (fuse_out && s == opt.nu_post - 1) {
-                run_rbgs_out<T, S>(D, z, b, out, red_scale + 1, stream);
-                have_out = true;
-            } else {
-                run_rbgs<T, S>(D, 1, z, b, stream);
-            }
-        }
-        zres = z;
-    }
-    (void)nl;
-    if (!have_out) run_cast_out<S>(D0, zres, red_scale + 1, out, stream);
 }
 
 // One visit of level l in a W-cycle (cycle index 2): pre-smoothing from zero or
@@ -885,28 +900,30 @@ void Problem::wcycle_t(const double* v, double* out, bool scaled) {
     run_cast_out<S>(D0, (const S*)levels[0].z, red_scale + 1, out, stream);
 }
 
-void Problem::vcycle(const double* v, double* out, bool scaled, bool out_basis) {
+void Problem::vcycle(const double* v, double* out, bool scaled, bool out_basis, int part) {
     const bool w = opt.cycle_gamma == 2;
+    if (w && part != 0) throw Error(IIM_E_INTERNAL, "the W-cycle runs whole");
     if (opt.precision == IIM_PREC_FP64) {
         if (w) wcycle_t<double, double>(v, out, scaled);
-        else vcycle_t<double, double>(v, out, scaled, out_basis);
+        else vcycle_t<double, double>(v, out, scaled, out_basis, part);
     } else if (opt.precision == IIM_PREC_MIXED32) {
         if (w) wcycle_t<float, float>(v, out, scaled);
-        else vcycle_t<float, float>(v, out, scaled, out_basis);
+        else vcycle_t<float, float>(v, out, scaled, out_basis, part);
     } else {
         if (w) wcycle_t<float, __half>(v, out, scaled);
-        else vcycle_t<float, __half>(v, out, scaled, out_basis);
+        else vcycle_t<float, __half>(v, out, scaled, out_basis, part);
     }
 }
 
 // One inner FGMRES iteration on the device: z_j = M^{-1} v_j, w = A z_j,
 // classical Gram-Schmidt against v_0..v_j, v_{j+1} = w / |w|, and the Hessenberg column copied to
 // pinned host memory.  Pointers are fixed per j, so it can be captured.
-void Problem::iteration_body(int j, hipEvent_t* evs) {
+void Problem::iteration_body(int j, hipEvent_t* evs, int part) {
     const int64_t N = krylov_len();
     double* vj = Vb + (size_t)j * ldv;
     double* zj = Zb + (size_t)j * ldv;
-    vcycle(vj, zj, j > 0, true);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
+    vcycle(vj, zj, j > 0, true, part);  // v_j (j > 0) came from this cycle's fused pass, which left max |v_j|
+    if (part == 1) return;
     if (evs) IIM_HIP(hipEventRecord(evs[1], stream));
     // bordered: the preconditioner is the identity on alpha, so z_j takes v_j's
     apply_op(zj, wk, vj + box.size());
@@ -986,19 +1003,29 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
             // it is queued before the host reads column j: the host's wait and
             // its Givens update overlap the next iteration.  A queued iteration
             // past convergence writes only basis vectors the update never reads.
-            auto capture = [&](int jj) {
-                if (iter_graph[jj]) return;
+            // With a tail runner (serving) the iteration is captured as two
+            // graphs, before and after the V-cycle's tail, and the runner runs
+            // the tail between their launches.
+            const bool split = tail_runner && opt.cycle_gamma == 1;
+            auto capture = [&](hipGraphExec_t* slot, int jj, int part) {
+                if (*slot) return;
                 hipGraph_t g;
                 IIM_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
-                iteration_body(jj);
+                iteration_body(jj, nullptr, part);
                 IIM_HIP(hipStreamEndCapture(stream, &g));
-                IIM_HIP(hipGraphInstantiate(&iter_graph[jj], g, nullptr, nullptr, 0));
+                IIM_HIP(hipGraphInstantiate(slot, g, nullptr, nullptr, 0));
                 IIM_HIP(hipGraphDestroy(g));
             };
             const bool pipelined = opt.use_graph != 0;
             auto enqueue = [&](int jj) {
-                if (opt.use_graph == 1) {
-                    capture(jj);
+                if (opt.use_graph == 1 && split) {
+                    capture(&pre_graph[jj], jj, 1);
+                    capture(&iter_graph[jj], jj, 2);
+                    IIM_HIP(hipGraphLaunch(pre_graph[jj], stream));
+                    tail_runner->run(*this);
+                    IIM_HIP(hipGraphLaunch(iter_graph[jj], stream));
+                } else if (opt.use_graph == 1) {
+                    capture(&iter_graph[jj], jj, 0);
                     IIM_HIP(hipGraphLaunch(iter_graph[jj], stream));
                 } else {
                     iteration_body(jj);
@@ -1091,6 +1118,51 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
     S.t_krylov_ms = t_kr;
     if (st) *st = S;
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// the caller's data (Sec. 2.1-2.3): boundary / interface values per control
+// point and box-face values, then the right-hand side b = f - L_Gamma u_Gamma
+// ---------------------------------------------------------------------------
+void Problem::set_boundary_data(const double* cp_data, const double* box_data, int mem_kind) {
+    const int64_t ncd = cp.ncp * (bc == IIM_BC_JUMP ? 2 : 1);
+    hipMemcpyKind k = mem_kind == IIM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (ncd) {
+        if (!cp_data) throw Error(IIM_E_INVALID_ARG, "cp_data is required");
+        IIM_HIP(hipMemcpyAsync(cpdata, cp_data, ncd * sizeof(double), k, stream));
+    }
+    if (box_data) {
+        const int64_t n1 = grid.n + 1;
+        const int64_t tot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
+        double* tmp = (double*)mem.alloc(tot * sizeof(double));
+        IIM_HIP(hipMemcpyAsync(tmp, box_data, tot * sizeof(double), k, stream));
+        run_full_to_box(dim, grid.n, box, tmp, boxval, levels[0].labels, 2, stream);
+        IIM_HIP(hipStreamSynchronize(stream));
+        mem.release(tmp);
+    } else {
+        IIM_HIP(hipMemsetAsync(boxval, 0, box.size() * sizeof(double), stream));
+    }
+    IIM_HIP(hipStreamSynchronize(stream));
+}
+
+void Problem::set_rhs(const double* f, int mem_kind) {
+    if (!f) throw Error(IIM_E_INVALID_ARG, "null argument");
+    const int64_t n1 = grid.n + 1;
+    const int64_t tot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
+    const double* src = f;
+    double* tmp = nullptr;
+    if (mem_kind != IIM_MEM_DEVICE) {
+        tmp = (double*)mem.alloc(tot * sizeof(double));
+        IIM_HIP(hipMemcpyAsync(tmp, f, tot * sizeof(double), hipMemcpyHostToDevice, stream));
+        src = tmp;
+    }
+    // b = f - L_Gamma u_Gamma = f - apply(0, with data)
+    run_full_to_box(dim, grid.n, box, src, rhs, levels[0].labels, 1, stream);
+    IIM_HIP(hipMemsetAsync(xk, 0, box.size() * sizeof(double), stream));
+    apply_box(xk, wk, 1);
+    run_axpby(-1.0, wk, 1.0, rhs, box.size(), stream);
+    IIM_HIP(hipStreamSynchronize(stream));
+    if (tmp) mem.release(tmp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1385,6 +1457,42 @@ int Problem::level_op(int l, int op, const double* in1, double* out) {
     return level_op_t<float, __half>(l, op, in1, out);
 }
 
+// A singular problem (interior domain, Neumann boundary) is bordered with one
+// constant (Sec. 2.3), which fixes the null space of a connected domain only.
+// The interior of a sphere union is connected exactly when the overlap graph of
+// its spheres is (two balls overlap when their centres are closer than the sum
+// of their radii); anything else is rejected here.
+void check_singular_connected(const iim_grid& g, const iim_geometry& geo) {
+    if (geo.kind != IIM_GEOM_SPHERE_UNION || geo.side != IIM_SIDE_INTERIOR || geo.bc != IIM_BC_NEUMANN) return;
+    const int cnt = (int)geo.params[0], d = g.dim;
+    std::vector<int> parent(std::max(cnt, 0));
+    for (int i = 0; i < cnt; ++i) parent[i] = i;
+    auto find = [&](int i) {
+        while (parent[i] != i) i = parent[i] = parent[parent[i]];
+        return i;
+    };
+    int comps = cnt;
+    for (int i = 0; i < cnt; ++i)
+        for (int j = i + 1; j < cnt; ++j) {
+            const double* a = geo.params + 1 + i * (d + 1);
+            const double* b = geo.params + 1 + j * (d + 1);
+            double d2 = 0.0;
+            for (int k = 0; k < d; ++k) d2 += (a[k] - b[k]) * (a[k] - b[k]);
+            const double rr = a[d] + b[d];
+            if (d2 < rr * rr) {
+                const int ri = find(i), rj = find(j);
+                if (ri != rj) {
+                    parent[ri] = rj;
+                    --comps;
+                }
+            }
+        }
+    if (comps > 1)
+        throw Error(IIM_E_INVALID_ARG,
+                    "interior Neumann sphere union is not connected: the bordered system fixes one constant, "
+                    "but each of the " + std::to_string(comps) + " components has its own");
+}
+
 std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo, const iim_options* opt,
                                       hipStream_t stream, double* hpin) {
     if (!g || !geo) throw Error(IIM_E_INVALID_ARG, "null argument");
@@ -1413,8 +1521,9 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     if (geo->kind == IIM_GEOM_SPHERE && geo->nparams < g->dim + 1)
         throw Error(IIM_E_INVALID_ARG, "sphere needs dim + 1 parameters");
     if (geo->kind == IIM_GEOM_SPHERE_UNION &&
-        (geo->nparams < 1 || geo->nparams < 1 + (g->dim + 1) * (int)geo->params[0]))
+        (geo->nparams < 1 || geo->params[0] < 0 || geo->nparams < 1 + (g->dim + 1) * (int)geo->params[0]))
         throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
+    check_singular_connected(*g, *geo);
     if (geo->side != IIM_SIDE_INTERIOR) {
         // box faces must coincide on every level
         int n = g->n;
@@ -1457,6 +1566,8 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
 Problem::~Problem() {
     if (stream) (void)hipStreamSynchronize(stream);
     for (auto& g : iter_graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& g : pre_graph)
         if (g) (void)hipGraphExecDestroy(g);
     for (int i = 0; i < 8; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
@@ -1613,49 +1724,15 @@ int iim_node_labels(const iim_problem* h, uint8_t* labels) {
 int iim_set_boundary_data(iim_problem* h, const double* cp_data, const double* box_data, int32_t mem_kind) {
     ABI_TRY({
         if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
-        Problem& p = *h->p;
-        const int64_t ncd = p.cp.ncp * (p.bc == IIM_BC_JUMP ? 2 : 1);
-        hipMemcpyKind k = mem_kind == IIM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        if (ncd) {
-            if (!cp_data) throw Error(IIM_E_INVALID_ARG, "cp_data is required");
-            IIM_HIP(hipMemcpyAsync(p.cpdata, cp_data, ncd * sizeof(double), k, p.stream));
-        }
-        if (box_data) {
-            const int64_t n1 = p.grid.n + 1;
-            const int64_t tot = p.dim == 2 ? n1 * n1 : n1 * n1 * n1;
-            double* tmp = (double*)p.mem.alloc(tot * sizeof(double));
-            IIM_HIP(hipMemcpyAsync(tmp, box_data, tot * sizeof(double), k, p.stream));
-            run_full_to_box(p.dim, p.grid.n, p.box, tmp, p.boxval, p.levels[0].labels, 2, p.stream);
-            IIM_HIP(hipStreamSynchronize(p.stream));
-            p.mem.release(tmp);
-        } else {
-            IIM_HIP(hipMemsetAsync(p.boxval, 0, p.box.size() * sizeof(double), p.stream));
-        }
-        IIM_HIP(hipStreamSynchronize(p.stream));
+        h->p->set_boundary_data(cp_data, box_data, mem_kind);
         return IIM_OK;
     })
 }
 
 int iim_set_rhs(iim_problem* h, const double* f, int32_t mem_kind) {
     ABI_TRY({
-        if (!h || !f) throw Error(IIM_E_INVALID_ARG, "null argument");
-        Problem& p = *h->p;
-        const int64_t n1 = p.grid.n + 1;
-        const int64_t tot = p.dim == 2 ? n1 * n1 : n1 * n1 * n1;
-        const double* src = f;
-        double* tmp = nullptr;
-        if (mem_kind != IIM_MEM_DEVICE) {
-            tmp = (double*)p.mem.alloc(tot * sizeof(double));
-            IIM_HIP(hipMemcpyAsync(tmp, f, tot * sizeof(double), hipMemcpyHostToDevice, p.stream));
-            src = tmp;
-        }
-        // b = f - L_Gamma u_Gamma = f - apply(0, with data)
-        run_full_to_box(p.dim, p.grid.n, p.box, src, p.rhs, p.levels[0].labels, 1, p.stream);
-        IIM_HIP(hipMemsetAsync(p.xk, 0, p.box.size() * sizeof(double), p.stream));
-        p.apply_box(p.xk, p.wk, 1);
-        run_axpby(-1.0, p.wk, 1.0, p.rhs, p.box.size(), p.stream);
-        IIM_HIP(hipStreamSynchronize(p.stream));
-        if (tmp) p.mem.release(tmp);
+        if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
+        h->p->set_rhs(f, mem_kind);
         return IIM_OK;
     })
 }

@@ -189,6 +189,16 @@ constexpr int64_t TAIL_LDS_MAX = 144 * 1024;
 template <typename T, typename S>
 void run_tail(int dim, const TailDev* d_tail, int64_t lds_bytes, hipStream_t s);
 void enable_tail_lds();
+// the tails of up to TAIL_BATCH_MAX independent problems (same precision and
+// dimension) in one launch, one workgroup each; lds[q] as run_tail's lds_bytes
+constexpr int TAIL_BATCH_MAX = 64;
+struct TailBatch {
+    int count;
+    const TailDev* d[TAIL_BATCH_MAX];
+    int64_t lds[TAIL_BATCH_MAX];
+};
+template <typename T, typename S>
+void run_tail_batch(int dim, const TailBatch& B, hipStream_t s);
 // fused legs (2D): zero + nu sweeps + residual + half-weighting; prolongation + nu sweeps.
 // Return false when the fused form does not apply (the caller launches the unfused kernels).
 // cast: the down leg also makes b from the FP64 input v (as run_cast_in, b is then

@@ -1220,8 +1220,7 @@ __device__ inline void for_core(const LevelDev& L, F fn) {
 }
 
 template <typename T, typename S, int DIM>
-__global__ void __launch_bounds__(1024) k_tail(const TailDev* __restrict__ Dp) {
-    const TailDev& D = *Dp;
+__device__ inline void tail_body(const TailDev& D) {
     for (int l = D.first; l < D.last; ++l) {
         const LevelDev& L = D.lev[l];
         S* z = (S*)D.z[l];
@@ -1270,9 +1269,7 @@ __global__ void __launch_bounds__(1024) k_tail(const TailDev* __restrict__ Dp) {
 // onto the finer level.  The vectors of level l start at byte D.lds_z[l] and
 // D.lds_b[l] of the dynamic LDS area.
 template <typename T, typename S, int DIM>
-__global__ void __launch_bounds__(1024) k_tail_lds(const TailDev* __restrict__ Dp) {
-    extern __shared__ __align__(16) char tail_smem[];
-    const TailDev& D = *Dp;
+__device__ inline void tail_lds_body(const TailDev& D, char* tail_smem) {
     auto zl = [&](int l) { return (S*)(tail_smem + D.lds_z[l]); };
     auto bl = [&](int l) { return (T*)(tail_smem + D.lds_b[l]); };
     {
@@ -1326,6 +1323,32 @@ __global__ void __launch_bounds__(1024) k_tail_lds(const TailDev* __restrict__ D
         S* zg = (S*)D.z[D.first];
         for (int64_t t = threadIdx.x; t < n0; t += blockDim.x) zg[t] = zl(D.first)[t];
     }
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(1024) k_tail(const TailDev* __restrict__ Dp) {
+    tail_body<T, S, DIM>(*Dp);
+}
+
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(1024) k_tail_lds(const TailDev* __restrict__ Dp) {
+    extern __shared__ __align__(16) char tail_smem[];
+    tail_lds_body<T, S, DIM>(*Dp, tail_smem);
+}
+
+// The tails of several independent problems in one launch, one workgroup per
+// problem: workgroup q runs exactly the single-problem tail of B.d[q] (its LDS
+// form when B.lds[q] > 0), so each problem's result is bit-for-bit the one of
+// its own launch.
+template <typename T, typename S, int DIM>
+__global__ void __launch_bounds__(1024) k_tail_batch(TailBatch B) {
+    extern __shared__ __align__(16) char tail_smem[];
+    const int q = blockIdx.x;
+    if (q >= B.count) return;
+    if (B.lds[q] > 0)
+        tail_lds_body<T, S, DIM>(*B.d[q], tail_smem);
+    else
+        tail_body<T, S, DIM>(*B.d[q]);
 }
 
 // ---- fused 2D smoothing legs with LDS tiles -------------------------------------
@@ -1675,13 +1698,30 @@ void run_tail(int dim, const TailDev* d_tail, int64_t lds_bytes, hipStream_t s) 
     IIM_LAUNCH_CHECK();
 }
 
+template <typename T, typename S>
+void run_tail_batch(int dim, const TailBatch& B, hipStream_t s) {
+    if (B.count <= 0) return;
+    if (B.count > TAIL_BATCH_MAX) throw Error(IIM_E_INTERNAL, "tail batch too large");
+    int64_t lds = 0;
+    for (int q = 0; q < B.count; ++q) lds = std::max(lds, B.lds[q]);
+    if (lds > TAIL_LDS_MAX) throw Error(IIM_E_INTERNAL, "tail: LDS request too large");
+    if (dim == 2)
+        hipLaunchKernelGGL((k_tail_batch<T, S, 2>), dim3(B.count), dim3(1024), (unsigned)lds, s, B);
+    else
+        hipLaunchKernelGGL((k_tail_batch<T, S, 3>), dim3(B.count), dim3(1024), (unsigned)lds, s, B);
+    IIM_LAUNCH_CHECK();
+}
+
 // lets every LDS-resident tail instantiation request TAIL_LDS_MAX bytes (once per process)
 void enable_tail_lds() {
     static std::once_flag once;
     std::call_once(once, [] {
         const void* fns[] = {(const void*)k_tail_lds<double, double, 2>, (const void*)k_tail_lds<double, double, 3>,
                              (const void*)k_tail_lds<float, float, 2>,   (const void*)k_tail_lds<float, float, 3>,
-                             (const void*)k_tail_lds<float, __half, 2>,  (const void*)k_tail_lds<float, __half, 3>};
+                             (const void*)k_tail_lds<float, __half, 2>,  (const void*)k_tail_lds<float, __half, 3>,
+                             (const void*)k_tail_batch<double, double, 2>, (const void*)k_tail_batch<double, double, 3>,
+                             (const void*)k_tail_batch<float, float, 2>,   (const void*)k_tail_batch<float, float, 3>,
+                             (const void*)k_tail_batch<float, __half, 2>,  (const void*)k_tail_batch<float, __half, 3>};
         for (const void* f : fns)
             IIM_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)TAIL_LDS_MAX));
     });
@@ -2021,6 +2061,7 @@ void run_box_to_full(int dim, int n, const Box& b, const double* boxed, const ui
     template void run_coarse_solve<T, S>(const LevelDev&, const int32_t*, int64_t, const T*, const T*, S*, \
                                          hipStream_t);                                                    \
     template void run_tail<T, S>(int, const TailDev*, int64_t, hipStream_t);                              \
+    template void run_tail_batch<T, S>(int, const TailBatch&, hipStream_t);                               \
     template bool run_down_fused<T, S>(const LevelDev&, const LevelDev&, const T*, S*, T*, int, hipStream_t,      \
                                        const CastInArgs*);                                                           \
     template bool run_up_fused<T, S>(const LevelDev&, const LevelDev&, int, const S*, const T*, const S*, S*, int, \

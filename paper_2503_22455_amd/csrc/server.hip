@@ -4,11 +4,21 @@
 // slots).  Each worker owns one non-blocking HIP stream and one pinned host
 // buffer, and runs a whole request on that stream: setup of the handle (its
 // level hierarchy and Krylov basis stay resident for the request's lifetime),
-// manufactured data, the FGMRES solve (HIP-graph iterations), the error
-// against the closed-form solution, and stream-ordered teardown.  Requests on
-// different slots therefore overlap on the device.  Admission is FIFO against a
-// byte budget: the head of the queue starts only when a slot is free and its
-// estimated peak device bytes fit in what running requests leave of the budget.
+// the caller's data or manufactured data, the FGMRES solve, the error against
+// the closed-form solution (manufactured data), and stream-ordered teardown.
+// Requests on different slots therefore overlap on the device.  Admission is
+// FIFO against a byte budget: the head of the queue starts only when a slot is
+// free and its estimated peak device bytes fit in what running requests leave
+// of the budget.
+//
+// Cross-request batching: the tail of every V-cycle (the small coarse levels
+// and the coarse solve, one workgroup's work) is handed to a tail engine.  The
+// engine gathers the tails of the requests that are solving, waits at most a
+// short window for the ones still on their way, and runs each group of equal
+// precision and dimension as one launch with one workgroup per request, on its
+// own stream, ordered after each request's finer levels (an event per request)
+// and before its prolongation (one event per batch).  A workgroup runs exactly
+// the request's own tail, so results do not depend on the batch.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -26,6 +36,66 @@ struct Job {
     iim_result res{};
 };
 
+// one V-cycle tail waiting for (or taken by) a batch
+struct TailJob {
+    Problem* p = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on p's stream after the levels above the tail
+    hipEvent_t done = nullptr;   // recorded on the engine's stream after the batch that ran it
+    bool launched = false;
+    int error = 0;
+};
+
+struct TailEngine final : TailRunner {
+    int device = 0;
+    int window_us = 100;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<TailJob*> pending;
+    int solving = 0;  // workers inside a solve: the ones whose tails may join a batch
+    bool stop = false;
+    std::vector<hipEvent_t> ring;  // one event per batch, reused after ring.size() batches
+    size_t ring_next = 0;
+    int64_t batches = 0, jobs = 0;
+    std::thread th;
+
+    void start(int dev, int window) {
+        device = dev;
+        window_us = window;
+        IIM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        ring.resize(256);
+        for (auto& e : ring) IIM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        th = std::thread([this] { loop(); });
+    }
+    void finish() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        if (th.joinable()) th.join();
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (auto& e : ring)
+            if (e) (void)hipEventDestroy(e);
+        if (stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+    void enter() {
+        std::lock_guard<std::mutex> lk(mu);
+        ++solving;
+    }
+    void leave() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            --solving;
+        }
+        cv.notify_all();  // a batch waiting for this worker's tail need not wait longer
+    }
+    void run(Problem& p) override;
+    void loop();
+    void launch(const std::vector<TailJob*>& batch);
+};
+
 struct Server {
     int device = 0;
     int64_t budget = 0;
@@ -37,6 +107,7 @@ struct Server {
     int64_t reserved = 0, peak = 0, submitted = 0, completed = 0, failed = 0, running = 0;
     bool stopping = false;
     std::vector<std::thread> workers;
+    std::unique_ptr<TailEngine> engine;  // null: every request launches its own tails
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     double clock() const {
@@ -46,20 +117,131 @@ struct Server {
     void run(Job& j, hipStream_t s, double* hpin);
 };
 
+// the calling worker's event that marks its problem's finer levels as done
+struct ReadyEvent {
+    hipEvent_t ev = nullptr;
+    ~ReadyEvent() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
+void TailEngine::run(Problem& p) {
+    thread_local ReadyEvent tl;
+    if (!tl.ev) IIM_HIP(hipEventCreateWithFlags(&tl.ev, hipEventDisableTiming));
+    TailJob job;
+    job.p = &p;
+    job.ready = tl.ev;
+    IIM_HIP(hipEventRecord(job.ready, p.stream));
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        pending.push_back(&job);
+        cv.notify_all();
+        cv.wait(lk, [&] { return job.launched; });
+    }
+    if (job.error) throw Error(job.error, "batched coarse-level launch failed");
+    IIM_HIP(hipStreamWaitEvent(p.stream, job.done, 0));
+}
+
+void TailEngine::launch(const std::vector<TailJob*>& batch) {
+    // one launch per (precision, dimension) group, at most TAIL_BATCH_MAX tails each
+    for (int prec = 0; prec <= 2; ++prec)
+        for (int dim = 2; dim <= 3; ++dim) {
+            TailBatch B{};
+            auto flush = [&] {
+                if (!B.count) return;
+                if (prec == IIM_PREC_FP64) run_tail_batch<double, double>(dim, B, stream);
+                else if (prec == IIM_PREC_MIXED32) run_tail_batch<float, float>(dim, B, stream);
+                else run_tail_batch<float, __half>(dim, B, stream);
+                B.count = 0;
+            };
+            for (TailJob* j : batch) {
+                if (j->p->opt.precision != prec || j->p->dim != dim) continue;
+                IIM_HIP(hipStreamWaitEvent(stream, j->ready, 0));
+                B.d[B.count] = j->p->d_tail;
+                B.lds[B.count] = j->p->tail_lds_bytes;
+                if (++B.count == TAIL_BATCH_MAX) flush();
+            }
+            flush();
+        }
+}
+
+void TailEngine::loop() {
+    if (hipSetDevice(device) != hipSuccess) return;
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        cv.wait(lk, [&] { return stop || !pending.empty(); });
+        if (pending.empty()) {
+            if (stop) break;
+            continue;
+        }
+        // give the other solving requests a short window to reach their tails
+        const auto deadline = std::chrono::steady_clock::now() + std::chrono::microseconds(window_us);
+        cv.wait_until(lk, deadline, [&] { return stop || (int)pending.size() >= solving; });
+        std::vector<TailJob*> batch;
+        batch.swap(pending);
+        hipEvent_t ev = ring[ring_next];
+        ring_next = (ring_next + 1) % ring.size();
+        lk.unlock();
+        int err = 0;
+        try {
+            launch(batch);
+            IIM_HIP(hipEventRecord(ev, stream));
+        } catch (const Error& e) {
+            err = e.code;
+        } catch (...) {
+            err = IIM_E_INTERNAL;
+        }
+        lk.lock();
+        for (TailJob* j : batch) {
+            j->done = ev;
+            j->error = err;
+            j->launched = true;
+        }
+        ++batches;
+        jobs += (int64_t)batch.size();
+        cv.notify_all();
+    }
+}
+
 void Server::run(Job& j, hipStream_t s, double* hpin) {
     iim_result& r = j.res;
     try {
         auto p = make_problem(&j.req.grid, &j.req.geom, &j.req.opt, s, hpin);
         r.n_unknowns = p->levels[0].nunk;
-        p->synth_data(j.req.data_kind);
+        if (j.req.data_kind == 0) {
+            // the caller's problem: data per control point, box faces and f
+            const int64_t ncd = p->cp.ncp * (p->bc == IIM_BC_JUMP ? 2 : 1);
+            if (j.req.n_cp_data != ncd)
+                throw Error(IIM_E_INVALID_ARG, "n_cp_data is " + std::to_string(j.req.n_cp_data) +
+                                                   ", the problem's control points need " + std::to_string(ncd));
+            p->set_boundary_data(j.req.cp_data, j.req.box_data, j.req.mem_kind);
+            p->set_rhs(j.req.f, j.req.mem_kind);
+        } else {
+            p->synth_data(j.req.data_kind);
+        }
         const int64_t n1 = j.req.grid.n + 1;
         const int64_t tot = j.req.grid.dim == 2 ? n1 * n1 : n1 * n1 * n1;
         double* u = j.req.u_out ? j.req.u_out : (double*)p->mem.alloc(tot * sizeof(double));
         iim_stats st{};
-        const int status = p->solve(u, nullptr, nullptr, 0, &st);
-        r.max_error = p->synth_error(j.req.data_kind, u);
+        if (engine) {
+            p->tail_runner = engine.get();
+            engine->enter();
+        }
+        int status;
+        try {
+            status = p->solve(u, nullptr, j.req.hist, j.req.hist_cap, &st);
+        } catch (...) {
+            if (engine) engine->leave();
+            p->tail_runner = nullptr;
+            throw;
+        }
+        if (engine) engine->leave();
+        p->tail_runner = nullptr;
+        r.max_error = j.req.data_kind == 0 ? 0.0 : p->synth_error(j.req.data_kind, u);
         r.status = status;
         r.iterations = st.iterations;
+        r.hist_len = st.hist_len;
+        r.shift_alpha = st.shift_alpha;
         r.rel_residual = st.final_rel_residual;
         r.device_bytes = (int64_t)p->mem.peak;
         r.t_finish = clock();  // the result is complete; teardown follows
@@ -130,7 +312,15 @@ static void check_request(const iim_request& q) {
         (geo.nparams < 1 || geo.params[0] < 0 || geo.nparams < 1 + (g.dim + 1) * (int64_t)geo.params[0]))
         throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
     if (geo.kind < 0 || geo.kind > 2) throw Error(IIM_E_INVALID_ARG, "bad geometry kind");
-    if (q.data_kind != 1) throw Error(IIM_E_INVALID_ARG, "unknown synthetic data kind");
+    check_singular_connected(g, geo);
+    if (q.data_kind != 0 && q.data_kind != 1) throw Error(IIM_E_INVALID_ARG, "unknown data kind");
+    if (q.data_kind == 0) {
+        if (!q.f) throw Error(IIM_E_INVALID_ARG, "caller data needs f");
+        if (q.n_cp_data < 0 || (q.n_cp_data > 0 && !q.cp_data))
+            throw Error(IIM_E_INVALID_ARG, "caller data needs cp_data");
+        if (q.mem_kind != IIM_MEM_HOST && q.mem_kind != IIM_MEM_DEVICE) throw Error(IIM_E_INVALID_ARG, "bad mem_kind");
+    }
+    if (q.hist_cap < 0 || (q.hist_cap > 0 && !q.hist)) throw Error(IIM_E_INVALID_ARG, "bad history buffer");
 }
 
 }  // namespace iim
@@ -157,20 +347,33 @@ struct iim_server {
 
 extern "C" {
 
-int iim_server_create(int64_t budget_bytes, int32_t max_slots, iim_server** out) {
+int iim_server_create_ex(int64_t budget_bytes, int32_t max_slots, const iim_server_options* opt,
+                         iim_server** out) {
     SRV_TRY({
         if (!out) throw Error(IIM_E_INVALID_ARG, "null argument");
         *out = nullptr;
         if (budget_bytes <= 0) throw Error(IIM_E_INVALID_ARG, "budget must be positive");
         if (max_slots < 1 || max_slots > 64) throw Error(IIM_E_INVALID_ARG, "max_slots must be in [1, 64]");
+        iim_server_options o{1, 100};
+        if (opt) o = *opt;
+        if (o.batch_window_us < 0 || o.batch_window_us > 100000)
+            throw Error(IIM_E_INVALID_ARG, "batch_window_us must be in [0, 100000]");
         auto srv = std::make_unique<iim_server>();
         IIM_HIP(hipGetDevice(&srv->s.device));
         configure_pool(srv->s.device);
         srv->s.budget = budget_bytes;
+        if (o.batch_tails) {
+            srv->s.engine = std::make_unique<TailEngine>();
+            srv->s.engine->start(srv->s.device, o.batch_window_us);
+        }
         for (int i = 0; i < max_slots; ++i) srv->s.workers.emplace_back([p = &srv->s] { p->worker(); });
         *out = srv.release();
         return IIM_OK;
     })
+}
+
+int iim_server_create(int64_t budget_bytes, int32_t max_slots, iim_server** out) {
+    return iim_server_create_ex(budget_bytes, max_slots, nullptr, out);
 }
 
 int iim_server_submit(iim_server* srv, const iim_request* req, uint64_t* ticket) {
@@ -244,6 +447,12 @@ int iim_server_stats_get(iim_server* srv, iim_server_stats* st) {
         st->bytes_reserved = s.reserved;
         st->bytes_budget = s.budget;
         st->peak_bytes_reserved = s.peak;
+        st->tail_batches = st->tail_jobs = 0;
+        if (s.engine) {
+            std::lock_guard<std::mutex> lk2(s.engine->mu);
+            st->tail_batches = s.engine->batches;
+            st->tail_jobs = s.engine->jobs;
+        }
         return IIM_OK;
     })
 }
@@ -258,6 +467,7 @@ void iim_server_destroy(iim_server* srv) {
     }
     srv->s.cv_work.notify_all();
     for (auto& t : srv->s.workers) t.join();
+    if (srv->s.engine) srv->s.engine->finish();
     delete srv;
     trim_pool();
 }

@@ -70,20 +70,27 @@ class Info(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("grid", Grid), ("geom", Geometry), ("opt", Options), ("data_kind", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("u_out", ctypes.c_void_p)]
+                ("mem_kind", ctypes.c_int32), ("u_out", ctypes.c_void_p), ("f", ctypes.c_void_p),
+                ("cp_data", ctypes.c_void_p), ("box_data", ctypes.c_void_p), ("n_cp_data", ctypes.c_int64),
+                ("hist", ctypes.c_void_p), ("hist_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("max_error", ctypes.c_double),
+                ("hist_len", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("max_error", ctypes.c_double),
                 ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_finish", ctypes.c_double),
                 ("n_unknowns", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("estimated_bytes", ctypes.c_int64)]
+                ("estimated_bytes", ctypes.c_int64), ("shift_alpha", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "running", "queued",
-                                              "bytes_reserved", "bytes_budget", "peak_bytes_reserved")]
+                                              "bytes_reserved", "bytes_budget", "peak_bytes_reserved",
+                                              "tail_batches", "tail_jobs")]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("batch_tails", ctypes.c_int32), ("batch_window_us", ctypes.c_int32)]
 
 
 _lib = None
@@ -122,6 +129,7 @@ def lib():
         L.iim_synthetic_error.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_double)]
         u64 = ctypes.c_uint64
         L.iim_server_create.argtypes = [i64, i32, ctypes.POINTER(vp)]
+        L.iim_server_create_ex.argtypes = [i64, i32, ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
         L.iim_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(u64)]
         L.iim_server_poll.argtypes = [vp, u64, ctypes.POINTER(Result)]
         L.iim_server_wait.argtypes = [vp, u64, ctypes.POINTER(Result)]
@@ -348,39 +356,61 @@ class Problem:
 class Server:
     """Continuous-batching solve server on the current device (iim_server_*)."""
 
-    def __init__(self, budget_bytes: int, max_slots: int):
+    def __init__(self, budget_bytes: int, max_slots: int, batch_tails: bool = True, batch_window_us: int = 100):
         self._s = ctypes.c_void_p()
         self._keep = {}
-        _check(lib().iim_server_create(int(budget_bytes), int(max_slots), ctypes.byref(self._s)))
+        o = ServerOptions(int(batch_tails), int(batch_window_us))
+        _check(lib().iim_server_create_ex(int(budget_bytes), int(max_slots), ctypes.byref(o), ctypes.byref(self._s)))
 
     def submit(self, dim: int, n: int, geom_kind: int, geom_params, side: int = SIDE_INTERIOR,
                bc: int = BC_DIRICHLET, data_kind: int = 1, u_out=None, lo: float = -1.0, hi: float = 1.0,
-               **opt) -> int:
+               f=None, cp_data=None, box_data=None, hist_cap: int = 0, **opt) -> int:
+        """data_kind 1: device-side manufactured data; data_kind 0: the caller's
+        f (full grid), cp_data (per control point, in the library's order) and
+        box_data (full grid or None), as contiguous CUDA tensors that stay
+        alive (the server keeps references) until the result is collected;
+        hist_cap > 0 collects the residual history (returned by wait/poll)."""
         pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
         req = Request(Grid(dim, n, lo, hi), Geometry(geom_kind, side, bc, len(geom_params), pa), make_options(**opt),
-                      data_kind, 0, None if u_out is None else _ptr(u_out))
+                      data_kind, MEM_DEVICE, None if u_out is None else _ptr(u_out))
+        keep = [u_out]
+        if data_kind == 0:
+            req.f = _ptr(f)
+            req.cp_data = _ptr(cp_data) if cp_data is not None and cp_data.numel() else None
+            req.n_cp_data = 0 if cp_data is None else int(cp_data.numel())
+            req.box_data = None if box_data is None else _ptr(box_data)
+            keep += [f, cp_data, box_data]
+        hist = None
+        if hist_cap > 0:
+            hist = np.zeros(int(hist_cap))
+            req.hist, req.hist_cap = hist.ctypes.data, int(hist_cap)
         t = ctypes.c_uint64()
         _check(lib().iim_server_submit(self._s, ctypes.byref(req), ctypes.byref(t)))
-        if u_out is not None:
-            self._keep[t.value] = u_out  # alive until the result is collected
+        self._keep[t.value] = (keep, hist)  # alive until the result is collected
         return t.value
 
     @staticmethod
     def _dict(r: Result) -> dict:
         return {k: getattr(r, k) for k, _ in Result._fields_}
 
+    def _collect(self, ticket: int, r: Result) -> dict:
+        d = self._dict(r)
+        keep, hist = self._keep.pop(ticket, (None, None))
+        if hist is not None:
+            d["hist"] = hist[: r.hist_len].copy()
+        return d
+
     def poll(self, ticket: int) -> dict:
         r = Result()
         _check(lib().iim_server_poll(self._s, ticket, ctypes.byref(r)))
         if r.done:
-            self._keep.pop(ticket, None)
+            return self._collect(ticket, r)
         return self._dict(r)
 
     def wait(self, ticket: int) -> dict:
         r = Result()
         _check(lib().iim_server_wait(self._s, ticket, ctypes.byref(r)))
-        self._keep.pop(ticket, None)
-        return self._dict(r)
+        return self._collect(ticket, r)
 
     def stats(self) -> dict:
         st = ServerStats()

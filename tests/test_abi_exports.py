@@ -45,7 +45,8 @@ def test_binding_structs_match_the_header(tmp_path):
     from paper_2503_22455_amd import iim
     mirrors = {"iim_grid": iim.Grid, "iim_geometry": iim.Geometry, "iim_options": iim.Options,
                "iim_stats": iim.Stats, "iim_info": iim.Info, "iim_request": iim.Request,
-               "iim_result": iim.Result, "iim_server_stats": iim.ServerStats}
+               "iim_result": iim.Result, "iim_server_stats": iim.ServerStats,
+               "iim_server_options": iim.ServerOptions}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "iim.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -196,3 +196,122 @@ def test_server_singular_requests():
             uu = uP[~torch.isnan(uP)]
             assert abs(float(uu.sum())) <= 1e-9 * float(uu.abs().sum())
         P.close()
+
+
+def _caller_specs():
+    """Requests that carry the caller's problem (data_kind 0): an interface
+    star with beta^-/beta^+ = 2 (two values per control point), and an exterior
+    Neumann sphere union with box faces (box data)."""
+    return [dataclasses.replace(W.cfg2_star(256, beta_plus=0.5, beta_minus=1.0), precision="mixed32"),
+            dataclasses.replace(W.cfg4_spheres(32, spheres=W.small_spheres_union()), precision="mixed32")]
+
+
+def _caller_data(wl, P):
+    """f, cp_data, box_data sampled by the caller at the library's control
+    points (device tensors)."""
+    from paper_2503_22455_amd import iim
+    lab = P.node_labels()
+    xyz, nrm = P.control_points()
+    cpd = torch.tensor(np.ascontiguousarray(wl.cp_data(xyz, nrm), dtype=np.float64).ravel(), device="cuda")
+    box = torch.tensor(iim.grid_to_flat(wl.box_data()), device="cuda") if wl.side != W.SIDE_INTERIOR else None
+    f = torch.tensor(iim.grid_to_flat(wl.rhs(iim.flat_to_grid(lab, wl.dim, wl.n))), device="cuda")
+    return f, cpd, box
+
+
+def _submit_wl(srv, wl, u_out, f, cpd, box, hist_cap=0, **kw):
+    return srv.submit(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, data_kind=0, u_out=u_out, f=f,
+                      cp_data=cpd, box_data=box, hist_cap=hist_cap, beta_plus=wl.beta_plus,
+                      beta_minus=wl.beta_minus, precision=wl.precision, rtol=1e-10, **kw)
+
+
+@pytest.mark.parametrize("batch", [True, False], ids=["batched-tails", "own-tails"])
+def test_server_caller_data_alone_and_in_mix(batch):
+    """Requests carrying the caller's f, control-point data and box data
+    (Sec. 2.1-2.3) give, alone on one slot and inside a mix of other requests on
+    four slots, bit for bit the u and residual history of a plain handle given
+    the same data."""
+    from paper_2503_22455_amd import iim
+    ref = []
+    for wl in _caller_specs():
+        P = gpu_for(wl, precision="mixed32", rtol=1e-10)
+        f, cpd, box = _caller_data(wl, P)
+        P.set_boundary_data(cpd, box)
+        P.set_rhs(f)
+        u, hist, st = P.solve()
+        assert st["status"] == 0, st
+        P.close()
+        ref.append((wl, f, cpd, box, u, hist, st))
+    # alone
+    for wl, f, cpd, box, u, hist, st in ref:
+        s1 = iim.Server(64 << 30, 1, batch_tails=batch)
+        uo = torch.empty_like(u)
+        r = s1.wait(_submit_wl(s1, wl, uo, f, cpd, box, hist_cap=500))
+        s1.close()
+        assert r["status"] == 0 and r["iterations"] == st["iterations"], r
+        assert torch.equal(uo.nan_to_num(0.0), u.nan_to_num(0.0))
+        assert np.array_equal(r["hist"], hist)
+    # in a mix
+    s4 = iim.Server(64 << 30, 4, batch_tails=batch)
+    outs, tickets = [], []
+    for i, spec in enumerate(MIX):
+        tickets.append(_submit(s4, spec))
+        if i < len(ref):
+            wl, f, cpd, box, u, hist, st = ref[i]
+            outs.append(torch.empty_like(u))
+            tickets.append(_submit_wl(s4, wl, outs[-1], f, cpd, box, hist_cap=500))
+    res = [s4.wait(t) for t in tickets]
+    st4 = s4.stats()
+    s4.close()
+    assert all(r["status"] == 0 for r in res), res
+    mine = [r for r in res if "hist" in r]
+    for (wl, f, cpd, box, u, hist, st), r, uo in zip(ref, mine, outs):
+        assert r["iterations"] == st["iterations"] and r["max_error"] == 0.0
+        assert torch.equal(uo.nan_to_num(0.0), u.nan_to_num(0.0))
+        assert np.array_equal(r["hist"], hist)
+    if batch:
+        assert st4["tail_batches"] > 0 and st4["tail_jobs"] > st4["tail_batches"], st4
+    else:
+        assert st4["tail_batches"] == 0
+
+
+def test_server_batched_tails_bitwise_and_graphs():
+    """The V-cycle tails of requests solving together run as batched launches
+    (more tails than launches); every result equals the one with each request
+    launching its own tails, bit for bit, also when the iterations are replayed
+    as captured HIP graphs around the batched tails."""
+    from paper_2503_22455_amd import iim
+    outs = {}
+    stats = {}
+    for mode in ("own", "batched", "batched-graph"):
+        srv = iim.Server(64 << 30, 4, batch_tails=mode != "own")
+        us = [torch.empty(_numel(spec), dtype=torch.float64, device="cuda") for spec in MIX]
+        kw = dict(use_graph=1) if mode == "batched-graph" else {}
+        tickets = [_submit(srv, spec, u, **kw) for spec, u in zip(MIX, us)]
+        res = [srv.wait(t) for t in tickets]
+        stats[mode] = srv.stats()
+        srv.close()
+        assert all(r["status"] == 0 and r["rel_residual"] <= 1e-10 for r in res), res
+        outs[mode] = (us, [r["iterations"] for r in res])
+    for mode in ("batched", "batched-graph"):
+        assert outs[mode][1] == outs["own"][1]
+        for a, b in zip(outs[mode][0], outs["own"][0]):
+            assert torch.equal(a.nan_to_num(0.0), b.nan_to_num(0.0)), mode
+        assert stats[mode]["tail_jobs"] > stats[mode]["tail_batches"] > 0, stats[mode]
+    assert stats["own"]["tail_batches"] == 0
+
+
+def test_server_rejects_mismatched_caller_data():
+    """A caller-data request whose control-point data do not match the
+    problem's control points fails with IIM_E_INVALID_ARG (and the server
+    carries on)."""
+    from paper_2503_22455_amd import iim
+    wl = _caller_specs()[0]
+    P = gpu_for(wl, precision="mixed32")
+    f, cpd, box = _caller_data(wl, P)
+    P.close()
+    srv = iim.Server(64 << 30, 1)
+    r = srv.wait(_submit_wl(srv, wl, None, f, cpd[:-2].contiguous(), box))
+    ok = srv.wait(_submit(srv, MIX[0]))
+    srv.close()
+    assert r["status"] == -1, r
+    assert ok["status"] == 0, ok

@@ -172,6 +172,57 @@ def ms_cos_sinh() -> Manufactured:
     return Manufactured(u, g, lap)
 
 
+def ms_body_flow(dim: int = 3, center=(0.0, 0.0, 0.0), radius: float = 0.5, u_inf=(1.0, 0.0, 0.0)) -> Manufactured:
+    """Disturbance potential of a uniform flow u_inf past a sphere (3D) or a
+    circular cylinder (2D) of radius R (textbook potential flow):
+    Phi = R^dim (u_inf . d) / ((dim - 1) |d|^dim), d = x - centre.  It is
+    harmonic, and the total velocity grad Phi + u_inf is tangent to the body,
+    so dPhi/dn = -u_inf . n there (n the outward normal)."""
+    c = [float(v) for v in center][:dim]
+    Rd = float(radius) ** dim
+    U = [float(v) for v in u_inf][:dim]
+    k = 1.0 / (dim - 1)
+
+    def parts(X):
+        d = [X[i] - c[i] for i in range(dim)]
+        r2 = sum(di * di for di in d)
+        ud = sum(U[i] * d[i] for i in range(dim))
+        return d, r2, ud
+
+    def u(*X):
+        d, r2, ud = parts(X)
+        return k * Rd * ud / r2 ** (0.5 * dim)
+
+    def g(*X):
+        d, r2, ud = parts(X)
+        return tuple(k * Rd * (U[i] / r2 ** (0.5 * dim) - dim * ud * d[i] / r2 ** (0.5 * dim + 1.0))
+                     for i in range(dim))
+
+    return Manufactured(u, g, lambda *X: 0.0 * X[0])
+
+
+def body_flow_cp(xyz, center=(0.0, 0.0, 0.0), u_inf=(1.0, 0.0, 0.0)) -> np.ndarray:
+    """Surface pressure coefficient of that flow on the body:
+    C_p = 1 - (dim / (dim - 1))^2 sin^2(theta), theta the angle between
+    x - centre and u_inf (1 - 4 sin^2 on the cylinder, 1 - 9/4 sin^2 on the sphere)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    dim = xyz.shape[1]
+    d = xyz - np.asarray(center, dtype=np.float64)[None, :dim]
+    U = np.asarray(u_inf, dtype=np.float64)[:dim]
+    cos_t = d @ U / (np.linalg.norm(d, axis=1) * np.linalg.norm(U))
+    return 1.0 - (dim / (dim - 1.0)) ** 2 * (1.0 - cos_t ** 2)
+
+
+def potential_body(dim: int, n: int, precision: str = "fp64", center=(0.02, -0.03, 0.01),
+                   radius: float = 0.5) -> Workload:
+    """Exterior potential flow past one circle (2D) or sphere (3D): Neumann data
+    -u_inf . n on the body, the exact potential on the box faces, f = 0 (the
+    wall-velocity and pressure-coefficient recovery of the paper's
+    potential-flow application, on a body whose answer is known in closed form)."""
+    return Workload("potential_body", dim, n, GEOM_SPHERE, list(center)[:dim] + [radius], SIDE_EXTERIOR,
+                    BC_NEUMANN, exact=ms_body_flow(dim, center, radius), precision=precision)
+
+
 def ms_paper_interface(dim: int = 2) -> Manufactured:
     """The paper's material-interface solution (Sec. 2.4):
     u^+ = 0.6 + 0.4 sin(4 pi x) sin(2 pi y),  u^- = sin(4 pi x) sin(2 pi y)."""
