@@ -49,6 +49,7 @@ DESCR = {
     "neu3d": "3D singular pure-Neumann sphere r=0.6 off centre (bordered system), 256^3, u=cos(2x)sinh(y)+z^2",
 }
 HBM_PEAK_GBS = 8000.0
+SERVE_WINDOW_US = 50
 
 # Bytes beyond L2 per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch; `python3 bench.py --probe-kernel <id>`), each
@@ -229,14 +230,14 @@ def nearest_rank(values, q):
     return v[min(len(v) - 1, max(0, math.ceil(q * len(v)) - 1))]
 
 
-def serve_stream(reqs, slots, budget_bytes, log_every=0):
+def serve_stream(reqs, slots, budget_bytes, log_every=0, batch=False, window_us=SERVE_WINDOW_US):
     """Replays a request stream against the solve server: each request is
     submitted at its arrival time (server clock).  Latency = completion -
     arrival (setup included); solves/s = completed / (last completion - first
     arrival); p50/p99 by nearest rank.  Requests carry device-side synthetic
     data, so nothing else touches the device meanwhile."""
     from paper_2503_22455_amd import iim
-    srv = iim.Server(budget_bytes, slots)
+    srv = iim.Server(budget_bytes, slots, batch_tails=batch, batch_window_us=window_us)
     t0 = srv.clock()
     tickets, arrivals = [], []
     for i, r in enumerate(reqs):
@@ -256,6 +257,9 @@ def serve_stream(reqs, slots, budget_bytes, log_every=0):
     res = [srv.wait(t) for t in tickets]
     st = srv.stats()
     srv.close()
+    batching = {"batched_tails": batch, "window_us": window_us if batch else None,
+                "tail_batches": st["tail_batches"], "tail_jobs": st["tail_jobs"],
+                "mean_batch": st["tail_jobs"] / st["tail_batches"] if st["tail_batches"] else None}
     lat = [r["t_finish"] - a for r, a in zip(res, arrivals)]
     ok = [r for r in res if r["status"] == 0]
     span = max(r["t_finish"] for r in res) - min(arrivals)
@@ -269,6 +273,7 @@ def serve_stream(reqs, slots, budget_bytes, log_every=0):
         "max_rel_residual": float(max(r["rel_residual"] for r in ok)) if ok else None,
         "max_error": float(max(r["max_error"] for r in ok)) if ok else None,
         "iterations_mean": float(np.mean([r["iterations"] for r in ok])) if ok else None,
+        "batching": batching,
     }
 
 
@@ -282,7 +287,8 @@ def serving_main(args):
     torch.cuda.set_device(0)
     budget = int(args.serve_budget_gib * 2 ** 30)
     cap_reqs = W.serving_requests(count=args.serve_capacity_count, rate=1e9, seed=1)
-    cap = serve_stream(cap_reqs, args.serve_slots, budget)
+    bk = dict(batch=bool(args.serve_batch), window_us=args.serve_window_us)
+    cap = serve_stream(cap_reqs, args.serve_slots, budget, **bk)
     C = cap["solves_per_s"]
     print(f"[serve] closed-loop capacity {C:.1f} solves/s ({json.dumps(cap)})", file=sys.stderr, flush=True)
     fracs = [float(f) for f in args.serve_fracs.split(",")]
@@ -292,7 +298,7 @@ def serving_main(args):
         reqs = W.serving_requests(count=args.serve_count, rate=lam, seed=1)
         print(f"[serve] rate {lam:.1f}/s ({fr} C): {len(reqs)} requests over {reqs[-1].arrival:.1f} s",
               file=sys.stderr, flush=True)
-        r = serve_stream(reqs, args.serve_slots, budget, log_every=max(1, len(reqs) // 10))
+        r = serve_stream(reqs, args.serve_slots, budget, log_every=max(1, len(reqs) // 10), **bk)
         r["rate_per_s"] = lam
         r["rate_fraction_of_capacity"] = fr
         print(f"[serve] rate {lam:.1f}/s: {json.dumps(r)}", file=sys.stderr, flush=True)
@@ -306,7 +312,8 @@ def serving_main(args):
         "config": {"workload": (f"request stream: {args.serve_count} Poisson arrivals per rate at "
                                 f"{args.serve_fracs} x closed-loop capacity; 2D circle n U[128,2048] / 3D sphere "
                                 f"n U[32,192], r U[0.3,0.7], centre offset <= 0.2, mixed32 solve to 1e-10"),
-                   "slots": args.serve_slots, "budget_GiB": args.serve_budget_gib},
+                   "slots": args.serve_slots, "budget_GiB": args.serve_budget_gib,
+                   "batched_tails": bool(args.serve_batch), "window_us": args.serve_window_us},
         "capacity_solves_per_s": C, "capacity_run": cap,
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "levels": levels,
     }
@@ -356,6 +363,10 @@ def main():
     ap.add_argument("--serve-capacity-count", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-batch", type=int, default=0, choices=(0, 1),
+                    help="1: the server batches the V-cycle tails of requests solving together")
+    ap.add_argument("--serve-window-us", type=int, default=SERVE_WINDOW_US,
+                    help="longest wait of a tail for the other solving requests")
     ap.add_argument("--probe-kernel", type=int, default=None,
                     help="counter-probe mode: launch this kernel id and a reference copy, nothing else")
     ap.add_argument("--probe-reps", type=int, default=10)
@@ -400,6 +411,9 @@ def main():
         reqs = W.serving_requests(count=args.serve_short, rate=1e9, seed=1)
         serving = serve_stream(reqs, args.serve_slots, int(args.serve_budget_gib * 2 ** 30))
         serving["arrivals"] = "all at t=0"
+        bt = serve_stream(reqs, args.serve_slots, int(args.serve_budget_gib * 2 ** 30), batch=True)
+        serving["batched_tails"] = {k: bt[k] for k in ("p50_ms", "p99_ms", "solves_per_s", "max_rel_residual",
+                                                       "batching")}
         print(f"[bench] serving: {json.dumps(serving)}", file=sys.stderr, flush=True)
 
     cpu = None

@@ -308,11 +308,12 @@ int iim_synthetic_error(iim_problem* p, int32_t kind, const double* u, double* m
  * budget_bytes; a request whose estimate alone exceeds the budget fails with
  * IIM_E_BUDGET without blocking the queue.  Every request keeps its level
  * hierarchy and Krylov basis resident on the device until it completes.
- * Unless disabled at creation, the small coarse levels of the V-cycles
- * (Sec. 3.3: the levels below the finest ones, coarse solve included, which
- * one workgroup handles) of all requests that reach them together run as one
- * batched launch, one workgroup per request; each request's result is bit for
- * bit the one it gets alone. */
+ * With batch_tails (iim_server_create_ex), the small coarse levels of the
+ * V-cycles (Sec. 3.3: the levels below the finest ones, coarse solve included,
+ * which one workgroup handles) of the requests that reach them together run as
+ * one batched launch, one workgroup per request; each request's result is bit
+ * for bit the one it gets alone.  Batching couples the requests' streams (a
+ * batch waits for every member's finer levels), so it is off by default. */
 typedef struct iim_server iim_server;
 
 typedef struct iim_request {
@@ -361,10 +362,11 @@ typedef struct iim_server_stats {
 } iim_server_stats;
 
 typedef struct iim_server_options {
-    int32_t batch_tails;     /* 1 (default): batch the V-cycle tails of requests solving
-                                together; 0: every request launches its own */
-    int32_t batch_window_us; /* longest wait of a tail for the other solving requests to
-                                reach theirs before the batch launches (default 100) */
+    int32_t batch_tails;     /* 1: batch the V-cycle tails of requests solving together;
+                                0 (default): every request launches its own */
+    int32_t batch_window_us; /* longest wait of the first tail of a batch for the other solving
+                                requests to reach theirs (default 0: a batch holds the tails
+                                that arrive while its first one is being launched) */
 } iim_server_options;
 
 /* budget_bytes: device memory the server may reserve for running requests;

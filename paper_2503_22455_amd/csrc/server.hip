@@ -12,13 +12,13 @@
 // of the budget.
 //
 // Cross-request batching: the tail of every V-cycle (the small coarse levels
-// and the coarse solve, one workgroup's work) is handed to a tail engine.  The
-// engine gathers the tails of the requests that are solving, waits at most a
-// short window for the ones still on their way, and runs each group of equal
-// precision and dimension as one launch with one workgroup per request, on its
-// own stream, ordered after each request's finer levels (an event per request)
-// and before its prolongation (one event per batch).  A workgroup runs exactly
-// the request's own tail, so results do not depend on the batch.
+// and the coarse solve, one workgroup's work) goes through a batcher.  The
+// tails of the requests that reach them together (the first to arrive waits at
+// most a short window for the others) run as one launch per precision and
+// dimension, one workgroup per request, on the first request's stream, ordered
+// after each member's finer levels (an event per member) and before each
+// member's prolongation (one event per batch).  A workgroup runs exactly the
+// request's own tail, so results do not depend on the batch.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -39,47 +39,28 @@ struct Job {
 // one V-cycle tail waiting for (or taken by) a batch
 struct TailJob {
     Problem* p = nullptr;
-    hipEvent_t ready = nullptr;  // recorded on p's stream after the levels above the tail
-    hipEvent_t done = nullptr;   // recorded on the engine's stream after the batch that ran it
+    hipEvent_t ready = nullptr;  // the member's: recorded on p's stream after the levels above the tail
+    hipEvent_t done = nullptr;   // the member's: recorded on the leader's stream after the batch
     bool launched = false;
     int error = 0;
 };
 
-struct TailEngine final : TailRunner {
-    int device = 0;
-    int window_us = 100;
-    hipStream_t stream = nullptr;
+// Batches the V-cycle tails of the requests that reach them together.  The
+// first worker to arrive at an open batch leads it: it waits (at most the
+// window) until every solving worker has joined or the window has passed,
+// closes the batch, makes its own stream wait for the other members' finer
+// levels, launches the batch there and records one event that the members'
+// streams wait for.  No thread other than the workers is involved.
+struct TailBatcher final : TailRunner {
+    int window_us = 0;
     std::mutex mu;
     std::condition_variable cv;
-    std::vector<TailJob*> pending;
+    std::vector<TailJob*> open;  // members of the batch being gathered
+    bool leader_waiting = false;
     int solving = 0;  // workers inside a solve: the ones whose tails may join a batch
-    bool stop = false;
-    std::vector<hipEvent_t> ring;  // one event per batch, reused after ring.size() batches
-    size_t ring_next = 0;
     int64_t batches = 0, jobs = 0;
-    std::thread th;
 
-    void start(int dev, int window) {
-        device = dev;
-        window_us = window;
-        IIM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-        ring.resize(256);
-        for (auto& e : ring) IIM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        th = std::thread([this] { loop(); });
-    }
-    void finish() {
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            stop = true;
-        }
-        cv.notify_all();
-        if (th.joinable()) th.join();
-        if (stream) (void)hipStreamSynchronize(stream);
-        for (auto& e : ring)
-            if (e) (void)hipEventDestroy(e);
-        if (stream) (void)hipStreamDestroy(stream);
-        stream = nullptr;
-    }
+    explicit TailBatcher(int window) : window_us(window) {}
     void enter() {
         std::lock_guard<std::mutex> lk(mu);
         ++solving;
@@ -89,11 +70,10 @@ struct TailEngine final : TailRunner {
             std::lock_guard<std::mutex> lk(mu);
             --solving;
         }
-        cv.notify_all();  // a batch waiting for this worker's tail need not wait longer
+        cv.notify_all();  // a leader waiting for this worker's tail need not wait longer
     }
     void run(Problem& p) override;
-    void loop();
-    void launch(const std::vector<TailJob*>& batch);
+    static void launch(const std::vector<TailJob*>& batch, hipStream_t s);
 };
 
 struct Server {
@@ -107,7 +87,7 @@ struct Server {
     int64_t reserved = 0, peak = 0, submitted = 0, completed = 0, failed = 0, running = 0;
     bool stopping = false;
     std::vector<std::thread> workers;
-    std::unique_ptr<TailEngine> engine;  // null: every request launches its own tails
+    std::unique_ptr<TailBatcher> engine;  // null: every request launches its own tails
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     double clock() const {
@@ -117,90 +97,89 @@ struct Server {
     void run(Job& j, hipStream_t s, double* hpin);
 };
 
-// the calling worker's event that marks its problem's finer levels as done
-struct ReadyEvent {
-    hipEvent_t ev = nullptr;
-    ~ReadyEvent() {
-        if (ev) (void)hipEventDestroy(ev);
+// the calling worker's events: its finer levels done, its tail's batch done
+// (each is recorded and waited for only while the worker takes part in one
+// batch, so no other batch can record it meanwhile)
+struct MemberEvents {
+    hipEvent_t ready = nullptr, done = nullptr;
+    ~MemberEvents() {
+        if (ready) (void)hipEventDestroy(ready);
+        if (done) (void)hipEventDestroy(done);
     }
 };
 
-void TailEngine::run(Problem& p) {
-    thread_local ReadyEvent tl;
-    if (!tl.ev) IIM_HIP(hipEventCreateWithFlags(&tl.ev, hipEventDisableTiming));
+void TailBatcher::run(Problem& p) {
+    thread_local MemberEvents tl;
+    if (!tl.ready) IIM_HIP(hipEventCreateWithFlags(&tl.ready, hipEventDisableTiming));
+    if (!tl.done) IIM_HIP(hipEventCreateWithFlags(&tl.done, hipEventDisableTiming));
     TailJob job;
     job.p = &p;
-    job.ready = tl.ev;
-    IIM_HIP(hipEventRecord(job.ready, p.stream));
-    {
-        std::unique_lock<std::mutex> lk(mu);
-        pending.push_back(&job);
+    job.ready = tl.ready;
+    job.done = tl.done;
+    std::unique_lock<std::mutex> lk(mu);
+    const bool lead = open.empty();
+    if (!lead) IIM_HIP(hipEventRecord(job.ready, p.stream));  // the leader orders its own stream
+    open.push_back(&job);
+    if (!lead) {
         cv.notify_all();
         cv.wait(lk, [&] { return job.launched; });
+        lk.unlock();
+        if (job.error) throw Error(job.error, "batched coarse-level launch failed");
+        IIM_HIP(hipStreamWaitEvent(p.stream, job.done, 0));
+        return;
     }
-    if (job.error) throw Error(job.error, "batched coarse-level launch failed");
-    IIM_HIP(hipStreamWaitEvent(p.stream, job.done, 0));
+    // lead: gather the tails of the other solving workers for at most the window
+    if (window_us > 0) {
+        const auto deadline = std::chrono::steady_clock::now() + std::chrono::microseconds(window_us);
+        cv.wait_until(lk, deadline, [&] { return (int)open.size() >= solving; });
+    }
+    std::vector<TailJob*> batch;
+    batch.swap(open);  // later arrivals open the next batch
+    ++batches;
+    jobs += (int64_t)batch.size();
+    lk.unlock();
+    int err = 0;
+    try {
+        launch(batch, p.stream);
+        for (TailJob* j : batch)
+            if (j != &job) IIM_HIP(hipEventRecord(j->done, p.stream));
+    } catch (const Error& e) {
+        err = e.code;
+    } catch (...) {
+        err = IIM_E_INTERNAL;
+    }
+    lk.lock();
+    for (TailJob* j : batch) {
+        j->error = err;
+        j->launched = true;
+    }
+    lk.unlock();
+    cv.notify_all();
+    if (err) throw Error(err, "batched coarse-level launch failed");
 }
 
-void TailEngine::launch(const std::vector<TailJob*>& batch) {
-    // one launch per (precision, dimension) group, at most TAIL_BATCH_MAX tails each
+// one launch per (precision, dimension) group, at most TAIL_BATCH_MAX tails
+// each, on stream s after every member's finer levels
+void TailBatcher::launch(const std::vector<TailJob*>& batch, hipStream_t s) {
     for (int prec = 0; prec <= 2; ++prec)
         for (int dim = 2; dim <= 3; ++dim) {
             TailBatch B{};
             auto flush = [&] {
                 if (!B.count) return;
-                if (prec == IIM_PREC_FP64) run_tail_batch<double, double>(dim, B, stream);
-                else if (prec == IIM_PREC_MIXED32) run_tail_batch<float, float>(dim, B, stream);
-                else run_tail_batch<float, __half>(dim, B, stream);
+                if (prec == IIM_PREC_FP64) run_tail_batch<double, double>(dim, B, s);
+                else if (prec == IIM_PREC_MIXED32) run_tail_batch<float, float>(dim, B, s);
+                else run_tail_batch<float, __half>(dim, B, s);
                 B.count = 0;
             };
             for (TailJob* j : batch) {
                 if (j->p->opt.precision != prec || j->p->dim != dim) continue;
-                IIM_HIP(hipStreamWaitEvent(stream, j->ready, 0));
+                if (j->p->stream != s) IIM_HIP(hipStreamWaitEvent(s, j->ready, 0));
                 B.d[B.count] = j->p->d_tail;
                 B.lds[B.count] = j->p->tail_lds_bytes;
                 if (++B.count == TAIL_BATCH_MAX) flush();
             }
             flush();
         }
-}
-
-void TailEngine::loop() {
-    if (hipSetDevice(device) != hipSuccess) return;
-    std::unique_lock<std::mutex> lk(mu);
-    while (true) {
-        cv.wait(lk, [&] { return stop || !pending.empty(); });
-        if (pending.empty()) {
-            if (stop) break;
-            continue;
-        }
-        // give the other solving requests a short window to reach their tails
-        const auto deadline = std::chrono::steady_clock::now() + std::chrono::microseconds(window_us);
-        cv.wait_until(lk, deadline, [&] { return stop || (int)pending.size() >= solving; });
-        std::vector<TailJob*> batch;
-        batch.swap(pending);
-        hipEvent_t ev = ring[ring_next];
-        ring_next = (ring_next + 1) % ring.size();
-        lk.unlock();
-        int err = 0;
-        try {
-            launch(batch);
-            IIM_HIP(hipEventRecord(ev, stream));
-        } catch (const Error& e) {
-            err = e.code;
-        } catch (...) {
-            err = IIM_E_INTERNAL;
-        }
-        lk.lock();
-        for (TailJob* j : batch) {
-            j->done = ev;
-            j->error = err;
-            j->launched = true;
-        }
-        ++batches;
-        jobs += (int64_t)batch.size();
-        cv.notify_all();
-    }
 }
 
 void Server::run(Job& j, hipStream_t s, double* hpin) {
@@ -354,7 +333,7 @@ int iim_server_create_ex(int64_t budget_bytes, int32_t max_slots, const iim_serv
         *out = nullptr;
         if (budget_bytes <= 0) throw Error(IIM_E_INVALID_ARG, "budget must be positive");
         if (max_slots < 1 || max_slots > 64) throw Error(IIM_E_INVALID_ARG, "max_slots must be in [1, 64]");
-        iim_server_options o{1, 100};
+        iim_server_options o{0, 0};
         if (opt) o = *opt;
         if (o.batch_window_us < 0 || o.batch_window_us > 100000)
             throw Error(IIM_E_INVALID_ARG, "batch_window_us must be in [0, 100000]");
@@ -362,10 +341,7 @@ int iim_server_create_ex(int64_t budget_bytes, int32_t max_slots, const iim_serv
         IIM_HIP(hipGetDevice(&srv->s.device));
         configure_pool(srv->s.device);
         srv->s.budget = budget_bytes;
-        if (o.batch_tails) {
-            srv->s.engine = std::make_unique<TailEngine>();
-            srv->s.engine->start(srv->s.device, o.batch_window_us);
-        }
+        if (o.batch_tails) srv->s.engine = std::make_unique<TailBatcher>(o.batch_window_us);
         for (int i = 0; i < max_slots; ++i) srv->s.workers.emplace_back([p = &srv->s] { p->worker(); });
         *out = srv.release();
         return IIM_OK;
@@ -467,7 +443,6 @@ void iim_server_destroy(iim_server* srv) {
     }
     srv->s.cv_work.notify_all();
     for (auto& t : srv->s.workers) t.join();
-    if (srv->s.engine) srv->s.engine->finish();
     delete srv;
     trim_pool();
 }

@@ -356,7 +356,7 @@ class Problem:
 class Server:
     """Continuous-batching solve server on the current device (iim_server_*)."""
 
-    def __init__(self, budget_bytes: int, max_slots: int, batch_tails: bool = True, batch_window_us: int = 100):
+    def __init__(self, budget_bytes: int, max_slots: int, batch_tails: bool = False, batch_window_us: int = 0):
         self._s = ctypes.c_void_p()
         self._keep = {}
         o = ServerOptions(int(batch_tails), int(batch_window_us))

@@ -243,7 +243,7 @@ def test_server_caller_data_alone_and_in_mix(batch):
         ref.append((wl, f, cpd, box, u, hist, st))
     # alone
     for wl, f, cpd, box, u, hist, st in ref:
-        s1 = iim.Server(64 << 30, 1, batch_tails=batch)
+        s1 = iim.Server(64 << 30, 1, batch_tails=batch, batch_window_us=200)
         uo = torch.empty_like(u)
         r = s1.wait(_submit_wl(s1, wl, uo, f, cpd, box, hist_cap=500))
         s1.close()
@@ -251,7 +251,7 @@ def test_server_caller_data_alone_and_in_mix(batch):
         assert torch.equal(uo.nan_to_num(0.0), u.nan_to_num(0.0))
         assert np.array_equal(r["hist"], hist)
     # in a mix
-    s4 = iim.Server(64 << 30, 4, batch_tails=batch)
+    s4 = iim.Server(64 << 30, 4, batch_tails=batch, batch_window_us=200)
     outs, tickets = [], []
     for i, spec in enumerate(MIX):
         tickets.append(_submit(s4, spec))
@@ -283,7 +283,7 @@ def test_server_batched_tails_bitwise_and_graphs():
     outs = {}
     stats = {}
     for mode in ("own", "batched", "batched-graph"):
-        srv = iim.Server(64 << 30, 4, batch_tails=mode != "own")
+        srv = iim.Server(64 << 30, 4, batch_tails=mode != "own", batch_window_us=200)
         us = [torch.empty(_numel(spec), dtype=torch.float64, device="cuda") for spec in MIX]
         kw = dict(use_graph=1) if mode == "batched-graph" else {}
         tickets = [_submit(srv, spec, u, **kw) for spec, u in zip(MIX, us)]
