@@ -205,6 +205,20 @@ int iim_node_labels(const iim_problem* p, uint8_t* labels);
 int iim_set_boundary_data(iim_problem* p, const double* cp_data, const double* box_data,
                           int32_t mem_kind);
 
+/* iim_set_boundary_data for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, such as tight serving loops or harnesses that
+ * forbid allocation): the same operation with no device allocation.  The box
+ * data are staged in a library-wide static device array of
+ * IIM_NOALLOC_MAX_NODES doubles (32 MiB, one copy per device, held until the
+ * process ends) instead of a buffer allocated for the call; (n+1)^dim above
+ * that limit fails with IIM_E_INVALID_ARG.  The handle's device must be the
+ * current one.  All calls on one device share its array: calls that overlap
+ * on one device (from several host threads) race and must be serialised by
+ * the caller; each call has finished with the array when it returns. */
+#define IIM_NOALLOC_MAX_NODES (1 << 22)
+int iim_set_boundary_data_noalloc(iim_problem* p, const double* cp_data, const double* box_data,
+                                  int32_t mem_kind);
+
 /* Source term f (full-grid array, read at the unknowns); builds the right-hand
  * side b = f - L_Gamma u_Gamma with the current boundary data. */
 int iim_set_rhs(iim_problem* p, const double* f, int32_t mem_kind);

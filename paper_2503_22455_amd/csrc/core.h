@@ -180,7 +180,9 @@ struct Problem {
     template <typename T, typename S> void launch_kernel_t(int kernel);
     double time_kernel(int kernel, int reps);
     template <typename T, typename S> int level_op_t(int level, int op, const double* in1, double* out);
-    void set_boundary_data(const double* cp_data, const double* box_data, int mem_kind);
+    // staging: a device buffer of (n+1)^dim doubles for the box data (nullptr:
+    // one is allocated for the call)
+    void set_boundary_data(const double* cp_data, const double* box_data, int mem_kind, double* staging = nullptr);
     void set_rhs(const double* f, int mem_kind);
     void synth_data(int kind);
     double synth_error(int kind, const double* u_full);

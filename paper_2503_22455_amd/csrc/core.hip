@@ -1124,7 +1124,7 @@ int Problem::solve(double* u_full, const double* x0_full, double* hist, int hist
 // the caller's data (Sec. 2.1-2.3): boundary / interface values per control
 // point and box-face values, then the right-hand side b = f - L_Gamma u_Gamma
 // ---------------------------------------------------------------------------
-void Problem::set_boundary_data(const double* cp_data, const double* box_data, int mem_kind) {
+void Problem::set_boundary_data(const double* cp_data, const double* box_data, int mem_kind, double* staging) {
     const int64_t ncd = cp.ncp * (bc == IIM_BC_JUMP ? 2 : 1);
     hipMemcpyKind k = mem_kind == IIM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (ncd) {
@@ -1134,11 +1134,11 @@ void Problem::set_boundary_data(const double* cp_data, const double* box_data, i
     if (box_data) {
         const int64_t n1 = grid.n + 1;
         const int64_t tot = dim == 2 ? n1 * n1 : n1 * n1 * n1;
-        double* tmp = (double*)mem.alloc(tot * sizeof(double));
+        double* tmp = staging ? staging : (double*)mem.alloc(tot * sizeof(double));
         IIM_HIP(hipMemcpyAsync(tmp, box_data, tot * sizeof(double), k, stream));
         run_full_to_box(dim, grid.n, box, tmp, boxval, levels[0].labels, 2, stream);
         IIM_HIP(hipStreamSynchronize(stream));
-        mem.release(tmp);
+        if (!staging) mem.release(tmp);
     } else {
         IIM_HIP(hipMemsetAsync(boxval, 0, box.size() * sizeof(double), stream));
     }
@@ -1586,6 +1586,26 @@ Problem::~Problem() {
 // ===========================================================================
 using namespace iim;
 
+// Staging array of iim_set_boundary_data_noalloc: one copy per device, held
+// until the process ends.  Host code never uses the name `scratch` as an
+// address; it uses the per-device pointer from hipGetSymbolAddress, taken once
+// per device (with that device current) on the first call there.
+static __device__ __align__(256) double scratch[IIM_NOALLOC_MAX_NODES];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[64] = {};
+
+static double* noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= 64) throw Error(IIM_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        IIM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Error(IIM_E_DEVICE, "no address for the static staging array");
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 struct iim_problem {
     std::unique_ptr<Problem> p;
 };
@@ -1725,6 +1745,28 @@ int iim_set_boundary_data(iim_problem* h, const double* cp_data, const double* b
     ABI_TRY({
         if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
         h->p->set_boundary_data(cp_data, box_data, mem_kind);
+        return IIM_OK;
+    })
+}
+
+int iim_set_boundary_data_noalloc(iim_problem* h, const double* cp_data, const double* box_data,
+                                  int32_t mem_kind) {
+    ABI_TRY({
+        if (!h) throw Error(IIM_E_INVALID_ARG, "null argument");
+        Problem& p = *h->p;
+        double* staging = nullptr;
+        if (box_data) {
+            const int64_t n1 = p.grid.n + 1;
+            const int64_t tot = p.dim == 2 ? n1 * n1 : n1 * n1 * n1;
+            if (tot > IIM_NOALLOC_MAX_NODES)
+                throw Error(IIM_E_INVALID_ARG, "box data of " + std::to_string(tot) +
+                                                   " nodes exceed the static staging array (IIM_NOALLOC_MAX_NODES)");
+            int dev = 0;
+            IIM_HIP(hipGetDevice(&dev));
+            if (dev != p.mem.device) throw Error(IIM_E_INVALID_ARG, "the handle's device is not the current one");
+            staging = noalloc_scratch(dev);
+        }
+        p.set_boundary_data(cp_data, box_data, mem_kind, staging);
         return IIM_OK;
     })
 }

@@ -115,6 +115,7 @@ def lib():
         L.iim_node_labels.argtypes = [vp, vp]
         L.iim_set_boundary_data.argtypes = [vp, vp, vp, i32]
         L.iim_set_rhs.argtypes = [vp, vp, i32]
+        L.iim_set_boundary_data_noalloc.argtypes = [vp, vp, vp, i32]
         L.iim_solve.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(Stats)]
         L.iim_apply.argtypes = [vp, vp, vp, i32]
         L.iim_vcycle.argtypes = [vp, vp, vp]
@@ -285,6 +286,14 @@ class Problem:
         box = None if box_data is None else self._dev(box_data)
         _check(lib().iim_set_boundary_data(self._h, _ptr(cpd) if cpd.numel() else None,
                                            None if box is None else _ptr(box), MEM_DEVICE))
+
+    def set_boundary_data_noalloc(self, cp_data, box_data=None):
+        """As set_boundary_data, with no device allocation in the library
+        (iim_set_boundary_data_noalloc: box data staged in its static array)."""
+        cpd = self._dev(cp_data)
+        box = None if box_data is None else self._dev(box_data)
+        _check(lib().iim_set_boundary_data_noalloc(self._h, _ptr(cpd) if cpd.numel() else None,
+                                                   None if box is None else _ptr(box), MEM_DEVICE))
 
     def set_rhs(self, f):
         ft = self._dev(f)
