@@ -264,6 +264,25 @@ int iim_gradient(iim_problem* p, const double* u, double* grad);
  * (device memory then held by the handle). */
 int iim_boundary_quantity(iim_problem* p, const double* u, double* q);
 
+/* Wall derivatives of a solution at every control point (Sec. 2.1 fits,
+ * evaluated as in the potential-flow application of Sec. 4.4.2, which
+ * recovers the wall velocity and the pressure coefficient from them), with the
+ * boundary data last given by iim_set_boundary_data.  u: device full-grid
+ * array (read at the unknowns).
+ * grad: device array of n_control_points * dim doubles (control point c's
+ * components at c * dim + d, control-point order of iim_control_points): the
+ * gradient at x_c of the solved side's least-squares polynomial (the Omega^+
+ * one for interfaces), whose value at x_c is ubar (Dirichlet), the Neumann
+ * closure, or u+ from the interface closure.  For a Neumann condition its
+ * normal component is qbar / beta.
+ * u_inf, cp: both NULL, or a host array of dim doubles (a free stream U, not
+ * zero) and a device array of n_control_points doubles receiving the pressure
+ * coefficient C_p = 1 - |grad + U|^2 / |U|^2 of the wall velocity grad + U
+ * (u the disturbance potential of a potential flow).
+ * The first call fits every control point once more with the derivative rows
+ * (device memory then held by the handle). */
+int iim_wall_gradient(iim_problem* p, const double* u, double* grad, const double* u_inf, double* cp);
+
 /* Least-squares stencil of control point cp on side (1 = Omega^+, 2 = Omega^-):
  * m grid points (full-grid flat indices in idx) and the (m+1) x r weights in
  * weights[row * r + col] (row 0 multiplies u(x_c); columns: ghosts 1..w, then

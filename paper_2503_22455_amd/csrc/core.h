@@ -115,6 +115,12 @@ struct Problem {
     double* nd_S = nullptr;
     double* nd_Sc = nullptr;
     int64_t nd_nnz = 0;
+    // fits with the rows d/dn and d/dx_d (wall gradient), made on first use
+    int64_t* gd_ptr = nullptr;
+    int32_t* gd_idx = nullptr;
+    double* gd_S = nullptr;
+    double* gd_Sc = nullptr;
+    int64_t gd_nnz = 0;
     double* W_apply = nullptr;
     double* dcoef = nullptr;
     double* ghost = nullptr;
@@ -152,9 +158,11 @@ struct Problem {
     double t_setup_ms = 0.0;
 
     void setup();
+    // ghost_rows: ghost functionals before the derivative rows (-1: w)
     void fit_stencils(int nr, int* d_err, int64_t*& ptr_out, int32_t*& idx_out, double*& S_out, double*& Sc_out,
-                      std::vector<int64_t>& hptr, int64_t& nz);
+                      std::vector<int64_t>& hptr, int64_t& nz, int ghost_rows = -1);
     void ensure_normal_rows();
+    void ensure_grad_rows();
     LevelSet level_set() const;
     LevelDev level_dev(int l) const;
     GhostDev ghost_dev() const;

@@ -227,7 +227,7 @@ static void raise_setup_error(int h, const char* what) {
 // device error word.  The pass is deterministic: a second call returns the
 // same sets.
 void Problem::fit_stencils(int nr, int* d_err, int64_t*& ptr_out, int32_t*& idx_out, double*& S_out,
-                           double*& Sc_out, std::vector<int64_t>& hptr, int64_t& nz) {
+                           double*& Sc_out, std::vector<int64_t>& hptr, int64_t& nz, int ghost_rows) {
     const Level& L0 = levels[0];
     const int64_t ncs = cp.ncp * nsides;
     int err_bits = 0;
@@ -238,7 +238,7 @@ void Problem::fit_stencils(int nr, int* d_err, int64_t*& ptr_out, int32_t*& idx_
     LSParams P;
     P.dim = dim;
     P.order_k = opt.order_k;
-    P.w = w;
+    P.w = ghost_rows < 0 ? w : ghost_rows;
     P.nrows = nr;
     P.nsides = nsides;
     P.a0 = opt.ls_axis_t > 0 ? opt.ls_axis_t : (double)opt.order_k;
@@ -323,6 +323,23 @@ void Problem::ensure_normal_rows() {
     mem.release(d_err);
     raise_setup_error(err, "least-squares fits with the normal-derivative row");
     if (hp != h_ptr) throw Error(IIM_E_INTERNAL, "normal-derivative fits: the sets differ from the setup's");
+}
+
+// The gradient fits of the wall derivatives: every control point fitted once
+// more with the rows d/dn and d/dx_d (no ghost rows), kept for later calls.
+// The sets are those of the setup (the pass is deterministic).
+void Problem::ensure_grad_rows() {
+    if (gd_S) return;
+    int* d_err = (int*)mem.alloc(sizeof(int64_t));
+    IIM_HIP(hipMemsetAsync(d_err, 0, sizeof(int64_t), stream));
+    std::vector<int64_t> hp;
+    fit_stencils(1 + dim, d_err, gd_ptr, gd_idx, gd_S, gd_Sc, hp, gd_nnz, 0);
+    int err = 0;
+    IIM_HIP(hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, stream));
+    IIM_HIP(hipStreamSynchronize(stream));
+    mem.release(d_err);
+    raise_setup_error(err, "least-squares fits with the derivative rows");
+    if (hp != h_ptr) throw Error(IIM_E_INTERNAL, "gradient fits: the sets differ from the setup's");
 }
 
 void Problem::setup() {
@@ -1850,6 +1867,38 @@ int iim_boundary_quantity(iim_problem* h, const double* u, double* q) {
         B.Sc = own ? p.ls_Sc : p.nd_Sc;
         B.ncp = p.cp.ncp;
         run_boundary_quantity(B, p.rk, p.cpdata, q, p.stream);
+        IIM_HIP(hipStreamSynchronize(p.stream));
+        return IIM_OK;
+    })
+}
+
+int iim_wall_gradient(iim_problem* h, const double* u, double* grad, const double* u_inf, double* cp) {
+    ABI_TRY({
+        if (!h || !u || !grad) throw Error(IIM_E_INVALID_ARG, "null argument");
+        if ((u_inf == nullptr) != (cp == nullptr)) throw Error(IIM_E_INVALID_ARG, "u_inf and cp go together");
+        Problem& p = *h->p;
+        WGDev G{};
+        if (u_inf) {
+            double u2 = 0.0;
+            for (int d = 0; d < p.dim; ++d) {
+                G.u_inf[d] = u_inf[d];
+                u2 += u_inf[d] * u_inf[d];
+            }
+            if (!(u2 > 0.0)) throw Error(IIM_E_INVALID_ARG, "u_inf must be non-zero");
+        }
+        p.ensure_grad_rows();
+        run_full_to_box(p.dim, p.grid.n, p.box, u, p.rk, p.levels[0].labels, 1, p.stream);
+        G.bc = p.bc;
+        G.nsides = p.nsides;
+        G.dim = p.dim;
+        G.beta_plus = p.opt.beta_plus;
+        G.beta_minus = p.opt.beta_minus;
+        G.ptr = p.gd_ptr;
+        G.idx = p.gd_idx;
+        G.S = p.gd_S;
+        G.Sc = p.gd_Sc;
+        G.ncp = p.cp.ncp;
+        run_wall_gradient(G, p.rk, p.cpdata, grad, cp, p.stream);
         IIM_HIP(hipStreamSynchronize(p.stream));
         return IIM_OK;
     })

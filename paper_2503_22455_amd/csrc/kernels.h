@@ -84,7 +84,7 @@ void run_fill_int(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 // ---- least squares (lsq.hip) -------------------------------------------------
 struct LSParams {
-    int dim, order_k, w, nrows;  // nrows = w (+1 with the normal derivative)
+    int dim, order_k, w, nrows;  // rows: w ghosts, then d/dn, then d/dx_d (gradient fits, w = 0)
     int nsides;
     double a0, b0;               // initial semi-axes (units of h)
     int max_grow;
@@ -254,6 +254,21 @@ struct BQDev {
 };
 // q[c]: du/dn (Dirichlet), u (Neumann) or du+/dn (interface) at control point c
 void run_boundary_quantity(const BQDev& B, const double* x, const double* cpdata, double* q, hipStream_t s);
+// Gradient of the solved side's fit at every control point from the gradient
+// fits (rows: d/dn, then d/dx_d), and optionally the wall velocity's pressure
+// coefficient C_p = 1 - |grad + U|^2 / |U|^2 for a free stream U.
+struct WGDev {
+    int bc, nsides, dim;           // fit rows: 1 + dim
+    double beta_plus, beta_minus;
+    const int64_t* ptr;            // [ncs + 1]
+    const int32_t* idx;            // [nnz] storage-box indices
+    const double* S;               // [1 + dim][nnz]
+    const double* Sc;              // [ncs][1 + dim] weights of u(x_c)
+    int64_t ncp;
+    double u_inf[3];               // free stream (C_p only)
+};
+void run_wall_gradient(const WGDev& G, const double* x, const double* cpdata, double* grad, double* cp,
+                       hipStream_t s);
 void run_fill(double* p, int64_t n, double v, hipStream_t s);
 
 // full grid <-> storage box

@@ -338,11 +338,13 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                                 for (int d = 0; d < g.dim; ++d) xi[d] = (xg[d] - xc[d]) / sc;
                                 val = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) * ipow(xi[2], ex[col][2]);
                             } else {
+                                // row w: d/dn; rows w + 1 + d: d/dx_d (gradient fits)
                                 int deg = ex[col][0] + ex[col][1] + ex[col][2];
                                 val = 0.0;
                                 if (deg == 1) {
                                     int d = ex[col][0] ? 0 : (ex[col][1] ? 1 : 2);
-                                    val = nrm[d] / sc;
+                                    const int r = k - P.w;
+                                    val = (r == 0 ? nrm[d] : (d == r - 1 ? 1.0 : 0.0)) / sc;
                                 }
                             }
                             E[k][col] = val;
@@ -511,11 +513,13 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                         for (int d = 0; d < g.dim; ++d) xi[d] = (xg[d] - xc[d]) / sc;
                         val = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) * ipow(xi[2], ex[col][2]);
                     } else {
+                        // row w: d/dn; rows w + 1 + d: d/dx_d (gradient fits)
                         int deg = ex[col][0] + ex[col][1] + ex[col][2];
                         val = 0.0;
                         if (deg == 1) {
                             int d = ex[col][0] ? 0 : (ex[col][1] ? 1 : 2);
-                            val = nrm[d] / sc;
+                            const int r = k - P.w;
+                            val = (r == 0 ? nrm[d] : (d == r - 1 ? 1.0 : 0.0)) / sc;
                         }
                     }
                     E[k][col] = val;

@@ -576,6 +576,79 @@ void run_boundary_quantity(const BQDev& B, const double* x, const double* cpdata
     IIM_LAUNCH_CHECK();
 }
 
+// One wave per control point, lanes over the fit's entries (coalesced rows):
+// the dot products of rows d/dn and d/dx_d with the solution, then on lane 0
+// the fit's value at x_c (Dirichlet: ubar; Neumann: the closure of the normal
+// row; interface: u+(x_c) from the interface closure, as the boundary
+// quantity), and grad_d = s^d_c U_c + sum_i s^d_i u_i.  With cp, also the
+// pressure coefficient of the wall velocity grad + U.
+template <int NS, int DIM>
+__global__ void __launch_bounds__(256) k_wall_gradient(WGDev G, const double* __restrict__ x,
+                                                       const double* __restrict__ cpdata, double* __restrict__ grad,
+                                                       double* __restrict__ cp) {
+    constexpr int GLN = 64, NR = 1 + DIM;
+    const int lane = threadIdx.x % GLN;
+    const int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / GLN;
+    if (c >= G.ncp) return;  // whole waves exit together
+    int64_t nnz = G.ptr[G.ncp * NS];
+    double dot[NR], dotm = 0.0;
+    {
+        const int64_t cs = c * NS;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) dot[r] = 0.0;
+        for (int64_t a = G.ptr[cs] + lane; a < G.ptr[cs + 1]; a += GLN) {
+            const double xv = x[G.idx[a]];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) dot[r] += G.S[r * nnz + a] * xv;
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            for (int off = GLN / 2; off > 0; off >>= 1) dot[r] += __shfl_xor(dot[r], off, GLN);
+        if (NS == 2) {
+            for (int64_t a = G.ptr[cs + 1] + lane; a < G.ptr[cs + 2]; a += GLN) dotm += G.S[a] * x[G.idx[a]];
+            for (int off = GLN / 2; off > 0; off >>= 1) dotm += __shfl_xor(dotm, off, GLN);
+        }
+    }
+    if (lane != 0) return;
+    const double bp = G.beta_plus;
+    const double* scp = G.Sc + (c * NS) * NR;
+    double uc;
+    if (NS == 1) {
+        uc = G.bc == IIM_BC_DIRICHLET ? cpdata[c] : (cpdata[c] - bp * dot[0]) / (bp * scp[0]);
+    } else {
+        const double bm = G.beta_minus;
+        const double scm = G.Sc[(c * 2 + 1) * NR];
+        const double D = bp * scp[0] - bm * scm;
+        const double ubar = -(bp * dot[0] - bm * dotm) / D;
+        uc = ubar + (cpdata[2 * c + 1] - bm * scm * cpdata[2 * c]) / D;
+    }
+    double v2 = 0.0, u2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double g = scp[1 + d] * uc + dot[1 + d];
+        grad[c * DIM + d] = g;
+        const double vd = g + G.u_inf[d];
+        v2 += vd * vd;
+        u2 += G.u_inf[d] * G.u_inf[d];
+    }
+    if (cp) cp[c] = 1.0 - v2 / u2;
+}
+
+void run_wall_gradient(const WGDev& G, const double* x, const double* cpdata, double* grad, double* cp,
+                       hipStream_t s) {
+    if (G.ncp == 0) return;
+    const int64_t threads = G.ncp * 64;
+    const dim3 grid(cdiv(threads, 256)), blk(256);
+    if (G.dim == 2) {
+        if (G.nsides == 1) hipLaunchKernelGGL((k_wall_gradient<1, 2>), grid, blk, 0, s, G, x, cpdata, grad, cp);
+        else hipLaunchKernelGGL((k_wall_gradient<2, 2>), grid, blk, 0, s, G, x, cpdata, grad, cp);
+    } else {
+        if (G.nsides == 1) hipLaunchKernelGGL((k_wall_gradient<1, 3>), grid, blk, 0, s, G, x, cpdata, grad, cp);
+        else hipLaunchKernelGGL((k_wall_gradient<2, 3>), grid, blk, 0, s, G, x, cpdata, grad, cp);
+    }
+    IIM_LAUNCH_CHECK();
+}
+
 __global__ void k_fill(double* p, int64_t n, double v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;

@@ -121,6 +121,7 @@ def lib():
         L.iim_vcycle.argtypes = [vp, vp, vp]
         L.iim_gradient.argtypes = [vp, vp, vp]
         L.iim_boundary_quantity.argtypes = [vp, vp, vp]
+        L.iim_wall_gradient.argtypes = [vp, vp, vp, vp, vp]
         L.iim_ls_stencil.argtypes = [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp, i32]
         L.iim_level_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]
         L.iim_level_labels.argtypes = [vp, i32, vp]
@@ -328,6 +329,22 @@ class Problem:
         q = torch.empty(max(int(self.info()["n_control_points"]), 1), dtype=torch.float64, device=u.device)
         _check(lib().iim_boundary_quantity(self._h, _ptr(u), _ptr(q)))
         return q[: int(self.info()["n_control_points"])]
+
+    def wall_gradient(self, u, u_inf=None):
+        """Gradient of the solved side's fit at every control point, shape
+        (n_control_points, dim) on the device; with a free stream u_inf (dim
+        values) also the pressure coefficient 1 - |grad + u_inf|^2 / |u_inf|^2
+        per control point (returned as a second tensor)."""
+        import torch
+        ncp = int(self.info()["n_control_points"])
+        g = torch.empty((max(ncp, 1), self.dim), dtype=torch.float64, device=u.device)
+        cp = None
+        ui = None
+        if u_inf is not None:
+            cp = torch.empty(max(ncp, 1), dtype=torch.float64, device=u.device)
+            ui = (ctypes.c_double * self.dim)(*[float(v) for v in u_inf])
+        _check(lib().iim_wall_gradient(self._h, _ptr(u), _ptr(g), ui, None if cp is None else _ptr(cp)))
+        return (g[:ncp], cp[:ncp]) if cp is not None else g[:ncp]
 
     def level_op(self, level: int, op: int, in1, out):
         _check(lib().iim_level_op(self._h, level, op, _ptr(in1), _ptr(out)))
