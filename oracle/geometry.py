@@ -24,19 +24,30 @@ import numpy as np
 from . import INACTIVE, PLUS, MINUS, BOX
 
 SIDE_INTERIOR, SIDE_EXTERIOR, SIDE_INTERFACE = 0, 1, 2
-GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION = 0, 1, 2
+GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION, GEOM_GYROID = 0, 1, 2, 3
 
 
 class Grid:
-    """Uniform vertex-centred grid on [-1, 1]^dim with n intervals per axis.
-    Coarse multigrid levels use the same origin and spacing h * 2^level."""
+    """Uniform vertex-centred grid on [lo, lo + n h]^dim with n intervals per
+    axis ([-1, 1] by default).  Coarse multigrid levels use the same origin
+    and spacing h * 2^level.
 
-    def __init__(self, dim: int, n: int, h: float = None, lo: float = -1.0):
+    periodic: the domain is periodic in every direction (Sec. 2.3: the
+    augmented system covers periodic problems); node n is then the image of
+    node 0 along each axis, stored but never an unknown, and every neighbour
+    index is taken modulo n (`wrap`)."""
+
+    def __init__(self, dim: int, n: int, h: float = None, lo: float = -1.0, periodic: bool = False):
         self.dim = dim
         self.n = n
         self.h = (2.0 / n) if h is None else h
         self.lo = lo
+        self.periodic = periodic
         self.shape = (n + 1,) * dim
+
+    def wrap(self, i):
+        """Index i taken into 0..n-1 (periodic grids); unchanged otherwise."""
+        return np.mod(i, self.n) if self.periodic else i
 
     def coord(self, i):
         return self.lo + np.asarray(i) * self.h
@@ -253,9 +264,102 @@ class SphereUnion:
         return 1.0 / self.spheres[which].r
 
 
+class Gyroid:
+    """phi = cos(k1 x) sin(k2 y) + cos(k2 y) sin(k3 z) + cos(k3 z) sin(k1 x) - alpha
+    (the paper's triply periodic heat-conduction domain, Sec. 4.4.1: the
+    solved region is phi > 0)."""
+
+    def __init__(self, k1, k2, k3, alpha):
+        self.k = (float(k1), float(k2), float(k3))
+        self.alpha = float(alpha)
+
+    def phi(self, X):
+        k1, k2, k3 = self.k
+        x, y, z = (np.asarray(v, dtype=np.float64) for v in X)
+        return (np.cos(k1 * x) * np.sin(k2 * y) + np.cos(k2 * y) * np.sin(k3 * z)
+                + np.cos(k3 * z) * np.sin(k1 * x) - self.alpha)
+
+    def sign(self, X):
+        return np.sign(self.phi(X))
+
+    def crossing(self, xa, axis, dir_, solved_inside=None, h: float = None):
+        """Bisection (64 halvings) on the segment between the two nodes, on the
+        sign of phi; a zero at an end point is the root."""
+        lo_pt = list(xa)
+        if dir_ < 0:
+            lo_pt[axis] = xa[axis] - h
+        hi_pt = list(lo_pt)
+        hi_pt[axis] = lo_pt[axis] + h
+        s_lo = np.sign(self.phi(lo_pt))
+        s_hi = np.sign(self.phi(hi_pt))
+        if s_lo == 0:
+            return lo_pt[axis], 0
+        if s_hi == 0:
+            return hi_pt[axis], 0
+        a, b = lo_pt[axis], hi_pt[axis]
+        p = list(lo_pt)
+        for _ in range(64):
+            m = 0.5 * (a + b)
+            p[axis] = m
+            sm = np.sign(self.phi(p))
+            if sm == 0:
+                return m, 0
+            if sm == s_lo:
+                a = m
+            else:
+                b = m
+        return 0.5 * (a + b), 0
+
+    def gradient(self, x):
+        k1, k2, k3 = self.k
+        cx, sx = math.cos(k1 * x[0]), math.sin(k1 * x[0])
+        cy, sy = math.cos(k2 * x[1]), math.sin(k2 * x[1])
+        cz, sz = math.cos(k3 * x[2]), math.sin(k3 * x[2])
+        return np.array([-k1 * sx * sy + k1 * cz * cx,
+                         k2 * cx * cy - k2 * sy * sz,
+                         k3 * cy * cz - k3 * sz * sx])
+
+    def hessian(self, x):
+        k1, k2, k3 = self.k
+        cx, sx = math.cos(k1 * x[0]), math.sin(k1 * x[0])
+        cy, sy = math.cos(k2 * x[1]), math.sin(k2 * x[1])
+        cz, sz = math.cos(k3 * x[2]), math.sin(k3 * x[2])
+        H = np.empty((3, 3))
+        H[0, 0] = -k1 * k1 * cx * sy - k1 * k1 * cz * sx
+        H[1, 1] = -k2 * k2 * cx * sy - k2 * k2 * cy * sz
+        H[2, 2] = -k3 * k3 * cy * sz - k3 * k3 * cz * sx
+        H[0, 1] = H[1, 0] = -k1 * k2 * sx * cy
+        H[1, 2] = H[2, 1] = -k2 * k3 * sy * cz
+        H[0, 2] = H[2, 0] = -k1 * k3 * sz * cx
+        return H
+
+    def grad_dir(self, x, which=0):
+        g = self.gradient(x)
+        return g / np.linalg.norm(g)
+
+    def curvature(self, x, which=0):
+        """Largest absolute principal curvature of the level surface: the
+        eigenvalues of the shape operator P H P / |grad phi| (P the tangent
+        projector) other than the zero along the normal, from its trace and
+        the sum of its principal 2x2 minors."""
+        g = self.gradient(x)
+        gn = np.linalg.norm(g)
+        nrm = g / gn
+        P = np.eye(3) - np.outer(nrm, nrm)
+        Sh = P @ self.hessian(x) @ P / gn
+        tr = np.trace(Sh)
+        m2 = Sh[0, 0] * Sh[1, 1] - Sh[0, 1] * Sh[1, 0] + Sh[0, 0] * Sh[2, 2] - Sh[0, 2] * Sh[2, 0] \
+            + Sh[1, 1] * Sh[2, 2] - Sh[1, 2] * Sh[2, 1]
+        half = 0.5 * tr
+        return abs(half) + math.sqrt(max(half * half - m2, 0.0))
+
+
 def make_geometry(kind: int, params, dim: int):
     """Geometry from the parameter list of the C ABI: sphere [c..., r];
-    star [cx, cy, r0, eps, lobes]; union [count, (c..., r) * count]."""
+    star [cx, cy, r0, eps, lobes]; union [count, (c..., r) * count];
+    gyroid [k1, k2, k3, alpha] (3D)."""
+    if kind == GEOM_GYROID:
+        return Gyroid(*params[:4])
     if kind == GEOM_SPHERE:
         g = Sphere(params[:-1], params[-1])
     elif kind == GEOM_STAR2D:
@@ -287,6 +391,22 @@ def node_labels(grid: Grid, geom, side: int) -> np.ndarray:
     problems and interfaces; Omega^- = {phi <= 0} for interfaces."""
     X = grid.node_coords()
     s = geom.sign(X)
+    if grid.periodic:
+        # no box faces; nodes of the image planes (index n) are not unknowns
+        image = np.zeros(grid.shape, dtype=bool)
+        for d in range(grid.dim):
+            idx = [slice(None)] * grid.dim
+            idx[d] = grid.n
+            image[tuple(idx)] = True
+        lab = np.zeros(grid.shape, dtype=np.uint8)
+        if side == SIDE_INTERIOR:
+            lab[(s < 0) & ~image] = PLUS
+        elif side == SIDE_EXTERIOR:
+            lab[(s > 0) & ~image] = PLUS
+        else:
+            lab[(s <= 0) & ~image] = MINUS
+            lab[(s > 0) & ~image] = PLUS
+        return lab
     face = np.zeros(grid.shape, dtype=bool)
     for d in range(grid.dim):
         idx = [slice(None)] * grid.dim
@@ -322,7 +442,7 @@ def is_crossing(la: int, lb: int, side: int) -> bool:
 
 
 class ControlPoint:
-    __slots__ = ("axis", "p", "q", "x", "n", "kappa", "a", "dir", "which")
+    __slots__ = ("axis", "p", "q", "x", "n", "kappa", "a", "dir", "which", "xa")
 
     def __repr__(self):
         return f"CP(axis={self.axis}, p={self.p}, x={self.x}, n={self.n})"
@@ -333,6 +453,8 @@ def control_points(grid: Grid, geom, side: int, labels: np.ndarray) -> List[Cont
     lower node of the segment.  For each control point and each side sigma of
     the problem, a[sigma] is the adjacent unknown of that side and dir[sigma]
     the step (+1/-1 along the axis) from it towards Gamma."""
+    if grid.periodic:
+        return _control_points_periodic(grid, geom, side, labels)
     out: List[ControlPoint] = []
     lab_flat = labels.ravel(order="F")
     dim = grid.dim
@@ -389,6 +511,69 @@ def control_points(grid: Grid, geom, side: int, labels: np.ndarray) -> List[Cont
                 cp.a[PLUS] = p if la == PLUS else q
             for sg, node in cp.a.items():
                 cp.dir[sg] = 1 if node == p else -1
+            out.append(cp)
+    return out
+
+
+def _control_points_periodic(grid: Grid, geom, side: int, labels: np.ndarray) -> List[ControlPoint]:
+    """Control points of a periodic grid: every segment from a node p with all
+    indices in 0..n-1 to its neighbour p + e_axis, taken modulo n (the last
+    segment of a line joins node n-1 to node 0 through the image node n).
+    The segment's coordinates are unwrapped: x_c lies between x_p and
+    x_p + h.  cp.xa[sigma] holds the unwrapped coordinates of the adjacent
+    unknown of side sigma (node q is then at x_p + h e_axis)."""
+    out: List[ControlPoint] = []
+    dim, n = grid.dim, grid.n
+    n1 = n + 1
+    strides = [n1 ** d for d in range(dim)]
+    core = labels[tuple(slice(0, n) for _ in range(dim))]
+    for axis in range(dim):
+        la_arr = core
+        lb_arr = np.roll(core, -1, axis=axis)
+        if side == SIDE_INTERFACE:
+            mask = ((la_arr == PLUS) & (lb_arr == MINUS)) | ((la_arr == MINUS) & (lb_arr == PLUS))
+        else:
+            mask = ((la_arr == PLUS) & (lb_arr == INACTIVE)) | ((la_arr == INACTIVE) & (lb_arr == PLUS))
+        idx = np.nonzero(mask)
+        flat_p = np.zeros(idx[0].shape, dtype=np.int64)
+        for d in reversed(range(dim)):
+            flat_p = flat_p * n1 + idx[d]
+        for p in np.sort(flat_p):
+            p = int(p)
+            ijk = list(grid.unflat(p))
+            qk = list(ijk)
+            qk[axis] = (qk[axis] + 1) % n
+            q = grid.flat(qk)
+            la, lb = labels[tuple(ijk)], labels[tuple(qk)]
+            cp = ControlPoint()
+            cp.axis, cp.p, cp.q = axis, p, q
+            xp = [float(grid.coord(v)) for v in ijk]
+            xq = list(xp)
+            xq[axis] = xp[axis] + grid.h       # unwrapped
+            if side == SIDE_INTERFACE:
+                from_p = la == MINUS
+                inside = True
+            else:
+                from_p = la == PLUS
+                inside = (side == SIDE_INTERIOR)
+            xa = xp if from_p else xq
+            dir_ = 1 if from_p else -1
+            root, which = geom.crossing(xa, axis, dir_, inside, grid.h)
+            root = min(max(root, xp[axis]), xq[axis])
+            x = list(xp)
+            x[axis] = root
+            cp.x = np.array(x)
+            cp.which = which
+            g = geom.grad_dir(cp.x, which)
+            cp.n = -g if side == SIDE_INTERIOR else g
+            cp.kappa = geom.curvature(cp.x, which)
+            cp.a, cp.dir, cp.xa = {}, {}, {}
+            sides = [PLUS, MINUS] if side == SIDE_INTERFACE else [PLUS]
+            for sg in sides:
+                at_p = la == sg
+                cp.a[sg] = p if at_p else q
+                cp.dir[sg] = 1 if at_p else -1
+                cp.xa[sg] = np.array(xp if at_p else xq)
             out.append(cp)
     return out
 

@@ -78,9 +78,11 @@ def lagrange_extrapolation(k: int, s: int) -> List[float]:
 class IIMProblem:
     def __init__(self, dim: int, n: int, geom_kind: int, geom_params, side: int, bc: int,
                  beta_plus: float = 1.0, beta_minus: float = 1.0, order_n: int = 4,
-                 order_k: int = 5, axes=None, check_kappa: bool = True):
+                 order_k: int = 5, axes=None, check_kappa: bool = True, lo: float = -1.0, hi: float = 1.0,
+                 periodic: bool = False):
         self.dim, self.n = dim, n
-        self.grid = Grid(dim, n)
+        self.periodic = periodic
+        self.grid = Grid(dim, n, (hi - lo) / n, lo, periodic)
         self.geom = make_geometry(geom_kind, list(geom_params), dim)
         self.geom_kind, self.geom_params = geom_kind, list(geom_params)
         self.side, self.bc = side, bc
@@ -254,8 +256,11 @@ class IIMProblem:
 
     # -- operator rows ---------------------------------------------------------
     def _step(self, f: int, d: int, s: int):
-        """Flat index of f + s e_d, or None outside the grid."""
+        """Flat index of f + s e_d, or None outside the grid (taken modulo n
+        on a periodic grid)."""
         i = (f // self.strides[d]) % (self.n + 1)
+        if self.periodic:
+            return f + (((i + s) % self.n) - i) * self.strides[d]
         if not 0 <= i + s <= self.n:
             return None
         return f + s * self.strides[d]
@@ -280,7 +285,8 @@ class IIMProblem:
                     state, face, jf = "box", q, j
                     data[self.ncp_data + q] += wj
                 else:
-                    key = (d, min(prev, q))
+                    # the segment's lower node: the one whose +e_d neighbour is the other
+                    key = (d, prev if dr > 0 else q)
                     c = self.seg[key]
                     assert self.cps[c].a[side] == prev
                     state, j0 = "ghost", j
@@ -364,6 +370,16 @@ class IIMProblem:
         """Unknowns whose whole stencil stays on their own side (flat mask)."""
         w = self.w
         lab = self.labels
+        if self.periodic:
+            n = self.n
+            core = lab[tuple(slice(0, n) for _ in range(self.dim))]
+            ok = (core == PLUS) | (core == MINUS)
+            for d in range(self.dim):
+                for s in list(range(-w, 0)) + list(range(1, w + 1)):
+                    ok &= np.roll(core, -s, axis=d) == core
+            full = np.zeros(lab.shape, dtype=bool)
+            full[tuple(slice(0, n) for _ in range(self.dim))] = ok
+            return full.ravel(order="F")
         pad = np.pad(lab, w, constant_values=255)
         ok = (lab == PLUS) | (lab == MINUS)
         core = tuple(slice(w, w + s) for s in lab.shape)
@@ -387,7 +403,11 @@ class IIMProblem:
         for d in range(self.dim):
             for j in range(1, self.w + 1):
                 for s in (j, -j):
-                    nb = reg_nodes + s * self.strides[d]
+                    if self.periodic:
+                        i = (reg_nodes // self.strides[d]) % (self.n + 1)
+                        nb = reg_nodes + (np.mod(i + s, self.n) - i) * self.strides[d]
+                    else:
+                        nb = reg_nodes + s * self.strides[d]
                     rows.append(ri); cols.append(self.uindex[nb]); vals.append(beta_node * self.a[j] / h2)
         for f in np.nonzero(~reg & (self.uindex >= 0))[0]:
             coef, data = self.row(int(f))

@@ -73,6 +73,45 @@ def vandermonde(xi: np.ndarray, exps) -> np.ndarray:
     return A
 
 
+def candidate_set_periodic(grid, labels_flat: np.ndarray, xc: np.ndarray, nu: np.ndarray,
+                           side: int, a: float, b: float):
+    """The candidate set on a periodic grid: nodes are taken at their
+    unwrapped positions around x_c (their labels and flat indices modulo n).
+    Returns (flat indices, unwrapped coordinates), ordered by the unwrapped
+    indices (z slowest), the closest point to x_c removed (ties: the first in
+    that order)."""
+    dim, h, n = grid.dim, grid.h, grid.n
+    R = int(math.ceil(max(a, b))) + 1
+    centre = [int(round((xc[d] - grid.lo) / h)) for d in range(dim)]
+    axes_idx = [np.arange(centre[d] - R, centre[d] + R + 1) for d in range(dim)]
+    mesh = np.meshgrid(*axes_idx, indexing="ij")
+    idx = [m.ravel() for m in mesh]
+    flat = np.zeros(idx[0].shape, dtype=np.int64)
+    key = np.zeros(idx[0].shape, dtype=np.int64)
+    span = 2 * R + 1
+    for d in reversed(range(dim)):
+        flat = flat * (n + 1) + np.mod(idx[d], n)
+        key = key * span + (idx[d] - centre[d] + R)
+    on_side = labels_flat[flat] == side
+    flat, key = flat[on_side], key[on_side]
+    idx = [v[on_side] for v in idx]
+    pos = np.stack([grid.lo + idx[d] * h for d in range(dim)], axis=1)
+    delta = (pos - xc[None, :]) / h
+    nn = delta @ nu
+    r2 = np.einsum("ij,ij->i", delta, delta)
+    t2 = np.maximum(r2 - nn * nn, 0.0)
+    keep = (nn >= -SET_TOL) & (t2 / (a * a) + nn * nn / (b * b) <= 1.0 + SET_TOL)
+    flat, key, r2, pos = flat[keep], key[keep], r2[keep], pos[keep]
+    if flat.size == 0:
+        return [], np.zeros((0, dim))
+    order = np.argsort(key)
+    flat, key, r2, pos = flat[order], key[order], r2[order], pos[order]
+    dmin = r2.min()
+    closest = np.nonzero(r2 <= dmin + SET_TOL)[0].min()
+    keep2 = np.arange(flat.size) != closest
+    return [int(f) for f in flat[keep2]], pos[keep2]
+
+
 def candidate_set(grid, labels_flat: np.ndarray, xc: np.ndarray, nu: np.ndarray,
                   side: int, a: float, b: float) -> List[int]:
     """Flat indices of the side's unknowns in the half-ellipse, in increasing
@@ -161,11 +200,17 @@ def ls_stencil(grid, labels_flat, cp, side: int, order_k: int, w: int, with_deri
     a, b = axes
     a_node = cp.a[side]
     step = cp.dir[side]
-    xa = np.array([grid.lo + i * h for i in grid.unflat(a_node)])
+    if getattr(grid, "periodic", False):
+        xa = np.array(cp.xa[side])
+    else:
+        xa = np.array([grid.lo + i * h for i in grid.unflat(a_node)])
     for grow in range(MAX_GROW + 1):
-        idx = candidate_set(grid, labels_flat, cp.x, nu, side, a, b)
-        if len(idx) + 1 >= len(exps):
+        if getattr(grid, "periodic", False):
+            idx, pts = candidate_set_periodic(grid, labels_flat, cp.x, nu, side, a, b)
+        else:
+            idx = candidate_set(grid, labels_flat, cp.x, nu, side, a, b)
             pts = np.array([[grid.lo + i * h for i in grid.unflat(f)] for f in idx])
+        if len(idx) + 1 >= len(exps):
             scale = a * h
             rows = []
             for j in range(1, w + 1):

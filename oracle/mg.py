@@ -19,7 +19,8 @@ the W-cycle, which visits each coarser level twice per visit of the level above
 first one left.  gamma = 1 is the V-cycle.
 
 Readings: vertex-centred coarsening (coarse node I = fine node 2I, ceil(n/2)
-intervals); half-weighting stencils 1/8 [0 1 0; 1 4 1; 0 1 0] in 2D and centre
+intervals; on a periodic grid n stays even down to the coarsest level and the
+transfers take indices modulo n); half-weighting stencils 1/8 [0 1 0; 1 4 1; 0 1 0] in 2D and centre
 1/2, faces 1/12 in 3D; red (even index sum) before black; V(2,2); box-face nodes
 hold zero and count as in-domain for the averaging interpolation; the coarse
 solve excludes rows with a zero diagonal (their value stays zero).  For a
@@ -54,6 +55,15 @@ from .geometry import Grid, SIDE_INTERFACE, SIDE_INTERIOR
 from .sw import SWLevel, BC_DIRICHLET, BC_NEUMANN, BC_JUMP
 
 
+def is_singular_setup(prob) -> bool:
+    """No Dirichlet value anywhere pins the constant: an interior domain with
+    a Neumann boundary, or a periodic domain whose immersed condition is not
+    Dirichlet (Neumann, or jumps)."""
+    if getattr(prob.grid, "periodic", False):
+        return prob.bc != BC_DIRICHLET
+    return prob.side == SIDE_INTERIOR and prob.bc == BC_NEUMANN
+
+
 def level_sizes(n: int, coarsest: int = 8) -> List[int]:
     out = [n]
     while out[-1] > coarsest:
@@ -76,7 +86,7 @@ class Hierarchy:
         self.sizes = level_sizes(prob.n, coarsest)
         self.levels: List[SWLevel] = []
         for l, nl in enumerate(self.sizes):
-            g = Grid(prob.dim, nl, prob.grid.h * 2 ** l)
+            g = Grid(prob.dim, nl, prob.grid.h * 2 ** l, prob.grid.lo, prob.grid.periodic)
             self.levels.append(SWLevel(g, prob.geom, prob.side, prob.bc,
                                        prob.beta[PLUS], prob.beta[MINUS], shift=shift))
         if prob.side == SIDE_INTERFACE or prob.bc == BC_DIRICHLET:
@@ -92,7 +102,7 @@ class Hierarchy:
         lc = self.levels[-1]
         self.coarse_rows = np.nonzero(lc.diag != 0.0)[0]
         Ad = lc.A.toarray()[np.ix_(self.coarse_rows, self.coarse_rows)]
-        self.bordered = prob.side == SIDE_INTERIOR and prob.bc == BC_NEUMANN
+        self.bordered = is_singular_setup(prob)
         if self.bordered and Ad.size:
             nc = Ad.shape[0]
             Ab = np.zeros((nc + 1, nc + 1))
@@ -132,7 +142,7 @@ class Hierarchy:
         for d in range(dim):
             for s in (-1, 1):
                 G = list(F)
-                G[d] = G[d] + s
+                G[d] = fine.grid.wrap(G[d] + s)   # modulo n on a periodic grid
                 out = out + w1 * rf[tuple(G)]
         return out
 
@@ -157,7 +167,7 @@ class Hierarchy:
                 if bits[d]:
                     use &= odd[d]
                 P.append(lo[d] + bits[d])
-            P = tuple(np.where(use, P[d], lo[d]) for d in range(self.dim))
+            P = tuple(coarse.grid.wrap(np.where(use, P[d], lo[d])) for d in range(self.dim))
             if self.mode == "average":
                 lab = lab_c[P]
                 use &= (lab == PLUS) | (lab == MINUS) | (lab == BOX)

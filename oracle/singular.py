@@ -15,8 +15,9 @@ the exact and the numerical solution.
 
 Readings:
   * A problem is singular when its domain is the interior of the immersed body
-    and the body carries a Neumann condition: interior domains never reach the
-    box faces, so no Dirichlet value pins the constant.
+    and the body carries a Neumann condition (interior domains never reach the
+    box faces), or when the box is periodic and the immersed condition is a
+    Neumann or jump condition: no Dirichlet value pins the constant.
   * gamma = 0: the unknowns sum to zero.
   * Preconditioner of the bordered system: one multigrid cycle on the first
     block, the identity on alpha; the cycle's coarsest SW matrix, singular in
@@ -35,12 +36,15 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .geometry import SIDE_INTERIOR
-from .iim import BC_NEUMANN
+from .iim import BC_NEUMANN, BC_DIRICHLET
 from .krylov import fgmres
 
 
 def is_singular(prob) -> bool:
-    """Interior domain with a Neumann condition on its whole boundary."""
+    """Interior domain with a Neumann condition on its whole boundary, or a
+    periodic domain whose immersed condition is not Dirichlet."""
+    if getattr(prob, "periodic", False):
+        return prob.bc != BC_DIRICHLET
     return prob.side == SIDE_INTERIOR and prob.bc == BC_NEUMANN
 
 

@@ -22,7 +22,8 @@ dn u ~ sign(n_i) d_i u (homogeneous inside the preconditioner).
 Intersection shifting: boundary walls psi <- max(psi, 1/2); interfaces
 psi^+ = psi^- = 1/2.  The operator here is the plain Laplacian: the
 interface preconditioner solves Lap u = f / beta on each side (Sec. 3.3).
-Box-face nodes are regular neighbours holding their (zero) value.
+Box-face nodes are regular neighbours holding their (zero) value.  On a
+periodic grid neighbours are taken modulo n.
 
 Parity: the 1D rows are pinned by exactness on {1, x, x^2}; the unshifted
 Dirichlet discretisation by its second-order convergence; the shifted operator
@@ -94,6 +95,8 @@ class SWLevel:
 
     def _neighbour(self, f: int, d: int, s: int):
         i = (f // self.strides[d]) % (self.grid.n + 1)
+        if getattr(self.grid, "periodic", False):
+            return f + (((i + s) % self.grid.n) - i) * self.strides[d]
         if not 0 <= i + s <= self.grid.n:
             return None
         return f + s * self.strides[d]
@@ -127,6 +130,16 @@ class SWLevel:
     def _regular_mask(self) -> np.ndarray:
         """Unknowns whose 2d neighbours are all unknowns of the same side."""
         lab = self.labels
+        if getattr(self.grid, "periodic", False):
+            n, dim = self.grid.n, self.grid.dim
+            core = lab[tuple(slice(0, n) for _ in range(dim))]
+            ok = (core == PLUS) | (core == MINUS)
+            for d in range(dim):
+                for s in (-1, 1):
+                    ok &= np.roll(core, -s, axis=d) == core
+            full = np.zeros(lab.shape, dtype=bool)
+            full[tuple(slice(0, n) for _ in range(dim))] = ok
+            return full.ravel(order="F")
         pad = np.pad(lab, 1, constant_values=255)
         ok = (lab == PLUS) | (lab == MINUS)
         core = tuple(slice(1, 1 + s) for s in lab.shape)
@@ -147,7 +160,12 @@ class SWLevel:
         rows.append(ri); cols.append(ri); vals.append(np.full(rn.size, -2.0 * dim / h2))
         for d in range(dim):
             for s in (-1, 1):
-                rows.append(ri); cols.append(self.uindex[rn + s * self.strides[d]])
+                if getattr(self.grid, "periodic", False):
+                    i = (rn // self.strides[d]) % (self.grid.n + 1)
+                    nb = rn + (np.mod(i + s, self.grid.n) - i) * self.strides[d]
+                else:
+                    nb = rn + s * self.strides[d]
+                rows.append(ri); cols.append(self.uindex[nb])
                 vals.append(np.full(rn.size, 1.0 / h2))
         r_l, c_l, v_l = [], [], []
         for f in np.nonzero(~reg & (self.uindex >= 0))[0]:

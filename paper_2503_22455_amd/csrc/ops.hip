@@ -2157,17 +2157,21 @@ template void run_cast_out<__half>(const LevelDev&, const __half*, const double*
 
 namespace iim {
 
-// Neumann apply weights: W_j = S_j - (Sc_j / Sc_n) S_n, data coefficient Sc_j / (beta Sc_n)
-__global__ void k_combine_neumann(const int64_t* ptr, int64_t ncs, int w, int nrows, const double* S, const double* Sc,
-                                  double beta, int64_t nnz, double* W, double* dcoef) {
-    int64_t cs = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Neumann apply weights: W_j = S_j - (Sc_j / Sc_n) S_n, data coefficient Sc_j / (beta Sc_n).
+// One wave per control-point side, lanes over its entries (contiguous in every row).
+__global__ void __launch_bounds__(256) k_combine_neumann(const int64_t* ptr, int64_t ncs, int w, int nrows,
+                                                         const double* S, const double* Sc, double beta, int64_t nnz,
+                                                         double* W, double* dcoef) {
+    const int lane = threadIdx.x % 64;
+    const int64_t cs = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / 64;
     if (cs >= ncs) return;
     const double scn = Sc[cs * nrows + w];
+    const int64_t a0 = ptr[cs], a1 = ptr[cs + 1];
     for (int j = 0; j < w; ++j) {
         const double scj = Sc[cs * nrows + j];
         const double f = scj / scn;
-        for (int64_t a = ptr[cs]; a < ptr[cs + 1]; ++a) W[j * nnz + a] = S[j * nnz + a] - f * S[w * nnz + a];
-        dcoef[cs * w + j] = scj / (beta * scn);
+        for (int64_t a = a0 + lane; a < a1; a += 64) W[j * nnz + a] = S[j * nnz + a] - f * S[w * nnz + a];
+        if (lane == 0) dcoef[cs * w + j] = scj / (beta * scn);
     }
 }
 
@@ -2181,8 +2185,8 @@ void run_apply_weights(int bc, const int64_t* ptr, int64_t ncs, int w, int nrows
                        double beta, int64_t nnz, double* W, double* dcoef, hipStream_t s) {
     if (ncs == 0) return;
     if (bc == IIM_BC_NEUMANN)
-        hipLaunchKernelGGL(k_combine_neumann, dim3(cdiv(ncs, 128)), dim3(128), 0, s, ptr, ncs, w, nrows, S, Sc, beta,
-                           nnz, W, dcoef);
+        hipLaunchKernelGGL(k_combine_neumann, dim3(cdiv(ncs * 64, 256)), dim3(256), 0, s, ptr, ncs, w, nrows, S, Sc,
+                           beta, nnz, W, dcoef);
     else
         hipLaunchKernelGGL(k_copy_dcoef, dim3(cdiv(ncs, 128)), dim3(128), 0, s, ncs, w, nrows, Sc, dcoef);
     IIM_LAUNCH_CHECK();

@@ -7,7 +7,8 @@ from oracle.iim import IIMProblem
 
 
 def oracle_for(wl, **kw):
-    return IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus, **kw)
+    return IIMProblem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus,
+                      lo=wl.lo, hi=wl.hi, periodic=wl.periodic, **kw)
 
 
 def gpu_for(wl, **kw):

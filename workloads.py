@@ -24,7 +24,7 @@ import numpy as np
 
 # geometry kinds, problem sides and boundary-condition kinds; the integer values
 # are the ones the C ABI uses (include/iim.h)
-GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION = 0, 1, 2
+GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION, GEOM_GYROID = 0, 1, 2, 3
 SIDE_INTERIOR, SIDE_EXTERIOR, SIDE_INTERFACE = 0, 1, 2
 BC_DIRICHLET, BC_NEUMANN, BC_JUMP = 0, 1, 2
 
@@ -57,6 +57,10 @@ class Workload:
     order: Tuple[int, int] = (4, 5)  # (n, k): the (4,5) scheme, or (6,7) in 2D
     orthogonalisation: int = 1       # solver's Arnoldi step: 1 CGS + second pass where needed, 0 CGS2
     cycle: str = "V"                 # preconditioner's multigrid cycle: V or W
+    lo: float = -1.0                 # domain [lo, hi]^dim
+    hi: float = 1.0
+    periodic: bool = False           # periodic in every direction (node n is node 0's image)
+    source: Optional[Callable] = None  # f(x...) overriding beta Lap(u) (problems without a closed-form u)
 
     # -- data sampling (pure evaluation of the manufactured solution) ----------
     def cp_data(self, xyz: np.ndarray, normal: np.ndarray) -> np.ndarray:
@@ -80,8 +84,8 @@ class Workload:
 
     def node_coords(self) -> List[np.ndarray]:
         """Full-grid node coordinates, arrays of shape (n+1,)*dim indexed [ix,iy(,iz)]."""
-        h = 2.0 / self.n
-        x1 = -1.0 + np.arange(self.n + 1) * h
+        h = (self.hi - self.lo) / self.n
+        x1 = self.lo + np.arange(self.n + 1) * h
         return list(np.meshgrid(*([x1] * self.dim), indexing="ij"))
 
     def box_data(self) -> np.ndarray:
@@ -95,6 +99,10 @@ class Workload:
         X = self.node_coords()
         ex = self.exact
         f = np.zeros(labels.shape)
+        if self.source is not None:
+            fs = self.source(*X) * np.ones_like(X[0])
+            f[(labels == 1) | (labels == 2)] = fs[(labels == 1) | (labels == 2)]
+            return f
         fp = self.beta_plus * ex.lap_plus(*X) * np.ones_like(X[0])
         f[labels == 1] = fp[labels == 1]
         if ex.lap_minus is not None:
@@ -221,6 +229,79 @@ def potential_body(dim: int, n: int, precision: str = "fp64", center=(0.02, -0.0
     potential-flow application, on a body whose answer is known in closed form)."""
     return Workload("potential_body", dim, n, GEOM_SPHERE, list(center)[:dim] + [radius], SIDE_EXTERIOR,
                     BC_NEUMANN, exact=ms_body_flow(dim, center, radius), precision=precision)
+
+
+def ms_periodic(dim: int, phase=(0.3, -0.7, 0.45)) -> Manufactured:
+    """A periodic solution of the unit box: u = prod_d sin(2 pi x_d + phase_d)
+    (its mean over a period is zero)."""
+    ph = [float(v) for v in phase][:dim]
+
+    def u(*X):
+        out = 1.0
+        for d in range(dim):
+            out = out * np.sin(TWO_PI * X[d] + ph[d])
+        return out
+
+    def g(*X):
+        comps = []
+        for k in range(dim):
+            t = TWO_PI * np.cos(TWO_PI * X[k] + ph[k])
+            for d in range(dim):
+                if d != k:
+                    t = t * np.sin(TWO_PI * X[d] + ph[d])
+            comps.append(t)
+        return tuple(comps)
+
+    return Manufactured(u, g, lambda *X: -dim * TWO_PI ** 2 * u(*X))
+
+
+GYROID_K = 8.0 * math.pi
+GYROID_ALPHA = -0.5 + 1e-9
+
+
+def gyroid_params(k: float = GYROID_K, alpha: float = GYROID_ALPHA) -> List[float]:
+    """phi = cos(k x) sin(k y) + cos(k y) sin(k z) + cos(k z) sin(k x) - alpha.
+    The paper uses alpha = -0.5; at that value some 384^3 nodes lie on Gamma in
+    exact arithmetic (x = z = 0, y = -1/48: sin(-pi/6) = -1/2), where the
+    rounding of two independent sin/cos implementations would decide the
+    label; alpha is moved by 1e-9 (Gamma moves by about 4e-11 h)."""
+    return [k, k, k, alpha]
+
+
+def compact_bump(center, gamma: float = 1.0 / 40.0, sigma: float = 1.0 / 80.0, amp: float = 1.0,
+                 period: float = 1.0) -> Callable:
+    """The paper's compact isotropic source profile (Sec. 4.4.1):
+    f(r) = amp exp(-(r/sigma)^2 / (1 - (r/gamma)^2)) for r < gamma, 0 beyond;
+    r measured to the nearest periodic image of the centre."""
+    c = [float(v) for v in center]
+
+    def f(*X):
+        r2 = 0.0
+        for d in range(len(c)):
+            t = X[d] - c[d]
+            t = t - period * np.round(t / period)
+            r2 = r2 + t * t
+        q = r2 / (gamma * gamma)
+        with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+            val = amp * np.exp(-(r2 / (sigma * sigma)) / (1.0 - q))
+        return np.where(q < 1.0, val, 0.0)
+
+    return f
+
+
+def gyroid_heat(n: int = 384, precision: str = "mixed32") -> Workload:
+    """The paper's heat conduction in a triply periodic gyroid (Sec. 4.4.1):
+    unit periodic cube, domain phi > 0, homogeneous Neumann (zero flux) on the
+    gyroid, Lap u = -q with q two compact bumps of amplitude +-1e5 at
+    x+ = (23, 19, 21)/32 and x- = (3, 7, 9)/32 (support 1/40, sigma 1/80).
+    In the ABI's convention div(beta grad u) = f, so f = -q."""
+    qp = compact_bump((23 / 32, 19 / 32, 21 / 32), amp=1e5)
+    qm = compact_bump((3 / 32, 7 / 32, 9 / 32), amp=-1e5)
+    zero = Manufactured(lambda *X: 0.0 * X[0], lambda *X: tuple(0.0 * X[0] for _ in range(3)),
+                        lambda *X: 0.0 * X[0])
+    return Workload("gyroid_heat", 3, n, GEOM_GYROID, gyroid_params(), SIDE_EXTERIOR, BC_NEUMANN,
+                    exact=zero, precision=precision, lo=0.0, hi=1.0, periodic=True,
+                    source=lambda *X: -(qp(*X) + qm(*X)))
 
 
 def ms_paper_interface(dim: int = 2) -> Manufactured:
