@@ -61,6 +61,9 @@ extern "C" {
 #define IIM_GEOM_SPHERE 0       /* circle / sphere [c_1..c_dim, r]                 */
 #define IIM_GEOM_STAR2D 1       /* star r(t)=r0+eps cos(L t) [cx, cy, r0, eps, L]   */
 #define IIM_GEOM_SPHERE_UNION 2 /* union [count, (c_1..c_dim, r) x count]          */
+#define IIM_GEOM_GYROID 3       /* 3D: phi = cos(k1 x) sin(k2 y) + cos(k2 y) sin(k3 z)
+                                   + cos(k3 z) sin(k1 x) - alpha  [k1, k2, k3, alpha]
+                                   (Sec. 4.4.1; the body is phi < 0)              */
 
 /* which side is solved */
 #define IIM_SIDE_INTERIOR 0  /* Omega^+ = {phi < 0}                          */
@@ -86,6 +89,12 @@ typedef struct iim_grid {
     int32_t n;    /* intervals per axis, >= 8 */
     double lo;    /* domain [lo, hi]^dim */
     double hi;
+    int32_t periodic; /* 1: periodic in every direction (Sec. 2.3, 4.4.1): no box faces; node n
+                         of a full-grid array is the image of node 0 and never an unknown (NaN in
+                         u).  n must halve exactly down to the coarsest level, n >= 32; the
+                         (4,5) scheme; no gradient post-processing.  A periodic problem whose
+                         immersed condition is Neumann or a jump is singular (bordered). */
+    int32_t reserved;
 } iim_grid;
 
 typedef struct iim_geometry {

@@ -264,20 +264,61 @@ class SphereUnion:
         return 1.0 / self.spheres[which].r
 
 
+# sin and cos for the gyroid from IEEE basic operations only (Cody-Waite
+# reduction by pi/2 split into three parts, then the Taylor series of sin and
+# cos on |r| <= pi/4 to degree 19 / 18, Horner form): the library evaluates
+# the same steps, so both sides round every node's phi identically and their
+# labels and bisection roots agree bit for bit (two libm implementations differ
+# in the last bit, which decides the sign of phi at nodes within rounding of
+# Gamma and grazing roots to about 1e-12).
+_TWO_OVER_PI = 0.6366197723675814
+_PIO2 = (1.570796325802803, 9.920935791635221e-10, 5.170182981794105e-19)
+_SIN_C = (-0.16666666666666666, 0.008333333333333333, -0.0001984126984126984, 2.7557319223985893e-06,
+          -2.505210838544172e-08, 1.6059043836821613e-10, -7.647163731819816e-13, 2.8114572543455206e-15,
+          -8.22063524662433e-18)
+_COS_C = (-0.5, 0.041666666666666664, -0.001388888888888889, 2.48015873015873e-05, -2.755731922398589e-07,
+          2.08767569878681e-09, -1.1470745597729725e-11, 4.779477332387385e-14, -1.5619206968586225e-16)
+
+
+def det_sincos(t):
+    """(sin t, cos t) for float or float64 arrays, by the steps above."""
+    t = np.asarray(t, dtype=np.float64)
+    q = np.floor(t * _TWO_OVER_PI + 0.5)
+    r = ((t - q * _PIO2[0]) - q * _PIO2[1]) - q * _PIO2[2]
+    z = r * r
+    ps = _SIN_C[-1]
+    for c in reversed(_SIN_C[:-1]):
+        ps = c + z * ps
+    sn = r + r * (z * ps)
+    pc = _COS_C[-1]
+    for c in reversed(_COS_C[:-1]):
+        pc = c + z * pc
+    cs = 1.0 + z * pc
+    m = np.mod(q, 4.0)
+    sin_t = np.where(m == 0, sn, np.where(m == 1, cs, np.where(m == 2, -sn, -cs)))
+    cos_t = np.where(m == 0, cs, np.where(m == 1, -sn, np.where(m == 2, -cs, sn)))
+    return sin_t, cos_t
+
+
 class Gyroid:
     """phi = cos(k1 x) sin(k2 y) + cos(k2 y) sin(k3 z) + cos(k3 z) sin(k1 x) - alpha
     (the paper's triply periodic heat-conduction domain, Sec. 4.4.1: the
-    solved region is phi > 0)."""
+    solved region is phi > 0), summed left to right, sin and cos by det_sincos."""
 
     def __init__(self, k1, k2, k3, alpha):
         self.k = (float(k1), float(k2), float(k3))
         self.alpha = float(alpha)
 
-    def phi(self, X):
+    def _trig(self, x):
         k1, k2, k3 = self.k
-        x, y, z = (np.asarray(v, dtype=np.float64) for v in X)
-        return (np.cos(k1 * x) * np.sin(k2 * y) + np.cos(k2 * y) * np.sin(k3 * z)
-                + np.cos(k3 * z) * np.sin(k1 * x) - self.alpha)
+        sx, cx = det_sincos(k1 * np.asarray(x[0], dtype=np.float64))
+        sy, cy = det_sincos(k2 * np.asarray(x[1], dtype=np.float64))
+        sz, cz = det_sincos(k3 * np.asarray(x[2], dtype=np.float64))
+        return sx, cx, sy, cy, sz, cz
+
+    def phi(self, X):
+        sx, cx, sy, cy, sz, cz = self._trig(X)
+        return ((cx * sy + cy * sz) + cz * sx) - self.alpha
 
     def sign(self, X):
         return np.sign(self.phi(X))
@@ -312,18 +353,14 @@ class Gyroid:
 
     def gradient(self, x):
         k1, k2, k3 = self.k
-        cx, sx = math.cos(k1 * x[0]), math.sin(k1 * x[0])
-        cy, sy = math.cos(k2 * x[1]), math.sin(k2 * x[1])
-        cz, sz = math.cos(k3 * x[2]), math.sin(k3 * x[2])
+        sx, cx, sy, cy, sz, cz = (float(v) for v in self._trig(x))
         return np.array([-k1 * sx * sy + k1 * cz * cx,
                          k2 * cx * cy - k2 * sy * sz,
                          k3 * cy * cz - k3 * sz * sx])
 
     def hessian(self, x):
         k1, k2, k3 = self.k
-        cx, sx = math.cos(k1 * x[0]), math.sin(k1 * x[0])
-        cy, sy = math.cos(k2 * x[1]), math.sin(k2 * x[1])
-        cz, sz = math.cos(k3 * x[2]), math.sin(k3 * x[2])
+        sx, cx, sy, cy, sz, cz = (float(v) for v in self._trig(x))
         H = np.empty((3, 3))
         H[0, 0] = -k1 * k1 * cx * sy - k1 * k1 * cz * sx
         H[1, 1] = -k2 * k2 * cx * sy - k2 * k2 * cy * sz

@@ -75,7 +75,14 @@ struct Geom {
     int n;          // intervals of this level
     double lo, h;   // node i at lo + i * h
     const double* p;  // device copy of the parameters
+    int periodic;   // 1: periodic in every direction (node n is node 0's image, not stored)
 };
+
+// index i taken into 0..n-1
+__host__ __device__ inline int wrap_index(int i, int n) {
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
 
 __device__ inline double node_coord(const Geom& g, int i) {
 #pragma clang fp contract(off)
@@ -133,9 +140,120 @@ __device__ inline double star_phi(const double* p, double x, double y) {
 
 __device__ inline int sgn(double v) { return v < 0.0 ? -1 : (v > 0.0 ? 1 : 0); }
 
+// sin t and cos t from IEEE basic operations only, so that every
+// implementation of these steps rounds them identically: Cody-Waite reduction
+// r = t - q pi/2 (pi/2 split into three parts, q the nearest integer of
+// t 2/pi), then the Taylor series of sin and cos on |r| <= pi/4 to degree 19
+// and 18 in Horner form, and the quadrant q mod 4.  Accurate to about 2 ulp.
+__device__ inline void det_sincos(double t, double* sn, double* cs) {
+#pragma clang fp contract(off)
+    const double q = floor(t * 0.6366197723675814 + 0.5);
+    const double r = ((t - q * 1.570796325802803) - q * 9.920935791635221e-10) - q * 5.170182981794105e-19;
+    const double z = r * r;
+    double ps = -8.22063524662433e-18;
+    ps = 2.8114572543455206e-15 + z * ps;
+    ps = -7.647163731819816e-13 + z * ps;
+    ps = 1.6059043836821613e-10 + z * ps;
+    ps = -2.505210838544172e-08 + z * ps;
+    ps = 2.7557319223985893e-06 + z * ps;
+    ps = -0.0001984126984126984 + z * ps;
+    ps = 0.008333333333333333 + z * ps;
+    ps = -0.16666666666666666 + z * ps;
+    const double s0 = r + r * (z * ps);
+    double pc = -1.5619206968586225e-16;
+    pc = 4.779477332387385e-14 + z * pc;
+    pc = -1.1470745597729725e-11 + z * pc;
+    pc = 2.08767569878681e-09 + z * pc;
+    pc = -2.755731922398589e-07 + z * pc;
+    pc = 2.48015873015873e-05 + z * pc;
+    pc = -0.001388888888888889 + z * pc;
+    pc = 0.041666666666666664 + z * pc;
+    pc = -0.5 + z * pc;
+    const double c0 = 1.0 + z * pc;
+    double m = fmod(q, 4.0);
+    if (m < 0.0) m += 4.0;
+    if (m == 0.0) {
+        *sn = s0;
+        *cs = c0;
+    } else if (m == 1.0) {
+        *sn = c0;
+        *cs = -s0;
+    } else if (m == 2.0) {
+        *sn = -s0;
+        *cs = -c0;
+    } else {
+        *sn = -c0;
+        *cs = s0;
+    }
+}
+
+// gyroid: phi = cos(k1 x) sin(k2 y) + cos(k2 y) sin(k3 z) + cos(k3 z) sin(k1 x) - alpha,
+// p = [k1, k2, k3, alpha]; the solved region is phi > 0 (exterior side).  Summed
+// left to right, sin and cos by det_sincos.
+__device__ inline double gyroid_phi(const double* p, const double* x) {
+#pragma clang fp contract(off)
+    double sx, cx, sy, cy, sz, cz;
+    det_sincos(p[0] * x[0], &sx, &cx);
+    det_sincos(p[1] * x[1], &sy, &cy);
+    det_sincos(p[2] * x[2], &sz, &cz);
+    return ((cx * sy + cy * sz) + cz * sx) - p[3];
+}
+
+__device__ inline void gyroid_grad(const double* p, const double* x, double* g) {
+    double sx, cx, sy, cy, sz, cz;
+    det_sincos(p[0] * x[0], &sx, &cx);
+    det_sincos(p[1] * x[1], &sy, &cy);
+    det_sincos(p[2] * x[2], &sz, &cz);
+    g[0] = -p[0] * sx * sy + p[0] * cz * cx;
+    g[1] = p[1] * cx * cy - p[1] * sy * sz;
+    g[2] = p[2] * cy * cz - p[2] * sz * sx;
+}
+
+// largest absolute principal curvature of the gyroid's level surface at x:
+// the non-normal eigenvalues of P Hess P / |grad| (P the tangent projector),
+// from the trace and the sum of the principal 2 x 2 minors
+__device__ inline double gyroid_curvature(const double* p, const double* x) {
+    double sx, cx, sy, cy, sz, cz;
+    det_sincos(p[0] * x[0], &sx, &cx);
+    det_sincos(p[1] * x[1], &sy, &cy);
+    det_sincos(p[2] * x[2], &sz, &cz);
+    double g[3];
+    gyroid_grad(p, x, g);
+    double H[3][3];
+    H[0][0] = -p[0] * p[0] * cx * sy - p[0] * p[0] * cz * sx;
+    H[1][1] = -p[1] * p[1] * cx * sy - p[1] * p[1] * cy * sz;
+    H[2][2] = -p[2] * p[2] * cy * sz - p[2] * p[2] * cz * sx;
+    H[0][1] = H[1][0] = -p[0] * p[1] * sx * cy;
+    H[1][2] = H[2][1] = -p[1] * p[2] * sy * cz;
+    H[0][2] = H[2][0] = -p[0] * p[2] * sz * cx;
+    const double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double nv[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+    double P[3][3], T[3][3], Sh[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) P[a][b] = (a == b ? 1.0 : 0.0) - nv[a] * nv[b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int c = 0; c < 3; ++c) t += P[a][c] * H[c][b];
+            T[a][b] = t;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (int c = 0; c < 3; ++c) t += T[a][c] * P[c][b];
+            Sh[a][b] = t / gn;
+        }
+    const double tr = Sh[0][0] + Sh[1][1] + Sh[2][2];
+    const double m2 = Sh[0][0] * Sh[1][1] - Sh[0][1] * Sh[1][0] + Sh[0][0] * Sh[2][2] - Sh[0][2] * Sh[2][0] +
+                      Sh[1][1] * Sh[2][2] - Sh[1][2] * Sh[2][1];
+    const double half = 0.5 * tr;
+    return fabs(half) + sqrt(fmax(half * half - m2, 0.0));
+}
+
 // sign of phi (-1 inside the body, 0 on Gamma, +1 outside)
 __device__ inline int geom_sign(const Geom& g, const double* x) {
     if (g.kind == IIM_GEOM_SPHERE) return sphere_sign(g.p, g.p[g.dim], g.dim, x);
+    if (g.kind == IIM_GEOM_GYROID) return sgn(gyroid_phi(g.p, x));
     if (g.kind == IIM_GEOM_STAR2D) return sgn(star_phi(g.p, x[0], x[1]));
     int cnt = (int)llround(g.p[0]);
     bool on = false;
@@ -152,6 +270,17 @@ __device__ inline int geom_sign(const Geom& g, const double* x) {
 __device__ inline uint8_t node_kind(const Geom& g, const int* ijk) {
     double x[3] = {0.0, 0.0, 0.0};
     bool face = false;
+    if (g.periodic) {
+        // no box faces; the image planes (index n) hold no unknowns
+        for (int d = 0; d < g.dim; ++d) {
+            if (ijk[d] >= g.n) return K_INACTIVE;
+            x[d] = node_coord(g, ijk[d]);
+        }
+        const int s = geom_sign(g, x);
+        if (g.side == IIM_SIDE_INTERIOR) return s < 0 ? K_PLUS : K_INACTIVE;
+        if (g.side == IIM_SIDE_EXTERIOR) return s > 0 ? K_PLUS : K_INACTIVE;
+        return s <= 0 ? K_MINUS : K_PLUS;
+    }
     for (int d = 0; d < g.dim; ++d) {
         x[d] = node_coord(g, ijk[d]);
         if (ijk[d] == 0 || ijk[d] == g.n) face = true;
@@ -188,6 +317,35 @@ __device__ inline double crossing_root(const Geom& g, const double* xa, int axis
         double s = sqrt(fmax(q, 0.0));
         bool inside = (g.side != IIM_SIDE_EXTERIOR);  // interior problems and interfaces walk out
         root = inside ? c[axis] + (double)dir * s : c[axis] - (double)dir * s;
+    } else if (g.kind == IIM_GEOM_GYROID) {
+        // bisection (64 halvings) on the sign of phi; a zero at an end point is the root
+        double lo_pt[3] = {xa[0], xa[1], xa[2]};
+        if (dir < 0) lo_pt[axis] = xa[axis] - g.h;
+        double hi_pt[3] = {lo_pt[0], lo_pt[1], lo_pt[2]};
+        hi_pt[axis] = lo_pt[axis] + g.h;
+        const int s_lo = sgn(gyroid_phi(g.p, lo_pt)), s_hi = sgn(gyroid_phi(g.p, hi_pt));
+        if (s_lo == 0) {
+            root = lo_pt[axis];
+        } else if (s_hi == 0) {
+            root = hi_pt[axis];
+        } else {
+            double a = lo_pt[axis], b = hi_pt[axis];
+            double pt[3] = {lo_pt[0], lo_pt[1], lo_pt[2]};
+            bool hit = false;
+            root = 0.0;
+            for (int it = 0; it < 64; ++it) {
+                const double m = 0.5 * (a + b);
+                pt[axis] = m;
+                const int s = sgn(gyroid_phi(g.p, pt));
+                if (s == 0) {
+                    root = m;
+                    hit = true;
+                    break;
+                }
+                if (s == s_lo) a = m; else b = m;
+            }
+            if (!hit) root = 0.5 * (a + b);
+        }
     } else if (g.kind == IIM_GEOM_STAR2D) {
         double lo_pt[2] = {xa[0], xa[1]};
         if (dir < 0) lo_pt[axis] = xa[axis] - g.h;
@@ -251,7 +409,9 @@ __device__ inline double crossing_root(const Geom& g, const double* xa, int axis
 // unit normal from Omega^- into Omega^+ at a point of Gamma
 __device__ inline void geom_normal(const Geom& g, const double* x, int which, double* n) {
     double v[3] = {0.0, 0.0, 0.0};
-    if (g.kind == IIM_GEOM_STAR2D) {
+    if (g.kind == IIM_GEOM_GYROID) {
+        gyroid_grad(g.p, x, v);
+    } else if (g.kind == IIM_GEOM_STAR2D) {
         double dx = x[0] - g.p[0], dy = x[1] - g.p[1];
         double rho = sqrt(dx * dx + dy * dy);
         double c = dx / rho;
@@ -275,6 +435,7 @@ __device__ inline void geom_normal(const Geom& g, const double* x, int which, do
 // largest principal curvature magnitude at a point of Gamma
 __device__ inline double geom_curvature(const Geom& g, const double* x, int which) {
     if (g.kind == IIM_GEOM_SPHERE) return 1.0 / g.p[g.dim];
+    if (g.kind == IIM_GEOM_GYROID) return gyroid_curvature(g.p, x);
     if (g.kind == IIM_GEOM_SPHERE_UNION) return 1.0 / g.p[1 + (g.dim + 1) * which + g.dim];
     double dx = x[0] - g.p[0], dy = x[1] - g.p[1];
     double rho = sqrt(dx * dx + dy * dy);

@@ -377,7 +377,7 @@ void Problem::setup() {
             Level& L = levels[l];
             L.n = sizes[l];
             L.h = h * (double)(1 << l);
-            L.geom = Geom{kind, side, dim, L.n, grid.lo, L.h, d_params};
+            L.geom = Geom{kind, side, dim, L.n, grid.lo, L.h, d_params, grid.periodic ? 1 : 0};
             G.g[l] = L.geom;
         }
         run_classify_levels(G, nl, d_part, d_bb, d_cnt, stream);
@@ -391,15 +391,26 @@ void Problem::setup() {
         for (int l = 0; l < nl; ++l) {
             Level& L = levels[l];
             const int* bb = h_bb.data() + 8 * l;
-            if (bb[6]) throw Error(IIM_E_GEOMETRY_UNRESOLVED, "the immersed body touches the domain box");
+            if (bb[6] && !grid.periodic)
+                throw Error(IIM_E_GEOMETRY_UNRESOLVED, "the immersed body touches the domain box");
             L.nunk = (int64_t)h_cnt[l];
             const bool empty = h_cnt[l] == 0;
-            int mn[3] = {bb[0], bb[1], dim == 3 ? bb[2] : 0};
-            int mx[3] = {bb[3], bb[4], dim == 3 ? bb[5] : 0};
-            L.box = make_box(dim, mn, mx, l == 0 ? w : 1, empty);  // level 0: the stencil's reach
-            for (int d = 0; d < 3; ++d) {
-                L.core_lo[d] = empty ? 1 : (d < dim ? mn[d] : 0);
-                L.core_hi[d] = empty ? 0 : (d < dim ? mx[d] : 0);
+            if (grid.periodic) {
+                // the storage box is the periodic cell: nodes 0..n-1 on every axis
+                // (neighbours are taken modulo n), no padding
+                L.box = Box{{0, 0, 0}, {L.n, L.n, dim == 3 ? L.n : 1}};
+                for (int d = 0; d < 3; ++d) {
+                    L.core_lo[d] = 0;
+                    L.core_hi[d] = d < dim ? L.n - 1 : 0;
+                }
+            } else {
+                int mn[3] = {bb[0], bb[1], dim == 3 ? bb[2] : 0};
+                int mx[3] = {bb[3], bb[4], dim == 3 ? bb[5] : 0};
+                L.box = make_box(dim, mn, mx, l == 0 ? w : 1, empty);  // level 0: the stencil's reach
+                for (int d = 0; d < 3; ++d) {
+                    L.core_lo[d] = empty ? 1 : (d < dim ? mn[d] : 0);
+                    L.core_hi[d] = empty ? 0 : (d < dim ? mx[d] : 0);
+                }
             }
             if (L.box.size() > (int64_t)INT32_MAX) throw Error(IIM_E_BUDGET, "storage box exceeds 2^31 nodes");
             L.labels = (uint8_t*)mem.alloc(L.box.size());
@@ -557,7 +568,7 @@ void Problem::setup() {
         double* A = (double*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(double));
         Ainv64 = (double*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(double));
         Ainv32 = (float*)mem.alloc(std::max<int64_t>(nc * nc, 1) * sizeof(float));
-        run_coarse_assemble(Lc.box, dim, Lc.labels, Lc.irr_index, Lc.rec64, coarse_list, d_col, nc, A, stream);
+        run_coarse_assemble(Lc.box, dim, grid.periodic, Lc.labels, Lc.irr_index, Lc.rec64, coarse_list, d_col, nc, A, stream);
         if (singular && nc) {
             // the coarsest SW matrix annihilates constants as the fine operator
             // does: invert the bordered [A 1; 1^T 0] and keep its leading block,
@@ -617,9 +628,10 @@ void Problem::setup() {
     const int64_t tail_default = TAIL_MAX_NODES;
     const int64_t tail_max = opt.tail_nodes == 0 ? tail_default : (int64_t)opt.tail_nodes;
     tail_first = nl - 1;
-    // the W-cycle visits every level from the host; the one-workgroup kernel
-    // then holds the coarse solve only
-    if (opt.cycle_gamma == 1)
+    // the W-cycle visits every level from the host, and periodic levels take
+    // the grid kernels (neighbours modulo n): the one-workgroup kernel then
+    // holds the coarse solve only
+    if (opt.cycle_gamma == 1 && !grid.periodic)
         while (tail_first > 0 && levels[tail_first - 1].box.size() <= tail_max) --tail_first;
     // 3D grid levels keep their vectors colour-split: a red-black half-sweep then
     // reads and writes whole contiguous colour rows
@@ -713,6 +725,7 @@ LevelDev Problem::level_dev(int l) const {
     D.hx = L.hx;
     D.half = L.half;
     D.lab_split = L.lab_split;
+    D.periodic = grid.periodic ? 1 : 0;
     return D;
 }
 
@@ -751,6 +764,11 @@ GhostDev Problem::ghost_dev() const {
 void Problem::apply_box(const double* x, double* y, int with_data) {
     run_ghosts(ghost_dev(), x, cpdata, with_data, ghost, stream);
     const Level& L0 = levels[0];
+    if (grid.periodic) {
+        run_ho_apply_periodic(dim, box, grid.n, L0.labels, ho_irr_index, ho_slots, ghost, 1.0 / (h * h),
+                              opt.beta_plus, opt.beta_minus, x, y, stream);
+        return;
+    }
     run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost, boxval,
                  w, 1.0 / (h * h),
                  opt.beta_plus, opt.beta_minus, x, y, with_data, stream);
@@ -1530,7 +1548,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     if (!(o.beta_plus > 0) || !(o.beta_minus > 0)) throw Error(IIM_E_INVALID_ARG, "beta must be positive");
     if ((geo->side == IIM_SIDE_INTERFACE) != (geo->bc == IIM_BC_JUMP))
         throw Error(IIM_E_INVALID_ARG, "jump conditions go with interface problems");
-    if (geo->kind < 0 || geo->kind > 2 || geo->side < 0 || geo->side > 2 || geo->bc < 0 || geo->bc > 2)
+    if (geo->kind < 0 || geo->kind > 3 || geo->side < 0 || geo->side > 2 || geo->bc < 0 || geo->bc > 2)
         throw Error(IIM_E_INVALID_ARG, "bad geometry enums");
     if (!geo->params) throw Error(IIM_E_INVALID_ARG, "null params");
     if (geo->kind == IIM_GEOM_STAR2D && (g->dim != 2 || geo->nparams < 5))
@@ -1541,8 +1559,14 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
         (geo->nparams < 1 || geo->params[0] < 0 || geo->nparams < 1 + (g->dim + 1) * (int)geo->params[0]))
         throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
     check_singular_connected(*g, *geo);
-    if (geo->side != IIM_SIDE_INTERIOR) {
-        // box faces must coincide on every level
+    if (g->periodic) {
+        if (!o45) throw Error(IIM_E_INVALID_ARG, "periodic problems: the (4,5) scheme");
+        if (g->n < 32) throw Error(IIM_E_INVALID_ARG, "periodic problems need n >= 32");
+    }
+    if (geo->kind == IIM_GEOM_GYROID && (g->dim != 3 || geo->nparams < 4 || !g->periodic))
+        throw Error(IIM_E_INVALID_ARG, "the gyroid needs dim 3, 4 parameters and a periodic grid");
+    if (geo->side != IIM_SIDE_INTERIOR || g->periodic) {
+        // box faces (periodic images) must coincide on every level
         int n = g->n;
         while (n > o.coarsest_n) {
             if (n % 2) throw Error(IIM_E_INVALID_ARG, "exterior/interface problems need n = m 2^L with m <= coarsest_n");
@@ -1572,10 +1596,15 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     p->kind = geo->kind;
     p->side = geo->side;
     p->bc = geo->bc;
-    p->singular = geo->side == IIM_SIDE_INTERIOR && geo->bc == IIM_BC_NEUMANN;
+    // no Dirichlet value pins the constant: an interior Neumann domain, or a
+    // periodic one whose immersed condition is Neumann or a jump
+    p->singular = g->periodic ? geo->bc != IIM_BC_DIRICHLET
+                              : (geo->side == IIM_SIDE_INTERIOR && geo->bc == IIM_BC_NEUMANN);
     p->params.assign(geo->params, geo->params + geo->nparams);
-    p->opt_fused = o.fused_smoothing != 0 && o.cycle_gamma == 1;  // the fused legs start from zero
-    p->opt_split = o.colour_split != 0;
+    // the fused legs start from zero; periodic levels keep the box layout and the
+    // per-node grid kernels
+    p->opt_fused = o.fused_smoothing != 0 && o.cycle_gamma == 1 && !g->periodic;
+    p->opt_split = o.colour_split != 0 && !g->periodic;
     p->setup();
     return p;
 }
@@ -1832,6 +1861,7 @@ int iim_vcycle(iim_problem* h, const double* v, double* z) {
 
 int iim_gradient(iim_problem* h, const double* u, double* grad) {
     ABI_TRY({
+        if (h && h->p->grid.periodic) throw Error(IIM_E_INVALID_ARG, "no gradient post-processing on periodic grids");
         if (!h || !u || !grad) throw Error(IIM_E_INVALID_ARG, "null argument");
         Problem& p = *h->p;
         const int64_t n1 = p.grid.n + 1;

@@ -76,7 +76,7 @@ void run_sw_records(const Geom& g, const Box& b, const uint8_t* labels, const in
                     int64_t nirr, int bc, double beta_plus, double beta_minus, double* rec64,
                     float* rec32, int32_t* irr_index, hipStream_t s);
 // dense scaled SW matrix on the coarsest level (rows/cols = listed unknowns), then its inverse
-void run_coarse_assemble(const Box& b, int dim, const uint8_t* labels, const int32_t* irr_index,
+void run_coarse_assemble(const Box& b, int dim, int periodic, const uint8_t* labels, const int32_t* irr_index,
                          const double* rec64, const int32_t* list, const int32_t* col_of, int64_t nc,
                          double* A, hipStream_t s);
 void run_coarse_invert(double* A, double* Ainv, int64_t nc, int* d_err, hipStream_t s);
@@ -118,6 +118,11 @@ struct GhostDev {
 };
 void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
                 hipStream_t s);
+// the same on a periodic grid whose storage box is the periodic cell (n nodes
+// per axis, neighbours modulo n), (4,5) scheme, one thread per node
+void run_ho_apply_periodic(int dim, const Box& b, int n, const uint8_t* labels, const int32_t* irr_index,
+                           const int32_t* slots, const double* ghost, double inv_h2, double beta_plus,
+                           double beta_minus, const double* x, double* y, hipStream_t s);
 // part: 0 = the whole apply, 1 = the stencil kernel alone, 2 = the 3D irregular-node kernel alone
 void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
                   const int32_t* irr_index, const int32_t* slots, const int32_t* irr_nodes, int64_t nirr,
@@ -143,6 +148,9 @@ struct LevelDev {
     int split, hx;
     int64_t half;
     const uint8_t* lab_split;
+    // 1: periodic level whose storage box is the periodic cell (0..n-1 per
+    // axis); neighbours are taken modulo n (box layout only)
+    int periodic;
 };
 // entries of a level vector and the index of node (i, j, k) in it
 __host__ __device__ inline int64_t vsize(const LevelDev& L) { return L.split ? 2 * L.half : L.box.size(); }

@@ -18,6 +18,16 @@
 
 namespace iim {
 
+// On a periodic grid a node index i (0..n-1) is taken at the image nearest to
+// the control point coordinate xcd (a fit spans a few h, the cell n h): the
+// unwrapped index, whose coordinate lo + i h is then formed as for any node.
+__device__ inline int unwrap_near(const Geom& g, int i, double xcd) {
+    if (!g.periodic) return i;
+    const double t = (xcd - g.lo) / g.h - (double)i;
+    return i + g.n * (int)llround(t / (double)g.n);
+}
+
+
 constexpr int LS_MAXC = 1024;  // candidates kept per set (LDS list)
 constexpr int LS_RROWS = 12;   // rows per lane of a register-held column (768 = the 3D slab height)
 constexpr double SET_TOL = 1e-12;
@@ -82,7 +92,7 @@ __device__ bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int cl
             int li = list_idx[r - 1 + (r - 1 >= closest ? 1 : 0)];
             int ijk[3];
             b.coords(li, ijk);
-            for (int d = 0; d < dim; ++d) xi[d] = (node_coord(g, ijk[d]) - xc[d]) / sc;
+            for (int d = 0; d < dim; ++d) xi[d] = (node_coord(g, unwrap_near(g, ijk[d], xc[d])) - xc[d]) / sc;
         }
 #pragma unroll
         for (int c = 0; c < PT; ++c)
@@ -254,7 +264,8 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
             int wlo[3] = {0, 0, 0}, wlen[3] = {1, 1, 1};
             for (int d = 0; d < g.dim; ++d) {
                 int ci = (int)floor((xc[d] - g.lo) / g.h + 0.5);
-                int lo = max(0, ci - R), hi = min(g.n, ci + R);
+                // periodic: the window is unwrapped (no clamp); labels and indices wrap below
+                int lo = g.periodic ? ci - R : max(0, ci - R), hi = g.periodic ? ci + R : min(g.n, ci + R);
                 wlo[d] = lo;
                 wlen[d] = hi - lo + 1;
             }
@@ -268,10 +279,13 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                 double r2 = 0.0;
                 if (t < total) {
                     int ijk[3] = {wlo[0] + t % wlen[0], wlo[1] + (t / wlen[0]) % wlen[1], wlo[2] + t / (wlen[0] * wlen[1])};
+                    int wk3[3] = {ijk[0], ijk[1], ijk[2]};
+                    if (g.periodic)
+                        for (int d = 0; d < g.dim; ++d) wk3[d] = wrap_index(ijk[d], g.n);
                     bool inbox = true;
-                    for (int d = 0; d < 3; ++d) inbox = inbox && ijk[d] >= b.lo[d] && ijk[d] < b.lo[d] + b.dims[d];
+                    for (int d = 0; d < 3; ++d) inbox = inbox && wk3[d] >= b.lo[d] && wk3[d] < b.lo[d] + b.dims[d];
                     if (inbox) {
-                        lidx = (int32_t)b.idx(ijk[0], ijk[1], ijk[2]);
+                        lidx = (int32_t)b.idx(wk3[0], wk3[1], wk3[2]);
                         if ((labels[lidx] & KIND_MASK) == side) {
 #pragma clang fp contract(off)
                             double nn = 0.0;
@@ -327,7 +341,7 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                     int acoord[3];
                     b.coords(anode, acoord);
                     double xa[3] = {0.0, 0.0, 0.0};
-                    for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, acoord[d]);
+                    for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, unwrap_near(g, acoord[d], xc[d]));
                     for (int k = 0; k < P.nrows; ++k)
                         for (int col = lane; col < p; col += 64) {
                             double val;
@@ -386,7 +400,7 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
                     int li = list_idx[r - 1 + (r - 1 >= closest ? 1 : 0)];
                     int ijk[3];
                     b.coords(li, ijk);
-                    for (int d = 0; d < g.dim; ++d) xi[d] = (node_coord(g, ijk[d]) - xc[d]) / sc;
+                    for (int d = 0; d < g.dim; ++d) xi[d] = (node_coord(g, unwrap_near(g, ijk[d], xc[d])) - xc[d]) / sc;
                 }
                 for (int col = 0; col < p; ++col)
                     Acol[(int64_t)col * mcap + r] = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) *
@@ -502,7 +516,7 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
             int acoord[3];
             b.coords(anode, acoord);
             double xa[3] = {0.0, 0.0, 0.0};
-            for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, acoord[d]);
+            for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, unwrap_near(g, acoord[d], xc[d]));
             for (int k = 0; k < P.nrows; ++k)
                 for (int col = lane; col < p; col += 64) {
                     double val;

@@ -216,6 +216,65 @@ __global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, con
     y[l] = beta * inv_h2 * acc;
 }
 
+// Apply on a periodic grid whose storage box is the periodic cell: one thread
+// per node, neighbours modulo n, irregular half-lines from their slots (grid
+// values up to the first crossing, then ghost values; a point back on the
+// stencil's side beyond a sliver reads the grid).  (4,5) scheme.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ho_apply_periodic(Box b, int n, const uint8_t* __restrict__ labels,
+                                                           const int32_t* __restrict__ irr_index,
+                                                           const int32_t* __restrict__ slots,
+                                                           const double* __restrict__ ghost, double inv_h2, double bp,
+                                                           double bm, const double* __restrict__ x,
+                                                           double* __restrict__ y) {
+    constexpr int W = 2;
+    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (l >= b.size()) return;
+    const uint8_t lab = labels[l];
+    const uint8_t kind = lab & KIND_MASK;
+    if (kind != K_PLUS && kind != K_MINUS) {
+        y[l] = 0.0;
+        return;
+    }
+    int ijk[3];
+    b.coords(l, ijk);
+    const bool irr = lab & F_HO_IRR;
+    const int32_t* rec = irr ? slots + (int64_t)irr_index[l] * 2 * DIM : nullptr;
+    double acc = (double)DIM * ho_a<W>(0) * x[l];
+    for (int d = 0; d < DIM; ++d)
+        for (int t = 0; t < 2; ++t) {
+            const int dir = t ? 1 : -1;
+            const int slot = irr ? rec[2 * d + t] : make_slot(SLOT_REG, 0, 0);
+            const int type = slot_type(slot), j0 = slot_j(slot);
+            for (int jj = 1; jj <= W; ++jj) {
+                int c[3] = {ijk[0], ijk[1], ijk[2]};
+                c[d] = wrap_index(c[d] + dir * jj, n);
+                const int64_t q = b.idx(c[0], c[1], c[2]);
+                double val;
+                if (type == SLOT_REG || jj < j0 || (labels[q] & KIND_MASK) == kind)
+                    val = x[q];
+                else
+                    val = ghost[(int64_t)slot_cs(slot) * W + (jj - j0)];
+                acc += ho_a<W>(jj) * val;
+            }
+        }
+    y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
+}
+
+void run_ho_apply_periodic(int dim, const Box& b, int n, const uint8_t* labels, const int32_t* irr_index,
+                           const int32_t* slots, const double* ghost, double inv_h2, double beta_plus,
+                           double beta_minus, const double* x, double* y, hipStream_t s) {
+    const int64_t N = b.size();
+    if (N == 0) return;
+    if (dim == 2)
+        hipLaunchKernelGGL((k_ho_apply_periodic<2>), dim3(cdiv(N, 256)), dim3(256), 0, s, b, n, labels, irr_index,
+                           slots, ghost, inv_h2, beta_plus, beta_minus, x, y);
+    else
+        hipLaunchKernelGGL((k_ho_apply_periodic<3>), dim3(cdiv(N, 256)), dim3(256), 0, s, b, n, labels, irr_index,
+                           slots, ghost, inv_h2, beta_plus, beta_minus, x, y);
+    IIM_LAUNCH_CHECK();
+}
+
 // Block index -> tile index such that each XCD (blocks are dealt to the 8 XCDs
 // round robin) receives one contiguous run of tiles: neighbouring tiles then
 // share that XCD's L2.
@@ -713,10 +772,15 @@ __device__ inline void sw_row(const LevelDev& L, int i, int j, int k, int64_t l,
     int64_t nm[3], np[3];  // indices of the neighbours (d, -) and (d, +)
     if (!L.split) {
         const int64_t st[3] = {1, (int64_t)L.box.dims[0], (int64_t)L.box.dims[0] * L.box.dims[1]};
+        const int c[3] = {i, j, k};
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             nm[d] = l - st[d];
             np[d] = l + st[d];
+            if (L.periodic) {  // the box is the periodic cell
+                if (c[d] == 0) nm[d] = l + (int64_t)(L.n - 1) * st[d];
+                if (c[d] == L.n - 1) np[d] = l - (int64_t)(L.n - 1) * st[d];
+            }
         }
     } else {
         // neighbours have the other colour: rows r, r +- 1, r +- dims_y of that array
@@ -775,11 +839,12 @@ __device__ inline void restrict_node(const LevelDev& F, const LevelDev& C, int I
         return;
     }
     const int f2[3] = {2 * I, 2 * J, 2 * K};
-    for (int d = 0; d < DIM; ++d)
-        if (f2[d] - 1 < F.box.lo[d] || f2[d] + 1 >= F.box.lo[d] + F.box.dims[d]) {
-            bc[vc] = (T)0;  // cannot happen: a coarse unknown is a fine unknown
-            return;
-        }
+    if (!F.periodic)
+        for (int d = 0; d < DIM; ++d)
+            if (f2[d] - 1 < F.box.lo[d] || f2[d] + 1 >= F.box.lo[d] + F.box.dims[d]) {
+                bc[vc] = (T)0;  // cannot happen: a coarse unknown is a fine unknown
+                return;
+            }
     const T w0 = (T)0.5, w1 = DIM == 2 ? (T)0.125 : (T)(1.0 / 12.0);
     T acc = w0 * fine_resid<T, S, DIM>(F, f2[0], f2[1], f2[2], z, b);
 #pragma unroll
@@ -787,6 +852,10 @@ __device__ inline void restrict_node(const LevelDev& F, const LevelDev& C, int I
         int p[3] = {f2[0], f2[1], f2[2]}, m[3] = {f2[0], f2[1], f2[2]};
         p[d] += 1;
         m[d] -= 1;
+        if (F.periodic) {  // fine neighbours modulo n
+            p[d] = wrap_index(p[d], F.n);
+            m[d] = wrap_index(m[d], F.n);
+        }
         acc += w1 * (fine_resid<T, S, DIM>(F, p[0], p[1], p[2], z, b) + fine_resid<T, S, DIM>(F, m[0], m[1], m[2], z, b));
     }
     bc[vc] = (T)4 * acc;
@@ -808,7 +877,12 @@ __device__ inline bool prolong_corr(const LevelDev& C, int i, int j, int k, int 
 #pragma unroll
             for (int cq = 0; cq < (DIM == 3 ? 2 : 1); ++cq) {
                 if (a >= ni || bq >= nj || cq >= nk) continue;
-                const int P0 = li + a, P1 = lj + bq, P2 = lk + cq;
+                int P0 = li + a, P1 = lj + bq, P2 = lk + cq;
+                if (C.periodic) {  // coarse parent n_c is the image of 0
+                    P0 = wrap_index(P0, C.n);
+                    P1 = wrap_index(P1, C.n);
+                    if (DIM == 3) P2 = wrap_index(P2, C.n);
+                }
                 const bool inb = P0 >= C.box.lo[0] && P0 < C.box.lo[0] + C.box.dims[0] && P1 >= C.box.lo[1] &&
                                  P1 < C.box.lo[1] + C.box.dims[1] && P2 >= C.box.lo[2] &&
                                  P2 < C.box.lo[2] + C.box.dims[2];
@@ -1856,7 +1930,10 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
     level_grid(C, &g, &k);
     if (F.dim == 2)
         hipLaunchKernelGGL((k_resid_restrict<T, S, 2>), g, k, 0, s, F, C, z, b, bc);
-    else
+    else if (F.periodic) {
+        if (zc0) throw Error(IIM_E_INTERNAL, "periodic levels keep the box layout");
+        hipLaunchKernelGGL((k_resid_restrict<T, S, 3>), g, k, 0, s, F, C, z, b, bc);
+    } else
         hipLaunchKernelGGL((k_restrict3<T, S>), dim3(g.x * g.y * g.z), dim3(256), 0, s, F, C, (int)g.x, (int)g.y, z, b,
                            bc, zc0);
     IIM_LAUNCH_CHECK();
@@ -1864,6 +1941,13 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
 
 template <typename T, typename S>
 void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S* z, hipStream_t s) {
+    if (F.dim == 3 && F.periodic) {
+        dim3 g, k;
+        level_grid(F, &g, &k);
+        hipLaunchKernelGGL((k_prolong<T, S, 3>), g, k, 0, s, F, C, mode, zc, z);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
     if (F.dim == 3) {
         // coarse cells whose fine nodes meet the fine core
         int c0[3], nc[3];

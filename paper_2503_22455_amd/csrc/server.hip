@@ -290,7 +290,9 @@ static void check_request(const iim_request& q) {
     if (geo.kind == IIM_GEOM_SPHERE_UNION &&
         (geo.nparams < 1 || geo.params[0] < 0 || geo.nparams < 1 + (g.dim + 1) * (int64_t)geo.params[0]))
         throw Error(IIM_E_INVALID_ARG, "sphere union parameter count");
-    if (geo.kind < 0 || geo.kind > 2) throw Error(IIM_E_INVALID_ARG, "bad geometry kind");
+    if (geo.kind < 0 || geo.kind > 3) throw Error(IIM_E_INVALID_ARG, "bad geometry kind");
+    if (geo.kind == IIM_GEOM_GYROID && (g.dim != 3 || geo.nparams < 4 || !g.periodic))
+        throw Error(IIM_E_INVALID_ARG, "the gyroid needs dim 3, 4 parameters and a periodic grid");
     check_singular_connected(g, geo);
     if (q.data_kind != 0 && q.data_kind != 1) throw Error(IIM_E_INVALID_ARG, "unknown data kind");
     if (q.data_kind == 0) {

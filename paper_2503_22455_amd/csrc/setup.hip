@@ -145,6 +145,12 @@ __global__ void k_cp_flags(Geom g, Box b, const uint8_t* labels, uint8_t* flags_
          l += (int64_t)gridDim.x * blockDim.x) {
         int ijk[3];
         b.coords(l, ijk);
+        if (g.periodic) {
+            // every segment, the last one of a line closing through the image of node 0
+            const int64_t q = ijk[axis] + 1 < g.n ? l + st : l - (int64_t)(g.n - 1) * st;
+            flags[l] = crossing_pair(labels[l], labels[q], g.side) ? 1 : 0;
+            continue;
+        }
         bool ok = ijk[axis] - b.lo[axis] + 1 < b.dims[axis];
         for (int d = 0; d < g.dim; ++d) ok = ok && ijk[d] >= 0 && ijk[d] <= g.n;
         ok = ok && ijk[axis] + 1 <= g.n;
@@ -245,7 +251,10 @@ __global__ void k_cp_compute(Geom g, Box b, const uint8_t* labels, CPDev cp, int
     if (c >= cp.ncp) return;
     int axis = cp.axis[c];
     int64_t p = cp.lower[c];
-    int64_t q = p + b.stride(axis);
+    int pijk[3];
+    b.coords(p, pijk);
+    // upper node: on a periodic grid the last segment of a line closes through node 0
+    int64_t q = (g.periodic && pijk[axis] == g.n - 1) ? p - (int64_t)(g.n - 1) * b.stride(axis) : p + b.stride(axis);
     uint8_t kp = labels[p] & KIND_MASK;
     int64_t a;
     if (g.side == IIM_SIDE_INTERFACE)
@@ -253,10 +262,11 @@ __global__ void k_cp_compute(Geom g, Box b, const uint8_t* labels, CPDev cp, int
     else
         a = (kp == K_PLUS) ? p : q;
     int dir = (a == p) ? 1 : -1;
-    int ijk[3];
-    b.coords(a, ijk);
+    // coordinates of the root-search node; on a periodic grid unwrapped: q sits
+    // at x_p + h e_axis
     double xa[3] = {0.0, 0.0, 0.0};
-    for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, ijk[d]);
+    for (int d = 0; d < g.dim; ++d) xa[d] = node_coord(g, pijk[d]);
+    if (a == q) xa[axis] = g.periodic ? node_coord(g, pijk[axis]) + g.h : node_coord(g, pijk[axis] + 1);
     int which = 0;
     double root = crossing_root(g, xa, axis, dir, &which);
     double x[3] = {xa[0], xa[1], xa[2]};
@@ -308,6 +318,7 @@ __device__ inline uint8_t kind_at(const Geom& g, const Box& b, const uint8_t* la
                                   int step, int64_t* l) {
     int c[3] = {ijk[0], ijk[1], ijk[2]};
     c[d] += step;
+    if (g.periodic) c[d] = wrap_index(c[d], g.n);
     if (c[d] < 0 || c[d] > g.n || c[d] < b.lo[d] || c[d] >= b.lo[d] + b.dims[d]) {
         *l = -1;
         return 255;
@@ -372,7 +383,8 @@ __global__ void k_ho_irr_records(Geom g, Box b, const uint8_t* labels, CPDev cp,
                 } else if (kq == 255) {
                     atomicOr(err, 4);  // stencil leaves the storage box
                 } else {
-                    int64_t lower = prev < q ? prev : q;
+                    // the segment's lower node: the one whose +e_d neighbour is the other
+                    int64_t lower = dir > 0 ? prev : q;
                     int64_t c = find_cp(cp, d, (int32_t)lower);
                     if (c < 0) {
                         atomicOr(err, 8);
@@ -530,7 +542,7 @@ void run_fill_int(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 }
 
 // dense coarse matrix: row r of the listed unknowns; col_of[l] = column of box node l (-1 if excluded)
-__global__ void k_coarse_assemble(Box b, int dim, const uint8_t* labels, const int32_t* irr_index,
+__global__ void k_coarse_assemble(Box b, int dim, int periodic, const uint8_t* labels, const int32_t* irr_index,
                                   const double* rec64, const int32_t* list, const int32_t* col_of, int64_t nc,
                                   double* A) {
     int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -544,18 +556,24 @@ __global__ void k_coarse_assemble(Box b, int dim, const uint8_t* labels, const i
     for (int d = 0; d < dim; ++d)
         for (int t = 0; t < 2; ++t) {
             int64_t q = l + (t ? 1 : -1) * b.stride(d);
+            if (periodic) {  // the box is the periodic cell: neighbours modulo its width
+                int ijk[3];
+                b.coords(l, ijk);
+                const int i2 = wrap_index(ijk[d] - b.lo[d] + (t ? 1 : -1), b.dims[d]);
+                q = l + (int64_t)(i2 - (ijk[d] - b.lo[d])) * b.stride(d);
+            }
             double c = irr ? rec64[irr_index[l] * R + 1 + 2 * d + t] : 1.0;
             int32_t col = col_of[q];
             if (c != 0.0 && col >= 0) A[r * nc + col] += c;
         }
 }
 
-void run_coarse_assemble(const Box& b, int dim, const uint8_t* labels, const int32_t* irr_index,
+void run_coarse_assemble(const Box& b, int dim, int periodic, const uint8_t* labels, const int32_t* irr_index,
                          const double* rec64, const int32_t* list, const int32_t* col_of, int64_t nc, double* A,
                          hipStream_t s) {
     if (nc == 0) return;
-    hipLaunchKernelGGL(k_coarse_assemble, dim3(cdiv(nc, 64)), dim3(64), 0, s, b, dim, labels, irr_index, rec64,
-                       list, col_of, nc, A);
+    hipLaunchKernelGGL(k_coarse_assemble, dim3(cdiv(nc, 64)), dim3(64), 0, s, b, dim, periodic, labels, irr_index,
+                       rec64, list, col_of, nc, A);
     IIM_LAUNCH_CHECK();
 }
 

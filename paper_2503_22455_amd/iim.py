@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libiim.so")
 
-GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION = 0, 1, 2
+GEOM_SPHERE, GEOM_STAR2D, GEOM_SPHERE_UNION, GEOM_GYROID = 0, 1, 2, 3
 SIDE_INTERIOR, SIDE_EXTERIOR, SIDE_INTERFACE = 0, 1, 2
 BC_DIRICHLET, BC_NEUMANN, BC_JUMP = 0, 1, 2
 PREC = {"fp64": 0, "mixed32": 1, "mixed16": 2}
@@ -33,7 +33,8 @@ class IIMError(RuntimeError):
 
 
 class Grid(ctypes.Structure):
-    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Geometry(ctypes.Structure):
@@ -202,12 +203,12 @@ class Problem:
                  precision: str = "fp64", ls_axes: Optional[Tuple[float, float]] = None,
                  lo: float = -1.0, hi: float = 1.0, use_graph: int = 2, tail_nodes: int = 0,
                  fused_smoothing: bool = True, colour_split: bool = True, order: Tuple[int, int] = (4, 5),
-                 orthogonalisation: int = 1, cycle: str = "V", stream=None):
+                 orthogonalisation: int = 1, cycle: str = "V", stream=None, periodic: bool = False):
         L = lib()
         self.dim, self.n = dim, n
         self.side, self.bc = side, bc
         self.total = (n + 1) ** dim
-        g = Grid(dim, n, lo, hi)
+        g = Grid(dim, n, lo, hi, int(periodic), 0)
         pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
         geo = Geometry(geom_kind, side, bc, len(geom_params), pa)
         o = make_options(beta_plus, beta_minus, rtol, max_iters, restart, nu_pre, nu_post, coarsest_n, precision,
@@ -390,14 +391,14 @@ class Server:
 
     def submit(self, dim: int, n: int, geom_kind: int, geom_params, side: int = SIDE_INTERIOR,
                bc: int = BC_DIRICHLET, data_kind: int = 1, u_out=None, lo: float = -1.0, hi: float = 1.0,
-               f=None, cp_data=None, box_data=None, hist_cap: int = 0, **opt) -> int:
+               f=None, cp_data=None, box_data=None, hist_cap: int = 0, periodic: bool = False, **opt) -> int:
         """data_kind 1: device-side manufactured data; data_kind 0: the caller's
         f (full grid), cp_data (per control point, in the library's order) and
         box_data (full grid or None), as contiguous CUDA tensors that stay
         alive (the server keeps references) until the result is collected;
         hist_cap > 0 collects the residual history (returned by wait/poll)."""
         pa = (ctypes.c_double * len(geom_params))(*[float(v) for v in geom_params])
-        req = Request(Grid(dim, n, lo, hi), Geometry(geom_kind, side, bc, len(geom_params), pa), make_options(**opt),
+        req = Request(Grid(dim, n, lo, hi, int(periodic), 0), Geometry(geom_kind, side, bc, len(geom_params), pa), make_options(**opt),
                       data_kind, MEM_DEVICE, None if u_out is None else _ptr(u_out))
         keep = [u_out]
         if data_kind == 0:
@@ -464,5 +465,8 @@ def from_workload(wl, precision: Optional[str] = None, **kw) -> Problem:
     kw.setdefault("order", tuple(getattr(wl, "order", (4, 5))))
     kw.setdefault("orthogonalisation", int(getattr(wl, "orthogonalisation", 1)))
     kw.setdefault("cycle", str(getattr(wl, "cycle", "V")))
+    kw.setdefault("lo", getattr(wl, "lo", -1.0))
+    kw.setdefault("hi", getattr(wl, "hi", 1.0))
+    kw.setdefault("periodic", bool(getattr(wl, "periodic", False)))
     return Problem(wl.dim, wl.n, wl.geom_kind, wl.geom_params, wl.side, wl.bc, wl.beta_plus, wl.beta_minus,
                    precision=precision or wl.precision, **kw)
