@@ -1428,6 +1428,12 @@ void Problem::launch_kernel_t(int kernel) {
         case 0:
         case 11: {
             const Level& L0 = levels[0];
+            if (grid.periodic) {  // one kernel covers every node of the periodic cell
+                if (kernel == 11) throw Error(IIM_E_INVALID_ARG, "periodic problems have no irregular-node kernel");
+                run_ho_apply_periodic(dim, box, grid.n, L0.labels, ho_irr_index, ho_slots, ghost, 1.0 / (h * h),
+                                      opt.beta_plus, opt.beta_minus, rk, wk, stream);
+                break;
+            }
             run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost,
                          boxval, w, 1.0 / (h * h), opt.beta_plus, opt.beta_minus, rk, wk, 0, stream,
                          kernel == 0 ? 1 : 2);
