@@ -139,7 +139,7 @@ def test_cylinder_flow_pressure_coefficient():
 
 def test_sphere_flow_pressure_coefficient_256():
     """Potential flow past a sphere at 256^3 (FP64 outer solve, FP32 V-cycle):
-    C_p at the 1e5 control points against the closed form 1 - (9/4) sin^2, a
+    C_p at the 77 k control points against the closed form 1 - (9/4) sin^2, a
     check that holds at any size (no oracle run at this size)."""
     import sys
     print("case: sphere potential flow 256^3", file=sys.stderr, flush=True)

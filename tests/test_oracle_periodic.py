@@ -148,3 +148,20 @@ def test_gyroid_geometry():
         Pt = np.eye(3) - np.outer(cp.n, cp.n)
         ev = np.linalg.eigvalsh(0.5 * (Pt @ J @ Pt + (Pt @ J @ Pt).T))
         assert abs(np.abs(ev).max() - cp.kappa) <= 1e-5 * max(1.0, cp.kappa), (ev, cp.kappa)
+
+
+def test_det_sincos_accuracy():
+    """The IEEE-only sin/cos used for the gyroid (Cody-Waite reduction by pi/2
+    in three parts, Taylor series on |r| <= pi/4) agrees with the platform's
+    sin and cos to a few ulp over the arguments k x takes (|t| <= 8 pi), keeps
+    sin^2 + cos^2 = 1, and is exact at the quadrant points where it must be."""
+    from oracle.geometry import det_sincos
+    t = np.concatenate([np.linspace(-8 * math.pi, 8 * math.pi, 200001),
+                        np.random.default_rng(0).uniform(-30.0, 30.0, 100000)])
+    s, c = det_sincos(t)
+    assert np.abs(s - np.sin(t)).max() <= 4.5e-16
+    assert np.abs(c - np.cos(t)).max() <= 4.5e-16
+    assert np.abs(s * s + c * c - 1.0).max() <= 5e-16
+    s0, c0 = det_sincos(np.array([0.0, math.pi / 2, -math.pi / 6]))
+    assert s0[0] == 0.0 and c0[0] == 1.0 and s0[1] == 1.0
+    assert abs(s0[2] + 0.5) <= 1.2e-16
