@@ -155,12 +155,24 @@ __device__ bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int cl
     for (int c = 0; c < PT; ++c)
         if (lane < PT && lane <= c) Rs[lane][c] = A[0][c];
     __syncthreads();
-    // R^T Y = E^T, one lane per functional
-    if (lane < nrows) {
+    // R^T Y = E^T by columns: lane j keeps E_j minus the terms known so far and
+    // subtracts R_ij y_i as soon as y_i is known (the same operations, in the same
+    // order, as the row-by-row substitution)
+    {
+        double acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = (k < nrows && lane < PT) ? E[k][lane] : 0.0;
+#pragma unroll 1
         for (int i = 0; i < PT; ++i) {
-            double acc = E[lane][i];
-            for (int l2 = 0; l2 < i; ++l2) acc -= Rs[l2][i] * Y[l2][lane];
-            Y[i][lane] = acc / Rs[i][i];
+            const double rii = Rs[i][i];
+            const double rij = (lane > i && lane < PT) ? Rs[i][lane] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k >= nrows) break;
+                const double yi = lane_value(acc[k], i) / rii;
+                if (lane == 0) Y[i][k] = yi;
+                if (lane > i) acc[k] -= rij * yi;
+            }
         }
     }
     __syncthreads();
@@ -204,7 +216,7 @@ __device__ bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int cl
         const int r = lane + 64 * q;
         if (r >= 1 && r < M) {
             int li = list_idx[r - 1 + (r - 1 >= closest ? 1 : 0)];
-            idx_out[base + r - 1] = li;
+            if (idx_out) idx_out[base + r - 1] = li;
             for (int k = 0; k < nrows; ++k) S_out[(int64_t)k * nnz + base + r - 1] = sv[k][q];
         }
     }
@@ -595,6 +607,196 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3D register fits of the (4,5) scheme (about 235 points, 35 monomials), in
+// two kernels.  The register QR holds a whole fit in one wavefront and runs
+// one wave per SIMD, so the candidate search, a chain of dependent label
+// loads, would stall it; here it runs in a kernel of its own with few
+// registers and many waves per SIMD.
+//
+// k_ls3_search (one wavefront per fit) finds the smallest growth whose set has
+// at least 35 points and writes the set, without its point closest to x_c,
+// into the fit's staging segment.  Sets larger than 256 points are routed to
+// the global-memory path.  k_ls3_qr then runs the register QR of k_ls on that
+// set (the same operations, so the same weights); a set that fails the rank
+// test is routed to the global-memory path, which grows it as k_ls does.
+constexpr int L3_CAP = 256;  // register rows (4 rows x 64 lanes) = the 3D staging segment
+
+__global__ void __launch_bounds__(256) k_ls3_search(Geom g, Box b, const uint8_t* labels, CPDev cp, LSParams P,
+                                                    int32_t* m_out, int32_t* grow_out, int32_t* st_idx,
+                                                    uint8_t* route, int* err) {
+    __shared__ int32_t list_idx[4][L3_CAP];
+    __shared__ double list_r2[4][L3_CAP];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t ncs = cp.ncp * P.nsides;
+    const int K = P.order_k;
+    const int p = K * (K + 1) * (K + 2) / 6;
+    const int64_t seg = L3_CAP;
+    for (int64_t cs = (int64_t)blockIdx.x * 4 + wv; cs < ncs; cs += (int64_t)gridDim.x * 4) {
+        const int64_t c = cs / P.nsides;
+        const int sidx = (int)(cs % P.nsides);
+        const uint8_t side = sidx == 0 ? K_PLUS : K_MINUS;
+        double xc[3], nu[3];
+        for (int d = 0; d < 3; ++d) {
+            xc[d] = cp.x[d * cp.ncp + c];
+            const double nd = cp.n[d * cp.ncp + c];
+            nu[d] = sidx == 0 ? nd : -nd;
+        }
+        int result = 0;  // 0: none, 1: found, 2: routed
+        for (int grow = 0; grow <= P.max_grow && result == 0; ++grow) {
+            const double a = P.a0 + 0.5 * grow, bb = P.b0 + 0.5 * grow;
+            const int R = (int)ceil(fmax(a, bb)) + 1;
+            int wlo[3], wlen[3];
+            for (int d = 0; d < 3; ++d) {
+                int ci = (int)floor((xc[d] - g.lo) / g.h + 0.5);
+                int lo = g.periodic ? ci - R : max(0, ci - R), hi = g.periodic ? ci + R : min(g.n, ci + R);
+                wlo[d] = lo;
+                wlen[d] = hi - lo + 1;
+            }
+            const int total = wlen[0] * wlen[1] * wlen[2];
+            int count = 0;
+            for (int base = 0; base < total; base += 64) {
+                const int t = base + lane;
+                bool keep = false;
+                int32_t lidx = 0;
+                double r2 = 0.0;
+                if (t < total) {
+                    const int q01 = t / wlen[0];
+                    int ijk[3] = {wlo[0] + (t - q01 * wlen[0]), wlo[1] + q01 % wlen[1], wlo[2] + q01 / wlen[1]};
+                    int wk3[3] = {ijk[0], ijk[1], ijk[2]};
+                    if (g.periodic)
+                        for (int d = 0; d < 3; ++d) wk3[d] = wrap_index(ijk[d], g.n);
+                    bool inbox = true;
+                    for (int d = 0; d < 3; ++d) inbox = inbox && wk3[d] >= b.lo[d] && wk3[d] < b.lo[d] + b.dims[d];
+                    if (inbox) {
+                        lidx = (int32_t)b.idx(wk3[0], wk3[1], wk3[2]);
+                        if ((labels[lidx] & KIND_MASK) == side) {
+#pragma clang fp contract(off)
+                            double nn = 0.0;
+                            for (int d = 0; d < 3; ++d) {
+                                double delta = (node_coord(g, ijk[d]) - xc[d]) / g.h;
+                                nn += delta * nu[d];
+                                r2 += delta * delta;
+                            }
+                            double tt = fmax(r2 - nn * nn, 0.0);
+                            keep = (nn >= -SET_TOL) && (tt / (a * a) + nn * nn / (bb * bb) <= 1.0 + SET_TOL);
+                        }
+                    }
+                }
+                unsigned long long mask = __ballot(keep);
+                int before = __popcll(mask & ((1ull << lane) - 1ull));
+                if (keep && count + before < L3_CAP) {
+                    list_idx[wv][count + before] = lidx;
+                    list_r2[wv][count + before] = r2;
+                }
+                count += __popcll(mask);
+            }
+            if (count > L3_CAP) {  // too large for the register kernel
+                result = 2;
+                break;
+            }
+            if (count < p) continue;  // too few points (or none): grow
+            // closest candidate: minimal r2, ties within SET_TOL to the lowest position
+            double dmin = 1e300;
+            for (int i = lane; i < count; i += 64) dmin = fmin(dmin, list_r2[wv][i]);
+            dmin = wave_min(dmin);
+            int closest = count;
+            for (int i = lane; i < count; i += 64)
+                if (list_r2[wv][i] <= dmin + SET_TOL) closest = min(closest, i);
+            for (int off = 32; off > 0; off >>= 1) closest = min(closest, __shfl_xor(closest, off, 64));
+            for (int i = lane; i < count - 1; i += 64) st_idx[cs * seg + i] = list_idx[wv][i + (i >= closest ? 1 : 0)];
+            if (lane == 0) {
+                m_out[cs] = count - 1;
+                grow_out[cs] = grow;
+            }
+            result = 1;
+        }
+        if (lane == 0) {
+            if (result == 2) {
+                route[cs] = 1;
+                grow_out[cs] = -3;
+                m_out[cs] = 0;
+            } else if (result == 0) {
+                m_out[cs] = 0;
+                grow_out[cs] = -1;
+                atomicOr(err, 128);
+            }
+        }
+    }
+}
+
+template <int PT, int RPL>
+__global__ void __launch_bounds__(64) k_ls3_qr(Geom g, Box b, CPDev cp, LSParams P, int32_t* m_out,
+                                               int32_t* grow_out, const int32_t* st_idx, double* S_out,
+                                               double* Sc_out, uint8_t* route) {
+    __shared__ int32_t list_idx[L3_CAP];
+    __shared__ int ex[84][3];
+    __shared__ double tauv[84];
+    __shared__ double Y[84][4];
+    __shared__ double E[4][84];
+    __shared__ double Rs[PT][PT];
+    const int lane = threadIdx.x;
+    if (lane == 0) monomials(3, P.order_k - 1, ex);
+    __syncthreads();
+    const int64_t ncs = cp.ncp * P.nsides;
+    const int64_t seg = L3_CAP;
+    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
+        const int grow = grow_out[cs];
+        if (grow < 0) continue;  // routed or failed in the search
+        const int m = m_out[cs];
+        const int M = m + 1;
+        const int64_t c = cs / P.nsides;
+        const int sidx = (int)(cs % P.nsides);
+        double xc[3], nrm[3];
+        for (int d = 0; d < 3; ++d) {
+            xc[d] = cp.x[d * cp.ncp + c];
+            nrm[d] = cp.n[d * cp.ncp + c];
+        }
+        const int axis = cp.axis[c];
+        const int64_t anode = cp.a[sidx * cp.ncp + c];
+        const int adir = cp.dir[sidx * cp.ncp + c];
+        const double sc = (P.a0 + 0.5 * grow) * g.h;
+        for (int i = lane; i < m; i += 64) list_idx[i] = st_idx[cs * seg + i];
+        // evaluation functionals: ghosts j = 1..w at anode + j adir e_axis, then d/dn (and d/dx_d)
+        int acoord[3];
+        b.coords(anode, acoord);
+        double xa[3];
+        for (int d = 0; d < 3; ++d) xa[d] = node_coord(g, unwrap_near(g, acoord[d], xc[d]));
+        for (int k = 0; k < P.nrows; ++k)
+            for (int col = lane; col < PT; col += 64) {
+                double val;
+                if (k < P.w) {
+                    double xg[3] = {xa[0], xa[1], xa[2]};
+                    xg[axis] = xa[axis] + (double)((k + 1) * adir) * g.h;
+                    double xi[3];
+                    for (int d = 0; d < 3; ++d) xi[d] = (xg[d] - xc[d]) / sc;
+                    val = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) * ipow(xi[2], ex[col][2]);
+                } else {
+                    // row w: d/dn; rows w + 1 + d: d/dx_d (gradient fits)
+                    int deg = ex[col][0] + ex[col][1] + ex[col][2];
+                    val = 0.0;
+                    if (deg == 1) {
+                        int d = ex[col][0] ? 0 : (ex[col][1] ? 1 : 2);
+                        const int r = k - P.w;
+                        val = (r == 0 ? nrm[d] : (d == r - 1 ? 1.0 : 0.0)) / sc;
+                    }
+                }
+                E[k][col] = val;
+            }
+        __syncthreads();
+        // the set is already without its closest point: no position is skipped
+        const bool ok = reg_qr<PT, RPL>(M, lane, 3, list_idx, M, b, g, xc, sc, ex, true, P.nrows, E, Y, tauv, Rs,
+                                        cs * seg, ncs * seg, cs, nullptr, S_out, Sc_out);
+        __syncthreads();
+        if (!ok && lane == 0) {  // rank deficient: the global-memory path grows the set
+            route[cs] = 1;
+            grow_out[cs] = -3;
+            m_out[cs] = 0;
+        }
+    }
+}
+
 // staging (fixed segments of seg entries per fit) -> CSR, for the fits of the
 // register path (route[cs] == 0); one wavefront per fit
 __global__ void __launch_bounds__(256) k_ls_compact(int64_t ncs, int seg, int nrows, const int32_t* m,
@@ -638,7 +840,13 @@ void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
     else if (g.dim == 2)
         hipLaunchKernelGGL((k_ls<15, 2>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
                            idx, S, Sc, scratch, d_err, cs_list, n_list, route);
-    else
+    else if (P.order_k == 5 && !cs_list && pass == 0 && idx) {
+        hipLaunchKernelGGL(k_ls3_search, dim3(cdiv(nwork, 4)), dim3(256), 0, s, g, b, labels, cp, P, m_out, grow_out,
+                           idx, route, d_err);
+        IIM_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_ls3_qr<35, 4>), dim3(blocks), dim3(64), 0, s, g, b, cp, P, m_out, grow_out, idx, S, Sc,
+                           route);
+    } else
         hipLaunchKernelGGL((k_ls<35, 4>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
                            idx, S, Sc, scratch, d_err, cs_list, n_list, route);
     IIM_LAUNCH_CHECK();
