@@ -52,30 +52,37 @@ def test_gradient_and_boundary_quantity(name):
 
 def test_solved_gradient_converges():
     """On the device's own solutions of the star interface problem the
-    gradient error falls at order 4 (the paper's gradient convergence):
-    measured 3.45 from n = 128 to 256, still pre-asymptotic (the oracle pins
-    order 4 on the paper's interface case over n = 128 .. 512)."""
+    gradient error falls at order 4 (the paper's gradient convergence), over
+    n = 128, 256, 512 (the oracle pins order 4 on the same case over the same
+    sizes).  The data come from the closed forms at the device's own labels and
+    control points."""
+    import sys
+    from paper_2503_22455_amd import iim
     errs = []
-    for n in (128, 256):
+    for n in (128, 256, 512):
         wl = W.cfg2_star(n)
-        O = oracle_for(wl)
-        cpd, box, f = oracle_data(O, wl)
         G = gpu_for(wl, precision="fp64", rtol=1e-13)
-        G.set_boundary_data(cpd, box)
-        G.set_rhs(f)
+        lab = G.node_labels()
+        xyz, nrm = G.control_points()
+        G.set_boundary_data(wl.cp_data(xyz, nrm), iim.grid_to_flat(wl.box_data()))
+        G.set_rhs(iim.grid_to_flat(wl.rhs(iim.flat_to_grid(lab, 2, n))))
         u, hist, st = G.solve()
         assert st["status"] == 0
         g = G.gradient(torch.nan_to_num(u, nan=0.0)).cpu().numpy()
-        X = [x.ravel(order="F")[O.unknowns] for x in wl.node_coords()]
-        lab = O.lab_flat[O.unknowns]
+        unk = np.flatnonzero((lab == 1) | (lab == 2))
+        X = [x.ravel(order="F")[unk] for x in wl.node_coords()]
+        lu = lab[unk]
         gp, gm = wl.exact.grad_plus(*X), wl.exact.grad_minus(*X)
         e = 0.0
         for d in range(2):
-            ge = np.where(lab == 2, np.asarray(gm[d]) * np.ones_like(X[0]), np.asarray(gp[d]) * np.ones_like(X[0]))
-            e = max(e, np.abs(g[d][O.unknowns] - ge).max())
+            ge = np.where(lu == 2, np.asarray(gm[d]) * np.ones_like(X[0]), np.asarray(gp[d]) * np.ones_like(X[0]))
+            e = max(e, np.abs(g[d][unk] - ge).max())
         errs.append(e)
         G.close()
-    assert np.log2(errs[0] / errs[1]) > 3.3, errs
+    rates = [float(np.log2(errs[i] / errs[i + 1])) for i in range(2)]
+    print(f"gradient errors {errs}, rates {rates}", file=sys.stderr, flush=True)
+    # measured 3.45 and 3.72: rising towards 4
+    assert rates[0] > 3.3 and rates[1] > 3.6 and rates[1] > rates[0], (errs, rates)
 
 
 # ---------------------------------------------------------------------------

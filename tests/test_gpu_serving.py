@@ -89,9 +89,10 @@ def test_server_result_same_alone_and_in_mix():
     res = [s4.wait(t) for t in tickets]
     st = s4.stats()
     s4.close()
-    for r in res:
+    for (dim, n, _), r in zip(MIX, res):
         assert r["status"] == 0 and r["rel_residual"] <= 1e-10, r
-        assert r["max_error"] < 1e-2, r  # discretisation error; 3D n = 33 is the coarsest
+        # fourth-order discretisation error: measured 48-80 h^4 (3D), 109-375 h^4 (2D)
+        assert r["max_error"] <= 600.0 * (2.0 / n) ** 4, r
     rB = res[2]
     assert rB["iterations"] == rA["iterations"]
     assert torch.equal(torch.isnan(uA), torch.isnan(uB))
