@@ -83,6 +83,8 @@ __host__ __device__ inline int wrap_index(int i, int n) {
     const int r = i % n;
     return r < 0 ? r + n : r;
 }
+// the same for -n <= i < 2n (neighbour offsets below the period): no division
+__host__ __device__ inline int wrap_near(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 __device__ inline double node_coord(const Geom& g, int i) {
 #pragma clang fp contract(off)

@@ -765,8 +765,8 @@ void Problem::apply_box(const double* x, double* y, int with_data) {
     run_ghosts(ghost_dev(), x, cpdata, with_data, ghost, stream);
     const Level& L0 = levels[0];
     if (grid.periodic) {
-        run_ho_apply_periodic(dim, box, grid.n, L0.labels, ho_irr_index, ho_slots, ghost, 1.0 / (h * h),
-                              opt.beta_plus, opt.beta_minus, x, y, stream);
+        run_ho_apply_periodic(dim, box, grid.n, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost,
+                              1.0 / (h * h), opt.beta_plus, opt.beta_minus, x, y, stream);
         return;
     }
     run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost, boxval,
@@ -1428,10 +1428,12 @@ void Problem::launch_kernel_t(int kernel) {
         case 0:
         case 11: {
             const Level& L0 = levels[0];
-            if (grid.periodic) {  // one kernel covers every node of the periodic cell
-                if (kernel == 11) throw Error(IIM_E_INVALID_ARG, "periodic problems have no irregular-node kernel");
-                run_ho_apply_periodic(dim, box, grid.n, L0.labels, ho_irr_index, ho_slots, ghost, 1.0 / (h * h),
-                                      opt.beta_plus, opt.beta_minus, rk, wk, stream);
+            if (grid.periodic) {
+                if (kernel == 11 && dim == 2)
+                    throw Error(IIM_E_INVALID_ARG, "2D periodic problems have no irregular-node kernel");
+                run_ho_apply_periodic(dim, box, grid.n, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost,
+                                      1.0 / (h * h), opt.beta_plus, opt.beta_minus, rk, wk, stream,
+                                      kernel == 0 ? 1 : 2);
                 break;
             }
             run_ho_apply(dim, box, L0.core_lo, L0.core_hi, L0.labels, ho_irr_index, ho_slots, ho_nodes, ho_nirr, ghost,

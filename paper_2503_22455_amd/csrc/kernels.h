@@ -119,10 +119,12 @@ struct GhostDev {
 void run_ghosts(const GhostDev& G, const double* x, const double* cpdata, int with_data, double* ghost,
                 hipStream_t s);
 // the same on a periodic grid whose storage box is the periodic cell (n nodes
-// per axis, neighbours modulo n), (4,5) scheme, one thread per node
+// per axis, neighbours modulo n), (4,5) scheme: in 2D one thread per node; in 3D
+// the z-march with wrapped loads (part 1) and the listed irregular nodes (part 2)
 void run_ho_apply_periodic(int dim, const Box& b, int n, const uint8_t* labels, const int32_t* irr_index,
-                           const int32_t* slots, const double* ghost, double inv_h2, double beta_plus,
-                           double beta_minus, const double* x, double* y, hipStream_t s);
+                           const int32_t* slots, const int32_t* irr_nodes, int64_t nirr, const double* ghost,
+                           double inv_h2, double beta_plus, double beta_minus, const double* x, double* y,
+                           hipStream_t s, int part = 0);
 // part: 0 = the whole apply, 1 = the stencil kernel alone, 2 = the 3D irregular-node kernel alone
 void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
                   const int32_t* irr_index, const int32_t* slots, const int32_t* irr_nodes, int64_t nirr,

@@ -31,20 +31,24 @@ __global__ void __launch_bounds__(256) k_ghosts(GhostDev G, const double* __rest
         double acc[2][NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[0][k] = acc[1][k] = 0.0;
-        int64_t a = b0 + lane;
-        // two entries per step so that twice the gathers are in flight
-        for (; a + GLN < b1; a += 2 * GLN) {
-            const double x0 = x[G.idx[a]], x1 = x[G.idx[a + GLN]];
+        // GU entries per lane and step: all their index loads, then all their
+        // gathers and weight loads are in flight together (a 3D set of ~235
+        // points is one step: one index-then-gather round trip)
+        constexpr int GU = 4;
+        for (int64_t a0 = b0 + lane; a0 < b1; a0 += GU * GLN) {
+            int32_t iv[GU];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                acc[0][k] += G.W[k * G.nnz + a] * x0;
-                acc[1][k] += G.W[k * G.nnz + a + GLN] * x1;
+            for (int u = 0; u < GU; ++u) iv[u] = a0 + u * GLN < b1 ? G.idx[a0 + u * GLN] : -1;
+            double xv[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) xv[u] = iv[u] >= 0 ? x[iv[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int64_t a = a0 + u * GLN;
+                if (a < b1)
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) acc[u & 1][k] += G.W[k * G.nnz + a] * xv[u];
             }
-        }
-        if (a < b1) {
-            const double x0 = x[G.idx[a]];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) acc[0][k] += G.W[k * G.nnz + a] * x0;
         }
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
@@ -221,23 +225,15 @@ __global__ void __launch_bounds__(256) k_ho_apply(Box b, int3 clo, int3 chi, con
 // values up to the first crossing, then ghost values; a point back on the
 // stencil's side beyond a sliver reads the grid).  (4,5) scheme.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_ho_apply_periodic(Box b, int n, const uint8_t* __restrict__ labels,
-                                                           const int32_t* __restrict__ irr_index,
-                                                           const int32_t* __restrict__ slots,
-                                                           const double* __restrict__ ghost, double inv_h2, double bp,
-                                                           double bm, const double* __restrict__ x,
-                                                           double* __restrict__ y) {
+__device__ inline double ho_periodic_node(const Box& b, int n, int64_t l, uint8_t lab,
+                                          const int32_t* __restrict__ irr_index, const int32_t* __restrict__ slots,
+                                          const uint8_t* __restrict__ labels, const double* __restrict__ ghost,
+                                          double inv_h2, double bp, double bm, const double* __restrict__ x) {
     constexpr int W = 2;
-    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (l >= b.size()) return;
-    const uint8_t lab = labels[l];
     const uint8_t kind = lab & KIND_MASK;
-    if (kind != K_PLUS && kind != K_MINUS) {
-        y[l] = 0.0;
-        return;
-    }
     int ijk[3];
     b.coords(l, ijk);
+    const int64_t st[3] = {1, (int64_t)b.dims[0], (int64_t)b.dims[0] * b.dims[1]};  // the box is the cell: dims n
     const bool irr = lab & F_HO_IRR;
     const int32_t* rec = irr ? slots + (int64_t)irr_index[l] * 2 * DIM : nullptr;
     double acc = (double)DIM * ho_a<W>(0) * x[l];
@@ -247,9 +243,10 @@ __global__ void __launch_bounds__(256) k_ho_apply_periodic(Box b, int n, const u
             const int slot = irr ? rec[2 * d + t] : make_slot(SLOT_REG, 0, 0);
             const int type = slot_type(slot), j0 = slot_j(slot);
             for (int jj = 1; jj <= W; ++jj) {
-                int c[3] = {ijk[0], ijk[1], ijk[2]};
-                c[d] = wrap_index(c[d] + dir * jj, n);
-                const int64_t q = b.idx(c[0], c[1], c[2]);
+                const int cd = ijk[d] + dir * jj;  // the neighbour's coordinate, then its image in the cell
+                int64_t q = l + (int64_t)(dir * jj) * st[d];
+                if (cd < 0) q += (int64_t)n * st[d];
+                else if (cd >= n) q -= (int64_t)n * st[d];
                 double val;
                 if (type == SLOT_REG || jj < j0 || (labels[q] & KIND_MASK) == kind)
                     val = x[q];
@@ -258,22 +255,42 @@ __global__ void __launch_bounds__(256) k_ho_apply_periodic(Box b, int n, const u
                 acc += ho_a<W>(jj) * val;
             }
         }
-    y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
+    return ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
 }
 
-void run_ho_apply_periodic(int dim, const Box& b, int n, const uint8_t* labels, const int32_t* irr_index,
-                           const int32_t* slots, const double* ghost, double inv_h2, double beta_plus,
-                           double beta_minus, const double* x, double* y, hipStream_t s) {
-    const int64_t N = b.size();
-    if (N == 0) return;
-    if (dim == 2)
-        hipLaunchKernelGGL((k_ho_apply_periodic<2>), dim3(cdiv(N, 256)), dim3(256), 0, s, b, n, labels, irr_index,
-                           slots, ghost, inv_h2, beta_plus, beta_minus, x, y);
-    else
-        hipLaunchKernelGGL((k_ho_apply_periodic<3>), dim3(cdiv(N, 256)), dim3(256), 0, s, b, n, labels, irr_index,
-                           slots, ghost, inv_h2, beta_plus, beta_minus, x, y);
-    IIM_LAUNCH_CHECK();
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ho_apply_periodic(Box b, int n, const uint8_t* __restrict__ labels,
+                                                           const int32_t* __restrict__ irr_index,
+                                                           const int32_t* __restrict__ slots,
+                                                           const double* __restrict__ ghost, double inv_h2, double bp,
+                                                           double bm, const double* __restrict__ x,
+                                                           double* __restrict__ y) {
+    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (l >= b.size()) return;
+    const uint8_t lab = labels[l];
+    const uint8_t kind = lab & KIND_MASK;
+    if (kind != K_PLUS && kind != K_MINUS) {
+        y[l] = 0.0;
+        return;
+    }
+    y[l] = ho_periodic_node<DIM>(b, n, l, lab, irr_index, slots, labels, ghost, inv_h2, bp, bm, x);
 }
+
+// the irregular nodes of a periodic cell, one thread each, from their list
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ho_irregular_periodic(Box b, int n, const int32_t* __restrict__ nodes,
+                                                               int64_t nirr, const uint8_t* __restrict__ labels,
+                                                               const int32_t* __restrict__ irr_index,
+                                                               const int32_t* __restrict__ slots,
+                                                               const double* __restrict__ ghost, double inv_h2,
+                                                               double bp, double bm, const double* __restrict__ x,
+                                                               double* __restrict__ y) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nirr) return;
+    const int64_t l = nodes[t];
+    y[l] = ho_periodic_node<DIM>(b, n, l, labels[l], irr_index, slots, labels, ghost, inv_h2, bp, bm, x);
+}
+
 
 // Block index -> tile index such that each XCD (blocks are dealt to the 8 XCDs
 // round robin) receives one contiguous run of tiles: neighbouring tiles then
@@ -308,7 +325,9 @@ __device__ inline Blk3 xcd_block3(int gx, int gy) {
 // k_ho_irregular.
 constexpr int ZM_TX = 64, ZM_RY = 1, ZM_TY = 4 * ZM_RY;
 
-template <int W>
+// PER: a periodic cell (the box itself, dims n, no margin): every load takes the
+// image of its node in the cell.
+template <int W, bool PER = false>
 __global__ void __launch_bounds__(256, W == 2 ? 8 : 6) k_ho_apply3_zm(Box b, int3 clo, int3 chi, int ntx, int nty, int zc,
                                                       const uint8_t* __restrict__ labels, double inv_h2, double bp,
                                                       double bm, const double* __restrict__ x,
@@ -324,16 +343,23 @@ __global__ void __launch_bounds__(256, W == 2 ? 8 : 6) k_ho_apply3_zm(Box b, int
     const int i = i0 + lane;
     const int zs = clo.z + tz * zc, ze = min(zs + zc - 1, chi.z);
     const int bxh = b.lo[0] + b.dims[0] - 1, byh = b.lo[1] + b.dims[1] - 1, bzh = b.lo[2] + b.dims[2] - 1;
-    // in-box loads (the box holds the core with a W-node margin; beyond it in x/y: 0)
+    const int n = b.dims[0];
+    // in-box loads (the box holds the core with a W-node margin; beyond it in x/y: 0);
+    // periodic: the column index is wrapped once per thread, rows and planes per load
     auto ldx = [&](int ii, int jj, int kk) -> double {
+        if constexpr (PER) return x[b.idx(ii, wrap_near(jj, n), wrap_near(kk, n))];
         return (ii <= bxh && jj <= byh) ? x[b.idx(ii, jj, kk)] : 0.0;
     };
-    auto ldl = [&](int jj, int kk) -> int { return (i <= bxh && jj <= byh) ? (int)labels[b.idx(i, jj, kk)] : 0; };
+    const int iw = PER ? wrap_index(i, n) : i;
+    auto ldl = [&](int jj, int kk) -> int {
+        if constexpr (PER) return (int)labels[b.idx(iw, wrap_near(jj, n), wrap_near(kk, n))];
+        return (i <= bxh && jj <= byh) ? (int)labels[b.idx(i, jj, kk)] : 0;
+    };
     // x-halo duty: lanes 0 .. 2W-1 load tile columns 0 .. W-1 and ZM_TX+W .. ZM_TX+2W-1
     // of the thread's rows; y-halo duty: halo row k (rows 0 .. W-1, then
     // ZM_TY+W .. ZM_TY+2W-1) is loaded by wavefront k % 4, as its slot k / 4
     const int hcol = lane < W ? lane : ZM_TX + lane;
-    const int hi = i0 - W + hcol;
+    const int hi = PER ? wrap_index(i0 - W + hcol, n) : i0 - W + hcol;
     int hr[NHY], hj[NHY];
 #pragma unroll
     for (int u = 0; u < NHY; ++u) {
@@ -347,10 +373,10 @@ __global__ void __launch_bounds__(256, W == 2 ? 8 : 6) k_ho_apply3_zm(Box b, int
 #pragma unroll
     for (int r = 0; r < ZM_RY; ++r)
 #pragma unroll
-        for (int d = 0; d < NQ - 1; ++d) q[r][d] = ldx(i, j0 + wy + 4 * r, zs - W + d);
+        for (int d = 0; d < NQ - 1; ++d) q[r][d] = ldx(iw, j0 + wy + 4 * r, zs - W + d);
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
-        const int zz = min(zs + s, bzh);
+        const int zz = PER ? zs + s : min(zs + s, bzh);
         lb[s] = 0;
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
@@ -358,20 +384,20 @@ __global__ void __launch_bounds__(256, W == 2 ? 8 : 6) k_ho_apply3_zm(Box b, int
             lb[s] |= (uint32_t)ldl(j0 + wy + 4 * r, zz) << (8 * r);
         }
 #pragma unroll
-        for (int u = 0; u < NHY; ++u) hy[s][u] = hr[u] >= 0 ? ldx(i, hj[u], zz) : 0.0;
+        for (int u = 0; u < NHY; ++u) hy[s][u] = hr[u] >= 0 ? ldx(iw, hj[u], zz) : 0.0;
     }
     for (int z = zs; z <= ze; ++z) {
-        const int zp = min(z + LA, bzh);  // clamped planes are never used
+        const int zp = PER ? z + LA : min(z + LA, bzh);  // clamped planes are never used
         double hxn[ZM_RY], hyn[NHY];
         uint32_t lbn = 0;
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
-            q[r][NQ - 1] = ldx(i, j0 + wy + 4 * r, zp);
+            q[r][NQ - 1] = ldx(iw, j0 + wy + 4 * r, zp);
             hxn[r] = lane < 2 * W ? ldx(hi, j0 + wy + 4 * r, zp) : 0.0;
             lbn |= (uint32_t)ldl(j0 + wy + 4 * r, zp) << (8 * r);
         }
 #pragma unroll
-        for (int u = 0; u < NHY; ++u) hyn[u] = hr[u] >= 0 ? ldx(i, hj[u], zp) : 0.0;
+        for (int u = 0; u < NHY; ++u) hyn[u] = hr[u] >= 0 ? ldx(iw, hj[u], zp) : 0.0;
 #pragma unroll
         for (int r = 0; r < ZM_RY; ++r) {
             tile[wy + 4 * r + W][lane + W] = q[r][W];
@@ -448,6 +474,38 @@ __global__ void __launch_bounds__(256) k_ho_irregular(Box b, const int32_t* __re
     acc += ho_irregular<DIM, W>(b, l, kind, labels, slots + (int64_t)irr_index[l] * 2 * DIM, ghost, boxval, x,
                                 with_data);
     y[l] = ((kind == K_PLUS) ? bp : bm) * inv_h2 * acc;
+}
+
+void run_ho_apply_periodic(int dim, const Box& b, int n, const uint8_t* labels, const int32_t* irr_index,
+                           const int32_t* slots, const int32_t* irr_nodes, int64_t nirr, const double* ghost,
+                           double inv_h2, double beta_plus, double beta_minus, const double* x, double* y,
+                           hipStream_t s, int part) {
+    const int64_t N = b.size();
+    if (N == 0) return;
+    if (dim == 2) {
+        hipLaunchKernelGGL((k_ho_apply_periodic<2>), dim3(cdiv(N, 256)), dim3(256), 0, s, b, n, labels, irr_index,
+                           slots, ghost, inv_h2, beta_plus, beta_minus, x, y);
+        IIM_LAUNCH_CHECK();
+        return;
+    }
+    // 3D: the z-march over the cell (loads wrapped), then the irregular nodes from their list
+    for (int d = 0; d < 3; ++d)
+        if (b.lo[d] != 0 || b.dims[d] != n) throw Error(IIM_E_INTERNAL, "apply: the periodic box must be the cell");
+    const int3 lo = make_int3(0, 0, 0), hi = make_int3(n - 1, n - 1, n - 1);
+    const int ntx = cdiv(n, ZM_TX), nty = cdiv(n, ZM_TY);
+    const int64_t cols = (int64_t)ntx * nty;
+    const int zc = (int)std::max<int64_t>(8, std::min<int64_t>(16, cols * n / 2048));
+    const int64_t nb = cols * cdiv(n, zc);
+    if (part != 2) {
+        hipLaunchKernelGGL((k_ho_apply3_zm<2, true>), dim3((unsigned)nb), dim3(256), 0, s, b, lo, hi, ntx, nty, zc,
+                           labels, inv_h2, beta_plus, beta_minus, x, y);
+        IIM_LAUNCH_CHECK();
+    }
+    if (nirr > 0 && part != 1) {
+        hipLaunchKernelGGL((k_ho_irregular_periodic<3>), dim3(cdiv(nirr, 256)), dim3(256), 0, s, b, n, irr_nodes, nirr,
+                           labels, irr_index, slots, ghost, inv_h2, beta_plus, beta_minus, x, y);
+        IIM_LAUNCH_CHECK();
+    }
 }
 
 void run_ho_apply(int dim, const Box& b, const int* core_lo, const int* core_hi, const uint8_t* labels,
@@ -853,8 +911,8 @@ __device__ inline void restrict_node(const LevelDev& F, const LevelDev& C, int I
         p[d] += 1;
         m[d] -= 1;
         if (F.periodic) {  // fine neighbours modulo n
-            p[d] = wrap_index(p[d], F.n);
-            m[d] = wrap_index(m[d], F.n);
+            p[d] = wrap_near(p[d], F.n);
+            m[d] = wrap_near(m[d], F.n);
         }
         acc += w1 * (fine_resid<T, S, DIM>(F, p[0], p[1], p[2], z, b) + fine_resid<T, S, DIM>(F, m[0], m[1], m[2], z, b));
     }
@@ -879,9 +937,9 @@ __device__ inline bool prolong_corr(const LevelDev& C, int i, int j, int k, int 
                 if (a >= ni || bq >= nj || cq >= nk) continue;
                 int P0 = li + a, P1 = lj + bq, P2 = lk + cq;
                 if (C.periodic) {  // coarse parent n_c is the image of 0
-                    P0 = wrap_index(P0, C.n);
-                    P1 = wrap_index(P1, C.n);
-                    if (DIM == 3) P2 = wrap_index(P2, C.n);
+                    P0 = wrap_near(P0, C.n);
+                    P1 = wrap_near(P1, C.n);
+                    if (DIM == 3) P2 = wrap_near(P2, C.n);
                 }
                 const bool inb = P0 >= C.box.lo[0] && P0 < C.box.lo[0] + C.box.dims[0] && P1 >= C.box.lo[1] &&
                                  P1 < C.box.lo[1] + C.box.dims[1] && P2 >= C.box.lo[2] &&
@@ -929,9 +987,11 @@ __device__ inline void coarse_row(const int32_t* list, int64_t nc, const T* Ainv
 // ---- grid kernels
 template <typename T, typename S, int DIM>
 __global__ void __launch_bounds__(256) k_rbgs(LevelDev L, int colour, S* z, const T* b) {
-    int i = L.core_lo[0] + blockIdx.x * blockDim.x + threadIdx.x;
-    int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
-    int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
+    // one thread per pair of x-neighbours: the one of the colour being updated
+    const int j = L.core_lo[1] + blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = DIM == 3 ? L.core_lo[2] + blockIdx.z : 0;
+    const int i0 = L.core_lo[0] + 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int i = i0 + ((i0 + j + k + colour) & 1);
     if (i > L.core_hi[0] || j > L.core_hi[1]) return;
     rbgs_node<T, S, DIM>(L, i, j, k, colour, z, b);
 }
@@ -1905,6 +1965,7 @@ void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s) {
     }
     dim3 g, k;
     level_grid(L, &g, &k);
+    g.x = cdiv(cdiv(std::max(L.core_hi[0] - L.core_lo[0] + 1, 1), 2), 64);  // a thread per pair of nodes
     if (L.dim == 2)
         hipLaunchKernelGGL((k_rbgs<T, S, 2>), g, k, 0, s, L, colour, z, b);
     else
