@@ -77,8 +77,9 @@ __device__ inline double ipow(double x, int e) {
 // unrolling, so A never leaves the register file.  Returns false if the rank
 // test fails.  With want_weights, writes the stencils s = Q R^{-T} e for the
 // functionals in E (nrows <= 4) to S_out / Sc_out exactly like the scratch path.
+// (inlined: as a called function it kept A's spill slots in scratch memory)
 template <int PT, int RPL>
-__device__ bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int closest, const Box& b, const Geom& g,
+__device__ __attribute__((always_inline)) bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int closest, const Box& b, const Geom& g,
                        const double* xc, double sc, const int (*ex)[3], bool want_weights, int nrows,
                        const double (*E)[84], double (*Y)[4], double* tauv, double (*Rs)[PT], int64_t base,
                        int64_t nnz, int64_t cs, int32_t* idx_out, double* S_out, double* Sc_out) {
