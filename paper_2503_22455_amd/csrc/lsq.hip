@@ -79,10 +79,12 @@ __device__ inline double ipow(double x, int e) {
 // functionals in E (nrows <= 4) to S_out / Sc_out exactly like the scratch path.
 // (inlined: as a called function it kept A's spill slots in scratch memory)
 template <int PT, int RPL>
-__device__ __attribute__((always_inline)) bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int closest, const Box& b, const Geom& g,
-                       const double* xc, double sc, const int (*ex)[3], bool want_weights, int nrows,
-                       const double (*E)[84], double (*Y)[4], double* tauv, double (*Rs)[PT], int64_t base,
-                       int64_t nnz, int64_t cs, int32_t* idx_out, double* S_out, double* Sc_out) {
+__device__ __attribute__((always_inline)) bool reg_qr(int M, int lane, int dim, const int32_t* list_idx, int closest,
+                                                      const Box& b, const Geom& g, const double* xc, double sc,
+                                                      const int (*ex)[3], bool want_weights, int nrows,
+                                                      const double (*E)[84], double (*Y)[4], double* tauv,
+                                                      double (*Rs)[PT], int64_t base, int64_t nnz, int64_t cs,
+                                                      int32_t* idx_out, double* S_out, double* Sc_out) {
     double A[RPL][PT];
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
