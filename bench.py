@@ -71,10 +71,10 @@ TRAFFIC = {
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/blas.hip",
                   "begin": "__global__ void __launch_bounds__(RED_THREADS) k_update_dot(",
                   "end": "void run_update_dot_stage1(", "sha": "c4fcc25941381676"},
-    ("cfg3", 1): {"fetch_kib": 319979.3920, "fetch_scale": 524288.0 / 262156.0, "write_kib": 1744.9432,
+    ("cfg3", 1): {"fetch_kib": 318942.0227, "fetch_scale": 524288.0 / 262156.0, "write_kib": 1755.0256,
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/ops.hip",
                   "begin": "__global__ void __launch_bounds__(256) k_ghosts(",
-                  "end": "static void launch_ghosts(", "sha": "758c691f69cf7445"},
+                  "end": "static void launch_ghosts(", "sha": "8fd85f2cdb738c85"},
 }
 
 
