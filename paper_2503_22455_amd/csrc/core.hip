@@ -1612,7 +1612,7 @@ std::unique_ptr<Problem> make_problem(const iim_grid* g, const iim_geometry* geo
     // the fused legs start from zero; periodic levels keep the box layout and the
     // per-node grid kernels
     p->opt_fused = o.fused_smoothing != 0 && o.cycle_gamma == 1 && !g->periodic;
-    p->opt_split = o.colour_split != 0 && !g->periodic;
+    p->opt_split = o.colour_split != 0;
     p->setup();
     return p;
 }

@@ -852,6 +852,15 @@ __device__ inline void sw_row(const LevelDev& L, int i, int j, int k, int64_t l,
         np[1] = base + ry + (a >> 1);
         nm[2] = base - rz + (a >> 1);
         np[2] = base + rz + (a >> 1);
+        if (L.periodic) {  // the box is the cell (lo 0, n per axis): neighbours across the seam
+            const int n = L.n;
+            if (i == 0) nm[0] = base + ((n - 1) >> 1);
+            if (i == n - 1) np[0] = base;
+            if (j == 0) nm[1] = base + (int64_t)(n - 1) * ry + (a >> 1);
+            if (j == n - 1) np[1] = base - (int64_t)(n - 1) * ry + (a >> 1);
+            if (k == 0) nm[2] = base + (int64_t)(n - 1) * rz + (a >> 1);
+            if (k == n - 1) np[2] = base - (int64_t)(n - 1) * rz + (a >> 1);
+        }
     }
     T zm[3], zp[3];
 #pragma unroll
@@ -1049,14 +1058,26 @@ __global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, int 
     const int oth = (colour ^ 1) * (int)L.half + r * L.hx + m0;
     const int ry = L.hx, rz = L.hx * L.box.dims[1];
     const uint32_t lab4 = *reinterpret_cast<const uint32_t*>(L.lab_split + own);
+    // neighbour rows and the entries before and after the thread's four; on a
+    // periodic cell (rows of exactly n / 2 entries) they wrap across the seam
+    int oym = oth - ry, oyp = oth + ry, ozm = oth - rz, ozp = oth + rz, ocm = oth - 1, ocp = oth + 4;
+    if (L.periodic) {
+        const int n = L.n;
+        if (j == 0) oym = oth + (n - 1) * ry;
+        if (j == n - 1) oyp = oth - (n - 1) * ry;
+        if (k == 0) ozm = oth + (n - 1) * rz;
+        if (k == n - 1) ozp = oth - (n - 1) * rz;
+        if (m0 == 0) ocm = oth + L.hx - 1;
+        if (m0 + 4 == L.hx) ocp = oth - m0;
+    }
     T bv[4], c4[4], ym[4], yp[4], zmv[4], zpv[4];
     ld4<T, T>(b, own, bv);
     ld4<T, S>(z, oth, c4);
-    ld4<T, S>(z, oth - ry, ym);
-    ld4<T, S>(z, oth + ry, yp);
-    ld4<T, S>(z, oth - rz, zmv);
-    ld4<T, S>(z, oth + rz, zpv);
-    const T cm = load_it<T, S>(z, oth - 1), cp = load_it<T, S>(z, oth + 4);  // in the box: core rows
+    ld4<T, S>(z, oym, ym);
+    ld4<T, S>(z, oyp, yp);
+    ld4<T, S>(z, ozm, zmv);
+    ld4<T, S>(z, ozp, zpv);
+    const T cm = load_it<T, S>(z, ocm), cp = load_it<T, S>(z, ocp);  // in the box: core rows
     asm volatile("" ::"v"(lab4), "v"(bv[0]), "v"(c4[0]), "v"(ym[0]), "v"(yp[0]), "v"(zmv[0]), "v"(zpv[0]), "v"(cm),
                  "v"(cp));
     T out[4];
@@ -1114,13 +1135,24 @@ __global__ void __launch_bounds__(256) k_rbgs_split1(LevelDev L, int colour, int
     const int ry = L.hx, rz = L.hx * L.box.dims[1];
     const uint8_t lab = L.labels[l];
     const T bv = b[own];
+    int oxm = base + ((a - 1) >> 1), oxp = base + ((a + 1) >> 1), oym = base - ry + m, oyp = base + ry + m,
+        ozm = base - rz + m, ozp = base + rz + m;
+    if (L.periodic) {  // the box is the cell: neighbours across the seam
+        const int n = L.n;
+        if (i == 0) oxm = base + ((n - 1) >> 1);
+        if (i == n - 1) oxp = base;
+        if (j == 0) oym = base + (n - 1) * ry + m;
+        if (j == n - 1) oyp = base - (n - 1) * ry + m;
+        if (k == 0) ozm = base + (n - 1) * rz + m;
+        if (k == n - 1) ozp = base - (n - 1) * rz + m;
+    }
     T zm[3], zp[3];
-    zm[0] = load_it<T, S>(z, base + ((a - 1) >> 1));
-    zp[0] = load_it<T, S>(z, base + ((a + 1) >> 1));
-    zm[1] = load_it<T, S>(z, base - ry + m);
-    zp[1] = load_it<T, S>(z, base + ry + m);
-    zm[2] = load_it<T, S>(z, base - rz + m);
-    zp[2] = load_it<T, S>(z, base + rz + m);
+    zm[0] = load_it<T, S>(z, oxm);
+    zp[0] = load_it<T, S>(z, oxp);
+    zm[1] = load_it<T, S>(z, oym);
+    zp[1] = load_it<T, S>(z, oyp);
+    zm[2] = load_it<T, S>(z, ozm);
+    zp[2] = load_it<T, S>(z, ozp);
     // keep the loads ahead of the label test (the compiler would otherwise sink
     // them below it and serialise two memory round trips)
     asm volatile("" ::"v"(bv), "v"(zm[0]), "v"(zp[0]), "v"(zm[1]), "v"(zp[1]), "v"(zm[2]), "v"(zp[2]));
@@ -1176,8 +1208,12 @@ __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, i
                 bool in = true;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    in = in && P[d] >= C.box.lo[d] && P[d] < C.box.lo[d] + C.box.dims[d];
-                    Q[d] = clampi(P[d], C.box.lo[d], C.box.lo[d] + C.box.dims[d] - 1);
+                    if (C.periodic) {  // coarse parent n_c is the image of 0
+                        Q[d] = wrap_near(P[d], C.n);
+                    } else {
+                        in = in && P[d] >= C.box.lo[d] && P[d] < C.box.lo[d] + C.box.dims[d];
+                        Q[d] = clampi(P[d], C.box.lo[d], C.box.lo[d] + C.box.dims[d] - 1);
+                    }
                 }
                 inb[a][bq][cq] = in;
                 v[a][bq][cq] = load_it<T, S>(zc, vidx(C, Q[0], Q[1], Q[2]));
@@ -1256,7 +1292,9 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int o = 0; o < 5; ++o) X[d][o] = clampi(c[d] + o - 2, F.box.lo[d], F.box.lo[d] + F.box.dims[d] - 1);
+        for (int o = 0; o < 5; ++o)
+            X[d][o] = F.periodic ? wrap_near(c[d] + o - 2, F.n)  // the box is the cell
+                                 : clampi(c[d] + o - 2, F.box.lo[d], F.box.lo[d] + F.box.dims[d] - 1);
     auto zat = [&](int ox, int oy, int oz) { return load_it<T, S>(z, vidx(F, X[0][ox + 2], X[1][oy + 2], X[2][oz + 2])); };
     // the seven residual nodes: 0 = c, 1 + 2d = c + e_d, 2 + 2d = c - e_d
     const int off[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
@@ -1284,7 +1322,7 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
     bool inside = is_unknown(labc);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        inside = inside && c[d] - 1 >= F.box.lo[d] && c[d] + 1 < F.box.lo[d] + F.box.dims[d];
+        inside = inside && (F.periodic || (c[d] - 1 >= F.box.lo[d] && c[d] + 1 < F.box.lo[d] + F.box.dims[d]));
     if (!inside) {
         bc[vc] = (T)0;
         if (zc0) store_t<T, S>(zc0, vc, (T)0);
@@ -1387,13 +1425,24 @@ __global__ void __launch_bounds__(256) k_rbgs_split_out(LevelDev L, int gx, int 
         const int own = (int)L.half + r * L.hx + m;
         const int ry = L.hx, rz = L.hx * L.box.dims[1];
         const int base = r * L.hx;  // colour-0 array, row r
+        int oxm = base + ((a1 - 1) >> 1), oxp = base + ((a1 + 1) >> 1), oym = base - ry + m, oyp = base + ry + m,
+            ozm = base - rz + m, ozp = base + rz + m;
+        if (L.periodic) {  // the box is the cell: neighbours across the seam
+            const int n = L.n;
+            if (i == 0) oxm = base + ((n - 1) >> 1);
+            if (i == n - 1) oxp = base;
+            if (j == 0) oym = base + (n - 1) * ry + m;
+            if (j == n - 1) oyp = base - (n - 1) * ry + m;
+            if (k == 0) ozm = base + (n - 1) * rz + m;
+            if (k == n - 1) ozp = base - (n - 1) * rz + m;
+        }
         T zm[3], zp[3];
-        zm[0] = load_it<T, S>(z, base + ((a1 - 1) >> 1));
-        zp[0] = load_it<T, S>(z, base + ((a1 + 1) >> 1));
-        zm[1] = load_it<T, S>(z, base - ry + m);
-        zp[1] = load_it<T, S>(z, base + ry + m);
-        zm[2] = load_it<T, S>(z, base - rz + m);
-        zp[2] = load_it<T, S>(z, base + rz + m);
+        zm[0] = load_it<T, S>(z, oxm);
+        zp[0] = load_it<T, S>(z, oxp);
+        zm[1] = load_it<T, S>(z, oym);
+        zp[1] = load_it<T, S>(z, oyp);
+        zm[2] = load_it<T, S>(z, ozm);
+        zp[2] = load_it<T, S>(z, ozp);
         const T bv = b[own];
         T diag, off;
         sw_combine<T, 3>(L, row + a1, lab, zm, zp, &diag, &off);
@@ -1953,7 +2002,8 @@ void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s) {
         const int ny = L.core_hi[1] - L.core_lo[1] + 1, nz = L.core_hi[2] - L.core_lo[2] + 1;
         if (ny <= 0 || nz <= 0 || L.hx <= 0) return;
         if (L.hx % 4 || !L.lab_split) throw Error(IIM_E_INTERNAL, "colour-split rows must hold a multiple of 4");
-        if (L.half >= SPLIT4_MIN_ENTRIES) {
+        // four entries per thread: periodic rows must hold exactly n / 2 entries (their seam wrap)
+        if (L.half >= SPLIT4_MIN_ENTRIES && (!L.periodic || 2 * L.hx == L.n)) {
             const int gx = cdiv(L.hx / 4, 64), gy = cdiv(ny, 4);
             hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, colour, gx, gy, z, b);
         } else {
@@ -1991,8 +2041,8 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
     level_grid(C, &g, &k);
     if (F.dim == 2)
         hipLaunchKernelGGL((k_resid_restrict<T, S, 2>), g, k, 0, s, F, C, z, b, bc);
-    else if (F.periodic) {
-        if (zc0) throw Error(IIM_E_INTERNAL, "periodic levels keep the box layout");
+    else if (F.periodic && !F.split) {
+        if (zc0) throw Error(IIM_E_INTERNAL, "coarse iterate start is built for colour-split levels");
         hipLaunchKernelGGL((k_resid_restrict<T, S, 3>), g, k, 0, s, F, C, z, b, bc);
     } else
         hipLaunchKernelGGL((k_restrict3<T, S>), dim3(g.x * g.y * g.z), dim3(256), 0, s, F, C, (int)g.x, (int)g.y, z, b,
@@ -2002,7 +2052,7 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
 
 template <typename T, typename S>
 void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S* z, hipStream_t s) {
-    if (F.dim == 3 && F.periodic) {
+    if (F.dim == 3 && F.periodic && !F.split) {
         dim3 g, k;
         level_grid(F, &g, &k);
         hipLaunchKernelGGL((k_prolong<T, S, 3>), g, k, 0, s, F, C, mode, zc, z);
