@@ -2041,10 +2041,7 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
     level_grid(C, &g, &k);
     if (F.dim == 2)
         hipLaunchKernelGGL((k_resid_restrict<T, S, 2>), g, k, 0, s, F, C, z, b, bc);
-    else if (F.periodic && !F.split) {
-        if (zc0) throw Error(IIM_E_INTERNAL, "coarse iterate start is built for colour-split levels");
-        hipLaunchKernelGGL((k_resid_restrict<T, S, 3>), g, k, 0, s, F, C, z, b, bc);
-    } else
+    else
         hipLaunchKernelGGL((k_restrict3<T, S>), dim3(g.x * g.y * g.z), dim3(256), 0, s, F, C, (int)g.x, (int)g.y, z, b,
                            bc, zc0);
     IIM_LAUNCH_CHECK();
@@ -2052,13 +2049,6 @@ void run_resid_restrict(const LevelDev& F, const LevelDev& C, const S* z, const 
 
 template <typename T, typename S>
 void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S* z, hipStream_t s) {
-    if (F.dim == 3 && F.periodic && !F.split) {
-        dim3 g, k;
-        level_grid(F, &g, &k);
-        hipLaunchKernelGGL((k_prolong<T, S, 3>), g, k, 0, s, F, C, mode, zc, z);
-        IIM_LAUNCH_CHECK();
-        return;
-    }
     if (F.dim == 3) {
         // coarse cells whose fine nodes meet the fine core
         int c0[3], nc[3];
