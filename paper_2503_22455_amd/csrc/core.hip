@@ -259,8 +259,16 @@ void Problem::fit_stencils(int nr, int* d_err, int64_t*& ptr_out, int32_t*& idx_
     int32_t* st_idx = (int32_t*)mem.alloc(ncs1 * seg * sizeof(int32_t));
     double* st_S = (double*)mem.alloc((size_t)nr * ncs1 * seg * sizeof(double));
     Sc_out = (double*)mem.alloc(ncs1 * nr * sizeof(double));
-    run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, st_idx, st_S, Sc_out, nullptr, 0, d_err,
-           nullptr, 0, d_route, stream);
+    if (dim == 3 && opt.order_k == 5 && nr <= 4) {  // the CSNE passes carry up to four functionals
+        const int64_t per = ls3_csne_doubles_per_fit();
+        double* work = (double*)mem.alloc((size_t)ncs1 * per * sizeof(double));
+        run_ls3_csne(L0.geom, box, L0.labels, cp, P, d_m, d_grow, st_idx, st_S, Sc_out, d_route, work,
+                     work + ncs1 * (per - 280), work + ncs1 * (per - 140), d_err, stream);
+        mem.release(work);
+    } else {
+        run_ls(L0.geom, box, L0.labels, cp, P, 0, d_m, d_grow, nullptr, st_idx, st_S, Sc_out, nullptr, 0, d_err,
+               nullptr, 0, d_route, stream);
+    }
     std::vector<int32_t> hmg(2 * ncs1);
     IIM_HIP(hipMemcpyAsync(hmg.data(), d_mg, 2 * ncs1 * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     read_err();

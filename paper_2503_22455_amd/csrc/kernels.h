@@ -92,6 +92,14 @@ struct LSParams {
 };
 // entries per fit of the staging layout of pass 0 (64 lanes x rows per lane)
 int ls_segment(int dim);
+// 3D (4,5) fits in staging layout by the corrected semi-normal equations (set
+// search, moments, Cholesky + solve, rows, solve, rows); mom (then L), zc,
+// rho: ls3_csne_doubles_per_fit() doubles per fit between them, zc and rho
+// 140 each
+void run_ls3_csne(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P,
+                  int32_t* m_out, int32_t* grow_out, int32_t* st_idx, double* S, double* Sc, uint8_t* route,
+                  double* mom, double* zc, double* rho, int* d_err, hipStream_t s);
+int64_t ls3_csne_doubles_per_fit();
 // staging -> CSR for the register-path fits (route[cs] == 0)
 void run_ls_compact(int64_t ncs, int seg, int nrows, const int32_t* m, const uint8_t* route, const int64_t* ptr,
                     const int32_t* st_idx, const double* st_S, int32_t* idx, double* S, hipStream_t s);

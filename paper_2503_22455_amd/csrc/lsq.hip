@@ -611,18 +611,16 @@ __global__ void __launch_bounds__(64) k_ls(Geom g, Box b, const uint8_t* labels,
 }
 
 // ---------------------------------------------------------------------------
-// 3D register fits of the (4,5) scheme (about 235 points, 35 monomials), in
-// two kernels.  The register QR holds a whole fit in one wavefront and runs
-// one wave per SIMD, so the candidate search, a chain of dependent label
-// loads, would stall it; here it runs in a kernel of its own with few
-// registers and many waves per SIMD.
+// 3D fits of the (4,5) scheme (about 235 points, 35 monomials).  The candidate
+// search, a chain of dependent label loads, runs in a kernel of its own with
+// few registers and many waves per SIMD.
 //
 // k_ls3_search (one wavefront per fit) finds the smallest growth whose set has
 // at least 35 points and writes the set, without its point closest to x_c,
 // into the fit's staging segment.  Sets larger than 256 points are routed to
-// the global-memory path.  k_ls3_qr then runs the register QR of k_ls on that
-// set (the same operations, so the same weights); a set that fails the rank
-// test is routed to the global-memory path, which grows it as k_ls does.
+// the global-memory path.  The passes below compute the weights on that set; a
+// set that fails the rank test is routed to the global-memory path, which
+// grows it as k_ls does.
 constexpr int L3_CAP = 256;  // register rows (4 rows x 64 lanes) = the 3D staging segment
 
 __global__ void __launch_bounds__(256) k_ls3_search(Geom g, Box b, const uint8_t* labels, CPDev cp, LSParams P,
@@ -729,76 +727,510 @@ __global__ void __launch_bounds__(256) k_ls3_search(Geom g, Box b, const uint8_t
     }
 }
 
-template <int PT, int RPL>
-__global__ void __launch_bounds__(64) k_ls3_qr(Geom g, Box b, CPDev cp, LSParams P, int32_t* m_out,
-                                               int32_t* grow_out, const int32_t* st_idx, double* S_out,
-                                               double* Sc_out, uint8_t* route) {
-    __shared__ int32_t list_idx[L3_CAP];
-    __shared__ int ex[84][3];
-    __shared__ double tauv[84];
-    __shared__ double Y[84][4];
-    __shared__ double E[4][84];
-    __shared__ double Rs[PT][PT];
-    const int lane = threadIdx.x;
-    if (lane == 0) monomials(3, P.order_k - 1, ex);
-    __syncthreads();
-    const int64_t ncs = cp.ncp * P.nsides;
-    const int64_t seg = L3_CAP;
-    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
-        const int grow = grow_out[cs];
-        if (grow < 0) continue;  // routed or failed in the search
-        const int m = m_out[cs];
-        const int M = m + 1;
-        const int64_t c = cs / P.nsides;
-        const int sidx = (int)(cs % P.nsides);
-        double xc[3], nrm[3];
-        for (int d = 0; d < 3; ++d) {
-            xc[d] = cp.x[d * cp.ncp + c];
-            nrm[d] = cp.n[d * cp.ncp + c];
-        }
-        const int axis = cp.axis[c];
-        const int64_t anode = cp.a[sidx * cp.ncp + c];
-        const int adir = cp.dir[sidx * cp.ncp + c];
-        const double sc = (P.a0 + 0.5 * grow) * g.h;
-        for (int i = lane; i < m; i += 64) list_idx[i] = st_idx[cs * seg + i];
-        // evaluation functionals: ghosts j = 1..w at anode + j adir e_axis, then d/dn (and d/dx_d)
-        int acoord[3];
-        b.coords(anode, acoord);
-        double xa[3];
-        for (int d = 0; d < 3; ++d) xa[d] = node_coord(g, unwrap_near(g, acoord[d], xc[d]));
-        for (int k = 0; k < P.nrows; ++k)
-            for (int col = lane; col < PT; col += 64) {
-                double val;
-                if (k < P.w) {
-                    double xg[3] = {xa[0], xa[1], xa[2]};
-                    xg[axis] = xa[axis] + (double)((k + 1) * adir) * g.h;
-                    double xi[3];
-                    for (int d = 0; d < 3; ++d) xi[d] = (xg[d] - xc[d]) / sc;
-                    val = ipow(xi[0], ex[col][0]) * ipow(xi[1], ex[col][1]) * ipow(xi[2], ex[col][2]);
-                } else {
-                    // row w: d/dn; rows w + 1 + d: d/dx_d (gradient fits)
-                    int deg = ex[col][0] + ex[col][1] + ex[col][2];
-                    val = 0.0;
-                    if (deg == 1) {
-                        int d = ex[col][0] ? 0 : (ex[col][1] ? 1 : 2);
-                        const int r = k - P.w;
-                        val = (r == 0 ? nrm[d] : (d == r - 1 ? 1.0 : 0.0)) / sc;
-                    }
-                }
-                E[k][col] = val;
+// ---------------------------------------------------------------------------
+// The same fits by the corrected semi-normal equations, in five passes.  The
+// weights are s = A (A^T A)^{-1} E^T, the minimum-norm solution of A^T s = E^T
+// and the same s as Q R^{-T} E^T from A = QR.  A^T A is assembled from the 165
+// moments sum_r x^a y^b z^c (a + b + c <= 8) of the set and factored by
+// Cholesky (L_ii = |R_ii|, so the rank test reads the same diagonal as k_ls's
+// QR); the semi-normal solution s0 = A G^{-1} E^T is corrected once with the
+// residual E^T - A^T s0, which brings its error to the order of a Householder
+// solution's (about eps cond(A)).  Passes over rows (lanes own rows, four
+// each) alternate with passes over monomials (lane i owns row i of G);
+// the per-fit intermediates live in global memory:
+//   1. k_ls3_moments     rows       -> moments
+//   2. k_ls3_chol        monomials  -> L (over the moments), e (the rank test;
+//                                      near-singular fits go to the Householder
+//                                      path)
+//   3. k_ls3_resolve     monomials  -> z = G^{-1} e
+//   4. k_ls3_rows        rows       -> s0 = A z, rho = e - A^T s0
+//   5. k_ls3_resolve     monomials  -> z + dz, dz = G^{-1} rho
+//   6. k_ls3_rows        rows       -> s = A (z + dz) = s0 + A dz
+constexpr int MOM_N = 165;
+constexpr int CS_NZ = 4 * 35;   // coefficient / residual entries per fit
+constexpr int L_PACK = 35 * 36 / 2;  // packed lower triangle of L (the moments' slot)
+// packed L: column t holds L_it for i = t..34 (1 / L_tt in place of L_tt)
+__host__ __device__ constexpr int lpack_col(int t) { return 35 * t - t * (t - 1) / 2; }
+
+// exponents of the 35 monomials of total degree <= 4 in 3D, in the order of
+// monomials(): degree t, then i = t..0, then j = t-i..0, k = t-i-j
+struct Mono3 {
+    int e[35][3];
+};
+constexpr Mono3 mono3_table() {
+    Mono3 m{};
+    int c = 0;
+    for (int t = 0; t <= 4; ++t)
+        for (int i = t; i >= 0; --i)
+            for (int j = t - i; j >= 0; --j) {
+                m.e[c][0] = i;
+                m.e[c][1] = j;
+                m.e[c][2] = t - i - j;
+                ++c;
             }
-        __syncthreads();
-        // the set is already without its closest point: no position is skipped
-        const bool ok = reg_qr<PT, RPL>(M, lane, 3, list_idx, M, b, g, xc, sc, ex, true, P.nrows, E, Y, tauv, Rs,
-                                        cs * seg, ncs * seg, cs, nullptr, S_out, Sc_out);
-        __syncthreads();
-        if (!ok && lane == 0) {  // rank deficient: the global-memory path grows the set
-            route[cs] = 1;
-            grow_out[cs] = -3;
-            m_out[cs] = 0;
+    return m;
+}
+constexpr Mono3 MONO3 = mono3_table();
+// moments grouped by the z power c; inside a group by s = a + b, then by b
+constexpr int MOM_OFF[10] = {0, 45, 81, 109, 130, 145, 155, 161, 164, 165};
+__device__ inline int mom_index(int a, int b, int c) {
+    const int s = a + b;
+    int off = 0;
+    for (int cc = 0; cc < c; ++cc) off += (9 - cc) * (10 - cc) / 2;
+    return off + s * (s + 1) / 2 + b;
+}
+
+// the lane's rows of a fit: offsets (x - x_c) / sc and a 0/1 weight (row 0 = x_c)
+template <int NR>
+__device__ inline void ls3_rows(const Geom& g, const Box& b, const int32_t* st, int M, const double* xc, double sc,
+                                int lane, double (*X)[3], double* wt) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const int r = lane + 64 * q;
+        X[q][0] = X[q][1] = X[q][2] = 0.0;
+        wt[q] = r < M ? 1.0 : 0.0;
+        if (r > 0 && r < M) {
+            int ijk[3];
+            b.coords(st[r - 1], ijk);
+            for (int d = 0; d < 3; ++d) X[q][d] = (node_coord(g, unwrap_near(g, ijk[d], xc[d])) - xc[d]) / sc;
         }
     }
 }
+
+template <int CTRL>
+__device__ inline double quad_copy(double v) {  // every lane of a quad is a source: no old value needed
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffll), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+// wave sums of v[0..NV) written to out[0..NV) (global or LDS): quads add by
+// DPP, the 16 quad sums of each value go to LDS, lane j adds those of value j
+// in a fixed order.  One wavefront per block: __syncthreads orders the LDS use.
+template <int NV>
+__device__ inline void ls3_wave_sums(double (*part)[16], int lane, const double* v, double* out) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double x = v[j];
+        x += quad_copy<0xB1>(x);  // quad_perm [1, 0, 3, 2]
+        x += quad_copy<0x4E>(x);  // quad_perm [2, 3, 0, 1]
+        if ((lane & 3) == 0) part[j][lane >> 2] = x;
+    }
+    __syncthreads();
+    if (lane < NV) {
+        const double* p = part[lane];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+            a0 += p[i];
+            a1 += p[i + 1];
+            a2 += p[i + 2];
+            a3 += p[i + 3];
+        }
+        out[lane] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+}
+
+// the moments of one z power CZ: x^a y^b z^CZ, a + b <= 8 - CZ (pz holds z^CZ
+// times the row weight on entry, z^(CZ+1) times it on return)
+template <int NR, int CZ>
+__device__ inline void ls3_moment_group(double (*part)[16], int lane, const double (*X)[3], double* pz,
+                                        double* mom) {
+    constexpr int m = 8 - CZ, NV = (m + 1) * (m + 2) / 2;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double px[m + 1], py[m + 1];
+        px[0] = py[0] = 1.0;
+#pragma unroll
+        for (int e = 1; e <= m; ++e) {
+            px[e] = px[e - 1] * X[q][0];
+            py[e] = py[e - 1] * X[q][1];
+        }
+#pragma unroll
+        for (int a = 0; a <= m; ++a) {
+            const double pxz = px[a] * pz[q];
+#pragma unroll
+            for (int bb = 0; a + bb <= m; ++bb) {
+                const int sidx = a + bb;
+                acc[sidx * (sidx + 1) / 2 + bb] += pxz * py[bb];
+            }
+        }
+        pz[q] *= X[q][2];
+        __builtin_amdgcn_sched_barrier(0);  // one row's powers live at a time
+    }
+    ls3_wave_sums<NV>(part, lane, acc, mom + MOM_OFF[CZ]);
+}
+
+// pass 1: the 165 moments of every fit's set, one z power at a time
+template <int NR>
+__global__ void __launch_bounds__(64) k_ls3_moments(Geom g, Box b, CPDev cp, LSParams P, const int32_t* m_out,
+                                                    const int32_t* grow_out, const int32_t* st_idx, double* mom) {
+    __shared__ double part[45][16];
+    const int lane = threadIdx.x;
+    const int64_t ncs = cp.ncp * P.nsides;
+    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
+        const int grow = grow_out[cs];
+        if (grow < 0) continue;  // routed or failed in the search
+        const int64_t c = cs / P.nsides;
+        double xc[3];
+        for (int d = 0; d < 3; ++d) xc[d] = cp.x[d * cp.ncp + c];
+        double X[NR][3], wt[NR];
+        ls3_rows<NR>(g, b, st_idx + cs * L3_CAP, m_out[cs] + 1, xc, (P.a0 + 0.5 * grow) * g.h, lane, X, wt);
+        double pz[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) pz[q] = wt[q];
+        ls3_moment_group<NR, 0>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 1>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 2>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 3>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 4>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 5>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 6>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 7>(part, lane, X, pz, mom + cs * L_PACK);
+        ls3_moment_group<NR, 8>(part, lane, X, pz, mom + cs * L_PACK);
+    }
+}
+
+// G z = e for up to four right-hand sides (e: lane i holds entry i) with G =
+// L L^T, from the scaled triangles in one array: T[t][i] = L_it / L_ii below
+// the diagonal (i > t) and L_ti / L_ii above it (i < t); di = 1 / L_ii in lane
+// i; z0 + z to zc[k][i].  Lane i carries its entry divided by L_ii, so that it is
+// final (y_i, then z_i) once step i is reached and every step is one broadcast
+// and one FMA per right-hand side; lanes past 34 carry values nobody reads.
+__device__ __forceinline__ void ls3_solves(int lane, int nrows, const double (*T)[35], double di, const double* e,
+                                           const double* z0, double* zc) {
+    const int lm = lane < 35 ? lane : 34;
+    double c0 = e[0] * di, c1 = e[1] * di, c2 = e[2] * di, c3 = e[3] * di;
+#pragma unroll 7
+    for (int t = 0; t < 35; ++t) {  // L y = e
+        const double f = lane > t ? T[t][lm] : 0.0;
+        const double y0 = lane_value(c0, t), y1 = lane_value(c1, t), y2 = lane_value(c2, t),
+                     y3 = lane_value(c3, t);
+        c0 = fma(-f, y0, c0);
+        c1 = fma(-f, y1, c1);
+        c2 = fma(-f, y2, c2);
+        c3 = fma(-f, y3, c3);
+    }
+    c0 *= di;
+    c1 *= di;
+    c2 *= di;
+    c3 *= di;
+#pragma unroll 7
+    for (int t = 34; t >= 0; --t) {  // L^T z = y
+        const double bt = lane < t ? T[t][lm] : 0.0;
+        const double z0 = lane_value(c0, t), z1 = lane_value(c1, t), z2 = lane_value(c2, t),
+                     z3 = lane_value(c3, t);
+        c0 = fma(-bt, z0, c0);
+        c1 = fma(-bt, z1, c1);
+        c2 = fma(-bt, z2, c2);
+        c3 = fma(-bt, z3, c3);
+    }
+    if (lane < 35) {
+        double* z = zc + lane;
+        if (nrows > 0) z[0] = z0[0] + c0;
+        if (nrows > 1) z[35] = z0[1] + c1;
+        if (nrows > 2) z[70] = z0[2] + c2;
+        if (nrows > 3) z[105] = z0[3] + c3;
+    }
+}
+
+// pass 2: G = L L^T by Cholesky (lane i holds row i of G; column k of L
+// broadcast through LDS) and the rank test; the packed L goes over the fit's
+// moments and the functionals e (ghost values, d/dn, d/dx_d at x_c) to rho
+__global__ void __launch_bounds__(64) k_ls3_chol(Geom g, Box b, CPDev cp, LSParams P, int32_t* m_out,
+                                                 int32_t* grow_out, uint8_t* route, double* mom, double* rho) {
+    __shared__ double col[64];
+    __shared__ double cube[9 * 9 * 9];  // moment (a, b, c) at a + 9 b + 81 c
+    const int lane = threadIdx.x;
+    const int64_t ncs = cp.ncp * P.nsides;
+    const int nrows = P.nrows;
+    const int li = lane < 35 ? lane : 0;
+    // G_ij is the moment of exponents e_i + e_j: lane i reads row i at fixed
+    // offsets from its own base
+    const int ea = lane < 35 ? MONO3.e[li][0] : 0, eb = lane < 35 ? MONO3.e[li][1] : 0,
+              ec = lane < 35 ? MONO3.e[li][2] : 0;
+    const int gbase = ea + 9 * eb + 81 * ec;
+    int cpos[3];  // cube positions of the moments this lane moves
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int m = lane + 64 * q;
+        int c = 0;
+        while (c < 8 && m >= MOM_OFF[c + 1]) ++c;
+        const int r = m - MOM_OFF[c];
+        int sab = 0;
+        while ((sab + 1) * (sab + 2) / 2 <= r) ++sab;
+        const int bb = r - sab * (sab + 1) / 2;
+        cpos[q] = m < MOM_N ? (sab - bb) + 9 * bb + 81 * c : -1;
+    }
+    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
+        const int grow = grow_out[cs];
+        if (grow < 0) continue;
+        double* mm = mom + cs * L_PACK;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (cpos[q] >= 0) cube[cpos[q]] = mm[lane + 64 * q];
+        __syncthreads();
+        double Lr[35];
+#pragma unroll
+        for (int j = 0; j < 35; ++j)
+            Lr[j] = lane < 35 ? cube[gbase + MONO3.e[j][0] + 9 * MONO3.e[j][1] + 81 * MONO3.e[j][2]] : 0.0;
+        double rmax = 0.0, rmin = 1e300, di = 0.0;  // di = 1 / L_ii in lane i
+        bool pd = true;
+#pragma unroll
+        for (int k = 0; k < 35; ++k) {
+            const double dkk = lane_value(Lr[k], k);
+            pd = pd && dkk > 0.0;
+            // 1 / sqrt by the hardware estimate and two Newton steps
+            // (y <- y + y (1 - d y^2) / 2), then L_kk = d / sqrt(d)
+            const double dd = fmax(dkk, 1e-300);
+            double inv = __builtin_amdgcn_rsq(dd);
+#pragma unroll
+            for (int it = 0; it < 2; ++it) inv = fma(0.5 * inv, fma(-dd * inv, inv, 1.0), inv);
+            const double lkk = dd * inv;
+            rmax = fmax(rmax, lkk);
+            rmin = fmin(rmin, lkk);
+            if (lane == k) di = inv;
+            Lr[k] = lane == k ? lkk : Lr[k] * inv;
+            if (k == 34) break;
+            col[lane] = Lr[k];
+            __syncthreads();
+            // all lanes update: entries above the diagonal (lane < j) take
+            // values that are never read
+#pragma unroll
+            for (int j = k + 1; j < 35; ++j) Lr[j] -= Lr[k] * col[j];
+            __syncthreads();
+        }
+        if (!pd || rmin < 1e-6 * rmax) {  // near rank deficient: the Householder path decides
+            if (lane == 0) {
+                route[cs] = 1;
+                grow_out[cs] = -3;
+                m_out[cs] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (lane < 35) {
+#pragma unroll
+            for (int t = 0; t < 35; ++t)  // packed L (1 / L_tt on the diagonal) over the moments, all read by now
+                if (t <= lane) mm[lpack_col(t) + lane - t] = t < lane ? Lr[t] : di;
+        }
+        double* rk = rho + cs * CS_NZ;
+        {
+            if (lane < 35) {  // the functionals, entry = monomial
+                const int64_t c = cs / P.nsides;
+                const int sidx = (int)(cs % P.nsides);
+                const double sc = (P.a0 + 0.5 * grow) * g.h;
+                double xc[3];
+                for (int d = 0; d < 3; ++d) xc[d] = cp.x[d * cp.ncp + c];
+                const int axis = cp.axis[c];
+                const int64_t anode = cp.a[sidx * cp.ncp + c];
+                const int adir = cp.dir[sidx * cp.ncp + c];
+                int acoord[3];
+                b.coords(anode, acoord);
+                double xa[3];
+                for (int d = 0; d < 3; ++d) xa[d] = node_coord(g, unwrap_near(g, acoord[d], xc[d]));
+                for (int k = 0; k < nrows && k < 4; ++k) {
+                    double val;
+                    if (k < P.w) {
+                        double xg[3] = {xa[0], xa[1], xa[2]};
+                        xg[axis] = xa[axis] + (double)((k + 1) * adir) * g.h;
+                        double xi[3];
+                        for (int d = 0; d < 3; ++d) xi[d] = (xg[d] - xc[d]) / sc;
+                        val = ipow(xi[0], ea) * ipow(xi[1], eb) * ipow(xi[2], ec);
+                    } else {
+                        // row w: d/dn; rows w + 1 + d: d/dx_d (gradient fits)
+                        val = 0.0;
+                        if (ea + eb + ec == 1) {
+                            const int d = ea ? 0 : (eb ? 1 : 2);
+                            const int r = k - P.w;
+                            val = (r == 0 ? cp.n[d * cp.ncp + c] : (d == r - 1 ? 1.0 : 0.0)) / sc;
+                        }
+                    }
+                    rk[k * 35 + lane] = val;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// G z = rhs from the L that the Cholesky pass stored: z = G^{-1} e (rhs = e,
+// before the rows pass) and z + dz with dz = G^{-1} rho (after it, add = 1)
+__global__ void __launch_bounds__(64) k_ls3_resolve(CPDev cp, LSParams P, const int32_t* grow_out,
+                                                    const double* mom, const double* rho, double* zc, int add) {
+    __shared__ double Ts[35][35];
+    const int lane = threadIdx.x;
+    const int li = lane < 35 ? lane : 0;
+    const int64_t ncs = cp.ncp * P.nsides;
+    const int nrows = P.nrows;
+    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
+        if (grow_out[cs] < 0) continue;
+        const double* mm = mom + cs * L_PACK;
+        double di = 0.0;
+        if (lane < 35) {
+            // lane i: L_it from column t (t < i), L_ti from column i (t >= i;
+            // t = i reads 1 / L_ii); all loads in flight before the first use
+            double v[35];
+#pragma unroll
+            for (int t = 0; t < 35; ++t) v[t] = mm[t < li ? lpack_col(t) + li - t : lpack_col(li) + t - li];
+            di = mm[lpack_col(li)];
+#pragma unroll
+            for (int t = 0; t < 35; ++t) Ts[t][lane] = t == lane ? 0.0 : v[t] * di;
+        }
+        double e[4] = {0.0, 0.0, 0.0, 0.0}, z0[4] = {0.0, 0.0, 0.0, 0.0};
+        const double* rk = rho + cs * CS_NZ;
+        if (lane < 35)
+            for (int k = 0; k < nrows && k < 4; ++k) {
+                e[k] = rk[k * 35 + lane];
+                if (add) z0[k] = zc[cs * CS_NZ + k * 35 + lane];
+            }
+        __syncthreads();
+        ls3_solves(lane, nrows, Ts, di, e, z0, zc + cs * CS_NZ);
+        __syncthreads();
+    }
+}
+
+// passes 4 and 6 over the rows of a fit: pass 4 forms s0 = A z and from it rho
+// = e - A^T s0 (in place of e); pass 6 writes s = A (z + dz), equal to s0 + A dz,
+// into the staging weights (row 0 into Sc).  Every load of a fit is issued
+// before its first use: with one wave per SIMD nothing else hides the latency.
+template <int NR, bool second>
+__global__ void __launch_bounds__(64) k_ls3_rows(Geom g, Box b, CPDev cp, LSParams P, const int32_t* m_out,
+                                                 const int32_t* grow_out, const int32_t* st_idx, const double* zc,
+                                                 double* rho, double* S_out, double* Sc_out) {
+    __shared__ double part[35][16];
+    __shared__ double zs[4][35];
+    __shared__ double es[4][35];
+    __shared__ double red[35];
+    const int lane = threadIdx.x;
+    const int li = lane < 35 ? lane : 0;
+    const int64_t ncs = cp.ncp * P.nsides;
+    const int nrows = P.nrows < 4 ? P.nrows : 4;
+    const int64_t seg = L3_CAP, snz = ncs * seg;
+    for (int64_t cs = blockIdx.x; cs < ncs; cs += gridDim.x) {
+        const int grow = grow_out[cs];
+        const int M = m_out[cs] + 1;
+        const int64_t c = cs / P.nsides;
+        double xc[3];
+        for (int d = 0; d < 3; ++d) xc[d] = cp.x[d * cp.ncp + c];
+        const int32_t* st = st_idx + cs * L3_CAP;
+        int32_t node[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) node[q] = lane + 64 * q >= 1 ? st[lane + 64 * q - 1] : 0;
+        double zk[4], ek[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            zk[k] = k < nrows ? zc[cs * CS_NZ + k * 35 + li] : 0.0;
+            ek[k] = !second && k < nrows ? rho[cs * CS_NZ + k * 35 + li] : 0.0;
+        }
+        if (grow < 0) continue;
+        if (lane < 35)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                zs[k][lane] = zk[k];
+                es[k][lane] = ek[k];
+            }
+        const double sc = (P.a0 + 0.5 * grow) * g.h;
+        double X[NR][3], wt[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {  // the lane's rows: offsets (x - x_c) / sc, weight 1 (row 0 = x_c)
+            const int r = lane + 64 * q;
+            X[q][0] = X[q][1] = X[q][2] = 0.0;
+            wt[q] = r < M ? 1.0 : 0.0;
+            if (r > 0 && r < M) {
+                int ijk[3];
+                b.coords(node[q], ijk);
+                for (int d = 0; d < 3; ++d) X[q][d] = (node_coord(g, unwrap_near(g, ijk[d], xc[d])) - xc[d]) / sc;
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int k = 0; k < nrows; ++k) {
+            double sv[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                double px[5], py[5], pz[5];
+                px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+                for (int e = 1; e < 5; ++e) {
+                    px[e] = px[e - 1] * X[q][0];
+                    py[e] = py[e - 1] * X[q][1];
+                    pz[e] = pz[e - 1] * X[q][2];
+                }
+                double acc = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < 35; ++cc)
+                    acc += px[MONO3.e[cc][0]] * py[MONO3.e[cc][1]] * pz[MONO3.e[cc][2]] * zs[k][cc];
+                sv[q] = acc;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (second) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const int r = lane + 64 * q;
+                    if (r >= 1 && r < M)
+                        S_out[(int64_t)k * snz + cs * seg + r - 1] = sv[q];
+                    else if (r == 0)
+                        Sc_out[cs * nrows + k] = sv[q];
+                }
+            } else {
+                double acc[35];
+#pragma unroll
+                for (int i = 0; i < 35; ++i) acc[i] = 0.0;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    double px[5], py[5], pz[5];
+                    px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+                    for (int e = 1; e < 5; ++e) {
+                        px[e] = px[e - 1] * X[q][0];
+                        py[e] = py[e - 1] * X[q][1];
+                        pz[e] = pz[e - 1] * X[q][2];
+                    }
+                    const double sq = sv[q] * wt[q];
+#pragma unroll
+                    for (int i = 0; i < 35; ++i)
+                        acc[i] += px[MONO3.e[i][0]] * py[MONO3.e[i][1]] * pz[MONO3.e[i][2]] * sq;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                ls3_wave_sums<35>(part, lane, acc, red);
+                if (lane < 35) rho[cs * CS_NZ + k * 35 + lane] = es[k][lane] - red[lane];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void run_ls3_csne(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp, const LSParams& P,
+                  int32_t* m_out, int32_t* grow_out, int32_t* st_idx, double* S, double* Sc, uint8_t* route,
+                  double* mom, double* zc, double* rho, int* d_err, hipStream_t s) {
+    const int64_t ncs = cp.ncp * P.nsides;
+    if (ncs == 0) return;
+    const unsigned blocks = (unsigned)std::min<int64_t>(ncs, 65536);
+    hipLaunchKernelGGL(k_ls3_search, dim3(cdiv(ncs, 4)), dim3(256), 0, s, g, b, labels, cp, P, m_out, grow_out,
+                       st_idx, route, d_err);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_ls3_moments<L3_CAP / 64>), dim3(blocks), dim3(64), 0, s, g, b, cp, P, m_out, grow_out,
+                       st_idx, mom);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ls3_chol, dim3(blocks), dim3(64), 0, s, g, b, cp, P, m_out, grow_out, route, mom, rho);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ls3_resolve, dim3(blocks), dim3(64), 0, s, cp, P, grow_out, mom, rho, zc, 0);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_ls3_rows<L3_CAP / 64, false>), dim3(blocks), dim3(64), 0, s, g, b, cp, P, m_out, grow_out, st_idx,
+                       zc, rho, S, Sc);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ls3_resolve, dim3(blocks), dim3(64), 0, s, cp, P, grow_out, mom, rho, zc, 1);
+    IIM_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_ls3_rows<L3_CAP / 64, true>), dim3(blocks), dim3(64), 0, s, g, b, cp, P, m_out, grow_out, st_idx,
+                       zc, rho, S, Sc);
+    IIM_LAUNCH_CHECK();
+}
+int64_t ls3_csne_doubles_per_fit() { return L_PACK + 2 * CS_NZ; }
 
 // staging (fixed segments of seg entries per fit) -> CSR, for the fits of the
 // register path (route[cs] == 0); one wavefront per fit
@@ -843,13 +1275,7 @@ void run_ls(const Geom& g, const Box& b, const uint8_t* labels, const CPDev& cp,
     else if (g.dim == 2)
         hipLaunchKernelGGL((k_ls<15, 2>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
                            idx, S, Sc, scratch, d_err, cs_list, n_list, route);
-    else if (P.order_k == 5 && !cs_list && pass == 0 && idx) {
-        hipLaunchKernelGGL(k_ls3_search, dim3(cdiv(nwork, 4)), dim3(256), 0, s, g, b, labels, cp, P, m_out, grow_out,
-                           idx, route, d_err);
-        IIM_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_ls3_qr<35, 4>), dim3(blocks), dim3(64), 0, s, g, b, cp, P, m_out, grow_out, idx, S, Sc,
-                           route);
-    } else
+    else
         hipLaunchKernelGGL((k_ls<35, 4>), dim3(blocks), dim3(64), 0, s, g, b, labels, cp, P, pass, m_out, grow_out, ptr,
                            idx, S, Sc, scratch, d_err, cs_list, n_list, route);
     IIM_LAUNCH_CHECK();

@@ -66,7 +66,13 @@ def test_bordered_solve_matches_oracle(name):
     uu = u.cpu().numpy()[O.unknowns]
     alpha = st["shift_alpha"]
     r = np.concatenate([b - L @ uu - alpha, [-uu.sum()]])
-    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(b), np.linalg.norm(r) / np.linalg.norm(b)
+    # the residual is taken with the oracle's operator: its Householder fits on
+    # the Neumann sphere lie up to 4.7e-13 (of the largest weight) from the
+    # least-squares weights computed in extended precision, the device's 3D fits
+    # (Cholesky of A^T A plus one correction) within 6e-14; an operator built
+    # from the latter leaves 1.1e-12 here while u agrees to 3e-13 (both measured
+    # on the CPU), so the bound is 3e-12 and u keeps 1e-12 below
+    assert np.linalg.norm(r) <= 3e-12 * np.linalg.norm(b), np.linalg.norm(r) / np.linalg.norm(b)
     ud, ad = S.direct_solve(O, b)
     # all-FP64, solved to its residual floor: u within 1e-12 of the bordered
     # direct solve, as for the non-singular cases
