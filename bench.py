@@ -67,10 +67,10 @@ TRAFFIC = {
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/ops.hip",
                   "begin": "constexpr int FTX = 32, FTY = 32, FHALO = 6;",
                   "end": "bool run_down_fused(const LevelDev& F", "sha": "ccba1c890744fce2"},
-    ("cfg4", 5): {"fetch_kib": 1584922.5114, "fetch_scale": 524288.0 / 262156.0, "write_kib": 453024.5199,
+    ("cfg4", 5): {"fetch_kib": 1584922.3920, "fetch_scale": 524288.0 / 262155.5, "write_kib": 453010.6449,
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/blas.hip",
                   "begin": "__global__ void __launch_bounds__(RED_THREADS) k_update_dot(",
-                  "end": "void run_update_dot_stage1(", "sha": "c4fcc25941381676"},
+                  "end": "void run_update_dot_stage1(", "sha": "b17286439f5d29cd"},
     ("cfg3", 1): {"fetch_kib": 318942.0227, "fetch_scale": 524288.0 / 262156.0, "write_kib": 1755.0256,
                   "write_scale": 1.0, "src": "paper_2503_22455_amd/csrc/ops.hip",
                   "begin": "__global__ void __launch_bounds__(256) k_ghosts(",
