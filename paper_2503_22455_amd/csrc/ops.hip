@@ -1182,43 +1182,86 @@ __global__ void __launch_bounds__(256) k_prolong(LevelDev F, LevelDev C, int mod
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Index offsets of a level vector for a reference node (i0, j0, k0) with i0, j0
+// and k0 even: the node (i0 + ox, j0 + oy, k0 + oz) sits at vidx(i0, j0, k0) +
+// voff_even(ox, oy, oz), the same offset for every such reference (its colour
+// is that of ox + oy + oz, and the half-index step along x is fixed by the
+// parity of lo_x).  boff: the same for the storage box.  Both take only
+// uniform values, so the per-load index arithmetic leaves the vector units.
+__device__ inline int64_t boff(const Box& b, int ox, int oy, int oz) {
+    return (int64_t)ox + (int64_t)b.dims[0] * ((int64_t)oy + (int64_t)b.dims[1] * oz);
+}
+__device__ inline int64_t voff_even(const LevelDev& L, int ox, int oy, int oz) {
+    if (!L.split) return boff(L.box, ox, oy, oz);
+    const int lx = L.box.lo[0];
+    return (int64_t)((ox + oy + oz) & 1) * L.half + ((int64_t)oy + (int64_t)L.box.dims[1] * oz) * L.hx +
+           (((ox - lx) >> 1) - ((-lx) >> 1));
+}
+
 // 3D prolongation by coarse cells: the thread of cell (I, J, K) loads the cell's
 // eight coarse corners once and corrects the fine nodes 2I + {0,1}, 2J + {0,1},
 // 2K + {0,1} (all inside the fine box).  Same parents, weights and summation
-// order as prolong_corr.  Every load is issued before the first test.
-template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, int mode, int I0, int J0, int K0,
-                                                        int nI, int nJ, const S* zc, S* z) {
-    const Blk3 B = xcd_block3((nI + 63) / 64, (nJ + 3) / 4);
-    const int I = I0 + B.x * 64 + (threadIdx.x & 63);
-    const int J = J0 + B.y * 4 + (threadIdx.x >> 6);
-    const int K = K0 + B.z;
-    if (I >= I0 + nI || J >= J0 + nJ) return;
+// order as prolong_corr.  Every load is issued before the first test.  A cell
+// whose far corner lies in the coarse box (INNER: no clamp or wrap) takes its
+// indices as per-lane bases plus uniform offsets.
+template <typename T, typename S, bool INNER>
+__device__ __forceinline__ void prolong_cell(const LevelDev& F, const LevelDev& C, int mode, int I, int J, int K,
+                                             const S* zc, S* z) {
     T v[2][2][2];
     uint8_t clab[2][2][2];
     bool inb[2][2][2];
+    // INNER: corner (I + a, J + bq, K + cq) at cb[a][colour flip] + its row step
+    int64_t cb[2][2] = {{0, 0}, {0, 0}}, clb = 0;
+    if (INNER) {
+        if (C.split) {
+            const int64_t row = ((int64_t)(J - C.box.lo[1]) + (int64_t)C.box.dims[1] * (K - C.box.lo[2])) * C.hx;
+            const int par = (I + J + K) & 1;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+                    cb[a][f] = (int64_t)(par ^ f) * C.half + row + ((I + a - C.box.lo[0]) >> 1);
+        } else {
+            cb[0][0] = cb[0][1] = C.box.idx(I, J, K);
+            cb[1][0] = cb[1][1] = cb[0][0] + 1;
+        }
+        clb = C.box.idx(I, J, K);
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int bq = 0; bq < 2; ++bq)
 #pragma unroll
             for (int cq = 0; cq < 2; ++cq) {
-                const int P[3] = {I + a, J + bq, K + cq};
-                int Q[3];
-                bool in = true;
+                int64_t ci, li;
+                if (INNER) {
+                    const int64_t rstep = C.split ? ((int64_t)bq + (int64_t)C.box.dims[1] * cq) * C.hx
+                                                  : boff(C.box, 0, bq, cq);
+                    ci = cb[a][(a + bq + cq) & 1] + rstep;
+                    li = clb + boff(C.box, a, bq, cq);
+                    inb[a][bq][cq] = true;
+                } else {
+                    const int P[3] = {I + a, J + bq, K + cq};
+                    int Q[3];
+                    bool in = true;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    if (C.periodic) {  // coarse parent n_c is the image of 0
-                        Q[d] = wrap_near(P[d], C.n);
-                    } else {
-                        in = in && P[d] >= C.box.lo[d] && P[d] < C.box.lo[d] + C.box.dims[d];
-                        Q[d] = clampi(P[d], C.box.lo[d], C.box.lo[d] + C.box.dims[d] - 1);
+                    for (int d = 0; d < 3; ++d) {
+                        if (C.periodic) {  // coarse parent n_c is the image of 0
+                            Q[d] = wrap_near(P[d], C.n);
+                        } else {
+                            in = in && P[d] >= C.box.lo[d] && P[d] < C.box.lo[d] + C.box.dims[d];
+                            Q[d] = clampi(P[d], C.box.lo[d], C.box.lo[d] + C.box.dims[d] - 1);
+                        }
                     }
+                    inb[a][bq][cq] = in;
+                    ci = vidx(C, Q[0], Q[1], Q[2]);
+                    li = C.box.idx(Q[0], Q[1], Q[2]);
                 }
-                inb[a][bq][cq] = in;
-                v[a][bq][cq] = load_it<T, S>(zc, vidx(C, Q[0], Q[1], Q[2]));
-                clab[a][bq][cq] = mode == 1 ? C.labels[C.box.idx(Q[0], Q[1], Q[2])] : (uint8_t)0;
+                v[a][bq][cq] = load_it<T, S>(zc, ci);
+                clab[a][bq][cq] = mode == 1 ? C.labels[li] : (uint8_t)0;
             }
+    // the fine nodes: 2I, 2J, 2K are even
+    const int64_t fb0 = vidx(F, 2 * I, 2 * J, 2 * K), fl0 = F.box.idx(2 * I, 2 * J, 2 * K);
     uint8_t flab[2][2][2];
     T fz[2][2][2];
 #pragma unroll
@@ -1227,9 +1270,8 @@ __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, i
         for (int fb = 0; fb < 2; ++fb)
 #pragma unroll
             for (int fa = 0; fa < 2; ++fa) {
-                const int i = 2 * I + fa, j = 2 * J + fb, k = 2 * K + fc;
-                flab[fa][fb][fc] = F.labels[F.box.idx(i, j, k)];
-                fz[fa][fb][fc] = load_it<T, S>(z, vidx(F, i, j, k));
+                flab[fa][fb][fc] = F.labels[fl0 + boff(F.box, fa, fb, fc)];
+                fz[fa][fb][fc] = load_it<T, S>(z, fb0 + voff_even(F, fa, fb, fc));
             }
     asm volatile("" ::"v"(v[0][0][0]), "v"(v[1][1][1]), "v"(fz[0][0][0]), "v"(fz[1][1][1]));
     bool use[2][2][2];
@@ -1269,8 +1311,26 @@ __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, i
                             }
                         }
                 if (cnt == 0) continue;
-                store_t<T, S>(z, vidx(F, i, j, k), fz[fa][fb][fc] + sum / (T)cnt);
+                store_t<T, S>(z, fb0 + voff_even(F, fa, fb, fc), fz[fa][fb][fc] + sum / (T)cnt);
             }
+}
+
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, int mode, int I0, int J0, int K0,
+                                                        int nI, int nJ, const S* zc, S* z) {
+    const Blk3 B = xcd_block3((nI + 63) / 64, (nJ + 3) / 4);
+    const int I = I0 + B.x * 64 + (threadIdx.x & 63);
+    const int J = J0 + B.y * 4 + (threadIdx.x >> 6);
+    const int K = K0 + B.z;
+    if (I >= I0 + nI || J >= J0 + nJ) return;
+    const int P[3] = {I, J, K};
+    bool inner = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) inner = inner && P[d] >= C.box.lo[d] && P[d] + 1 < C.box.lo[d] + C.box.dims[d];
+    if (inner)
+        prolong_cell<T, S, true>(F, C, mode, I, J, K, zc, z);
+    else
+        prolong_cell<T, S, false>(F, C, mode, I, J, K, zc, z);
 }
 
 // 3D residual + restriction: the thread of coarse node (I, J, K) evaluates the
@@ -1279,23 +1339,29 @@ __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, i
 // are clamped into the fine box; a clamped value is only ever used by a node
 // that is not an unknown (an unknown's neighbours lie in the box), whose
 // residual is zero.  Same weights and summation order as restrict_node.
-template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int gx, int gy, const S* z, const T* b,
-                                                    T* bc, S* zc0) {
-    const Blk3 B = xcd_block3(gx, gy);
-    const int I = C.core_lo[0] + B.x * 64 + (threadIdx.x & 63);
-    const int J = C.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
-    const int K = C.core_lo[2] + B.z;
-    if (I > C.core_hi[0] || J > C.core_hi[1] || K > C.core_hi[2]) return;
+// INNER: c +- 2 lies in the fine box on every axis (no clamp or wrap), and the
+// indices are per-lane bases plus uniform offsets.
+template <typename T, typename S, bool INNER>
+__device__ __forceinline__ void restrict3_node(const LevelDev& F, const LevelDev& C, int I, int J, int K, const S* z,
+                                               const T* b, T* bc, S* zc0) {
     const int c[3] = {2 * I, 2 * J, 2 * K};
-    int X[3][5];  // clamped coordinates c[d] - 2 .. c[d] + 2
+    int X[3][5];  // clamped coordinates c[d] - 2 .. c[d] + 2 (not INNER)
+    int64_t vb = 0, lb = 0;
+    if (INNER) {
+        vb = vidx(F, c[0], c[1], c[2]);
+        lb = F.box.idx(c[0], c[1], c[2]);
+    } else {
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int o = 0; o < 5; ++o)
-            X[d][o] = F.periodic ? wrap_near(c[d] + o - 2, F.n)  // the box is the cell
-                                 : clampi(c[d] + o - 2, F.box.lo[d], F.box.lo[d] + F.box.dims[d] - 1);
-    auto zat = [&](int ox, int oy, int oz) { return load_it<T, S>(z, vidx(F, X[0][ox + 2], X[1][oy + 2], X[2][oz + 2])); };
+            for (int o = 0; o < 5; ++o)
+                X[d][o] = F.periodic ? wrap_near(c[d] + o - 2, F.n)  // the box is the cell
+                                     : clampi(c[d] + o - 2, F.box.lo[d], F.box.lo[d] + F.box.dims[d] - 1);
+    }
+    auto vat = [&](int ox, int oy, int oz) -> int64_t {
+        return INNER ? vb + voff_even(F, ox, oy, oz) : vidx(F, X[0][ox + 2], X[1][oy + 2], X[2][oz + 2]);
+    };
+    auto zat = [&](int ox, int oy, int oz) { return load_it<T, S>(z, vat(ox, oy, oz)); };
     // the seven residual nodes: 0 = c, 1 + 2d = c + e_d, 2 + 2d = c - e_d
     const int off[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
     const uint8_t labc = C.labels[C.box.idx(I, J, K)];
@@ -1305,10 +1371,10 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
 #pragma unroll
     for (int n = 0; n < 7; ++n) {
         const int ox = off[n][0], oy = off[n][1], oz = off[n][2];
-        const int xi = X[0][ox + 2], yi = X[1][oy + 2], zi = X[2][oz + 2];
-        lbox[n] = (int)F.box.idx(xi, yi, zi);
+        lbox[n] = INNER ? (int)(lb + boff(F.box, ox, oy, oz))
+                        : (int)F.box.idx(X[0][ox + 2], X[1][oy + 2], X[2][oz + 2]);
         lab[n] = F.labels[lbox[n]];
-        bv[n] = b[vidx(F, xi, yi, zi)];
+        bv[n] = b[vat(ox, oy, oz)];
         zc[n] = zat(ox, oy, oz);
         zm[n][0] = zat(ox - 1, oy, oz);
         zp[n][0] = zat(ox + 1, oy, oz);
@@ -1322,7 +1388,7 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
     bool inside = is_unknown(labc);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        inside = inside && (F.periodic || (c[d] - 1 >= F.box.lo[d] && c[d] + 1 < F.box.lo[d] + F.box.dims[d]));
+        inside = inside && (INNER || F.periodic || (c[d] - 1 >= F.box.lo[d] && c[d] + 1 < F.box.lo[d] + F.box.dims[d]));
     if (!inside) {
         bc[vc] = (T)0;
         if (zc0) store_t<T, S>(zc0, vc, (T)0);
@@ -1354,6 +1420,24 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
         }
         store_t<T, S>(zc0, vc, zv);
     }
+}
+
+template <typename T, typename S>
+__global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int gx, int gy, const S* z, const T* b,
+                                                    T* bc, S* zc0) {
+    const Blk3 B = xcd_block3(gx, gy);
+    const int I = C.core_lo[0] + B.x * 64 + (threadIdx.x & 63);
+    const int J = C.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
+    const int K = C.core_lo[2] + B.z;
+    if (I > C.core_hi[0] || J > C.core_hi[1] || K > C.core_hi[2]) return;
+    const int c[3] = {2 * I, 2 * J, 2 * K};
+    bool inner = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) inner = inner && c[d] - 2 >= F.box.lo[d] && c[d] + 2 < F.box.lo[d] + F.box.dims[d];
+    if (inner)
+        restrict3_node<T, S, true>(F, C, I, J, K, z, b, bc, zc0);
+    else
+        restrict3_node<T, S, false>(F, C, I, J, K, z, b, bc, zc0);
 }
 
 // The first steps of the level-0 pre-smoothing of a colour-split level in one
