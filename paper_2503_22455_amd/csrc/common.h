@@ -253,41 +253,48 @@ __device__ inline double gyroid_curvature(const double* p, const double* x) {
 }
 
 // sign of phi (-1 inside the body, 0 on Gamma, +1 outside)
-__device__ inline int geom_sign(const Geom& g, const double* x) {
-    if (g.kind == IIM_GEOM_SPHERE) return sphere_sign(g.p, g.p[g.dim], g.dim, x);
-    if (g.kind == IIM_GEOM_GYROID) return sgn(gyroid_phi(g.p, x));
-    if (g.kind == IIM_GEOM_STAR2D) return sgn(star_phi(g.p, x[0], x[1]));
-    int cnt = (int)llround(g.p[0]);
+// sign of the level set at x for a DIM known at compile time; p: the
+// parameters (g.p, or a copy of them staged by the caller)
+template <int DIM>
+__device__ inline int geom_sign_d(const Geom& g, const double* p, const double* x) {
+    if (g.kind == IIM_GEOM_SPHERE) return sphere_sign(p, p[DIM], DIM, x);
+    if (g.kind == IIM_GEOM_GYROID) return sgn(gyroid_phi(p, x));
+    if (g.kind == IIM_GEOM_STAR2D) return sgn(star_phi(p, x[0], x[1]));
+    int cnt = (int)llround(p[0]);
     bool on = false;
     for (int s = 0; s < cnt; ++s) {
-        const double* q = g.p + 1 + (g.dim + 1) * s;
-        int v = sphere_sign(q, q[g.dim], g.dim, x);
+        const double* q = p + 1 + (DIM + 1) * s;
+        int v = sphere_sign(q, q[DIM], DIM, x);
         if (v < 0) return -1;
         if (v == 0) on = true;
     }
     return on ? 0 : 1;
 }
+__device__ inline int geom_sign(const Geom& g, const double* x) {
+    return g.dim == 3 ? geom_sign_d<3>(g, g.p, x) : geom_sign_d<2>(g, g.p, x);
+}
 
 // kind of a node of the level (box faces included), or 255 = rejected
-__device__ inline uint8_t node_kind(const Geom& g, const int* ijk) {
+template <int DIM>
+__device__ inline uint8_t node_kind_d(const Geom& g, const double* p, const int* ijk) {
     double x[3] = {0.0, 0.0, 0.0};
     bool face = false;
     if (g.periodic) {
         // no box faces; the image planes (index n) hold no unknowns
-        for (int d = 0; d < g.dim; ++d) {
+        for (int d = 0; d < DIM; ++d) {
             if (ijk[d] >= g.n) return K_INACTIVE;
             x[d] = node_coord(g, ijk[d]);
         }
-        const int s = geom_sign(g, x);
+        const int s = geom_sign_d<DIM>(g, p, x);
         if (g.side == IIM_SIDE_INTERIOR) return s < 0 ? K_PLUS : K_INACTIVE;
         if (g.side == IIM_SIDE_EXTERIOR) return s > 0 ? K_PLUS : K_INACTIVE;
         return s <= 0 ? K_MINUS : K_PLUS;
     }
-    for (int d = 0; d < g.dim; ++d) {
+    for (int d = 0; d < DIM; ++d) {
         x[d] = node_coord(g, ijk[d]);
         if (ijk[d] == 0 || ijk[d] == g.n) face = true;
     }
-    int s = geom_sign(g, x);
+    int s = geom_sign_d<DIM>(g, p, x);
     if (face) {
         if (s <= 0) return 255;  // body touches the box
         return g.side == IIM_SIDE_INTERIOR ? K_INACTIVE : K_BOX;

@@ -12,18 +12,39 @@ namespace iim {
 // Pass 1, one launch for every level (blockIdx.y = level): each block
 // classifies a grid-stride share of the level's nodes and writes its partial
 // {min x,y,z, max x,y,z, touches-the-box flag, unknown count} to part.
-__global__ void __launch_bounds__(256) k_classify_levels(GeomSet G, int* part) {
-    __shared__ int sh[8][256];
-    const Geom& g = G.g[blockIdx.y];
+// The two kernels below evaluate the level set at every node of a level, with
+// the dimension as a template parameter (a runtime dimension turned every
+// coordinate into a chain of selects) and a linear index below 2^31 split by
+// 32-bit division (cfg-4 setup 27.9 -> 25.4 ms).  The parameters stay in
+// global memory: read through the scalar cache they are free operands, and a
+// copy in LDS made both kernels slower.
+// node (i, j, k) of linear index l in an n1 x n1 (x n1) grid or a box
+__device__ inline void split_index(int64_t l, int64_t d0, int64_t d1, bool narrow, int* ijk) {
+    if (narrow) {
+        const uint32_t l32 = (uint32_t)l, a = (uint32_t)d0, b = (uint32_t)d1;
+        const uint32_t q = l32 / a;
+        ijk[0] = (int)(l32 - q * a);
+        ijk[1] = (int)(q % b);
+        ijk[2] = (int)(q / b);
+    } else {
+        const int64_t q = l / d0;
+        ijk[0] = (int)(l - q * d0);
+        ijk[1] = (int)(q % d1);
+        ijk[2] = (int)(q / d1);
+    }
+}
+
+template <int DIM>
+__device__ inline void classify_share(const Geom& g, const double* gp, int* mn, int* mx, int& cnt, int& bad) {
     const int64_t n1 = g.n + 1;
-    const int64_t total = g.dim == 2 ? n1 * n1 : n1 * n1 * n1;
-    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-    int cnt = 0, bad = 0;
+    const int64_t total = DIM == 2 ? n1 * n1 : n1 * n1 * n1;
+    const bool narrow = total < ((int64_t)1 << 31);
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = l / n1;
-        int ijk[3] = {(int)(l - q * n1), (int)(q % n1), g.dim == 3 ? (int)(q / n1) : 0};
-        const uint8_t k = node_kind(g, ijk);
+        int ijk[3];
+        split_index(l, n1, n1, narrow, ijk);
+        if (DIM == 2) ijk[2] = 0;
+        const uint8_t k = node_kind_d<DIM>(g, gp, ijk);
         if (k == 255) {
             bad = 1;
             continue;
@@ -36,6 +57,18 @@ __global__ void __launch_bounds__(256) k_classify_levels(GeomSet G, int* part) {
             ++cnt;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_classify_levels(GeomSet G, int* part) {
+    __shared__ int sh[8][256];
+    const Geom& g = G.g[blockIdx.y];
+    const double* gp = g.p;
+    int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    int cnt = 0, bad = 0;
+    if (g.dim == 3)
+        classify_share<3>(g, gp, mn, mx, cnt, bad);
+    else
+        classify_share<2>(g, gp, mn, mx, cnt, bad);
     const int t = threadIdx.x;
     for (int d = 0; d < 3; ++d) {
         sh[d][t] = mn[d];
@@ -103,20 +136,29 @@ void run_classify_levels(const GeomSet& G, int nl, int* d_part, int* d_bbox, uns
     IIM_LAUNCH_CHECK();
 }
 
-__global__ void k_box_labels(LevelSet S) {
-    const Geom& g = S.g[blockIdx.y];
-    const Box& b = S.b[blockIdx.y];
-    uint8_t* labels = S.labels[blockIdx.y];
-    int64_t total = b.size();
+template <int DIM>
+__device__ inline void box_labels_share(const Geom& g, const double* gp, const Box& b, uint8_t* labels) {
+    const int64_t total = b.size();
+    const bool narrow = total < ((int64_t)1 << 31);
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
          l += (int64_t)gridDim.x * blockDim.x) {
         int ijk[3];
-        b.coords(l, ijk);
+        split_index(l, b.dims[0], b.dims[1], narrow, ijk);
+        for (int d = 0; d < 3; ++d) ijk[d] += b.lo[d];
         bool in = true;
-        for (int d = 0; d < g.dim; ++d) in = in && ijk[d] >= 0 && ijk[d] <= g.n;
-        uint8_t k = in ? node_kind(g, ijk) : K_INACTIVE;
+        for (int d = 0; d < DIM; ++d) in = in && ijk[d] >= 0 && ijk[d] <= g.n;
+        uint8_t k = in ? node_kind_d<DIM>(g, gp, ijk) : K_INACTIVE;
         labels[l] = (k == 255) ? K_INACTIVE : k;
     }
+}
+
+__global__ void __launch_bounds__(256) k_box_labels(LevelSet S) {
+    const Geom& g = S.g[blockIdx.y];
+    const double* gp = g.p;
+    if (g.dim == 3)
+        box_labels_share<3>(g, gp, S.b[blockIdx.y], S.labels[blockIdx.y]);
+    else
+        box_labels_share<2>(g, gp, S.b[blockIdx.y], S.labels[blockIdx.y]);
 }
 
 void run_box_labels(const LevelSet& S, int nl, hipStream_t s) {
