@@ -58,6 +58,14 @@ struct Box {
         return d == 0 ? 1 : (d == 1 ? (int64_t)dims[0] : (int64_t)dims[0] * dims[1]);
     }
     __host__ __device__ void coords(int64_t l, int* ijk) const {
+        if (l >= 0 && l <= 0x7fffffff) {  // 32-bit division: a fraction of the 64-bit sequence
+            const uint32_t u = (uint32_t)l, d0 = (uint32_t)dims[0], d1 = (uint32_t)dims[1];
+            const uint32_t r = u / d0;
+            ijk[0] = (int)(u - r * d0) + lo[0];
+            ijk[1] = (int)(r % d1) + lo[1];
+            ijk[2] = (int)(r / d1) + lo[2];
+            return;
+        }
         ijk[0] = (int)(l % dims[0]) + lo[0];
         int64_t r = l / dims[0];
         ijk[1] = (int)(r % dims[1]) + lo[1];

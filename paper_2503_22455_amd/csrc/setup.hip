@@ -625,7 +625,8 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* A, double* X, in
     __shared__ int red_i[1024];
     __shared__ int piv_s;
     int tid = threadIdx.x;
-    for (int64_t i = tid; i < nc * nc; i += blockDim.x) X[i] = ((i / nc) == (i % nc)) ? 1.0 : 0.0;
+    for (int64_t r = tid >> 6; r < nc; r += blockDim.x >> 6)
+        for (int64_t c = tid & 63; c < nc; c += 64) X[r * nc + c] = r == c ? 1.0 : 0.0;
     __syncthreads();
     for (int64_t k = 0; k < nc; ++k) {
         double best = -1.0;
@@ -676,13 +677,15 @@ __global__ void __launch_bounds__(1024) k_coarse_invert(double* A, double* X, in
             X[k * nc + c] *= inv;
         }
         __syncthreads();
-        for (int64_t i = tid; i < nc * nc; i += blockDim.x) {
-            int64_t r = i / nc, c = i % nc;
+        // rows over wavefronts, columns over lanes (no index division per entry)
+        for (int64_t r = tid >> 6; r < nc; r += blockDim.x >> 6) {
             if (r == k) continue;
-            double f = A[r * nc + k];
-            if (c == k) continue;  // column k of A updated last
-            A[r * nc + c] -= f * A[k * nc + c];
-            X[r * nc + c] -= f * X[k * nc + c];
+            const double f = A[r * nc + k];
+            for (int64_t c = tid & 63; c < nc; c += 64) {
+                if (c == k) continue;  // column k of A updated last
+                A[r * nc + c] -= f * A[k * nc + c];
+                X[r * nc + c] -= f * X[k * nc + c];
+            }
         }
         __syncthreads();
         for (int64_t r = tid; r < nc; r += blockDim.x) {
@@ -757,12 +760,14 @@ __global__ void __launch_bounds__(1024) k_coarse_invert_lds(double* Ag, double* 
             X[k * nc + c] *= inv;
         }
         __syncthreads();
-        for (int i = tid; i < n2; i += blockDim.x) {
-            const int r = i / nc, c = i - r * nc;
-            if (r == k || c == k) continue;  // column k of A updated last
+        for (int r = tid >> 6; r < nc; r += blockDim.x >> 6) {
+            if (r == k) continue;
             const double f = A[r * nc + k];
-            A[r * nc + c] -= f * A[k * nc + c];
-            X[r * nc + c] -= f * X[k * nc + c];
+            for (int c = tid & 63; c < nc; c += 64) {
+                if (c == k) continue;  // column k of A updated last
+                A[r * nc + c] -= f * A[k * nc + c];
+                X[r * nc + c] -= f * X[k * nc + c];
+            }
         }
         __syncthreads();
         for (int r = tid; r < nc; r += blockDim.x) {
