@@ -210,6 +210,7 @@ void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, uint8_t* f
 // flagged selections, several at once, in three launches: per-block counts,
 // one scan per selection, an ordered scatter (ballot prefix within wavefronts)
 // ---------------------------------------------------------------------------
+constexpr int SEL_TILE = 16;
 __device__ inline void sel_chunk(int64_t n, int b, int64_t* lo, int64_t* hi) {
     const int64_t c = (n + SEL_BLOCKS - 1) / SEL_BLOCKS;
     *lo = min(n, (int64_t)b * c);
@@ -221,8 +222,15 @@ __global__ void __launch_bounds__(256) k_sel_count(SelSet S, int* part) {
     const SelItem& it = S.it[blockIdx.y];
     int64_t lo, hi;
     sel_chunk(it.n, blockIdx.x, &lo, &hi);
+    // SEL_TILE consecutive flags per thread and step, their loads independent
     int c = 0;
-    for (int64_t l = lo + threadIdx.x; l < hi; l += blockDim.x) c += it.flags[l] != 0;
+    for (int64_t l0 = lo + SEL_TILE * (int64_t)threadIdx.x; l0 < hi; l0 += SEL_TILE * (int64_t)blockDim.x) {
+        uint8_t v[SEL_TILE];
+#pragma unroll
+        for (int j = 0; j < SEL_TILE; ++j) v[j] = l0 + j < hi ? it.flags[l0 + j] : 0;
+#pragma unroll
+        for (int j = 0; j < SEL_TILE; ++j) c += v[j] != 0;
+    }
     const int t = threadIdx.x;
     sh[t] = c;
     __syncthreads();
@@ -250,6 +258,10 @@ __global__ void __launch_bounds__(SEL_BLOCKS) k_sel_scan(SelSet S, int* part) {
     if (t == SEL_BLOCKS - 1) *S.it[blockIdx.x].count = sh[t];
 }
 
+// the block's steps cover 256 x SEL_TILE consecutive flags: thread t takes
+// the SEL_TILE flags from t0 + SEL_TILE t on and writes its selected indices
+// after those of the threads before it (an exclusive scan of the per-thread
+// counts), so the output keeps increasing index order
 __global__ void __launch_bounds__(256) k_sel_scatter(SelSet S, const int* part) {
     __shared__ int wsum[4];
     const SelItem& it = S.it[blockIdx.y];
@@ -257,17 +269,29 @@ __global__ void __launch_bounds__(256) k_sel_scatter(SelSet S, const int* part) 
     sel_chunk(it.n, blockIdx.x, &lo, &hi);
     int base = part[blockIdx.y * SEL_BLOCKS + blockIdx.x];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int64_t t0 = lo; t0 < hi; t0 += 256) {
-        const int64_t l = t0 + t;
-        const bool f = l < hi && it.flags[l] != 0;
-        const uint64_t m = __ballot(f);
-        const int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wsum[w] = __popcll(m);
+    for (int64_t t0 = lo; t0 < hi; t0 += SEL_TILE * 256) {
+        const int64_t l0 = t0 + SEL_TILE * (int64_t)t;
+        uint8_t v[SEL_TILE];
+#pragma unroll
+        for (int j = 0; j < SEL_TILE; ++j) v[j] = l0 + j < hi ? it.flags[l0 + j] : 0;
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < SEL_TILE; ++j) cnt += v[j] != 0;
+        int inc = cnt;  // inclusive scan over the wavefront
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
         __syncthreads();
         int off = 0;
         for (int q = 0; q < w; ++q) off += wsum[q];
         const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        if (f) it.out[base + off + pre] = (int32_t)l;
+        int pos = base + off + inc - cnt;
+#pragma unroll
+        for (int j = 0; j < SEL_TILE; ++j)
+            if (v[j]) it.out[pos++] = (int32_t)(l0 + j);
         base += tot;
         __syncthreads();
     }
