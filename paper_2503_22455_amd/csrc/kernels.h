@@ -34,7 +34,7 @@ void run_cp_flags(const Geom& g, const Box& b, const uint8_t* labels, uint8_t* f
 // Flagged selections: out = indices (0..n-1) of the nonzero flags in increasing
 // order, *count = their number; up to SEL_MAX selections in three launches,
 // stream ordered, no host wait; d_part: SEL_BLOCKS * k ints of scratch.
-constexpr int SEL_MAX = 20, SEL_BLOCKS = 256;
+constexpr int SEL_MAX = 20, SEL_BLOCKS = 1024;
 struct SelItem {
     const uint8_t* flags;
     int64_t n;

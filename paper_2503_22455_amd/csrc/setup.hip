@@ -393,6 +393,26 @@ __device__ inline uint8_t kind_at(const Geom& g, const Box& b, const uint8_t* la
     return labels[*l] & KIND_MASK;
 }
 
+// true if a node of kind k at l (coordinates ijk) sees, within w nodes along
+// an axis, a node of another kind or the edge of the box or grid (as kind_at,
+// with the neighbour's index stepped from l along the axis)
+template <int DIM>
+__device__ inline bool ho_irregular_node(const Geom& g, const Box& b, const uint8_t* labels, int64_t l,
+                                         const int* ijk, uint8_t k, int w) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const int64_t st = b.stride(d);
+        for (int s = -w; s <= w; ++s) {
+            if (s == 0) continue;
+            int c = ijk[d] + s;
+            if (g.periodic) c = wrap_index(c, g.n);
+            if (c < 0 || c > g.n || c < b.lo[d] || c >= b.lo[d] + b.dims[d]) return true;
+            if ((labels[l + (int64_t)(c - ijk[d]) * st] & KIND_MASK) != k) return true;
+        }
+    }
+    return false;
+}
+
 __global__ void k_ho_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags, int w) {
     int64_t total = b.size();
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < total;
@@ -403,12 +423,8 @@ __global__ void k_ho_irr_flag(Geom g, Box b, uint8_t* labels, uint8_t* flags, in
         if (k == K_PLUS || k == K_MINUS) {
             int ijk[3];
             b.coords(l, ijk);
-            for (int d = 0; d < g.dim && !irr; ++d)
-                for (int s = -w; s <= w; ++s) {
-                    if (s == 0) continue;
-                    int64_t q;
-                    if (kind_at(g, b, labels, ijk, d, s, &q) != k) irr = true;
-                }
+            irr = g.dim == 3 ? ho_irregular_node<3>(g, b, labels, l, ijk, k, w)
+                             : ho_irregular_node<2>(g, b, labels, l, ijk, k, w);
         }
         flags[l] = irr ? 1 : 0;
         if (irr) labels[l] = lab | F_HO_IRR;
