@@ -1150,6 +1150,37 @@ __global__ void __launch_bounds__(64) k_ls3_rows(Geom g, Box b, CPDev cp, LSPara
         __syncthreads();
 #pragma unroll 1
         for (int k = 0; k < nrows; ++k) {
+            if constexpr (!second) {
+                // s0 = A z row by row and rho = e - A^T s0, each row's monomials
+                // formed once for both
+                double acc[35];
+#pragma unroll
+                for (int i = 0; i < 35; ++i) acc[i] = 0.0;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    double px[5], py[5], pz[5];
+                    px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+                    for (int e = 1; e < 5; ++e) {
+                        px[e] = px[e - 1] * X[q][0];
+                        py[e] = py[e - 1] * X[q][1];
+                        pz[e] = pz[e - 1] * X[q][2];
+                    }
+                    double mono[35];
+#pragma unroll
+                    for (int cc = 0; cc < 35; ++cc) mono[cc] = px[MONO3.e[cc][0]] * py[MONO3.e[cc][1]] * pz[MONO3.e[cc][2]];
+                    double sv = 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < 35; ++cc) sv += mono[cc] * zs[k][cc];
+                    const double sq = sv * wt[q];
+#pragma unroll
+                    for (int i = 0; i < 35; ++i) acc[i] += mono[i] * sq;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                ls3_wave_sums<35>(part, lane, acc, red);
+                if (lane < 35) rho[cs * CS_NZ + k * 35 + lane] = es[k][lane] - red[lane];
+                continue;
+            }
             double sv[NR];
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
