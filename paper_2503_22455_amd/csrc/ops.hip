@@ -1045,13 +1045,19 @@ __device__ inline void ld4(const S* p, int e, T (&out)[4]) {
 // the other colour's entries in the rows beside them (y +- 1, z +- 1) and in
 // their own row (plus one entry at either end for the x-neighbours).  Every load
 // is issued before the first test (the neighbours of core rows lie in the box).
+// Threads run over (core row, quad) pairs without gaps (nq = hx / 4 quads a
+// row, ny core rows a plane, nrows core rows), blocks in XCD-contiguous order:
+// a row of 49 quads (cfg-4 level 0) left 15 of 64 lanes idle.  Rows are
+// contiguous in a colour array, so lanes still read consecutive entries.
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, int gx, int gy, S* z, const T* b) {
-    const Blk3 B = xcd_block3(gx, gy);
-    const int m0 = 4 * (B.x * 64 + (threadIdx.x & 63));
-    const int j = L.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
-    const int k = L.core_lo[2] + B.z;
-    if (j > L.core_hi[1] || m0 >= L.hx) return;
+__global__ void __launch_bounds__(256) k_rbgs_split(LevelDev L, int colour, int nq, int ny, int nrows, S* z,
+                                                    const T* b) {
+    const int f = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int row = f / nq;
+    if (row >= nrows) return;
+    const int m0 = 4 * (f - row * nq);
+    const int j = L.core_lo[1] + row % ny;
+    const int k = L.core_lo[2] + row / ny;
     const int p = (colour ^ (L.box.lo[0] + j + k)) & 1;  // node of entry m: x offset a = 2m + p
     const int r = (j - L.box.lo[1]) + L.box.dims[1] * (k - L.box.lo[2]);
     const int own = colour * (int)L.half + r * L.hx + m0;
@@ -2088,8 +2094,11 @@ void run_rbgs(const LevelDev& L, int colour, S* z, const T* b, hipStream_t s) {
         if (L.hx % 4 || !L.lab_split) throw Error(IIM_E_INTERNAL, "colour-split rows must hold a multiple of 4");
         // four entries per thread: periodic rows must hold exactly n / 2 entries (their seam wrap)
         if (L.half >= SPLIT4_MIN_ENTRIES && (!L.periodic || 2 * L.hx == L.n)) {
-            const int gx = cdiv(L.hx / 4, 64), gy = cdiv(ny, 4);
-            hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, colour, gx, gy, z, b);
+            const int nq = L.hx / 4, nrows = ny * nz;
+            const int64_t nthreads = (int64_t)nq * nrows;
+            if (nthreads > INT32_MAX - 256) throw Error(IIM_E_INTERNAL, "level too large for the half-sweep grid");
+            hipLaunchKernelGGL((k_rbgs_split<T, S>), dim3((unsigned)cdiv(nthreads, 256)), dim3(256), 0, s, L, colour,
+                               nq, ny, nrows, z, b);
         } else {
             const int gx = cdiv(L.hx, 64), gy = cdiv(ny, 4);
             hipLaunchKernelGGL((k_rbgs_split1<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, colour, gx, gy, z, b);
