@@ -1452,12 +1452,13 @@ __global__ void __launch_bounds__(256) k_restrict3(LevelDev F, LevelDev C, int g
 // neighbour is zero).  A thread owns the two nodes 2m, 2m + 1 of a box row (one
 // of each colour); every row of the box is covered, padding entries included.
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_cast_sweep0(LevelDev L, int gxm, const double* v, const double* scale,
-                                                     double h2, double bp, double bm, T* b, S* z) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m = (blockIdx.x % gxm) * 64 + lane, r = 4 * (blockIdx.x / gxm) + wv;
+__global__ void __launch_bounds__(256) k_cast_sweep0(LevelDev L, const double* v, const double* scale, double h2,
+                                                     double bp, double bm, T* b, S* z) {
+    // threads over (box row, pair) without gaps: f = r hx + m
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    const int r = f / L.hx, m = f - r * L.hx;
     const int nrows = L.box.dims[1] * L.box.dims[2];
-    if (m >= L.hx || r >= nrows) return;
+    if (r >= nrows) return;
     const int j = L.box.lo[1] + r % L.box.dims[1], k = L.box.lo[2] + r / L.box.dims[1];
     const int par = (L.box.lo[0] + j + k) & 1;  // colour of node a = 2m
     const double sc = *scale;
@@ -1491,13 +1492,15 @@ __global__ void __launch_bounds__(256) k_cast_sweep0(LevelDev L, int gxm, const 
 // unknowns, 0 elsewhere) for both nodes of each pair 2m, 2m + 1 of the core's
 // rows.  The output is zero off those rows already (a Krylov basis column).
 template <typename T, typename S>
-__global__ void __launch_bounds__(256) k_rbgs_split_out(LevelDev L, int gx, int gy, const S* z, const T* b,
+__global__ void __launch_bounds__(256) k_rbgs_split_out(LevelDev L, int ny, int nrows, const S* z, const T* b,
                                                         double* out, const double* scale) {
-    const Blk3 B = xcd_block3(gx, gy);
-    const int m = B.x * 64 + (threadIdx.x & 63);
-    const int j = L.core_lo[1] + B.y * 4 + (threadIdx.x >> 6);
-    const int k = L.core_lo[2] + B.z;
-    if (j > L.core_hi[1] || m >= L.hx) return;
+    // threads over (core row, pair) without gaps, blocks in XCD-contiguous order
+    const int f = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int crow = f / L.hx;
+    if (crow >= nrows) return;
+    const int m = f - crow * L.hx;
+    const int j = L.core_lo[1] + crow % ny;
+    const int k = L.core_lo[2] + crow / ny;
     const int p1 = (1 ^ (L.box.lo[0] + j + k)) & 1;
     const int a1 = 2 * m + p1, a0 = 2 * m + (p1 ^ 1);  // colour-1 node and its colour-0 partner
     const int r = (j - L.box.lo[1]) + L.box.dims[1] * (k - L.box.lo[2]);
@@ -2290,9 +2293,10 @@ template <typename T, typename S>
 void run_cast_sweep0(const LevelDev& L, const double* v, const double* scale_dev, double h2, double bp, double bm,
                      T* b, S* z, hipStream_t s) {
     if (!L.split || L.dim != 3) throw Error(IIM_E_INTERNAL, "cast + first half-sweep needs a colour-split 3D level");
-    const int gxm = cdiv(L.hx, 64);
-    const int nb = gxm * cdiv((int64_t)L.box.dims[1] * L.box.dims[2], 4);
-    hipLaunchKernelGGL((k_cast_sweep0<T, S>), dim3(nb), dim3(256), 0, s, L, gxm, v, scale_dev, h2, bp, bm, b, z);
+    const int64_t nthreads = (int64_t)L.hx * L.box.dims[1] * L.box.dims[2];
+    if (nthreads > INT32_MAX - 256) throw Error(IIM_E_INTERNAL, "level too large for the cast grid");
+    hipLaunchKernelGGL((k_cast_sweep0<T, S>), dim3((unsigned)cdiv(nthreads, 256)), dim3(256), 0, s, L, v, scale_dev,
+                       h2, bp, bm, b, z);
     IIM_LAUNCH_CHECK();
 }
 
@@ -2301,9 +2305,10 @@ void run_rbgs_out(const LevelDev& L, const S* z, const T* b, double* out, const 
     if (!L.split || L.dim != 3) throw Error(IIM_E_INTERNAL, "half-sweep with output needs a colour-split 3D level");
     const int ny = L.core_hi[1] - L.core_lo[1] + 1, nz = L.core_hi[2] - L.core_lo[2] + 1;
     if (ny <= 0 || nz <= 0 || L.hx <= 0) return;
-    const int gx = cdiv(L.hx, 64), gy = cdiv(ny, 4);
-    hipLaunchKernelGGL((k_rbgs_split_out<T, S>), dim3(gx * gy * nz), dim3(256), 0, s, L, gx, gy, z, b, out,
-                       scale_dev);
+    const int64_t nthreads = (int64_t)L.hx * ny * nz;
+    if (nthreads > INT32_MAX - 256) throw Error(IIM_E_INTERNAL, "level too large for the half-sweep grid");
+    hipLaunchKernelGGL((k_rbgs_split_out<T, S>), dim3((unsigned)cdiv(nthreads, 256)), dim3(256), 0, s, L, ny,
+                       ny * nz, z, b, out, scale_dev);
     IIM_LAUNCH_CHECK();
 }
 
