@@ -1321,14 +1321,17 @@ __device__ __forceinline__ void prolong_cell(const LevelDev& F, const LevelDev& 
             }
 }
 
+// threads over the coarse cells without gaps (nI x nJ x nK, x fastest), blocks
+// in XCD-contiguous order
 template <typename T, typename S>
 __global__ void __launch_bounds__(256) k_prolong_cells(LevelDev F, LevelDev C, int mode, int I0, int J0, int K0,
-                                                        int nI, int nJ, const S* zc, S* z) {
-    const Blk3 B = xcd_block3((nI + 63) / 64, (nJ + 3) / 4);
-    const int I = I0 + B.x * 64 + (threadIdx.x & 63);
-    const int J = J0 + B.y * 4 + (threadIdx.x >> 6);
-    const int K = K0 + B.z;
-    if (I >= I0 + nI || J >= J0 + nJ) return;
+                                                        int nI, int nJ, int ntot, const S* zc, S* z) {
+    const int f = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (f >= ntot) return;
+    const int q = f / nI;
+    const int I = I0 + (f - q * nI);
+    const int J = J0 + q % nJ;
+    const int K = K0 + q / nJ;
     const int P[3] = {I, J, K};
     bool inner = true;
 #pragma unroll
@@ -2153,8 +2156,10 @@ void run_prolong(const LevelDev& F, const LevelDev& C, int mode, const S* zc, S*
             nc[d] = (F.core_hi[d] >> 1) - c0[d] + 1;
             if (F.core_hi[d] < F.core_lo[d]) return;
         }
-        hipLaunchKernelGGL((k_prolong_cells<T, S>), dim3(cdiv(nc[0], 64) * cdiv(nc[1], 4) * nc[2]), dim3(256), 0, s,
-                           F, C, mode, c0[0], c0[1], c0[2], nc[0], nc[1], zc, z);
+        const int64_t ntot = (int64_t)nc[0] * nc[1] * nc[2];
+        if (ntot > INT32_MAX - 256) throw Error(IIM_E_INTERNAL, "level too large for the prolongation grid");
+        hipLaunchKernelGGL((k_prolong_cells<T, S>), dim3((unsigned)cdiv(ntot, 256)), dim3(256), 0, s, F, C, mode,
+                           c0[0], c0[1], c0[2], nc[0], nc[1], (int)ntot, zc, z);
         IIM_LAUNCH_CHECK();
         return;
     }
